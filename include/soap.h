@@ -1,0 +1,212 @@
+/*
+ * soap.h - C ABI of libsoap: disk-integrated spectrum synthesis of an active
+ * star on one MI355X (gfx950), following Zhao & Dumusque (2023), "SOAP-GPU:
+ * Efficient Spectral Modelling of Stellar Activity Using Graphical
+ * Processing Units".
+ *
+ * Pipeline per call (every step runs in HIP kernels of this library):
+ *   soap_grid_init       disk grid, limb darkening, rotation shift per disk
+ *                        column, quiet integrated spectrum (section 2.1,
+ *                        Algorithm 1, Eqs. 6 and 9-11)
+ *   soap_active_spectra  per rotation phase: region positions, InfoMap owner
+ *                        per cell, per-column weights, shifted and summed
+ *                        differences, final spectra (section 3.3,
+ *                        Algorithm 5, Eqs. 1-4; chromatic contrast of
+ *                        section 4.3.1)
+ *   soap_ccf_rv          CCF against a line mask and Gaussian fit, RV = fitted
+ *                        mean (section 4.1)
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns a soap_status; no C++ exception crosses the ABI.
+ *   - Arguments are validated before anything is enqueued.  A call that
+ *     fails validation leaves the context unchanged and usable; the message
+ *     is kept in the context (soap_last_error) until the next failing call.
+ *   - Input arrays are read during the call (host arrays are copied before
+ *     the call returns); the caller keeps ownership of everything it passes.
+ *     Output arrays are allocated by the caller.
+ *   - Device pointers must be HIP device memory on the device that was
+ *     current at soap_grid_init.  "*_on_device = 0" means a host pointer; the
+ *     call then synchronises its stream before returning.  With device
+ *     outputs the call only enqueues work on the context's stream.
+ *   - Floating-point arrays of spectra and fluxes are float in SOAP_PREC_FP32
+ *     contexts and double in SOAP_PREC_FP64 contexts.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef SOAP_H
+#define SOAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SOAP_ABI_VERSION 1
+
+typedef enum {
+  SOAP_OK = 0,
+  SOAP_ERR_ARG = -1,         /* invalid argument (message says which)          */
+  SOAP_ERR_OOM = -2,         /* device or pinned host allocation failed         */
+  SOAP_ERR_HIP = -3,         /* a HIP runtime call failed (message has the text) */
+  SOAP_ERR_STATE = -4,       /* call not valid in the context's current state   */
+  SOAP_ERR_NOCONV = -5,      /* reserved: fit did not converge (per-RV flag)    */
+  SOAP_ERR_UNSUPPORTED = -6  /* valid but beyond a stated implementation limit  */
+} soap_status;
+
+/* surface types: index into soap_star_desc.spectra */
+enum { SOAP_QUIET = 0, SOAP_SPOT = 1, SOAP_FACULA = 2 };
+
+/* effect of active regions, section 2.1:
+ *   TOT   Eq. 3: active cells contribute C * S'_active
+ *   FLUX  Eq. 1: active cells contribute C * S'_quiet
+ *   BCONV Eq. 2: active cells contribute S'_active          */
+enum { SOAP_EFFECT_TOT = 0, SOAP_EFFECT_FLUX = 1, SOAP_EFFECT_BCONV = 2 };
+
+/* arithmetic of the synthesis:
+ *   FP64  everything in double
+ *   FP32  float spectra, interpolation and per-pixel accumulation; float
+ *         per-lane column sums with Kahan compensation; double for the sum
+ *         over the disk (column sums -> tap weights), the quiet spectrum and
+ *         the final per-pixel combine; the CCF sums and the fit in double    */
+enum { SOAP_PREC_FP64 = 0, SOAP_PREC_FP32 = 1 };
+
+/* contrast of active regions (section 4.3.1):
+ *   SCALAR  soap_region.contrast, one number per region
+ *   PLANCK  per pixel B_lambda(T_act) / B_lambda(T_eff), T_act = T_eff - dT_spot
+ *           for spots and T_eff + dT_f(mu_b) for faculae, with
+ *           dT_f(mu) = c0 + c1 mu + c2 mu^2 evaluated at the mu bin; it
+ *           multiplies the spectrum after the Doppler shift                 */
+enum { SOAP_CONTRAST_SCALAR = 0, SOAP_CONTRAST_PLANCK = 1 };
+
+typedef struct soap_ctx soap_ctx;
+
+/* Star description.  Disk: n_grid x n_grid cells with centres
+ * x_i = -1 + (2i+1)/n_grid (same for y); a cell is on the disk when
+ * x^2 + y^2 < 1; mu = sqrt(1 - x^2 - y^2); weight (2/n_grid)^2 * I(mu) with
+ * I(mu) = 1 - ld_u1 (1-mu) - ld_u2 (1-mu)^2; line-of-sight velocity
+ * vsini_kms * x (receding for x > 0).  Wavelength grid: log-uniform,
+ * ln(lambda_m / Angstrom) = ln_lambda0 + m * dln_lambda, m = 0..n_pix-1.
+ * Local spectra: spectra[t] holds n_mu rows of n_pix samples, row b for the
+ * mu bin mu_bins[b]; a cell takes the row of the closest mu bin (ties to the
+ * lower index).  spectra[SOAP_QUIET] is required; spectra[SOAP_SPOT] and
+ * spectra[SOAP_FACULA] are required only if regions of that type are used
+ * (NULL otherwise).                                                          */
+typedef struct {
+  int32_t n_grid;            /* 2 .. 4096                                   */
+  int32_t n_mu;              /* 1 .. 64                                     */
+  int64_t n_pix;             /* >= 2 * max shift + 4                        */
+  double vsini_kms;          /* |vsini| < 0.1 c                             */
+  double incl_deg;           /* inclination of the rotation axis, 0 .. 180  */
+  double ld_u1, ld_u2;       /* quadratic limb darkening                    */
+  double ln_lambda0;         /* ln(lambda_0 / Angstrom)                     */
+  double dln_lambda;         /* > 0                                         */
+  const double* mu_bins;     /* host, [n_mu], strictly decreasing in (0, 1] */
+  const void* spectra[3];    /* [n_mu][n_pix] row-major, float or double    */
+  int32_t spectra_on_device; /* 1: spectra are device pointers              */
+  int32_t precision;         /* SOAP_PREC_*                                 */
+  int32_t contrast_mode;     /* SOAP_CONTRAST_*                             */
+  int32_t reserved0;
+  double teff_k;             /* PLANCK mode: quiet effective temperature    */
+  double dt_spot_k;          /* PLANCK mode: spot temperature deficit       */
+  double dt_fac_coef[3];     /* PLANCK mode: facula dT_f(mu) coefficients   */
+} soap_star_desc;
+
+/* One circular active region (section 2.1 region parameters).  Its centre
+ * sits at latitude lat_deg and longitude lon_deg + 360 deg * phase; the cap
+ * has angular radius asin(radius).  Regions are written into the disk map in
+ * list order, so the last listed region covering a cell owns it
+ * (section 3.3).  contrast is the scalar I_active / I_quiet used in
+ * SOAP_CONTRAST_SCALAR mode (ignored in PLANCK mode).                        */
+typedef struct {
+  int32_t type;              /* SOAP_SPOT or SOAP_FACULA                    */
+  int32_t reserved0;
+  double lat_deg;            /* -90 .. 90                                   */
+  double lon_deg;
+  double radius;             /* sin(alpha), 0 < radius < 1                  */
+  double contrast;           /* > 0 (scalar mode)                           */
+} soap_region;
+
+/* CCF line mask.  Line l at rest wavelength exp(ln_lambda[l]) with weight
+ * weight[l] has, at trial velocity v_k = v0_kms + k dv_kms (k < n_v), a hole
+ * spanning the Doppler-shifted (Eq. 6) wavelengths of v_k -/+ half_width_kms.
+ * CCF_k = sum_l weight[l] sum_m F_m |pixel_m intersect hole| / dln_lambda,
+ * pixel m covering ln(lambda) in [ln_lambda0 + (m - 1/2) dln, + (m + 1/2) dln)
+ * and only existing pixels contributing.                                     */
+typedef struct {
+  int64_t n_lines;           /* 1 .. 1<<20                                  */
+  const double* ln_lambda;   /* host, [n_lines]                             */
+  const double* weight;      /* host, [n_lines]                             */
+  double half_width_kms;     /* > 0, hole at most 8 pixels wide             */
+  double v0_kms;
+  double dv_kms;             /* > 0                                         */
+  int32_t n_v;               /* 4 .. 1024                                   */
+  int32_t reserved0;
+} soap_mask;
+
+/* Result of the Gaussian fit c0 - amp exp(-(v - rv)^2 / (2 sigma^2)) of one
+ * CCF (section 4.1: RV = the fitted mean).  status 0 = converged,
+ * 1 = iteration limit reached, 2 = degenerate CCF.                           */
+typedef struct {
+  double rv_kms;
+  double fwhm_kms;           /* 2 sqrt(2 ln 2) |sigma|                      */
+  double c0;
+  double amp;
+  double sigma_kms;
+  double chi2;               /* sum of squared residuals                    */
+  int32_t iters;
+  int32_t status;
+} soap_rv;
+
+/* Creates a context for one star: copies the description and spectra to the
+ * device, computes the per-column Doppler shift, interpolation weights
+ * (Eqs. 6, 9-11 on the log grid), the contrast arrays (PLANCK mode) and the
+ * quiet integrated spectrum of Algorithm 1, all on `hip_stream` (a
+ * hipStream_t; NULL = the null stream).  The context owns all device
+ * workspace until soap_destroy.  On error *out is set to NULL.              */
+soap_status soap_grid_init(const soap_star_desc* desc, void* hip_stream, soap_ctx** out);
+
+/* Copies the quiet integrated spectrum (Algorithm 1) to out[n_pix].          */
+soap_status soap_quiet_spectrum(soap_ctx* ctx, void* out, int32_t out_on_device);
+
+/* Integrated spectra of the star with active regions at each phase
+ * (Algorithm 5, Eqs. 1-4): flux[n_phases][n_pix], row-major.  regions and
+ * phases are host arrays (n_regions 0 .. 64, n_phases 1 .. 1<<20); phase is
+ * in rotations (longitude advances 360 deg per unit).  Types present in
+ * regions must have spectra.                                                 */
+soap_status soap_active_spectra(soap_ctx* ctx, const soap_region* regions, int32_t n_regions,
+                                const double* phases, int32_t n_phases, int32_t effect,
+                                void* flux, int32_t flux_on_device);
+
+/* CCF of n_spec spectra flux[n_spec][n_pix] (the context's grid and float
+ * type) against `mask`, then a Gaussian fit per CCF (section 4.1).
+ * ccf_out[n_spec][n_v] (double, may be NULL) and rv_out[n_spec] (may be
+ * NULL) are host or device memory as flagged.  The mask is uploaded and its
+ * pixel overlaps precomputed on the first call with a new mask (the context
+ * compares against the last one).                                            */
+soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device, int64_t n_spec,
+                        const soap_mask* mask, double* ccf_out, int32_t ccf_on_device,
+                        soap_rv* rv_out, int32_t rv_on_device);
+
+/* Waits for all work the context enqueued.                                   */
+soap_status soap_sync(soap_ctx* ctx);
+
+/* Frees the context and its workspace (waits for its work first).  NULL is a
+ * no-op.                                                                      */
+void soap_destroy(soap_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none); with ctx == NULL, the
+ * message of the last failing soap_grid_init in this thread.  Valid until the
+ * next call on the same context.                                             */
+const char* soap_last_error(const soap_ctx* ctx);
+
+/* Static name of a status code.                                               */
+const char* soap_status_string(soap_status status);
+
+/* SOAP_ABI_VERSION of the built library.                                      */
+int32_t soap_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOAP_H */

@@ -1,0 +1,215 @@
+"""Disk-integrated spectra (oracle, test infrastructure only).
+
+Follows, in FP64:
+
+* Eq. 6: a cell moving at line-of-sight velocity v sees lambda' = lambda (1+f),
+  1 + f = sqrt((1+beta)/(1-beta)), beta = v/c.
+* Eqs. 9-11: the shifted spectrum (S_n at lambda'_n) is projected back onto
+  the original grid: for output pixel m find n with
+  lambda'_n <= lambda_m < lambda'_{n+1} and interpolate linearly in lambda
+  (the "project back to the original wavelength grid" step of Algorithm 1,
+  i.e. the gather form; the scatter of Algorithm 3 is a GPU implementation
+  detail of the paper).  Outside the shifted grid the end value is held
+  (reading: the paper says nothing about the ends).
+* Algorithm 1: quiet integrated spectrum = sum over visible cells of
+  A * I(mu) * S'_quiet,bin(cell).
+* Algorithm 5 with Eqs. 1-4: per phase, cells owned by an active region use
+  the differences
+      flux  (Eq. 1): S'_q - C * S'_q
+      bconv (Eq. 2): S'_q - S'_a
+      tot   (Eq. 3): S'_q - C * S'_a
+  and S_final = S_quiet - sum of the differences (Eq. 4).
+* Section 4.3.1: the contrast C is either a scalar per region or, in the
+  chromatic mode, the ratio of two Planck functions B_lambda(T_act) /
+  B_lambda(T_eff) per pixel, with T_act = T_eff - dT_spot for spots and
+  T_eff + dT_f(mu_b) for faculae (dT_f the facula law of section 4.3.3,
+  evaluated at the bin's mu).  It multiplies the spectrum after the shift, on
+  the common grid (Eqs. 3, 13 and 14 apply it to shifted spectra).
+
+Two formulations are provided and pinned against each other:
+``integrated_bruteforce`` walks the cells one by one exactly as Algorithms 1
+and 5 do (for small grids), and ``integrated`` sums the final spectrum
+directly (no quiet-minus-difference step) with cells of one disk column
+grouped, which is exact because the velocity depends on x only.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import disk
+
+C_KMS = 299792.458
+# second radiation constant h c / k_B in m K (exact in SI 2019)
+C2_MK = 1.438776877e-2
+
+TOT, FLUX, BCONV = 0, 1, 2
+QUIET, SPOT, FACULA = 0, 1, 2
+
+
+def wavelengths(ln_lambda0: float, dln: float, n_pix: int) -> np.ndarray:
+    """lambda_m = exp(ln lambda0 + m dln) (log-uniform grid)."""
+    return np.exp(ln_lambda0 + dln * np.arange(n_pix, dtype=np.float64))
+
+
+def doppler_factor(v_kms):
+    """1 + f(beta) = sqrt((1 + beta) / (1 - beta)), Eq. 6."""
+    b = np.asarray(v_kms, dtype=np.float64) / C_KMS
+    return np.sqrt((1.0 + b) / (1.0 - b))
+
+
+class Shift:
+    """Bracketing indices and interpolation factors of Eqs. 9-11 for one velocity."""
+
+    def __init__(self, lam: np.ndarray, v_kms: float):
+        self.lam = lam
+        lam_s = lam * doppler_factor(v_kms)  # lambda'_n
+        p = len(lam)
+        n = np.searchsorted(lam_s, lam, side="right") - 1  # lambda'_n <= lambda_m
+        self.lo = n < 0
+        self.hi = n >= p - 1
+        self.mid = ~(self.lo | self.hi)
+        nm = n[self.mid]
+        self.n = nm
+        # Eq. 11: (lambda_m - lambda'_n) / (lambda'_{n+1} - lambda'_n)
+        self.frac = (lam[self.mid] - lam_s[nm]) / (lam_s[nm + 1] - lam_s[nm])
+
+    def apply(self, s: np.ndarray) -> np.ndarray:
+        s = np.asarray(s, dtype=np.float64)
+        out = np.empty(len(self.lam), dtype=np.float64)
+        nm = self.n
+        out[self.mid] = (s[nm + 1] - s[nm]) * self.frac + s[nm]
+        out[self.lo] = s[0]
+        out[self.hi] = s[-1]
+        return out
+
+
+def shift_spectrum(s, lam, v_kms):
+    """S'(lambda_m) of a spectrum S(lambda_n) Doppler shifted by v (Eqs. 6, 9-11)."""
+    return Shift(lam, v_kms).apply(s)
+
+
+def planck_ratio(lam_a, t_act, t_ref):
+    """B_lambda(T_act) / B_lambda(T_ref) (section 4.3.1, the chromatic contrast)."""
+    lam_m = np.asarray(lam_a, dtype=np.float64) * 1e-10
+    return np.expm1(C2_MK / (lam_m * t_ref)) / np.expm1(C2_MK / (lam_m * t_act))
+
+
+def facula_dt(mu, coef):
+    """dT_f(mu) = a0 + a1 mu + a2 mu^2 (section 4.3.3)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    return coef[0] + coef[1] * mu + coef[2] * mu * mu
+
+
+def contrast_array(star, typ: int, b: int, lam):
+    """Per-pixel contrast of surface type ``typ`` in mu bin ``b`` (chromatic
+    mode), or None in scalar mode."""
+    if star.contrast_mode == 0:
+        return None
+    if typ == SPOT:
+        return planck_ratio(lam, star.teff_k - star.dt_spot_k, star.teff_k)
+    return planck_ratio(lam, star.teff_k + facula_dt(star.mu_bins[b], star.dt_fac_coef), star.teff_k)
+
+
+def _spec(star, typ, b):
+    return np.asarray(star.spectra[typ][b], dtype=np.float64)
+
+
+def quiet_bruteforce(star) -> np.ndarray:
+    """Algorithm 1, one cell at a time."""
+    lam = wavelengths(star.ln_lambda0, star.dln_lambda, star.n_pix)
+    _, _, x, y, mu = disk.disk_cells(star.n_grid)
+    area = disk.cell_area(star.n_grid)
+    inten = disk.limb_darkening(mu, star.ld_u1, star.ld_u2)
+    bins = disk.mu_bin(mu, star.mu_bins)
+    out = np.zeros(star.n_pix)
+    for c in range(len(x)):
+        v = disk.los_velocity(x[c], star.vsini_kms)
+        out += area * inten[c] * shift_spectrum(_spec(star, QUIET, bins[c]), lam, v)
+    return out
+
+
+def integrated_bruteforce(star, phase: float, effect: int = TOT, regions=None) -> np.ndarray:
+    """Algorithm 5 with Eqs. 1-4, one cell at a time: quiet disk minus the
+    summed per-cell differences of the active cells."""
+    regions = star.regions if regions is None else regions
+    lam = wavelengths(star.ln_lambda0, star.dln_lambda, star.n_pix)
+    _, _, x, y, mu = disk.disk_cells(star.n_grid)
+    area = disk.cell_area(star.n_grid)
+    inten = disk.limb_darkening(mu, star.ld_u1, star.ld_u2)
+    bins = disk.mu_bin(mu, star.mu_bins)
+    owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg)
+    s_quiet = quiet_bruteforce(star)
+    diff = np.zeros(star.n_pix)
+    for c in np.nonzero(owner >= 0)[0]:
+        reg = regions[owner[c]]
+        b = bins[c]
+        v = disk.los_velocity(x[c], star.vsini_kms)
+        w = area * inten[c]
+        sq = w * shift_spectrum(_spec(star, QUIET, b), lam, v)
+        sa = w * shift_spectrum(_spec(star, reg.type, b), lam, v)
+        carr = contrast_array(star, reg.type, b, lam)
+        cval = reg.contrast if carr is None else carr
+        if effect == FLUX:
+            d = sq - cval * sq  # Eq. 1
+        elif effect == BCONV:
+            d = sq - sa  # Eq. 2
+        else:
+            d = sq - cval * sa  # Eq. 3
+        diff += d
+    return s_quiet - diff  # Eq. 4
+
+
+def integrated(star, phase: float, effect: int = TOT, regions=None) -> np.ndarray:
+    """Final spectrum summed directly over the disk, cells grouped by column.
+
+    Each visible cell contributes A * I * X'(cell), where X is its quiet
+    spectrum or, for a cell owned by an active region, the active term that
+    Eqs. 1-4 leave in place of the quiet one: C * S_a (tot), C * S_q (flux),
+    S_a (bconv).  Cells of one column share one velocity, so their weights are
+    summed per (source spectrum, contrast) before one shift per column.
+    """
+    regions = star.regions if regions is None else regions
+    lam = wavelengths(star.ln_lambda0, star.dln_lambda, star.n_pix)
+    ix, _, x, y, mu = disk.disk_cells(star.n_grid)
+    area = disk.cell_area(star.n_grid)
+    inten = disk.limb_darkening(mu, star.ld_u1, star.ld_u2)
+    bins = disk.mu_bin(mu, star.mu_bins)
+    owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg)
+    wcell = area * inten
+    # key: (source type, bin, contrast type or -1) -> accumulated shifted spectrum
+    acc = {}
+    xs = disk.cell_centres(star.n_grid)
+    for col in np.unique(ix):
+        sel = ix == col
+        weights = {}
+        for c in np.nonzero(sel)[0]:
+            o = owner[c]
+            b = int(bins[c])
+            if o < 0:
+                key, w = (QUIET, b, -1), wcell[c]
+            else:
+                reg = regions[o]
+                scal = 1.0 if star.contrast_mode == 1 else reg.contrast
+                if effect == FLUX:
+                    key, w = (QUIET, b, reg.type), wcell[c] * scal
+                elif effect == BCONV:
+                    key, w = (reg.type, b, -1), wcell[c]
+                else:
+                    key, w = (reg.type, b, reg.type), wcell[c] * scal
+            weights[key] = weights.get(key, 0.0) + w
+        sh = Shift(lam, disk.los_velocity(xs[col], star.vsini_kms))
+        for key, w in weights.items():
+            src = _spec(star, key[0], key[1])
+            acc[key] = acc.get(key, 0.0) + w * sh.apply(src)
+    out = np.zeros(star.n_pix)
+    for key, a in sorted(acc.items()):
+        if key[2] >= 0 and star.contrast_mode == 1:
+            out += contrast_array(star, key[2], key[1], lam) * a
+        else:
+            out += a
+    return out
+
+
+def quiet(star) -> np.ndarray:
+    """Quiet integrated spectrum (Algorithm 1), column-grouped."""
+    return integrated(star, 0.0, TOT, regions=[])

@@ -1,0 +1,32 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module only *makes inputs*: local spectra per (surface type, mu bin),
+active-region lists, phase lists and CCF masks.  It holds none of the disk
+integration, interpolation, CCF or fitting arithmetic; the HIP library and the
+CPU oracle each implement those on their own and both consume what is made
+here.  The paper's own inputs (Kitt Peak atlases, PHOENIX spectra, the SOAP 2.0
+CCF mask) are not available, so line-list spectra of the same shape stand in
+for them.
+"""
+from .stars import (  # noqa: F401
+    C_KMS,
+    StarInputs,
+    Region,
+    Mask,
+    QUIET,
+    SPOT,
+    FACULA,
+    CONTRAST_SCALAR,
+    CONTRAST_PLANCK,
+    EFFECT_TOT,
+    EFFECT_FLUX,
+    EFFECT_BCONV,
+    PREC_FP64,
+    PREC_FP32,
+    cb_velocity_ms,
+    make_cfg1,
+    make_cfg2,
+    make_tiny,
+    make_velocity_grid,
+    input_digest,
+)

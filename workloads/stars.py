@@ -1,0 +1,396 @@
+"""Seeded synthetic stars, active regions and CCF masks.
+
+Everything here is input preparation: line lists rendered into local spectra
+on a log-uniform wavelength grid (one spectrum per surface type and mu bin),
+plus region lists, phase lists and a binary line mask.  The recipe follows the
+paper's workloads in shape (full visible range at R = 115000, a 300 x 300 disk,
+spot / facula / quiet spectra with a convective-blueshift law that varies with
+mu) but every value is drawn from ``numpy.random.default_rng(seed)`` in a fixed
+order, so the same seed always gives the same arrays.
+
+The local spectra are *inputs* of the method (the paper injects observed or
+PHOENIX spectra per mu bin, section 4.3.2); the Doppler shift that places a
+line centre at its convective-blueshift velocity here is a first-order
+generator detail, not the method's relativistic shift of section 3.2.
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+C_KMS = 299792.458
+C_MS = C_KMS * 1e3
+
+QUIET, SPOT, FACULA = 0, 1, 2
+CONTRAST_SCALAR, CONTRAST_PLANCK = 0, 1
+EFFECT_TOT, EFFECT_FLUX, EFFECT_BCONV = 0, 1, 2
+PREC_FP64, PREC_FP32 = 0, 1
+
+# Facula temperature excess law of the Sun, dT_f(mu) = a0 + a1*mu + a2*mu^2
+# (section 4.3.3, quoted from Meunier et al. 2010).
+FACULA_DT_SUN = (250.9, -407.7, 190.9)
+
+
+@dataclass
+class Region:
+    """One circular active region.
+
+    type     SPOT or FACULA
+    lat_deg, lon_deg  centre latitude / longitude on the star (degrees)
+    radius   sin(alpha) of the cap's angular radius, in stellar radii
+    contrast scalar intensity ratio I_active / I_quiet (scalar-contrast mode)
+    """
+
+    type: int
+    lat_deg: float
+    lon_deg: float
+    radius: float
+    contrast: float = 1.0
+
+
+@dataclass
+class Mask:
+    """Binary (or weighted) CCF line mask and the velocity grid it is run on."""
+
+    ln_lambda: np.ndarray  # (L,) ln(lambda / Angstrom) of the line centres
+    weight: np.ndarray  # (L,)
+    half_width_kms: float
+    v0_kms: float
+    dv_kms: float
+    n_v: int
+
+
+@dataclass
+class StarInputs:
+    n_grid: int
+    vsini_kms: float
+    incl_deg: float
+    ld_u1: float
+    ld_u2: float
+    ln_lambda0: float
+    dln_lambda: float
+    n_pix: int
+    mu_bins: np.ndarray  # (B,) strictly decreasing in (0, 1]
+    spectra: List[Optional[np.ndarray]]  # [QUIET, SPOT, FACULA], each (B, P) or None
+    precision: int = PREC_FP64
+    contrast_mode: int = CONTRAST_SCALAR
+    teff_k: float = 5778.0
+    dt_spot_k: float = 663.0
+    dt_fac_coef: tuple = FACULA_DT_SUN
+    regions: List[Region] = field(default_factory=list)
+    phases: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    mask: Optional[Mask] = None
+    name: str = ""
+
+    @property
+    def n_mu(self) -> int:
+        return int(len(self.mu_bins))
+
+    @property
+    def dtype(self):
+        return np.float64 if self.precision == PREC_FP64 else np.float32
+
+
+def cb_velocity_ms(teff_k):
+    """Convective-blueshift amplitude vs effective temperature (section 4.3.3).
+
+    The paper fits a cubic to the Liebing et al. data, valid 4800-6300 K; the
+    temperature is clamped to that range before evaluating it.
+    """
+    t = np.clip(np.asarray(teff_k, dtype=np.float64), 4800.0, 6300.0)
+    return 95.2388 * ((t - 4400.0) / 1000.0) ** 3 + 91.2791
+
+
+def cb_law_ms(mu_b, amplitude_ms=350.0):
+    """Blueshift per mu bin: -amplitude at mu = 1, falling linearly to 0 at mu = 0.1."""
+    return -amplitude_ms * (np.asarray(mu_b, dtype=np.float64) - 0.1) / 0.9
+
+
+def make_velocity_grid(v0_kms, dv_kms, n_v):
+    return v0_kms + dv_kms * np.arange(n_v, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# line rendering
+# ---------------------------------------------------------------------------
+
+
+def _render(ln0, dln, n_pix, centre_a, depth, sigma_a, gamma_a, v_ms, nsig=8.0, nsig_voigt=40.0):
+    """prod_l (1 - d_l * phi_l(lambda)) on the grid, phi normalised to peak 1.
+
+    Gaussian lines use exp(-x^2/2); lines with gamma > 0 use the Voigt profile
+    (scipy) normalised at its centre.  Each profile is truncated at nsig (or
+    nsig_voigt) Gaussian sigmas, which is part of this synthetic recipe.
+    """
+    from scipy.special import voigt_profile
+
+    lam = np.exp(ln0 + dln * np.arange(n_pix, dtype=np.float64))
+    lam_c = centre_a * (1.0 + v_ms / C_MS)
+    pc = (np.log(lam_c) - ln0) / dln
+    sig_px = sigma_a / (lam_c * dln)
+    log_s = np.zeros(n_pix, dtype=np.float64)
+    order = np.argsort(sig_px * np.where(gamma_a > 0, nsig_voigt, nsig))
+    chunk = 1024
+    for s in range(0, len(order), chunk):
+        sel = order[s : s + chunk]
+        is_v = gamma_a[sel] > 0
+        hw = np.ceil(sig_px[sel] * np.where(is_v, nsig_voigt, nsig)).astype(np.int64) + 1
+        w = int(hw.max())
+        offs = np.arange(-w, w + 1, dtype=np.int64)
+        idx = np.rint(pc[sel]).astype(np.int64)[:, None] + offs[None, :]
+        ok = (idx >= 0) & (idx < n_pix) & (np.abs(offs)[None, :] <= hw[:, None])
+        idc = np.clip(idx, 0, n_pix - 1)
+        x = lam[idc] - lam_c[sel][:, None]
+        sg = sigma_a[sel][:, None]
+        prof = np.exp(-0.5 * (x / sg) ** 2)
+        if is_v.any():
+            vi = np.nonzero(is_v)[0]
+            g = gamma_a[sel][vi][:, None]
+            sv = sg[vi]
+            prof[vi] = voigt_profile(x[vi], sv, g) / voigt_profile(0.0, sv, g)
+        contrib = np.log1p(-depth[sel][:, None] * prof)
+        log_s += np.bincount(idx[ok], weights=contrib[ok], minlength=n_pix)
+    return np.exp(log_s)
+
+
+def _select_mask_lines(centre_a, depth, sigma_a, n_max):
+    """Deepest lines with no neighbour deeper than 0.1*d within +-2 sigma."""
+    order = np.argsort(centre_a)
+    c = centre_a[order]
+    d = depth[order]
+    sg = sigma_a[order]
+    keep = np.ones(len(c), dtype=bool)
+    lo = np.searchsorted(c, c - 2 * sg, side="left")
+    hi = np.searchsorted(c, c + 2 * sg, side="right")
+    for i in range(len(c)):
+        for j in range(lo[i], hi[i]):
+            if j != i and d[j] > 0.1 * d[i]:
+                keep[i] = False
+                break
+    cand = np.nonzero(keep)[0]
+    cand = cand[np.argsort(-d[cand], kind="stable")][:n_max]
+    cand = np.sort(cand)
+    return c[cand], d[cand]
+
+
+def input_digest(star: StarInputs) -> str:
+    h = hashlib.sha256()
+    for arr in star.spectra:
+        if arr is not None:
+            h.update(np.ascontiguousarray(arr).tobytes())
+    h.update(np.ascontiguousarray(star.mu_bins).tobytes())
+    h.update(np.ascontiguousarray(star.phases).tobytes())
+    for r in star.regions:
+        h.update(np.array([r.type, r.lat_deg, r.lon_deg, r.radius, r.contrast]).tobytes())
+    if star.mask is not None:
+        h.update(star.mask.ln_lambda.tobytes())
+        h.update(star.mask.weight.tobytes())
+    return h.hexdigest()
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+
+def make_cfg1(seed: int = 1) -> StarInputs:
+    """Plain method in FP64: 100 x 100 disk, 5000-5050 A in 4096 px, 20 lines.
+
+    5 mu bins with blueshift -350 m/s at mu = 1 to 0 at mu = 0.1; quadratic
+    limb darkening (0.4, 0.25); v sin i = 2 km/s, i = 90 deg; one spot of 5%
+    disk area at latitude 20 deg, contrast 0.6, lines 30% deeper; 25 phases.
+    """
+    rng = np.random.default_rng(seed)
+    n_pix = 4096
+    ln0 = np.log(5000.0)
+    dln = np.log(5050.0 / 5000.0) / (n_pix - 1)
+    n_lines = 20
+    centre = rng.uniform(5001.0, 5049.0, n_lines)
+    depth = rng.uniform(0.1, 0.8, n_lines)
+    sigma = rng.uniform(0.03, 0.08, n_lines)
+    gamma = np.zeros(n_lines)
+    mu_b = 1.0 - 0.225 * np.arange(5)
+    cb = cb_law_ms(mu_b)
+    quiet = np.stack([_render(ln0, dln, n_pix, centre, depth, sigma, gamma, v) for v in cb])
+    spot_depth = np.minimum(depth * 1.3, 0.99)
+    spot_one = _render(ln0, dln, n_pix, centre, spot_depth, sigma, gamma, 0.0)
+    spot = np.stack([spot_one] * len(mu_b))
+    mlam, _ = _select_mask_lines(centre, depth, sigma, 4000)
+    mask = Mask(np.log(mlam), np.ones(len(mlam)), 0.41, -20.0, 0.25, 161)
+    return StarInputs(
+        n_grid=100,
+        vsini_kms=2.0,
+        incl_deg=90.0,
+        ld_u1=0.4,
+        ld_u2=0.25,
+        ln_lambda0=ln0,
+        dln_lambda=dln,
+        n_pix=n_pix,
+        mu_bins=mu_b,
+        spectra=[quiet, spot, None],
+        precision=PREC_FP64,
+        contrast_mode=CONTRAST_SCALAR,
+        regions=[Region(SPOT, 20.0, 180.0, float(np.sqrt(0.05)), 0.6)],
+        phases=np.arange(25, dtype=np.float64) / 25.0,
+        mask=mask,
+        name="cfg1: 100^2 disk, 4096 px, 5 mu bins, 1 spot, 25 phases, FP64",
+    )
+
+
+def make_cfg2(seed: int = 2, precision: int = PREC_FP32, n_phases: int = 100) -> StarInputs:
+    """Full visible range at R = 115000 on a 300 x 300 disk (headline workload).
+
+    3800-6900 A at dln = 1/(3*115000) (205800 px); 30k lines (deepest 10%
+    Voigt); 20 mu bins; spot spectrum at T_eff - 600 K with 30% deeper lines
+    plus 5k weak molecular-band lines; facula spectrum = quiet lines with no
+    blueshift; chromatic Planck contrast; a facula with a spot inside it and a
+    second spot; 100 phases; 4000-line binary mask.
+    """
+    rng = np.random.default_rng(seed)
+    dln = 1.0 / (3.0 * 115000.0)
+    ln0 = np.log(3800.0)
+    n_pix = int(np.floor(np.log(6900.0 / 3800.0) / dln)) + 1
+    n_lines = 30000
+    centre = rng.uniform(3805.0, 6895.0, n_lines)
+    u = rng.uniform(0.0, 1.0, n_lines)
+    depth = 0.05 + 0.85 * u * u
+    sig_v = rng.uniform(1.5, 3.0, n_lines)
+    sigma = centre * sig_v / C_KMS
+    gamma = np.zeros(n_lines)
+    deep = np.argsort(-depth)[: n_lines // 10]
+    gamma[deep] = 0.1 * sigma[deep]
+    n_mu = 20
+    mu_b = 1.0 - 0.9 * np.arange(n_mu) / (n_mu - 1)
+    cb = cb_law_ms(mu_b)
+    quiet = np.stack([_render(ln0, dln, n_pix, centre, depth, sigma, gamma, v) for v in cb])
+    # spot: deeper lines, no blueshift, plus weak molecular-band lines in the red
+    n_weak = 5000
+    band_c = 5800.0 + (np.arange(10) + 0.5) * 110.0
+    wc = band_c[rng.integers(0, 10, n_weak)] + rng.uniform(-15.0, 15.0, n_weak)
+    wd = rng.uniform(0.01, 0.05, n_weak)
+    ws = wc * rng.uniform(1.5, 3.0, n_weak) / C_KMS
+    sc = np.concatenate([centre, wc])
+    sd = np.concatenate([np.minimum(depth * 1.3, 0.99), wd])
+    ss = np.concatenate([sigma, ws])
+    sgm = np.concatenate([gamma, np.zeros(n_weak)])
+    spot_one = _render(ln0, dln, n_pix, sc, sd, ss, sgm, 0.0)
+    fac_one = _render(ln0, dln, n_pix, centre, depth, sigma, gamma, 0.0)
+    dt = np.float64 if precision == PREC_FP64 else np.float32
+    spot = np.broadcast_to(spot_one, (n_mu, n_pix)).astype(dt)
+    fac = np.broadcast_to(fac_one, (n_mu, n_pix)).astype(dt)
+    mlam, _ = _select_mask_lines(centre, depth, sigma, 4000)
+    mask = Mask(np.log(mlam), np.ones(len(mlam)), 0.41, -20.0, 0.25, 161)
+    return StarInputs(
+        n_grid=300,
+        vsini_kms=2.0,
+        incl_deg=90.0,
+        ld_u1=0.4,
+        ld_u2=0.25,
+        ln_lambda0=ln0,
+        dln_lambda=dln,
+        n_pix=n_pix,
+        mu_bins=mu_b,
+        spectra=[quiet.astype(dt), spot, fac],
+        precision=precision,
+        contrast_mode=CONTRAST_PLANCK,
+        teff_k=5778.0,
+        dt_spot_k=600.0,
+        dt_fac_coef=FACULA_DT_SUN,
+        regions=[
+            Region(FACULA, 30.0, 180.0, 0.3, 1.0),
+            Region(SPOT, 30.0, 180.0, 0.1, 1.0),
+            Region(SPOT, -15.0, 60.0, 0.1414, 1.0),
+        ],
+        phases=np.arange(n_phases, dtype=np.float64) / n_phases,
+        mask=mask,
+        name="cfg2: 300^2 disk, 205800 px, 20 mu bins, facula+2 spots, 100 phases",
+    )
+
+
+def make_tiny(
+    seed: int,
+    n_grid: int = 16,
+    n_pix: int = 700,
+    n_mu: int = 4,
+    precision: int = PREC_FP64,
+    contrast_mode: int = CONTRAST_SCALAR,
+    n_regions: Optional[int] = None,
+    n_phases: int = 5,
+    vsini_kms: Optional[float] = None,
+    incl_deg: Optional[float] = None,
+    with_facula: bool = True,
+) -> StarInputs:
+    """Small random star for parity tests: every bin and type gets its own
+    spectrum (random per-bin velocities for all types) so that an indexing
+    mistake on any axis changes the result."""
+    rng = np.random.default_rng(seed)
+    dln = rng.uniform(2.0e-6, 6.0e-6)
+    ln0 = np.log(rng.uniform(4000.0, 6000.0))
+    lam_hi = np.exp(ln0 + dln * (n_pix - 1))
+    lam_lo = np.exp(ln0)
+    n_lines = max(4, n_pix // 40)
+    centre = rng.uniform(lam_lo, lam_hi, n_lines)
+    depth = rng.uniform(0.1, 0.9, n_lines)
+    sigma = centre * rng.uniform(1.5, 4.0, n_lines) / C_KMS
+    gamma = np.zeros(n_lines)
+    mu_b = np.sort(rng.uniform(0.05, 1.0, n_mu))[::-1].copy()
+    mu_b[0] = 1.0
+    types = [QUIET, SPOT, FACULA] if with_facula else [QUIET, SPOT]
+    spectra: List[Optional[np.ndarray]] = [None, None, None]
+    dt = np.float64 if precision == PREC_FP64 else np.float32
+    for t in types:
+        scale = {QUIET: 1.0, SPOT: 1.3, FACULA: 0.9}[t]
+        vb = rng.uniform(-600.0, 300.0, n_mu)
+        spectra[t] = np.stack(
+            [
+                _render(ln0, dln, n_pix, centre, np.minimum(depth * scale, 0.99), sigma, gamma, v)
+                for v in vb
+            ]
+        ).astype(dt)
+    if vsini_kms is None:
+        vsini_kms = float(rng.uniform(1.0, 8.0))
+    if incl_deg is None:
+        incl_deg = float(rng.uniform(20.0, 90.0))
+    if n_regions is None:
+        n_regions = int(rng.integers(1, 5))
+    regs = []
+    for _ in range(n_regions):
+        t = int(rng.integers(1, 3)) if with_facula else SPOT
+        regs.append(
+            Region(
+                t,
+                float(rng.uniform(-60.0, 60.0)),
+                float(rng.uniform(0.0, 360.0)),
+                float(rng.uniform(0.1, 0.45)),
+                float(rng.uniform(0.3, 1.4)),
+            )
+        )
+    phases = np.sort(rng.uniform(0.0, 1.0, n_phases))
+    # a short mask of the deepest lines, velocity grid wide enough for v sin i
+    order = np.argsort(-depth)[: max(2, n_lines // 2)]
+    mlam = np.sort(centre[order])
+    mask = Mask(np.log(mlam), rng.uniform(0.5, 1.0, len(mlam)), 0.41, -15.0, 0.5, 61)
+    return StarInputs(
+        n_grid=n_grid,
+        vsini_kms=vsini_kms,
+        incl_deg=incl_deg,
+        ld_u1=float(rng.uniform(0.1, 0.6)),
+        ld_u2=float(rng.uniform(0.0, 0.3)),
+        ln_lambda0=ln0,
+        dln_lambda=dln,
+        n_pix=n_pix,
+        mu_bins=mu_b,
+        spectra=spectra,
+        precision=precision,
+        contrast_mode=contrast_mode,
+        teff_k=float(rng.uniform(4800.0, 6300.0)),
+        dt_spot_k=float(rng.uniform(300.0, 900.0)),
+        dt_fac_coef=FACULA_DT_SUN,
+        regions=regs,
+        phases=phases,
+        mask=mask,
+        name=f"tiny seed={seed} N={n_grid} P={n_pix} B={n_mu}",
+    )
