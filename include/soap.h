@@ -187,6 +187,28 @@ soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device,
                         const soap_mask* mask, double* ccf_out, int32_t ccf_on_device,
                         soap_rv* rv_out, int32_t rv_on_device);
 
+/* Per-stage GPU time and traffic bookkeeping, for benchmarks.  With
+ * profiling on, every stage kernel of soap_active_spectra and soap_ccf_rv is
+ * bracketed by HIP events on the context's stream; soap_profile_read waits
+ * for the stream and returns the summed stage times since the last
+ * soap_profile_enable(ctx, 1), plus the number of distinct local spectra and
+ * contrast arrays the last soap_active_spectra read (its touched inputs).   */
+typedef struct {
+  double weights_ms;         /* region weights + InfoMap + column sums      */
+  double compact_ms;         /* tap lists                                   */
+  double apply_ms;           /* shift-and-sum of the final spectra          */
+  double ccf_ms;             /* CCF (incl. the fixed-order reduction)       */
+  double gfit_ms;            /* Gaussian fits                               */
+  int64_t active_calls;
+  int64_t ccf_calls;
+  int64_t src_arrays;        /* last apply: distinct local spectra read     */
+  int64_t con_arrays;        /* last apply: distinct contrast arrays read   */
+  int64_t last_phases;       /* last apply: number of phases                */
+} soap_profile;
+
+soap_status soap_profile_enable(soap_ctx* ctx, int32_t on);
+soap_status soap_profile_read(soap_ctx* ctx, soap_profile* out);
+
 /* Waits for all work the context enqueued.                                   */
 soap_status soap_sync(soap_ctx* ctx);
 

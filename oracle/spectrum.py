@@ -72,15 +72,42 @@ class Shift:
         self.n = nm
         # Eq. 11: (lambda_m - lambda'_n) / (lambda'_{n+1} - lambda'_n)
         self.frac = (lam[self.mid] - lam_s[nm]) / (lam_s[nm + 1] - lam_s[nm])
+        idx = np.nonzero(self.mid)[0]
+        self._run = None
+        if len(idx) and idx[-1] - idx[0] + 1 == len(idx) and np.all(np.diff(nm) == 1):
+            self._run = (int(idx[0]), int(idx[-1]) + 1, int(nm[0]))
 
     def apply(self, s: np.ndarray) -> np.ndarray:
         s = np.asarray(s, dtype=np.float64)
         out = np.empty(len(self.lam), dtype=np.float64)
         nm = self.n
-        out[self.mid] = (s[nm + 1] - s[nm]) * self.frac + s[nm]
+        if self._run is not None:
+            # the bracketing indices of the interior are consecutive: same
+            # arithmetic on slices instead of gathers
+            a, b, n0 = self._run
+            lo, hi = s[n0 : n0 + (b - a)], s[n0 + 1 : n0 + 1 + (b - a)]
+            out[a:b] = (hi - lo) * self.frac + lo
+        else:
+            out[self.mid] = (s[nm + 1] - s[nm]) * self.frac + s[nm]
         out[self.lo] = s[0]
         out[self.hi] = s[-1]
         return out
+
+
+    def accumulate(self, acc: np.ndarray, w: float, s: np.ndarray) -> None:
+        """acc += w * S' (same arithmetic as apply, fewer temporaries)."""
+        if self._run is None or self.lo[self._run[0]:].any() or self.hi[: self._run[1]].any():
+            acc += w * self.apply(s)
+            return
+        a, b, n0 = self._run
+        lo = s[n0 : n0 + (b - a)]
+        t = s[n0 + 1 : n0 + 1 + (b - a)] - lo
+        t *= self.frac
+        t += lo
+        t *= w
+        acc[a:b] += t
+        acc[:a] += w * s[0]
+        acc[b:] += w * s[-1]
 
 
 def shift_spectrum(s, lam, v_kms):
@@ -176,31 +203,40 @@ def integrated(star, phase: float, effect: int = TOT, regions=None) -> np.ndarra
     bins = disk.mu_bin(mu, star.mu_bins)
     owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg)
     wcell = area * inten
-    # key: (source type, bin, contrast type or -1) -> accumulated shifted spectrum
+    # per cell: the (source type, bin, contrast type or -1) its term uses and
+    # its weight, then summed per (column, key)
+    src_t = np.zeros(len(x), dtype=np.int64)
+    con_t = np.full(len(x), -1, dtype=np.int64)
+    w = wcell.copy()
+    for r_idx, reg in enumerate(regions):
+        sel = owner == r_idx
+        scal = 1.0 if star.contrast_mode == 1 else reg.contrast
+        if effect == FLUX:
+            con_t[sel] = reg.type
+            w[sel] = wcell[sel] * scal
+        elif effect == BCONV:
+            src_t[sel] = reg.type
+        else:
+            src_t[sel] = reg.type
+            con_t[sel] = reg.type
+            w[sel] = wcell[sel] * scal
+    nb = len(star.mu_bins)
+    code = (src_t * nb + bins) * 4 + (con_t + 1)
+    ncode = 3 * nb * 4
+    n = star.n_grid
+    wsum = np.bincount(ix * ncode + code, weights=w, minlength=n * ncode).reshape(n, ncode)
     acc = {}
-    xs = disk.cell_centres(star.n_grid)
-    for col in np.unique(ix):
-        sel = ix == col
-        weights = {}
-        for c in np.nonzero(sel)[0]:
-            o = owner[c]
-            b = int(bins[c])
-            if o < 0:
-                key, w = (QUIET, b, -1), wcell[c]
-            else:
-                reg = regions[o]
-                scal = 1.0 if star.contrast_mode == 1 else reg.contrast
-                if effect == FLUX:
-                    key, w = (QUIET, b, reg.type), wcell[c] * scal
-                elif effect == BCONV:
-                    key, w = (reg.type, b, -1), wcell[c]
-                else:
-                    key, w = (reg.type, b, reg.type), wcell[c] * scal
-            weights[key] = weights.get(key, 0.0) + w
+    srcs = {}
+    xs = disk.cell_centres(n)
+    for col in np.nonzero(wsum.any(axis=1))[0]:
         sh = Shift(lam, disk.los_velocity(xs[col], star.vsini_kms))
-        for key, w in weights.items():
-            src = _spec(star, key[0], key[1])
-            acc[key] = acc.get(key, 0.0) + w * sh.apply(src)
+        for cd in np.nonzero(wsum[col])[0]:
+            key = (int(cd // 4 // nb), int(cd // 4 % nb), int(cd % 4) - 1)
+            if key[:2] not in srcs:
+                srcs[key[:2]] = _spec(star, key[0], key[1])
+            if key not in acc:
+                acc[key] = np.zeros(star.n_pix)
+            sh.accumulate(acc[key], wsum[col, cd], srcs[key[:2]])
     out = np.zeros(star.n_pix)
     for key, a in sorted(acc.items()):
         if key[2] >= 0 and star.contrast_mode == 1:

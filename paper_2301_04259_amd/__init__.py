@@ -1,0 +1,353 @@
+"""Python binding of libsoap (include/soap.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libsoap.so``; this module
+converts Python objects into the C structs of the ABI and passes pointers.
+Device buffers are torch tensors on the GPU (torch is used for device memory
+and streams only); host buffers are numpy arrays.  Importing this module
+fails loudly when the built library is missing: there is no fallback.
+
+Functions carry the ABI names:
+
+    ctx = soap_grid_init(star, stream=None)
+    soap_quiet_spectrum(ctx, out)
+    soap_active_spectra(ctx, regions, phases, effect, out)
+    soap_ccf_rv(ctx, flux, mask, ccf_out=None, rv_out=None)
+    soap_sync(ctx); soap_destroy(ctx); soap_last_error(ctx)
+
+``star`` is any object with the fields of ``soap_star_desc`` (n_grid,
+vsini_kms, incl_deg, ld_u1, ld_u2, ln_lambda0, dln_lambda, n_pix, mu_bins,
+spectra[3], precision, contrast_mode, teff_k, dt_spot_k, dt_fac_coef);
+regions carry type / lat_deg / lon_deg / radius / contrast; a mask carries
+ln_lambda / weight / half_width_kms / v0_kms / dv_kms / n_v.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsoap.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is not built; run `python paper_2301_04259_amd/build.py` "
+        "(hipcc, gfx950) before importing the binding"
+    )
+
+_lib = C.CDLL(LIB_PATH)
+
+SOAP_OK = 0
+QUIET, SPOT, FACULA = 0, 1, 2
+EFFECT_TOT, EFFECT_FLUX, EFFECT_BCONV = 0, 1, 2
+PREC_FP64, PREC_FP32 = 0, 1
+CONTRAST_SCALAR, CONTRAST_PLANCK = 0, 1
+
+SYMBOLS = (
+    "soap_grid_init",
+    "soap_quiet_spectrum",
+    "soap_active_spectra",
+    "soap_ccf_rv",
+    "soap_sync",
+    "soap_destroy",
+    "soap_last_error",
+    "soap_status_string",
+    "soap_abi_version",
+    "soap_profile_enable",
+    "soap_profile_read",
+)
+
+
+class StarDesc(C.Structure):
+    _fields_ = [
+        ("n_grid", C.c_int32),
+        ("n_mu", C.c_int32),
+        ("n_pix", C.c_int64),
+        ("vsini_kms", C.c_double),
+        ("incl_deg", C.c_double),
+        ("ld_u1", C.c_double),
+        ("ld_u2", C.c_double),
+        ("ln_lambda0", C.c_double),
+        ("dln_lambda", C.c_double),
+        ("mu_bins", C.POINTER(C.c_double)),
+        ("spectra", C.c_void_p * 3),
+        ("spectra_on_device", C.c_int32),
+        ("precision", C.c_int32),
+        ("contrast_mode", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("teff_k", C.c_double),
+        ("dt_spot_k", C.c_double),
+        ("dt_fac_coef", C.c_double * 3),
+    ]
+
+
+class RegionC(C.Structure):
+    _fields_ = [
+        ("type", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("lat_deg", C.c_double),
+        ("lon_deg", C.c_double),
+        ("radius", C.c_double),
+        ("contrast", C.c_double),
+    ]
+
+
+class MaskC(C.Structure):
+    _fields_ = [
+        ("n_lines", C.c_int64),
+        ("ln_lambda", C.POINTER(C.c_double)),
+        ("weight", C.POINTER(C.c_double)),
+        ("half_width_kms", C.c_double),
+        ("v0_kms", C.c_double),
+        ("dv_kms", C.c_double),
+        ("n_v", C.c_int32),
+        ("reserved0", C.c_int32),
+    ]
+
+
+class ProfileC(C.Structure):
+    _fields_ = [
+        ("weights_ms", C.c_double),
+        ("compact_ms", C.c_double),
+        ("apply_ms", C.c_double),
+        ("ccf_ms", C.c_double),
+        ("gfit_ms", C.c_double),
+        ("active_calls", C.c_int64),
+        ("ccf_calls", C.c_int64),
+        ("src_arrays", C.c_int64),
+        ("con_arrays", C.c_int64),
+        ("last_phases", C.c_int64),
+    ]
+
+
+RV_DTYPE = np.dtype(
+    [
+        ("rv_kms", "<f8"),
+        ("fwhm_kms", "<f8"),
+        ("c0", "<f8"),
+        ("amp", "<f8"),
+        ("sigma_kms", "<f8"),
+        ("chi2", "<f8"),
+        ("iters", "<i4"),
+        ("status", "<i4"),
+    ]
+)
+
+_ctx_p = C.c_void_p
+_lib.soap_grid_init.argtypes = [C.POINTER(StarDesc), C.c_void_p, C.POINTER(_ctx_p)]
+_lib.soap_grid_init.restype = C.c_int
+_lib.soap_quiet_spectrum.argtypes = [_ctx_p, C.c_void_p, C.c_int32]
+_lib.soap_quiet_spectrum.restype = C.c_int
+_lib.soap_active_spectra.argtypes = [
+    _ctx_p, C.POINTER(RegionC), C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_void_p, C.c_int32,
+]
+_lib.soap_active_spectra.restype = C.c_int
+_lib.soap_ccf_rv.argtypes = [
+    _ctx_p, C.c_void_p, C.c_int32, C.c_int64, C.POINTER(MaskC), C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+]
+_lib.soap_ccf_rv.restype = C.c_int
+_lib.soap_sync.argtypes = [_ctx_p]
+_lib.soap_sync.restype = C.c_int
+_lib.soap_destroy.argtypes = [_ctx_p]
+_lib.soap_destroy.restype = None
+_lib.soap_last_error.argtypes = [_ctx_p]
+_lib.soap_last_error.restype = C.c_char_p
+_lib.soap_status_string.argtypes = [C.c_int]
+_lib.soap_status_string.restype = C.c_char_p
+_lib.soap_profile_enable.argtypes = [_ctx_p, C.c_int32]
+_lib.soap_profile_enable.restype = C.c_int
+_lib.soap_profile_read.argtypes = [_ctx_p, C.POINTER(ProfileC)]
+_lib.soap_profile_read.restype = C.c_int
+_lib.soap_abi_version.argtypes = []
+_lib.soap_abi_version.restype = C.c_int32
+
+
+class SoapError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        super().__init__(f"{_lib.soap_status_string(status).decode()}: {message}")
+
+
+def _is_tensor(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    """(pointer, on_device) of a torch tensor or a numpy array."""
+    if _is_tensor(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr(), 1 if x.is_cuda else 0
+    if not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return x.ctypes.data, 0
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Context:
+    """Owns a soap_ctx* and the host objects its pointers were made from."""
+
+    def __init__(self, handle, star, keep):
+        self.handle = handle
+        self.star = star
+        self._keep = keep
+        self.precision = int(star.precision)
+        self.n_pix = int(star.n_pix)
+        self.dtype = np.float32 if self.precision == PREC_FP32 else np.float64
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.soap_destroy(h)
+            self.handle = None
+
+
+def _check(st, ctx_handle):
+    if st != SOAP_OK:
+        raise SoapError(st, _lib.soap_last_error(ctx_handle).decode())
+
+
+def abi_version():
+    return int(_lib.soap_abi_version())
+
+
+def soap_grid_init(star, stream=None):
+    d = StarDesc()
+    d.n_grid = int(star.n_grid)
+    mu = np.ascontiguousarray(star.mu_bins, dtype=np.float64)
+    d.n_mu = len(mu)
+    d.n_pix = int(star.n_pix)
+    d.vsini_kms = float(star.vsini_kms)
+    d.incl_deg = float(star.incl_deg)
+    d.ld_u1 = float(star.ld_u1)
+    d.ld_u2 = float(star.ld_u2)
+    d.ln_lambda0 = float(star.ln_lambda0)
+    d.dln_lambda = float(star.dln_lambda)
+    d.mu_bins = mu.ctypes.data_as(C.POINTER(C.c_double))
+    keep = [mu]
+    on_dev = None
+    want = np.float32 if int(star.precision) == PREC_FP32 else np.float64
+    for t in range(3):
+        s = star.spectra[t]
+        if s is None:
+            d.spectra[t] = None
+            continue
+        if not _is_tensor(s):
+            s = np.ascontiguousarray(s, dtype=want)
+        keep.append(s)
+        p, dev = _ptr(s)
+        if on_dev is None:
+            on_dev = dev
+        elif on_dev != dev:
+            raise ValueError("spectra must all be host arrays or all device tensors")
+        d.spectra[t] = p
+    d.spectra_on_device = int(on_dev or 0)
+    d.precision = int(star.precision)
+    d.contrast_mode = int(getattr(star, "contrast_mode", CONTRAST_SCALAR))
+    d.teff_k = float(getattr(star, "teff_k", 5778.0))
+    d.dt_spot_k = float(getattr(star, "dt_spot_k", 0.0))
+    coef = tuple(getattr(star, "dt_fac_coef", (0.0, 0.0, 0.0)))
+    for i in range(3):
+        d.dt_fac_coef[i] = float(coef[i])
+    h = _ctx_p()
+    st = _lib.soap_grid_init(C.byref(d), _stream_handle(stream), C.byref(h))
+    _check(st, None)
+    return Context(h, star, keep)
+
+
+def soap_quiet_spectrum(ctx, out):
+    p, dev = _ptr(out)
+    _check(_lib.soap_quiet_spectrum(ctx.handle, p, dev), ctx.handle)
+    return out
+
+
+def _regions(regions):
+    arr = (RegionC * max(1, len(regions)))()
+    for i, r in enumerate(regions):
+        arr[i].type = int(r.type)
+        arr[i].lat_deg = float(r.lat_deg)
+        arr[i].lon_deg = float(r.lon_deg)
+        arr[i].radius = float(r.radius)
+        arr[i].contrast = float(r.contrast)
+    return arr
+
+
+def soap_active_spectra(ctx, regions, phases, effect, out):
+    ph = np.ascontiguousarray(phases, dtype=np.float64)
+    regs = _regions(regions)
+    p, dev = _ptr(out)
+    st = _lib.soap_active_spectra(
+        ctx.handle, regs, len(regions), ph.ctypes.data_as(C.POINTER(C.c_double)), len(ph), int(effect), p, dev
+    )
+    _check(st, ctx.handle)
+    return out
+
+
+def _mask(mask):
+    m = MaskC()
+    lnl = np.ascontiguousarray(mask.ln_lambda, dtype=np.float64)
+    w = np.ascontiguousarray(mask.weight, dtype=np.float64)
+    m.n_lines = len(lnl)
+    m.ln_lambda = lnl.ctypes.data_as(C.POINTER(C.c_double))
+    m.weight = w.ctypes.data_as(C.POINTER(C.c_double))
+    m.half_width_kms = float(mask.half_width_kms)
+    m.v0_kms = float(mask.v0_kms)
+    m.dv_kms = float(mask.dv_kms)
+    m.n_v = int(mask.n_v)
+    return m, (lnl, w)
+
+
+def soap_ccf_rv(ctx, flux, mask, ccf_out=None, rv_out=None, n_spec=None):
+    """CCF (double, [n_spec][n_v]) and Gaussian-fit RVs (RV_DTYPE records)."""
+    fp, fdev = _ptr(flux)
+    if n_spec is None:
+        n_spec = int(np.prod(flux.shape[:-1])) if len(flux.shape) > 1 else 1
+    m, keep = _mask(mask)
+    cp, cdev = (None, 0) if ccf_out is None else _ptr(ccf_out)
+    rp, rdev = (None, 0) if rv_out is None else _ptr(rv_out)
+    st = _lib.soap_ccf_rv(ctx.handle, fp, fdev, int(n_spec), C.byref(m), cp, cdev, rp, rdev)
+    del keep
+    _check(st, ctx.handle)
+    return ccf_out, rv_out
+
+
+def soap_profile_enable(ctx, on=True):
+    _check(_lib.soap_profile_enable(ctx.handle, 1 if on else 0), ctx.handle)
+
+
+def soap_profile_read(ctx):
+    p = ProfileC()
+    _check(_lib.soap_profile_read(ctx.handle, C.byref(p)), ctx.handle)
+    return {k: getattr(p, k) for k, _ in ProfileC._fields_}
+
+
+def soap_sync(ctx):
+    _check(_lib.soap_sync(ctx.handle), ctx.handle)
+
+
+def soap_destroy(ctx):
+    if ctx.handle:
+        _lib.soap_destroy(ctx.handle)
+        ctx.handle = None
+
+
+def soap_last_error(ctx=None):
+    return _lib.soap_last_error(ctx.handle if ctx is not None else None).decode()
+
+
+def rv_records(n):
+    """Host array for soap_ccf_rv's rv_out."""
+    return np.zeros(n, dtype=RV_DTYPE)

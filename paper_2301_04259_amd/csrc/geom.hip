@@ -1,0 +1,238 @@
+// Per-star kernels: disk-column Doppler shifts, chromatic contrast and the
+// quiet integrated spectrum.
+//
+// Section 3.2 (Eqs. 5-11): on a log-uniform grid ln(lambda_m) = ln0 + m dln
+// the relativistic factor of Eq. 6 is a translation by
+// s = ln(1+f)/dln = atanh(beta)/dln pixels, the same for every pixel.  A disk
+// column at x has beta = vsini x / c for all its cells (solid-body rotation),
+// so the whole column shares one shift.  The bracketing index of Eqs. 9-10
+// is n = m - ceil(s) and the interpolation factor of Eq. 11,
+// (lambda_m - lambda'_n)/(lambda'_{n+1} - lambda'_n), evaluates exactly to
+// w = expm1(u dln)/expm1(dln) with u = ceil(s) - s.  The shifted spectrum is
+// S'_m = (1-w) S[m - c] + w S[m - c + 1] with the source index held inside
+// [0, P-1] (end values held outside the shifted grid).
+//
+// Algorithm 1 (quiet disk): Q = sum over disk cells of A I(mu) S'_{q,bin}.
+// Cells are summed per (column, mu bin) first ("column sums", FP32 + Kahan in
+// the FP32 mode, FP64 otherwise, then one wave64 reduction in FP64), then the
+// column sums are collapsed in FP64 onto integer offsets j:
+//   K[b][j] = sum_{c_i = j} (1 - w_i) W[i][b] + sum_{c_i - 1 = j} w_i W[i][b]
+// and Q[m] = sum_b sum_j K[b][j] S_{q,b}[clamp(m - j)], accumulated in FP64.
+#include "soap_internal.hpp"
+
+namespace soap {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__global__ void k_geom(int N, double vsini, double dln, int* __restrict__ col_c,
+                       double* __restrict__ col_w) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double x = cell_coord(i, N);
+  double beta = vsini * x / C_KMS;
+  double s = atanh(beta) / dln;
+  double c = ceil(s);
+  double u = c - s;
+  col_c[i] = (int)c;
+  col_w[i] = expm1(u * dln) / expm1(dln);
+}
+
+template <typename T>
+__global__ void k_contrast(int64_t P, int B, double ln0, double dln, double teff, double dts, double f0,
+                           double f1, double f2, const double* __restrict__ mu_b, T* __restrict__ con_spot,
+                           T* __restrict__ con_fac) {
+  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= P) return;
+  double lam = exp(ln0 + dln * (double)m) * 1e-10;
+  double eref = expm1(C2_MK / (lam * teff));
+  con_spot[m] = (T)(eref / expm1(C2_MK / (lam * (teff - dts))));
+  for (int b = 0; b < B; ++b) {
+    double mu = mu_b[b];
+    double dt = f0 + f1 * mu + f2 * mu * mu;
+    con_fac[(int64_t)b * P + m] = (T)(eref / expm1(C2_MK / (lam * (teff + dt))));
+  }
+}
+
+// one wave64 per disk column: W[i][b] = sum_{cells of column i in bin b} A I
+template <bool KAHAN32>
+__global__ void __launch_bounds__(64) k_quiet_colsum(int N, int B, double u1, double u2,
+                                                     const double* __restrict__ mu_b,
+                                                     double* __restrict__ colW) {
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double x = cell_coord(i, N);
+  const double area = (2.0 / N) * (2.0 / N);
+  int bmin = B, bmax = -1;
+  for (int k = lane; k < N; k += 64) {
+    double y = cell_coord(k, N);
+    double r2;
+    {
+#pragma clang fp contract(off)
+      r2 = x * x + y * y;
+    }
+    if (r2 < 1.0) {
+      int b = nearest_bin(sqrt(1.0 - r2), mu_b, B);
+      bmin = min(bmin, b);
+      bmax = max(bmax, b);
+    }
+  }
+  bmin = wave_min(bmin);
+  bmax = wave_max(bmax);
+  for (int b = 0; b < B; ++b) {
+    double tot = 0.0;
+    if (b >= bmin && b <= bmax) {
+      double part;
+      if (KAHAN32) {
+        float s = 0.f, comp = 0.f;
+        for (int k = lane; k < N; k += 64) {
+          double y = cell_coord(k, N);
+          double r2;
+          {
+#pragma clang fp contract(off)
+            r2 = x * x + y * y;
+          }
+          if (r2 < 1.0) {
+            double mu = sqrt(1.0 - r2);
+            if (nearest_bin(mu, mu_b, B) == b) {
+              float v = (float)(area * limb_dark(mu, u1, u2));
+              float yk = v - comp;
+              float t = s + yk;
+              comp = (t - s) - yk;
+              s = t;
+            }
+          }
+        }
+        part = (double)s - (double)comp;
+      } else {
+        double s = 0.0;
+        for (int k = lane; k < N; k += 64) {
+          double y = cell_coord(k, N);
+          double r2;
+          {
+#pragma clang fp contract(off)
+            r2 = x * x + y * y;
+          }
+          if (r2 < 1.0) {
+            double mu = sqrt(1.0 - r2);
+            if (nearest_bin(mu, mu_b, B) == b) s += area * limb_dark(mu, u1, u2);
+          }
+        }
+        part = s;
+      }
+      tot = wave_sum(part);
+    }
+    if (lane == 0) colW[(int64_t)i * B + b] = tot;
+  }
+}
+
+// K[b][j] over columns in index order (FP64, deterministic)
+__global__ void k_quiet_collapse(int N, int B, int jmin, int J, const int* __restrict__ col_c,
+                                 const double* __restrict__ col_w, const double* __restrict__ colW,
+                                 double* __restrict__ Kq) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * J) return;
+  int b = t / J;
+  int j = jmin + t % J;
+  double acc = 0.0;
+  for (int i = 0; i < N; ++i) {
+    int c = col_c[i];
+    double w = col_w[i];
+    double W = colW[(int64_t)i * B + b];
+    if (c == j) acc += (1.0 - w) * W;
+    if (c - 1 == j) acc += w * W;
+  }
+  Kq[t] = acc;
+}
+
+template <typename T>
+__global__ void k_quiet(int64_t P, int B, int jmin, int J, const double* __restrict__ Kq,
+                        const T* __restrict__ S, double* __restrict__ Q) {
+  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= P) return;
+  double acc = 0.0;
+  for (int b = 0; b < B; ++b) {
+    const T* row = S + (int64_t)b * P;
+    for (int jj = 0; jj < J; ++jj) {
+      double k = Kq[b * J + jj];
+      if (k != 0.0) {
+        int64_t src = m - (jmin + jj);
+        src = src < 0 ? 0 : (src >= P ? P - 1 : src);
+        acc += k * (double)row[src];
+      }
+    }
+  }
+  Q[m] = acc;
+}
+
+template <typename T>
+__global__ void k_q_convert(int64_t P, const double* __restrict__ Q, T* __restrict__ out) {
+  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < P) out[m] = (T)Q[m];
+}
+
+hipError_t launch_geom(soap_ctx* c) {
+  hipLaunchKernelGGL(k_geom, dim3((c->N + 255) / 256), dim3(256), 0, c->stream, c->N, c->vsini, c->dln,
+                     c->d_col_c, c->d_col_w);
+  return hipGetLastError();
+}
+
+hipError_t launch_contrast(soap_ctx* c) {
+  dim3 grid((unsigned)((c->P + 255) / 256));
+  if (c->prec == SOAP_PREC_FP32)
+    hipLaunchKernelGGL(k_contrast<float>, grid, dim3(256), 0, c->stream, c->P, c->B, c->ln0, c->dln, c->teff,
+                       c->dt_spot, c->dt_fac[0], c->dt_fac[1], c->dt_fac[2], c->d_mu, (float*)c->d_con_spot,
+                       (float*)c->d_con_fac);
+  else
+    hipLaunchKernelGGL(k_contrast<double>, grid, dim3(256), 0, c->stream, c->P, c->B, c->ln0, c->dln, c->teff,
+                       c->dt_spot, c->dt_fac[0], c->dt_fac[1], c->dt_fac[2], c->d_mu, (double*)c->d_con_spot,
+                       (double*)c->d_con_fac);
+  return hipGetLastError();
+}
+
+hipError_t launch_quiet(soap_ctx* c) {
+  if (c->prec == SOAP_PREC_FP32)
+    hipLaunchKernelGGL(k_quiet_colsum<true>, dim3(c->N), dim3(64), 0, c->stream, c->N, c->B, c->u1, c->u2,
+                       c->d_mu, c->d_colW);
+  else
+    hipLaunchKernelGGL(k_quiet_colsum<false>, dim3(c->N), dim3(64), 0, c->stream, c->N, c->B, c->u1, c->u2,
+                       c->d_mu, c->d_colW);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int nt = c->B * c->J;
+  hipLaunchKernelGGL(k_quiet_collapse, dim3((nt + 255) / 256), dim3(256), 0, c->stream, c->N, c->B, c->jmin,
+                     c->J, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)((c->P + 255) / 256));
+  if (c->prec == SOAP_PREC_FP32)
+    hipLaunchKernelGGL(k_quiet<float>, grid, dim3(256), 0, c->stream, c->P, c->B, c->jmin, c->J, c->d_Kq,
+                       (const float*)c->d_spec[SOAP_QUIET], c->d_Q);
+  else
+    hipLaunchKernelGGL(k_quiet<double>, grid, dim3(256), 0, c->stream, c->P, c->B, c->jmin, c->J, c->d_Kq,
+                       (const double*)c->d_spec[SOAP_QUIET], c->d_Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_q_convert(soap_ctx* c, void* out) {
+  dim3 grid((unsigned)((c->P + 255) / 256));
+  hipLaunchKernelGGL(k_q_convert<float>, grid, dim3(256), 0, c->stream, c->P, c->d_Q, (float*)out);
+  return hipGetLastError();
+}
+
+}  // namespace soap

@@ -1,0 +1,605 @@
+// C ABI of libsoap (declarations and documentation in include/soap.h).
+//
+// This file holds argument validation, the context and its device workspace,
+// host <-> device staging and the order of kernel launches.  All arithmetic of
+// the method runs in the kernels of geom.hip, weights.hip, apply.hip and
+// ccf.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "soap_internal.hpp"
+
+#define SOAP_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+thread_local std::string g_init_err;
+
+void setf(std::string& dst, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  dst = buf;
+}
+
+#define ARG_CHECK(cond, ...)        \
+  do {                              \
+    if (!(cond)) {                  \
+      setf(err, __VA_ARGS__);       \
+      return SOAP_ERR_ARG;          \
+    }                               \
+  } while (0)
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      setf(c->err, "%s failed: %s", #expr, hipGetErrorString(e_));                     \
+      return (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation) ? SOAP_ERR_OOM \
+                                                                           : SOAP_ERR_HIP; \
+    }                                                                                  \
+  } while (0)
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+template <typename T>
+bool all_finite_host(const void* p, size_t n) {
+  const T* a = static_cast<const T*>(p);
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite((double)a[i])) return false;
+  return true;
+}
+
+soap_status validate_desc(const soap_star_desc* d, std::string& err) {
+  ARG_CHECK(d != nullptr, "desc is NULL");
+  ARG_CHECK(d->n_grid >= 2 && d->n_grid <= soap::MAX_GRID, "n_grid must be in [2, %d], got %d", soap::MAX_GRID,
+            d->n_grid);
+  ARG_CHECK(d->n_mu >= 1 && d->n_mu <= soap::MAX_MU, "n_mu must be in [1, %d], got %d", soap::MAX_MU, d->n_mu);
+  ARG_CHECK(d->n_pix >= 8 && d->n_pix <= (int64_t(1) << 30), "n_pix must be in [8, 2^30], got %lld",
+            (long long)d->n_pix);
+  ARG_CHECK(d->precision == SOAP_PREC_FP32 || d->precision == SOAP_PREC_FP64, "unknown precision %d",
+            d->precision);
+  ARG_CHECK(d->contrast_mode == SOAP_CONTRAST_SCALAR || d->contrast_mode == SOAP_CONTRAST_PLANCK,
+            "unknown contrast_mode %d", d->contrast_mode);
+  ARG_CHECK(is_finite(d->vsini_kms) && std::fabs(d->vsini_kms) < 0.1 * soap::C_KMS, "vsini_kms out of range");
+  ARG_CHECK(is_finite(d->incl_deg) && d->incl_deg >= 0.0 && d->incl_deg <= 180.0, "incl_deg must be in [0, 180]");
+  ARG_CHECK(is_finite(d->ld_u1) && is_finite(d->ld_u2), "limb-darkening coefficients must be finite");
+  ARG_CHECK(is_finite(d->ln_lambda0), "ln_lambda0 must be finite");
+  ARG_CHECK(is_finite(d->dln_lambda) && d->dln_lambda > 0.0 && d->dln_lambda < 1.0, "dln_lambda must be in (0, 1)");
+  ARG_CHECK(d->mu_bins != nullptr, "mu_bins is NULL");
+  for (int b = 0; b < d->n_mu; ++b) {
+    ARG_CHECK(is_finite(d->mu_bins[b]) && d->mu_bins[b] > 0.0 && d->mu_bins[b] <= 1.0,
+              "mu_bins[%d] must be in (0, 1]", b);
+    if (b) ARG_CHECK(d->mu_bins[b] < d->mu_bins[b - 1], "mu_bins must be strictly decreasing");
+  }
+  ARG_CHECK(d->spectra[SOAP_QUIET] != nullptr, "spectra[SOAP_QUIET] is NULL");
+  if (!d->spectra_on_device) {
+    const size_t n = (size_t)d->n_mu * (size_t)d->n_pix;
+    for (int t = 0; t < 3; ++t) {
+      if (!d->spectra[t]) continue;
+      bool ok = (d->precision == SOAP_PREC_FP32) ? all_finite_host<float>(d->spectra[t], n)
+                                                 : all_finite_host<double>(d->spectra[t], n);
+      ARG_CHECK(ok, "spectra[%d] holds a non-finite value", t);
+    }
+  }
+  if (d->contrast_mode == SOAP_CONTRAST_PLANCK) {
+    ARG_CHECK(is_finite(d->teff_k) && d->teff_k > 100.0, "teff_k must be > 100 K");
+    ARG_CHECK(is_finite(d->dt_spot_k) && d->teff_k - d->dt_spot_k > 100.0, "spot temperature must be > 100 K");
+    for (int b = 0; b < d->n_mu; ++b) {
+      double mu = d->mu_bins[b];
+      double dt = d->dt_fac_coef[0] + d->dt_fac_coef[1] * mu + d->dt_fac_coef[2] * mu * mu;
+      ARG_CHECK(is_finite(dt) && d->teff_k + dt > 100.0, "facula temperature must be > 100 K");
+    }
+  }
+  return SOAP_OK;
+}
+
+hipError_t grow(soap::Workspace& w, size_t bytes) {
+  if (w.bytes >= bytes) return hipSuccess;
+  if (w.ptr) {
+    hipError_t e = hipFree(w.ptr);
+    if (e != hipSuccess) return e;
+    w.ptr = nullptr;
+    w.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&w.ptr, want);
+  if (e == hipSuccess) w.bytes = want;
+  return e;
+}
+
+void free_ws(soap::Workspace& w) {
+  if (w.ptr) (void)hipFree(w.ptr);
+  w.ptr = nullptr;
+  w.bytes = 0;
+}
+
+void destroy_ctx(soap_ctx* c) {
+  if (!c) return;
+  if (c->hip_used) (void)hipStreamSynchronize(c->stream);
+  for (int t = 0; t < 3; ++t)
+    if (c->d_spec[t]) (void)hipFree(c->d_spec[t]);
+  void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_spot, c->d_con_fac};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  soap::Workspace* ws[] = {&c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_ent, &c->ws_flux,
+                           &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
+  for (auto* w : ws) free_ws(*w);
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (int k = 0; k < soap_ctx::NSLOT; ++k) {
+    if (c->slot[k]) (void)hipHostFree(c->slot[k]);
+    if (c->slot_done[k]) (void)hipEventDestroy(c->slot_done[k]);
+  }
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->pinned_done) (void)hipEventDestroy(c->pinned_done);
+  delete c;
+}
+
+soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
+  c->N = d->n_grid;
+  c->B = d->n_mu;
+  c->P = d->n_pix;
+  c->vsini = d->vsini_kms;
+  c->incl = d->incl_deg;
+  c->u1 = d->ld_u1;
+  c->u2 = d->ld_u2;
+  c->ln0 = d->ln_lambda0;
+  c->dln = d->dln_lambda;
+  c->prec = d->precision;
+  c->cmode = d->contrast_mode;
+  c->teff = d->teff_k;
+  c->dt_spot = d->dt_spot_k;
+  for (int i = 0; i < 3; ++i) c->dt_fac[i] = d->dt_fac_coef[i];
+  c->mu_bins.assign(d->mu_bins, d->mu_bins + d->n_mu);
+  c->esize = (c->prec == SOAP_PREC_FP32) ? sizeof(float) : sizeof(double);
+
+  // tap offset range: a bound on the column shifts |s| <= atanh(|vsini| x_max / c) / dln
+  // with one offset of margin on each side, so rounding of the device's
+  // own shift can never leave the table
+  const double xmax = 1.0 - 1.0 / c->N;
+  const double smax = std::atanh(std::fabs(c->vsini) * xmax / soap::C_KMS) / c->dln;
+  c->jmin = -(int)std::floor(smax) - 2;
+  c->jmax = (int)std::ceil(smax) + 1;
+  c->J = c->jmax - c->jmin + 1;
+  std::string& err = c->err;
+  ARG_CHECK(c->J <= 64, "rotation shift of %.1f pixels exceeds the supported 30 pixels", smax);
+  ARG_CHECK(c->P >= 2 * (int64_t)c->J + 4, "n_pix must be at least 2 * (max shift + 3) + 4");
+  const size_t gj_bytes = (size_t)3 * c->B * c->J * sizeof(double);
+  if (gj_bytes > 60 * 1024) {
+    setf(c->err, "n_mu x shift range too large for the per-phase tap table (%zu bytes)", gj_bytes);
+    return SOAP_ERR_UNSUPPORTED;
+  }
+
+  c->hip_used = true;
+  HIP_TRY(hipGetDevice(&c->device));
+  const size_t row_bytes = (size_t)c->P * c->esize;
+  hipMemcpyKind kind = d->spectra_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  for (int t = 0; t < 3; ++t) {
+    if (!d->spectra[t]) continue;
+    HIP_TRY(hipMalloc(&c->d_spec[t], row_bytes * c->B));
+    HIP_TRY(hipMemcpyAsync(c->d_spec[t], d->spectra[t], row_bytes * c->B, kind, c->stream));
+    c->has_type[t] = true;
+  }
+  HIP_TRY(hipMalloc((void**)&c->d_mu, sizeof(double) * c->B));
+  HIP_TRY(hipMemcpyAsync(c->d_mu, d->mu_bins, sizeof(double) * c->B, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMalloc((void**)&c->d_col_c, sizeof(int) * c->N));
+  HIP_TRY(hipMalloc((void**)&c->d_col_w, sizeof(double) * c->N));
+  HIP_TRY(hipMalloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
+  HIP_TRY(hipMalloc((void**)&c->d_Kq, sizeof(double) * c->B * c->J));
+  HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->P));
+  if (c->cmode == SOAP_CONTRAST_PLANCK) {
+    HIP_TRY(hipMalloc(&c->d_con_spot, row_bytes));
+    HIP_TRY(hipMalloc(&c->d_con_fac, row_bytes * c->B));
+  }
+  HIP_TRY(hipEventCreateWithFlags(&c->pinned_done, hipEventDisableTiming));
+  for (int k = 0; k < soap_ctx::NSLOT; ++k) HIP_TRY(hipEventCreateWithFlags(&c->slot_done[k], hipEventDisableTiming));
+
+  HIP_TRY(soap::launch_geom(c));
+  if (c->cmode == SOAP_CONTRAST_PLANCK) HIP_TRY(soap::launch_contrast(c));
+  HIP_TRY(soap::launch_quiet(c));
+  // host arrays (mu bins, spectra) may be released once the call returns
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SOAP_OK;
+}
+
+// copy a small host block to device memory through pinned staging; the host
+// waits for the previous staging copy before overwriting the buffer
+soap_status stage_to_device(soap_ctx* c, const void* src, size_t bytes, void* dst) {
+  if (c->pinned_bytes < bytes) {
+    HIP_TRY(hipEventSynchronize(c->pinned_done));
+    if (c->pinned) HIP_TRY(hipHostFree(c->pinned));
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+    size_t want = std::max<size_t>(bytes, 64 * 1024);
+    HIP_TRY(hipHostMalloc(&c->pinned, want, hipHostMallocDefault));
+    c->pinned_bytes = want;
+  } else {
+    HIP_TRY(hipEventSynchronize(c->pinned_done));
+  }
+  std::memcpy(c->pinned, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst, c->pinned, bytes, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipEventRecord(c->pinned_done, c->stream));
+  return SOAP_OK;
+}
+
+// brackets one stage with events on the context stream when profiling is on
+struct StageTimer {
+  soap_ctx* c;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(soap_ctx* c_, int s) : c(c_), stage(s) {
+    if (c->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, c->stream);
+  }
+  void done() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, c->stream) == hipSuccess) {
+      c->pending.push_back({stage, a, b});
+    } else {
+      (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+    a = nullptr;
+  }
+};
+
+enum { ST_WEIGHTS = 0, ST_COMPACT = 1, ST_APPLY = 2, ST_CCF = 3, ST_GFIT = 4 };
+
+}  // namespace
+
+SOAP_API int32_t soap_abi_version(void) { return SOAP_ABI_VERSION; }
+
+SOAP_API const char* soap_status_string(soap_status s) {
+  switch (s) {
+    case SOAP_OK: return "SOAP_OK";
+    case SOAP_ERR_ARG: return "SOAP_ERR_ARG";
+    case SOAP_ERR_OOM: return "SOAP_ERR_OOM";
+    case SOAP_ERR_HIP: return "SOAP_ERR_HIP";
+    case SOAP_ERR_STATE: return "SOAP_ERR_STATE";
+    case SOAP_ERR_NOCONV: return "SOAP_ERR_NOCONV";
+    case SOAP_ERR_UNSUPPORTED: return "SOAP_ERR_UNSUPPORTED";
+  }
+  return "unknown soap_status";
+}
+
+SOAP_API const char* soap_last_error(const soap_ctx* c) {
+  if (!c) return g_init_err.c_str();
+  return c->err.c_str();
+}
+
+SOAP_API soap_status soap_grid_init(const soap_star_desc* desc, void* hip_stream, soap_ctx** out) {
+  if (!out) {
+    g_init_err = "out is NULL";
+    return SOAP_ERR_ARG;
+  }
+  *out = nullptr;
+  {
+    std::string err;
+    soap_status st = validate_desc(desc, err);
+    if (st != SOAP_OK) {
+      g_init_err = err;
+      return st;
+    }
+  }
+  soap_ctx* c = new (std::nothrow) soap_ctx();
+  if (!c) {
+    g_init_err = "host allocation of the context failed";
+    return SOAP_ERR_OOM;
+  }
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  soap_status st = init_impl(desc, c);
+  if (st != SOAP_OK) {
+    g_init_err = c->err;
+    destroy_ctx(c);
+    return st;
+  }
+  *out = c;
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_quiet_spectrum(soap_ctx* c, void* out, int32_t out_on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(out != nullptr, "out is NULL");
+  const size_t bytes = (size_t)c->P * c->esize;
+  void* dst = out;
+  if (!out_on_device) {
+    HIP_TRY(grow(c->ws_flux, bytes));
+    dst = c->ws_flux.ptr;
+  }
+  if (c->prec == SOAP_PREC_FP64)
+    HIP_TRY(hipMemcpyAsync(dst, c->d_Q, bytes, hipMemcpyDeviceToDevice, c->stream));
+  else
+    HIP_TRY(soap::launch_q_convert(c, dst));
+  if (!out_on_device) {
+    HIP_TRY(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions, int32_t n_regions,
+                                         const double* phases, int32_t n_phases, int32_t effect, void* flux,
+                                         int32_t flux_on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(n_regions >= 0 && n_regions <= soap::MAX_REGIONS, "n_regions must be in [0, %d]", soap::MAX_REGIONS);
+  ARG_CHECK(n_regions == 0 || regions != nullptr, "regions is NULL");
+  ARG_CHECK(n_phases >= 1 && n_phases <= soap::MAX_PHASES, "n_phases must be in [1, %d]", soap::MAX_PHASES);
+  ARG_CHECK(phases != nullptr, "phases is NULL");
+  ARG_CHECK(effect == SOAP_EFFECT_TOT || effect == SOAP_EFFECT_FLUX || effect == SOAP_EFFECT_BCONV,
+            "unknown effect %d", effect);
+  ARG_CHECK(flux != nullptr, "flux is NULL");
+  for (int p = 0; p < n_phases; ++p) ARG_CHECK(is_finite(phases[p]), "phases[%d] is not finite", p);
+  for (int r = 0; r < n_regions; ++r) {
+    const soap_region& R = regions[r];
+    ARG_CHECK(R.type == SOAP_SPOT || R.type == SOAP_FACULA, "regions[%d].type must be SOAP_SPOT or SOAP_FACULA",
+              r);
+    ARG_CHECK(is_finite(R.lat_deg) && R.lat_deg >= -90.0 && R.lat_deg <= 90.0, "regions[%d].lat_deg out of range", r);
+    ARG_CHECK(is_finite(R.lon_deg), "regions[%d].lon_deg is not finite", r);
+    ARG_CHECK(is_finite(R.radius) && R.radius > 0.0 && R.radius < 1.0, "regions[%d].radius must be in (0, 1)", r);
+    ARG_CHECK(is_finite(R.contrast) && R.contrast > 0.0, "regions[%d].contrast must be > 0", r);
+    if (effect != SOAP_EFFECT_FLUX)
+      ARG_CHECK(c->has_type[R.type], "regions[%d] has type %d but the star has no spectra of that type", r, R.type);
+  }
+  const int G = 3 * c->B;
+  const int n_chunks = (n_phases + soap::APPLY_PC - 1) / soap::APPLY_PC;
+  const int nwin = (c->J + soap::APPLY_JW - 1) / soap::APPLY_JW;
+  const int vg_cap = G * nwin;
+  const int ent_cap = vg_cap * soap::APPLY_PC * 2;
+  const size_t ent_bytes = (c->prec == SOAP_PREC_FP32) ? sizeof(soap::Entry<float>) : sizeof(soap::Entry<double>);
+
+  // parameter block (regions then phases) in the next pinned slot; the
+  // weights kernel reads it in place
+  const size_t reg_bytes = sizeof(soap::Region) * soap::MAX_REGIONS;
+  const size_t par_bytes = reg_bytes + sizeof(double) * n_phases;
+  HIP_TRY(grow(c->ws_K, sizeof(double) * (size_t)n_phases * G * c->J));
+  HIP_TRY(grow(c->ws_vg, sizeof(soap::VGroup) * (size_t)n_chunks * vg_cap));
+  HIP_TRY(grow(c->ws_nvg, sizeof(int) * (size_t)n_chunks));
+  HIP_TRY(grow(c->ws_ent, ent_bytes * (size_t)n_chunks * ent_cap));
+  const size_t out_bytes = (size_t)n_phases * c->P * c->esize;
+  void* dflux = flux;
+  const size_t vec_align = soap::APPLY_R * c->esize;
+  if (!flux_on_device || (reinterpret_cast<uintptr_t>(flux) % vec_align) != 0) {
+    HIP_TRY(grow(c->ws_flux, out_bytes));
+    dflux = c->ws_flux.ptr;
+  }
+  const int k = c->slot_next;
+  c->slot_next = (k + 1) % soap_ctx::NSLOT;
+  HIP_TRY(hipEventSynchronize(c->slot_done[k]));
+  if (c->slot_bytes[k] < par_bytes) {
+    if (c->slot[k]) HIP_TRY(hipHostFree(c->slot[k]));
+    c->slot[k] = nullptr;
+    c->slot_bytes[k] = 0;
+    const size_t want = std::max<size_t>(par_bytes, 16 * 1024);
+    HIP_TRY(hipHostMalloc(&c->slot[k], want, hipHostMallocMapped | hipHostMallocCoherent));
+    c->slot_bytes[k] = want;
+  }
+  unsigned char* host = static_cast<unsigned char*>(c->slot[k]);
+  soap::Region* hr = reinterpret_cast<soap::Region*>(host);
+  for (int r = 0; r < n_regions; ++r) {
+    hr[r].type = regions[r].type;
+    hr[r].pad = 0;
+    hr[r].lat_deg = regions[r].lat_deg;
+    hr[r].lon_deg = regions[r].lon_deg;
+    hr[r].radius = regions[r].radius;
+    hr[r].contrast = regions[r].contrast;
+  }
+  std::memcpy(host + reg_bytes, phases, sizeof(double) * n_phases);
+  void* dev_view = nullptr;
+  HIP_TRY(hipHostGetDevicePointer(&dev_view, c->slot[k], 0));
+  const soap::Region* d_reg = static_cast<const soap::Region*>(dev_view);
+  const double* d_ph = reinterpret_cast<const double*>(static_cast<const unsigned char*>(dev_view) + reg_bytes);
+
+  double* dK = static_cast<double*>(c->ws_K.ptr);
+  {
+    StageTimer t(c, ST_WEIGHTS);
+    HIP_TRY(soap::launch_weights(c, d_reg, n_regions, d_ph, n_phases, effect, dK));
+    t.done();
+  }
+  HIP_TRY(hipEventRecord(c->slot_done[k], c->stream));
+  {
+    StageTimer t(c, ST_COMPACT);
+    HIP_TRY(soap::launch_compact(c, dK, n_phases, static_cast<soap::VGroup*>(c->ws_vg.ptr),
+                                 static_cast<int*>(c->ws_nvg.ptr), c->ws_ent.ptr, vg_cap, ent_cap));
+    t.done();
+  }
+  {
+    StageTimer t(c, ST_APPLY);
+    HIP_TRY(soap::launch_apply(c, static_cast<const soap::VGroup*>(c->ws_vg.ptr),
+                               static_cast<const int*>(c->ws_nvg.ptr), c->ws_ent.ptr, vg_cap, ent_cap, n_phases,
+                               effect, dflux));
+    t.done();
+  }
+  c->active_calls++;
+  c->last_phases = n_phases;
+  c->last_effect = effect;
+  c->last_vg_cap = vg_cap;
+  if (dflux != flux) {
+    HIP_TRY(hipMemcpyAsync(flux, dflux, out_bytes, flux_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream));
+    if (!flux_on_device) HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_device, int64_t n_spec,
+                                 const soap_mask* mask, double* ccf_out, int32_t ccf_on_device, soap_rv* rv_out,
+                                 int32_t rv_on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(flux != nullptr, "flux is NULL");
+  ARG_CHECK(n_spec >= 1 && n_spec <= (int64_t(1) << 24), "n_spec must be in [1, 2^24]");
+  ARG_CHECK(mask != nullptr, "mask is NULL");
+  ARG_CHECK(mask->n_lines >= 1 && mask->n_lines <= (int64_t(1) << 20), "mask.n_lines must be in [1, 2^20]");
+  ARG_CHECK(mask->ln_lambda != nullptr && mask->weight != nullptr, "mask arrays are NULL");
+  ARG_CHECK(mask->n_v >= 4 && mask->n_v <= 1024, "mask.n_v must be in [4, 1024]");
+  ARG_CHECK(is_finite(mask->v0_kms) && is_finite(mask->dv_kms) && mask->dv_kms > 0.0, "mask velocity grid invalid");
+  ARG_CHECK(is_finite(mask->half_width_kms) && mask->half_width_kms > 0.0, "mask.half_width_kms must be > 0");
+  const double vlo = mask->v0_kms - mask->half_width_kms;
+  const double vhi = mask->v0_kms + mask->dv_kms * (mask->n_v - 1) + mask->half_width_kms;
+  ARG_CHECK(std::fabs(vlo) < 0.1 * soap::C_KMS && std::fabs(vhi) < 0.1 * soap::C_KMS,
+            "mask velocity grid beyond 0.1 c");
+  const double hole_px = 2.0 * std::atanh(mask->half_width_kms / soap::C_KMS) / c->dln;
+  if (hole_px > 8.0) {
+    setf(c->err, "mask holes of %.2f pixels exceed the supported 8 pixels", hole_px);
+    return SOAP_ERR_UNSUPPORTED;
+  }
+  const int nl = (int)mask->n_lines;
+  for (int l = 0; l < nl; ++l)
+    ARG_CHECK(is_finite(mask->ln_lambda[l]) && is_finite(mask->weight[l]), "mask line %d is not finite", l);
+
+  // mask upload when it differs from the cached one
+  bool same = c->mask_valid && (int)c->mask_lnl.size() == nl && c->mask_h == mask->half_width_kms &&
+              c->mask_v0 == mask->v0_kms && c->mask_dv == mask->dv_kms && c->mask_nv == mask->n_v &&
+              std::memcmp(c->mask_lnl.data(), mask->ln_lambda, sizeof(double) * nl) == 0 &&
+              std::memcmp(c->mask_w.data(), mask->weight, sizeof(double) * nl) == 0;
+  if (!same) {
+    c->mask_valid = false;
+    HIP_TRY(grow(c->ws_mask, sizeof(double) * 4 * (size_t)nl));
+    std::vector<double> host(2 * (size_t)nl);
+    std::memcpy(host.data(), mask->ln_lambda, sizeof(double) * nl);
+    std::memcpy(host.data() + nl, mask->weight, sizeof(double) * nl);
+    double* raw = static_cast<double*>(c->ws_mask.ptr) + 2 * (size_t)nl;  // staging half
+    soap_status st = stage_to_device(c, host.data(), sizeof(double) * 2 * nl, raw);
+    if (st != SOAP_OK) return st;
+    HIP_TRY(soap::launch_mask_prep(c, raw, raw + nl, nl, static_cast<double*>(c->ws_mask.ptr)));
+    c->mask_lnl.assign(mask->ln_lambda, mask->ln_lambda + nl);
+    c->mask_w.assign(mask->weight, mask->weight + nl);
+    c->mask_h = mask->half_width_kms;
+    c->mask_v0 = mask->v0_kms;
+    c->mask_dv = mask->dv_kms;
+    c->mask_nv = mask->n_v;
+    c->mask_valid = true;
+  }
+
+  const void* dflux = flux;
+  const size_t in_bytes = (size_t)n_spec * c->P * c->esize;
+  if (!flux_on_device) {
+    HIP_TRY(grow(c->ws_specin, in_bytes));
+    HIP_TRY(hipMemcpyAsync(c->ws_specin.ptr, flux, in_bytes, hipMemcpyHostToDevice, c->stream));
+    dflux = c->ws_specin.ptr;
+  }
+  const int nlb = soap::ccf_line_blocks(nl);
+  const size_t ccf_elems = (size_t)n_spec * c->mask_nv;
+  HIP_TRY(grow(c->ws_ccf, sizeof(double) * ccf_elems * nlb));
+  double* dccf = (ccf_out && ccf_on_device) ? ccf_out : nullptr;
+  if (!dccf) {
+    HIP_TRY(grow(c->ws_ccfout, sizeof(double) * ccf_elems));
+    dccf = static_cast<double*>(c->ws_ccfout.ptr);
+  }
+  {
+    StageTimer t(c, ST_CCF);
+    HIP_TRY(soap::launch_ccf(c, dflux, n_spec, static_cast<const double*>(c->ws_mask.ptr), nl,
+                             static_cast<double*>(c->ws_ccf.ptr), dccf));
+    t.done();
+  }
+  c->ccf_calls++;
+  bool sync = false;
+  if (rv_out) {
+    soap_rv* drv = rv_on_device ? rv_out : nullptr;
+    if (!drv) {
+      HIP_TRY(grow(c->ws_rv, sizeof(soap_rv) * (size_t)n_spec));
+      drv = static_cast<soap_rv*>(c->ws_rv.ptr);
+    }
+    {
+      StageTimer t(c, ST_GFIT);
+      HIP_TRY(soap::launch_gfit(c, dccf, n_spec, drv));
+      t.done();
+    }
+    if (!rv_on_device) {
+      HIP_TRY(hipMemcpyAsync(rv_out, drv, sizeof(soap_rv) * n_spec, hipMemcpyDeviceToHost, c->stream));
+      sync = true;
+    }
+  }
+  if (ccf_out && !ccf_on_device) {
+    HIP_TRY(hipMemcpyAsync(ccf_out, dccf, sizeof(double) * ccf_elems, hipMemcpyDeviceToHost, c->stream));
+    sync = true;
+  }
+  if (sync || !flux_on_device) HIP_TRY(hipStreamSynchronize(c->stream));
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_profile_enable(soap_ctx* c, int32_t on) {
+  if (!c) return SOAP_ERR_ARG;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c->pending.clear();
+  for (double& v : c->stage_ms) v = 0.0;
+  c->active_calls = c->ccf_calls = 0;
+  c->prof = on != 0;
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(out != nullptr, "out is NULL");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, p.a, p.b);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+    if (e == hipSuccess) c->stage_ms[p.stage] += ms;
+  }
+  c->pending.clear();
+  out->weights_ms = c->stage_ms[ST_WEIGHTS];
+  out->compact_ms = c->stage_ms[ST_COMPACT];
+  out->apply_ms = c->stage_ms[ST_APPLY];
+  out->ccf_ms = c->stage_ms[ST_CCF];
+  out->gfit_ms = c->stage_ms[ST_GFIT];
+  out->active_calls = c->active_calls;
+  out->ccf_calls = c->ccf_calls;
+  out->src_arrays = out->con_arrays = 0;
+  out->last_phases = c->last_phases;
+  if (c->last_phases > 0) {
+    // distinct inputs the last apply walked, from its virtual-group lists
+    const int n_chunks = (c->last_phases + soap::APPLY_PC - 1) / soap::APPLY_PC;
+    std::vector<int> nvg(n_chunks);
+    std::vector<soap::VGroup> vg((size_t)n_chunks * c->last_vg_cap);
+    HIP_TRY(hipMemcpy(nvg.data(), c->ws_nvg.ptr, sizeof(int) * n_chunks, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vg.data(), c->ws_vg.ptr, sizeof(soap::VGroup) * vg.size(), hipMemcpyDeviceToHost));
+    std::vector<char> src(3 * c->B, 0), con(3 * c->B, 0);
+    for (int ch = 0; ch < n_chunks; ++ch)
+      for (int v = 0; v < nvg[ch]; ++v) {
+        const int g = vg[(size_t)ch * c->last_vg_cap + v].g;
+        const int t = g / c->B, b = g % c->B;
+        if (t == 0) {
+          src[b] = 1;
+          continue;
+        }
+        const bool planck = c->cmode == SOAP_CONTRAST_PLANCK;
+        if (c->last_effect == SOAP_EFFECT_FLUX) src[b] = 1;
+        else src[t * c->B + b] = 1;
+        // spot contrast is one array for every bin, facula one per bin
+        if (planck && c->last_effect != SOAP_EFFECT_BCONV) con[t == SOAP_SPOT ? SOAP_SPOT * c->B : t * c->B + b] = 1;
+      }
+    for (char x : src) out->src_arrays += x;
+    for (char x : con) out->con_arrays += x;
+  }
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_sync(soap_ctx* c) {
+  if (!c) return SOAP_ERR_ARG;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return SOAP_OK;
+}
+
+SOAP_API void soap_destroy(soap_ctx* c) { destroy_ctx(c); }
