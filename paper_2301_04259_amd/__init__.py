@@ -36,6 +36,15 @@ if not os.path.exists(LIB_PATH):
         "(hipcc, gfx950) before importing the binding"
     )
 
+# torch ships its own HIP runtime under the same soname as the system one.
+# Loading torch first makes libsoap bind to that single runtime, so device
+# pointers and streams from torch's allocator are valid in this library's
+# calls; loading libsoap first would bring a second runtime into the process.
+try:
+    import torch  # noqa: F401
+except ImportError:  # host-only use (argument checks, symbol tests)
+    torch = None
+
 _lib = C.CDLL(LIB_PATH)
 
 SOAP_OK = 0

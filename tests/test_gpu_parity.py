@@ -1,7 +1,10 @@
 """GPU parity: libsoap (through the C ABI) against the FP64 CPU oracle.
 
 Flux bar (per pixel): |F_gpu - F_oracle| <= 1e-6 * max(|F_oracle|, 1e-3 * max|F_oracle|).
-RV bar: |RV_gpu - RV_oracle| <= 1 cm/s.  FP64 contexts are held to 1e-11.
+RV bar: |RV_gpu - RV_oracle| <= 1 cm/s.  FP64 contexts are held to 1e-9: the
+oracle evaluates Eq. 11 in absolute wavelengths, where lambda_m - lambda'_n
+(~lambda * dln) keeps about eps / dln ~ 5e-11 of relative precision, so
+agreement below ~1e-10 is not expected from either side's arithmetic.
 The oracle receives exactly the arrays the GPU receives (FP32 inputs are
 upcast), so input rounding is not charged to the GPU.
 """
@@ -22,7 +25,7 @@ torch = pytest.importorskip("torch")
 L = pytest.importorskip("paper_2301_04259_amd", reason="libsoap.so not built")
 
 FLUX_REL = 1e-6
-FLUX_REL_FP64 = 1e-11
+FLUX_REL_FP64 = 1e-9
 RV_CMS = 1.0
 
 
@@ -100,7 +103,8 @@ def test_quiet_spectrum_matches_oracle():
         torch.cuda.synchronize()
         want = OS.quiet(star)
         bar = FLUX_REL_FP64 if prec == W.PREC_FP64 else FLUX_REL
-        assert _flux_err(q.cpu().numpy(), want) <= bar
+        err = _flux_err(q.cpu().numpy(), want)
+        assert err <= bar, err
         assert np.array_equal(q.cpu().numpy(), qh)
 
 
@@ -266,7 +270,11 @@ def test_ccf_and_fit_match_oracle_on_same_flux():
     L.soap_ccf_rv(ctx, out, m, ccf_out=ccf, rv_out=rv)
     torch.cuda.synchronize()
     c_or, rv_or = _rv_oracle(star, out.cpu().numpy().astype(np.float64))
-    assert np.allclose(ccf.cpu().numpy(), c_or, rtol=1e-10, atol=0)
+    # the oracle places hole edges with log(1 + f) of a number within 1e-5 of
+    # one: ~1e-16 absolute in ln(lambda), i.e. ~5e-11 pixel; CCF values agree
+    # to ~1e-10 relative
+    rel = np.max(np.abs(ccf.cpu().numpy() - c_or) / np.abs(c_or))
+    assert rel < 1e-9, rel
     assert np.all(rv["status"] == 0)
     assert np.max(np.abs(rv["rv_kms"] - rv_or)) * 1e5 < 1e-3  # same CCF: fits agree to 1e-3 cm/s
 
