@@ -53,20 +53,35 @@ __global__ void k_geom(int N, double vsini, double dln, int* __restrict__ col_c,
   col_w[i] = expm1(u * dln) / expm1(dln);
 }
 
+// contrast arrays over whole padded rows: pad entries hold the end values
 template <typename T>
-__global__ void k_contrast(int64_t P, int B, double ln0, double dln, double teff, double dts, double f0,
-                           double f1, double f2, const double* __restrict__ mu_b, T* __restrict__ con_spot,
-                           T* __restrict__ con_fac) {
-  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= P) return;
+__global__ void k_contrast(int64_t P, int64_t Pstride, int B, double ln0, double dln, double teff, double dts,
+                           double f0, double f1, double f2, const double* __restrict__ mu_b,
+                           T* __restrict__ con_spot, T* __restrict__ con_fac) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // index in the padded row
+  if (i >= Pstride) return;
+  int64_t m = i - PAD_FRONT;
+  m = m < 0 ? 0 : (m >= P ? P - 1 : m);
   double lam = exp(ln0 + dln * (double)m) * 1e-10;
   double eref = expm1(C2_MK / (lam * teff));
-  con_spot[m] = (T)(eref / expm1(C2_MK / (lam * (teff - dts))));
+  con_spot[i] = (T)(eref / expm1(C2_MK / (lam * (teff - dts))));
   for (int b = 0; b < B; ++b) {
     double mu = mu_b[b];
     double dt = f0 + f1 * mu + f2 * mu * mu;
-    con_fac[(int64_t)b * P + m] = (T)(eref / expm1(C2_MK / (lam * (teff + dt))));
+    con_fac[(int64_t)b * Pstride + i] = (T)(eref / expm1(C2_MK / (lam * (teff + dt))));
   }
+}
+
+// fill the pads of every row with the row's first / last sample
+template <typename T>
+__global__ void k_pad(int64_t P, int64_t Pstride, int rows, T* __restrict__ base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  if (row >= rows || i >= Pstride) return;
+  T* r = base + (int64_t)row * Pstride;
+  const int64_t m = i - PAD_FRONT;
+  if (m < 0) r[i] = r[PAD_FRONT];
+  else if (m >= P) r[i] = r[PAD_FRONT + P - 1];
 }
 
 // one wave64 per disk column: W[i][b] = sum_{cells of column i in bin b} A I
@@ -161,13 +176,17 @@ __global__ void k_quiet_collapse(int N, int B, int jmin, int J, const int* __res
 }
 
 template <typename T>
-__global__ void k_quiet(int64_t P, int B, int jmin, int J, const double* __restrict__ Kq,
-                        const T* __restrict__ S, double* __restrict__ Q) {
+__global__ void k_quiet(int64_t P, int64_t Pstride, int64_t Qlen, int B, int jmin, int J,
+                        const double* __restrict__ Kq, const T* __restrict__ S, double* __restrict__ Q) {
   int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= P) return;
+  if (m >= Qlen) return;
+  if (m >= P) {
+    Q[m] = 0.0;
+    return;
+  }
   double acc = 0.0;
   for (int b = 0; b < B; ++b) {
-    const T* row = S + (int64_t)b * P;
+    const T* row = S + (int64_t)b * Pstride;
     for (int jj = 0; jj < J; ++jj) {
       double k = Kq[b * J + jj];
       if (k != 0.0) {
@@ -193,16 +212,33 @@ hipError_t launch_geom(soap_ctx* c) {
 }
 
 hipError_t launch_contrast(soap_ctx* c) {
-  dim3 grid((unsigned)((c->P + 255) / 256));
+  dim3 grid((unsigned)((c->Pstride + 255) / 256));
+  // the pointers address pixel 0; the kernel writes whole padded rows
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_contrast<float>, grid, dim3(256), 0, c->stream, c->P, c->B, c->ln0, c->dln, c->teff,
-                       c->dt_spot, c->dt_fac[0], c->dt_fac[1], c->dt_fac[2], c->d_mu, (float*)c->d_con_spot,
-                       (float*)c->d_con_fac);
+    hipLaunchKernelGGL(k_contrast<float>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, c->B, c->ln0, c->dln,
+                       c->teff, c->dt_spot, c->dt_fac[0], c->dt_fac[1], c->dt_fac[2], c->d_mu,
+                       (float*)c->d_con_spot - PAD_FRONT, (float*)c->d_con_fac - PAD_FRONT);
   else
-    hipLaunchKernelGGL(k_contrast<double>, grid, dim3(256), 0, c->stream, c->P, c->B, c->ln0, c->dln, c->teff,
-                       c->dt_spot, c->dt_fac[0], c->dt_fac[1], c->dt_fac[2], c->d_mu, (double*)c->d_con_spot,
-                       (double*)c->d_con_fac);
+    hipLaunchKernelGGL(k_contrast<double>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, c->B, c->ln0, c->dln,
+                       c->teff, c->dt_spot, c->dt_fac[0], c->dt_fac[1], c->dt_fac[2], c->d_mu,
+                       (double*)c->d_con_spot - PAD_FRONT, (double*)c->d_con_fac - PAD_FRONT);
   return hipGetLastError();
+}
+
+hipError_t launch_pad(soap_ctx* c) {
+  for (int t = 0; t < 3; ++t) {
+    if (!c->d_spec_base[t]) continue;
+    dim3 grid((unsigned)((c->Pstride + 255) / 256), c->B);
+    if (c->prec == SOAP_PREC_FP32)
+      hipLaunchKernelGGL(k_pad<float>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, c->B,
+                         (float*)c->d_spec_base[t]);
+    else
+      hipLaunchKernelGGL(k_pad<double>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, c->B,
+                         (double*)c->d_spec_base[t]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_quiet(soap_ctx* c) {
@@ -219,13 +255,14 @@ hipError_t launch_quiet(soap_ctx* c) {
                      c->J, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)((c->P + 255) / 256));
+  const int64_t qlen = (int64_t)c->n_tiles * APPLY_TILE;
+  dim3 grid((unsigned)((qlen + 255) / 256));
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_quiet<float>, grid, dim3(256), 0, c->stream, c->P, c->B, c->jmin, c->J, c->d_Kq,
-                       (const float*)c->d_spec[SOAP_QUIET], c->d_Q);
+    hipLaunchKernelGGL(k_quiet<float>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, qlen, c->B, c->jmin,
+                       c->J, c->d_Kq, (const float*)c->d_spec[SOAP_QUIET], c->d_Q);
   else
-    hipLaunchKernelGGL(k_quiet<double>, grid, dim3(256), 0, c->stream, c->P, c->B, c->jmin, c->J, c->d_Kq,
-                       (const double*)c->d_spec[SOAP_QUIET], c->d_Q);
+    hipLaunchKernelGGL(k_quiet<double>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, qlen, c->B, c->jmin,
+                       c->J, c->d_Kq, (const double*)c->d_spec[SOAP_QUIET], c->d_Q);
   return hipGetLastError();
 }
 

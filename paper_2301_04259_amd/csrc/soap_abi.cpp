@@ -127,11 +127,11 @@ void destroy_ctx(soap_ctx* c) {
   if (!c) return;
   if (c->hip_used) (void)hipStreamSynchronize(c->stream);
   for (int t = 0; t < 3; ++t)
-    if (c->d_spec[t]) (void)hipFree(c->d_spec[t]);
-  void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_spot, c->d_con_fac};
+    if (c->d_spec_base[t]) (void)hipFree(c->d_spec_base[t]);
+  void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
-  soap::Workspace* ws[] = {&c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_ent, &c->ws_flux,
+  soap::Workspace* ws[] = {&c->ws_Kp, &c->ws_slab, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_ent, &c->ws_flux,
                            &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
   for (auto* w : ws) free_ws(*w);
   for (auto& p : c->pending) {
@@ -176,7 +176,7 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   std::string& err = c->err;
   ARG_CHECK(c->J <= 64, "rotation shift of %.1f pixels exceeds the supported 30 pixels", smax);
   ARG_CHECK(c->P >= 2 * (int64_t)c->J + 4, "n_pix must be at least 2 * (max shift + 3) + 4");
-  const size_t gj_bytes = (size_t)3 * c->B * c->J * sizeof(double);
+  const size_t gj_bytes = (size_t)3 * c->B * c->J * sizeof(double) + 192 * sizeof(int);
   if (gj_bytes > 60 * 1024) {
     setf(c->err, "n_mu x shift range too large for the per-phase tap table (%zu bytes)", gj_bytes);
     return SOAP_ERR_UNSUPPORTED;
@@ -184,12 +184,20 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
 
   c->hip_used = true;
   HIP_TRY(hipGetDevice(&c->device));
-  const size_t row_bytes = (size_t)c->P * c->esize;
+  c->pc = (c->prec == SOAP_PREC_FP32) ? soap::PC_F32 : soap::PC_F64;
+  c->n_tiles = (int)((c->P + soap::APPLY_TILE - 1) / soap::APPLY_TILE);
+  // padded rows: PAD_FRONT samples before pixel 0, and past the last tile
+  // enough room for the widest window the apply kernel reads
+  const int64_t tail = (int64_t)c->n_tiles * soap::APPLY_TILE + 2 * soap::MAX_J + 64;
+  c->Pstride = ((soap::PAD_FRONT + tail + 63) / 64) * 64;
+  const size_t row_bytes = (size_t)c->Pstride * c->esize;
   hipMemcpyKind kind = d->spectra_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   for (int t = 0; t < 3; ++t) {
     if (!d->spectra[t]) continue;
-    HIP_TRY(hipMalloc(&c->d_spec[t], row_bytes * c->B));
-    HIP_TRY(hipMemcpyAsync(c->d_spec[t], d->spectra[t], row_bytes * c->B, kind, c->stream));
+    HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B));
+    c->d_spec[t] = static_cast<unsigned char*>(c->d_spec_base[t]) + soap::PAD_FRONT * c->esize;
+    HIP_TRY(hipMemcpy2DAsync(c->d_spec[t], row_bytes, d->spectra[t], (size_t)c->P * c->esize,
+                             (size_t)c->P * c->esize, c->B, kind, c->stream));
     c->has_type[t] = true;
   }
   HIP_TRY(hipMalloc((void**)&c->d_mu, sizeof(double) * c->B));
@@ -198,14 +206,16 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   HIP_TRY(hipMalloc((void**)&c->d_col_w, sizeof(double) * c->N));
   HIP_TRY(hipMalloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
   HIP_TRY(hipMalloc((void**)&c->d_Kq, sizeof(double) * c->B * c->J));
-  HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->P));
+  HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE));
   if (c->cmode == SOAP_CONTRAST_PLANCK) {
-    HIP_TRY(hipMalloc(&c->d_con_spot, row_bytes));
-    HIP_TRY(hipMalloc(&c->d_con_fac, row_bytes * c->B));
+    HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * (c->B + 1)));
+    c->d_con_spot = static_cast<unsigned char*>(c->d_con_base) + soap::PAD_FRONT * c->esize;
+    c->d_con_fac = static_cast<unsigned char*>(c->d_con_spot) + row_bytes;
   }
   HIP_TRY(hipEventCreateWithFlags(&c->pinned_done, hipEventDisableTiming));
   for (int k = 0; k < soap_ctx::NSLOT; ++k) HIP_TRY(hipEventCreateWithFlags(&c->slot_done[k], hipEventDisableTiming));
 
+  HIP_TRY(soap::launch_pad(c));
   HIP_TRY(soap::launch_geom(c));
   if (c->cmode == SOAP_CONTRAST_PLANCK) HIP_TRY(soap::launch_contrast(c));
   HIP_TRY(soap::launch_quiet(c));
@@ -354,25 +364,36 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
     if (effect != SOAP_EFFECT_FLUX)
       ARG_CHECK(c->has_type[R.type], "regions[%d] has type %d but the star has no spectra of that type", r, R.type);
   }
-  const int G = 3 * c->B;
-  const int n_chunks = (n_phases + soap::APPLY_PC - 1) / soap::APPLY_PC;
-  const int nwin = (c->J + soap::APPLY_JW - 1) / soap::APPLY_JW;
-  const int vg_cap = G * nwin;
-  const int ent_cap = vg_cap * soap::APPLY_PC * 2;
+  // per-call plan: paired tables when every active weight equals its
+  // removal weight (chromatic contrast, the convective effect, or unit
+  // scalar contrasts); otherwise split tables with explicit removal rows
+  soap::Plan pl;
+  pl.n_ph = n_phases;
+  pl.effect = effect;
+  bool unit = true;
+  for (int r = 0; r < n_regions; ++r) unit = unit && regions[r].contrast == 1.0;
+  pl.paired = (c->cmode == SOAP_CONTRAST_PLANCK || effect == SOAP_EFFECT_BCONV || unit) ? 1 : 0;
+  pl.G = (pl.paired ? 2 : 3) * c->B;
+  pl.n_slabs = (c->N + soap::SLAB_COLS - 1) / soap::SLAB_COLS;
+  pl.n_chunks = (n_phases + c->pc - 1) / c->pc;
+  pl.vg_cap = pl.G * ((c->J + soap::APPLY_JW - 1) / soap::APPLY_JW);
   const size_t ent_bytes = (c->prec == SOAP_PREC_FP32) ? sizeof(soap::Entry<float>) : sizeof(soap::Entry<double>);
+  const size_t GJ = (size_t)pl.G * c->J;
 
   // parameter block (regions then phases) in the next pinned slot; the
   // weights kernel reads it in place
   const size_t reg_bytes = sizeof(soap::Region) * soap::MAX_REGIONS;
   const size_t par_bytes = reg_bytes + sizeof(double) * n_phases;
-  HIP_TRY(grow(c->ws_K, sizeof(double) * (size_t)n_phases * G * c->J));
-  HIP_TRY(grow(c->ws_vg, sizeof(soap::VGroup) * (size_t)n_chunks * vg_cap));
-  HIP_TRY(grow(c->ws_nvg, sizeof(int) * (size_t)n_chunks));
-  HIP_TRY(grow(c->ws_ent, ent_bytes * (size_t)n_chunks * ent_cap));
+  HIP_TRY(grow(c->ws_Kp, sizeof(double) * (size_t)n_phases * pl.n_slabs * GJ));
+  HIP_TRY(grow(c->ws_slab, sizeof(int) * (size_t)n_phases * pl.n_slabs));
+  HIP_TRY(grow(c->ws_K, sizeof(double) * (size_t)n_phases * GJ));
+  HIP_TRY(grow(c->ws_mask64, sizeof(unsigned long long) * (size_t)n_phases * pl.G));
+  HIP_TRY(grow(c->ws_vg, sizeof(soap::VGroup) * (size_t)pl.n_chunks * pl.vg_cap));
+  HIP_TRY(grow(c->ws_nvg, sizeof(int) * (size_t)pl.n_chunks));
+  HIP_TRY(grow(c->ws_ent, ent_bytes * (size_t)pl.n_chunks * pl.vg_cap * c->pc * soap::ENT_PER));
   const size_t out_bytes = (size_t)n_phases * c->P * c->esize;
   void* dflux = flux;
-  const size_t vec_align = soap::APPLY_R * c->esize;
-  if (!flux_on_device || (reinterpret_cast<uintptr_t>(flux) % vec_align) != 0) {
+  if (!flux_on_device) {
     HIP_TRY(grow(c->ws_flux, out_bytes));
     dflux = c->ws_flux.ptr;
   }
@@ -403,34 +424,37 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   const soap::Region* d_reg = static_cast<const soap::Region*>(dev_view);
   const double* d_ph = reinterpret_cast<const double*>(static_cast<const unsigned char*>(dev_view) + reg_bytes);
 
+  double* dKp = static_cast<double*>(c->ws_Kp.ptr);
+  int* dslab = static_cast<int*>(c->ws_slab.ptr);
   double* dK = static_cast<double*>(c->ws_K.ptr);
+  unsigned long long* dmask = static_cast<unsigned long long*>(c->ws_mask64.ptr);
   {
     StageTimer t(c, ST_WEIGHTS);
-    HIP_TRY(soap::launch_weights(c, d_reg, n_regions, d_ph, n_phases, effect, dK));
+    HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, d_ph, dKp, dslab));
     t.done();
   }
   HIP_TRY(hipEventRecord(c->slot_done[k], c->stream));
   {
     StageTimer t(c, ST_COMPACT);
-    HIP_TRY(soap::launch_compact(c, dK, n_phases, static_cast<soap::VGroup*>(c->ws_vg.ptr),
-                                 static_cast<int*>(c->ws_nvg.ptr), c->ws_ent.ptr, vg_cap, ent_cap));
+    HIP_TRY(soap::launch_reduce_taps(c, pl, dKp, dslab, dK, dmask));
+    HIP_TRY(soap::launch_compact(c, pl, dK, dmask, static_cast<soap::VGroup*>(c->ws_vg.ptr),
+                                 static_cast<int*>(c->ws_nvg.ptr), c->ws_ent.ptr));
     t.done();
   }
   {
     StageTimer t(c, ST_APPLY);
-    HIP_TRY(soap::launch_apply(c, static_cast<const soap::VGroup*>(c->ws_vg.ptr),
-                               static_cast<const int*>(c->ws_nvg.ptr), c->ws_ent.ptr, vg_cap, ent_cap, n_phases,
-                               effect, dflux));
+    HIP_TRY(soap::launch_apply(c, pl, static_cast<const soap::VGroup*>(c->ws_vg.ptr),
+                               static_cast<const int*>(c->ws_nvg.ptr), c->ws_ent.ptr, dflux));
     t.done();
   }
   c->active_calls++;
   c->last_phases = n_phases;
   c->last_effect = effect;
-  c->last_vg_cap = vg_cap;
+  c->last_vg_cap = pl.vg_cap;
+  c->last_paired = pl.paired;
   if (dflux != flux) {
-    HIP_TRY(hipMemcpyAsync(flux, dflux, out_bytes, flux_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                           c->stream));
-    if (!flux_on_device) HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpyAsync(flux, dflux, out_bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
   }
   return SOAP_OK;
 }
@@ -570,21 +594,23 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
   out->last_phases = c->last_phases;
   if (c->last_phases > 0) {
     // distinct inputs the last apply walked, from its virtual-group lists
-    const int n_chunks = (c->last_phases + soap::APPLY_PC - 1) / soap::APPLY_PC;
+    const int n_chunks = (c->last_phases + c->pc - 1) / c->pc;
     std::vector<int> nvg(n_chunks);
     std::vector<soap::VGroup> vg((size_t)n_chunks * c->last_vg_cap);
     HIP_TRY(hipMemcpy(nvg.data(), c->ws_nvg.ptr, sizeof(int) * n_chunks, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(vg.data(), c->ws_vg.ptr, sizeof(soap::VGroup) * vg.size(), hipMemcpyDeviceToHost));
     std::vector<char> src(3 * c->B, 0), con(3 * c->B, 0);
+    const bool planck = c->cmode == SOAP_CONTRAST_PLANCK;
     for (int ch = 0; ch < n_chunks; ++ch)
       for (int v = 0; v < nvg[ch]; ++v) {
         const int g = vg[(size_t)ch * c->last_vg_cap + v].g;
-        const int t = g / c->B, b = g % c->B;
+        const int t = c->last_paired ? g / c->B + 1 : g / c->B;
+        const int b = g % c->B;
         if (t == 0) {
           src[b] = 1;
           continue;
         }
-        const bool planck = c->cmode == SOAP_CONTRAST_PLANCK;
+        if (c->last_paired) src[b] = 1;  // the implied quiet removal
         if (c->last_effect == SOAP_EFFECT_FLUX) src[b] = 1;
         else src[t * c->B + b] = 1;
         // spot contrast is one array for every bin, facula one per bin

@@ -21,29 +21,45 @@ constexpr int MAX_REGIONS = 64;
 constexpr int MAX_MU = 64;
 constexpr int MAX_GRID = 4096;
 constexpr int MAX_PHASES = 1 << 20;
+constexpr int MAX_J = 64;  // tap offsets per table row
 
-// apply kernel shape: R pixels per thread, PC phases per chunk, JW offsets
-// per virtual group window, 256 threads per block.
+// Apply kernel shape: 256 threads x APPLY_R consecutive pixels per tile; a
+// chunk of PC phases per block (16 in FP32, 8 in FP64); taps grouped in
+// windows of APPLY_JW offsets.
 constexpr int APPLY_R = 4;
-constexpr int APPLY_PC = 8;
 constexpr int APPLY_JW = 8;
 constexpr int APPLY_THREADS = 256;
 constexpr int APPLY_TILE = APPLY_R * APPLY_THREADS;
+constexpr int PC_MAX = 16;
+constexpr int PC_F32 = 16;
+constexpr int PC_F64 = 8;
+constexpr int ENT_PER = 2;  // entries per (window, phase): APPLY_JW / 4
 
-// region record as the kernels read it (device copy of soap_region)
+// Padded rows of the local spectra and contrast arrays: PAD_FRONT copies of
+// the first sample before it and copies of the last sample after it, so that
+// every window the apply kernel reads is in bounds and the end-value hold of
+// the interpolation comes for free.
+constexpr int PAD_FRONT = 128;
+
+// Column slabs of the per-phase weight kernel.
+constexpr int SLAB_COLS = 32;
+constexpr int WEIGHT_WAVES = 8;
+
+// region record as the kernels read it (device view of soap_region)
 struct Region {
   int type;
   int pad;
   double lat_deg, lon_deg, radius, contrast;
 };
 
-// one virtual group of a phase chunk: source group g = type*B + bin (type 0 =
-// quiet removal), window of APPLY_JW offsets starting at jlo, and for each
-// phase of the chunk the range [off[p], off[p+1]) of its entries
+// A window of APPLY_JW tap offsets [jlo, jlo + APPLY_JW) of one group in one
+// phase chunk, with the number of tap runs each phase of the chunk has in it.
+// Group g: paired tables g = (type - 1) * B + bin; split tables
+// g = type * B + bin with type 0 the quiet removal.
 struct VGroup {
   int g;
   int jlo;
-  int off[APPLY_PC + 1];
+  unsigned char cnt[PC_MAX];
 };
 
 // one run of <= 4 consecutive taps inside a window: code = q0*4 + (w-1)
@@ -70,6 +86,8 @@ struct soap_ctx {
   // star
   int N = 0, B = 0;
   int64_t P = 0;
+  int64_t Pstride = 0;  // padded row length (elements); row data starts at PAD_FRONT
+  int n_tiles = 0;
   double vsini = 0, incl = 0, u1 = 0, u2 = 0, ln0 = 0, dln = 0;
   int prec = SOAP_PREC_FP64, cmode = SOAP_CONTRAST_SCALAR;
   double teff = 0, dt_spot = 0, dt_fac[3] = {0, 0, 0};
@@ -77,23 +95,29 @@ struct soap_ctx {
   bool has_type[3] = {false, false, false};
   int jmin = 0, jmax = 0, J = 0;  // tap offset range [jmin, jmax], J = jmax - jmin + 1
   size_t esize = 8;               // element size of spectra / flux
+  int pc = soap::PC_F64;          // phases per apply chunk
 
-  // resident device state
-  void* d_spec[3] = {nullptr, nullptr, nullptr};  // [B][P]
+  // resident device state (row pointers point at pixel 0 of row 0)
+  void* d_spec_base[3] = {nullptr, nullptr, nullptr};
+  void* d_spec[3] = {nullptr, nullptr, nullptr};  // [B][Pstride]
   double* d_mu = nullptr;                          // [B]
   int* d_col_c = nullptr;                          // [N]
   double* d_col_w = nullptr;                       // [N]
   double* d_colW = nullptr;                        // [N][B] quiet column weights
   double* d_Kq = nullptr;                          // [B][J] quiet taps
-  double* d_Q = nullptr;                           // [P]
-  void* d_con_spot = nullptr;                      // [P] (PLANCK)
-  void* d_con_fac = nullptr;                       // [B][P] (PLANCK)
+  double* d_Q = nullptr;                           // [n_tiles * TILE]
+  void* d_con_base = nullptr;
+  void* d_con_spot = nullptr;                      // [Pstride] (PLANCK)
+  void* d_con_fac = nullptr;                       // [B][Pstride] (PLANCK)
 
   // per-call workspace (grown on demand, freed by soap_destroy)
+  soap::Workspace ws_Kp;       // [n_phases][n_slabs][G][J] slab partial taps
+  soap::Workspace ws_slab;     // [n_phases][n_slabs] slab non-empty flags
   soap::Workspace ws_K;        // [n_phases][G][J] double
-  soap::Workspace ws_vg;       // [n_chunks][G*ceil(J/JW)] VGroup
+  soap::Workspace ws_mask64;   // [n_phases][G] bitmask of nonzero offsets
+  soap::Workspace ws_vg;       // [n_chunks][vg_cap] VGroup
   soap::Workspace ws_nvg;      // [n_chunks] int
-  soap::Workspace ws_ent;      // [n_chunks][max entries] Entry<T>
+  soap::Workspace ws_ent;      // [n_chunks][vg_cap][PC][ENT_PER] Entry<T>
   soap::Workspace ws_flux;     // host-output staging for fluxes
   soap::Workspace ws_ccf;      // partial CCFs
   soap::Workspace ws_ccfout;   // [n_spec][n_v] double
@@ -121,7 +145,7 @@ struct soap_ctx {
   std::vector<Pending> pending;
   double stage_ms[5] = {0, 0, 0, 0, 0};
   int64_t active_calls = 0, ccf_calls = 0;
-  int last_phases = 0, last_effect = 0, last_vg_cap = 0;
+  int last_phases = 0, last_effect = 0, last_vg_cap = 0, last_paired = 0;
 
   // cached mask
   std::vector<double> mask_lnl, mask_w;
@@ -132,19 +156,33 @@ struct soap_ctx {
 
 namespace soap {
 
+// Per-call plan shared by the weight, compaction and apply launches.
+struct Plan {
+  int n_ph = 0;
+  int effect = 0;
+  int paired = 0;   // 1: one tap table per active (type, bin); removal implied
+  int G = 0;        // groups per table: 2B (paired) or 3B (split)
+  int n_slabs = 0;
+  int n_chunks = 0;
+  int vg_cap = 0;   // virtual groups per chunk
+};
+
 // ---- launchers (each enqueues on ctx->stream; return hipError_t) ----------
 hipError_t launch_geom(soap_ctx* c);
+hipError_t launch_pad(soap_ctx* c);
 hipError_t launch_contrast(soap_ctx* c);
 hipError_t launch_quiet(soap_ctx* c);
-hipError_t launch_weights(soap_ctx* c, const Region* d_reg, int n_reg, const double* d_ph, int n_ph,
-                          int effect, double* d_K);
-hipError_t launch_compact(soap_ctx* c, const double* d_K, int n_ph, VGroup* d_vg, int* d_nvg,
-                          void* d_ent, int vg_cap, int ent_cap);
-hipError_t launch_apply(soap_ctx* c, const VGroup* d_vg, const int* d_nvg, const void* d_ent,
-                        int vg_cap, int ent_cap, int n_ph, int effect, void* d_flux);
+hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
+                          double* d_Kp, int* d_slab);
+hipError_t launch_reduce_taps(soap_ctx* c, const Plan& pl, const double* d_Kp, const int* d_slab, double* d_K,
+                              unsigned long long* d_mask);
+hipError_t launch_compact(soap_ctx* c, const Plan& pl, const double* d_K, const unsigned long long* d_mask,
+                          VGroup* d_vg, int* d_nvg, void* d_ent);
+hipError_t launch_apply(soap_ctx* c, const Plan& pl, const VGroup* d_vg, const int* d_nvg, const void* d_ent,
+                        void* d_flux);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
-hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask,
-                      int n_lines, double* d_part, double* d_ccf);
+hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
+                      double* d_part, double* d_ccf);
 hipError_t launch_gfit(soap_ctx* c, const double* d_ccf, int64_t n_spec, soap_rv* d_rv);
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask);
 
@@ -172,18 +210,22 @@ SOAP_DEV double limb_dark(double mu, double u1, double u2) {
   return 1.0 - u1 * om - u2 * om * om;
 }
 
+// index of the closest mu bin (ties to the lower index); mu_b is strictly
+// decreasing, so the two candidates are found by bisection and compared
 SOAP_DEV int nearest_bin(double mu, const double* mu_b, int B) {
 #pragma clang fp contract(off)
-  int bi = 0;
-  double best = fabs(mu - mu_b[0]);
-  for (int b = 1; b < B; ++b) {
-    double d = fabs(mu - mu_b[b]);
-    if (d < best) {
-      best = d;
-      bi = b;
-    }
+  // first index with mu_b[idx] < mu (B if none)
+  int lo = 0, hi = B;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (mu_b[mid] < mu) hi = mid;
+    else lo = mid + 1;
   }
-  return bi;
+  if (lo == 0) return 0;
+  if (lo == B) return B - 1;
+  double da = fabs(mu - mu_b[lo - 1]);
+  double db = fabs(mu - mu_b[lo]);
+  return (db < da) ? lo : lo - 1;
 }
 
 // observer-frame unit vector of a region centre at a rotation phase

@@ -1,39 +1,37 @@
 // Per-phase active-region weights (section 3.3, Algorithm 5).
 //
-// For each phase one workgroup
+// k_weights: one block per (phase, slab of SLAB_COLS disk columns), flattened
 //   1. rotates every region centre to the phase (longitude + 360 deg * phase,
-//      axis tilted by the inclination) and takes the bounding box of the
-//      visible caps;
-//   2. walks the disk columns of that box, one wave64 per column and one lane
-//      per cell: a cell belongs to a region when the angle between its surface
-//      point and the centre is at most asin(radius); the InfoMap owner is the
-//      last region in list order that covers it;
-//   3. sums, per column, the weights A I(mu) of active cells per mu bin: the
-//      quiet removal (-A I, every active cell) and the active terms
-//      (+A I c, per region type; c = the region's scalar contrast in the
-//      scalar mode of Eqs. 1 and 3, 1 otherwise).  Each lane accumulates its
-//      cells (FP32 + Kahan in the FP32 mode, FP64 otherwise), the 64 lane
-//      partials are reduced in FP64;
-//   4. collapses the column sums onto the integer offsets of the column's
-//      shift (weights 1 - w at j = c, w at j = c - 1, Eq. 11) in FP64, in a
-//      per-wave table, and finally sums the waves in a fixed order.
-// The result is a dense tap table K[phase][g][j] with g = type * B + bin
-// (type 0 = quiet removal, 1 = spot, 2 = facula) and j - jmin in [0, J).
+//      axis tilted by the inclination) and bounds the visible caps;
+//   2. one wave64 per column, one lane per cell: a cell belongs to a region
+//      when the angle between its surface point and the region centre is at
+//      most asin(radius); the InfoMap owner is the last listed region that
+//      covers it;
+//   3. per column, the weights A I(mu) of the active cells are summed per
+//      (type, mu bin).  Each lane sums its own cells (FP32 + Kahan in the
+//      FP32 mode, FP64 otherwise); all (type, bin) slots of the column are
+//      then reduced over the 64 lanes at once in FP64 by a transposed
+//      butterfly (16 slots in 17 shuffles);
+//   4. each column sum is collapsed onto the two integer offsets of the
+//      column's shift (1 - w at j = c, w at j = c - 1: Eq. 11) in a per-wave
+//      FP64 table; the waves are summed in a fixed order into the slab's
+//      partial table.
+// Tables: paired mode (every active weight equals its removal weight:
+// chromatic contrast, the convective effect, or unit scalar contrasts) keeps
+// one table row per active (type, bin), g = (type - 1) * B + bin, and the
+// quiet removal is implied by the apply kernel.  Split mode (scalar
+// contrasts other than one) keeps g = type * B + bin with type 0 the removal
+// (-A I) and the active rows scaled by the region contrast.
 //
-// k_compact then turns the taps of each chunk of phases into the list the
-// apply kernel walks: virtual groups (a group and a window of APPLY_JW
-// offsets) and, per phase, runs of <= 4 consecutive taps.
+// k_reduce_taps sums the slab partials in slab order and records, per
+// (phase, group), the bitmask of non-zero offsets.  k_compact turns each
+// chunk of phases into windows of APPLY_JW offsets and runs of <= 4 taps.
+// Every sum has a fixed order, so results repeat bit for bit.
 #include "soap_internal.hpp"
 
 namespace soap {
 
 namespace {
-
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 __device__ __forceinline__ unsigned long long wor(unsigned long long v) {
 #pragma unroll
@@ -41,35 +39,65 @@ __device__ __forceinline__ unsigned long long wor(unsigned long long v) {
   return v;
 }
 
-constexpr int MAXC = 4;  // cells cached per lane per row pass (256 rows)
+constexpr int MAXC = 4;   // cells per lane per row pass (256 rows)
+constexpr int SLOTS = 16; // slots reduced together
+
+// Sum v[0..15] over the 64 lanes; lane l ends with the total of slot
+// (l >> 2) & 15.
+__device__ __forceinline__ double butterfly16(double (&v)[SLOTS], int lane) {
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double send = b5 ? v[i] : v[i + 8];
+    double keep = b5 ? v[i + 8] : v[i];
+    v[i] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double send = b4 ? v[i] : v[i + 4];
+    double keep = b4 ? v[i + 4] : v[i];
+    v[i] = keep + __shfl_xor(send, 16, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    double send = b3 ? v[i] : v[i + 2];
+    double keep = b3 ? v[i + 2] : v[i];
+    v[i] = keep + __shfl_xor(send, 8, 64);
+  }
+  {
+    double send = b2 ? v[0] : v[1];
+    double keep = b2 ? v[1] : v[0];
+    v[0] = keep + __shfl_xor(send, 4, 64);
+  }
+  double s = v[0];
+  s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 1, 64);
+  return s;
+}
 
 }  // namespace
 
 template <bool KAHAN32>
-__global__ void __launch_bounds__(1024) k_weights(int N, int B, int J, int jmin, double u1, double u2,
-                                                  double incl, int effect, int cmode,
-                                                  const double* __restrict__ mu_b,
-                                                  const int* __restrict__ col_c,
-                                                  const double* __restrict__ col_w,
-                                                  const Region* __restrict__ reg, int n_reg,
-                                                  const double* __restrict__ phases,
-                                                  double* __restrict__ K) {
-  extern __shared__ double lds[];
+__global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
+    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, double incl, int effect,
+    int cmode, const double* __restrict__ mu_b, const int* __restrict__ col_c, const double* __restrict__ col_w,
+    const Region* __restrict__ reg, int n_reg, const double* __restrict__ phases, double* __restrict__ Kp,
+    int* __restrict__ slab_flag) {
+  extern __shared__ double lds[];  // [nw][G*J] tables, then [nw][192] slot codes
   __shared__ double rcx[MAX_REGIONS], rcy[MAX_REGIONS], rcz[MAX_REGIONS], rcos[MAX_REGIONS],
       rscal[MAX_REGIONS];
   __shared__ int rtype[MAX_REGIONS];
   __shared__ int box[4];
 
-  const int ph = blockIdx.x;
+  const int ph = blockIdx.x / n_slabs;
+  const int slab = blockIdx.x - ph * n_slabs;
   const int nw = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int G = 3 * B;
   const int GJ = G * J;
   const double phase = phases[ph];
   const double area = (2.0 / N) * (2.0 / N);
 
-  for (int t = threadIdx.x; t < nw * GJ; t += blockDim.x) lds[t] = 0.0;
   if (threadIdx.x < n_reg) {
     const Region r = reg[threadIdx.x];
     double cx, cy, cz;
@@ -82,7 +110,7 @@ __global__ void __launch_bounds__(1024) k_weights(int N, int B, int J, int jmin,
       rcos[threadIdx.x] = sqrt(1.0 - r.radius * r.radius);
     }
     rtype[threadIdx.x] = r.type;
-    rscal[threadIdx.x] = (cmode == SOAP_CONTRAST_SCALAR && effect != SOAP_EFFECT_BCONV) ? r.contrast : 1.0;
+    rscal[threadIdx.x] = (!paired && effect != SOAP_EFFECT_BCONV) ? r.contrast : 1.0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -91,7 +119,7 @@ __global__ void __launch_bounds__(1024) k_weights(int N, int B, int J, int jmin,
     // which bounds its projected distance from the centre
     double xlo = 2.0, xhi = -2.0, ylo = 2.0, yhi = -2.0;
     for (int r = 0; r < n_reg; ++r) {
-      double rad = sqrt(1.0 - rcos[r] * rcos[r]);
+      double rad = sqrt(fmax(0.0, 1.0 - rcos[r] * rcos[r]));
       if (rcz[r] <= -rad - 1e-12) continue;
       double d = sqrt(fmax(0.0, 2.0 - 2.0 * rcos[r])) + 1e-9;
       xlo = fmin(xlo, rcx[r] - d);
@@ -103,23 +131,32 @@ __global__ void __launch_bounds__(1024) k_weights(int N, int B, int J, int jmin,
     int i1 = (int)ceil((xhi + 1.0) * 0.5 * N) + 1;
     int k0 = (int)floor((ylo + 1.0) * 0.5 * N) - 1;
     int k1 = (int)ceil((yhi + 1.0) * 0.5 * N) + 1;
-    box[0] = max(i0, 0);
-    box[1] = min(i1, N - 1);
+    i0 = max(i0, slab * SLAB_COLS);
+    i1 = min(i1, min(N, (slab + 1) * SLAB_COLS) - 1);
+    box[0] = i0;
+    box[1] = i1;
     box[2] = max(k0, 0);
     box[3] = min(k1, N - 1);
+    slab_flag[ph * n_slabs + slab] = (i0 <= i1 && box[2] <= box[3]) ? 1 : 0;
   }
   __syncthreads();
   const int i0 = box[0], i1 = box[1], k0 = box[2], k1 = box[3];
+  if (i0 > i1 || k0 > k1) return;  // uniform: nothing of this slab is covered
+
+  for (int t = threadIdx.x; t < nw * GJ; t += blockDim.x) lds[t] = 0.0;
+  __syncthreads();
   double* myK = lds + wave * GJ;
+  int* slots = reinterpret_cast<int*>(lds + nw * GJ) + wave * 192;
 
   for (int i = i0 + wave; i <= i1; i += nw) {
     const double x = cell_coord(i, N);
     const int ci = col_c[i];
     const double wi = col_w[i];
+    const int ja = ci - jmin, jb = ci - 1 - jmin;
     for (int kbase = k0; kbase <= k1; kbase += 64 * MAXC) {
-      int cb[MAXC];      // bin | (type << 8), or -1 when not active
-      double cw[MAXC];   // A I(mu)
-      double cs[MAXC];   // owner contrast scale
+      int cb[MAXC];     // bin | (type << 8), or -1 when not active
+      double cw[MAXC];  // A I(mu)
+      double cs[MAXC];  // owner contrast scale
       unsigned long long m1 = 0, m2 = 0;
 #pragma unroll
       for (int q = 0; q < MAXC; ++q) {
@@ -159,75 +196,65 @@ __global__ void __launch_bounds__(1024) k_weights(int N, int B, int J, int jmin,
       }
       m1 = wor(m1);
       m2 = wor(m2);
-      unsigned long long mall = m1 | m2;
-      while (mall) {
-        const int b = __builtin_ctzll(mall);
-        mall &= mall - 1;
-        double prem, pspot, pfac;
-        if (KAHAN32) {
-          float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f, s2 = 0.f, c2 = 0.f;
+      const unsigned long long m0 = paired ? 0ull : (m1 | m2);
+      if (!(m1 | m2)) continue;  // uniform
+      // slot list: removal bins (split mode), spot bins, facula bins
+      const int n0 = __popcll(m0), n1 = __popcll(m1), n2 = __popcll(m2);
+      const int nslot = n0 + n1 + n2;
+      {
+        const unsigned long long below = (lane == 0) ? 0ull : ((1ull << lane) - 1ull);
+        if ((m0 >> lane) & 1) slots[__popcll(m0 & below)] = lane;
+        if ((m1 >> lane) & 1) slots[n0 + __popcll(m1 & below)] = lane | (SOAP_SPOT << 8);
+        if ((m2 >> lane) & 1) slots[n0 + n1 + __popcll(m2 & below)] = lane | (SOAP_FACULA << 8);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int sb = 0; sb < nslot; sb += SLOTS) {
+        double v[SLOTS];
 #pragma unroll
-          for (int q = 0; q < MAXC; ++q) {
-            if (cb[q] >= 0 && (cb[q] & 0xff) == b) {
-              const float v = (float)cw[q];
-              const float va = (float)(cw[q] * cs[q]);
-              float yk = v - c0, t = s0 + yk;
-              c0 = (t - s0) - yk;
-              s0 = t;
-              if ((cb[q] >> 8) == SOAP_SPOT) {
-                yk = va - c1;
-                t = s1 + yk;
-                c1 = (t - s1) - yk;
-                s1 = t;
-              } else {
-                yk = va - c2;
-                t = s2 + yk;
-                c2 = (t - s2) - yk;
-                s2 = t;
+        for (int s = 0; s < SLOTS; ++s) {
+          const int code = (sb + s < nslot) ? slots[sb + s] : -2;
+          const int tb = code & 0xff, tt = code >> 8;  // tt == 0: removal
+          if (KAHAN32) {
+            float acc = 0.f, comp = 0.f;
+#pragma unroll
+            for (int q = 0; q < MAXC; ++q) {
+              const bool hit = cb[q] >= 0 && (cb[q] & 0xff) == tb && (tt == 0 || (cb[q] >> 8) == tt);
+              if (code >= 0 && hit) {
+                const float val = (tt == 0) ? -(float)cw[q] : (float)(cw[q] * cs[q]);
+                const float yk = val - comp;
+                const float tk = acc + yk;
+                comp = (tk - acc) - yk;
+                acc = tk;
               }
             }
-          }
-          prem = (double)s0 - (double)c0;
-          pspot = (double)s1 - (double)c1;
-          pfac = (double)s2 - (double)c2;
-        } else {
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            v[s] = (double)acc - (double)comp;
+          } else {
+            double acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < MAXC; ++q) {
-            if (cb[q] >= 0 && (cb[q] & 0xff) == b) {
-              s0 += cw[q];
-              if ((cb[q] >> 8) == SOAP_SPOT) s1 += cw[q] * cs[q];
-              else s2 += cw[q] * cs[q];
+            for (int q = 0; q < MAXC; ++q) {
+              const bool hit = cb[q] >= 0 && (cb[q] & 0xff) == tb && (tt == 0 || (cb[q] >> 8) == tt);
+              if (code >= 0 && hit) acc += (tt == 0) ? -cw[q] : cw[q] * cs[q];
             }
+            v[s] = acc;
           }
-          prem = s0;
-          pspot = s1;
-          pfac = s2;
         }
-        const double Wrem = wsum(prem);
-        const double Wspot = (m1 >> b) & 1 ? wsum(pspot) : 0.0;
-        const double Wfac = (m2 >> b) & 1 ? wsum(pfac) : 0.0;
-        const int ja = ci - jmin, jb = ci - 1 - jmin;
-        if (lane == 0 && jb >= 0 && ja < J) {
-          double* kr = myK + (0 * B + b) * J;
-          kr[ja] -= (1.0 - wi) * Wrem;
-          kr[jb] -= wi * Wrem;
-          if (Wspot != 0.0) {
-            kr = myK + (SOAP_SPOT * B + b) * J;
-            kr[ja] += (1.0 - wi) * Wspot;
-            kr[jb] += wi * Wspot;
-          }
-          if (Wfac != 0.0) {
-            kr = myK + (SOAP_FACULA * B + b) * J;
-            kr[ja] += (1.0 - wi) * Wfac;
-            kr[jb] += wi * Wfac;
-          }
+        const double W = butterfly16(v, lane);
+        const int s = (lane >> 2) & (SLOTS - 1);
+        if ((lane & 3) == 0 && sb + s < nslot && jb >= 0 && ja < J) {
+          const int code = slots[sb + s];
+          const int tb = code & 0xff, tt = code >> 8;
+          const int g = paired ? (tt - 1) * B + tb : tt * B + tb;
+          double* kr = myK + g * J;
+          kr[ja] += (1.0 - wi) * W;
+          kr[jb] += wi * W;
         }
       }
+      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
-  double* out = K + (int64_t)ph * GJ;
+  double* out = Kp + ((int64_t)ph * n_slabs + slab) * GJ;
   for (int t = threadIdx.x; t < GJ; t += blockDim.x) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += lds[w * GJ + t];
@@ -235,42 +262,56 @@ __global__ void __launch_bounds__(1024) k_weights(int N, int B, int J, int jmin,
   }
 }
 
-// one block per chunk of APPLY_PC phases
-template <typename T>
-__global__ void __launch_bounds__(256) k_compact(int n_ph, int G, int J, int jmin, const double* __restrict__ K,
-                                                 VGroup* __restrict__ vgs, int* __restrict__ nvg,
-                                                 Entry<T>* __restrict__ ents, int vg_cap, int ent_cap) {
-  extern __shared__ int sm[];
-  int* s_cnt = sm;             // [G] virtual groups per group
-  int* s_base = sm + G;        // [G]
-  int* s_ecnt = sm + 2 * G;    // [vg_cap] entries per virtual group
-  int* s_ebase = s_ecnt + vg_cap;
-  const int chunk = blockIdx.x;
-  const int p0 = chunk * APPLY_PC;
-  const int np = min(APPLY_PC, n_ph - p0);
+// K[ph][g][j] = sum over non-empty slabs (slab order); mask of non-zero j
+__global__ void k_reduce_taps(int n_ph, int G, int J, int n_slabs, const double* __restrict__ Kp,
+                              const int* __restrict__ slab_flag, double* __restrict__ K,
+                              unsigned long long* __restrict__ mask) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_ph * G) return;
+  const int ph = t / G, g = t - ph * G;
   const int GJ = G * J;
-  const double* Kc = K + (int64_t)p0 * GJ;
-  VGroup* vg = vgs + (int64_t)chunk * vg_cap;
-  Entry<T>* en = ents + (int64_t)chunk * ent_cap;
-  const int nwin_max = (J + APPLY_JW - 1) / APPLY_JW;
+  unsigned long long mk = 0;
+  for (int j = 0; j < J; ++j) {
+    double s = 0.0;
+    for (int sl = 0; sl < n_slabs; ++sl)
+      if (slab_flag[ph * n_slabs + sl]) s += Kp[((int64_t)ph * n_slabs + sl) * GJ + g * J + j];
+    K[(int64_t)ph * GJ + g * J + j] = s;
+    if (s != 0.0) mk |= 1ull << j;
+  }
+  mask[(int64_t)ph * G + g] = mk;
+}
 
-  // pass 1: windows with any tap per group
+// one block per chunk of PC phases: windows and tap runs
+template <typename T>
+__global__ void __launch_bounds__(256) k_compact(int n_ph, int PC, int G, int J, int jmin,
+                                                 const double* __restrict__ K,
+                                                 const unsigned long long* __restrict__ mask,
+                                                 VGroup* __restrict__ vgs, int* __restrict__ nvg,
+                                                 Entry<T>* __restrict__ ents, int vg_cap) {
+  extern __shared__ int sm[];
+  int* s_cnt = sm;           // [G] windows per group
+  int* s_base = sm + G;      // [G] first window index
+  int* s_lo = sm + 2 * G;    // [G] first non-zero offset of the union
+  unsigned long long* s_union = reinterpret_cast<unsigned long long*>(sm + 4 * G);  // [G]
+  const int chunk = blockIdx.x;
+  const int p0 = chunk * PC;
+  const int np = min(PC, n_ph - p0);
+  const int GJ = G * J;
+  VGroup* vg = vgs + (int64_t)chunk * vg_cap;
+  Entry<T>* en = ents + (int64_t)chunk * vg_cap * PC * ENT_PER;
+
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
-    unsigned long long any = 0;
-    for (int p = 0; p < np; ++p)
-      for (int j = 0; j < J; ++j)
-        if (Kc[(int64_t)p * GJ + g * J + j] != 0.0) any |= 1ull << j;
-    int cnt = 0;
-    if (any) {
-      const int lo = __builtin_ctzll(any);
-      for (int wv = 0; wv < nwin_max; ++wv) {
-        const int a = lo + wv * APPLY_JW;
-        if (a >= J) break;
-        const unsigned long long wm = (any >> a) & ((1ull << APPLY_JW) - 1);
-        if (wm) ++cnt;
-      }
+    unsigned long long u = 0;
+    for (int p = 0; p < np; ++p) u |= mask[(int64_t)(p0 + p) * G + g];
+    int cnt = 0, lo = 0;
+    if (u) {
+      lo = __builtin_ctzll(u);
+      for (int a = lo; a < J; a += APPLY_JW)
+        if ((u >> a) & ((1ull << APPLY_JW) - 1)) ++cnt;
     }
     s_cnt[g] = cnt;
+    s_lo[g] = lo;
+    s_union[g] = u;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -282,110 +323,84 @@ __global__ void __launch_bounds__(256) k_compact(int n_ph, int G, int J, int jmi
     nvg[chunk] = acc;
   }
   __syncthreads();
-  // pass 2: virtual group records and entry counts
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+  // one thread per (group, phase): window records (phase 0 writes g / jlo)
+  // and the runs of <= 4 taps of that phase in each window
+  for (int t = threadIdx.x; t < G * PC; t += blockDim.x) {
+    const int g = t / PC, p = t - g * PC;
     if (!s_cnt[g]) continue;
-    unsigned long long any = 0;
-    for (int p = 0; p < np; ++p)
-      for (int j = 0; j < J; ++j)
-        if (Kc[(int64_t)p * GJ + g * J + j] != 0.0) any |= 1ull << j;
-    const int lo = __builtin_ctzll(any);
+    const unsigned long long u = s_union[g];
     int v = s_base[g];
-    for (int wv = 0; wv < nwin_max; ++wv) {
-      const int a = lo + wv * APPLY_JW;
-      if (a >= J) break;
-      if (!((any >> a) & ((1ull << APPLY_JW) - 1))) continue;
-      int ecount = 0;
-      for (int p = 0; p < np; ++p) {
-        const double* kr = Kc + (int64_t)p * GJ + g * J;
+    for (int a = s_lo[g]; a < J; a += APPLY_JW) {
+      if (!((u >> a) & ((1ull << APPLY_JW) - 1))) continue;
+      if (p == 0) {
+        vg[v].g = g;
+        vg[v].jlo = jmin + a;
+      }
+      int e = 0;
+      if (p < np) {
+        const double* kr = K + (int64_t)(p0 + p) * GJ + g * J;
+        const unsigned long long mp = mask[(int64_t)(p0 + p) * G + g];
         int q = 0;
         while (q < APPLY_JW) {
-          if (a + q < J && kr[a + q] != 0.0) {
-            ++ecount;
+          if (a + q < J && ((mp >> (a + q)) & 1)) {
+            int w = 1;
+            for (int s = 1; s < 4 && q + s < APPLY_JW && a + q + s < J; ++s)
+              if ((mp >> (a + q + s)) & 1) w = s + 1;
+            Entry<T> E;
+            E.code = q * 4 + (w - 1);
+            E.pad = 0;
+            for (int s = 0; s < 4; ++s) E.k[s] = (s < w) ? (T)kr[a + q + s] : (T)0;
+            en[((int64_t)v * PC + p) * ENT_PER + e] = E;
+            ++e;
             q += 4;
           } else {
             ++q;
           }
         }
       }
-      vg[v].g = g;
-      vg[v].jlo = jmin + a;
-      s_ecnt[v] = ecount;
+      vg[v].cnt[p] = (unsigned char)e;
       ++v;
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    const int n = nvg[chunk];
-    for (int v = 0; v < n; ++v) {
-      s_ebase[v] = acc;
-      acc += s_ecnt[v];
-    }
-  }
-  __syncthreads();
-  // pass 3: entries, phase-major inside each virtual group
-  const int n = nvg[chunk];
-  for (int v = threadIdx.x; v < n; v += blockDim.x) {
-    const int g = vg[v].g;
-    const int a = vg[v].jlo - jmin;
-    int e = s_ebase[v];
-    for (int p = 0; p < APPLY_PC; ++p) {
-      vg[v].off[p] = e;
-      if (p >= np) continue;
-      const double* kr = Kc + (int64_t)p * GJ + g * J;
-      int q = 0;
-      while (q < APPLY_JW) {
-        if (a + q < J && kr[a + q] != 0.0) {
-          int w = 1;
-          for (int t = 1; t < 4 && q + t < APPLY_JW && a + q + t < J; ++t)
-            if (kr[a + q + t] != 0.0) w = t + 1;
-          Entry<T> E;
-          E.code = q * 4 + (w - 1);
-          E.pad = 0;
-          for (int t = 0; t < 4; ++t) E.k[t] = (t < w) ? (T)kr[a + q + t] : (T)0;
-          en[e++] = E;
-          q += 4;
-        } else {
-          ++q;
-        }
-      }
-    }
-    vg[v].off[APPLY_PC] = e;
-  }
 }
 
-hipError_t launch_weights(soap_ctx* c, const Region* d_reg, int n_reg, const double* d_ph, int n_ph,
-                          int effect, double* d_K) {
-  const int G = 3 * c->B;
-  const size_t per_wave = (size_t)G * c->J * sizeof(double);
+hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
+                          double* d_Kp, int* d_slab) {
+  const size_t per_wave = (size_t)pl.G * c->J * sizeof(double) + 192 * sizeof(int);
   // dynamic LDS stays below 60 KB so that with the static arrays the block
   // fits a 64 KB workgroup allocation
-  int nw = (int)std::min<size_t>(16, (60 * 1024) / per_wave);
+  int nw = (int)std::min<size_t>(WEIGHT_WAVES, (60 * 1024) / per_wave);
   if (nw < 1) nw = 1;
   const size_t lds = nw * per_wave;
+  dim3 grid((unsigned)pl.n_slabs * (unsigned)pl.n_ph);
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_weights<true>, dim3(n_ph), dim3(64 * nw), lds, c->stream, c->N, c->B, c->J, c->jmin,
-                       c->u1, c->u2, c->incl, effect, c->cmode, c->d_mu, c->d_col_c, c->d_col_w, d_reg, n_reg,
-                       d_ph, d_K);
+    hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * nw), lds, c->stream, c->N, c->B, c->J, c->jmin, pl.G,
+                       pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu, c->d_col_c,
+                       c->d_col_w, d_reg, n_reg, d_ph, d_Kp, d_slab);
   else
-    hipLaunchKernelGGL(k_weights<false>, dim3(n_ph), dim3(64 * nw), lds, c->stream, c->N, c->B, c->J,
-                       c->jmin, c->u1, c->u2, c->incl, effect, c->cmode, c->d_mu, c->d_col_c, c->d_col_w,
-                       d_reg, n_reg, d_ph, d_K);
+    hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * nw), lds, c->stream, c->N, c->B, c->J, c->jmin, pl.G,
+                       pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu, c->d_col_c,
+                       c->d_col_w, d_reg, n_reg, d_ph, d_Kp, d_slab);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(soap_ctx* c, const double* d_K, int n_ph, VGroup* d_vg, int* d_nvg, void* d_ent,
-                          int vg_cap, int ent_cap) {
-  const int G = 3 * c->B;
-  const int n_chunks = (n_ph + APPLY_PC - 1) / APPLY_PC;
-  const size_t lds = (size_t)(2 * G + 2 * vg_cap) * sizeof(int);
+hipError_t launch_reduce_taps(soap_ctx* c, const Plan& pl, const double* d_Kp, const int* d_slab, double* d_K,
+                              unsigned long long* d_mask) {
+  const int nt = pl.n_ph * pl.G;
+  hipLaunchKernelGGL(k_reduce_taps, dim3((nt + 127) / 128), dim3(128), 0, c->stream, pl.n_ph, pl.G, c->J,
+                     pl.n_slabs, d_Kp, d_slab, d_K, d_mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(soap_ctx* c, const Plan& pl, const double* d_K, const unsigned long long* d_mask,
+                          VGroup* d_vg, int* d_nvg, void* d_ent) {
+  const size_t lds = (size_t)4 * pl.G * sizeof(int) + (size_t)pl.G * sizeof(unsigned long long);
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_compact<float>, dim3(n_chunks), dim3(256), lds, c->stream, n_ph, G, c->J, c->jmin, d_K,
-                       d_vg, d_nvg, (Entry<float>*)d_ent, vg_cap, ent_cap);
+    hipLaunchKernelGGL(k_compact<float>, dim3(pl.n_chunks), dim3(256), lds, c->stream, pl.n_ph, c->pc, pl.G, c->J,
+                       c->jmin, d_K, d_mask, d_vg, d_nvg, (Entry<float>*)d_ent, pl.vg_cap);
   else
-    hipLaunchKernelGGL(k_compact<double>, dim3(n_chunks), dim3(256), lds, c->stream, n_ph, G, c->J, c->jmin,
-                       d_K, d_vg, d_nvg, (Entry<double>*)d_ent, vg_cap, ent_cap);
+    hipLaunchKernelGGL(k_compact<double>, dim3(pl.n_chunks), dim3(256), lds, c->stream, pl.n_ph, c->pc, pl.G,
+                       c->J, c->jmin, d_K, d_mask, d_vg, d_nvg, (Entry<double>*)d_ent, pl.vg_cap);
   return hipGetLastError();
 }
 
