@@ -139,7 +139,8 @@ typedef struct {
   double half_width_kms;     /* > 0, hole at most 8 pixels wide             */
   double v0_kms;
   double dv_kms;             /* > 0                                         */
-  int32_t n_v;               /* 4 .. 1024                                   */
+  int32_t n_v;               /* 4 .. 768; the grid (with holes) spans at most
+                                508 pixels in FP64 contexts, 1020 in FP32  */
   int32_t reserved0;
 } soap_mask;
 

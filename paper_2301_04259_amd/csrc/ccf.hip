@@ -20,11 +20,16 @@
 
 namespace soap {
 
-constexpr int CCF_LINES = 32;  // lines per block
-constexpr int CCF_SB = 16;     // spectra per block
-constexpr int CCF_THREADS = 256;
+constexpr int CCF_LINES = 64;  // lines per block (partial sums per block)
+constexpr int CCF_BATCH = 16;  // lines staged in LDS at a time
+constexpr int CCF_SB = 8;      // spectra per block
+constexpr int CCF_THREADS = 192;
+constexpr int CCF_LDS = 32768; // bytes of staged spectra per block
+template <typename T>
+constexpr int ccf_span() { return CCF_LDS / (CCF_SB * (int)sizeof(T)); }  // pixels per spectrum
 
 int ccf_line_blocks(int n_lines) { return (n_lines + CCF_LINES - 1) / CCF_LINES; }
+int ccf_span_pixels(bool fp32) { return fp32 ? ccf_span<float>() : ccf_span<double>(); }
 
 __global__ void k_mask_prep(int n, double ln0, double dln, const double* __restrict__ lnl,
                             const double* __restrict__ w, double2* __restrict__ out) {
@@ -32,41 +37,104 @@ __global__ void k_mask_prep(int n, double ln0, double dln, const double* __restr
   if (l < n) out[l] = make_double2((lnl[l] - ln0) / dln + 0.5, w[l]);
 }
 
+// One block per (64 mask lines, 8 spectra).  Lines are taken in batches of
+// up to 16 whose holes, at any trial velocity, reach a pixel span that fits
+// the LDS stage; that span is staged for the block's spectra (coalesced
+// loads), then one thread per velocity computes each hole's pixel overlaps
+// once and applies them to every staged spectrum, accumulating in double.
 template <typename T>
 __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int64_t P, int64_t n_spec, const T* __restrict__ F,
                                                      int n_lines, const double2* __restrict__ mask, int n_v,
                                                      double v0, double dv, double h, double dln,
                                                      double* __restrict__ part) {
+  constexpr int SPAN = ccf_span<T>();
+  __shared__ T st[CCF_SB][SPAN];
+  __shared__ int64_t s_lo;
+  __shared__ int s_len, s_b1;
   const int lb = blockIdx.x;
   const int64_t s0 = (int64_t)blockIdx.y * CCF_SB;
   const int l0 = lb * CCF_LINES;
   const int l1 = min(n_lines, l0 + CCF_LINES);
   const int ns = (int)min<int64_t>(CCF_SB, n_spec - s0);
-  for (int k = threadIdx.x; k < n_v; k += blockDim.x) {
+  // hole edges of every velocity this block handles: a thread keeps its own
+  const int kk = threadIdx.x;  // velocities kk, kk + blockDim.x, ...
+  // extreme edges over the velocity grid bound the staged span
+  const double alo_min = atanh((v0 - h) / C_KMS) / dln;
+  const double ahi_max = atanh((v0 + dv * (n_v - 1) + h) / C_KMS) / dln;
+  double acc[4][CCF_SB];  // up to 4 velocities per thread (n_v <= 4 * CCF_THREADS)
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int s = 0; s < CCF_SB; ++s) acc[a][s] = 0.0;
+  double alo[4], ahi[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int k = kk + a * CCF_THREADS;
     const double vk = v0 + dv * k;
-    const double alo = atanh((vk - h) / C_KMS) / dln;
-    const double ahi = atanh((vk + h) / C_KMS) / dln;
-    double acc[CCF_SB];
-#pragma unroll
-    for (int s = 0; s < CCF_SB; ++s) acc[s] = 0.0;
-    for (int l = l0; l < l1; ++l) {
+    alo[a] = atanh((vk - h) / C_KMS) / dln;
+    ahi[a] = atanh((vk + h) / C_KMS) / dln;
+  }
+  for (int b0 = l0; b0 < l1;) {
+    if (threadIdx.x == 0) {
+      // grow the batch while the reach of all its holes fits the stage
+      int64_t lo = (int64_t)floor(mask[b0].x + alo_min);
+      int64_t hi = (int64_t)floor(mask[b0].x + ahi_max) + 1;
+      int e = b0 + 1;
+      while (e < l1 && e - b0 < CCF_BATCH) {
+        const int64_t nlo = min(lo, (int64_t)floor(mask[e].x + alo_min));
+        const int64_t nhi = max(hi, (int64_t)floor(mask[e].x + ahi_max) + 1);
+        if (nhi - nlo + 1 > SPAN) break;
+        lo = nlo;
+        hi = nhi;
+        ++e;
+      }
+      s_lo = lo;
+      s_len = (int)min<int64_t>(SPAN, hi - lo + 1);
+      s_b1 = e;
+    }
+    __syncthreads();
+    const int64_t lo = s_lo;
+    const int len = s_len;
+    const int b1 = s_b1;
+    for (int s = 0; s < ns; ++s) {
+      const T* row = F + (s0 + s) * P;
+      for (int i = threadIdx.x; i < len; i += blockDim.x) {
+        const int64_t m = lo + i;
+        st[s][i] = (m >= 0 && m < P) ? row[m] : T(0);
+      }
+    }
+    __syncthreads();
+    for (int l = b0; l < b1; ++l) {
       const double2 mw = mask[l];
-      const double qlo = mw.x + alo;
-      const double qhi = mw.x + ahi;
-      const int64_t ma = (int64_t)floor(qlo);
-      const int64_t mb = (int64_t)floor(qhi);
-      for (int64_t m = ma; m <= mb; ++m) {
-        const double ov = fmin(qhi, (double)(m + 1)) - fmax(qlo, (double)m);
-        if (ov > 0.0 && m >= 0 && m < P) {
-          const double wo = mw.y * ov;
-          const T* col = F + s0 * P + m;
 #pragma unroll
-          for (int s = 0; s < CCF_SB; ++s)
-            if (s < ns) acc[s] = fma(wo, (double)col[(int64_t)s * P], acc[s]);
+      for (int a = 0; a < 4; ++a) {
+        const int k = kk + a * CCF_THREADS;
+        if (k >= n_v) break;
+        const double qlo = mw.x + alo[a];
+        const double qhi = mw.x + ahi[a];
+        const int64_t ma = (int64_t)floor(qlo);
+        const int64_t mb = (int64_t)floor(qhi);
+        for (int64_t m = ma; m <= mb; ++m) {
+          const double ov = fmin(qhi, (double)(m + 1)) - fmax(qlo, (double)m);
+          const int64_t i = m - lo;
+          if (ov > 0.0 && m >= 0 && m < P && i >= 0 && i < len) {
+            const double wo = mw.y * ov;
+#pragma unroll
+            for (int s = 0; s < CCF_SB; ++s) acc[a][s] = fma(wo, (double)st[s][i], acc[a][s]);
+          }
         }
       }
     }
-    for (int s = 0; s < ns; ++s) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = acc[s];
+    __syncthreads();
+    b0 = b1;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int k = kk + a * CCF_THREADS;
+    if (k >= n_v) break;
+#pragma unroll
+    for (int s = 0; s < CCF_SB; ++s)
+      if (s < ns) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = acc[a][s];
   }
 }
 
@@ -88,7 +156,7 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 constexpr double FWHM_PER_SIGMA = 2.3548200450309493;  // 2 sqrt(2 ln 2)
-constexpr int GF_MAXPT = 16;                            // points per lane (n_v <= 1024)
+constexpr int GF_MAXPT = 12;                            // points per lane (n_v <= 768)
 
 // chi^2 and optionally J^T J (10 unique) / J^T r (4) at p
 __device__ void gf_eval(const double* y, int n_v, double v0, double dv, const double p[4], bool jac,

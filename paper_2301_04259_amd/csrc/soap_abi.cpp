@@ -131,7 +131,7 @@ void destroy_ctx(soap_ctx* c) {
   void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
-  soap::Workspace* ws[] = {&c->ws_Kp, &c->ws_slab, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_ent, &c->ws_flux,
+  soap::Workspace* ws[] = {&c->ws_Kp, &c->ws_slab, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_taps, &c->ws_flux,
                            &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
   for (auto* w : ws) free_ws(*w);
   for (auto& p : c->pending) {
@@ -194,9 +194,9 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   hipMemcpyKind kind = d->spectra_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   for (int t = 0; t < 3; ++t) {
     if (!d->spectra[t]) continue;
-    HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B));
+    HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B * soap::NCOPY));
     c->d_spec[t] = static_cast<unsigned char*>(c->d_spec_base[t]) + soap::PAD_FRONT * c->esize;
-    HIP_TRY(hipMemcpy2DAsync(c->d_spec[t], row_bytes, d->spectra[t], (size_t)c->P * c->esize,
+    HIP_TRY(hipMemcpy2DAsync(c->d_spec[t], row_bytes * soap::NCOPY, d->spectra[t], (size_t)c->P * c->esize,
                              (size_t)c->P * c->esize, c->B, kind, c->stream));
     c->has_type[t] = true;
   }
@@ -377,7 +377,6 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   pl.n_slabs = (c->N + soap::SLAB_COLS - 1) / soap::SLAB_COLS;
   pl.n_chunks = (n_phases + c->pc - 1) / c->pc;
   pl.vg_cap = pl.G * ((c->J + soap::APPLY_JW - 1) / soap::APPLY_JW);
-  const size_t ent_bytes = (c->prec == SOAP_PREC_FP32) ? sizeof(soap::Entry<float>) : sizeof(soap::Entry<double>);
   const size_t GJ = (size_t)pl.G * c->J;
 
   // parameter block (regions then phases) in the next pinned slot; the
@@ -390,7 +389,7 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   HIP_TRY(grow(c->ws_mask64, sizeof(unsigned long long) * (size_t)n_phases * pl.G));
   HIP_TRY(grow(c->ws_vg, sizeof(soap::VGroup) * (size_t)pl.n_chunks * pl.vg_cap));
   HIP_TRY(grow(c->ws_nvg, sizeof(int) * (size_t)pl.n_chunks));
-  HIP_TRY(grow(c->ws_ent, ent_bytes * (size_t)pl.n_chunks * pl.vg_cap * c->pc * soap::ENT_PER));
+  HIP_TRY(grow(c->ws_taps, c->esize * (size_t)pl.n_chunks * pl.vg_cap * soap::APPLY_JW * soap::PC_MAX));
   const size_t out_bytes = (size_t)n_phases * c->P * c->esize;
   void* dflux = flux;
   if (!flux_on_device) {
@@ -438,13 +437,13 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
     StageTimer t(c, ST_COMPACT);
     HIP_TRY(soap::launch_reduce_taps(c, pl, dKp, dslab, dK, dmask));
     HIP_TRY(soap::launch_compact(c, pl, dK, dmask, static_cast<soap::VGroup*>(c->ws_vg.ptr),
-                                 static_cast<int*>(c->ws_nvg.ptr), c->ws_ent.ptr));
+                                 static_cast<int*>(c->ws_nvg.ptr), c->ws_taps.ptr));
     t.done();
   }
   {
     StageTimer t(c, ST_APPLY);
     HIP_TRY(soap::launch_apply(c, pl, static_cast<const soap::VGroup*>(c->ws_vg.ptr),
-                               static_cast<const int*>(c->ws_nvg.ptr), c->ws_ent.ptr, dflux));
+                               static_cast<const int*>(c->ws_nvg.ptr), c->ws_taps.ptr, dflux));
     t.done();
   }
   c->active_calls++;
@@ -469,7 +468,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   ARG_CHECK(mask != nullptr, "mask is NULL");
   ARG_CHECK(mask->n_lines >= 1 && mask->n_lines <= (int64_t(1) << 20), "mask.n_lines must be in [1, 2^20]");
   ARG_CHECK(mask->ln_lambda != nullptr && mask->weight != nullptr, "mask arrays are NULL");
-  ARG_CHECK(mask->n_v >= 4 && mask->n_v <= 1024, "mask.n_v must be in [4, 1024]");
+  ARG_CHECK(mask->n_v >= 4 && mask->n_v <= 768, "mask.n_v must be in [4, 768]");
   ARG_CHECK(is_finite(mask->v0_kms) && is_finite(mask->dv_kms) && mask->dv_kms > 0.0, "mask velocity grid invalid");
   ARG_CHECK(is_finite(mask->half_width_kms) && mask->half_width_kms > 0.0, "mask.half_width_kms must be > 0");
   const double vlo = mask->v0_kms - mask->half_width_kms;
@@ -479,6 +478,12 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   const double hole_px = 2.0 * std::atanh(mask->half_width_kms / soap::C_KMS) / c->dln;
   if (hole_px > 8.0) {
     setf(c->err, "mask holes of %.2f pixels exceed the supported 8 pixels", hole_px);
+    return SOAP_ERR_UNSUPPORTED;
+  }
+  const double reach_px = (std::atanh(vhi / soap::C_KMS) - std::atanh(vlo / soap::C_KMS)) / c->dln;
+  if (reach_px + 4.0 > soap::ccf_span_pixels(c->prec == SOAP_PREC_FP32)) {
+    setf(c->err, "the velocity grid spans %.0f pixels, beyond the supported %d", reach_px,
+         soap::ccf_span_pixels(c->prec == SOAP_PREC_FP32) - 4);
     return SOAP_ERR_UNSUPPORTED;
   }
   const int nl = (int)mask->n_lines;

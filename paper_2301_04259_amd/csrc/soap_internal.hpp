@@ -33,13 +33,15 @@ constexpr int APPLY_TILE = APPLY_R * APPLY_THREADS;
 constexpr int PC_MAX = 16;
 constexpr int PC_F32 = 16;
 constexpr int PC_F64 = 8;
-constexpr int ENT_PER = 2;  // entries per (window, phase): APPLY_JW / 4
 
 // Padded rows of the local spectra and contrast arrays: PAD_FRONT copies of
 // the first sample before it and copies of the last sample after it, so that
 // every window the apply kernel reads is in bounds and the end-value hold of
-// the interpolation comes for free.
+// the interpolation comes for free.  Each local-spectrum row is stored four
+// times, copy d shifted left by d samples (row (4 b + d)), so that a window
+// starting at any pixel is an aligned 16-byte load from one of the copies.
 constexpr int PAD_FRONT = 128;
+constexpr int NCOPY = 4;
 
 // Column slabs of the per-phase weight kernel.
 constexpr int SLAB_COLS = 32;
@@ -53,21 +55,15 @@ struct Region {
 };
 
 // A window of APPLY_JW tap offsets [jlo, jlo + APPLY_JW) of one group in one
-// phase chunk, with the number of tap runs each phase of the chunk has in it.
+// phase chunk.  Bit p of qmask[q]: phase p of the chunk has a non-zero tap at
+// offset jlo + q.  The taps themselves are stored densely per window as
+// taps[q][p] (PC_MAX values per q, zeros where the bit is clear).
 // Group g: paired tables g = (type - 1) * B + bin; split tables
 // g = type * B + bin with type 0 the quiet removal.
 struct VGroup {
   int g;
   int jlo;
-  unsigned char cnt[PC_MAX];
-};
-
-// one run of <= 4 consecutive taps inside a window: code = q0*4 + (w-1)
-template <typename T>
-struct Entry {
-  int code;
-  int pad;
-  T k[4];
+  unsigned int qmask[APPLY_JW];
 };
 
 struct Workspace {
@@ -99,7 +95,7 @@ struct soap_ctx {
 
   // resident device state (row pointers point at pixel 0 of row 0)
   void* d_spec_base[3] = {nullptr, nullptr, nullptr};
-  void* d_spec[3] = {nullptr, nullptr, nullptr};  // [B][Pstride]
+  void* d_spec[3] = {nullptr, nullptr, nullptr};  // [B][NCOPY][Pstride]
   double* d_mu = nullptr;                          // [B]
   int* d_col_c = nullptr;                          // [N]
   double* d_col_w = nullptr;                       // [N]
@@ -117,7 +113,7 @@ struct soap_ctx {
   soap::Workspace ws_mask64;   // [n_phases][G] bitmask of nonzero offsets
   soap::Workspace ws_vg;       // [n_chunks][vg_cap] VGroup
   soap::Workspace ws_nvg;      // [n_chunks] int
-  soap::Workspace ws_ent;      // [n_chunks][vg_cap][PC][ENT_PER] Entry<T>
+  soap::Workspace ws_taps;     // [n_chunks][vg_cap][APPLY_JW][PC_MAX] taps (T)
   soap::Workspace ws_flux;     // host-output staging for fluxes
   soap::Workspace ws_ccf;      // partial CCFs
   soap::Workspace ws_ccfout;   // [n_spec][n_v] double
@@ -177,8 +173,8 @@ hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int 
 hipError_t launch_reduce_taps(soap_ctx* c, const Plan& pl, const double* d_Kp, const int* d_slab, double* d_K,
                               unsigned long long* d_mask);
 hipError_t launch_compact(soap_ctx* c, const Plan& pl, const double* d_K, const unsigned long long* d_mask,
-                          VGroup* d_vg, int* d_nvg, void* d_ent);
-hipError_t launch_apply(soap_ctx* c, const Plan& pl, const VGroup* d_vg, const int* d_nvg, const void* d_ent,
+                          VGroup* d_vg, int* d_nvg, void* d_taps);
+hipError_t launch_apply(soap_ctx* c, const Plan& pl, const VGroup* d_vg, const int* d_nvg, const void* d_taps,
                         void* d_flux);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
@@ -187,6 +183,7 @@ hipError_t launch_gfit(soap_ctx* c, const double* d_ccf, int64_t n_spec, soap_rv
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask);
 
 int ccf_line_blocks(int n_lines);
+int ccf_span_pixels(bool fp32);
 
 // ---- device helpers ---------------------------------------------------------
 #ifdef __HIP_DEVICE_COMPILE__

@@ -25,7 +25,8 @@
 //
 // k_reduce_taps sums the slab partials in slab order and records, per
 // (phase, group), the bitmask of non-zero offsets.  k_compact turns each
-// chunk of phases into windows of APPLY_JW offsets and runs of <= 4 taps.
+// chunk of phases into windows of APPLY_JW offsets with dense taps and
+// per-offset phase masks.
 // Every sum has a fixed order, so results repeat bit for bit.
 #include "soap_internal.hpp"
 
@@ -281,13 +282,14 @@ __global__ void k_reduce_taps(int n_ph, int G, int J, int n_slabs, const double*
   mask[(int64_t)ph * G + g] = mk;
 }
 
-// one block per chunk of PC phases: windows and tap runs
+// one block per chunk of PC phases: windows of APPLY_JW offsets with their
+// dense [offset][phase] taps and per-offset phase masks
 template <typename T>
 __global__ void __launch_bounds__(256) k_compact(int n_ph, int PC, int G, int J, int jmin,
                                                  const double* __restrict__ K,
                                                  const unsigned long long* __restrict__ mask,
                                                  VGroup* __restrict__ vgs, int* __restrict__ nvg,
-                                                 Entry<T>* __restrict__ ents, int vg_cap) {
+                                                 T* __restrict__ taps, int vg_cap) {
   extern __shared__ int sm[];
   int* s_cnt = sm;           // [G] windows per group
   int* s_base = sm + G;      // [G] first window index
@@ -297,8 +299,9 @@ __global__ void __launch_bounds__(256) k_compact(int n_ph, int PC, int G, int J,
   const int p0 = chunk * PC;
   const int np = min(PC, n_ph - p0);
   const int GJ = G * J;
+  const int nwin = (J + APPLY_JW - 1) / APPLY_JW;
   VGroup* vg = vgs + (int64_t)chunk * vg_cap;
-  Entry<T>* en = ents + (int64_t)chunk * vg_cap * PC * ENT_PER;
+  T* tp = taps + (int64_t)chunk * vg_cap * APPLY_JW * PC_MAX;
 
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     unsigned long long u = 0;
@@ -323,44 +326,32 @@ __global__ void __launch_bounds__(256) k_compact(int n_ph, int PC, int G, int J,
     nvg[chunk] = acc;
   }
   __syncthreads();
-  // one thread per (group, phase): window records (phase 0 writes g / jlo)
-  // and the runs of <= 4 taps of that phase in each window
-  for (int t = threadIdx.x; t < G * PC; t += blockDim.x) {
-    const int g = t / PC, p = t - g * PC;
+  // one thread per (group, window slot, offset)
+  for (int t = threadIdx.x; t < G * nwin * APPLY_JW; t += blockDim.x) {
+    const int g = t / (nwin * APPLY_JW);
+    const int rem = t - g * nwin * APPLY_JW;
+    const int wslot = rem / APPLY_JW;
+    const int q = rem - wslot * APPLY_JW;
     if (!s_cnt[g]) continue;
     const unsigned long long u = s_union[g];
+    const int a = s_lo[g] + wslot * APPLY_JW;
+    if (a >= J || !((u >> a) & ((1ull << APPLY_JW) - 1))) continue;
     int v = s_base[g];
-    for (int a = s_lo[g]; a < J; a += APPLY_JW) {
-      if (!((u >> a) & ((1ull << APPLY_JW) - 1))) continue;
-      if (p == 0) {
-        vg[v].g = g;
-        vg[v].jlo = jmin + a;
-      }
-      int e = 0;
-      if (p < np) {
-        const double* kr = K + (int64_t)(p0 + p) * GJ + g * J;
-        const unsigned long long mp = mask[(int64_t)(p0 + p) * G + g];
-        int q = 0;
-        while (q < APPLY_JW) {
-          if (a + q < J && ((mp >> (a + q)) & 1)) {
-            int w = 1;
-            for (int s = 1; s < 4 && q + s < APPLY_JW && a + q + s < J; ++s)
-              if ((mp >> (a + q + s)) & 1) w = s + 1;
-            Entry<T> E;
-            E.code = q * 4 + (w - 1);
-            E.pad = 0;
-            for (int s = 0; s < 4; ++s) E.k[s] = (s < w) ? (T)kr[a + q + s] : (T)0;
-            en[((int64_t)v * PC + p) * ENT_PER + e] = E;
-            ++e;
-            q += 4;
-          } else {
-            ++q;
-          }
-        }
-      }
-      vg[v].cnt[p] = (unsigned char)e;
-      ++v;
+    for (int b = s_lo[g]; b < a; b += APPLY_JW)
+      if ((u >> b) & ((1ull << APPLY_JW) - 1)) ++v;
+    if (q == 0) {
+      vg[v].g = g;
+      vg[v].jlo = jmin + a;
     }
+    unsigned int m = 0;
+    T* row = tp + ((int64_t)v * APPLY_JW + q) * PC_MAX;
+    for (int p = 0; p < PC_MAX; ++p) {
+      double k = 0.0;
+      if (p < np && a + q < J) k = K[(int64_t)(p0 + p) * GJ + g * J + a + q];
+      row[p] = (T)k;
+      if (k != 0.0) m |= 1u << p;
+    }
+    vg[v].qmask[q] = m;
   }
 }
 
@@ -393,14 +384,14 @@ hipError_t launch_reduce_taps(soap_ctx* c, const Plan& pl, const double* d_Kp, c
 }
 
 hipError_t launch_compact(soap_ctx* c, const Plan& pl, const double* d_K, const unsigned long long* d_mask,
-                          VGroup* d_vg, int* d_nvg, void* d_ent) {
+                          VGroup* d_vg, int* d_nvg, void* d_taps) {
   const size_t lds = (size_t)4 * pl.G * sizeof(int) + (size_t)pl.G * sizeof(unsigned long long);
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_compact<float>, dim3(pl.n_chunks), dim3(256), lds, c->stream, pl.n_ph, c->pc, pl.G, c->J,
-                       c->jmin, d_K, d_mask, d_vg, d_nvg, (Entry<float>*)d_ent, pl.vg_cap);
+                       c->jmin, d_K, d_mask, d_vg, d_nvg, (float*)d_taps, pl.vg_cap);
   else
     hipLaunchKernelGGL(k_compact<double>, dim3(pl.n_chunks), dim3(256), lds, c->stream, pl.n_ph, c->pc, pl.G,
-                       c->J, c->jmin, d_K, d_mask, d_vg, d_nvg, (Entry<double>*)d_ent, pl.vg_cap);
+                       c->J, c->jmin, d_K, d_mask, d_vg, d_nvg, (double*)d_taps, pl.vg_cap);
   return hipGetLastError();
 }
 
