@@ -80,6 +80,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=16, help="phases timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument(
+        "--copy-calib-mb",
+        type=int,
+        default=0,
+        help="run one plain elementwise copy (torch.neg) of this many MiB of float32 before the timed "
+        "region, as the known-size reference for hardware byte counters (0 = skip)",
+    )
     args = ap.parse_args()
     if args.gpus != 1:
         print(
@@ -129,6 +136,16 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+
+    if args.copy_calib_mb > 0:
+        n = args.copy_calib_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr, flush=True)
+        del src, dst
 
     print("[bench] timed steps", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
@@ -204,6 +221,11 @@ def main():
             for k in ("weights_ms", "compact_ms", "apply_ms", "ccf_ms", "gfit_ms")
         },
         "init_ms": init_ms,
+        "fit": {
+            "mean_iters": float(rvh["iters"].mean()),
+            "max_iters": int(rvh["iters"].max()),
+            "converged": int((rvh["status"] == 0).sum()),
+        },
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

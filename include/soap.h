@@ -140,7 +140,7 @@ typedef struct {
   double v0_kms;
   double dv_kms;             /* > 0                                         */
   int32_t n_v;               /* 4 .. 768; the grid (with holes) spans at most
-                                508 pixels in FP64 contexts, 1020 in FP32  */
+                                508 pixels                                  */
   int32_t reserved0;
 } soap_mask;
 
@@ -196,7 +196,7 @@ soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device,
  * contrast arrays the last soap_active_spectra read (its touched inputs).   */
 typedef struct {
   double weights_ms;         /* region weights + InfoMap + column sums      */
-  double compact_ms;         /* tap lists                                   */
+  double compact_ms;         /* slab sums and tap lists                     */
   double apply_ms;           /* shift-and-sum of the final spectra          */
   double ccf_ms;             /* CCF (incl. the fixed-order reduction)       */
   double gfit_ms;            /* Gaussian fits                               */

@@ -17,25 +17,30 @@
 //
 // Work split: one block = 256 threads x APPLY_R consecutive pixels (one tile)
 // x one chunk of PC phases.  The PC x APPLY_R accumulators live in registers.
-// For each window of APPLY_JW offsets of one group, every thread loads its
-// 11-sample source windows with three aligned 16-byte loads from the row copy
-// whose shift matches the window start (rows are padded with their end
-// samples, so no load needs a bounds check and the end-value hold of the
-// interpolation is built in).  Then, offset by offset, the chunk's taps for
-// that offset are read into scalar registers and every phase with a tap
-// there adds it with fused multiply-adds; a wave-uniform bit test skips
-// phases without one, so only non-zero taps cost arithmetic.  The next
-// window's loads are issued before the current one is consumed.  The
-// block-to-work mapping keeps the chunks of one tile on one XCD so their
-// shared input windows hit the same L2.  The final combine adds Q in double.
+// The block first copies its chunk's window records (header and dense taps,
+// built by the compaction kernel) into LDS, so the main loop reads no
+// scalar memory.  For each window of APPLY_JW offsets of one group, every
+// thread loads its 11-sample source windows with three 16-byte loads (rows
+// are padded with their end samples, so no load needs a bounds check and the
+// end-value hold of the interpolation is built in).  Then, offset by offset, the taps
+// of each group of four phases that has one there are read from LDS
+// (broadcast) and added with fused multiply-adds; a wave-uniform mask test
+// skips the other groups.  The next window's loads are issued before the
+// current one is consumed.  The block-to-work mapping keeps the chunks of
+// one tile on one XCD so their shared input windows hit the same L2.  The
+// final combine adds Q in double.
 #include "soap_internal.hpp"
 
 namespace soap {
 
 namespace {
 
-// 12 consecutive elements from an aligned address (the 11-sample window of
-// APPLY_R + APPLY_JW - 1 values plus one)
+// 12 consecutive elements from an element-aligned address (the 11-sample
+// window of APPLY_R + APPLY_JW - 1 values plus one): three 16-byte loads whose
+// type promises only element alignment
+typedef float f4e __attribute__((ext_vector_type(4), aligned(4)));
+typedef double d2e __attribute__((ext_vector_type(2), aligned(8)));
+
 template <typename T>
 struct Win12 {
   T v[12];
@@ -44,20 +49,18 @@ struct Win12 {
 template <typename T>
 __device__ __forceinline__ void load12(Win12<T>& w, const T* p) {
   if constexpr (sizeof(T) == 4) {
-    const float4* q = reinterpret_cast<const float4*>(p);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float4 f = q[k];
+      const f4e f = *reinterpret_cast<const f4e*>(p + 4 * k);
       w.v[4 * k + 0] = f.x;
       w.v[4 * k + 1] = f.y;
       w.v[4 * k + 2] = f.z;
       w.v[4 * k + 3] = f.w;
     }
   } else {
-    const double2* q = reinterpret_cast<const double2*>(p);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      double2 f = q[k];
+      const d2e f = *reinterpret_cast<const d2e*>(p + 2 * k);
       w.v[2 * k + 0] = f.x;
       w.v[2 * k + 1] = f.y;
     }
@@ -86,35 +89,41 @@ __device__ __forceinline__ void load4(T (&c)[4], const T* p) {
 // j = jlo + q, with window sample s = r - q + APPLY_JW - 1
 template <typename T>
 struct Operands {
-  Win12<T> a, b;
+  Win12<T> a, b;  // b is used by paired tables only (D = C A - B)
   T c[4];
-  int sub;  // 1: D = C A - B, 0: D = C A
 };
 
 template <typename T>
 struct ApplyArgs {
   int64_t P, Pstride;
-  int B, n_ph, n_chunks, n_tiles, effect, paired, vg_cap, vec_ok;
+  int B, n_ph, n_chunks, n_tiles, effect, paired, vg_cap, vec_ok, lds_win;
   const T *Sq, *Ss, *Sf, *Cs, *Cf;
   const double* Q;
-  const VGroup* vgs;
+  const unsigned char* wins;
   const int* nvg;
-  const T* taps;
   T* out;
 };
 
-template <typename T, int R, int JW>
-__device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int g, int jlo, int64_t m0) {
-  // group -> (type, bin) and the effect's operands
-  int t, b;
-  if (A.paired) {
-    t = g / A.B + 1;
-    b = g - (t - 1) * A.B;
-  } else {
-    t = g / A.B;
-    b = g - t * A.B;
-  }
-  const int64_t rs = (int64_t)NCOPY * A.Pstride;  // stride between mu-bin rows
+// wave-uniform header of window v in LDS
+struct Head {
+  int t, b, jlo;
+  unsigned gm;
+};
+
+__device__ __forceinline__ Head read_head(const unsigned char* s_win, int v) {
+  const int4 h = *reinterpret_cast<const int4*>(s_win + v * WIN_BYTES);
+  Head r;
+  r.t = __builtin_amdgcn_readfirstlane(h.x);
+  r.b = __builtin_amdgcn_readfirstlane(h.y);
+  r.jlo = __builtin_amdgcn_readfirstlane(h.z);
+  r.gm = (unsigned)__builtin_amdgcn_readfirstlane(h.w);
+  return r;
+}
+
+template <typename T, int R, int JW, bool PAIRED>
+__device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, const Head& h, int64_t m0) {
+  const int t = h.t, b = h.b;
+  const int64_t rs = A.Pstride;  // stride between mu-bin rows
   const T* sq = A.Sq + (int64_t)b * rs;
   const T* src;
   const T* con = nullptr;
@@ -131,17 +140,17 @@ __device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int
       src = (t == SOAP_SPOT ? A.Ss : A.Sf) + (int64_t)b * rs;
       con = (A.effect == SOAP_EFFECT_TOT) ? ct : nullptr;
     }
-    if (A.paired) sub = sq;
+    if (PAIRED) sub = sq;
   }
-  // window start m0 - jlo - (JW - 1): an aligned load from the row copy
-  // shifted by the start's distance d from alignment
-  const int off = -jlo - (JW - 1);
-  const int d = off & 3;
-  const int64_t at = (int64_t)d * A.Pstride + m0 + (off - d);
+  // window start m0 - jlo - (JW - 1)
+  const int64_t at = m0 - h.jlo - (JW - 1);
   load12(o.a, src + at);
-  o.sub = sub ? 1 : 0;
-  if (sub && sub != src) load12(o.b, sub + at);
-  else if (sub) o.b = o.a;
+  if (PAIRED) {
+    // every paired window has an active type; the flux effect shifts the
+    // quiet spectrum itself, so its difference is (C - 1) S_q
+    if (sub != src) load12(o.b, sub + at);
+    else o.b = o.a;
+  }
   if (con) {
     load4(o.c, con + m0);
   } else {
@@ -150,33 +159,54 @@ __device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int
   }
 }
 
+// taps of four consecutive phases at one offset, from LDS (all lanes read
+// the same address)
+template <typename T>
+__device__ __forceinline__ void load_taps4(T (&k)[4], const T* p) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    k[0] = f.x;
+    k[1] = f.y;
+    k[2] = f.z;
+    k[3] = f.w;
+  } else {
+    const double2 u = reinterpret_cast<const double2*>(p)[0];
+    const double2 w = reinterpret_cast<const double2*>(p)[1];
+    k[0] = u.x;
+    k[1] = u.y;
+    k[2] = w.x;
+    k[3] = w.y;
+  }
+}
+
 // One window: for every offset q with any tap in the chunk, form the
-// difference row, read the chunk's PC taps of that offset into scalar
-// registers, and let every phase with a tap add k * D with fused
-// multiply-adds (a wave-uniform bit test skips the others).
-template <typename T, int R, int PC, int JW>
-__device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, const VGroup& vg, const T* tw) {
-  unsigned m[JW];
-#pragma unroll
-  for (int q = 0; q < JW; ++q) m[q] = vg.qmask[q];
+// difference row, read the taps of the groups of four phases active there
+// and add k * D with fused multiply-adds.
+template <typename T, int R, int PC, int JW, bool PAIRED>
+__device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, unsigned gm, const T* tw) {
+  constexpr int NG = PC / 4;
+  constexpr unsigned GMASK = (1u << NG) - 1u;
 #pragma unroll
   for (int q = 0; q < JW; ++q) {
-    if (m[q] == 0) continue;
+    const unsigned nib = (gm >> (q * NG)) & GMASK;
+    if (nib == 0u) continue;
+    T k[NG][4];
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi)
+      if ((nib >> gi) & 1u) load_taps4(k[gi], tw + q * PC + 4 * gi);
     T D[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int s = r - q + JW - 1;
-      D[r] = o.sub ? fma(o.c[r], o.a.v[s], -o.b.v[s]) : o.c[r] * o.a.v[s];
+      D[r] = PAIRED ? fma(o.c[r], o.a.v[s], -o.b.v[s]) : o.c[r] * o.a.v[s];
     }
-    const T* kq = tw + q * PC_MAX;
-    T k[PC];
 #pragma unroll
-    for (int p = 0; p < PC; ++p) k[p] = kq[p];
+    for (int gi = 0; gi < NG; ++gi) {
+      if ((nib >> gi) & 1u) {
 #pragma unroll
-    for (int p = 0; p < PC; ++p) {
-      if ((m[q] >> p) & 1u) {
+        for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[p][r] = fma(k[p], D[r], acc[p][r]);
+          for (int r = 0; r < R; ++r) acc[4 * gi + p][r] = fma(k[gi][p], D[r], acc[4 * gi + p][r]);
       }
     }
   }
@@ -184,9 +214,11 @@ __device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, c
 
 }  // namespace
 
-template <typename T, int R, int PC, int JW>
+template <typename T, int R, int PC, int JW, bool PAIRED>
 __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs<T> A) {
   static_assert(R == 4 && JW == 8, "window loads are written for 4 pixels x 8 offsets");
+  static_assert(PC % 4 == 0 && JW * PC * sizeof(T) == WIN_TAP_BYTES, "record layout");
+  extern __shared__ __align__(16) unsigned char s_win[];  // [lds_win][WIN_BYTES]
   const int total = A.n_tiles * A.n_chunks;
   const int per_xcd = (total + 7) / 8;
   const int bid = blockIdx.x;
@@ -203,16 +235,33 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs<T> A) {
     for (int r = 0; r < R; ++r) acc[p][r] = T(0);
 
   const int nv = A.nvg[chunk];
-  const VGroup* vg = A.vgs + (int64_t)chunk * A.vg_cap;
-  const T* tw = A.taps + (int64_t)chunk * A.vg_cap * JW * PC_MAX;
-  Operands<T> o0, o1;
-  if (nv > 0) fetch<T, R, JW>(o0, A, vg[0].g, vg[0].jlo, m0);
-  for (int v = 0; v < nv; v += 2) {
-    if (v + 1 < nv) fetch<T, R, JW>(o1, A, vg[v + 1].g, vg[v + 1].jlo, m0);
-    consume<T, R, PC, JW>(acc, o0, vg[v], tw + (int64_t)v * JW * PC_MAX);
-    if (v + 1 < nv) {
-      if (v + 2 < nv) fetch<T, R, JW>(o0, A, vg[v + 2].g, vg[v + 2].jlo, m0);
-      consume<T, R, PC, JW>(acc, o1, vg[v + 1], tw + (int64_t)(v + 1) * JW * PC_MAX);
+  const unsigned char* gw = A.wins + (int64_t)chunk * A.vg_cap * WIN_BYTES;
+  for (int vb = 0; vb < nv; vb += A.lds_win) {
+    const int nb = min(A.lds_win, nv - vb);
+    if (vb) __syncthreads();  // every wave is done with the previous pass
+    {
+      const int4* src = reinterpret_cast<const int4*>(gw + (int64_t)vb * WIN_BYTES);
+      int4* dst = reinterpret_cast<int4*>(s_win);
+      const int n16 = nb * (WIN_BYTES / 16);
+      for (int u = threadIdx.x; u < n16; u += APPLY_THREADS) dst[u] = src[u];
+    }
+    __syncthreads();
+    Operands<T> o0, o1;
+    Head h0 = read_head(s_win, 0), h1;
+    fetch<T, R, JW, PAIRED>(o0, A, h0, m0);
+    for (int v = 0; v < nb; v += 2) {
+      if (v + 1 < nb) {
+        h1 = read_head(s_win, v + 1);
+        fetch<T, R, JW, PAIRED>(o1, A, h1, m0);
+      }
+      consume<T, R, PC, JW, PAIRED>(acc, o0, h0.gm, reinterpret_cast<const T*>(s_win + v * WIN_BYTES + 16));
+      if (v + 1 < nb) {
+        if (v + 2 < nb) {
+          h0 = read_head(s_win, v + 2);
+          fetch<T, R, JW, PAIRED>(o0, A, h0, m0);
+        }
+        consume<T, R, PC, JW, PAIRED>(acc, o1, h1.gm, reinterpret_cast<const T*>(s_win + (v + 1) * WIN_BYTES + 16));
+      }
     }
   }
 
@@ -243,27 +292,39 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs<T> A) {
   }
 }
 
-hipError_t launch_apply(soap_ctx* c, const Plan& pl, const VGroup* d_vg, const int* d_nvg, const void* d_taps,
-                        void* d_flux) {
+hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux) {
   const int total = pl.n_chunks * c->n_tiles;
   const int per_xcd = (total + 7) / 8;
   dim3 grid(8 * per_xcd);
   const bool vec_ok = (c->P % APPLY_R == 0) &&
                       (reinterpret_cast<uintptr_t>(d_flux) % (APPLY_R * c->esize) == 0);
+  const int lds_win = std::min(pl.vg_cap, APPLY_LDS_WIN);
+  const size_t lds = (size_t)lds_win * WIN_BYTES;
+  const unsigned char* w = static_cast<const unsigned char*>(d_win);
   if (c->prec == SOAP_PREC_FP32) {
     ApplyArgs<float> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, c->n_tiles, pl.effect, pl.paired, pl.vg_cap,
-                       vec_ok ? 1 : 0,
+                       vec_ok ? 1 : 0, lds_win,
                        (const float*)c->d_spec[0], (const float*)c->d_spec[1], (const float*)c->d_spec[2],
-                       (const float*)c->d_con_spot, (const float*)c->d_con_fac, c->d_Q, d_vg, d_nvg,
-                       (const float*)d_taps, (float*)d_flux};
-    hipLaunchKernelGGL((k_apply<float, APPLY_R, PC_F32, APPLY_JW>), grid, dim3(APPLY_THREADS), 0, c->stream, A);
+                       (const float*)c->d_con_spot, (const float*)c->d_con_fac, c->d_Q, w, d_nvg,
+                       (float*)d_flux};
+    if (pl.paired)
+      hipLaunchKernelGGL((k_apply<float, APPLY_R, PC_F32, APPLY_JW, true>), grid, dim3(APPLY_THREADS), lds,
+                         c->stream, A);
+    else
+      hipLaunchKernelGGL((k_apply<float, APPLY_R, PC_F32, APPLY_JW, false>), grid, dim3(APPLY_THREADS), lds,
+                         c->stream, A);
   } else {
     ApplyArgs<double> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, c->n_tiles, pl.effect, pl.paired,
-                        pl.vg_cap, vec_ok ? 1 : 0,
+                        pl.vg_cap, vec_ok ? 1 : 0, lds_win,
                         (const double*)c->d_spec[0], (const double*)c->d_spec[1], (const double*)c->d_spec[2],
-                        (const double*)c->d_con_spot, (const double*)c->d_con_fac, c->d_Q, d_vg, d_nvg,
-                        (const double*)d_taps, (double*)d_flux};
-    hipLaunchKernelGGL((k_apply<double, APPLY_R, PC_F64, APPLY_JW>), grid, dim3(APPLY_THREADS), 0, c->stream, A);
+                        (const double*)c->d_con_spot, (const double*)c->d_con_fac, c->d_Q, w, d_nvg,
+                        (double*)d_flux};
+    if (pl.paired)
+      hipLaunchKernelGGL((k_apply<double, APPLY_R, PC_F64, APPLY_JW, true>), grid, dim3(APPLY_THREADS), lds,
+                         c->stream, A);
+    else
+      hipLaunchKernelGGL((k_apply<double, APPLY_R, PC_F64, APPLY_JW, false>), grid, dim3(APPLY_THREADS), lds,
+                         c->stream, A);
   }
   return hipGetLastError();
 }

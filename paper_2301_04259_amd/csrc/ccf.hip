@@ -11,126 +11,159 @@
 // geometry for every spectrum of the block.  Partial sums per line block are
 // added in a fixed order by a second kernel, so results repeat bit for bit.
 //
-// Fit: one wave64 per CCF; Levenberg-Marquardt in double on the unweighted
-// least squares of c0 - a exp(-(v - mu)^2 / (2 sigma^2)); J^T J and J^T r
-// are wave reductions, the 4 x 4 damped system is solved by Cholesky in every
-// lane.  Start values: c0 = max, a = c0 - min, mu = v at the min, sigma from
-// the half-depth width.
+// Fit: one wave64 per CCF; damped Newton (Levenberg-Marquardt damping) in
+// double on the unweighted least squares of c0 - a exp(-(v - mu)^2 /
+// (2 sigma^2)); the gradient, J^T J and the second-derivative sums are wave
+// reductions, the 4 x 4 damped system is solved by Cholesky in every lane.
+// Start values: c0 = max, a = c0 - min, mu = v at the min, sigma from the
+// half-depth width.
 #include "soap_internal.hpp"
+#include "wave.hpp"
 
 namespace soap {
 
 constexpr int CCF_LINES = 64;  // lines per block (partial sums per block)
-constexpr int CCF_BATCH = 16;  // lines staged in LDS at a time
 constexpr int CCF_SB = 8;      // spectra per block
 constexpr int CCF_THREADS = 192;
-constexpr int CCF_LDS = 32768; // bytes of staged spectra per block
-template <typename T>
-constexpr int ccf_span() { return CCF_LDS / (CCF_SB * (int)sizeof(T)); }  // pixels per spectrum
+constexpr int CCF_SPAN = 512;  // staged pixels per spectrum (double, 32 KB per block)
+// a line's hole centre, in pixels, is kept within this margin of the grid:
+// lines further out reach no pixel
+constexpr double CCF_U_MARGIN = 4096.0;
 
 int ccf_line_blocks(int n_lines) { return (n_lines + CCF_LINES - 1) / CCF_LINES; }
-int ccf_span_pixels(bool fp32) { return fp32 ? ccf_span<float>() : ccf_span<double>(); }
+int ccf_span_pixels(bool) { return CCF_SPAN; }
 
-__global__ void k_mask_prep(int n, double ln0, double dln, const double* __restrict__ lnl,
+__global__ void k_mask_prep(int n, double ln0, double dln, double P, const double* __restrict__ lnl,
                             const double* __restrict__ w, double2* __restrict__ out) {
   int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < n) out[l] = make_double2((lnl[l] - ln0) / dln + 0.5, w[l]);
+  if (l < n) {
+    const double u = (lnl[l] - ln0) / dln + 0.5;
+    out[l] = make_double2(fmin(fmax(u, -CCF_U_MARGIN), P + CCF_U_MARGIN), w[l]);
+  }
 }
 
-// One block per (64 mask lines, 8 spectra).  Lines are taken in batches of
-// up to 16 whose holes, at any trial velocity, reach a pixel span that fits
-// the LDS stage; that span is staged for the block's spectra (coalesced
-// loads), then one thread per velocity computes each hole's pixel overlaps
-// once and applies them to every staged spectrum, accumulating in double.
-template <typename T>
-__global__ void __launch_bounds__(CCF_THREADS) k_ccf(int64_t P, int64_t n_spec, const T* __restrict__ F,
+// One block per (64 mask lines, 8 spectra).  The block's lines go to LDS
+// and are split once into batches whose holes, at any trial velocity, reach
+// a pixel span that fits the LDS stage.  Batch by batch the span of the
+// block's spectra is staged in double (coalesced loads; the next batch's
+// loads are in flight in registers while the current one is used), then one
+// thread per velocity computes each hole's pixel overlaps once and applies
+// them to every staged spectrum, accumulating in double.
+template <typename T, int A>
+__global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, const T* __restrict__ F,
                                                      int n_lines, const double2* __restrict__ mask, int n_v,
                                                      double v0, double dv, double h, double dln,
                                                      double* __restrict__ part) {
-  constexpr int SPAN = ccf_span<T>();
-  __shared__ T st[CCF_SB][SPAN];
-  __shared__ int64_t s_lo;
-  __shared__ int s_len, s_b1;
+  constexpr int U = (CCF_SPAN + CCF_THREADS - 1) / CCF_THREADS;  // staged elements per thread and spectrum
+  __shared__ double st[CCF_SB][CCF_SPAN];
+  __shared__ double2 s_mask[CCF_LINES];
+  __shared__ int s_lo[CCF_LINES], s_len[CCF_LINES], s_end[CCF_LINES];
+  __shared__ int s_nb;
+  const int tid = threadIdx.x;
   const int lb = blockIdx.x;
   const int64_t s0 = (int64_t)blockIdx.y * CCF_SB;
   const int l0 = lb * CCF_LINES;
-  const int l1 = min(n_lines, l0 + CCF_LINES);
+  const int nl = min(CCF_LINES, n_lines - l0);
   const int ns = (int)min<int64_t>(CCF_SB, n_spec - s0);
-  // hole edges of every velocity this block handles: a thread keeps its own
-  const int kk = threadIdx.x;  // velocities kk, kk + blockDim.x, ...
+  if (tid < nl) s_mask[tid] = mask[l0 + tid];
   // extreme edges over the velocity grid bound the staged span
   const double alo_min = atanh((v0 - h) / C_KMS) / dln;
   const double ahi_max = atanh((v0 + dv * (n_v - 1) + h) / C_KMS) / dln;
-  double acc[4][CCF_SB];  // up to 4 velocities per thread (n_v <= 4 * CCF_THREADS)
+  // hole edges of the velocities this thread handles: tid + a * CCF_THREADS
+  double alo[A], ahi[A], acc[A][CCF_SB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int s = 0; s < CCF_SB; ++s) acc[a][s] = 0.0;
-  double alo[4], ahi[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int k = kk + a * CCF_THREADS;
-    const double vk = v0 + dv * k;
+  for (int a = 0; a < A; ++a) {
+    const double vk = v0 + dv * (tid + a * CCF_THREADS);
     alo[a] = atanh((vk - h) / C_KMS) / dln;
     ahi[a] = atanh((vk + h) / C_KMS) / dln;
+#pragma unroll
+    for (int s = 0; s < CCF_SB; ++s) acc[a][s] = 0.0;
   }
-  for (int b0 = l0; b0 < l1;) {
-    if (threadIdx.x == 0) {
-      // grow the batch while the reach of all its holes fits the stage
-      int64_t lo = (int64_t)floor(mask[b0].x + alo_min);
-      int64_t hi = (int64_t)floor(mask[b0].x + ahi_max) + 1;
-      int e = b0 + 1;
-      while (e < l1 && e - b0 < CCF_BATCH) {
-        const int64_t nlo = min(lo, (int64_t)floor(mask[e].x + alo_min));
-        const int64_t nhi = max(hi, (int64_t)floor(mask[e].x + ahi_max) + 1);
-        if (nhi - nlo + 1 > SPAN) break;
+  __syncthreads();
+  if (tid == 0) {
+    // batches of consecutive lines whose joint reach fits the stage
+    int nb = 0;
+    int lo = (int)floor(s_mask[0].x + alo_min);
+    int hi = (int)floor(s_mask[0].x + ahi_max) + 1;
+    for (int l = 1; l < nl; ++l) {
+      const int llo = (int)floor(s_mask[l].x + alo_min);
+      const int lhi = (int)floor(s_mask[l].x + ahi_max) + 1;
+      const int nlo = min(lo, llo), nhi = max(hi, lhi);
+      if (nhi - nlo + 1 > CCF_SPAN) {
+        s_lo[nb] = lo;
+        s_len[nb] = min(CCF_SPAN, hi - lo + 1);
+        s_end[nb] = l;
+        ++nb;
+        lo = llo;
+        hi = lhi;
+      } else {
         lo = nlo;
         hi = nhi;
-        ++e;
-      }
-      s_lo = lo;
-      s_len = (int)min<int64_t>(SPAN, hi - lo + 1);
-      s_b1 = e;
-    }
-    __syncthreads();
-    const int64_t lo = s_lo;
-    const int len = s_len;
-    const int b1 = s_b1;
-    for (int s = 0; s < ns; ++s) {
-      const T* row = F + (s0 + s) * P;
-      for (int i = threadIdx.x; i < len; i += blockDim.x) {
-        const int64_t m = lo + i;
-        st[s][i] = (m >= 0 && m < P) ? row[m] : T(0);
       }
     }
-    __syncthreads();
-    for (int l = b0; l < b1; ++l) {
-      const double2 mw = mask[l];
+    s_lo[nb] = lo;
+    s_len[nb] = min(CCF_SPAN, hi - lo + 1);
+    s_end[nb] = nl;
+    s_nb = nb + 1;
+  }
+  __syncthreads();
+  const int nb = s_nb;
+  T vals[CCF_SB][U];
+  auto load = [&](int bi) {
+    const int lo = s_lo[bi];
+    const int len = s_len[bi];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int k = kk + a * CCF_THREADS;
+    for (int s = 0; s < CCF_SB; ++s) {
+      const T* row = F + (s0 + s) * (int64_t)P;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = tid + u * CCF_THREADS;
+        const int m = lo + i;
+        vals[s][u] = (s < ns && i < len && m >= 0 && m < P) ? row[m] : T(0);
+      }
+    }
+  };
+  load(0);
+  for (int bi = 0; bi < nb; ++bi) {
+    const int lo = s_lo[bi];
+    const int len = s_len[bi];
+    const int lbeg = bi ? s_end[bi - 1] : 0;
+    const int lend = s_end[bi];
+    if (bi) __syncthreads();  // every thread is done with the previous stage
+#pragma unroll
+    for (int s = 0; s < CCF_SB; ++s)
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = tid + u * CCF_THREADS;
+        if (i < len) st[s][i] = (double)vals[s][u];
+      }
+    __syncthreads();
+    if (bi + 1 < nb) load(bi + 1);
+    for (int l = lbeg; l < lend; ++l) {
+      const double2 mw = s_mask[l];
+#pragma unroll
+      for (int a = 0; a < A; ++a) {
+        const int k = tid + a * CCF_THREADS;
         if (k >= n_v) break;
         const double qlo = mw.x + alo[a];
         const double qhi = mw.x + ahi[a];
-        const int64_t ma = (int64_t)floor(qlo);
-        const int64_t mb = (int64_t)floor(qhi);
-        for (int64_t m = ma; m <= mb; ++m) {
+        const int ma = (int)floor(qlo);
+        const int mb = (int)floor(qhi);
+        for (int m = ma; m <= mb; ++m) {
           const double ov = fmin(qhi, (double)(m + 1)) - fmax(qlo, (double)m);
-          const int64_t i = m - lo;
-          if (ov > 0.0 && m >= 0 && m < P && i >= 0 && i < len) {
+          const int i = m - lo;
+          if (ov > 0.0 && m >= 0 && m < P && (unsigned)i < (unsigned)len) {
             const double wo = mw.y * ov;
 #pragma unroll
-            for (int s = 0; s < CCF_SB; ++s) acc[a][s] = fma(wo, (double)st[s][i], acc[a][s]);
+            for (int s = 0; s < CCF_SB; ++s) acc[a][s] = fma(wo, st[s][i], acc[a][s]);
           }
         }
       }
     }
-    __syncthreads();
-    b0 = b1;
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int k = kk + a * CCF_THREADS;
+  for (int a = 0; a < A; ++a) {
+    const int k = tid + a * CCF_THREADS;
     if (k >= n_v) break;
 #pragma unroll
     for (int s = 0; s < CCF_SB; ++s)
@@ -149,63 +182,84 @@ __global__ void k_ccf_reduce(int n_lb, int64_t n_spec, int n_v, const double* __
 
 namespace {
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 constexpr double FWHM_PER_SIGMA = 2.3548200450309493;  // 2 sqrt(2 ln 2)
 constexpr int GF_MAXPT = 12;                            // points per lane (n_v <= 768)
 
-// chi^2 and optionally J^T J (10 unique) / J^T r (4) at p
-__device__ void gf_eval(const double* y, int n_v, double v0, double dv, const double p[4], bool jac,
-                        double& chi2, double jtj[10], double jtr[4]) {
+// Sums of the fit at p, identical in every lane: S[0] = chi^2,
+// S[1..4] = g = J^T r, S[5..14] = J^T J (upper triangle, row by row),
+// S[15..19] = sum r d2f/dp_a dp_b for (amp, mu), (amp, sigma), (mu, mu),
+// (mu, sigma), (sigma, sigma) (the only second derivatives that are not
+// zero), with f = c0 - amp e, e = exp(-(v - mu)^2 / (2 sigma^2)), r = f - y
+// and parameters ordered (c0, amp, mu, sigma).
+__device__ void gf_eval(const double (&y)[GF_MAXPT], int n_v, double v0, double dv, const double p[4],
+                        double S[20]) {
   const int lane = threadIdx.x;
-  double c2 = 0.0;
-  double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  double b[4] = {0, 0, 0, 0};
-  const double is2 = 1.0 / (p[3] * p[3]);
+  double v[16], w[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = w[q] = 0.0;
+  const double is = 1.0 / p[3];
+  const double is2 = is * is;
+#pragma unroll
   for (int t = 0; t < GF_MAXPT; ++t) {
+    if (64 * t >= n_v) break;  // uniform
     const int i = lane + 64 * t;
-    if (i >= n_v) break;
-    const double v = v0 + dv * i;
-    const double d = v - p[2];
-    const double e = exp(-0.5 * d * d * is2);
-    const double r = p[0] - p[1] * e - y[i];
-    c2 += r * r;
-    if (jac) {
-      const double g0 = 1.0;
-      const double g1 = -e;
-      const double g2 = -p[1] * e * d * is2;
-      const double g3 = -p[1] * e * d * d * is2 / p[3];
-      const double g[4] = {g0, g1, g2, g3};
-      int q = 0;
-      for (int r0 = 0; r0 < 4; ++r0) {
-        b[r0] += g[r0] * r;
-        for (int r1 = r0; r1 < 4; ++r1) a[q++] += g[r0] * g[r1];
-      }
+    if (i < n_v) {
+      const double x = v0 + dv * i;
+      const double d = x - p[2];
+      const double z = d * d * is2;  // (d / sigma)^2
+      const double e = exp(-0.5 * z);
+      const double ae = p[1] * e;
+      const double r = p[0] - ae - y[t];
+      const double g[4] = {1.0, -e, -ae * d * is2, -ae * z * is};
+      v[0] += r * r;
+#pragma unroll
+      for (int r0 = 0; r0 < 4; ++r0) v[1 + r0] += g[r0] * r;
+      int q = 5;
+#pragma unroll
+      for (int r0 = 0; r0 < 4; ++r0)
+#pragma unroll
+        for (int r1 = r0; r1 < 4; ++r1) v[q++] += g[r0] * g[r1];
+      const double re = r * e;
+      w[0] += re * (-d * is2);                       // (amp, mu)
+      w[1] += re * (-z * is);                        // (amp, sigma)
+      w[2] += r * (-ae * (z - 1.0) * is2);           // (mu, mu)
+      w[3] += r * (-ae * d * (z - 2.0) * is2 * is);  // (mu, sigma)
+      w[4] += r * (-ae * z * (z - 3.0) * is2);       // (sigma, sigma)
     }
   }
-  chi2 = wsum(c2);
-  if (jac) {
-    for (int q = 0; q < 10; ++q) jtj[q] = wsum(a[q]);
-    for (int q = 0; q < 4; ++q) jtr[q] = wsum(b[q]);
-  }
+  const double tv = butterfly16(v, lane);
+  const double tw = butterfly16(w, lane);
+#pragma unroll
+  for (int q = 0; q < 15; ++q) S[q] = read_lane(tv, 4 * q);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) S[15 + q] = read_lane(tw, 4 * q);
 }
 
-// solve (A + lam diag A) x = -g for symmetric positive definite 4 x 4 A
-__device__ bool gf_solve(const double jtj[10], const double jtr[4], double lam, double x[4]) {
+// Solves (H + lam diag(J^T J)) x = -g by Cholesky, H = J^T J (+ the
+// second-derivative sums when newton is set).  False when the matrix is not
+// positive definite.
+__device__ bool gf_solve(const double S[20], bool newton, double lam, double x[4]) {
   double A[4][4];
-  int q = 0;
+  int q = 5;
   for (int r0 = 0; r0 < 4; ++r0)
     for (int r1 = r0; r1 < 4; ++r1) {
-      A[r0][r1] = jtj[q];
-      A[r1][r0] = jtj[q];
+      A[r0][r1] = S[q];
+      A[r1][r0] = S[q];
       ++q;
     }
-  for (int r = 0; r < 4; ++r) A[r][r] *= (1.0 + lam);
-  double L[4][4] = {{0}};
+  if (newton) {
+    A[1][2] += S[15];
+    A[2][1] += S[15];
+    A[1][3] += S[16];
+    A[3][1] += S[16];
+    A[2][2] += S[17];
+    A[2][3] += S[18];
+    A[3][2] += S[18];
+    A[3][3] += S[19];
+  }
+  const double dg[4] = {S[5], S[9], S[12], S[14]};  // diag(J^T J)
+  for (int r = 0; r < 4; ++r) A[r][r] += lam * dg[r];
+  double L[4][4] = {{0}}, rd[4];
   for (int i = 0; i < 4; ++i) {
     for (int j = 0; j <= i; ++j) {
       double s = A[i][j];
@@ -213,40 +267,63 @@ __device__ bool gf_solve(const double jtj[10], const double jtr[4], double lam, 
       if (i == j) {
         if (!(s > 0.0)) return false;
         L[i][i] = sqrt(s);
+        rd[i] = 1.0 / L[i][i];
       } else {
-        L[i][j] = s / L[j][j];
+        L[i][j] = s * rd[j];
       }
     }
   }
   double z[4];
   for (int i = 0; i < 4; ++i) {
-    double s = -jtr[i];
+    double s = -S[1 + i];
     for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
-    z[i] = s / L[i][i];
+    z[i] = s * rd[i];
   }
   for (int i = 3; i >= 0; --i) {
     double s = z[i];
     for (int k = i + 1; k < 4; ++k) s -= L[k][i] * x[k];
-    x[i] = s / L[i][i];
+    x[i] = s * rd[i];
   }
   return true;
 }
 
 }  // namespace
 
+// Damped Newton / Levenberg-Marquardt: the step solves
+// (H + lam diag(J^T J)) x = -J^T r with H the full Hessian of chi^2 / 2
+// (J^T J plus the residual-weighted second derivatives; the CCF is not an
+// exact Gaussian, so the residuals stay finite and Gauss-Newton alone
+// converges only linearly) and falls back to H = J^T J where the full one
+// is not positive definite.  A trial step is evaluated with all its sums,
+// so an accepted step costs one pass over the CCF.  The fit has converged
+// when an accepted step moves every parameter by at most 1e-10 of its scale
+// (sigma for the centre and width), or when it no longer lowers chi^2 and
+// moves the centre and width by at most 1e-9 sigma (the rounding floor); a
+// run of rejected steps that drives the damping past 1e10 means no downhill
+// step exists at this precision, which is also the minimum.
 __global__ void __launch_bounds__(64) k_gfit(int64_t n_spec, int n_v, double v0, double dv,
                                              const double* __restrict__ ccf, soap_rv* __restrict__ out) {
   const int64_t s = blockIdx.x;
   const int lane = threadIdx.x;
-  const double* y = ccf + s * n_v;
+  const double* yg = ccf + s * n_v;
+  double y[GF_MAXPT];
+#pragma unroll
+  for (int t = 0; t < GF_MAXPT; ++t) {
+    const int i = lane + 64 * t;
+    y[t] = (i < n_v) ? yg[i] : 0.0;
+  }
   // start values: max, first argmin, half-depth width
   double ymax = -1e308, ymin = 1e308;
   int kmin = n_v;
-  for (int i = lane; i < n_v; i += 64) {
-    ymax = fmax(ymax, y[i]);
-    if (y[i] < ymin) {
-      ymin = y[i];
-      kmin = i;
+#pragma unroll
+  for (int t = 0; t < GF_MAXPT; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n_v) {
+      ymax = fmax(ymax, y[t]);
+      if (y[t] < ymin) {
+        ymin = y[t];
+        kmin = i;
+      }
     }
   }
 #pragma unroll
@@ -263,8 +340,10 @@ __global__ void __launch_bounds__(64) k_gfit(int64_t n_spec, int n_v, double v0,
   const double a0 = c0 - ymin;
   const double half = c0 - 0.5 * a0;
   int first = n_v, last = -1;
-  for (int i = lane; i < n_v; i += 64) {
-    if (y[i] <= half) {
+#pragma unroll
+  for (int t = 0; t < GF_MAXPT; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n_v && y[t] <= half) {
       first = min(first, i);
       last = max(last, i);
     }
@@ -283,49 +362,46 @@ __global__ void __launch_bounds__(64) k_gfit(int64_t n_spec, int n_v, double v0,
     res.status = 2;
     res.iters = 0;
   } else {
-    double chi2, jtj[10], jtr[4];
-    gf_eval(y, n_v, v0, dv, p, true, chi2, jtj, jtr);
+    double S[20];
+    gf_eval(y, n_v, v0, dv, p, S);
     double lam = 1e-3;
     int it = 0;
     res.status = 1;
-    for (; it < 200; ++it) {
-      bool accepted = false;
-      double step[4] = {0, 0, 0, 0};
-      double chi2n = chi2;
-      while (lam < 1e20) {
-        double x[4];
-        if (gf_solve(jtj, jtr, lam, x)) {
-          double pn[4] = {p[0] + x[0], p[1] + x[1], p[2] + x[2], p[3] + x[3]};
-          double dummy10[10], dummy4[4];
-          gf_eval(y, n_v, v0, dv, pn, false, chi2n, dummy10, dummy4);
-          if (chi2n <= chi2) {
-            for (int q = 0; q < 4; ++q) {
-              step[q] = x[q];
-              p[q] = pn[q];
-            }
-            accepted = true;
-            lam = fmax(lam * 0.1, 1e-12);
-            break;
-          }
+    for (; it < 100; ++it) {
+      double x[4];
+      double Sn[20];
+      bool ok = gf_solve(S, true, lam, x) || gf_solve(S, false, lam, x);
+      double pn[4] = {p[0], p[1], p[2], p[3]};
+      if (ok) {
+        for (int q = 0; q < 4; ++q) pn[q] = p[q] + x[q];
+        gf_eval(y, n_v, v0, dv, pn, Sn);
+        ok = Sn[0] <= S[0];
+      }
+      if (!ok) {
+        lam = (lam > 0.0) ? lam * 10.0 : 1e-6;
+        if (lam > 1e10) {
+          res.status = 0;
+          ++it;
+          break;
         }
-        lam *= 10.0;
+        continue;
       }
-      if (!accepted) {
-        // no downhill step at any damping: at the minimum to rounding
-        res.status = 0;
-        break;
-      }
-      const double dchi = chi2 - chi2n;
-      chi2 = chi2n;
-      gf_eval(y, n_v, v0, dv, p, true, chi2, jtj, jtr);
-      if (fabs(step[2]) < 1e-11 && fabs(step[3]) < 1e-11 * fabs(p[3]) && dchi <= 1e-14 * chi2 + 1e-300) {
+      const double sig = fabs(pn[3]);
+      const double dchi = S[0] - Sn[0];
+      for (int q = 0; q < 4; ++q) p[q] = pn[q];
+      for (int q = 0; q < 20; ++q) S[q] = Sn[q];
+      lam = (lam > 1e-9) ? lam * 0.1 : 0.0;
+      const bool small = fabs(x[0]) <= 1e-10 * fabs(p[0]) && fabs(x[1]) <= 1e-10 * fabs(p[1]) &&
+                         fabs(x[2]) <= 1e-10 * sig && fabs(x[3]) <= 1e-10 * sig;
+      const bool floor_hit = dchi <= 1e-15 * S[0] && fabs(x[2]) <= 1e-9 * sig && fabs(x[3]) <= 1e-9 * sig;
+      if (small || floor_hit) {
         res.status = 0;
         ++it;
         break;
       }
     }
     res.iters = it;
-    res.chi2 = chi2;
+    res.chi2 = S[0];
   }
   res.rv_kms = p[2];
   res.sigma_kms = fabs(p[3]);
@@ -336,18 +412,29 @@ __global__ void __launch_bounds__(64) k_gfit(int64_t n_spec, int n_v, double v0,
   if (lane == 0) out[s] = res;
 }
 
+template <typename T>
+static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, const double* d_mask,
+                         int n_lines, double* d_part) {
+  const T* F = static_cast<const T*>(d_flux);
+  const double2* M = reinterpret_cast<const double2*>(d_mask);
+  const int nv = c->mask_nv;
+  if (nv <= CCF_THREADS)
+    hipLaunchKernelGGL((k_ccf<T, 1>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M, nv,
+                       c->mask_v0, c->mask_dv, c->mask_h, c->dln, d_part);
+  else if (nv <= 2 * CCF_THREADS)
+    hipLaunchKernelGGL((k_ccf<T, 2>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M, nv,
+                       c->mask_v0, c->mask_dv, c->mask_h, c->dln, d_part);
+  else
+    hipLaunchKernelGGL((k_ccf<T, 4>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M, nv,
+                       c->mask_v0, c->mask_dv, c->mask_h, c->dln, d_part);
+}
+
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
                       double* d_part, double* d_ccf) {
   const int nlb = ccf_line_blocks(n_lines);
   dim3 grid(nlb, (unsigned)((n_spec + CCF_SB - 1) / CCF_SB));
-  if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_ccf<float>, grid, dim3(CCF_THREADS), 0, c->stream, c->P, n_spec,
-                       (const float*)d_flux, n_lines, (const double2*)d_mask, c->mask_nv, c->mask_v0,
-                       c->mask_dv, c->mask_h, c->dln, d_part);
-  else
-    hipLaunchKernelGGL(k_ccf<double>, grid, dim3(CCF_THREADS), 0, c->stream, c->P, n_spec,
-                       (const double*)d_flux, n_lines, (const double2*)d_mask, c->mask_nv, c->mask_v0,
-                       c->mask_dv, c->mask_h, c->dln, d_part);
+  if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_mask, n_lines, d_part);
+  else launch_ccf_t<double>(c, grid, d_flux, n_spec, d_mask, n_lines, d_part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nt = n_spec * c->mask_nv;
@@ -357,8 +444,8 @@ hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const dou
 }
 
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask) {
-  hipLaunchKernelGGL(k_mask_prep, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->ln0, c->dln, d_lnl, d_w,
-                     (double2*)d_mask);
+  hipLaunchKernelGGL(k_mask_prep, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->ln0, c->dln,
+                     (double)c->P, d_lnl, d_w, (double2*)d_mask);
   return hipGetLastError();
 }
 

@@ -72,30 +72,16 @@ __global__ void k_contrast(int64_t P, int64_t Pstride, int B, double ln0, double
   }
 }
 
-// fill the pads of copy 0 of every row with the row's first / last sample
+// fill the pads of every row with the row's first / last sample
 template <typename T>
 __global__ void k_pad(int64_t P, int64_t Pstride, int rows, T* __restrict__ base) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int row = blockIdx.y;
   if (row >= rows || i >= Pstride) return;
-  T* r = base + (int64_t)row * NCOPY * Pstride;
+  T* r = base + (int64_t)row * Pstride;
   const int64_t m = i - PAD_FRONT;
   if (m < 0) r[i] = r[PAD_FRONT];
   else if (m >= P) r[i] = r[PAD_FRONT + P - 1];
-}
-
-// copies 1..3 of every row: copy d holds copy 0 shifted left by d samples
-template <typename T>
-__global__ void k_shift_copies(int64_t Pstride, int rows, T* __restrict__ base) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int row = blockIdx.y;
-  if (row >= rows || i >= Pstride) return;
-  const T* r0 = base + (int64_t)row * NCOPY * Pstride;
-#pragma unroll
-  for (int d = 1; d < NCOPY; ++d) {
-    const int64_t src = i + d < Pstride ? i + d : Pstride - 1;
-    base[((int64_t)row * NCOPY + d) * Pstride + i] = r0[src];
-  }
 }
 
 // one wave64 per disk column: W[i][b] = sum_{cells of column i in bin b} A I
@@ -200,7 +186,7 @@ __global__ void k_quiet(int64_t P, int64_t Pstride, int64_t Qlen, int B, int jmi
   }
   double acc = 0.0;
   for (int b = 0; b < B; ++b) {
-    const T* row = S + (int64_t)b * NCOPY * Pstride;
+    const T* row = S + (int64_t)b * Pstride;
     for (int jj = 0; jj < J; ++jj) {
       double k = Kq[b * J + jj];
       if (k != 0.0) {
@@ -246,12 +232,8 @@ hipError_t launch_pad(soap_ctx* c) {
     if (c->prec == SOAP_PREC_FP32) {
       hipLaunchKernelGGL(k_pad<float>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, c->B,
                          (float*)c->d_spec_base[t]);
-      hipLaunchKernelGGL(k_shift_copies<float>, grid, dim3(256), 0, c->stream, c->Pstride, c->B,
-                         (float*)c->d_spec_base[t]);
     } else {
       hipLaunchKernelGGL(k_pad<double>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, c->B,
-                         (double*)c->d_spec_base[t]);
-      hipLaunchKernelGGL(k_shift_copies<double>, grid, dim3(256), 0, c->stream, c->Pstride, c->B,
                          (double*)c->d_spec_base[t]);
     }
     hipError_t e = hipGetLastError();

@@ -131,7 +131,7 @@ void destroy_ctx(soap_ctx* c) {
   void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
-  soap::Workspace* ws[] = {&c->ws_Kp, &c->ws_slab, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_taps, &c->ws_flux,
+  soap::Workspace* ws[] = {&c->ws_Kp, &c->ws_slab, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_flux,
                            &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
   for (auto* w : ws) free_ws(*w);
   for (auto& p : c->pending) {
@@ -194,9 +194,9 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   hipMemcpyKind kind = d->spectra_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   for (int t = 0; t < 3; ++t) {
     if (!d->spectra[t]) continue;
-    HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B * soap::NCOPY));
+    HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B));
     c->d_spec[t] = static_cast<unsigned char*>(c->d_spec_base[t]) + soap::PAD_FRONT * c->esize;
-    HIP_TRY(hipMemcpy2DAsync(c->d_spec[t], row_bytes * soap::NCOPY, d->spectra[t], (size_t)c->P * c->esize,
+    HIP_TRY(hipMemcpy2DAsync(c->d_spec[t], row_bytes, d->spectra[t], (size_t)c->P * c->esize,
                              (size_t)c->P * c->esize, c->B, kind, c->stream));
     c->has_type[t] = true;
   }
@@ -387,9 +387,8 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   HIP_TRY(grow(c->ws_slab, sizeof(int) * (size_t)n_phases * pl.n_slabs));
   HIP_TRY(grow(c->ws_K, sizeof(double) * (size_t)n_phases * GJ));
   HIP_TRY(grow(c->ws_mask64, sizeof(unsigned long long) * (size_t)n_phases * pl.G));
-  HIP_TRY(grow(c->ws_vg, sizeof(soap::VGroup) * (size_t)pl.n_chunks * pl.vg_cap));
+  HIP_TRY(grow(c->ws_vg, (size_t)soap::WIN_BYTES * pl.n_chunks * pl.vg_cap));
   HIP_TRY(grow(c->ws_nvg, sizeof(int) * (size_t)pl.n_chunks));
-  HIP_TRY(grow(c->ws_taps, c->esize * (size_t)pl.n_chunks * pl.vg_cap * soap::APPLY_JW * soap::PC_MAX));
   const size_t out_bytes = (size_t)n_phases * c->P * c->esize;
   void* dflux = flux;
   if (!flux_on_device) {
@@ -423,27 +422,27 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   const soap::Region* d_reg = static_cast<const soap::Region*>(dev_view);
   const double* d_ph = reinterpret_cast<const double*>(static_cast<const unsigned char*>(dev_view) + reg_bytes);
 
-  double* dKp = static_cast<double*>(c->ws_Kp.ptr);
-  int* dslab = static_cast<int*>(c->ws_slab.ptr);
-  double* dK = static_cast<double*>(c->ws_K.ptr);
-  unsigned long long* dmask = static_cast<unsigned long long*>(c->ws_mask64.ptr);
+  soap::WeightsOut wo;
+  wo.Kp = static_cast<double*>(c->ws_Kp.ptr);
+  wo.slab = static_cast<int*>(c->ws_slab.ptr);
+  wo.K = static_cast<double*>(c->ws_K.ptr);
+  wo.mask = static_cast<unsigned long long*>(c->ws_mask64.ptr);
+  wo.wins = static_cast<unsigned char*>(c->ws_vg.ptr);
+  wo.nvg = static_cast<int*>(c->ws_nvg.ptr);
   {
     StageTimer t(c, ST_WEIGHTS);
-    HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, d_ph, dKp, dslab));
+    HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, d_ph, wo));
     t.done();
   }
   HIP_TRY(hipEventRecord(c->slot_done[k], c->stream));
   {
     StageTimer t(c, ST_COMPACT);
-    HIP_TRY(soap::launch_reduce_taps(c, pl, dKp, dslab, dK, dmask));
-    HIP_TRY(soap::launch_compact(c, pl, dK, dmask, static_cast<soap::VGroup*>(c->ws_vg.ptr),
-                                 static_cast<int*>(c->ws_nvg.ptr), c->ws_taps.ptr));
+    HIP_TRY(soap::launch_finish(c, pl, wo));
     t.done();
   }
   {
     StageTimer t(c, ST_APPLY);
-    HIP_TRY(soap::launch_apply(c, pl, static_cast<const soap::VGroup*>(c->ws_vg.ptr),
-                               static_cast<const int*>(c->ws_nvg.ptr), c->ws_taps.ptr, dflux));
+    HIP_TRY(soap::launch_apply(c, pl, c->ws_vg.ptr, static_cast<const int*>(c->ws_nvg.ptr), dflux));
     t.done();
   }
   c->active_calls++;
@@ -601,16 +600,16 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
     // distinct inputs the last apply walked, from its virtual-group lists
     const int n_chunks = (c->last_phases + c->pc - 1) / c->pc;
     std::vector<int> nvg(n_chunks);
-    std::vector<soap::VGroup> vg((size_t)n_chunks * c->last_vg_cap);
+    std::vector<unsigned char> vg((size_t)n_chunks * c->last_vg_cap * soap::WIN_BYTES);
     HIP_TRY(hipMemcpy(nvg.data(), c->ws_nvg.ptr, sizeof(int) * n_chunks, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(vg.data(), c->ws_vg.ptr, sizeof(soap::VGroup) * vg.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vg.data(), c->ws_vg.ptr, vg.size(), hipMemcpyDeviceToHost));
     std::vector<char> src(3 * c->B, 0), con(3 * c->B, 0);
     const bool planck = c->cmode == SOAP_CONTRAST_PLANCK;
     for (int ch = 0; ch < n_chunks; ++ch)
       for (int v = 0; v < nvg[ch]; ++v) {
-        const int g = vg[(size_t)ch * c->last_vg_cap + v].g;
-        const int t = c->last_paired ? g / c->B + 1 : g / c->B;
-        const int b = g % c->B;
+        soap::WinHead h;
+        std::memcpy(&h, vg.data() + ((size_t)ch * c->last_vg_cap + v) * soap::WIN_BYTES, sizeof(h));
+        const int t = h.t, b = h.b;
         if (t == 0) {
           src[b] = 1;
           continue;

@@ -37,15 +37,14 @@ constexpr int PC_F64 = 8;
 // Padded rows of the local spectra and contrast arrays: PAD_FRONT copies of
 // the first sample before it and copies of the last sample after it, so that
 // every window the apply kernel reads is in bounds and the end-value hold of
-// the interpolation comes for free.  Each local-spectrum row is stored four
-// times, copy d shifted left by d samples (row (4 b + d)), so that a window
-// starting at any pixel is an aligned 16-byte load from one of the copies.
+// the interpolation comes for free.
 constexpr int PAD_FRONT = 128;
-constexpr int NCOPY = 4;
 
 // Column slabs of the per-phase weight kernel.
 constexpr int SLAB_COLS = 32;
 constexpr int WEIGHT_WAVES = 8;
+constexpr int MAX_SLABS = (MAX_GRID + SLAB_COLS - 1) / SLAB_COLS;
+constexpr int FINISH_THREADS = 512;
 
 // region record as the kernels read it (device view of soap_region)
 struct Region {
@@ -54,17 +53,25 @@ struct Region {
   double lat_deg, lon_deg, radius, contrast;
 };
 
-// A window of APPLY_JW tap offsets [jlo, jlo + APPLY_JW) of one group in one
-// phase chunk.  Bit p of qmask[q]: phase p of the chunk has a non-zero tap at
-// offset jlo + q.  The taps themselves are stored densely per window as
-// taps[q][p] (PC_MAX values per q, zeros where the bit is clear).
+// A window record: APPLY_JW tap offsets [jlo, jlo + APPLY_JW) of one group
+// in one phase chunk, stored as a 16-byte header followed by the dense taps
+// taps[q][p] (q < APPLY_JW, p < the chunk's phase count; zeros where a phase
+// has no tap).  Bit (q * NG + k) of gmask: some phase of the k-th group of
+// four phases has a non-zero tap at offset jlo + q (NG = phases / 4).
 // Group g: paired tables g = (type - 1) * B + bin; split tables
 // g = type * B + bin with type 0 the quiet removal.
-struct VGroup {
-  int g;
+struct WinHead {
+  int t;    // surface type of the group (0 = quiet removal)
+  int b;    // mu bin of the group
   int jlo;
-  unsigned int qmask[APPLY_JW];
+  unsigned int gmask;
 };
+constexpr int WIN_TAP_BYTES = 512;  // APPLY_JW x 16 floats or APPLY_JW x 8 doubles
+constexpr int WIN_BYTES = 16 + WIN_TAP_BYTES;
+static_assert(APPLY_JW * PC_F32 * 4 == WIN_TAP_BYTES && APPLY_JW * PC_F64 * 8 == WIN_TAP_BYTES,
+              "window record size");
+// windows staged in LDS per pass of the apply kernel
+constexpr int APPLY_LDS_WIN = 48;
 
 struct Workspace {
   void* ptr = nullptr;
@@ -95,7 +102,7 @@ struct soap_ctx {
 
   // resident device state (row pointers point at pixel 0 of row 0)
   void* d_spec_base[3] = {nullptr, nullptr, nullptr};
-  void* d_spec[3] = {nullptr, nullptr, nullptr};  // [B][NCOPY][Pstride]
+  void* d_spec[3] = {nullptr, nullptr, nullptr};  // [B][Pstride]
   double* d_mu = nullptr;                          // [B]
   int* d_col_c = nullptr;                          // [N]
   double* d_col_w = nullptr;                       // [N]
@@ -111,9 +118,8 @@ struct soap_ctx {
   soap::Workspace ws_slab;     // [n_phases][n_slabs] slab non-empty flags
   soap::Workspace ws_K;        // [n_phases][G][J] double
   soap::Workspace ws_mask64;   // [n_phases][G] bitmask of nonzero offsets
-  soap::Workspace ws_vg;       // [n_chunks][vg_cap] VGroup
+  soap::Workspace ws_vg;       // [n_chunks][vg_cap] window records (WIN_BYTES each)
   soap::Workspace ws_nvg;      // [n_chunks] int
-  soap::Workspace ws_taps;     // [n_chunks][vg_cap][APPLY_JW][PC_MAX] taps (T)
   soap::Workspace ws_flux;     // host-output staging for fluxes
   soap::Workspace ws_ccf;      // partial CCFs
   soap::Workspace ws_ccfout;   // [n_spec][n_v] double
@@ -168,14 +174,19 @@ hipError_t launch_geom(soap_ctx* c);
 hipError_t launch_pad(soap_ctx* c);
 hipError_t launch_contrast(soap_ctx* c);
 hipError_t launch_quiet(soap_ctx* c);
+// outputs and scratch of the weight kernel
+struct WeightsOut {
+  double* Kp;                // [n_phases][n_slabs][G][J] slab partial taps
+  int* slab;                 // [n_phases][n_slabs] slab covered flags
+  double* K;                 // [n_phases][G][J] taps
+  unsigned long long* mask;  // [n_phases][G] non-zero offsets
+  unsigned char* wins;       // [n_chunks][vg_cap] window records
+  int* nvg;                  // [n_chunks] windows per chunk
+};
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
-                          double* d_Kp, int* d_slab);
-hipError_t launch_reduce_taps(soap_ctx* c, const Plan& pl, const double* d_Kp, const int* d_slab, double* d_K,
-                              unsigned long long* d_mask);
-hipError_t launch_compact(soap_ctx* c, const Plan& pl, const double* d_K, const unsigned long long* d_mask,
-                          VGroup* d_vg, int* d_nvg, void* d_taps);
-hipError_t launch_apply(soap_ctx* c, const Plan& pl, const VGroup* d_vg, const int* d_nvg, const void* d_taps,
-                        void* d_flux);
+                          const WeightsOut& o);
+hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o);
+hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
                       double* d_part, double* d_ccf);

@@ -23,12 +23,16 @@
 // contrasts other than one) keeps g = type * B + bin with type 0 the removal
 // (-A I) and the active rows scaled by the region contrast.
 //
-// k_reduce_taps sums the slab partials in slab order and records, per
-// (phase, group), the bitmask of non-zero offsets.  k_compact turns each
-// chunk of phases into windows of APPLY_JW offsets with dense taps and
-// per-offset phase masks.
+// k_finish, one block per chunk of phases, sums the slab partials in slab
+// order, records per (phase, group) the bitmask of non-zero offsets, and
+// turns the chunk into window records of APPLY_JW offsets with dense taps
+// and per-offset masks of the groups of four phases that have a tap.
 // Every sum has a fixed order, so results repeat bit for bit.
+#include <algorithm>
+#include <type_traits>
+
 #include "soap_internal.hpp"
+#include "wave.hpp"
 
 namespace soap {
 
@@ -41,52 +45,163 @@ __device__ __forceinline__ unsigned long long wor(unsigned long long v) {
 }
 
 constexpr int MAXC = 4;   // cells per lane per row pass (256 rows)
-constexpr int SLOTS = 16; // slots reduced together
-
-// Sum v[0..15] over the 64 lanes; lane l ends with the total of slot
-// (l >> 2) & 15.
-__device__ __forceinline__ double butterfly16(double (&v)[SLOTS], int lane) {
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    double send = b5 ? v[i] : v[i + 8];
-    double keep = b5 ? v[i + 8] : v[i];
-    v[i] = keep + __shfl_xor(send, 32, 64);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double send = b4 ? v[i] : v[i + 4];
-    double keep = b4 ? v[i + 4] : v[i];
-    v[i] = keep + __shfl_xor(send, 16, 64);
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    double send = b3 ? v[i] : v[i + 2];
-    double keep = b3 ? v[i + 2] : v[i];
-    v[i] = keep + __shfl_xor(send, 8, 64);
-  }
-  {
-    double send = b2 ? v[0] : v[1];
-    double keep = b2 ? v[1] : v[0];
-    v[0] = keep + __shfl_xor(send, 4, 64);
-  }
-  double s = v[0];
-  s += __shfl_xor(s, 2, 64);
-  s += __shfl_xor(s, 1, 64);
-  return s;
-}
+constexpr int SLOTS = 16; // slots reduced together (butterfly16)
 
 }  // namespace
 
+// Window records of one chunk of PC phases (one block): windows of APPLY_JW
+// offsets with their dense [offset][phase] taps and per-offset masks of the
+// groups of four phases that have a tap.  sm: LDS of at least
+// (4 G + vg_cap + 2) ints + G 64-bit words.
+template <typename T>
+__device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmin, int B, int paired,
+                              const double* __restrict__ K, const unsigned long long* __restrict__ mask,
+                              unsigned char* __restrict__ wins, int* __restrict__ nvg, int vg_cap, int* sm) {
+  int* s_cnt = sm;           // [G] windows per group
+  int* s_base = sm + G;      // [G] first window index
+  int* s_lo = sm + 2 * G;    // [G] first non-zero offset of the union
+  int* s_nv = sm + 3 * G;    // [1]
+  unsigned int* s_gm = reinterpret_cast<unsigned int*>(sm + 4 * G);  // [vg_cap] group masks
+  unsigned long long* s_union = reinterpret_cast<unsigned long long*>(sm + 4 * G + vg_cap + (vg_cap & 1));  // [G]
+  const int p0 = chunk * PC;
+  const int np = min(PC, n_ph - p0);
+  const int NG = PC / 4;
+  const int GJ = G * J;
+  const int nwin = (J + APPLY_JW - 1) / APPLY_JW;
+  unsigned char* wrec = wins + (int64_t)chunk * vg_cap * WIN_BYTES;
+
+  for (int g = threadIdx.x; g < G; g += blockDim.x) {
+    unsigned long long u = 0;
+#pragma unroll
+    for (int p = 0; p < PC_MAX; ++p)
+      if (p < np) u |= mask[(int64_t)(p0 + p) * G + g];
+    int cnt = 0, lo = 0;
+    if (u) {
+      lo = __builtin_ctzll(u);
+      for (int a = lo; a < J; a += APPLY_JW)
+        if ((u >> a) & ((1ull << APPLY_JW) - 1)) ++cnt;
+    }
+    s_cnt[g] = cnt;
+    s_lo[g] = lo;
+    s_union[g] = u;
+  }
+  for (int v = threadIdx.x; v < vg_cap; v += blockDim.x) s_gm[v] = 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int g = 0; g < G; ++g) {
+      s_base[g] = acc;
+      acc += s_cnt[g];
+    }
+    nvg[chunk] = acc;
+    *s_nv = acc;
+  }
+  __syncthreads();
+  // one thread per (group, window slot, offset)
+  for (int t = threadIdx.x; t < G * nwin * APPLY_JW; t += blockDim.x) {
+    const int g = t / (nwin * APPLY_JW);
+    const int rem = t - g * nwin * APPLY_JW;
+    const int wslot = rem / APPLY_JW;
+    const int q = rem - wslot * APPLY_JW;
+    if (!s_cnt[g]) continue;
+    const unsigned long long u = s_union[g];
+    const int a = s_lo[g] + wslot * APPLY_JW;
+    if (a >= J || !((u >> a) & ((1ull << APPLY_JW) - 1))) continue;
+    int v = s_base[g];
+    for (int b = s_lo[g]; b < a; b += APPLY_JW)
+      if ((u >> b) & ((1ull << APPLY_JW) - 1)) ++v;
+    unsigned char* rec = wrec + (int64_t)v * WIN_BYTES;
+    if (q == 0) {
+      WinHead h;
+      h.t = paired ? g / B + 1 : g / B;
+      h.b = g % B;
+      h.jlo = jmin + a;
+      h.gmask = 0u;
+      *reinterpret_cast<WinHead*>(rec) = h;
+    }
+    T* row = reinterpret_cast<T*>(rec + 16) + q * PC;
+    double kv[PC_MAX];
+#pragma unroll
+    for (int p = 0; p < PC_MAX; ++p)
+      kv[p] = (p < np && a + q < J) ? K[(int64_t)(p0 + p) * GJ + g * J + a + q] : 0.0;
+    unsigned int m = 0;
+#pragma unroll
+    for (int p = 0; p < PC_MAX; ++p) {
+      if (p < PC) {
+        row[p] = (T)kv[p];
+        if (kv[p] != 0.0) m |= 1u << ((q * NG) + (p >> 2));
+      }
+    }
+    if (m) atomicOr(&s_gm[v], m);
+  }
+  __syncthreads();
+  const int nv = *s_nv;
+  for (int v = threadIdx.x; v < nv; v += blockDim.x)
+    reinterpret_cast<WinHead*>(wrec + (int64_t)v * WIN_BYTES)->gmask = s_gm[v];
+}
+
+// One block per chunk of PC phases: the phases' taps K[ph][g][j] = sum of
+// the covered slab partials in slab order, the per-(phase, group) bitmask
+// of non-zero offsets, then the chunk's window records.
+template <typename T>
+__global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int G, int J, int jmin, int B,
+                                                           int paired, int n_slabs, int vg_cap,
+                                                           const double* __restrict__ Kp,
+                                                           const int* __restrict__ slab_flag, double* __restrict__ K,
+                                                           unsigned long long* __restrict__ mask,
+                                                           unsigned char* __restrict__ wins, int* __restrict__ nvg) {
+  extern __shared__ int sm[];
+  __shared__ int s_flag[PC_MAX * MAX_SLABS];
+  const int chunk = blockIdx.x;
+  const int p0 = chunk * PC;
+  const int np = min(PC, n_ph - p0);
+  const int GJ = G * J;
+  for (int t = threadIdx.x; t < np * n_slabs; t += blockDim.x) s_flag[t] = slab_flag[p0 * n_slabs + t];
+  __syncthreads();
+  // every (phase, table entry) of the chunk: its slab partials are loaded
+  // together, then added in slab order
+  for (int t = threadIdx.x; t < np * GJ; t += blockDim.x) {
+    const int p = t / GJ;
+    const int e = t - p * GJ;
+    const double* src = Kp + (int64_t)(p0 + p) * n_slabs * GJ + e;
+    const int* fl = s_flag + p * n_slabs;
+    double s = 0.0;
+    for (int sl0 = 0; sl0 < n_slabs; sl0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int sl = sl0 + u;
+        v[u] = (sl < n_slabs && fl[sl]) ? src[(int64_t)sl * GJ] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (sl0 + u < n_slabs && fl[sl0 + u]) s += v[u];
+    }
+    K[(int64_t)(p0 + p) * GJ + e] = s;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < np * G; t += blockDim.x) {
+    const int p = t / G;
+    const int g = t - p * G;
+    const double* kr = K + (int64_t)(p0 + p) * GJ + g * J;
+    unsigned long long mk = 0;
+    for (int j = 0; j < J; ++j)
+      if (kr[j] != 0.0) mk |= 1ull << j;
+    mask[(int64_t)(p0 + p) * G + g] = mk;
+  }
+  __syncthreads();
+  compact_chunk<T>(chunk, n_ph, PC, G, J, jmin, B, paired, K, mask, wins, nvg, vg_cap, sm);
+}
+
 template <bool KAHAN32>
 __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
-    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, double incl, int effect,
-    int cmode, const double* __restrict__ mu_b, const int* __restrict__ col_c, const double* __restrict__ col_w,
-    const Region* __restrict__ reg, int n_reg, const double* __restrict__ phases, double* __restrict__ Kp,
-    int* __restrict__ slab_flag) {
+    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, double incl, int effect, int cmode, const double* __restrict__ mu_b, const int* __restrict__ col_c,
+    const double* __restrict__ col_w, const Region* __restrict__ reg, int n_reg, const double* __restrict__ phases,
+    double* __restrict__ Kp, int* __restrict__ slab_flag) {
   extern __shared__ double lds[];  // [nw][G*J] tables, then [nw][192] slot codes
   __shared__ double rcx[MAX_REGIONS], rcy[MAX_REGIONS], rcz[MAX_REGIONS], rcos[MAX_REGIONS],
       rscal[MAX_REGIONS];
+  __shared__ double s_mub[MAX_MU];
   __shared__ int rtype[MAX_REGIONS];
   __shared__ int box[4];
 
@@ -99,6 +214,7 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
   const double phase = phases[ph];
   const double area = (2.0 / N) * (2.0 / N);
 
+  for (int b = threadIdx.x; b < B; b += blockDim.x) s_mub[b] = mu_b[b];
   if (threadIdx.x < n_reg) {
     const Region r = reg[threadIdx.x];
     double cx, cy, cz;
@@ -142,8 +258,7 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
   }
   __syncthreads();
   const int i0 = box[0], i1 = box[1], k0 = box[2], k1 = box[3];
-  if (i0 > i1 || k0 > k1) return;  // uniform: nothing of this slab is covered
-
+  if (i0 <= i1 && k0 <= k1) {  // uniform: some of this slab is covered
   for (int t = threadIdx.x; t < nw * GJ; t += blockDim.x) lds[t] = 0.0;
   __syncthreads();
   double* myK = lds + wave * GJ;
@@ -184,7 +299,7 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
               if (dot >= rcos[r]) own = r;
             }
             if (own >= 0) {
-              const int b = nearest_bin(mu, mu_b, B);
+              const int b = nearest_bin(mu, s_mub, B);
               const int t = rtype[own];
               cb[q] = b | (t << 8);
               cw[q] = area * limb_dark(mu, u1, u2);
@@ -261,102 +376,11 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
     for (int w = 0; w < nw; ++w) s += lds[w * GJ + t];
     out[t] = s;
   }
-}
-
-// K[ph][g][j] = sum over non-empty slabs (slab order); mask of non-zero j
-__global__ void k_reduce_taps(int n_ph, int G, int J, int n_slabs, const double* __restrict__ Kp,
-                              const int* __restrict__ slab_flag, double* __restrict__ K,
-                              unsigned long long* __restrict__ mask) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_ph * G) return;
-  const int ph = t / G, g = t - ph * G;
-  const int GJ = G * J;
-  unsigned long long mk = 0;
-  for (int j = 0; j < J; ++j) {
-    double s = 0.0;
-    for (int sl = 0; sl < n_slabs; ++sl)
-      if (slab_flag[ph * n_slabs + sl]) s += Kp[((int64_t)ph * n_slabs + sl) * GJ + g * J + j];
-    K[(int64_t)ph * GJ + g * J + j] = s;
-    if (s != 0.0) mk |= 1ull << j;
-  }
-  mask[(int64_t)ph * G + g] = mk;
-}
-
-// one block per chunk of PC phases: windows of APPLY_JW offsets with their
-// dense [offset][phase] taps and per-offset phase masks
-template <typename T>
-__global__ void __launch_bounds__(256) k_compact(int n_ph, int PC, int G, int J, int jmin,
-                                                 const double* __restrict__ K,
-                                                 const unsigned long long* __restrict__ mask,
-                                                 VGroup* __restrict__ vgs, int* __restrict__ nvg,
-                                                 T* __restrict__ taps, int vg_cap) {
-  extern __shared__ int sm[];
-  int* s_cnt = sm;           // [G] windows per group
-  int* s_base = sm + G;      // [G] first window index
-  int* s_lo = sm + 2 * G;    // [G] first non-zero offset of the union
-  unsigned long long* s_union = reinterpret_cast<unsigned long long*>(sm + 4 * G);  // [G]
-  const int chunk = blockIdx.x;
-  const int p0 = chunk * PC;
-  const int np = min(PC, n_ph - p0);
-  const int GJ = G * J;
-  const int nwin = (J + APPLY_JW - 1) / APPLY_JW;
-  VGroup* vg = vgs + (int64_t)chunk * vg_cap;
-  T* tp = taps + (int64_t)chunk * vg_cap * APPLY_JW * PC_MAX;
-
-  for (int g = threadIdx.x; g < G; g += blockDim.x) {
-    unsigned long long u = 0;
-    for (int p = 0; p < np; ++p) u |= mask[(int64_t)(p0 + p) * G + g];
-    int cnt = 0, lo = 0;
-    if (u) {
-      lo = __builtin_ctzll(u);
-      for (int a = lo; a < J; a += APPLY_JW)
-        if ((u >> a) & ((1ull << APPLY_JW) - 1)) ++cnt;
-    }
-    s_cnt[g] = cnt;
-    s_lo[g] = lo;
-    s_union[g] = u;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int g = 0; g < G; ++g) {
-      s_base[g] = acc;
-      acc += s_cnt[g];
-    }
-    nvg[chunk] = acc;
-  }
-  __syncthreads();
-  // one thread per (group, window slot, offset)
-  for (int t = threadIdx.x; t < G * nwin * APPLY_JW; t += blockDim.x) {
-    const int g = t / (nwin * APPLY_JW);
-    const int rem = t - g * nwin * APPLY_JW;
-    const int wslot = rem / APPLY_JW;
-    const int q = rem - wslot * APPLY_JW;
-    if (!s_cnt[g]) continue;
-    const unsigned long long u = s_union[g];
-    const int a = s_lo[g] + wslot * APPLY_JW;
-    if (a >= J || !((u >> a) & ((1ull << APPLY_JW) - 1))) continue;
-    int v = s_base[g];
-    for (int b = s_lo[g]; b < a; b += APPLY_JW)
-      if ((u >> b) & ((1ull << APPLY_JW) - 1)) ++v;
-    if (q == 0) {
-      vg[v].g = g;
-      vg[v].jlo = jmin + a;
-    }
-    unsigned int m = 0;
-    T* row = tp + ((int64_t)v * APPLY_JW + q) * PC_MAX;
-    for (int p = 0; p < PC_MAX; ++p) {
-      double k = 0.0;
-      if (p < np && a + q < J) k = K[(int64_t)(p0 + p) * GJ + g * J + a + q];
-      row[p] = (T)k;
-      if (k != 0.0) m |= 1u << p;
-    }
-    vg[v].qmask[q] = m;
-  }
+  }  // covered slab
 }
 
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
-                          double* d_Kp, int* d_slab) {
+                          const WeightsOut& o) {
   const size_t per_wave = (size_t)pl.G * c->J * sizeof(double) + 192 * sizeof(int);
   // dynamic LDS stays below 60 KB so that with the static arrays the block
   // fits a 64 KB workgroup allocation
@@ -367,31 +391,25 @@ hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int 
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * nw), lds, c->stream, c->N, c->B, c->J, c->jmin, pl.G,
                        pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu, c->d_col_c,
-                       c->d_col_w, d_reg, n_reg, d_ph, d_Kp, d_slab);
+                       c->d_col_w, d_reg, n_reg, d_ph, o.Kp, o.slab);
   else
     hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * nw), lds, c->stream, c->N, c->B, c->J, c->jmin, pl.G,
                        pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu, c->d_col_c,
-                       c->d_col_w, d_reg, n_reg, d_ph, d_Kp, d_slab);
+                       c->d_col_w, d_reg, n_reg, d_ph, o.Kp, o.slab);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_taps(soap_ctx* c, const Plan& pl, const double* d_Kp, const int* d_slab, double* d_K,
-                              unsigned long long* d_mask) {
-  const int nt = pl.n_ph * pl.G;
-  hipLaunchKernelGGL(k_reduce_taps, dim3((nt + 127) / 128), dim3(128), 0, c->stream, pl.n_ph, pl.G, c->J,
-                     pl.n_slabs, d_Kp, d_slab, d_K, d_mask);
-  return hipGetLastError();
-}
-
-hipError_t launch_compact(soap_ctx* c, const Plan& pl, const double* d_K, const unsigned long long* d_mask,
-                          VGroup* d_vg, int* d_nvg, void* d_taps) {
-  const size_t lds = (size_t)4 * pl.G * sizeof(int) + (size_t)pl.G * sizeof(unsigned long long);
+hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o) {
+  if (pl.n_slabs > MAX_SLABS) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(6 * pl.G + pl.vg_cap + 2) * sizeof(int);
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_compact<float>, dim3(pl.n_chunks), dim3(256), lds, c->stream, pl.n_ph, c->pc, pl.G, c->J,
-                       c->jmin, d_K, d_mask, d_vg, d_nvg, (float*)d_taps, pl.vg_cap);
+    hipLaunchKernelGGL(k_finish<float>, dim3(pl.n_chunks), dim3(FINISH_THREADS), lds, c->stream, pl.n_ph, c->pc,
+                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.n_slabs, pl.vg_cap, o.Kp, o.slab, o.K, o.mask,
+                       o.wins, o.nvg);
   else
-    hipLaunchKernelGGL(k_compact<double>, dim3(pl.n_chunks), dim3(256), lds, c->stream, pl.n_ph, c->pc, pl.G,
-                       c->J, c->jmin, d_K, d_mask, d_vg, d_nvg, (double*)d_taps, pl.vg_cap);
+    hipLaunchKernelGGL(k_finish<double>, dim3(pl.n_chunks), dim3(FINISH_THREADS), lds, c->stream, pl.n_ph, c->pc,
+                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.n_slabs, pl.vg_cap, o.Kp, o.slab, o.K, o.mask,
+                       o.wins, o.nvg);
   return hipGetLastError();
 }
 
