@@ -102,6 +102,7 @@ def main():
 
     import paper_2301_04259_amd as L
     import workloads as W
+    from paper_2301_04259_amd import prof_summary
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -173,6 +174,11 @@ def main():
     apply_bytes = n_arrays * P * 4 + P * 8 + n_ph * P * 4
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
 
+    # HBM bytes per launch from the committed counter summary, valid only
+    # while the kernel's sources are the ones the counters were taken on
+    tr = prof_summary.read_traffic(os.path.join(ROOT, "profiles", "k_apply_full_visible_r115000_traffic.txt"))
+    traffic = tr[0] if tr is not None and tr[1] == prof_summary.sources_sha256() else None
+
     rvh = np.frombuffer(rv.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
     assert np.all(np.isfinite(rvh["rv_kms"])) and torch.isfinite(flux).all()
 
@@ -210,7 +216,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "k_apply",
             "kernel_ms": apply_ms,
             "algorithmic_bytes": apply_bytes,
