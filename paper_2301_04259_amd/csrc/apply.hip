@@ -97,66 +97,50 @@ template <typename T>
 struct ApplyArgs {
   int64_t P, Pstride;
   int B, n_ph, n_chunks, n_tiles, effect, paired, vg_cap, vec_ok, lds_win;
-  const T *Sq, *Ss, *Sf, *Cs, *Cf;
+  const T *Sq, *Ss, *Sf, *Cs, *Cf, *ones;
   const double* Q;
   const unsigned char* wins;
   const int* nvg;
   T* out;
 };
 
-// wave-uniform header of window v in LDS
-struct Head {
-  int t, b, jlo;
-  unsigned gm;
-};
-
-__device__ __forceinline__ Head read_head(const unsigned char* s_win, int v) {
-  const int4 h = *reinterpret_cast<const int4*>(s_win + v * WIN_BYTES);
-  Head r;
-  r.t = __builtin_amdgcn_readfirstlane(h.x);
-  r.b = __builtin_amdgcn_readfirstlane(h.y);
-  r.jlo = __builtin_amdgcn_readfirstlane(h.z);
-  r.gm = (unsigned)__builtin_amdgcn_readfirstlane(h.w);
-  return r;
+// header of window v in LDS (type, bin, first offset, group mask)
+__device__ __forceinline__ int4 head_raw(const unsigned char* s_win, int v) {
+  return *reinterpret_cast<const int4*>(s_win + v * WIN_BYTES);
 }
 
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Every fetch issues the same loads (a, b for paired tables, c), so that the
+// compiler can count outstanding loads exactly and the next window's loads
+// stay in flight while the current window is consumed.  Without a contrast
+// the c operand comes from a resident row of ones; for the flux effect the
+// active operand is the quiet row itself, loaded a second time.
 template <typename T, int R, int JW, bool PAIRED>
-__device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, const Head& h, int64_t m0) {
-  const int t = h.t, b = h.b;
+__device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int4 hr, int64_t m0) {
+  const int t = uni(hr.x), b = uni(hr.y), jlo = uni(hr.z);
   const int64_t rs = A.Pstride;  // stride between mu-bin rows
   const T* sq = A.Sq + (int64_t)b * rs;
   const T* src;
-  const T* con = nullptr;
-  const T* sub = nullptr;
+  const T* con = A.ones;
   if (t == 0) {
     src = sq;
   } else {
-    const T* ct = nullptr;
+    const T* ct = A.ones;
     if (A.Cs) ct = (t == SOAP_SPOT) ? A.Cs : A.Cf + (int64_t)b * A.Pstride;
     if (A.effect == SOAP_EFFECT_FLUX) {
       src = sq;
       con = ct;
     } else {
       src = (t == SOAP_SPOT ? A.Ss : A.Sf) + (int64_t)b * rs;
-      con = (A.effect == SOAP_EFFECT_TOT) ? ct : nullptr;
+      if (A.effect == SOAP_EFFECT_TOT) con = ct;
     }
-    if (PAIRED) sub = sq;
   }
   // window start m0 - jlo - (JW - 1)
-  const int64_t at = m0 - h.jlo - (JW - 1);
+  const int64_t at = m0 - jlo - (JW - 1);
   load12(o.a, src + at);
-  if (PAIRED) {
-    // every paired window has an active type; the flux effect shifts the
-    // quiet spectrum itself, so its difference is (C - 1) S_q
-    if (sub != src) load12(o.b, sub + at);
-    else o.b = o.a;
-  }
-  if (con) {
-    load4(o.c, con + m0);
-  } else {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o.c[r] = T(1);
-  }
+  if (PAIRED) load12(o.b, sq + at);
+  load4(o.c, con + m0);
 }
 
 // taps of four consecutive phases at one offset, from LDS (all lanes read
@@ -179,9 +163,9 @@ __device__ __forceinline__ void load_taps4(T (&k)[4], const T* p) {
   }
 }
 
-// One window: for every offset q with any tap in the chunk, form the
-// difference row, read the taps of the groups of four phases active there
-// and add k * D with fused multiply-adds.
+// One window: for every offset q with any tap in the chunk, read the taps of
+// all phases of that offset from LDS, form the difference row, and let each
+// active group of four phases add k * D with fused multiply-adds.
 template <typename T, int R, int PC, int JW, bool PAIRED>
 __device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, unsigned gm, const T* tw) {
   constexpr int NG = PC / 4;
@@ -192,8 +176,7 @@ __device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, u
     if (nib == 0u) continue;
     T k[NG][4];
 #pragma unroll
-    for (int gi = 0; gi < NG; ++gi)
-      if ((nib >> gi) & 1u) load_taps4(k[gi], tw + q * PC + 4 * gi);
+    for (int gi = 0; gi < NG; ++gi) load_taps4(k[gi], tw + q * PC + 4 * gi);
     T D[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -215,7 +198,7 @@ __device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, u
 }  // namespace
 
 template <typename T, int R, int PC, int JW, bool PAIRED>
-__global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs<T> A) {
+__global__ void __launch_bounds__(APPLY_THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(ApplyArgs<T> A) {
   static_assert(R == 4 && JW == 8, "window loads are written for 4 pixels x 8 offsets");
   static_assert(PC % 4 == 0 && JW * PC * sizeof(T) == WIN_TAP_BYTES, "record layout");
   extern __shared__ __align__(16) unsigned char s_win[];  // [lds_win][WIN_BYTES]
@@ -246,22 +229,28 @@ __global__ void __launch_bounds__(APPLY_THREADS) k_apply(ApplyArgs<T> A) {
       for (int u = threadIdx.x; u < n16; u += APPLY_THREADS) dst[u] = src[u];
     }
     __syncthreads();
+    // Two windows in flight: the loads of the next window are issued before
+    // the current one is consumed.  Fetches are unconditional (past the end
+    // they repeat the last window and are not consumed), so the compiler
+    // can count outstanding loads exactly; headers are read one window
+    // ahead of their fetch.
+    const int last = nb - 1;
     Operands<T> o0, o1;
-    Head h0 = read_head(s_win, 0), h1;
+    int4 h0 = head_raw(s_win, 0);
+    int4 h1 = head_raw(s_win, min(1, last));
     fetch<T, R, JW, PAIRED>(o0, A, h0, m0);
     for (int v = 0; v < nb; v += 2) {
-      if (v + 1 < nb) {
-        h1 = read_head(s_win, v + 1);
-        fetch<T, R, JW, PAIRED>(o1, A, h1, m0);
-      }
-      consume<T, R, PC, JW, PAIRED>(acc, o0, h0.gm, reinterpret_cast<const T*>(s_win + v * WIN_BYTES + 16));
-      if (v + 1 < nb) {
-        if (v + 2 < nb) {
-          h0 = read_head(s_win, v + 2);
-          fetch<T, R, JW, PAIRED>(o0, A, h0, m0);
-        }
-        consume<T, R, PC, JW, PAIRED>(acc, o1, h1.gm, reinterpret_cast<const T*>(s_win + (v + 1) * WIN_BYTES + 16));
-      }
+      fetch<T, R, JW, PAIRED>(o1, A, h1, m0);
+      const int4 h2 = head_raw(s_win, min(v + 2, last));
+      consume<T, R, PC, JW, PAIRED>(acc, o0, (unsigned)uni(h0.w),
+                                    reinterpret_cast<const T*>(s_win + v * WIN_BYTES + 16));
+      fetch<T, R, JW, PAIRED>(o0, A, h2, m0);
+      const int4 h3 = head_raw(s_win, min(v + 3, last));
+      if (v + 1 < nb)
+        consume<T, R, PC, JW, PAIRED>(acc, o1, (unsigned)uni(h1.w),
+                                      reinterpret_cast<const T*>(s_win + (v + 1) * WIN_BYTES + 16));
+      h0 = h2;
+      h1 = h3;
     }
   }
 
@@ -305,7 +294,7 @@ hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const in
     ApplyArgs<float> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, c->n_tiles, pl.effect, pl.paired, pl.vg_cap,
                        vec_ok ? 1 : 0, lds_win,
                        (const float*)c->d_spec[0], (const float*)c->d_spec[1], (const float*)c->d_spec[2],
-                       (const float*)c->d_con_spot, (const float*)c->d_con_fac, c->d_Q, w, d_nvg,
+                       (const float*)c->d_con_spot, (const float*)c->d_con_fac, (const float*)c->d_ones, c->d_Q, w, d_nvg,
                        (float*)d_flux};
     if (pl.paired)
       hipLaunchKernelGGL((k_apply<float, APPLY_R, PC_F32, APPLY_JW, true>), grid, dim3(APPLY_THREADS), lds,
@@ -317,7 +306,7 @@ hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const in
     ApplyArgs<double> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, c->n_tiles, pl.effect, pl.paired,
                         pl.vg_cap, vec_ok ? 1 : 0, lds_win,
                         (const double*)c->d_spec[0], (const double*)c->d_spec[1], (const double*)c->d_spec[2],
-                        (const double*)c->d_con_spot, (const double*)c->d_con_fac, c->d_Q, w, d_nvg,
+                        (const double*)c->d_con_spot, (const double*)c->d_con_fac, (const double*)c->d_ones, c->d_Q, w, d_nvg,
                         (double*)d_flux};
     if (pl.paired)
       hipLaunchKernelGGL((k_apply<double, APPLY_R, PC_F64, APPLY_JW, true>), grid, dim3(APPLY_THREADS), lds,

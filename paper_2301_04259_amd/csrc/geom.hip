@@ -72,6 +72,12 @@ __global__ void k_contrast(int64_t P, int64_t Pstride, int B, double ln0, double
   }
 }
 
+template <typename T>
+__global__ void k_fill_one(int64_t n, T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = T(1);
+}
+
 // fill the pads of every row with the row's first / last sample
 template <typename T>
 __global__ void k_pad(int64_t P, int64_t Pstride, int rows, T* __restrict__ base) {
@@ -222,6 +228,16 @@ hipError_t launch_contrast(soap_ctx* c) {
     hipLaunchKernelGGL(k_contrast<double>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, c->B, c->ln0, c->dln,
                        c->teff, c->dt_spot, c->dt_fac[0], c->dt_fac[1], c->dt_fac[2], c->d_mu,
                        (double*)c->d_con_spot - PAD_FRONT, (double*)c->d_con_fac - PAD_FRONT);
+  return hipGetLastError();
+}
+
+hipError_t launch_ones(soap_ctx* c) {
+  const int64_t n = (int64_t)c->n_tiles * APPLY_TILE;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (c->prec == SOAP_PREC_FP32)
+    hipLaunchKernelGGL(k_fill_one<float>, grid, dim3(256), 0, c->stream, n, (float*)c->d_ones);
+  else
+    hipLaunchKernelGGL(k_fill_one<double>, grid, dim3(256), 0, c->stream, n, (double*)c->d_ones);
   return hipGetLastError();
 }
 

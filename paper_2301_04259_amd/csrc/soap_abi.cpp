@@ -128,7 +128,7 @@ void destroy_ctx(soap_ctx* c) {
   if (c->hip_used) (void)hipStreamSynchronize(c->stream);
   for (int t = 0; t < 3; ++t)
     if (c->d_spec_base[t]) (void)hipFree(c->d_spec_base[t]);
-  void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base};
+  void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base, c->d_ones};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   soap::Workspace* ws[] = {&c->ws_Kp, &c->ws_slab, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_flux,
@@ -207,6 +207,7 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   HIP_TRY(hipMalloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
   HIP_TRY(hipMalloc((void**)&c->d_Kq, sizeof(double) * c->B * c->J));
   HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE));
+  HIP_TRY(hipMalloc(&c->d_ones, c->esize * c->n_tiles * soap::APPLY_TILE));
   if (c->cmode == SOAP_CONTRAST_PLANCK) {
     HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * (c->B + 1)));
     c->d_con_spot = static_cast<unsigned char*>(c->d_con_base) + soap::PAD_FRONT * c->esize;
@@ -217,6 +218,7 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
 
   HIP_TRY(soap::launch_pad(c));
   HIP_TRY(soap::launch_geom(c));
+  HIP_TRY(soap::launch_ones(c));
   if (c->cmode == SOAP_CONTRAST_PLANCK) HIP_TRY(soap::launch_contrast(c));
   HIP_TRY(soap::launch_quiet(c));
   // host arrays (mu bins, spectra) may be released once the call returns

@@ -112,6 +112,7 @@ struct soap_ctx {
   void* d_con_base = nullptr;
   void* d_con_spot = nullptr;                      // [Pstride] (PLANCK)
   void* d_con_fac = nullptr;                       // [B][Pstride] (PLANCK)
+  void* d_ones = nullptr;                          // [n_tiles * TILE] of 1 (no-contrast operand)
 
   // per-call workspace (grown on demand, freed by soap_destroy)
   soap::Workspace ws_Kp;       // [n_phases][n_slabs][G][J] slab partial taps
@@ -173,6 +174,7 @@ struct Plan {
 hipError_t launch_geom(soap_ctx* c);
 hipError_t launch_pad(soap_ctx* c);
 hipError_t launch_contrast(soap_ctx* c);
+hipError_t launch_ones(soap_ctx* c);
 hipError_t launch_quiet(soap_ctx* c);
 // outputs and scratch of the weight kernel
 struct WeightsOut {
