@@ -198,8 +198,8 @@ typedef struct {
   double weights_ms;         /* region weights + InfoMap + column sums      */
   double compact_ms;         /* slab sums and tap lists                     */
   double apply_ms;           /* shift-and-sum of the final spectra          */
-  double ccf_ms;             /* CCF (incl. the fixed-order reduction)       */
-  double gfit_ms;            /* Gaussian fits                               */
+  double ccf_ms;             /* CCF partial sums per block of mask lines    */
+  double gfit_ms;            /* fixed-order sum of the partials + fits      */
   int64_t active_calls;
   int64_t ccf_calls;
   int64_t src_arrays;        /* last apply: distinct local spectra read     */

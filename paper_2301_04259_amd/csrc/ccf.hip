@@ -9,7 +9,7 @@
 // Layout: one block per (block of lines, block of SB spectra), one thread per
 // velocity; each thread keeps SB double accumulators and reuses its hole
 // geometry for every spectrum of the block.  Partial sums per line block are
-// added in a fixed order by a second kernel, so results repeat bit for bit.
+// added in a fixed order by the fit kernel, so results repeat bit for bit.
 //
 // Fit: one wave64 per CCF; damped Newton (Levenberg-Marquardt damping) in
 // double on the unweighted least squares of c0 - a exp(-(v - mu)^2 /
@@ -171,19 +171,12 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
   }
 }
 
-__global__ void k_ccf_reduce(int n_lb, int64_t n_spec, int n_v, const double* __restrict__ part,
-                             double* __restrict__ ccf) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_spec * n_v) return;
-  double s = 0.0;
-  for (int lb = 0; lb < n_lb; ++lb) s += part[(int64_t)lb * n_spec * n_v + t];
-  ccf[t] = s;
-}
 
 namespace {
 
 constexpr double FWHM_PER_SIGMA = 2.3548200450309493;  // 2 sqrt(2 ln 2)
 constexpr int GF_MAXPT = 12;                            // points per lane (n_v <= 768)
+constexpr int CCF_FIN_THREADS = 256;
 
 // Sums of the fit at p, identical in every lane: S[0] = chi^2,
 // S[1..4] = g = J^T r, S[5..14] = J^T J (upper triangle, row by row),
@@ -289,29 +282,71 @@ __device__ bool gf_solve(const double S[20], bool newton, double lam, double x[4
 
 }  // namespace
 
-// Damped Newton / Levenberg-Marquardt: the step solves
+// One block of four waves per spectrum.  The waves first add the line
+// blocks' partial CCFs (wave w takes the line blocks lb = w mod 4, in
+// order; the four partial sums are then added in wave order, so the result
+// repeats bit for bit) and write the CCF.  With fit set, wave 0 then fits
+// the Gaussian.
+//
+// Fit: damped Newton / Levenberg-Marquardt.  The step solves
 // (H + lam diag(J^T J)) x = -J^T r with H the full Hessian of chi^2 / 2
 // (J^T J plus the residual-weighted second derivatives; the CCF is not an
 // exact Gaussian, so the residuals stay finite and Gauss-Newton alone
 // converges only linearly) and falls back to H = J^T J where the full one
 // is not positive definite.  A trial step is evaluated with all its sums,
 // so an accepted step costs one pass over the CCF.  The fit has converged
-// when an accepted step moves every parameter by at most 1e-10 of its scale
-// (sigma for the centre and width), or when it no longer lowers chi^2 and
-// moves the centre and width by at most 1e-9 sigma (the rounding floor); a
-// run of rejected steps that drives the damping past 1e10 means no downhill
-// step exists at this precision, which is also the minimum.
-__global__ void __launch_bounds__(64) k_gfit(int64_t n_spec, int n_v, double v0, double dv,
-                                             const double* __restrict__ ccf, soap_rv* __restrict__ out) {
+// when a step, accepted or not, moves every parameter by at most 1e-10 of
+// its scale (sigma for the centre and width; at that size a rejection only
+// reflects rounding of chi^2), or when an accepted step no longer lowers
+// chi^2 and moves the centre and width by at most 1e-9 sigma; a run of
+// rejected steps that drives the damping past 1e10 means no downhill step
+// exists at this precision, which is also the minimum.
+__global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n_spec, int n_v, double v0,
+                                                             double dv, const double* __restrict__ part,
+                                                             double* __restrict__ ccf, int fit,
+                                                             soap_rv* __restrict__ out) {
+  __shared__ double s_sum[CCF_FIN_THREADS / 64][GF_MAXPT * 64];
   const int64_t s = blockIdx.x;
-  const int lane = threadIdx.x;
-  const double* yg = ccf + s * n_v;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  constexpr int NW = CCF_FIN_THREADS / 64;
+  {
+    double acc[GF_MAXPT];
+#pragma unroll
+    for (int t = 0; t < GF_MAXPT; ++t) acc[t] = 0.0;
+    for (int lb0 = wave; lb0 < n_lb; lb0 += 4 * NW) {
+      double v[4][GF_MAXPT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int lb = lb0 + u * NW;
+        const double* src = part + ((int64_t)lb * n_spec + s) * n_v;
+#pragma unroll
+        for (int t = 0; t < GF_MAXPT; ++t) {
+          const int i = lane + 64 * t;
+          v[u][t] = (lb < n_lb && i < n_v) ? src[i] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < GF_MAXPT; ++t) acc[t] += v[u][t];
+    }
+#pragma unroll
+    for (int t = 0; t < GF_MAXPT; ++t) s_sum[wave][lane + 64 * t] = acc[t];
+  }
+  __syncthreads();
+  if (wave != 0) return;
   double y[GF_MAXPT];
 #pragma unroll
   for (int t = 0; t < GF_MAXPT; ++t) {
     const int i = lane + 64 * t;
-    y[t] = (i < n_v) ? yg[i] : 0.0;
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) a += s_sum[w][i];
+    y[t] = a;
+    if (i < n_v) ccf[s * n_v + i] = a;
   }
+  if (!fit) return;
   // start values: max, first argmin, half-depth width
   double ymax = -1e308, ymin = 1e308;
   int kmin = n_v;
@@ -371,30 +406,37 @@ __global__ void __launch_bounds__(64) k_gfit(int64_t n_spec, int n_v, double v0,
       double x[4];
       double Sn[20];
       bool ok = gf_solve(S, true, lam, x) || gf_solve(S, false, lam, x);
-      double pn[4] = {p[0], p[1], p[2], p[3]};
+      bool tiny = false;
       if (ok) {
+        const double sig = fabs(p[3]);
+        tiny = fabs(x[0]) <= 1e-10 * fabs(p[0]) && fabs(x[1]) <= 1e-10 * fabs(p[1]) &&
+               fabs(x[2]) <= 1e-10 * sig && fabs(x[3]) <= 1e-10 * sig;
+        double pn[4];
         for (int q = 0; q < 4; ++q) pn[q] = p[q] + x[q];
         gf_eval(y, n_v, v0, dv, pn, Sn);
-        ok = Sn[0] <= S[0];
-      }
-      if (!ok) {
-        lam = (lam > 0.0) ? lam * 10.0 : 1e-6;
-        if (lam > 1e10) {
-          res.status = 0;
-          ++it;
-          break;
+        if (Sn[0] <= S[0]) {
+          const double dchi = S[0] - Sn[0];
+          for (int q = 0; q < 4; ++q) p[q] = pn[q];
+          for (int q = 0; q < 20; ++q) S[q] = Sn[q];
+          lam = (lam > 1e-9) ? lam * 0.1 : 0.0;
+          const double sgn = fabs(p[3]);
+          const bool floor_hit =
+              dchi <= 1e-15 * S[0] && fabs(x[2]) <= 1e-9 * sgn && fabs(x[3]) <= 1e-9 * sgn;
+          if (tiny || floor_hit) {
+            res.status = 0;
+            ++it;
+            break;
+          }
+          continue;
         }
-        continue;
       }
-      const double sig = fabs(pn[3]);
-      const double dchi = S[0] - Sn[0];
-      for (int q = 0; q < 4; ++q) p[q] = pn[q];
-      for (int q = 0; q < 20; ++q) S[q] = Sn[q];
-      lam = (lam > 1e-9) ? lam * 0.1 : 0.0;
-      const bool small = fabs(x[0]) <= 1e-10 * fabs(p[0]) && fabs(x[1]) <= 1e-10 * fabs(p[1]) &&
-                         fabs(x[2]) <= 1e-10 * sig && fabs(x[3]) <= 1e-10 * sig;
-      const bool floor_hit = dchi <= 1e-15 * S[0] && fabs(x[2]) <= 1e-9 * sig && fabs(x[3]) <= 1e-9 * sig;
-      if (small || floor_hit) {
+      if (tiny) {  // a rounding-size step that does not lower chi^2
+        res.status = 0;
+        ++it;
+        break;
+      }
+      lam = (lam > 0.0) ? lam * 10.0 : 1e-6;
+      if (lam > 1e10) {
         res.status = 0;
         ++it;
         break;
@@ -430,16 +472,19 @@ static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_s
 }
 
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
-                      double* d_part, double* d_ccf) {
+                      double* d_part) {
   const int nlb = ccf_line_blocks(n_lines);
   dim3 grid(nlb, (unsigned)((n_spec + CCF_SB - 1) / CCF_SB));
   if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_mask, n_lines, d_part);
   else launch_ccf_t<double>(c, grid, d_flux, n_spec, d_mask, n_lines, d_part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t nt = n_spec * c->mask_nv;
-  hipLaunchKernelGGL(k_ccf_reduce, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, nlb, n_spec,
-                     c->mask_nv, d_part, d_ccf);
+  return hipGetLastError();
+}
+
+hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_t n_spec, double* d_ccf,
+                          soap_rv* d_rv) {
+  const int nlb = ccf_line_blocks(n_lines);
+  hipLaunchKernelGGL(k_ccf_fit, dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, c->stream, nlb, n_spec,
+                     c->mask_nv, c->mask_v0, c->mask_dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);
   return hipGetLastError();
 }
 
@@ -449,10 +494,5 @@ hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w,
   return hipGetLastError();
 }
 
-hipError_t launch_gfit(soap_ctx* c, const double* d_ccf, int64_t n_spec, soap_rv* d_rv) {
-  hipLaunchKernelGGL(k_gfit, dim3((unsigned)n_spec), dim3(64), 0, c->stream, n_spec, c->mask_nv, c->mask_v0,
-                     c->mask_dv, d_ccf, d_rv);
-  return hipGetLastError();
-}
 
 }  // namespace soap

@@ -533,26 +533,27 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   {
     StageTimer t(c, ST_CCF);
     HIP_TRY(soap::launch_ccf(c, dflux, n_spec, static_cast<const double*>(c->ws_mask.ptr), nl,
-                             static_cast<double*>(c->ws_ccf.ptr), dccf));
+                             static_cast<double*>(c->ws_ccf.ptr)));
     t.done();
   }
   c->ccf_calls++;
   bool sync = false;
+  soap_rv* drv = nullptr;
   if (rv_out) {
-    soap_rv* drv = rv_on_device ? rv_out : nullptr;
+    drv = rv_on_device ? rv_out : nullptr;
     if (!drv) {
       HIP_TRY(grow(c->ws_rv, sizeof(soap_rv) * (size_t)n_spec));
       drv = static_cast<soap_rv*>(c->ws_rv.ptr);
     }
-    {
-      StageTimer t(c, ST_GFIT);
-      HIP_TRY(soap::launch_gfit(c, dccf, n_spec, drv));
-      t.done();
-    }
-    if (!rv_on_device) {
-      HIP_TRY(hipMemcpyAsync(rv_out, drv, sizeof(soap_rv) * n_spec, hipMemcpyDeviceToHost, c->stream));
-      sync = true;
-    }
+  }
+  {
+    StageTimer t(c, ST_GFIT);
+    HIP_TRY(soap::launch_ccf_fit(c, nl, static_cast<const double*>(c->ws_ccf.ptr), n_spec, dccf, drv));
+    t.done();
+  }
+  if (rv_out && !rv_on_device) {
+    HIP_TRY(hipMemcpyAsync(rv_out, drv, sizeof(soap_rv) * n_spec, hipMemcpyDeviceToHost, c->stream));
+    sync = true;
   }
   if (ccf_out && !ccf_on_device) {
     HIP_TRY(hipMemcpyAsync(ccf_out, dccf, sizeof(double) * ccf_elems, hipMemcpyDeviceToHost, c->stream));

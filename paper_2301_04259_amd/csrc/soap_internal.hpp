@@ -191,8 +191,10 @@ hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o);
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
-                      double* d_part, double* d_ccf);
-hipError_t launch_gfit(soap_ctx* c, const double* d_ccf, int64_t n_spec, soap_rv* d_rv);
+                      double* d_part);
+// sums the partial CCFs into d_ccf and, when d_rv is not null, fits them
+hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_t n_spec, double* d_ccf,
+                          soap_rv* d_rv);
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask);
 
 int ccf_line_blocks(int n_lines);
