@@ -49,7 +49,7 @@ __global__ void k_mask_prep(int n, double ln0, double dln, double P, const doubl
 // loads are in flight in registers while the current one is used), then one
 // thread per velocity computes each hole's pixel overlaps once and applies
 // them to every staged spectrum, accumulating in double.
-template <typename T, int A>
+template <typename T, int A, int NPX>
 __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, const T* __restrict__ F,
                                                      int n_lines, const double2* __restrict__ mask, int n_v,
                                                      double v0, double dv, double h, double dln,
@@ -148,15 +148,18 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
         const double qlo = mw.x + alo[a];
         const double qhi = mw.x + ahi[a];
         const int ma = (int)floor(qlo);
-        const int mb = (int)floor(qhi);
-        for (int m = ma; m <= mb; ++m) {
+        // a hole narrower than NPX - 1 pixels meets at most NPX pixels; the
+        // pixels past its end get a zero weight (an exact no-op)
+#pragma unroll(A * NPX <= 10 ? NPX : 1)
+        for (int px = 0; px < NPX; ++px) {
+          const int m = ma + px;
           const double ov = fmin(qhi, (double)(m + 1)) - fmax(qlo, (double)m);
           const int i = m - lo;
-          if (ov > 0.0 && m >= 0 && m < P && (unsigned)i < (unsigned)len) {
-            const double wo = mw.y * ov;
+          const bool use = ov > 0.0 && m >= 0 && m < P && (unsigned)i < (unsigned)len;
+          const double wo = use ? mw.y * ov : 0.0;
+          const int ii = use ? i : 0;
 #pragma unroll
-            for (int s = 0; s < CCF_SB; ++s) acc[a][s] = fma(wo, st[s][i], acc[a][s]);
-          }
+          for (int s = 0; s < CCF_SB; ++s) acc[a][s] = fma(wo, st[s][ii], acc[a][s]);
         }
       }
     }
@@ -454,29 +457,40 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
   if (lane == 0) out[s] = res;
 }
 
+template <typename T, int A, int NPX>
+static void launch_ccf_a(soap_ctx* c, dim3 grid, const T* F, int64_t n_spec, const double2* M, int n_lines) {
+  hipLaunchKernelGGL((k_ccf<T, A, NPX>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M,
+                     c->mask_nv, c->mask_v0, c->mask_dv, c->mask_h, c->dln, c->ccf_part);
+}
+
+template <typename T, int NPX>
+static void launch_ccf_n(soap_ctx* c, dim3 grid, const T* F, int64_t n_spec, const double2* M, int n_lines) {
+  const int nv = c->mask_nv;
+  if (nv <= CCF_THREADS) launch_ccf_a<T, 1, NPX>(c, grid, F, n_spec, M, n_lines);
+  else if (nv <= 2 * CCF_THREADS) launch_ccf_a<T, 2, NPX>(c, grid, F, n_spec, M, n_lines);
+  else launch_ccf_a<T, 4, NPX>(c, grid, F, n_spec, M, n_lines);
+}
+
 template <typename T>
 static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, const double* d_mask,
-                         int n_lines, double* d_part) {
+                         int n_lines) {
   const T* F = static_cast<const T*>(d_flux);
   const double2* M = reinterpret_cast<const double2*>(d_mask);
-  const int nv = c->mask_nv;
-  if (nv <= CCF_THREADS)
-    hipLaunchKernelGGL((k_ccf<T, 1>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M, nv,
-                       c->mask_v0, c->mask_dv, c->mask_h, c->dln, d_part);
-  else if (nv <= 2 * CCF_THREADS)
-    hipLaunchKernelGGL((k_ccf<T, 2>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M, nv,
-                       c->mask_v0, c->mask_dv, c->mask_h, c->dln, d_part);
-  else
-    hipLaunchKernelGGL((k_ccf<T, 4>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M, nv,
-                       c->mask_v0, c->mask_dv, c->mask_h, c->dln, d_part);
+  // pixels a hole can meet: its width (at the widest velocity) plus two
+  const double wpx = c->mask_hole_px;
+  if (wpx < 1.0) launch_ccf_n<T, 2>(c, grid, F, n_spec, M, n_lines);
+  else if (wpx < 2.0) launch_ccf_n<T, 3>(c, grid, F, n_spec, M, n_lines);
+  else if (wpx < 4.0) launch_ccf_n<T, 5>(c, grid, F, n_spec, M, n_lines);
+  else launch_ccf_n<T, 10>(c, grid, F, n_spec, M, n_lines);
 }
 
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
                       double* d_part) {
   const int nlb = ccf_line_blocks(n_lines);
   dim3 grid(nlb, (unsigned)((n_spec + CCF_SB - 1) / CCF_SB));
-  if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_mask, n_lines, d_part);
-  else launch_ccf_t<double>(c, grid, d_flux, n_spec, d_mask, n_lines, d_part);
+  c->ccf_part = d_part;
+  if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_mask, n_lines);
+  else launch_ccf_t<double>(c, grid, d_flux, n_spec, d_mask, n_lines);
   return hipGetLastError();
 }
 

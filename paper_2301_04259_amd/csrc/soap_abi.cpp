@@ -131,7 +131,7 @@ void destroy_ctx(soap_ctx* c) {
   void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base, c->d_ones};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
-  soap::Workspace* ws[] = {&c->ws_Kp, &c->ws_slab, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_flux,
+  soap::Workspace* ws[] = {&c->ws_Kfx, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_flux,
                            &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
   for (auto* w : ws) free_ws(*w);
   for (auto& p : c->pending) {
@@ -385,8 +385,17 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   // weights kernel reads it in place
   const size_t reg_bytes = sizeof(soap::Region) * soap::MAX_REGIONS;
   const size_t par_bytes = reg_bytes + sizeof(double) * n_phases;
-  HIP_TRY(grow(c->ws_Kp, sizeof(double) * (size_t)n_phases * pl.n_slabs * GJ));
-  HIP_TRY(grow(c->ws_slab, sizeof(int) * (size_t)n_phases * pl.n_slabs));
+  {
+    // fixed-point tap accumulators: zero when allocated; every call that
+    // accumulates also clears them, so they are zeroed again only after an
+    // interrupted call
+    const size_t kfx_bytes = sizeof(unsigned long long) * (size_t)n_phases * GJ;
+    if (c->ws_Kfx.bytes < kfx_bytes || c->kfx_dirty) {
+      HIP_TRY(grow(c->ws_Kfx, kfx_bytes));
+      HIP_TRY(hipMemsetAsync(c->ws_Kfx.ptr, 0, c->ws_Kfx.bytes, c->stream));
+      c->kfx_dirty = false;
+    }
+  }
   HIP_TRY(grow(c->ws_K, sizeof(double) * (size_t)n_phases * GJ));
   HIP_TRY(grow(c->ws_mask64, sizeof(unsigned long long) * (size_t)n_phases * pl.G));
   HIP_TRY(grow(c->ws_vg, (size_t)soap::WIN_BYTES * pl.n_chunks * pl.vg_cap));
@@ -425,12 +434,12 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   const double* d_ph = reinterpret_cast<const double*>(static_cast<const unsigned char*>(dev_view) + reg_bytes);
 
   soap::WeightsOut wo;
-  wo.Kp = static_cast<double*>(c->ws_Kp.ptr);
-  wo.slab = static_cast<int*>(c->ws_slab.ptr);
+  wo.Kfx = static_cast<unsigned long long*>(c->ws_Kfx.ptr);
   wo.K = static_cast<double*>(c->ws_K.ptr);
   wo.mask = static_cast<unsigned long long*>(c->ws_mask64.ptr);
   wo.wins = static_cast<unsigned char*>(c->ws_vg.ptr);
   wo.nvg = static_cast<int*>(c->ws_nvg.ptr);
+  c->kfx_dirty = true;
   {
     StageTimer t(c, ST_WEIGHTS);
     HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, d_ph, wo));
@@ -442,6 +451,7 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
     HIP_TRY(soap::launch_finish(c, pl, wo));
     t.done();
   }
+  c->kfx_dirty = false;
   {
     StageTimer t(c, ST_APPLY);
     HIP_TRY(soap::launch_apply(c, pl, c->ws_vg.ptr, static_cast<const int*>(c->ws_nvg.ptr), dflux));
@@ -512,6 +522,17 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
     c->mask_v0 = mask->v0_kms;
     c->mask_dv = mask->dv_kms;
     c->mask_nv = mask->n_v;
+    {
+      // widest hole over the grid: the hole edges are Doppler-shifted
+      // (Eq. 6), so its width in pixels grows with |v|
+      double w = 0.0;
+      for (int k : {0, mask->n_v - 1}) {
+        const double vk = mask->v0_kms + mask->dv_kms * k;
+        w = std::max(w, (std::atanh((vk + mask->half_width_kms) / soap::C_KMS) -
+                         std::atanh((vk - mask->half_width_kms) / soap::C_KMS)) / c->dln);
+      }
+      c->mask_hole_px = w;
+    }
     c->mask_valid = true;
   }
 

@@ -42,9 +42,11 @@ constexpr int PAD_FRONT = 128;
 
 // Column slabs of the per-phase weight kernel.
 constexpr int SLAB_COLS = 32;
-constexpr int WEIGHT_WAVES = 8;
-constexpr int MAX_SLABS = (MAX_GRID + SLAB_COLS - 1) / SLAB_COLS;
+constexpr int WEIGHT_WAVES = 4;
 constexpr int FINISH_THREADS = 512;
+// fixed-point unit of the per-phase tap accumulators
+constexpr double FX_ONE = 2305843009213693952.0;        // 2^61
+constexpr double FX_INV = 1.0 / 2305843009213693952.0;  // 2^-61
 
 // region record as the kernels read it (device view of soap_region)
 struct Region {
@@ -115,8 +117,8 @@ struct soap_ctx {
   void* d_ones = nullptr;                          // [n_tiles * TILE] of 1 (no-contrast operand)
 
   // per-call workspace (grown on demand, freed by soap_destroy)
-  soap::Workspace ws_Kp;       // [n_phases][n_slabs][G][J] slab partial taps
-  soap::Workspace ws_slab;     // [n_phases][n_slabs] slab non-empty flags
+  soap::Workspace ws_Kfx;      // [n_phases][G][J] fixed-point tap accumulators (kept zero)
+  bool kfx_dirty = false;      // a call stopped between accumulation and clearing
   soap::Workspace ws_K;        // [n_phases][G][J] double
   soap::Workspace ws_mask64;   // [n_phases][G] bitmask of nonzero offsets
   soap::Workspace ws_vg;       // [n_chunks][vg_cap] window records (WIN_BYTES each)
@@ -153,6 +155,8 @@ struct soap_ctx {
   // cached mask
   std::vector<double> mask_lnl, mask_w;
   double mask_h = 0, mask_v0 = 0, mask_dv = 0;
+  double mask_hole_px = 0;  // widest hole of the velocity grid, in pixels
+  double* ccf_part = nullptr;  // partial CCFs of the launch being enqueued
   int mask_nv = 0;
   bool mask_valid = false;
 };
@@ -178,8 +182,7 @@ hipError_t launch_ones(soap_ctx* c);
 hipError_t launch_quiet(soap_ctx* c);
 // outputs and scratch of the weight kernel
 struct WeightsOut {
-  double* Kp;                // [n_phases][n_slabs][G][J] slab partial taps
-  int* slab;                 // [n_phases][n_slabs] slab covered flags
+  unsigned long long* Kfx;   // [n_phases][G][J] fixed-point taps, zero between calls
   double* K;                 // [n_phases][G][J] taps
   unsigned long long* mask;  // [n_phases][G] non-zero offsets
   unsigned char* wins;       // [n_chunks][vg_cap] window records

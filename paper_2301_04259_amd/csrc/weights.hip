@@ -8,14 +8,12 @@
 //      most asin(radius); the InfoMap owner is the last listed region that
 //      covers it;
 //   3. per column, the weights A I(mu) of the active cells are summed per
-//      (type, mu bin).  Each lane sums its own cells (FP32 + Kahan in the
-//      FP32 mode, FP64 otherwise); all (type, bin) slots of the column are
-//      then reduced over the 64 lanes at once in FP64 by a transposed
-//      butterfly (16 slots in 17 shuffles);
+//      (type, mu bin), one (type, bin) present in the pass at a time: each
+//      lane sums its own cells (FP32 + Kahan in the FP32 mode, FP64
+//      otherwise), and the 64 lane sums are added in FP64 by DPP exchanges
+//      in a fixed order;
 //   4. each column sum is collapsed onto the two integer offsets of the
-//      column's shift (1 - w at j = c, w at j = c - 1: Eq. 11) in a per-wave
-//      FP64 table; the waves are summed in a fixed order into the slab's
-//      partial table.
+//      column's shift (1 - w at j = c, w at j = c - 1: Eq. 11).
 // Tables: paired mode (every active weight equals its removal weight:
 // chromatic contrast, the convective effect, or unit scalar contrasts) keeps
 // one table row per active (type, bin), g = (type - 1) * B + bin, and the
@@ -23,10 +21,13 @@
 // contrasts other than one) keeps g = type * B + bin with type 0 the removal
 // (-A I) and the active rows scaled by the region contrast.
 //
-// k_finish, one block per chunk of phases, sums the slab partials in slab
-// order, records per (phase, group) the bitmask of non-zero offsets, and
-// turns the chunk into window records of APPLY_JW offsets with dense taps
-// and per-offset masks of the groups of four phases that have a tap.
+// Column contributions go straight to per-phase tap tables in 64-bit fixed
+// point (exact integer atomics, so the totals repeat bit for bit whatever
+// the order).  k_finish, one block per chunk of phases, converts the tables
+// to double (clearing them for the next call), records per (phase, group)
+// the bitmask of non-zero offsets, and turns the chunk into window records
+// of APPLY_JW offsets with dense taps and per-offset masks of the groups of
+// four phases that have a tap.
 // Every sum has a fixed order, so results repeat bit for bit.
 #include <algorithm>
 #include <type_traits>
@@ -38,14 +39,15 @@ namespace soap {
 
 namespace {
 
-__device__ __forceinline__ unsigned long long wor(unsigned long long v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off, 64);
-  return v;
-}
 
 constexpr int MAXC = 4;   // cells per lane per row pass (256 rows)
-constexpr int SLOTS = 16; // slots reduced together (butterfly16)
+
+// taps are accumulated as 64-bit fixed point in units of 2^-61 (|tap| < 4):
+// integer addition is exact, so the totals do not depend on the order in
+// which columns arrive
+__device__ __forceinline__ unsigned long long to_fx(double x) {
+  return (unsigned long long)__double2ll_rn(x * FX_ONE);
+}
 
 }  // namespace
 
@@ -140,54 +142,35 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
     reinterpret_cast<WinHead*>(wrec + (int64_t)v * WIN_BYTES)->gmask = s_gm[v];
 }
 
-// One block per chunk of PC phases: the phases' taps K[ph][g][j] = sum of
-// the covered slab partials in slab order, the per-(phase, group) bitmask
-// of non-zero offsets, then the chunk's window records.
+// One block per chunk of PC phases: the phases' taps K[ph][g][j] from the
+// fixed-point accumulators (which are cleared for the next call), the
+// per-(phase, group) bitmask of non-zero offsets, then the chunk's window
+// records.
 template <typename T>
 __global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int G, int J, int jmin, int B,
-                                                           int paired, int n_slabs, int vg_cap,
-                                                           const double* __restrict__ Kp,
-                                                           const int* __restrict__ slab_flag, double* __restrict__ K,
+                                                           int paired, int vg_cap,
+                                                           unsigned long long* __restrict__ Kfx,
+                                                           double* __restrict__ K,
                                                            unsigned long long* __restrict__ mask,
                                                            unsigned char* __restrict__ wins, int* __restrict__ nvg) {
   extern __shared__ int sm[];
-  __shared__ int s_flag[PC_MAX * MAX_SLABS];
   const int chunk = blockIdx.x;
   const int p0 = chunk * PC;
   const int np = min(PC, n_ph - p0);
   const int GJ = G * J;
-  for (int t = threadIdx.x; t < np * n_slabs; t += blockDim.x) s_flag[t] = slab_flag[p0 * n_slabs + t];
-  __syncthreads();
-  // every (phase, table entry) of the chunk: its slab partials are loaded
-  // together, then added in slab order
+  const int64_t base = (int64_t)p0 * GJ;
   for (int t = threadIdx.x; t < np * GJ; t += blockDim.x) {
-    const int p = t / GJ;
-    const int e = t - p * GJ;
-    const double* src = Kp + (int64_t)(p0 + p) * n_slabs * GJ + e;
-    const int* fl = s_flag + p * n_slabs;
-    double s = 0.0;
-    for (int sl0 = 0; sl0 < n_slabs; sl0 += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int sl = sl0 + u;
-        v[u] = (sl < n_slabs && fl[sl]) ? src[(int64_t)sl * GJ] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (sl0 + u < n_slabs && fl[sl0 + u]) s += v[u];
-    }
-    K[(int64_t)(p0 + p) * GJ + e] = s;
+    const long long v = (long long)Kfx[base + t];
+    Kfx[base + t] = 0ull;
+    K[base + t] = (double)v * FX_INV;
   }
   __syncthreads();
   for (int t = threadIdx.x; t < np * G; t += blockDim.x) {
-    const int p = t / G;
-    const int g = t - p * G;
-    const double* kr = K + (int64_t)(p0 + p) * GJ + g * J;
+    const double* kr = K + base + (int64_t)t * J;
     unsigned long long mk = 0;
     for (int j = 0; j < J; ++j)
       if (kr[j] != 0.0) mk |= 1ull << j;
-    mask[(int64_t)(p0 + p) * G + g] = mk;
+    mask[(int64_t)p0 * G + t] = mk;
   }
   __syncthreads();
   compact_chunk<T>(chunk, n_ph, PC, G, J, jmin, B, paired, K, mask, wins, nvg, vg_cap, sm);
@@ -195,10 +178,10 @@ __global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int
 
 template <bool KAHAN32>
 __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
-    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, double incl, int effect, int cmode, const double* __restrict__ mu_b, const int* __restrict__ col_c,
-    const double* __restrict__ col_w, const Region* __restrict__ reg, int n_reg, const double* __restrict__ phases,
-    double* __restrict__ Kp, int* __restrict__ slab_flag) {
-  extern __shared__ double lds[];  // [nw][G*J] tables, then [nw][192] slot codes
+    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, double incl, int effect,
+    int cmode, const double* __restrict__ mu_b, const int* __restrict__ col_c, const double* __restrict__ col_w,
+    const Region* __restrict__ reg, int n_reg, const double* __restrict__ phases,
+    unsigned long long* __restrict__ Kfx) {
   __shared__ double rcx[MAX_REGIONS], rcy[MAX_REGIONS], rcz[MAX_REGIONS], rcos[MAX_REGIONS],
       rscal[MAX_REGIONS];
   __shared__ double s_mub[MAX_MU];
@@ -254,15 +237,11 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
     box[1] = i1;
     box[2] = max(k0, 0);
     box[3] = min(k1, N - 1);
-    slab_flag[ph * n_slabs + slab] = (i0 <= i1 && box[2] <= box[3]) ? 1 : 0;
   }
   __syncthreads();
   const int i0 = box[0], i1 = box[1], k0 = box[2], k1 = box[3];
-  if (i0 <= i1 && k0 <= k1) {  // uniform: some of this slab is covered
-  for (int t = threadIdx.x; t < nw * GJ; t += blockDim.x) lds[t] = 0.0;
-  __syncthreads();
-  double* myK = lds + wave * GJ;
-  int* slots = reinterpret_cast<int*>(lds + nw * GJ) + wave * 192;
+  if (i0 > i1 || k0 > k1) return;  // uniform: nothing of this slab is covered
+  unsigned long long* Kph = Kfx + (int64_t)ph * GJ;
 
   for (int i = i0 + wave; i <= i1; i += nw) {
     const double x = cell_coord(i, N);
@@ -310,33 +289,24 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
           }
         }
       }
-      m1 = wor(m1);
-      m2 = wor(m2);
+      m1 = wave_or64(m1);
+      m2 = wave_or64(m2);
       const unsigned long long m0 = paired ? 0ull : (m1 | m2);
       if (!(m1 | m2)) continue;  // uniform
-      // slot list: removal bins (split mode), spot bins, facula bins
-      const int n0 = __popcll(m0), n1 = __popcll(m1), n2 = __popcll(m2);
-      const int nslot = n0 + n1 + n2;
-      {
-        const unsigned long long below = (lane == 0) ? 0ull : ((1ull << lane) - 1ull);
-        if ((m0 >> lane) & 1) slots[__popcll(m0 & below)] = lane;
-        if ((m1 >> lane) & 1) slots[n0 + __popcll(m1 & below)] = lane | (SOAP_SPOT << 8);
-        if ((m2 >> lane) & 1) slots[n0 + n1 + __popcll(m2 & below)] = lane | (SOAP_FACULA << 8);
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      for (int sb = 0; sb < nslot; sb += SLOTS) {
-        double v[SLOTS];
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-          const int code = (sb + s < nslot) ? slots[sb + s] : -2;
-          const int tb = code & 0xff, tt = code >> 8;  // tt == 0: removal
+      // one (type, bin) slot at a time, in a fixed order: removal bins
+      // (split tables), then spot bins, then facula bins
+      for (int tt = paired ? 1 : 0; tt <= 2; ++tt) {
+        unsigned long long mt = (tt == 0) ? m0 : (tt == 1 ? m1 : m2);
+        while (mt) {
+          const int tb = __builtin_ctzll(mt);
+          mt &= mt - 1;
+          double part;
           if (KAHAN32) {
             float acc = 0.f, comp = 0.f;
 #pragma unroll
             for (int q = 0; q < MAXC; ++q) {
               const bool hit = cb[q] >= 0 && (cb[q] & 0xff) == tb && (tt == 0 || (cb[q] >> 8) == tt);
-              if (code >= 0 && hit) {
+              if (hit) {
                 const float val = (tt == 0) ? -(float)cw[q] : (float)(cw[q] * cs[q]);
                 const float yk = val - comp;
                 const float tk = acc + yk;
@@ -344,72 +314,53 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
                 acc = tk;
               }
             }
-            v[s] = (double)acc - (double)comp;
+            part = (double)acc - (double)comp;
           } else {
             double acc = 0.0;
 #pragma unroll
             for (int q = 0; q < MAXC; ++q) {
               const bool hit = cb[q] >= 0 && (cb[q] & 0xff) == tb && (tt == 0 || (cb[q] >> 8) == tt);
-              if (code >= 0 && hit) acc += (tt == 0) ? -cw[q] : cw[q] * cs[q];
+              if (hit) acc += (tt == 0) ? -cw[q] : cw[q] * cs[q];
             }
-            v[s] = acc;
+            part = acc;
+          }
+          const double W = wave_sum_f64(part);
+          if (lane == 0 && jb >= 0 && ja < J) {
+            const int g = paired ? (tt - 1) * B + tb : tt * B + tb;
+            // exact, order-free accumulation: fixed point with 2^-61 units
+            unsigned long long* kr = Kph + g * J;
+            atomicAdd(kr + ja, to_fx((1.0 - wi) * W));
+            atomicAdd(kr + jb, to_fx(wi * W));
           }
         }
-        const double W = butterfly16(v, lane);
-        const int s = (lane >> 2) & (SLOTS - 1);
-        if ((lane & 3) == 0 && sb + s < nslot && jb >= 0 && ja < J) {
-          const int code = slots[sb + s];
-          const int tb = code & 0xff, tt = code >> 8;
-          const int g = paired ? (tt - 1) * B + tb : tt * B + tb;
-          double* kr = myK + g * J;
-          kr[ja] += (1.0 - wi) * W;
-          kr[jb] += wi * W;
-        }
       }
-      __builtin_amdgcn_wave_barrier();
     }
   }
-  __syncthreads();
-  double* out = Kp + ((int64_t)ph * n_slabs + slab) * GJ;
-  for (int t = threadIdx.x; t < GJ; t += blockDim.x) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += lds[w * GJ + t];
-    out[t] = s;
-  }
-  }  // covered slab
 }
 
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
                           const WeightsOut& o) {
-  const size_t per_wave = (size_t)pl.G * c->J * sizeof(double) + 192 * sizeof(int);
-  // dynamic LDS stays below 60 KB so that with the static arrays the block
-  // fits a 64 KB workgroup allocation
-  int nw = (int)std::min<size_t>(WEIGHT_WAVES, (60 * 1024) / per_wave);
-  if (nw < 1) nw = 1;
-  const size_t lds = nw * per_wave;
   dim3 grid((unsigned)pl.n_slabs * (unsigned)pl.n_ph);
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * nw), lds, c->stream, c->N, c->B, c->J, c->jmin, pl.G,
-                       pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu, c->d_col_c,
-                       c->d_col_w, d_reg, n_reg, d_ph, o.Kp, o.slab);
+    hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, c->stream, c->N, c->B, c->J, c->jmin,
+                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu,
+                       c->d_col_c, c->d_col_w, d_reg, n_reg, d_ph, o.Kfx);
   else
-    hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * nw), lds, c->stream, c->N, c->B, c->J, c->jmin, pl.G,
-                       pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu, c->d_col_c,
-                       c->d_col_w, d_reg, n_reg, d_ph, o.Kp, o.slab);
+    hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * WEIGHT_WAVES), 0, c->stream, c->N, c->B, c->J, c->jmin,
+                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu,
+                       c->d_col_c, c->d_col_w, d_reg, n_reg, d_ph, o.Kfx);
   return hipGetLastError();
 }
 
 hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o) {
-  if (pl.n_slabs > MAX_SLABS) return hipErrorInvalidValue;
   const size_t lds = (size_t)(6 * pl.G + pl.vg_cap + 2) * sizeof(int);
+  if (lds > 60 * 1024) return hipErrorInvalidValue;
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_finish<float>, dim3(pl.n_chunks), dim3(FINISH_THREADS), lds, c->stream, pl.n_ph, c->pc,
-                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.n_slabs, pl.vg_cap, o.Kp, o.slab, o.K, o.mask,
-                       o.wins, o.nvg);
+                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
   else
     hipLaunchKernelGGL(k_finish<double>, dim3(pl.n_chunks), dim3(FINISH_THREADS), lds, c->stream, pl.n_ph, c->pc,
-                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.n_slabs, pl.vg_cap, o.Kp, o.slab, o.K, o.mask,
-                       o.wins, o.nvg);
+                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
   return hipGetLastError();
 }
 

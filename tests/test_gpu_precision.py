@@ -1,0 +1,97 @@
+"""Precision study on the headline workload (full visible range at R = 115000,
+300 x 300 disk, 100 phases): the FP32 mode (FP32 spectra and taps,
+compensated column sums, FP64 final disk sum, CCF and fit) and the FP64 mode
+run on identical input values (the FP32 spectra, upcast), each against the
+FP64 oracle, phase by phase.
+
+Prints one line per sampled phase: the maximum relative flux error and the
+RV error in cm/s of both modes.  Twelve phases spread over the rotation are
+checked by default; SOAP_PRECISION_ALL_PHASES=1 checks all 100.
+"""
+import dataclasses
+import os
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ccf as OC
+from oracle import fit as OF
+from oracle import spectrum as OS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2301_04259_amd", reason="libsoap.so not built")
+
+FLUX_REL = {W.PREC_FP32: 1e-6, W.PREC_FP64: 1e-9}
+RV_CMS = {W.PREC_FP32: 1.0, W.PREC_FP64: 1e-2}
+
+
+def _say(*a):
+    print("[precision]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _oracle_phase(args):
+    star, ph = args
+    f = OS.integrated(star, ph, OS.TOT)
+    m = star.mask
+    v = W.make_velocity_grid(m.v0_kms, m.dv_kms, m.n_v)
+    c = OC.ccf(f[None, :], star.ln_lambda0, star.dln_lambda, m.ln_lambda, m.weight, m.half_width_kms, v)[0]
+    return f, OF.gauss_fit(v, c)["mu"]
+
+
+def _run(star):
+    ctx = L.soap_grid_init(star)
+    dt = torch.float32 if star.precision == W.PREC_FP32 else torch.float64
+    out = torch.empty((len(star.phases), star.n_pix), dtype=dt, device="cuda")
+    L.soap_active_spectra(ctx, star.regions, star.phases, W.EFFECT_TOT, out)
+    rv = L.rv_records(len(star.phases))
+    L.soap_ccf_rv(ctx, out, star.mask, rv_out=rv)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy(), rv["rv_kms"].copy()
+    L.soap_destroy(ctx)
+    return res
+
+
+def test_precision_modes_against_oracle_per_phase():
+    s32 = W.make_cfg2()
+    # the FP64 run sees the very same input values
+    s64 = dataclasses.replace(
+        s32, precision=W.PREC_FP64, spectra=[None if s is None else np.asarray(s, np.float64) for s in s32.spectra]
+    )
+    n_ph = len(s32.phases)
+    if os.environ.get("SOAP_PRECISION_ALL_PHASES") == "1":
+        idx = list(range(n_ph))
+    else:
+        idx = sorted(set(np.linspace(0, n_ph - 1, 12).round().astype(int).tolist()))
+    _say("phases", len(idx))
+    got = {W.PREC_FP32: _run(s32), W.PREC_FP64: _run(s64)}
+    with ProcessPoolExecutor(max_workers=max(1, min(16, len(idx), os.cpu_count() or 1))) as ex:
+        ref = list(ex.map(_oracle_phase, [(s32, s32.phases[i]) for i in idx]))
+    _say(f"{'phase':>6s} {'fp32 flux':>10s} {'fp32 RV cm/s':>13s} {'fp64 flux':>10s} {'fp64 RV cm/s':>13s}")
+    worst = {W.PREC_FP32: [0.0, 0.0], W.PREC_FP64: [0.0, 0.0]}
+    for n, i in enumerate(idx):
+        f_or, rv_or = ref[n]
+        scale = np.maximum(np.abs(f_or), 1e-3 * np.abs(f_or).max())
+        row = []
+        for prec in (W.PREC_FP32, W.PREC_FP64):
+            flux, rv = got[prec]
+            e = float(np.max(np.abs(flux[i].astype(np.float64) - f_or) / scale))
+            d = abs(rv[i] - rv_or) * 1e5
+            worst[prec][0] = max(worst[prec][0], e)
+            worst[prec][1] = max(worst[prec][1], d)
+            row += [e, d]
+        _say(f"{s32.phases[i]:6.2f} {row[0]:10.2e} {row[1]:13.2e} {row[2]:10.2e} {row[3]:13.2e}")
+    _say("worst fp32", worst[W.PREC_FP32], "fp64", worst[W.PREC_FP64])
+    for prec in (W.PREC_FP32, W.PREC_FP64):
+        assert worst[prec][0] <= FLUX_REL[prec]
+        assert worst[prec][1] <= RV_CMS[prec]
