@@ -27,8 +27,9 @@
 // (broadcast) and added with fused multiply-adds; a wave-uniform mask test
 // skips the other groups.  The next window's loads are issued before the
 // current one is consumed.  The block-to-work mapping keeps the chunks of
-// one tile on one XCD so their shared input windows hit the same L2.  The
-// final combine adds Q in double.
+// one tile on one XCD so their shared input windows hit the same L2, and
+// starts the chunks with the most windows first.  The final combine adds Q
+// in double.
 #include "soap_internal.hpp"
 
 namespace soap {
@@ -202,13 +203,38 @@ __global__ void __launch_bounds__(APPLY_THREADS, sizeof(T) == 4 ? 3 : 2) k_apply
   static_assert(R == 4 && JW == 8, "window loads are written for 4 pixels x 8 offsets");
   static_assert(PC % 4 == 0 && JW * PC * sizeof(T) == WIN_TAP_BYTES, "record layout");
   extern __shared__ __align__(16) unsigned char s_win[];  // [lds_win][WIN_BYTES]
-  const int total = A.n_tiles * A.n_chunks;
-  const int per_xcd = (total + 7) / 8;
+  __shared__ int s_order[APPLY_RANKED];
+  // Blocks are dealt to the 8 XCDs in turn (blockIdx mod 8).  Each XCD owns
+  // a contiguous range of tiles, so the chunks of a tile share its L2, and
+  // walks its (chunk, tile) items heaviest chunk first (most windows), so
+  // that the long blocks start early and the short ones fill the end.
   const int bid = blockIdx.x;
-  const int w = (bid & 7) * per_xcd + (bid >> 3);
-  if (w >= total) return;
-  const int tile = w / A.n_chunks;
-  const int chunk = w - tile * A.n_chunks;
+  const int xcd = bid & 7;
+  const int seq = bid >> 3;
+  const int tpx = (A.n_tiles + 7) / 8;
+  const int t0 = xcd * tpx;
+  const int nt = min(A.n_tiles, t0 + tpx) - t0;
+  if (nt <= 0 || seq >= nt * A.n_chunks) return;
+  const int rank = seq / nt;
+  const int tile = t0 + (seq - rank * nt);
+  int chunk = rank;
+  if (A.n_chunks <= APPLY_RANKED) {
+    // rank of each chunk by window count (ties in chunk order)
+    const int c = threadIdx.x;
+    const int wc = c < A.n_chunks ? A.nvg[c] : 0;
+    if (c < A.n_chunks) s_order[c] = wc;  // window counts, then the order
+    __syncthreads();
+    int r = 0;
+    if (c < A.n_chunks)
+      for (int d = 0; d < A.n_chunks; ++d) {
+        const int wd = s_order[d];
+        r += (wd > wc || (wd == wc && d < c)) ? 1 : 0;
+      }
+    __syncthreads();
+    if (c < A.n_chunks) s_order[r] = c;
+    __syncthreads();
+    chunk = s_order[rank];
+  }
   const int64_t m0 = (int64_t)tile * (R * APPLY_THREADS) + (int64_t)threadIdx.x * R;
 
   T acc[PC][R];
@@ -282,9 +308,8 @@ __global__ void __launch_bounds__(APPLY_THREADS, sizeof(T) == 4 ? 3 : 2) k_apply
 }
 
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux) {
-  const int total = pl.n_chunks * c->n_tiles;
-  const int per_xcd = (total + 7) / 8;
-  dim3 grid(8 * per_xcd);
+  const int tpx = (c->n_tiles + 7) / 8;
+  dim3 grid(8 * tpx * pl.n_chunks);
   const bool vec_ok = (c->P % APPLY_R == 0) &&
                       (reinterpret_cast<uintptr_t>(d_flux) % (APPLY_R * c->esize) == 0);
   const int lds_win = std::min(pl.vg_cap, APPLY_LDS_WIN);

@@ -74,6 +74,8 @@ static_assert(APPLY_JW * PC_F32 * 4 == WIN_TAP_BYTES && APPLY_JW * PC_F64 * 8 ==
               "window record size");
 // windows staged in LDS per pass of the apply kernel
 constexpr int APPLY_LDS_WIN = 48;
+// phase chunks the apply kernel orders by work (more run in their natural order)
+constexpr int APPLY_RANKED = 64;
 
 struct Workspace {
   void* ptr = nullptr;
