@@ -131,7 +131,7 @@ void destroy_ctx(soap_ctx* c) {
   void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base, c->d_ones};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
-  soap::Workspace* ws[] = {&c->ws_Kfx, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_flux,
+  soap::Workspace* ws[] = {&c->ws_par, &c->ws_Kfx, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_flux,
                            &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
   for (auto* w : ws) free_ws(*w);
   for (auto& p : c->pending) {
@@ -433,7 +433,13 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   const soap::Region* d_reg = static_cast<const soap::Region*>(dev_view);
   const double* d_ph = reinterpret_cast<const double*>(static_cast<const unsigned char*>(dev_view) + reg_bytes);
 
+  const size_t reg_dev = 256 * ((sizeof(soap::Region) * soap::MAX_REGIONS + 255) / 256);
+  const size_t cen_dev = 256 * ((sizeof(double4) * (size_t)n_phases * std::max(1, n_regions) + 255) / 256);
+  HIP_TRY(grow(c->ws_par, reg_dev + cen_dev + sizeof(int4) * (size_t)n_phases));
   soap::WeightsOut wo;
+  wo.reg = static_cast<soap::Region*>(c->ws_par.ptr);
+  wo.cen = reinterpret_cast<double4*>(static_cast<unsigned char*>(c->ws_par.ptr) + reg_dev);
+  wo.box = reinterpret_cast<int4*>(static_cast<unsigned char*>(c->ws_par.ptr) + reg_dev + cen_dev);
   wo.Kfx = static_cast<unsigned long long*>(c->ws_Kfx.ptr);
   wo.K = static_cast<double*>(c->ws_K.ptr);
   wo.mask = static_cast<unsigned long long*>(c->ws_mask64.ptr);

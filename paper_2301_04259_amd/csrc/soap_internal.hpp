@@ -40,8 +40,8 @@ constexpr int PC_F64 = 8;
 // the interpolation comes for free.
 constexpr int PAD_FRONT = 128;
 
-// Column slabs of the per-phase weight kernel.
-constexpr int SLAB_COLS = 32;
+// Column slabs of the per-phase weight kernel (one wave per column).
+constexpr int SLAB_COLS = 4;
 constexpr int WEIGHT_WAVES = 4;
 constexpr int FINISH_THREADS = 512;
 // fixed-point unit of the per-phase tap accumulators
@@ -119,6 +119,7 @@ struct soap_ctx {
   void* d_ones = nullptr;                          // [n_tiles * TILE] of 1 (no-contrast operand)
 
   // per-call workspace (grown on demand, freed by soap_destroy)
+  soap::Workspace ws_par;      // regions, per-phase region centres and bounding boxes
   soap::Workspace ws_Kfx;      // [n_phases][G][J] fixed-point tap accumulators (kept zero)
   bool kfx_dirty = false;      // a call stopped between accumulation and clearing
   soap::Workspace ws_K;        // [n_phases][G][J] double
@@ -184,6 +185,9 @@ hipError_t launch_ones(soap_ctx* c);
 hipError_t launch_quiet(soap_ctx* c);
 // outputs and scratch of the weight kernel
 struct WeightsOut {
+  Region* reg;               // [n_regions] device copy of the regions
+  double4* cen;              // [n_phases][n_regions] region centres (x, y, z) and cos(alpha)
+  int4* box;                 // [n_phases] disk-cell bounding box of the visible caps
   unsigned long long* Kfx;   // [n_phases][G][J] fixed-point taps, zero between calls
   double* K;                 // [n_phases][G][J] taps
   unsigned long long* mask;  // [n_phases][G] non-zero offsets

@@ -8,10 +8,9 @@
 //      most asin(radius); the InfoMap owner is the last listed region that
 //      covers it;
 //   3. per column, the weights A I(mu) of the active cells are summed per
-//      (type, mu bin), one (type, bin) present in the pass at a time: each
-//      lane sums its own cells (FP32 + Kahan in the FP32 mode, FP64
-//      otherwise), and the 64 lane sums are added in FP64 by DPP exchanges
-//      in a fixed order;
+//      (type, mu bin): each lane sums its own cells (FP32 + Kahan in the
+//      FP32 mode, FP64 otherwise) and adds each sum to a per-wave LDS table
+//      as an exact 64-bit fixed-point integer;
 //   4. each column sum is collapsed onto the two integer offsets of the
 //      column's shift (1 - w at j = c, w at j = c - 1: Eq. 11).
 // Tables: paired mode (every active weight equals its removal weight:
@@ -176,17 +175,62 @@ __global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int
   compact_chunk<T>(chunk, n_ph, PC, G, J, jmin, B, paired, K, mask, wins, nvg, vg_cap, sm);
 }
 
+// Per phase (one thread each): every region centre rotated to the phase
+// (longitude + 360 deg * phase, axis tilted by the inclination), cos(alpha),
+// and the disk-cell bounding box of the caps that reach the visible
+// hemisphere.  The regions and phases are read once from the caller's
+// parameter block, so the weight kernel's many blocks read device memory.
+__global__ void __launch_bounds__(128) k_params(int N, int n_reg, int n_ph, double incl,
+                                                const Region* __restrict__ reg,
+                                                const double* __restrict__ phases,
+                                                Region* __restrict__ reg_out, double4* __restrict__ cen,
+                                                int4* __restrict__ box) {
+  __shared__ Region s_reg[MAX_REGIONS];
+  for (int r = threadIdx.x; r < n_reg; r += blockDim.x) {
+    s_reg[r] = reg[r];
+    if (blockIdx.x == 0) reg_out[r] = s_reg[r];
+  }
+  __syncthreads();
+  const int ph = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ph >= n_ph) return;
+  const double phase = phases[ph];
+  // a cap point p satisfies |p - c| <= 2 sin(alpha / 2) = sqrt(2 - 2 cos
+  // alpha), which bounds its projected distance from the centre
+  double xlo = 2.0, xhi = -2.0, ylo = 2.0, yhi = -2.0;
+  for (int r = 0; r < n_reg; ++r) {
+    double cx, cy, cz, rc;
+    region_centre(s_reg[r].lat_deg, s_reg[r].lon_deg, phase, incl, &cx, &cy, &cz);
+    {
+#pragma clang fp contract(off)
+      rc = sqrt(1.0 - s_reg[r].radius * s_reg[r].radius);
+    }
+    cen[(int64_t)ph * n_reg + r] = make_double4(cx, cy, cz, rc);
+    const double rad = sqrt(fmax(0.0, 1.0 - rc * rc));
+    if (cz <= -rad - 1e-12) continue;
+    const double d = sqrt(fmax(0.0, 2.0 - 2.0 * rc)) + 1e-9;
+    xlo = fmin(xlo, cx - d);
+    xhi = fmax(xhi, cx + d);
+    ylo = fmin(ylo, cy - d);
+    yhi = fmax(yhi, cy + d);
+  }
+  const int i0 = (int)floor((xlo + 1.0) * 0.5 * N) - 1;
+  const int i1 = (int)ceil((xhi + 1.0) * 0.5 * N) + 1;
+  const int k0 = (int)floor((ylo + 1.0) * 0.5 * N) - 1;
+  const int k1 = (int)ceil((yhi + 1.0) * 0.5 * N) + 1;
+  box[ph] = make_int4(i0, i1, max(k0, 0), min(k1, N - 1));
+}
+
 template <bool KAHAN32>
 __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
-    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, double incl, int effect,
-    int cmode, const double* __restrict__ mu_b, const int* __restrict__ col_c, const double* __restrict__ col_w,
-    const Region* __restrict__ reg, int n_reg, const double* __restrict__ phases,
+    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, int effect,
+    const double* __restrict__ mu_b, const int* __restrict__ col_c, const double* __restrict__ col_w,
+    const Region* __restrict__ reg, int n_reg, const double4* __restrict__ cen, const int4* __restrict__ pbox,
     unsigned long long* __restrict__ Kfx) {
   __shared__ double rcx[MAX_REGIONS], rcy[MAX_REGIONS], rcz[MAX_REGIONS], rcos[MAX_REGIONS],
-      rscal[MAX_REGIONS];
+      rscal[MAX_REGIONS], rreach[MAX_REGIONS];
   __shared__ double s_mub[MAX_MU];
   __shared__ int rtype[MAX_REGIONS];
-  __shared__ int box[4];
+  __shared__ unsigned long long s_tab[WEIGHT_WAVES][3 * MAX_MU];  // per-wave column table
 
   const int ph = blockIdx.x / n_slabs;
   const int slab = blockIdx.x - ph * n_slabs;
@@ -194,72 +238,65 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int GJ = G * J;
-  const double phase = phases[ph];
   const double area = (2.0 / N) * (2.0 / N);
 
+  // uniform: the slab's part of the phase's bounding box
+  const int4 bx = pbox[ph];
+  const int i0 = max(bx.x, slab * SLAB_COLS);
+  const int i1 = min(bx.y, min(N, (slab + 1) * SLAB_COLS) - 1);
+  const int k0 = bx.z, k1 = bx.w;
+  if (i0 > i1 || k0 > k1) return;  // nothing of this slab is covered
   for (int b = threadIdx.x; b < B; b += blockDim.x) s_mub[b] = mu_b[b];
   if (threadIdx.x < n_reg) {
-    const Region r = reg[threadIdx.x];
-    double cx, cy, cz;
-    region_centre(r.lat_deg, r.lon_deg, phase, incl, &cx, &cy, &cz);
-    rcx[threadIdx.x] = cx;
-    rcy[threadIdx.x] = cy;
-    rcz[threadIdx.x] = cz;
-    {
-#pragma clang fp contract(off)
-      rcos[threadIdx.x] = sqrt(1.0 - r.radius * r.radius);
-    }
-    rtype[threadIdx.x] = r.type;
-    rscal[threadIdx.x] = (!paired && effect != SOAP_EFFECT_BCONV) ? r.contrast : 1.0;
+    const double4 c4 = cen[(int64_t)ph * n_reg + threadIdx.x];
+    rcx[threadIdx.x] = c4.x;
+    rcy[threadIdx.x] = c4.y;
+    rcz[threadIdx.x] = c4.z;
+    rcos[threadIdx.x] = c4.w;
+    rtype[threadIdx.x] = reg[threadIdx.x].type;
+    rscal[threadIdx.x] = (!paired && effect != SOAP_EFFECT_BCONV) ? reg[threadIdx.x].contrast : 1.0;
+    // projected reach of the cap around its centre, or -1 when the cap
+    // cannot reach the visible hemisphere (the bounding-box rule)
+    const double rad = sqrt(fmax(0.0, 1.0 - c4.w * c4.w));
+    rreach[threadIdx.x] = (c4.z <= -rad - 1e-12) ? -1.0 : sqrt(fmax(0.0, 2.0 - 2.0 * c4.w)) + 1e-9;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // bounding box of the caps that reach the visible hemisphere; a cap
-    // point p satisfies |p - c| <= 2 sin(alpha / 2) = sqrt(2 - 2 cos alpha),
-    // which bounds its projected distance from the centre
-    double xlo = 2.0, xhi = -2.0, ylo = 2.0, yhi = -2.0;
-    for (int r = 0; r < n_reg; ++r) {
-      double rad = sqrt(fmax(0.0, 1.0 - rcos[r] * rcos[r]));
-      if (rcz[r] <= -rad - 1e-12) continue;
-      double d = sqrt(fmax(0.0, 2.0 - 2.0 * rcos[r])) + 1e-9;
-      xlo = fmin(xlo, rcx[r] - d);
-      xhi = fmax(xhi, rcx[r] + d);
-      ylo = fmin(ylo, rcy[r] - d);
-      yhi = fmax(yhi, rcy[r] + d);
-    }
-    int i0 = (int)floor((xlo + 1.0) * 0.5 * N) - 1;
-    int i1 = (int)ceil((xhi + 1.0) * 0.5 * N) + 1;
-    int k0 = (int)floor((ylo + 1.0) * 0.5 * N) - 1;
-    int k1 = (int)ceil((yhi + 1.0) * 0.5 * N) + 1;
-    i0 = max(i0, slab * SLAB_COLS);
-    i1 = min(i1, min(N, (slab + 1) * SLAB_COLS) - 1);
-    box[0] = i0;
-    box[1] = i1;
-    box[2] = max(k0, 0);
-    box[3] = min(k1, N - 1);
-  }
-  __syncthreads();
-  const int i0 = box[0], i1 = box[1], k0 = box[2], k1 = box[3];
-  if (i0 > i1 || k0 > k1) return;  // uniform: nothing of this slab is covered
   unsigned long long* Kph = Kfx + (int64_t)ph * GJ;
+  unsigned long long* tab = s_tab[wave];
 
   for (int i = i0 + wave; i <= i1; i += nw) {
     const double x = cell_coord(i, N);
+    // rows of this column that any cap can reach: the hull of the chords of
+    // the discs of radius reach around the projected centres
+    double ylo = 2.0, yhi = -2.0;
+    for (int r = 0; r < n_reg; ++r) {
+      const double d = rreach[r];
+      const double dx = x - rcx[r];
+      if (d < 0.0 || fabs(dx) > d) continue;
+      const double h = sqrt(fmax(0.0, d * d - dx * dx));
+      ylo = fmin(ylo, rcy[r] - h);
+      yhi = fmax(yhi, rcy[r] + h);
+    }
+    if (ylo > yhi) continue;  // uniform
+    const int kc0 = max(k0, (int)floor((ylo + 1.0) * 0.5 * N) - 1);
+    const int kc1 = min(k1, (int)ceil((yhi + 1.0) * 0.5 * N) + 1);
     const int ci = col_c[i];
     const double wi = col_w[i];
     const int ja = ci - jmin, jb = ci - 1 - jmin;
-    for (int kbase = k0; kbase <= k1; kbase += 64 * MAXC) {
+    for (int e = lane; e < G; e += 64) tab[e] = 0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int kbase = kc0; kbase <= kc1; kbase += 64 * MAXC) {
       int cb[MAXC];     // bin | (type << 8), or -1 when not active
       double cw[MAXC];  // A I(mu)
       double cs[MAXC];  // owner contrast scale
-      unsigned long long m1 = 0, m2 = 0;
 #pragma unroll
       for (int q = 0; q < MAXC; ++q) {
         cb[q] = -1;
         cw[q] = 0.0;
         cs[q] = 0.0;
         const int k = kbase + lane + 64 * q;
-        if (k <= k1) {
+        if (k <= kc1) {
           const double y = cell_coord(k, N);
           double r2;
           {
@@ -283,32 +320,31 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
               cb[q] = b | (t << 8);
               cw[q] = area * limb_dark(mu, u1, u2);
               cs[q] = rscal[own];
-              if (t == SOAP_SPOT) m1 |= 1ull << b;
-              else m2 |= 1ull << b;
             }
           }
         }
       }
-      m1 = wave_or64(m1);
-      m2 = wave_or64(m2);
-      const unsigned long long m0 = paired ? 0ull : (m1 | m2);
-      if (!(m1 | m2)) continue;  // uniform
-      // one (type, bin) slot at a time, in a fixed order: removal bins
-      // (split tables), then spot bins, then facula bins
-      for (int tt = paired ? 1 : 0; tt <= 2; ++tt) {
-        unsigned long long mt = (tt == 0) ? m0 : (tt == 1 ? m1 : m2);
-        while (mt) {
-          const int tb = __builtin_ctzll(mt);
-          mt &= mt - 1;
+      // Each lane sums its own cells per table row (FP32 + Kahan in the
+      // FP32 mode, FP64 otherwise) and adds each sum to the wave's column
+      // table as an exact fixed-point integer, so the column totals do not
+      // depend on the order of the lanes.  Split tables also give every
+      // active cell a removal entry (row = bin, weight -A I).
+#pragma unroll
+      for (int q = 0; q < MAXC; ++q) {
+        if (cb[q] < 0) continue;
+        const int tb = cb[q] & 0xff, tt = cb[q] >> 8;
+        // active entry: first cell of this lane with this (type, bin)
+        bool first = true;
+#pragma unroll
+        for (int q2 = 0; q2 < q; ++q2) first = first && cb[q2] != cb[q];
+        if (first) {
           double part;
           if (KAHAN32) {
             float acc = 0.f, comp = 0.f;
 #pragma unroll
-            for (int q = 0; q < MAXC; ++q) {
-              const bool hit = cb[q] >= 0 && (cb[q] & 0xff) == tb && (tt == 0 || (cb[q] >> 8) == tt);
-              if (hit) {
-                const float val = (tt == 0) ? -(float)cw[q] : (float)(cw[q] * cs[q]);
-                const float yk = val - comp;
+            for (int q2 = q; q2 < MAXC; ++q2) {
+              if (cb[q2] == cb[q]) {
+                const float yk = (float)(cw[q2] * cs[q2]) - comp;
                 const float tk = acc + yk;
                 comp = (tk - acc) - yk;
                 acc = tk;
@@ -318,37 +354,77 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
           } else {
             double acc = 0.0;
 #pragma unroll
-            for (int q = 0; q < MAXC; ++q) {
-              const bool hit = cb[q] >= 0 && (cb[q] & 0xff) == tb && (tt == 0 || (cb[q] >> 8) == tt);
-              if (hit) acc += (tt == 0) ? -cw[q] : cw[q] * cs[q];
-            }
+            for (int q2 = q; q2 < MAXC; ++q2)
+              if (cb[q2] == cb[q]) acc += cw[q2] * cs[q2];
             part = acc;
           }
-          const double W = wave_sum_f64(part);
-          if (lane == 0 && jb >= 0 && ja < J) {
-            const int g = paired ? (tt - 1) * B + tb : tt * B + tb;
-            // exact, order-free accumulation: fixed point with 2^-61 units
-            unsigned long long* kr = Kph + g * J;
-            atomicAdd(kr + ja, to_fx((1.0 - wi) * W));
-            atomicAdd(kr + jb, to_fx(wi * W));
+          const int g = paired ? (tt - 1) * B + tb : tt * B + tb;
+          atomicAdd(&tab[g], to_fx(part));
+        }
+        if (!paired) {
+          // removal entry: first active cell of this lane in this bin
+          bool firstb = true;
+#pragma unroll
+          for (int q2 = 0; q2 < q; ++q2) firstb = firstb && (cb[q2] < 0 || (cb[q2] & 0xff) != tb);
+          if (firstb) {
+            double part;
+            if (KAHAN32) {
+              float acc = 0.f, comp = 0.f;
+#pragma unroll
+              for (int q2 = q; q2 < MAXC; ++q2) {
+                if (cb[q2] >= 0 && (cb[q2] & 0xff) == tb) {
+                  const float yk = -(float)cw[q2] - comp;
+                  const float tk = acc + yk;
+                  comp = (tk - acc) - yk;
+                  acc = tk;
+                }
+              }
+              part = (double)acc - (double)comp;
+            } else {
+              double acc = 0.0;
+#pragma unroll
+              for (int q2 = q; q2 < MAXC; ++q2)
+                if (cb[q2] >= 0 && (cb[q2] & 0xff) == tb) acc -= cw[q2];
+              part = acc;
+            }
+            atomicAdd(&tab[tb], to_fx(part));
           }
         }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // the column's sums, split onto the two integer offsets of its shift
+    // (1 - w at j = c, w at j = c - 1: Eq. 11), go to the phase's table
+    if (jb >= 0 && ja < J) {
+      for (int e = lane; e < G; e += 64) {
+        const long long v = (long long)tab[e];
+        if (v == 0) continue;
+        const double W = (double)v * FX_INV;
+        unsigned long long* kr = Kph + e * J;
+        atomicAdd(kr + ja, to_fx((1.0 - wi) * W));
+        atomicAdd(kr + jb, to_fx(wi * W));
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
                           const WeightsOut& o) {
+  hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, c->stream, c->N, n_reg,
+                     pl.n_ph, c->incl, d_reg, d_ph, o.reg, o.cen, o.box);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   dim3 grid((unsigned)pl.n_slabs * (unsigned)pl.n_ph);
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, c->stream, c->N, c->B, c->J, c->jmin,
-                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu,
-                       c->d_col_c, c->d_col_w, d_reg, n_reg, d_ph, o.Kfx);
+                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
+                       o.reg, n_reg, o.cen, o.box, o.Kfx);
   else
     hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * WEIGHT_WAVES), 0, c->stream, c->N, c->B, c->J, c->jmin,
-                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, c->incl, pl.effect, c->cmode, c->d_mu,
-                       c->d_col_c, c->d_col_w, d_reg, n_reg, d_ph, o.Kfx);
+                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
+                       o.reg, n_reg, o.cen, o.box, o.Kfx);
   return hipGetLastError();
 }
 
