@@ -45,8 +45,8 @@ __global__ void k_mask_prep(int n, double ln0, double dln, double P, const doubl
 // One block per (64 mask lines, 8 spectra).  The block's lines go to LDS
 // and are split once into batches whose holes, at any trial velocity, reach
 // a pixel span that fits the LDS stage.  Batch by batch the span of the
-// block's spectra is staged in double (coalesced loads; the next batch's
-// loads are in flight in registers while the current one is used), then one
+// block's spectra is staged in double (coalesced loads; the next two
+// batches' loads are in flight in registers while one is used), then one
 // thread per velocity computes each hole's pixel overlaps once and applies
 // them to every staged spectrum, accumulating in double.
 template <typename T, int A, int NPX>
@@ -55,6 +55,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
                                                      double v0, double dv, double h, double dln,
                                                      double* __restrict__ part) {
   constexpr int U = (CCF_SPAN + CCF_THREADS - 1) / CCF_THREADS;  // staged elements per thread and spectrum
+  constexpr int UNR = A * NPX <= 10 ? NPX : 1;                   // unrolled hole pixels
   __shared__ double st[CCF_SB][CCF_SPAN];
   __shared__ double2 s_mask[CCF_LINES];
   __shared__ int s_lo[CCF_LINES], s_len[CCF_LINES], s_end[CCF_LINES];
@@ -108,8 +109,11 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
   }
   __syncthreads();
   const int nb = s_nb;
-  T vals[CCF_SB][U];
-  auto load = [&](int bi) {
+  // two batches in flight: while batch bi is used, the loads of bi + 1 and
+  // bi + 2 are outstanding in two register buffers
+  T va[CCF_SB][U], vb[CCF_SB][U];
+  auto load = [&](T (&vals)[CCF_SB][U], int bi) {
+    if (bi >= nb) return;
     const int lo = s_lo[bi];
     const int len = s_len[bi];
 #pragma unroll
@@ -123,8 +127,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
       }
     }
   };
-  load(0);
-  for (int bi = 0; bi < nb; ++bi) {
+  auto batch = [&](T (&vals)[CCF_SB][U], int bi) {
     const int lo = s_lo[bi];
     const int len = s_len[bi];
     const int lbeg = bi ? s_end[bi - 1] : 0;
@@ -138,7 +141,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
         if (i < len) st[s][i] = (double)vals[s][u];
       }
     __syncthreads();
-    if (bi + 1 < nb) load(bi + 1);
+    load(vals, bi + 2);
     for (int l = lbeg; l < lend; ++l) {
       const double2 mw = s_mask[l];
 #pragma unroll
@@ -150,7 +153,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
         const int ma = (int)floor(qlo);
         // a hole narrower than NPX - 1 pixels meets at most NPX pixels; the
         // pixels past its end get a zero weight (an exact no-op)
-#pragma unroll(A * NPX <= 10 ? NPX : 1)
+#pragma unroll UNR
         for (int px = 0; px < NPX; ++px) {
           const int m = ma + px;
           const double ov = fmin(qhi, (double)(m + 1)) - fmax(qlo, (double)m);
@@ -163,6 +166,12 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
         }
       }
     }
+  };
+  load(va, 0);
+  load(vb, 1);
+  for (int bi = 0; bi < nb; bi += 2) {
+    batch(va, bi);
+    if (bi + 1 < nb) batch(vb, bi + 1);
   }
 #pragma unroll
   for (int a = 0; a < A; ++a) {
