@@ -150,17 +150,18 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
         if (k >= n_v) break;
         const double qlo = mw.x + alo[a];
         const double qhi = mw.x + ahi[a];
-        const int ma = (int)floor(qlo);
-        // a hole narrower than NPX - 1 pixels meets at most NPX pixels; the
-        // pixels past its end get a zero weight (an exact no-op)
+        const double fa = floor(qlo);
+        const int i0 = (int)fa - lo;  // stage index of the first pixel
+        // A hole narrower than NPX - 1 pixels meets at most NPX pixels; the
+        // pixels past its end get a zero weight (an exact no-op).  Pixels
+        // outside the spectrum are staged as zeros, and the first pixel's
+        // lower edge is the hole's (every later pixel starts inside it).
 #pragma unroll UNR
         for (int px = 0; px < NPX; ++px) {
-          const int m = ma + px;
-          const double ov = fmin(qhi, (double)(m + 1)) - fmax(qlo, (double)m);
-          const int i = m - lo;
-          const bool use = ov > 0.0 && m >= 0 && m < P && (unsigned)i < (unsigned)len;
-          const double wo = use ? mw.y * ov : 0.0;
-          const int ii = use ? i : 0;
+          const double mlo = fa + (double)px;
+          const double ov = fmin(qhi, mlo + 1.0) - (px == 0 ? qlo : mlo);
+          const double wo = mw.y * fmax(ov, 0.0);
+          const int ii = min(i0 + px, len - 1);
 #pragma unroll
           for (int s = 0; s < CCF_SB; ++s) acc[a][s] = fma(wo, st[s][ii], acc[a][s]);
         }
