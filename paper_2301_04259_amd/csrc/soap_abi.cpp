@@ -125,15 +125,24 @@ void free_ws(soap::Workspace& w) {
 
 void destroy_ctx(soap_ctx* c) {
   if (!c) return;
-  if (c->hip_used) (void)hipStreamSynchronize(c->stream);
+  if (c->hip_used) {
+    (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+  }
   for (int t = 0; t < 3; ++t)
     if (c->d_spec_base[t]) (void)hipFree(c->d_spec_base[t]);
   void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base, c->d_ones};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
-  soap::Workspace* ws[] = {&c->ws_par, &c->ws_Kfx, &c->ws_mask64, &c->ws_K, &c->ws_vg, &c->ws_nvg, &c->ws_flux,
-                           &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
+  soap::Workspace* ws[] = {&c->ws_flux, &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
   for (auto* w : ws) free_ws(*w);
+  for (auto& S : c->prep) {
+    soap::Workspace* pw[] = {&S.par, &S.Kfx, &S.K, &S.mask64, &S.vg, &S.nvg};
+    for (auto* w : pw) free_ws(*w);
+    if (S.prep_done) (void)hipEventDestroy(S.prep_done);
+    if (S.apply_done) (void)hipEventDestroy(S.apply_done);
+  }
+  if (c->side) (void)hipStreamDestroy(c->side);
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -215,6 +224,11 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   }
   HIP_TRY(hipEventCreateWithFlags(&c->pinned_done, hipEventDisableTiming));
   for (int k = 0; k < soap_ctx::NSLOT; ++k) HIP_TRY(hipEventCreateWithFlags(&c->slot_done[k], hipEventDisableTiming));
+  HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  for (auto& S : c->prep) {
+    HIP_TRY(hipEventCreateWithFlags(&S.prep_done, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&S.apply_done, hipEventDisableTiming));
+  }
 
   HIP_TRY(soap::launch_pad(c));
   HIP_TRY(soap::launch_geom(c));
@@ -250,14 +264,15 @@ soap_status stage_to_device(soap_ctx* c, const void* src, size_t bytes, void* ds
 struct StageTimer {
   soap_ctx* c;
   int stage;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  StageTimer(soap_ctx* c_, int s) : c(c_), stage(s) {
-    if (c->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, c->stream);
+  StageTimer(soap_ctx* c_, int s, hipStream_t st_ = nullptr) : c(c_), stage(s), st(st_ ? st_ : c_->stream) {
+    if (c->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
   }
   void done() {
     if (!a) return;
     hipEvent_t b = nullptr;
-    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, c->stream) == hipSuccess) {
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st) == hipSuccess) {
       c->pending.push_back({stage, a, b});
     } else {
       (void)hipEventDestroy(a);
@@ -385,21 +400,40 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   // weights kernel reads it in place
   const size_t reg_bytes = sizeof(soap::Region) * soap::MAX_REGIONS;
   const size_t par_bytes = reg_bytes + sizeof(double) * n_phases;
-  {
+  // this call's table set; its kernels run on the side stream after the
+  // apply that last read the set (two calls ago) is done
+  const int sidx = c->prep_next;
+  soap_ctx::PrepSet& S = c->prep[sidx];
+  c->prep_next ^= 1;
+  const size_t reg_dev = 256 * ((sizeof(soap::Region) * soap::MAX_REGIONS + 255) / 256);
+  const size_t cen_dev = 256 * ((sizeof(double4) * (size_t)n_phases * std::max(1, n_regions) + 255) / 256);
+  const size_t par_dev = reg_dev + cen_dev + sizeof(int4) * (size_t)n_phases;
+  const size_t kfx_bytes = sizeof(unsigned long long) * (size_t)n_phases * GJ;
+  const size_t k_bytes = sizeof(double) * (size_t)n_phases * GJ;
+  const size_t m_bytes = sizeof(unsigned long long) * (size_t)n_phases * pl.G;
+  const size_t vg_bytes = (size_t)soap::WIN_BYTES * pl.n_chunks * pl.vg_cap;
+  const size_t nvg_bytes = sizeof(int) * (size_t)pl.n_chunks;
+  const bool regrow = S.par.bytes < par_dev || S.Kfx.bytes < kfx_bytes || S.K.bytes < k_bytes ||
+                      S.mask64.bytes < m_bytes || S.vg.bytes < vg_bytes || S.nvg.bytes < nvg_bytes;
+  if (regrow) {
+    // buffers are replaced only with both streams idle
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipStreamSynchronize(c->side));
+    HIP_TRY(grow(S.par, par_dev));
+    HIP_TRY(grow(S.K, k_bytes));
+    HIP_TRY(grow(S.mask64, m_bytes));
+    HIP_TRY(grow(S.vg, vg_bytes));
+    HIP_TRY(grow(S.nvg, nvg_bytes));
+  }
+  HIP_TRY(hipStreamWaitEvent(c->side, S.apply_done, 0));
+  if (S.Kfx.bytes < kfx_bytes || S.kfx_dirty) {
     // fixed-point tap accumulators: zero when allocated; every call that
     // accumulates also clears them, so they are zeroed again only after an
     // interrupted call
-    const size_t kfx_bytes = sizeof(unsigned long long) * (size_t)n_phases * GJ;
-    if (c->ws_Kfx.bytes < kfx_bytes || c->kfx_dirty) {
-      HIP_TRY(grow(c->ws_Kfx, kfx_bytes));
-      HIP_TRY(hipMemsetAsync(c->ws_Kfx.ptr, 0, c->ws_Kfx.bytes, c->stream));
-      c->kfx_dirty = false;
-    }
+    HIP_TRY(grow(S.Kfx, kfx_bytes));
+    HIP_TRY(hipMemsetAsync(S.Kfx.ptr, 0, S.Kfx.bytes, c->side));
+    S.kfx_dirty = false;
   }
-  HIP_TRY(grow(c->ws_K, sizeof(double) * (size_t)n_phases * GJ));
-  HIP_TRY(grow(c->ws_mask64, sizeof(unsigned long long) * (size_t)n_phases * pl.G));
-  HIP_TRY(grow(c->ws_vg, (size_t)soap::WIN_BYTES * pl.n_chunks * pl.vg_cap));
-  HIP_TRY(grow(c->ws_nvg, sizeof(int) * (size_t)pl.n_chunks));
   const size_t out_bytes = (size_t)n_phases * c->P * c->esize;
   void* dflux = flux;
   if (!flux_on_device) {
@@ -433,36 +467,37 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   const soap::Region* d_reg = static_cast<const soap::Region*>(dev_view);
   const double* d_ph = reinterpret_cast<const double*>(static_cast<const unsigned char*>(dev_view) + reg_bytes);
 
-  const size_t reg_dev = 256 * ((sizeof(soap::Region) * soap::MAX_REGIONS + 255) / 256);
-  const size_t cen_dev = 256 * ((sizeof(double4) * (size_t)n_phases * std::max(1, n_regions) + 255) / 256);
-  HIP_TRY(grow(c->ws_par, reg_dev + cen_dev + sizeof(int4) * (size_t)n_phases));
   soap::WeightsOut wo;
-  wo.reg = static_cast<soap::Region*>(c->ws_par.ptr);
-  wo.cen = reinterpret_cast<double4*>(static_cast<unsigned char*>(c->ws_par.ptr) + reg_dev);
-  wo.box = reinterpret_cast<int4*>(static_cast<unsigned char*>(c->ws_par.ptr) + reg_dev + cen_dev);
-  wo.Kfx = static_cast<unsigned long long*>(c->ws_Kfx.ptr);
-  wo.K = static_cast<double*>(c->ws_K.ptr);
-  wo.mask = static_cast<unsigned long long*>(c->ws_mask64.ptr);
-  wo.wins = static_cast<unsigned char*>(c->ws_vg.ptr);
-  wo.nvg = static_cast<int*>(c->ws_nvg.ptr);
-  c->kfx_dirty = true;
+  wo.reg = static_cast<soap::Region*>(S.par.ptr);
+  wo.cen = reinterpret_cast<double4*>(static_cast<unsigned char*>(S.par.ptr) + reg_dev);
+  wo.box = reinterpret_cast<int4*>(static_cast<unsigned char*>(S.par.ptr) + reg_dev + cen_dev);
+  wo.Kfx = static_cast<unsigned long long*>(S.Kfx.ptr);
+  wo.K = static_cast<double*>(S.K.ptr);
+  wo.mask = static_cast<unsigned long long*>(S.mask64.ptr);
+  wo.wins = static_cast<unsigned char*>(S.vg.ptr);
+  wo.nvg = static_cast<int*>(S.nvg.ptr);
+  S.kfx_dirty = true;
   {
-    StageTimer t(c, ST_WEIGHTS);
-    HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, d_ph, wo));
+    StageTimer t(c, ST_WEIGHTS, c->side);
+    HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, d_ph, wo, c->side));
     t.done();
   }
-  HIP_TRY(hipEventRecord(c->slot_done[k], c->stream));
+  HIP_TRY(hipEventRecord(c->slot_done[k], c->side));
   {
-    StageTimer t(c, ST_COMPACT);
-    HIP_TRY(soap::launch_finish(c, pl, wo));
+    StageTimer t(c, ST_COMPACT, c->side);
+    HIP_TRY(soap::launch_finish(c, pl, wo, c->side));
     t.done();
   }
-  c->kfx_dirty = false;
+  S.kfx_dirty = false;
+  HIP_TRY(hipEventRecord(S.prep_done, c->side));
+  HIP_TRY(hipStreamWaitEvent(c->stream, S.prep_done, 0));
   {
     StageTimer t(c, ST_APPLY);
-    HIP_TRY(soap::launch_apply(c, pl, c->ws_vg.ptr, static_cast<const int*>(c->ws_nvg.ptr), dflux));
+    HIP_TRY(soap::launch_apply(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), dflux));
     t.done();
   }
+  HIP_TRY(hipEventRecord(S.apply_done, c->stream));
+  c->last_prep = sidx;
   c->active_calls++;
   c->last_phases = n_phases;
   c->last_effect = effect;
@@ -592,6 +627,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
 
 SOAP_API soap_status soap_profile_enable(soap_ctx* c, int32_t on) {
   if (!c) return SOAP_ERR_ARG;
+  HIP_TRY(hipStreamSynchronize(c->side));
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (auto& p : c->pending) {
     (void)hipEventDestroy(p.a);
@@ -608,6 +644,7 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
   if (!c) return SOAP_ERR_ARG;
   std::string& err = c->err;
   ARG_CHECK(out != nullptr, "out is NULL");
+  HIP_TRY(hipStreamSynchronize(c->side));
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (auto& p : c->pending) {
     float ms = 0.f;
@@ -631,8 +668,9 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
     const int n_chunks = (c->last_phases + c->pc - 1) / c->pc;
     std::vector<int> nvg(n_chunks);
     std::vector<unsigned char> vg((size_t)n_chunks * c->last_vg_cap * soap::WIN_BYTES);
-    HIP_TRY(hipMemcpy(nvg.data(), c->ws_nvg.ptr, sizeof(int) * n_chunks, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(vg.data(), c->ws_vg.ptr, vg.size(), hipMemcpyDeviceToHost));
+    const soap_ctx::PrepSet& S = c->prep[c->last_prep];
+    HIP_TRY(hipMemcpy(nvg.data(), S.nvg.ptr, sizeof(int) * n_chunks, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(vg.data(), S.vg.ptr, vg.size(), hipMemcpyDeviceToHost));
     std::vector<char> src(3 * c->B, 0), con(3 * c->B, 0);
     const bool planck = c->cmode == SOAP_CONTRAST_PLANCK;
     for (int ch = 0; ch < n_chunks; ++ch)
@@ -658,6 +696,7 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
 
 SOAP_API soap_status soap_sync(soap_ctx* c) {
   if (!c) return SOAP_ERR_ARG;
+  HIP_TRY(hipStreamSynchronize(c->side));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return SOAP_OK;
 }

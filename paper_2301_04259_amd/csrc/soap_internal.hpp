@@ -119,13 +119,24 @@ struct soap_ctx {
   void* d_ones = nullptr;                          // [n_tiles * TILE] of 1 (no-contrast operand)
 
   // per-call workspace (grown on demand, freed by soap_destroy)
-  soap::Workspace ws_par;      // regions, per-phase region centres and bounding boxes
-  soap::Workspace ws_Kfx;      // [n_phases][G][J] fixed-point tap accumulators (kept zero)
-  bool kfx_dirty = false;      // a call stopped between accumulation and clearing
-  soap::Workspace ws_K;        // [n_phases][G][J] double
-  soap::Workspace ws_mask64;   // [n_phases][G] bitmask of nonzero offsets
-  soap::Workspace ws_vg;       // [n_chunks][vg_cap] window records (WIN_BYTES each)
-  soap::Workspace ws_nvg;      // [n_chunks] int
+  // Per-call tables (region parameters, tap accumulators and taps, window
+  // records), in two sets used by alternate calls.  Their kernels run on
+  // the side stream, so the tables of the next call are built while the
+  // context stream still runs the previous call's later stages.
+  struct PrepSet {
+    soap::Workspace par;     // regions, per-phase region centres and bounding boxes
+    soap::Workspace Kfx;     // [n_phases][G][J] fixed-point tap accumulators (kept zero)
+    soap::Workspace K;       // [n_phases][G][J] double
+    soap::Workspace mask64;  // [n_phases][G] bitmask of nonzero offsets
+    soap::Workspace vg;      // [n_chunks][vg_cap] window records (WIN_BYTES each)
+    soap::Workspace nvg;     // [n_chunks] int
+    bool kfx_dirty = false;  // a call stopped between accumulation and clearing
+    hipEvent_t prep_done = nullptr;   // side stream: this set's tables are built
+    hipEvent_t apply_done = nullptr;  // context stream: the apply that read them is done
+  };
+  PrepSet prep[2];
+  int prep_next = 0, last_prep = 0;
+  hipStream_t side = nullptr;  // stream of the per-call table kernels
   soap::Workspace ws_flux;     // host-output staging for fluxes
   soap::Workspace ws_ccf;      // partial CCFs
   soap::Workspace ws_ccfout;   // [n_spec][n_v] double
@@ -195,8 +206,8 @@ struct WeightsOut {
   int* nvg;                  // [n_chunks] windows per chunk
 };
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
-                          const WeightsOut& o);
-hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o);
+                          const WeightsOut& o, hipStream_t st);
+hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o, hipStream_t st);
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,

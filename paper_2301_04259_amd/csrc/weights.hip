@@ -52,12 +52,13 @@ __device__ __forceinline__ unsigned long long to_fx(double x) {
 
 // Window records of one chunk of PC phases (one block): windows of APPLY_JW
 // offsets with their dense [offset][phase] taps and per-offset masks of the
-// groups of four phases that have a tap.  sm: LDS of at least
+// groups of four phases that have a tap.  Kc: the chunk's taps [np][G][J],
+// maskc: its offset masks [np][G] (LDS or global).  sm: LDS of at least
 // (4 G + vg_cap + 2) ints + G 64-bit words.
 template <typename T>
 __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmin, int B, int paired,
-                              const double* __restrict__ K, const unsigned long long* __restrict__ mask,
-                              unsigned char* __restrict__ wins, int* __restrict__ nvg, int vg_cap, int* sm) {
+                              const double* Kc, const unsigned long long* maskc, unsigned char* __restrict__ wins,
+                              int* __restrict__ nvg, int vg_cap, int* sm) {
   int* s_cnt = sm;           // [G] windows per group
   int* s_base = sm + G;      // [G] first window index
   int* s_lo = sm + 2 * G;    // [G] first non-zero offset of the union
@@ -75,7 +76,7 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
     unsigned long long u = 0;
 #pragma unroll
     for (int p = 0; p < PC_MAX; ++p)
-      if (p < np) u |= mask[(int64_t)(p0 + p) * G + g];
+      if (p < np) u |= maskc[p * G + g];
     int cnt = 0, lo = 0;
     if (u) {
       lo = __builtin_ctzll(u);
@@ -124,7 +125,7 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
     double kv[PC_MAX];
 #pragma unroll
     for (int p = 0; p < PC_MAX; ++p)
-      kv[p] = (p < np && a + q < J) ? K[(int64_t)(p0 + p) * GJ + g * J + a + q] : 0.0;
+      kv[p] = (p < np && a + q < J) ? Kc[p * GJ + g * J + a + q] : 0.0;
     unsigned int m = 0;
 #pragma unroll
     for (int p = 0; p < PC_MAX; ++p) {
@@ -144,35 +145,53 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
 // One block per chunk of PC phases: the phases' taps K[ph][g][j] from the
 // fixed-point accumulators (which are cleared for the next call), the
 // per-(phase, group) bitmask of non-zero offsets, then the chunk's window
-// records.
-template <typename T>
+// records.  With IN_LDS the chunk's taps and masks stay in LDS; otherwise
+// they go through K and mask in global memory.
+template <typename T, bool IN_LDS>
 __global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int G, int J, int jmin, int B,
                                                            int paired, int vg_cap,
                                                            unsigned long long* __restrict__ Kfx,
                                                            double* __restrict__ K,
                                                            unsigned long long* __restrict__ mask,
                                                            unsigned char* __restrict__ wins, int* __restrict__ nvg) {
-  extern __shared__ int sm[];
+  extern __shared__ __align__(16) unsigned char fin_lds[];
   const int chunk = blockIdx.x;
   const int p0 = chunk * PC;
   const int np = min(PC, n_ph - p0);
   const int GJ = G * J;
+  const int n = np * GJ;
   const int64_t base = (int64_t)p0 * GJ;
-  for (int t = threadIdx.x; t < np * GJ; t += blockDim.x) {
-    const long long v = (long long)Kfx[base + t];
-    Kfx[base + t] = 0ull;
-    K[base + t] = (double)v * FX_INV;
+  double* Kc = IN_LDS ? reinterpret_cast<double*>(fin_lds) : K + base;
+  unsigned long long* maskc =
+      IN_LDS ? reinterpret_cast<unsigned long long*>(fin_lds + (size_t)PC * GJ * sizeof(double)) : mask + (int64_t)p0 * G;
+  int* sm = reinterpret_cast<int*>(fin_lds + (IN_LDS ? (size_t)PC * (GJ + G) * sizeof(double) : 0));
+  // eight accumulators per thread and round, loaded together
+  for (int t0 = threadIdx.x; t0 < n; t0 += 8 * FINISH_THREADS) {
+    unsigned long long v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * FINISH_THREADS;
+      v[u] = t < n ? Kfx[base + t] : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u * FINISH_THREADS;
+      if (t < n) {
+        Kfx[base + t] = 0ull;
+        Kc[t] = (double)(long long)v[u] * FX_INV;
+      }
+    }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < np * G; t += blockDim.x) {
-    const double* kr = K + base + (int64_t)t * J;
+    const double* kr = Kc + (int64_t)t * J;
     unsigned long long mk = 0;
     for (int j = 0; j < J; ++j)
       if (kr[j] != 0.0) mk |= 1ull << j;
-    mask[(int64_t)p0 * G + t] = mk;
+    maskc[t] = mk;
   }
   __syncthreads();
-  compact_chunk<T>(chunk, n_ph, PC, G, J, jmin, B, paired, K, mask, wins, nvg, vg_cap, sm);
+  compact_chunk<T>(chunk, n_ph, PC, G, J, jmin, B, paired, Kc, maskc, wins, nvg, vg_cap, sm);
 }
 
 // Per phase (one thread each): every region centre rotated to the phase
@@ -411,32 +430,45 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
 }
 
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
-                          const WeightsOut& o) {
-  hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, c->stream, c->N, n_reg,
+                          const WeightsOut& o, hipStream_t st) {
+  hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, st, c->N, n_reg,
                      pl.n_ph, c->incl, d_reg, d_ph, o.reg, o.cen, o.box);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)pl.n_slabs * (unsigned)pl.n_ph);
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, c->stream, c->N, c->B, c->J, c->jmin,
+    hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, st, c->N, c->B, c->J, c->jmin,
                        pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
                        o.reg, n_reg, o.cen, o.box, o.Kfx);
   else
-    hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * WEIGHT_WAVES), 0, c->stream, c->N, c->B, c->J, c->jmin,
+    hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * WEIGHT_WAVES), 0, st, c->N, c->B, c->J, c->jmin,
                        pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
                        o.reg, n_reg, o.cen, o.box, o.Kfx);
   return hipGetLastError();
 }
 
-hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o) {
-  const size_t lds = (size_t)(6 * pl.G + pl.vg_cap + 2) * sizeof(int);
+hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o, hipStream_t st) {
+  const size_t cmp = (size_t)(6 * pl.G + pl.vg_cap + 2) * sizeof(int);
+  const size_t tab = (size_t)c->pc * ((size_t)pl.G * c->J + pl.G) * sizeof(double);
+  const bool in_lds = tab + cmp <= 60 * 1024;
+  const size_t lds = in_lds ? tab + cmp : cmp;
   if (lds > 60 * 1024) return hipErrorInvalidValue;
-  if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_finish<float>, dim3(pl.n_chunks), dim3(FINISH_THREADS), lds, c->stream, pl.n_ph, c->pc,
-                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
-  else
-    hipLaunchKernelGGL(k_finish<double>, dim3(pl.n_chunks), dim3(FINISH_THREADS), lds, c->stream, pl.n_ph, c->pc,
-                       pl.G, c->J, c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+  const dim3 grid(pl.n_chunks), block(FINISH_THREADS);
+  if (c->prec == SOAP_PREC_FP32) {
+    if (in_lds)
+      hipLaunchKernelGGL((k_finish<float, true>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J, c->jmin,
+                         c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+    else
+      hipLaunchKernelGGL((k_finish<float, false>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J,
+                         c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+  } else {
+    if (in_lds)
+      hipLaunchKernelGGL((k_finish<double, true>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J,
+                         c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+    else
+      hipLaunchKernelGGL((k_finish<double, false>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J,
+                         c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+  }
   return hipGetLastError();
 }
 
