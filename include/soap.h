@@ -188,6 +188,19 @@ soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device,
                         const soap_mask* mask, double* ccf_out, int32_t ccf_on_device,
                         soap_rv* rv_out, int32_t rv_on_device);
 
+/* Fits the CCFs of spectra written as a quiet part plus a linear
+ * combination of basis spectra, without forming the spectra: the CCF
+ * (section 4.1) is linear in the flux, so for F_i = F_0 + sum_k coef[i][k] B_k
+ *   CCF(F_i) = base[v] + sum_k coef[i][k] basis[k][v]
+ * with base = CCF(F_0) and basis[k] = CCF(B_k) on the context's current mask
+ * velocity grid (the last mask given to soap_ccf_rv, which must exist).
+ * The sum runs in double in increasing k, then each row is fitted as in
+ * soap_ccf_rv.  All arrays are device memory: coef[n][k] float,
+ * base[n_v] and basis[k][n_v] double, ccf_out[n][n_v] double (may be NULL),
+ * rv_out[n] (may be NULL).  n 1 .. 1<<24, k 1 .. 4096.  Enqueues only.     */
+soap_status soap_ccf_linear_rv(soap_ctx* ctx, const float* coef, int64_t n, int32_t k, const double* base,
+                               const double* basis, double* ccf_out, soap_rv* rv_out);
+
 /* Per-stage GPU time and traffic bookkeeping, for benchmarks.  With
  * profiling on, every stage kernel of soap_active_spectra and soap_ccf_rv is
  * bracketed by HIP events on the context's stream; soap_profile_read waits
@@ -227,6 +240,86 @@ const char* soap_status_string(soap_status status);
 
 /* SOAP_ABI_VERSION of the built library.                                      */
 int32_t soap_abi_version(void);
+
+/* ---- learned surrogate --------------------------------------------------
+ * Simulations at scale feed data-driven activity models (PCA of line-profile
+ * time series, neural networks on CCFs: section 1; section 5 invites such
+ * methods to train and test on simulated spectral series).  The surrogate
+ * stands in for the synthesis of one spectrum: a small ensemble of MLPs maps
+ * the parameters x[n_in] of a configuration (active region, phase) to the
+ * normalised PCA coefficients of its difference from the quiet spectrum,
+ * and the ensemble spread of the resulting RVs decides which samples go back
+ * to the full synthesis.
+ *
+ * Network of each member: SiLU(x W1 + b1) -> SiLU(. W2 + b2) -> . W3 + b3,
+ * W1 [n_in][hidden], W2 [hidden][hidden], W3 [hidden][n_out].  FP32 master
+ * parameters; the products run in BF16 on the matrix cores with FP32
+ * accumulation.  Loss: mean over batch and outputs of the squared error.
+ * Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected).
+ * Parameter vectors in the natural layout: W1, b1, W2, b2, W3, b3, each
+ * row-major, soap_surrogate_n_params floats per member.  Members start from
+ * Glorot-uniform weights drawn with SplitMix64 from (seed, member) and zero
+ * biases.  Every kernel adds in a fixed order: results repeat bit for bit.
+ * One surrogate is used by one host thread at a time; all its work runs on
+ * `hip_stream` (NULL = the null stream).                                    */
+typedef struct soap_surrogate soap_surrogate;
+
+/* n_in 1 .. 32; hidden and n_out multiples of 32 in [32, 4096];
+ * n_ensemble 1 .. 16.  On error *out is NULL.                                */
+soap_status soap_surrogate_create(int32_t n_in, int32_t hidden, int32_t n_out, int32_t n_ensemble,
+                                  uint64_t seed, void* hip_stream, soap_surrogate** out);
+
+/* Parameters per member in the natural layout (-1 for NULL).                 */
+int64_t soap_surrogate_n_params(const soap_surrogate* s);
+
+/* One Adam step of every member on the same batch: x[batch][n_in] and
+ * targets y[batch][n_out], device float arrays; batch a multiple of 32 in
+ * [32, 1<<20].  loss_out (host, may be NULL) receives the members' mean loss
+ * before the step and makes the call wait for the stream.                   */
+soap_status soap_surrogate_train_step(soap_surrogate* s, const float* x, const float* y, int32_t batch, float lr,
+                                      float* loss_out);
+
+/* Forward pass of every member: coef[batch][n_out] = ensemble mean,
+ * members[n_ensemble][batch][n_out] = each member's output (may be NULL).
+ * Device float arrays; batch a multiple of 16 in [16, 1<<20].  Enqueues
+ * only.                                                                      */
+soap_status soap_surrogate_predict(soap_surrogate* s, const float* x, int32_t batch, float* coef, float* members);
+
+/* Copy one member's parameters, or its gradients from the last train step
+ * (before that step's update), to / from a host array of n_params floats.
+ * These wait for the stream.                                                 */
+soap_status soap_surrogate_get_params(const soap_surrogate* s, int32_t member, float* out);
+soap_status soap_surrogate_set_params(soap_surrogate* s, int32_t member, const float* in);
+soap_status soap_surrogate_get_grads(const soap_surrogate* s, int32_t member, float* out);
+
+/* Checkpoint of parameters, Adam moments and step count; load requires a
+ * surrogate of the same shape and restores it bit for bit.                  */
+soap_status soap_surrogate_save(const soap_surrogate* s, const char* path);
+soap_status soap_surrogate_load(soap_surrogate* s, const char* path);
+
+/* Message of the last failing call on s.                                     */
+const char* soap_surrogate_last_error(const soap_surrogate* s);
+
+/* Frees s (waits for its stream).  NULL is a no-op.                          */
+void soap_surrogate_destroy(soap_surrogate* s);
+
+/* Projection onto a PCA basis: coef[i][j] = sum_p (d[i][p] - mean[p]) V[p][j]
+ * for i < n, j < k, in FP32.  d rows have stride ld >= n_pix floats; all
+ * arrays are device memory.  n 1 .. 2^25, k 1 .. 4096.  Enqueues on
+ * hip_stream.                                                                */
+soap_status soap_pca_project(const float* d, int64_t n, int64_t n_pix, int64_t ld, const float* mean,
+                             const float* V, int32_t k, float* coef, void* hip_stream);
+
+/* Ensemble gate.  rv[(1 + n_ens) n] (device) holds the fits of the
+ * ensemble-mean prediction (rows 0 .. n-1) and then of member e (rows
+ * (1 + e) n ..).  For sample i: rv_kms[i] = the mean prediction's RV,
+ * err_kms[i] = calib * the sample standard deviation of the members' RVs,
+ * fallback[i] = 1 when err_kms[i] >= threshold_kms or any of its fits did
+ * not converge, else 0 (threshold 0 sends every sample to the full
+ * synthesis).  n_ens 2 .. 16; device outputs (err_kms may be NULL).
+ * Enqueues on hip_stream.                                                    */
+soap_status soap_surrogate_gate(const soap_rv* rv, int64_t n, int32_t n_ens, double calib, double threshold_kms,
+                                double* rv_kms, double* err_kms, int32_t* fallback, void* hip_stream);
 
 #ifdef __cplusplus
 }

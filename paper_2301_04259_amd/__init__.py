@@ -65,6 +65,20 @@ SYMBOLS = (
     "soap_abi_version",
     "soap_profile_enable",
     "soap_profile_read",
+    "soap_ccf_linear_rv",
+    "soap_surrogate_create",
+    "soap_surrogate_n_params",
+    "soap_surrogate_train_step",
+    "soap_surrogate_predict",
+    "soap_surrogate_get_params",
+    "soap_surrogate_set_params",
+    "soap_surrogate_get_grads",
+    "soap_surrogate_save",
+    "soap_surrogate_load",
+    "soap_surrogate_last_error",
+    "soap_surrogate_destroy",
+    "soap_pca_project",
+    "soap_surrogate_gate",
 )
 
 
@@ -170,6 +184,36 @@ _lib.soap_profile_read.argtypes = [_ctx_p, C.POINTER(ProfileC)]
 _lib.soap_profile_read.restype = C.c_int
 _lib.soap_abi_version.argtypes = []
 _lib.soap_abi_version.restype = C.c_int32
+_lib.soap_ccf_linear_rv.argtypes = [_ctx_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]
+_lib.soap_ccf_linear_rv.restype = C.c_int
+_sg_p = C.c_void_p
+_lib.soap_surrogate_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
+                                       C.POINTER(_sg_p)]
+_lib.soap_surrogate_create.restype = C.c_int
+_lib.soap_surrogate_n_params.argtypes = [_sg_p]
+_lib.soap_surrogate_n_params.restype = C.c_int64
+_lib.soap_surrogate_train_step.argtypes = [_sg_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_float,
+                                           C.POINTER(C.c_float)]
+_lib.soap_surrogate_train_step.restype = C.c_int
+_lib.soap_surrogate_predict.argtypes = [_sg_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+_lib.soap_surrogate_predict.restype = C.c_int
+for _n in ("soap_surrogate_get_params", "soap_surrogate_set_params", "soap_surrogate_get_grads"):
+    getattr(_lib, _n).argtypes = [_sg_p, C.c_int32, C.c_void_p]
+    getattr(_lib, _n).restype = C.c_int
+for _n in ("soap_surrogate_save", "soap_surrogate_load"):
+    getattr(_lib, _n).argtypes = [_sg_p, C.c_char_p]
+    getattr(_lib, _n).restype = C.c_int
+_lib.soap_surrogate_last_error.argtypes = [_sg_p]
+_lib.soap_surrogate_last_error.restype = C.c_char_p
+_lib.soap_surrogate_destroy.argtypes = [_sg_p]
+_lib.soap_surrogate_destroy.restype = None
+_lib.soap_pca_project.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_void_p, C.c_void_p]
+_lib.soap_pca_project.restype = C.c_int
+_lib.soap_surrogate_gate.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.soap_surrogate_gate.restype = C.c_int
 
 
 class SoapError(RuntimeError):
@@ -217,10 +261,10 @@ class Context:
         self.n_pix = int(star.n_pix)
         self.dtype = np.float32 if self.precision == PREC_FP32 else np.float64
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.soap_destroy):
         h = getattr(self, "handle", None)
         if h:
-            _lib.soap_destroy(h)
+            _destroy(h)
             self.handle = None
 
 
@@ -360,3 +404,126 @@ def soap_last_error(ctx=None):
 def rv_records(n):
     """Host array for soap_ccf_rv's rv_out."""
     return np.zeros(n, dtype=RV_DTYPE)
+
+
+# ---- linear CCF, surrogate network, PCA projection, gate --------------------
+
+
+def _dptr(x, what):
+    """Device pointer of a contiguous GPU tensor (None passes through)."""
+    if x is None:
+        return None
+    if not (_is_tensor(x) and x.is_cuda and x.is_contiguous()):
+        raise ValueError(f"{what} must be a contiguous GPU tensor")
+    return x.data_ptr()
+
+
+def soap_ccf_linear_rv(ctx, coef, base, basis, ccf_out=None, rv_out=None):
+    """Fits CCF rows base + coef @ basis (device tensors; see soap.h)."""
+    n, k = int(coef.shape[0]), int(coef.shape[1])
+    st = _lib.soap_ccf_linear_rv(ctx.handle, _dptr(coef, "coef"), n, k, _dptr(base, "base"), _dptr(basis, "basis"),
+                                 _dptr(ccf_out, "ccf_out"), _dptr(rv_out, "rv_out"))
+    _check(st, ctx.handle)
+    return ccf_out, rv_out
+
+
+class Surrogate:
+    """Owns a soap_surrogate*."""
+
+    def __init__(self, handle, n_in, hidden, n_out, n_ens):
+        self.handle = handle
+        self.n_in, self.hidden, self.n_out, self.n_ens = n_in, hidden, n_out, n_ens
+
+    def __del__(self, _destroy=_lib.soap_surrogate_destroy):
+        h = getattr(self, "handle", None)
+        if h:
+            _destroy(h)
+            self.handle = None
+
+
+def _sg_check(st, s):
+    if st != SOAP_OK:
+        msg = _lib.soap_surrogate_last_error(s.handle).decode() if s is not None and s.handle else ""
+        raise SoapError(st, msg)
+
+
+def soap_surrogate_create(n_in, hidden, n_out, n_ensemble=1, seed=0, stream=None):
+    h = _sg_p()
+    st = _lib.soap_surrogate_create(int(n_in), int(hidden), int(n_out), int(n_ensemble), int(seed) & (2**64 - 1),
+                                    _stream_handle(stream), C.byref(h))
+    _sg_check(st, None)
+    return Surrogate(h, int(n_in), int(hidden), int(n_out), int(n_ensemble))
+
+
+def soap_surrogate_n_params(s):
+    return int(_lib.soap_surrogate_n_params(s.handle))
+
+
+def soap_surrogate_train_step(s, x, y, lr, want_loss=True):
+    loss = C.c_float(0.0)
+    st = _lib.soap_surrogate_train_step(s.handle, _dptr(x, "x"), _dptr(y, "y"), int(x.shape[0]), float(lr),
+                                        C.byref(loss) if want_loss else None)
+    _sg_check(st, s)
+    return float(loss.value) if want_loss else None
+
+
+def soap_surrogate_predict(s, x, coef, members=None):
+    st = _lib.soap_surrogate_predict(s.handle, _dptr(x, "x"), int(x.shape[0]), _dptr(coef, "coef"),
+                                     _dptr(members, "members"))
+    _sg_check(st, s)
+    return coef, members
+
+
+def _host_f32(a, n):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != n:
+        raise ValueError(f"expected {n} floats, got {a.size}")
+    return a
+
+
+def soap_surrogate_get_params(s, member=0):
+    out = np.empty(soap_surrogate_n_params(s), np.float32)
+    _sg_check(_lib.soap_surrogate_get_params(s.handle, int(member), out.ctypes.data), s)
+    return out
+
+
+def soap_surrogate_get_grads(s, member=0):
+    out = np.empty(soap_surrogate_n_params(s), np.float32)
+    _sg_check(_lib.soap_surrogate_get_grads(s.handle, int(member), out.ctypes.data), s)
+    return out
+
+
+def soap_surrogate_set_params(s, member, params):
+    a = _host_f32(params, soap_surrogate_n_params(s))
+    _sg_check(_lib.soap_surrogate_set_params(s.handle, int(member), a.ctypes.data), s)
+
+
+def soap_surrogate_save(s, path):
+    _sg_check(_lib.soap_surrogate_save(s.handle, os.fsencode(path)), s)
+
+
+def soap_surrogate_load(s, path):
+    _sg_check(_lib.soap_surrogate_load(s.handle, os.fsencode(path)), s)
+
+
+def soap_surrogate_destroy(s):
+    if s.handle:
+        _lib.soap_surrogate_destroy(s.handle)
+        s.handle = None
+
+
+def soap_pca_project(d, mean, V, coef, n_pix=None, stream=None):
+    """coef[n][k] = (d[:, :n_pix] - mean) @ V, FP32 on the GPU."""
+    n, ld = int(d.shape[0]), int(d.shape[1])
+    n_pix = ld if n_pix is None else int(n_pix)
+    st = _lib.soap_pca_project(_dptr(d, "d"), n, n_pix, ld, _dptr(mean, "mean"), _dptr(V, "V"), int(V.shape[1]),
+                               _dptr(coef, "coef"), _stream_handle(stream))
+    _sg_check(st, None)
+    return coef
+
+
+def soap_surrogate_gate(rv, n, n_ens, calib, threshold_kms, rv_kms, fallback, err_kms=None, stream=None):
+    st = _lib.soap_surrogate_gate(_dptr(rv, "rv"), int(n), int(n_ens), float(calib), float(threshold_kms),
+                                  _dptr(rv_kms, "rv_kms"), _dptr(err_kms, "err_kms"), _dptr(fallback, "fallback"),
+                                  _stream_handle(stream))
+    _sg_check(st, None)

@@ -512,6 +512,40 @@ hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_
   return hipGetLastError();
 }
 
+// ccf[i][v] = base[v] + sum_k coef[i][k] basis[k][v] (double, increasing k):
+// the CCF of a spectrum written in a basis, by linearity.  One block per row.
+__global__ void __launch_bounds__(256) k_ccf_linear(int64_t n, int k, int n_v, const float* __restrict__ coef,
+                                                    const double* __restrict__ base,
+                                                    const double* __restrict__ basis, double* __restrict__ ccf) {
+  __shared__ double s_c[256];
+  const int64_t i = blockIdx.x;
+  for (int v0 = 0; v0 < n_v; v0 += 256) {
+    const int v = v0 + threadIdx.x;
+    double a = v < n_v ? base[v] : 0.0;
+    for (int k0 = 0; k0 < k; k0 += 256) {
+      __syncthreads();
+      if (k0 + (int)threadIdx.x < k) s_c[threadIdx.x] = (double)coef[i * k + k0 + threadIdx.x];
+      __syncthreads();
+      const int kn = min(256, k - k0);
+      if (v < n_v)
+        for (int j = 0; j < kn; ++j) a = fma(s_c[j], basis[(int64_t)(k0 + j) * n_v + v], a);
+    }
+    if (v < n_v) ccf[i * n_v + v] = a;
+  }
+}
+
+hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, int k, const double* d_base,
+                                 const double* d_basis, double* d_lin, double* d_ccf, soap_rv* d_rv) {
+  hipLaunchKernelGGL(k_ccf_linear, dim3((unsigned)n), dim3(256), 0, c->stream, n, k, c->mask_nv, d_coef, d_base,
+                     d_basis, d_lin);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // the rows are complete CCFs: one "block of lines" for the fit kernel
+  hipLaunchKernelGGL(k_ccf_fit, dim3((unsigned)n), dim3(CCF_FIN_THREADS), 0, c->stream, 1, n, c->mask_nv,
+                     c->mask_v0, c->mask_dv, d_lin, d_ccf, d_rv ? 1 : 0, d_rv);
+  return hipGetLastError();
+}
+
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask) {
   hipLaunchKernelGGL(k_mask_prep, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->ln0, c->dln,
                      (double)c->P, d_lnl, d_w, (double2*)d_mask);

@@ -625,6 +625,28 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   return SOAP_OK;
 }
 
+SOAP_API soap_status soap_ccf_linear_rv(soap_ctx* c, const float* coef, int64_t n, int32_t k, const double* base,
+                                        const double* basis, double* ccf_out, soap_rv* rv_out) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(coef && base && basis, "coef, base and basis must be device arrays");
+  ARG_CHECK(n >= 1 && n <= (int64_t(1) << 24), "n must be in [1, 2^24]");
+  ARG_CHECK(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+  if (!c->mask_valid) {
+    setf(c->err, "no mask yet: call soap_ccf_rv with the mask first");
+    return SOAP_ERR_STATE;
+  }
+  double* lin = ccf_out;
+  if (!lin) {
+    HIP_TRY(grow(c->ws_ccfout, sizeof(double) * (size_t)n * c->mask_nv));
+    lin = static_cast<double*>(c->ws_ccfout.ptr);
+  }
+  // the fit reads each row into registers before writing it back, so the
+  // linear CCF and the output may share storage
+  HIP_TRY(soap::launch_ccf_linear_fit(c, coef, n, k, base, basis, lin, lin, rv_out));
+  return SOAP_OK;
+}
+
 SOAP_API soap_status soap_profile_enable(soap_ctx* c, int32_t on) {
   if (!c) return SOAP_ERR_ARG;
   HIP_TRY(hipStreamSynchronize(c->side));

@@ -215,6 +215,8 @@ hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const dou
 // sums the partial CCFs into d_ccf and, when d_rv is not null, fits them
 hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_t n_spec, double* d_ccf,
                           soap_rv* d_rv);
+hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, int k, const double* d_base,
+                                 const double* d_basis, double* d_lin, double* d_ccf, soap_rv* d_rv);
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask);
 
 int ccf_line_blocks(int n_lines);

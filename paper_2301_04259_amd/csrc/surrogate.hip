@@ -1,0 +1,361 @@
+// Learned surrogate of the disk-integrated spectrum: a small MLP that maps
+// the active-region and star parameters of one spectrum to the PCA
+// coefficients of its difference from the quiet spectrum (Eqs. 1-4 give the
+// spectrum the network stands in for), with its training and inference
+// kernels.
+//
+// Network per ensemble member: x[n_in] -> SiLU(x W1 + b1)[H] ->
+// SiLU(. W2 + b2)[H] -> . W3 + b3 [n_out].  Parameters are FP32 masters;
+// the matrix products run on BF16 copies with MFMA (v_mfma_f32_16x16x32_bf16,
+// FP32 accumulate), one 16 x 16 output tile per wave.  Training minimises the
+// mean squared error over the batch and outputs with Adam (bias-corrected
+// moments, FP32).  Every kernel has a fixed order of operations, so results
+// repeat bit for bit.
+//
+// The PCA projection coef = (d - mean) V of spectra differences onto a basis
+// is an FP32 tiled product (K = pixels, large).
+#include <cmath>
+
+#include "surrogate_internal.hpp"
+
+namespace soap {
+
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ float silu_grad(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+}  // namespace
+
+// C[M][N] = op(A)[M][K] op(B)[K][N] for every ensemble member (grid z), BF16
+// in, FP32 accumulate.  op(A)(i, k) = TA ? A[k lda + i] : A[i lda + k];
+// op(B)(k, j) = TB ? B[j ldb + k] : B[k ldb + j].  M, N multiples of 16, K a
+// multiple of 32.  A 64-thread block computes one 16 x 16 tile: lane l holds
+// A(l % 16, 8 (l / 16) + e) and B(8 (l / 16) + e, l % 16), e < 8, and ends
+// with C(4 (l / 16) + r, l % 16), r < 4.
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(64) k_mm_bf16(int M, int N, int K, const __bf16* __restrict__ A, int lda,
+                                                int64_t sA, const __bf16* __restrict__ B, int ldb, int64_t sB,
+                                                const float* __restrict__ bias, int64_t sBias, float* __restrict__ Cf,
+                                                int ldc, int64_t sC, __bf16* __restrict__ Cb, int64_t sCb,
+                                                const float* __restrict__ Z, int64_t sZ) {
+  const int l = threadIdx.x;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  const int e_ = blockIdx.z;
+  A += e_ * sA;
+  B += e_ * sB;
+  const int ia = i0 + (l & 15), jb = j0 + (l & 15), kq = 8 * (l >> 4);
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + kq + e;
+      a[e] = TA ? A[(int64_t)k * lda + ia] : A[(int64_t)ia * lda + k];
+      b[e] = TB ? B[(int64_t)jb * ldb + k] : B[(int64_t)k * ldb + jb];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  const int j = j0 + (l & 15);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + 4 * (l >> 4) + r;
+    const int64_t o = (int64_t)i * ldc + j;
+    const float v = acc[r];
+    if constexpr (EPI == MM_HIDDEN) {  // z = v + b, keep z, emit SiLU(z) in BF16
+      const float z = v + bias[e_ * sBias + j];
+      Cf[e_ * sC + o] = z;
+      Cb[e_ * sCb + o] = (__bf16)silu(z);
+    } else if constexpr (EPI == MM_OUTPUT) {  // y = v + b
+      Cf[e_ * sC + o] = v + bias[e_ * sBias + j];
+    } else if constexpr (EPI == MM_DHIDDEN) {  // dz = v SiLU'(z), in FP32 and BF16
+      const float dz = v * silu_grad(Z[e_ * sZ + o]);
+      Cf[e_ * sC + o] = dz;
+      Cb[e_ * sCb + o] = (__bf16)dz;
+    } else {  // MM_PLAIN: weight gradient
+      Cf[e_ * sC + o] = v;
+    }
+  }
+}
+
+// x[B][n_in] (FP32) -> X[B][K0] (BF16, zero padded)
+__global__ void k_pack_input(int B, int n_in, int K0, const float* __restrict__ x, __bf16* __restrict__ X) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * K0) return;
+  const int i = (int)(t / K0), k = (int)(t - (int64_t)i * K0);
+  X[t] = (__bf16)(k < n_in ? x[(int64_t)i * n_in + k] : 0.f);
+}
+
+// Squared error per (member, row) and dY = 2 (y - t) / (B n_out) in BF16.
+__global__ void k_mse(int B, int n_out, int E, const float* __restrict__ Y, const float* __restrict__ T,
+                      __bf16* __restrict__ dY, float* __restrict__ row_se) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (i >= B) return;
+  const float sc = 2.0f / ((float)B * (float)n_out);
+  float se = 0.f;
+  const float* y = Y + ((int64_t)e * B + i) * n_out;
+  const float* t = T + (int64_t)i * n_out;
+  __bf16* d = dY + ((int64_t)e * B + i) * n_out;
+  for (int j = 0; j < n_out; ++j) {
+    const float df = y[j] - t[j];
+    se += df * df;
+    d[j] = (__bf16)(sc * df);
+  }
+  row_se[(int64_t)e * B + i] = se;
+}
+
+// per member: loss = sum of row_se / (B n_out), rows added in order by one
+// block of 256 threads (strided partials, then a fixed tree)
+__global__ void __launch_bounds__(256) k_loss_sum(int B, int n_out, const float* __restrict__ row_se,
+                                                  float* __restrict__ loss) {
+  __shared__ float s[256];
+  const int e = blockIdx.x;
+  float a = 0.f;
+  for (int i = threadIdx.x; i < B; i += 256) a += row_se[(int64_t)e * B + i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[e] = s[0] / ((float)B * (float)n_out);
+}
+
+// db[j] = sum_i D[i][j] per member (rows in order)
+__global__ void k_colsum(int B, int N, const float* __restrict__ D, int64_t sD, float* __restrict__ db,
+                         int64_t sdb) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = blockIdx.y;
+  if (j >= N) return;
+  float a = 0.f;
+  for (int i = 0; i < B; ++i) a += D[e * sD + (int64_t)i * N + j];
+  db[e * sdb + j] = a;
+}
+
+// dY (BF16) -> FP32 copy for the output-bias gradient
+__global__ void k_bf16_to_f32(int64_t n, const __bf16* __restrict__ a, float* __restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) b[t] = (float)a[t];
+}
+
+// Adam on the FP32 masters (all members), then the BF16 copies
+__global__ void k_adam(int64_t n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       float* __restrict__ P, const float* __restrict__ G, float* __restrict__ Mm,
+                       float* __restrict__ Vm, __bf16* __restrict__ Pb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float g = G[t];
+  const float m = b1 * Mm[t] + (1.0f - b1) * g;
+  const float v = b2 * Vm[t] + (1.0f - b2) * g * g;
+  Mm[t] = m;
+  Vm[t] = v;
+  const float mh = m / c1, vh = v / c2;
+  const float p = P[t] - lr * mh / (sqrtf(vh) + eps);
+  P[t] = p;
+  Pb[t] = (__bf16)p;
+}
+
+__global__ void k_f32_to_bf16(int64_t n, const float* __restrict__ a, __bf16* __restrict__ b) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) b[t] = (__bf16)a[t];
+}
+
+// ensemble mean of the outputs (members added in order)
+__global__ void k_ens_mean(int64_t n, int E, const float* __restrict__ Y, float* __restrict__ mean) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  float m = 0.f;
+  for (int e = 0; e < E; ++e) m += Y[(int64_t)e * n + t];
+  mean[t] = m / (float)E;
+}
+
+// per sample: RV of the mean prediction, calib x sample standard deviation
+// of the members' RVs, and the fallback flag
+__global__ void k_gate(int64_t n, int E, double calib, double thr, const soap_rv* __restrict__ rv,
+                       double* __restrict__ rv_kms, double* __restrict__ err_kms, int* __restrict__ fallback) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  bool bad = rv[i].status != 0;
+  double m = 0.0;
+  for (int e = 0; e < E; ++e) {
+    const soap_rv& r = rv[(1 + e) * n + i];
+    bad = bad || r.status != 0;
+    m += r.rv_kms;
+  }
+  m /= (double)E;
+  double v = 0.0;
+  for (int e = 0; e < E; ++e) {
+    const double d = rv[(1 + e) * n + i].rv_kms - m;
+    v += d * d;
+  }
+  const double err = calib * sqrt(v / (double)(E - 1));
+  rv_kms[i] = rv[i].rv_kms;
+  if (err_kms) err_kms[i] = err;
+  fallback[i] = (bad || !(err < thr)) ? 1 : 0;
+}
+
+// coef[n][k] = sum_p (D[n][p] - mean[p]) V[p][k]: 64 x 64 tile per block of
+// 256 threads (4 x 4 outputs each), K in steps of 32 through LDS, FP32
+__global__ void __launch_bounds__(256) k_pca_project(int n, int P, int k, const float* __restrict__ D,
+                                                     int64_t ldd, const float* __restrict__ mean,
+                                                     const float* __restrict__ V, float* __restrict__ coef) {
+  __shared__ float sA[32][64 + 1];
+  __shared__ float sB[32][64 + 1];
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;  // rows on x: up to 2^25 / 64 blocks
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  float acc[4][4] = {};
+  for (int p0 = 0; p0 < P; p0 += 32) {
+    for (int t = threadIdx.x; t < 32 * 64; t += 256) {
+      const int pp = t & 31, rr = t >> 5;  // A: row rr, pixel pp (coalesced over pixels)
+      const int row = r0 + rr, pix = p0 + pp;
+      sA[pp][rr] = (row < n && pix < P) ? D[(int64_t)row * ldd + pix] - mean[pix] : 0.f;
+      const int cc = t & 63, pq = t >> 6;  // B: pixel pq < 32, component cc
+      const int pb = p0 + pq, col = c0 + cc;
+      sB[pq][cc] = (pb < P && col < k) ? V[(int64_t)pb * k + col] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int pp = 0; pp < 32; ++pp) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = sA[pp][ty * 4 + u];
+        b[u] = sB[pp][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) acc[u][w] = fmaf(a[u], b[w], acc[u][w]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const int row = r0 + ty * 4 + u, col = c0 + tx * 4 + w;
+      if (row < n && col < k) coef[(int64_t)row * k + col] = acc[u][w];
+    }
+}
+
+// ---- launchers -------------------------------------------------------------
+
+namespace {
+
+template <bool TA, bool TB, int EPI>
+hipError_t mm(hipStream_t st, int E, int M, int N, int K, const __bf16* A, int lda, int64_t sA, const __bf16* B,
+              int ldb, int64_t sB, const float* bias, int64_t sBias, float* Cf, int ldc, int64_t sC, __bf16* Cb,
+              int64_t sCb, const float* Z, int64_t sZ) {
+  dim3 grid(N / 16, M / 16, E);
+  hipLaunchKernelGGL((k_mm_bf16<TA, TB, EPI>), grid, dim3(64), 0, st, M, N, K, A, lda, sA, B, ldb, sB, bias,
+                     sBias, Cf, ldc, sC, Cb, sCb, Z, sZ);
+  return hipGetLastError();
+}
+
+inline dim3 blocks(int64_t n, int t = 256) { return dim3((unsigned)((n + t - 1) / t)); }
+
+}  // namespace
+
+#define SG_TRY(x)                              \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return e_;           \
+  } while (0)
+
+hipError_t sg_forward(soap_surrogate* s, const float* x, int B) {
+  const SgLayout& L = s->lay;
+  const int E = s->n_ens, H = s->hidden;
+  hipStream_t st = s->stream;
+  hipLaunchKernelGGL(k_pack_input, blocks((int64_t)B * SG_K0), dim3(256), 0, st, B, s->n_in, SG_K0, x, s->X);
+  SG_TRY(hipGetLastError());
+  const int64_t sP = L.n_params;
+  // layer 1: K0 -> H
+  SG_TRY((mm<false, false, MM_HIDDEN>(st, E, B, H, SG_K0, s->X, SG_K0, 0, s->Pb + L.W1, H, sP, s->P + L.b1, sP,
+                                      s->Z1, H, (int64_t)B * H, s->H1, (int64_t)B * H, nullptr, 0)));
+  // layer 2: H -> H
+  SG_TRY((mm<false, false, MM_HIDDEN>(st, E, B, H, H, s->H1, H, (int64_t)B * H, s->Pb + L.W2, H, sP, s->P + L.b2,
+                                      sP, s->Z2, H, (int64_t)B * H, s->H2, (int64_t)B * H, nullptr, 0)));
+  // layer 3: H -> n_out
+  SG_TRY((mm<false, false, MM_OUTPUT>(st, E, B, s->n_out, H, s->H2, H, (int64_t)B * H, s->Pb + L.W3, s->n_out, sP,
+                                      s->P + L.b3, sP, s->Y, s->n_out, (int64_t)B * s->n_out, nullptr, 0, nullptr,
+                                      0)));
+  return hipSuccess;
+}
+
+hipError_t sg_backward(soap_surrogate* s, const float* target, int B) {
+  const SgLayout& L = s->lay;
+  const int E = s->n_ens, H = s->hidden, O = s->n_out;
+  hipStream_t st = s->stream;
+  const int64_t sP = L.n_params, sBH = (int64_t)B * H, sBO = (int64_t)B * O;
+  hipLaunchKernelGGL(k_mse, dim3((B + 255) / 256, E), dim3(256), 0, st, B, O, E, s->Y, target, s->dY, s->row_se);
+  SG_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_loss_sum, dim3(E), dim3(256), 0, st, B, O, s->row_se, s->loss);
+  SG_TRY(hipGetLastError());
+  // output layer: dW3 = H2^T dY, db3 = colsum dY
+  SG_TRY((mm<true, false, MM_PLAIN>(st, E, H, O, B, s->H2, H, sBH, s->dY, O, sBO, nullptr, 0, s->G + L.W3, O, sP,
+                                    nullptr, 0, nullptr, 0)));
+  hipLaunchKernelGGL(k_bf16_to_f32, blocks((int64_t)E * B * O), dim3(256), 0, st, (int64_t)E * B * O, s->dY,
+                     s->dYf);
+  SG_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_colsum, dim3((O + 63) / 64, E), dim3(64), 0, st, B, O, s->dYf, sBO, s->G + L.b3, sP);
+  SG_TRY(hipGetLastError());
+  // dZ2 = (dY W3^T) SiLU'(Z2); dW2 = H1^T dZ2; db2 = colsum dZ2
+  SG_TRY((mm<false, true, MM_DHIDDEN>(st, E, B, H, O, s->dY, O, sBO, s->Pb + L.W3, O, sP, nullptr, 0, s->dZf, H, sBH,
+                                      s->dZb, sBH, s->Z2, sBH)));
+  SG_TRY((mm<true, false, MM_PLAIN>(st, E, H, H, B, s->H1, H, sBH, s->dZb, H, sBH, nullptr, 0, s->G + L.W2, H, sP,
+                                    nullptr, 0, nullptr, 0)));
+  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64, E), dim3(64), 0, st, B, H, s->dZf, sBH, s->G + L.b2, sP);
+  SG_TRY(hipGetLastError());
+  // dZ1 = (dZ2 W2^T) SiLU'(Z1); dW1 = X^T dZ1; db1 = colsum dZ1
+  SG_TRY((mm<false, true, MM_DHIDDEN>(st, E, B, H, H, s->dZb, H, sBH, s->Pb + L.W2, H, sP, nullptr, 0, s->dZf2, H,
+                                      sBH, s->dZb2, sBH, s->Z1, sBH)));
+  SG_TRY((mm<true, false, MM_PLAIN>(st, E, SG_K0, H, B, s->X, SG_K0, 0, s->dZb2, H, sBH, nullptr, 0, s->G + L.W1, H,
+                                    sP, nullptr, 0, nullptr, 0)));
+  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64, E), dim3(64), 0, st, B, H, s->dZf2, sBH, s->G + L.b1, sP);
+  return hipGetLastError();
+}
+
+hipError_t sg_adam(soap_surrogate* s, float lr) {
+  s->step += 1;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.0f - powf(b1, (float)s->step), c2 = 1.0f - powf(b2, (float)s->step);
+  const int64_t n = (int64_t)s->n_ens * s->lay.n_params;
+  hipLaunchKernelGGL(k_adam, blocks(n), dim3(256), 0, s->stream, n, lr, b1, b2, eps, c1, c2, s->P, s->G, s->M, s->V,
+                     s->Pb);
+  return hipGetLastError();
+}
+
+hipError_t sg_sync_bf16(soap_surrogate* s) {
+  const int64_t n = (int64_t)s->n_ens * s->lay.n_params;
+  hipLaunchKernelGGL(k_f32_to_bf16, blocks(n), dim3(256), 0, s->stream, n, s->P, s->Pb);
+  return hipGetLastError();
+}
+
+hipError_t sg_ens_mean(soap_surrogate* s, int B, float* mean) {
+  const int64_t n = (int64_t)B * s->n_out;
+  hipLaunchKernelGGL(k_ens_mean, blocks(n), dim3(256), 0, s->stream, n, s->n_ens, s->Y, mean);
+  return hipGetLastError();
+}
+
+hipError_t sg_gate(hipStream_t st, const soap_rv* rv, int64_t n, int E, double calib, double thr, double* rv_kms,
+                   double* err_kms, int* fallback) {
+  hipLaunchKernelGGL(k_gate, blocks(n), dim3(256), 0, st, n, E, calib, thr, rv, rv_kms, err_kms, fallback);
+  return hipGetLastError();
+}
+
+hipError_t sg_pca_project(hipStream_t st, int n, int P, int k, const float* D, int64_t ldd, const float* mean,
+                          const float* V, float* coef) {
+  dim3 grid((n + 63) / 64, (k + 63) / 64);
+  hipLaunchKernelGGL(k_pca_project, grid, dim3(256), 0, st, n, P, k, D, ldd, mean, V, coef);
+  return hipGetLastError();
+}
+
+}  // namespace soap

@@ -26,6 +26,9 @@ from .stars import (  # noqa: F401
     cb_velocity_ms,
     make_cfg1,
     make_cfg2,
+    make_cfg5,
+    cfg5_samples,
+    SpotSamples,
     make_tiny,
     make_velocity_grid,
     input_digest,

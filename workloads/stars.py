@@ -394,3 +394,87 @@ def make_tiny(
         mask=mask,
         name=f"tiny seed={seed} N={n_grid} P={n_pix} B={n_mu}",
     )
+
+
+def make_cfg5(seed: int = 5, precision: int = PREC_FP32, n_grid: int = 300) -> StarInputs:
+    """Star of the surrogate data set: a 20000-pixel window from 5000 A at
+    R = 115000 (about 298 A), a 300 x 300 disk, 20 mu bins, solar limb
+    darkening, v sin i = 2 km/s, i = 90 deg, scalar contrast.  Line density
+    follows the full-range star (about 10 lines per A, the deepest 10% Voigt);
+    the spot spectrum has 30% deeper lines and no blueshift.  Regions and
+    phases come per sample from ``cfg5_samples``; the mask holds the window's
+    deepest lines (up to 400)."""
+    rng = np.random.default_rng(seed)
+    dln = 1.0 / (3.0 * 115000.0)
+    ln0 = np.log(5000.0)
+    n_pix = 20000
+    lam_hi = float(np.exp(ln0 + dln * (n_pix - 1)))
+    n_lines = int(round((lam_hi - 5000.0) * 30000 / 3100.0))
+    centre = rng.uniform(5002.0, lam_hi - 2.0, n_lines)
+    u = rng.uniform(0.0, 1.0, n_lines)
+    depth = 0.05 + 0.85 * u * u
+    sigma = centre * rng.uniform(1.5, 3.0, n_lines) / C_KMS
+    gamma = np.zeros(n_lines)
+    deep = np.argsort(-depth)[: n_lines // 10]
+    gamma[deep] = 0.1 * sigma[deep]
+    n_mu = 20
+    mu_b = 1.0 - 0.9 * np.arange(n_mu) / (n_mu - 1)
+    cb = cb_law_ms(mu_b)
+    dt = np.float64 if precision == PREC_FP64 else np.float32
+    quiet = np.stack([_render(ln0, dln, n_pix, centre, depth, sigma, gamma, v) for v in cb]).astype(dt)
+    spot_one = _render(ln0, dln, n_pix, centre, np.minimum(depth * 1.3, 0.99), sigma, gamma, 0.0)
+    spot = np.broadcast_to(spot_one, (n_mu, n_pix)).astype(dt)
+    mlam, _ = _select_mask_lines(centre, depth, sigma, 400)
+    mask = Mask(np.log(mlam), np.ones(len(mlam)), 0.41, -20.0, 0.25, 161)
+    return StarInputs(
+        n_grid=n_grid,
+        vsini_kms=2.0,
+        incl_deg=90.0,
+        ld_u1=0.4,
+        ld_u2=0.25,
+        ln_lambda0=ln0,
+        dln_lambda=dln,
+        n_pix=n_pix,
+        mu_bins=mu_b,
+        spectra=[quiet, spot, None],
+        precision=precision,
+        contrast_mode=CONTRAST_SCALAR,
+        regions=[],
+        phases=np.zeros(0),
+        mask=mask,
+        name=f"cfg5: {n_grid}^2 disk, 20000 px window at 5000 A, 20 mu bins, one spot per sample",
+    )
+
+
+@dataclass
+class SpotSamples:
+    """Single-spot configurations of the surrogate data set: spot k has
+    (lat_deg, lon_deg, radius, contrast) and is seen at phases[k] (n_per
+    phases each).  Sample i = spot i // n_per at phase phases.flat[i]."""
+
+    lat_deg: np.ndarray
+    lon_deg: np.ndarray
+    radius: np.ndarray
+    contrast: np.ndarray
+    phases: np.ndarray  # (n_spots, n_per)
+
+    @property
+    def n(self) -> int:
+        return int(self.phases.size)
+
+    @property
+    def n_per(self) -> int:
+        return int(self.phases.shape[1])
+
+
+def cfg5_samples(n_spots: int, n_per: int = 8, seed: int = 5) -> SpotSamples:
+    """lat U[-60, 60] deg, lon U[0, 360) deg, radius U[0.01, 0.10], contrast
+    U[0.3, 0.9], phases U[0, 1) (n_per per spot)."""
+    rng = np.random.default_rng([seed, n_spots, n_per])
+    return SpotSamples(
+        lat_deg=rng.uniform(-60.0, 60.0, n_spots),
+        lon_deg=rng.uniform(0.0, 360.0, n_spots),
+        radius=rng.uniform(0.01, 0.10, n_spots),
+        contrast=rng.uniform(0.3, 0.9, n_spots),
+        phases=rng.uniform(0.0, 1.0, (n_spots, n_per)),
+    )
