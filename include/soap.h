@@ -178,6 +178,18 @@ soap_status soap_active_spectra(soap_ctx* ctx, const soap_region* regions, int32
                                 const double* phases, int32_t n_phases, int32_t effect,
                                 void* flux, int32_t flux_on_device);
 
+/* Many activity configurations of one star in one pass of the kernels
+ * (Algorithm 5 per phase, each phase with its own region list): job j has
+ * regions[region_offsets[j] .. region_offsets[j+1]) (0 .. 64 of them) and
+ * phases[phase_offsets[j] .. phase_offsets[j+1]) (at least one); its spectra
+ * are rows phase_offsets[j] .. of flux[total phases][n_pix].  offsets are
+ * host arrays of n_jobs + 1 entries starting at 0; at most 2^22 regions and
+ * 2^20 phases in all.  Every row equals, bit for bit, what
+ * soap_active_spectra gives for that job's regions at that phase.           */
+soap_status soap_active_spectra_jobs(soap_ctx* ctx, const soap_region* regions, const int32_t* region_offsets,
+                                     const double* phases, const int32_t* phase_offsets, int32_t n_jobs,
+                                     int32_t effect, void* flux, int32_t flux_on_device);
+
 /* CCF of n_spec spectra flux[n_spec][n_pix] (the context's grid and float
  * type) against `mask`, then a Gaussian fit per CCF (section 4.1).
  * ccf_out[n_spec][n_v] (double, may be NULL) and rv_out[n_spec] (may be

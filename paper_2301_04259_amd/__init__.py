@@ -66,6 +66,7 @@ SYMBOLS = (
     "soap_profile_enable",
     "soap_profile_read",
     "soap_ccf_linear_rv",
+    "soap_active_spectra_jobs",
     "soap_surrogate_create",
     "soap_surrogate_n_params",
     "soap_surrogate_train_step",
@@ -187,6 +188,9 @@ _lib.soap_abi_version.restype = C.c_int32
 _lib.soap_ccf_linear_rv.argtypes = [_ctx_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
 _lib.soap_ccf_linear_rv.restype = C.c_int
+_lib.soap_active_spectra_jobs.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                          C.c_int32, C.c_void_p, C.c_int32]
+_lib.soap_active_spectra_jobs.restype = C.c_int
 _sg_p = C.c_void_p
 _lib.soap_surrogate_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
                                        C.POINTER(_sg_p)]
@@ -345,6 +349,23 @@ def soap_active_spectra(ctx, regions, phases, effect, out):
     st = _lib.soap_active_spectra(
         ctx.handle, regs, len(regions), ph.ctypes.data_as(C.POINTER(C.c_double)), len(ph), int(effect), p, dev
     )
+    _check(st, ctx.handle)
+    return out
+
+
+def soap_active_spectra_jobs(ctx, job_regions, job_phases, effect, out):
+    """Jobs = (region list, phases) pairs of one star in one call; out rows
+    follow the jobs' phases in order."""
+    regs = [r for rl in job_regions for r in rl]
+    roff = np.zeros(len(job_regions) + 1, np.int32)
+    roff[1:] = np.cumsum([len(rl) for rl in job_regions])
+    ph = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64).reshape(-1) for p in job_phases]))
+    poff = np.zeros(len(job_phases) + 1, np.int32)
+    poff[1:] = np.cumsum([np.asarray(p).size for p in job_phases])
+    arr = _regions(regs)
+    p, dev = _ptr(out)
+    st = _lib.soap_active_spectra_jobs(ctx.handle, C.cast(arr, C.c_void_p), roff.ctypes.data, ph.ctypes.data,
+                                       poff.ctypes.data, len(job_regions), int(effect), p, dev)
     _check(st, ctx.handle)
     return out
 

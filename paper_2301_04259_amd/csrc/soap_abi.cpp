@@ -357,30 +357,14 @@ SOAP_API soap_status soap_quiet_spectrum(soap_ctx* c, void* out, int32_t out_on_
   return SOAP_OK;
 }
 
-SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions, int32_t n_regions,
-                                         const double* phases, int32_t n_phases, int32_t effect, void* flux,
-                                         int32_t flux_on_device) {
-  if (!c) return SOAP_ERR_ARG;
-  std::string& err = c->err;
-  ARG_CHECK(n_regions >= 0 && n_regions <= soap::MAX_REGIONS, "n_regions must be in [0, %d]", soap::MAX_REGIONS);
-  ARG_CHECK(n_regions == 0 || regions != nullptr, "regions is NULL");
-  ARG_CHECK(n_phases >= 1 && n_phases <= soap::MAX_PHASES, "n_phases must be in [1, %d]", soap::MAX_PHASES);
-  ARG_CHECK(phases != nullptr, "phases is NULL");
-  ARG_CHECK(effect == SOAP_EFFECT_TOT || effect == SOAP_EFFECT_FLUX || effect == SOAP_EFFECT_BCONV,
-            "unknown effect %d", effect);
-  ARG_CHECK(flux != nullptr, "flux is NULL");
-  for (int p = 0; p < n_phases; ++p) ARG_CHECK(is_finite(phases[p]), "phases[%d] is not finite", p);
-  for (int r = 0; r < n_regions; ++r) {
-    const soap_region& R = regions[r];
-    ARG_CHECK(R.type == SOAP_SPOT || R.type == SOAP_FACULA, "regions[%d].type must be SOAP_SPOT or SOAP_FACULA",
-              r);
-    ARG_CHECK(is_finite(R.lat_deg) && R.lat_deg >= -90.0 && R.lat_deg <= 90.0, "regions[%d].lat_deg out of range", r);
-    ARG_CHECK(is_finite(R.lon_deg), "regions[%d].lon_deg is not finite", r);
-    ARG_CHECK(is_finite(R.radius) && R.radius > 0.0 && R.radius < 1.0, "regions[%d].radius must be in (0, 1)", r);
-    ARG_CHECK(is_finite(R.contrast) && R.contrast > 0.0, "regions[%d].contrast must be > 0", r);
-    if (effect != SOAP_EFFECT_FLUX)
-      ARG_CHECK(c->has_type[R.type], "regions[%d] has type %d but the star has no spectra of that type", r, R.type);
-  }
+namespace {
+
+// Shared body of soap_active_spectra and soap_active_spectra_jobs.  With
+// pj_host == NULL every phase uses regions[0 .. n_regions); otherwise phase
+// p uses pj_host[p] = (first region, count).  Arguments are validated.
+soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regions, int max_reg,
+                        const int2* pj_host, const double* phases, int32_t n_phases, int32_t effect, void* flux,
+                        int32_t flux_on_device) {
   // per-call plan: paired tables when every active weight equals its
   // removal weight (chromatic contrast, the convective effect, or unit
   // scalar contrasts); otherwise split tables with explicit removal rows
@@ -398,16 +382,19 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
 
   // parameter block (regions then phases) in the next pinned slot; the
   // weights kernel reads it in place
-  const size_t reg_bytes = sizeof(soap::Region) * soap::MAX_REGIONS;
-  const size_t par_bytes = reg_bytes + sizeof(double) * n_phases;
+  const size_t n_reg_slots = std::max<size_t>(soap::MAX_REGIONS, (size_t)n_regions);
+  const size_t reg_bytes = 256 * ((sizeof(soap::Region) * n_reg_slots + 255) / 256);
+  const size_t ph_bytes = 256 * ((sizeof(double) * n_phases + 255) / 256);
+  const size_t par_bytes = reg_bytes + ph_bytes + (pj_host ? sizeof(int2) * n_phases : 0);
   // this call's table set; its kernels run on the side stream after the
   // apply that last read the set (two calls ago) is done
   const int sidx = c->prep_next;
   soap_ctx::PrepSet& S = c->prep[sidx];
   c->prep_next ^= 1;
-  const size_t reg_dev = 256 * ((sizeof(soap::Region) * soap::MAX_REGIONS + 255) / 256);
-  const size_t cen_dev = 256 * ((sizeof(double4) * (size_t)n_phases * std::max(1, n_regions) + 255) / 256);
-  const size_t par_dev = reg_dev + cen_dev + sizeof(int4) * (size_t)n_phases;
+  const size_t reg_dev = reg_bytes;
+  const size_t pj_dev = 256 * ((sizeof(int2) * (size_t)n_phases + 255) / 256);
+  const size_t cen_dev = 256 * ((sizeof(double4) * (size_t)n_phases * std::max(1, max_reg) + 255) / 256);
+  const size_t par_dev = reg_dev + pj_dev + cen_dev + sizeof(int4) * (size_t)n_phases;
   const size_t kfx_bytes = sizeof(unsigned long long) * (size_t)n_phases * GJ;
   const size_t k_bytes = sizeof(double) * (size_t)n_phases * GJ;
   const size_t m_bytes = sizeof(unsigned long long) * (size_t)n_phases * pl.G;
@@ -462,15 +449,20 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
     hr[r].contrast = regions[r].contrast;
   }
   std::memcpy(host + reg_bytes, phases, sizeof(double) * n_phases);
+  if (pj_host) std::memcpy(host + reg_bytes + ph_bytes, pj_host, sizeof(int2) * n_phases);
   void* dev_view = nullptr;
   HIP_TRY(hipHostGetDevicePointer(&dev_view, c->slot[k], 0));
   const soap::Region* d_reg = static_cast<const soap::Region*>(dev_view);
   const double* d_ph = reinterpret_cast<const double*>(static_cast<const unsigned char*>(dev_view) + reg_bytes);
+  const int2* d_pj =
+      pj_host ? reinterpret_cast<const int2*>(static_cast<const unsigned char*>(dev_view) + reg_bytes + ph_bytes)
+              : nullptr;
 
   soap::WeightsOut wo;
   wo.reg = static_cast<soap::Region*>(S.par.ptr);
-  wo.cen = reinterpret_cast<double4*>(static_cast<unsigned char*>(S.par.ptr) + reg_dev);
-  wo.box = reinterpret_cast<int4*>(static_cast<unsigned char*>(S.par.ptr) + reg_dev + cen_dev);
+  wo.pj = reinterpret_cast<int2*>(static_cast<unsigned char*>(S.par.ptr) + reg_dev);
+  wo.cen = reinterpret_cast<double4*>(static_cast<unsigned char*>(S.par.ptr) + reg_dev + pj_dev);
+  wo.box = reinterpret_cast<int4*>(static_cast<unsigned char*>(S.par.ptr) + reg_dev + pj_dev + cen_dev);
   wo.Kfx = static_cast<unsigned long long*>(S.Kfx.ptr);
   wo.K = static_cast<double*>(S.K.ptr);
   wo.mask = static_cast<unsigned long long*>(S.mask64.ptr);
@@ -479,7 +471,7 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
   S.kfx_dirty = true;
   {
     StageTimer t(c, ST_WEIGHTS, c->side);
-    HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, d_ph, wo, c->side));
+    HIP_TRY(soap::launch_weights(c, pl, d_reg, n_regions, std::max(1, max_reg), d_ph, d_pj, wo, c->side));
     t.done();
   }
   HIP_TRY(hipEventRecord(c->slot_done[k], c->side));
@@ -508,6 +500,78 @@ SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions
     HIP_TRY(hipStreamSynchronize(c->stream));
   }
   return SOAP_OK;
+}
+
+soap_status check_region(soap_ctx* c, const soap_region& R, int r, int32_t effect) {
+  std::string& err = c->err;
+  ARG_CHECK(R.type == SOAP_SPOT || R.type == SOAP_FACULA, "regions[%d].type must be SOAP_SPOT or SOAP_FACULA", r);
+  ARG_CHECK(is_finite(R.lat_deg) && R.lat_deg >= -90.0 && R.lat_deg <= 90.0, "regions[%d].lat_deg out of range", r);
+  ARG_CHECK(is_finite(R.lon_deg), "regions[%d].lon_deg is not finite", r);
+  ARG_CHECK(is_finite(R.radius) && R.radius > 0.0 && R.radius < 1.0, "regions[%d].radius must be in (0, 1)", r);
+  ARG_CHECK(is_finite(R.contrast) && R.contrast > 0.0, "regions[%d].contrast must be > 0", r);
+  if (effect != SOAP_EFFECT_FLUX)
+    ARG_CHECK(c->has_type[R.type], "regions[%d] has type %d but the star has no spectra of that type", r, R.type);
+  return SOAP_OK;
+}
+
+soap_status check_common(soap_ctx* c, const double* phases, int64_t n_phases, int32_t effect, void* flux) {
+  std::string& err = c->err;
+  ARG_CHECK(n_phases >= 1 && n_phases <= soap::MAX_PHASES, "n_phases must be in [1, %d]", soap::MAX_PHASES);
+  ARG_CHECK(phases != nullptr, "phases is NULL");
+  ARG_CHECK(effect == SOAP_EFFECT_TOT || effect == SOAP_EFFECT_FLUX || effect == SOAP_EFFECT_BCONV,
+            "unknown effect %d", effect);
+  ARG_CHECK(flux != nullptr, "flux is NULL");
+  for (int64_t p = 0; p < n_phases; ++p) ARG_CHECK(is_finite(phases[p]), "phases[%lld] is not finite", (long long)p);
+  return SOAP_OK;
+}
+
+}  // namespace
+
+SOAP_API soap_status soap_active_spectra(soap_ctx* c, const soap_region* regions, int32_t n_regions,
+                                         const double* phases, int32_t n_phases, int32_t effect, void* flux,
+                                         int32_t flux_on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(n_regions >= 0 && n_regions <= soap::MAX_REGIONS, "n_regions must be in [0, %d]", soap::MAX_REGIONS);
+  ARG_CHECK(n_regions == 0 || regions != nullptr, "regions is NULL");
+  soap_status st = check_common(c, phases, n_phases, effect, flux);
+  if (st != SOAP_OK) return st;
+  for (int r = 0; r < n_regions; ++r)
+    if ((st = check_region(c, regions[r], r, effect)) != SOAP_OK) return st;
+  return active_impl(c, regions, n_regions, n_regions, nullptr, phases, n_phases, effect, flux, flux_on_device);
+}
+
+SOAP_API soap_status soap_active_spectra_jobs(soap_ctx* c, const soap_region* regions,
+                                              const int32_t* region_offsets, const double* phases,
+                                              const int32_t* phase_offsets, int32_t n_jobs, int32_t effect,
+                                              void* flux, int32_t flux_on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(n_jobs >= 1 && n_jobs <= soap::MAX_PHASES, "n_jobs must be in [1, %d]", soap::MAX_PHASES);
+  ARG_CHECK(region_offsets && phase_offsets, "offset arrays are NULL");
+  ARG_CHECK(region_offsets[0] == 0 && phase_offsets[0] == 0, "offsets must start at 0");
+  int max_reg = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    const int64_t nr = (int64_t)region_offsets[j + 1] - region_offsets[j];
+    const int64_t np = (int64_t)phase_offsets[j + 1] - phase_offsets[j];
+    ARG_CHECK(nr >= 0 && nr <= soap::MAX_REGIONS, "job %d has %lld regions (0 .. %d allowed)", j, (long long)nr,
+              soap::MAX_REGIONS);
+    ARG_CHECK(np >= 1, "job %d has no phases", j);
+    max_reg = std::max(max_reg, (int)nr);
+  }
+  const int64_t n_regions = region_offsets[n_jobs], n_phases = phase_offsets[n_jobs];
+  ARG_CHECK(n_regions <= (int64_t(1) << 22), "at most 2^22 regions in all");
+  ARG_CHECK(n_regions == 0 || regions != nullptr, "regions is NULL");
+  soap_status st = check_common(c, phases, n_phases, effect, flux);
+  if (st != SOAP_OK) return st;
+  for (int64_t r = 0; r < n_regions; ++r)
+    if ((st = check_region(c, regions[r], (int)r, effect)) != SOAP_OK) return st;
+  std::vector<int2> pj((size_t)n_phases);
+  for (int j = 0; j < n_jobs; ++j)
+    for (int p = phase_offsets[j]; p < phase_offsets[j + 1]; ++p)
+      pj[p] = make_int2(region_offsets[j], region_offsets[j + 1] - region_offsets[j]);
+  return active_impl(c, regions, (int32_t)n_regions, max_reg, pj.data(), phases, (int32_t)n_phases, effect, flux,
+                     flux_on_device);
 }
 
 SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_device, int64_t n_spec,

@@ -197,7 +197,8 @@ hipError_t launch_quiet(soap_ctx* c);
 // outputs and scratch of the weight kernel
 struct WeightsOut {
   Region* reg;               // [n_regions] device copy of the regions
-  double4* cen;              // [n_phases][n_regions] region centres (x, y, z) and cos(alpha)
+  int2* pj;                  // [n_phases] (first region, count) per phase, or unused
+  double4* cen;              // [n_phases][max regions per phase] centres (x, y, z) and cos(alpha)
   int4* box;                 // [n_phases] disk-cell bounding box of the visible caps
   unsigned long long* Kfx;   // [n_phases][G][J] fixed-point taps, zero between calls
   double* K;                 // [n_phases][G][J] taps
@@ -205,8 +206,8 @@ struct WeightsOut {
   unsigned char* wins;       // [n_chunks][vg_cap] window records
   int* nvg;                  // [n_chunks] windows per chunk
 };
-hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
-                          const WeightsOut& o, hipStream_t st);
+hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, int max_reg,
+                          const double* d_ph, const int2* d_pj, const WeightsOut& o, hipStream_t st);
 hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o, hipStream_t st);
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux);
 hipError_t launch_q_convert(soap_ctx* c, void* out);

@@ -199,31 +199,39 @@ __global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int
 // and the disk-cell bounding box of the caps that reach the visible
 // hemisphere.  The regions and phases are read once from the caller's
 // parameter block, so the weight kernel's many blocks read device memory.
-__global__ void __launch_bounds__(128) k_params(int N, int n_reg, int n_ph, double incl,
+__global__ void __launch_bounds__(128) k_params(int N, int n_reg, int max_reg, int n_ph, double incl,
                                                 const Region* __restrict__ reg,
-                                                const double* __restrict__ phases,
-                                                Region* __restrict__ reg_out, double4* __restrict__ cen,
-                                                int4* __restrict__ box) {
+                                                const double* __restrict__ phases, const int2* __restrict__ pj,
+                                                Region* __restrict__ reg_out, int2* __restrict__ pj_out,
+                                                double4* __restrict__ cen, int4* __restrict__ box) {
+  // one region list for every phase (pj == NULL): staged in LDS; per-phase
+  // lists (pj[ph] = first region, count): read from the parameter block
   __shared__ Region s_reg[MAX_REGIONS];
-  for (int r = threadIdx.x; r < n_reg; r += blockDim.x) {
-    s_reg[r] = reg[r];
-    if (blockIdx.x == 0) reg_out[r] = s_reg[r];
-  }
+  if (!pj)
+    for (int r = threadIdx.x; r < n_reg; r += blockDim.x) s_reg[r] = reg[r];
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_reg; r += gridDim.x * blockDim.x) reg_out[r] = reg[r];
   __syncthreads();
   const int ph = blockIdx.x * blockDim.x + threadIdx.x;
   if (ph >= n_ph) return;
   const double phase = phases[ph];
+  int2 rl = make_int2(0, n_reg);
+  if (pj) {
+    rl = pj[ph];
+    pj_out[ph] = rl;
+  }
+  const Region* R = pj ? reg + rl.x : s_reg;
   // a cap point p satisfies |p - c| <= 2 sin(alpha / 2) = sqrt(2 - 2 cos
   // alpha), which bounds its projected distance from the centre
   double xlo = 2.0, xhi = -2.0, ylo = 2.0, yhi = -2.0;
-  for (int r = 0; r < n_reg; ++r) {
+  for (int r = 0; r < rl.y; ++r) {
+    const Region g = R[r];
     double cx, cy, cz, rc;
-    region_centre(s_reg[r].lat_deg, s_reg[r].lon_deg, phase, incl, &cx, &cy, &cz);
+    region_centre(g.lat_deg, g.lon_deg, phase, incl, &cx, &cy, &cz);
     {
 #pragma clang fp contract(off)
-      rc = sqrt(1.0 - s_reg[r].radius * s_reg[r].radius);
+      rc = sqrt(1.0 - g.radius * g.radius);
     }
-    cen[(int64_t)ph * n_reg + r] = make_double4(cx, cy, cz, rc);
+    cen[(int64_t)ph * max_reg + r] = make_double4(cx, cy, cz, rc);
     const double rad = sqrt(fmax(0.0, 1.0 - rc * rc));
     if (cz <= -rad - 1e-12) continue;
     const double d = sqrt(fmax(0.0, 2.0 - 2.0 * rc)) + 1e-9;
@@ -243,8 +251,8 @@ template <bool KAHAN32>
 __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
     int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, int effect,
     const double* __restrict__ mu_b, const int* __restrict__ col_c, const double* __restrict__ col_w,
-    const Region* __restrict__ reg, int n_reg, const double4* __restrict__ cen, const int4* __restrict__ pbox,
-    unsigned long long* __restrict__ Kfx) {
+    const Region* __restrict__ reg, int n_reg_all, int max_reg, const int2* __restrict__ pj,
+    const double4* __restrict__ cen, const int4* __restrict__ pbox, unsigned long long* __restrict__ Kfx) {
   __shared__ double rcx[MAX_REGIONS], rcy[MAX_REGIONS], rcz[MAX_REGIONS], rcos[MAX_REGIONS],
       rscal[MAX_REGIONS], rreach[MAX_REGIONS];
   __shared__ double s_mub[MAX_MU];
@@ -266,14 +274,22 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
   const int k0 = bx.z, k1 = bx.w;
   if (i0 > i1 || k0 > k1) return;  // nothing of this slab is covered
   for (int b = threadIdx.x; b < B; b += blockDim.x) s_mub[b] = mu_b[b];
+  // this phase's region list (uniform)
+  int rbase = 0, n_reg = n_reg_all;
+  if (pj) {
+    const int2 rl = pj[ph];
+    rbase = rl.x;
+    n_reg = rl.y;
+  }
   if (threadIdx.x < n_reg) {
-    const double4 c4 = cen[(int64_t)ph * n_reg + threadIdx.x];
+    const double4 c4 = cen[(int64_t)ph * max_reg + threadIdx.x];
+    const Region& g = reg[rbase + threadIdx.x];
     rcx[threadIdx.x] = c4.x;
     rcy[threadIdx.x] = c4.y;
     rcz[threadIdx.x] = c4.z;
     rcos[threadIdx.x] = c4.w;
-    rtype[threadIdx.x] = reg[threadIdx.x].type;
-    rscal[threadIdx.x] = (!paired && effect != SOAP_EFFECT_BCONV) ? reg[threadIdx.x].contrast : 1.0;
+    rtype[threadIdx.x] = g.type;
+    rscal[threadIdx.x] = (!paired && effect != SOAP_EFFECT_BCONV) ? g.contrast : 1.0;
     // projected reach of the cap around its centre, or -1 when the cap
     // cannot reach the visible hemisphere (the bounding-box rule)
     const double rad = sqrt(fmax(0.0, 1.0 - c4.w * c4.w));
@@ -429,21 +445,22 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
   }
 }
 
-hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, const double* d_ph,
-                          const WeightsOut& o, hipStream_t st) {
-  hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, st, c->N, n_reg,
-                     pl.n_ph, c->incl, d_reg, d_ph, o.reg, o.cen, o.box);
+hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, int max_reg,
+                          const double* d_ph, const int2* d_pj, const WeightsOut& o, hipStream_t st) {
+  hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, st, c->N, n_reg, max_reg,
+                     pl.n_ph, c->incl, d_reg, d_ph, d_pj, o.reg, o.pj, o.cen, o.box);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const int2* pj = d_pj ? o.pj : nullptr;
   dim3 grid((unsigned)pl.n_slabs * (unsigned)pl.n_ph);
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, st, c->N, c->B, c->J, c->jmin,
                        pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
-                       o.reg, n_reg, o.cen, o.box, o.Kfx);
+                       o.reg, n_reg, max_reg, pj, o.cen, o.box, o.Kfx);
   else
     hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * WEIGHT_WAVES), 0, st, c->N, c->B, c->J, c->jmin,
                        pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
-                       o.reg, n_reg, o.cen, o.box, o.Kfx);
+                       o.reg, n_reg, max_reg, pj, o.cen, o.box, o.Kfx);
   return hipGetLastError();
 }
 

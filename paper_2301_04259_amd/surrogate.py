@@ -5,7 +5,7 @@ library's kernels).
 Pipeline (the synthesis it stands in for: Algorithm 5, Eqs. 1-4; its RV:
 section 4.1):
 
-  build_dataset   runs soap_active_spectra for every single-spot sample and
+  synthesize      runs soap_active_spectra_jobs over the single-spot samples and
                   keeps the spectra F (device, float32)
   fit_basis       offline: mean and the first k principal axes of the
                   differences F - Q from an FP64 SVD of a subset (host), then
@@ -19,12 +19,14 @@ section 4.1):
                   soap_ccf_linear_rv (CCF of the quiet-plus-basis expansion,
                   by linearity) -> soap_surrogate_gate; samples whose
                   predicted error is not below the threshold go through the
-                  full synthesis (soap_active_spectra + soap_ccf_rv)
+                  full synthesis (soap_active_spectra_jobs + soap_ccf_rv)
 
 The input features of a sample are its spot latitude, the sine and cosine of
 its longitude at the observed phase (longitude + 360 deg x phase: the star
-looks the same for equal values of that sum), its radius and its contrast,
-each scaled to about unit range.
+looks the same for equal values of that sum), the same two scaled by the
+cosine of the latitude (for an equator-on star, the spot centre's position
+across the disk and its mu), its radius and its contrast, each scaled to
+about unit range.
 """
 from __future__ import annotations
 
@@ -39,7 +41,7 @@ from . import (
     PREC_FP32,
     RV_DTYPE,
     SPOT,
-    soap_active_spectra,
+    soap_active_spectra_jobs,
     soap_ccf_linear_rv,
     soap_ccf_rv,
     soap_quiet_spectrum,
@@ -49,7 +51,7 @@ from . import (
     soap_surrogate_train_step,
 )
 
-N_FEATURES = 5
+N_FEATURES = 7
 
 Region = namedtuple("Region", "type lat_deg lon_deg radius contrast")
 
@@ -63,14 +65,16 @@ def _torch():
 
 
 def features(lat_deg, lon_deg, radius, contrast, phase):
-    """float32 [n][5] inputs of the network (see the module docstring)."""
-    lat = np.asarray(lat_deg, np.float64)
+    """float32 [n][7] inputs of the network (see the module docstring)."""
+    lat = np.deg2rad(np.asarray(lat_deg, np.float64))
     th = np.deg2rad(np.asarray(lon_deg, np.float64) + 360.0 * np.asarray(phase, np.float64))
     x = np.stack(
         [
-            lat / 60.0,
+            lat / np.deg2rad(60.0),
             np.sin(th),
             np.cos(th),
+            np.cos(lat) * np.sin(th),
+            np.cos(lat) * np.cos(th),
             (np.asarray(radius, np.float64) - 0.055) / 0.045,
             (np.asarray(contrast, np.float64) - 0.6) / 0.3,
         ],
@@ -95,8 +99,8 @@ def _region(samples, k):
 
 def synthesize(ctx, samples, out, idx=None):
     """Full synthesis of samples (all, or the sorted indices idx) into out
-    [n][n_pix] (device): one soap_active_spectra call per spot with the
-    phases of its selected samples."""
+    [n][n_pix] (device): one soap_active_spectra_jobs call, one job per spot
+    with the phases of its selected samples."""
     n_per = samples.n_per
     idx = np.arange(samples.n) if idx is None else np.asarray(idx)
     if len(idx) == 0:
@@ -105,10 +109,9 @@ def synthesize(ctx, samples, out, idx=None):
     starts = np.flatnonzero(np.r_[True, spots[1:] != spots[:-1]])
     ends = np.r_[starts[1:], len(idx)]
     ph = samples.phases.reshape(-1)
-    for a, b in zip(starts, ends):
-        k = int(spots[a])
-        phases = np.ascontiguousarray(ph[idx[a:b]], dtype=np.float64)
-        soap_active_spectra(ctx, [_region(samples, k)], phases, EFFECT_TOT, out[a:b])
+    regions = [[_region(samples, int(spots[a]))] for a in starts]
+    phases = [ph[idx[a:b]] for a, b in zip(starts, ends)]
+    soap_active_spectra_jobs(ctx, regions, phases, EFFECT_TOT, out[: len(idx)])
     return out
 
 
@@ -170,7 +173,7 @@ class SurrogateModel:
         self.Q = quiet(ctx)
         self.basis = None
         self.calib = 1.0
-        self.threshold_kms = 1e-3  # 10 cm/s
+        self.threshold_kms = 1e-4  # 10 cm/s
 
     # -- data ---------------------------------------------------------------
     def project(self, F_dev):
@@ -183,12 +186,17 @@ class SurrogateModel:
         soap_pca_project(F_dev, self._centre_dev, self._V_dev, coef)
         return coef
 
-    def set_basis(self, mean, V, coef_train):
+    def set_basis(self, mean, V, coef_train, norm="global"):
         """Installs the basis and the normalisation of the training
-        coefficients (host [n][k])."""
+        coefficients (host [n][k]): centred, then divided by their own
+        standard deviations (norm="component") or all by the largest one
+        (norm="global", which keeps the loss proportional to the spectral
+        error)."""
         c = np.asarray(coef_train, np.float64)
         mu = c.mean(axis=0)
         sd = c.std(axis=0)
+        if norm == "global":
+            sd = np.full_like(sd, sd.max())
         sd = np.where(sd > 0, sd, 1.0)
         self.basis = Basis(np.asarray(mean, np.float64), np.asarray(V, np.float64), mu, sd)
         self._build_ccf_tables()
@@ -287,14 +295,21 @@ class SurrogateModel:
             out[fb] = plain_rv(self.ctx, samples, self.mask, sel)["rv_kms"]
         return out, fb, err
 
-    def calibrate(self, samples, idx, rv_plain_kms, bufs, quantile=0.95):
-        """Sets calib so that |surrogate - full| <= calib x spread holds for
-        the given quantile of the held-out samples; returns the raw ratios."""
+    def calibrate(self, samples, idx, rv_plain_kms, bufs, threshold_kms=None, margin=1.25):
+        """Sets calib from held-out samples with known full-synthesis RVs:
+        the smallest factor for which every held-out sample whose surrogate
+        error reaches the threshold is predicted to reach it too (times a
+        margin; the 99th percentile of |error| / spread when no sample
+        reaches the threshold).  Returns (|error|, spread) in km/s."""
         torch = self.torch
+        thr = self.threshold_kms if threshold_kms is None else threshold_kms
         x = torch.from_numpy(sample_features(samples, idx)).cuda()
         self.surrogate_rv(x, bufs, calib=1.0, threshold_kms=math.inf)
-        spread = bufs["err"].cpu().numpy()
-        rv = bufs["rv_kms"].cpu().numpy()
-        ratio = np.abs(rv - rv_plain_kms) / np.maximum(spread, 1e-12)
-        self.calib = float(np.quantile(ratio, quantile))
-        return ratio
+        spread = np.maximum(bufs["err"].cpu().numpy(), 1e-12)
+        err = np.abs(bufs["rv_kms"].cpu().numpy() - rv_plain_kms)
+        bad = err >= thr
+        if bad.any():
+            self.calib = float(margin * np.max(thr / spread[bad]))
+        else:
+            self.calib = float(np.quantile(err / spread, 0.99))
+        return err, spread
