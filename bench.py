@@ -73,6 +73,65 @@ def cpu_baseline(star, n_sample):
     }
 
 
+def surrogate_leg(args, L, W, np, torch):
+    """Surrogate vs full synthesis on the 20000-pixel window star: RVs per
+    second of each on the same held-out test samples (all inputs resident),
+    with the surrogate gated at 10 cm/s and its fallback samples run through
+    the full synthesis inside the timed region."""
+    from paper_2301_04259_amd import surrogate as S
+
+    def say(*a):
+        print("[bench] surrogate:", *a, file=sys.stderr, flush=True)
+
+    star = W.make_cfg5()
+    ctx = L.soap_grid_init(star)
+    n = args.surrogate_spots
+    train = W.cfg5_samples(n, 8, seed=5)
+    held = W.cfg5_samples(max(2, n // 10), 8, seed=6)
+    test = W.cfg5_samples(max(2, n // 10), 8, seed=7)
+    model, info = S.build(ctx, star.mask, train, held, epochs=args.surrogate_epochs,
+                          weighting=args.surrogate_weighting, log=say)
+    nt = (test.n // 16) * 16
+    idx = np.arange(nt)
+    bufs = model.alloc(nt)
+    x = torch.from_numpy(S.sample_features(test, idx)).cuda()
+    rv_plain = S.plain_rv(ctx, test, star.mask, idx)["rv_kms"]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, out
+
+    t_plain, _ = timed(lambda: S.plain_rv(ctx, test, star.mask, idx), 5)
+    t_kern, _ = timed(lambda: model.surrogate_rv(x, bufs), 5)
+    t_gated, (rv_s, fb, _) = timed(lambda: model.rv(test, idx, bufs), 5)
+    e = np.abs(rv_s - rv_plain) * 1e5
+    acc = ~fb
+    res = {
+        "workload": "20000 px window at 5000 A (R=115000), 300x300 disk, 20 mu bins, one spot per sample "
+        "(lat, lon, radius 0.01-0.10, contrast 0.3-0.9, phase); MLP 7-256-256-64 x 4 members, 64 PCA components",
+        "train_samples": train.n,
+        "test_samples": nt,
+        "plain_rv_per_s": nt / t_plain,
+        "surrogate_kernels_rv_per_s": nt / t_kern,
+        "gated_rv_per_s": nt / t_gated,
+        "surrogate_x": t_plain / t_gated,
+        "accepted_frac": float(acc.mean()),
+        "accepted_err_cms": {"rms": float(np.sqrt(np.mean(e[acc] ** 2))) if acc.any() else None,
+                             "max": float(e[acc].max()) if acc.any() else None,
+                             "frac_over_10": float(np.mean(e[acc] > 10.0)) if acc.any() else None},
+        "fallback_bit_exact": bool(np.array_equal(rv_s[fb], rv_plain[fb])),
+        "threshold_cms": 10.0,
+    }
+    res.update(info)
+    L.soap_destroy(ctx)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +139,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=16, help="phases timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--surrogate-spots", type=int, default=12500,
+                    help="training spots of the surrogate leg (8 phases each; 0 = skip the leg)")
+    ap.add_argument("--surrogate-epochs", type=int, default=300)
+    ap.add_argument("--surrogate-weighting", default="rv", choices=("rv", "component"),
+                    help="training-loss weight of each PCA coefficient: its RV sensitivity, or uniform after "
+                    "per-coefficient normalisation")
     ap.add_argument(
         "--copy-calib-mb",
         type=int,
@@ -182,6 +247,11 @@ def main():
     rvh = np.frombuffer(rv.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
     assert np.all(np.isfinite(rvh["rv_kms"])) and torch.isfinite(flux).all()
 
+    sur = None
+    if args.surrogate_spots > 0:
+        print("[bench] surrogate leg", file=sys.stderr, flush=True)
+        sur = surrogate_leg(args, L, W, np, torch)
+
     cpu = None
     if args.cpu_sample > 0:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -233,6 +303,7 @@ def main():
             "converged": int((rvh["status"] == 0).sum()),
         },
         "cpu_baseline": cpu,
+        "surrogate": sur,
     }
     print(json.dumps(out))
 

@@ -213,6 +213,26 @@ soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device,
 soap_status soap_ccf_linear_rv(soap_ctx* ctx, const float* coef, int64_t n, int32_t k, const double* base,
                                const double* basis, double* ccf_out, soap_rv* rv_out);
 
+/* Surrogate RVs with their gate in one pass, one sample per wave:
+ *   rv_out[i], rv_kms[i]: the fit of the CCF of the ensemble-mean prediction
+ *     coef[i] (the same CCF and fit as soap_ccf_linear_rv);
+ *   err_kms[i] = calib x the sample standard deviation over the members of
+ *     the first-order RV change their predictions cause: the fitted
+ *     parameters move by H^-1 J^T dy for a CCF change dy (H the Hessian of
+ *     half the squared residual sum at the fit, J the model's Jacobian), so
+ *     member e moves the RV by h . (members[e][i] - coef[i]) with
+ *     h = basis (J H^-1 e_rv);
+ *   fallback[i] = 1 when err_kms[i] >= threshold_kms or the fit did not
+ *     converge (err_kms is then +inf), else 0.
+ * coef[n][k], members[n_ens][n][k] float; base[n_v], basis[k][n_v] double
+ * on the context's mask grid (which must exist); outputs device arrays
+ * (rv_out and err_kms may be NULL).  n 1 .. 1<<24, n_ens 2 .. 16.
+ * Enqueues only.                                                             */
+soap_status soap_surrogate_rv(soap_ctx* ctx, const float* coef, const float* members, int64_t n, int32_t n_ens,
+                              int32_t k, const double* base, const double* basis, double calib,
+                              double threshold_kms, soap_rv* rv_out, double* rv_kms, double* err_kms,
+                              int32_t* fallback);
+
 /* Per-stage GPU time and traffic bookkeeping, for benchmarks.  With
  * profiling on, every stage kernel of soap_active_spectra and soap_ccf_rv is
  * bracketed by HIP events on the context's stream; soap_profile_read waits

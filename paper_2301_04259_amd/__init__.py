@@ -67,6 +67,7 @@ SYMBOLS = (
     "soap_profile_read",
     "soap_ccf_linear_rv",
     "soap_active_spectra_jobs",
+    "soap_surrogate_rv",
     "soap_surrogate_create",
     "soap_surrogate_n_params",
     "soap_surrogate_train_step",
@@ -188,6 +189,10 @@ _lib.soap_abi_version.restype = C.c_int32
 _lib.soap_ccf_linear_rv.argtypes = [_ctx_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
 _lib.soap_ccf_linear_rv.restype = C.c_int
+_lib.soap_surrogate_rv.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
+                                   C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]
+_lib.soap_surrogate_rv.restype = C.c_int
 _lib.soap_active_spectra_jobs.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_int32, C.c_void_p, C.c_int32]
 _lib.soap_active_spectra_jobs.restype = C.c_int
@@ -353,19 +358,45 @@ def soap_active_spectra(ctx, regions, phases, effect, out):
     return out
 
 
-def soap_active_spectra_jobs(ctx, job_regions, job_phases, effect, out):
-    """Jobs = (region list, phases) pairs of one star in one call; out rows
-    follow the jobs' phases in order."""
-    regs = [r for rl in job_regions for r in rl]
-    roff = np.zeros(len(job_regions) + 1, np.int32)
-    roff[1:] = np.cumsum([len(rl) for rl in job_regions])
-    ph = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64).reshape(-1) for p in job_phases]))
-    poff = np.zeros(len(job_phases) + 1, np.int32)
-    poff[1:] = np.cumsum([np.asarray(p).size for p in job_phases])
-    arr = _regions(regs)
+REGION_DTYPE = np.dtype(
+    [("type", "<i4"), ("reserved0", "<i4"), ("lat_deg", "<f8"), ("lon_deg", "<f8"), ("radius", "<f8"),
+     ("contrast", "<f8")]
+)
+
+
+def region_array(type_, lat_deg, lon_deg, radius, contrast):
+    """Host soap_region array from per-region columns (numpy)."""
+    a = np.zeros(len(np.atleast_1d(lat_deg)), dtype=REGION_DTYPE)
+    a["type"], a["lat_deg"], a["lon_deg"], a["radius"], a["contrast"] = type_, lat_deg, lon_deg, radius, contrast
+    return a
+
+
+def soap_active_spectra_jobs(ctx, job_regions, job_phases, effect, out, region_offsets=None, phase_offsets=None):
+    """Many (region list, phases) jobs of one star in one call; out rows
+    follow the jobs' phases in order.  Either lists of region lists and of
+    phase arrays, or (fast path) a REGION_DTYPE array, a flat phase array and
+    the two offset arrays."""
+    if region_offsets is None:
+        regs = [r for rl in job_regions for r in rl]
+        arr = np.zeros(len(regs), dtype=REGION_DTYPE)
+        for i, r in enumerate(regs):
+            arr[i] = (int(r.type), 0, float(r.lat_deg), float(r.lon_deg), float(r.radius), float(r.contrast))
+        roff = np.zeros(len(job_regions) + 1, np.int32)
+        roff[1:] = np.cumsum([len(rl) for rl in job_regions])
+        ph = np.concatenate([np.asarray(p, np.float64).reshape(-1) for p in job_phases])
+        poff = np.zeros(len(job_phases) + 1, np.int32)
+        poff[1:] = np.cumsum([np.asarray(p).size for p in job_phases])
+    else:
+        arr = np.ascontiguousarray(job_regions, dtype=REGION_DTYPE)
+        ph = job_phases
+        roff = np.ascontiguousarray(region_offsets, dtype=np.int32)
+        poff = np.ascontiguousarray(phase_offsets, dtype=np.int32)
+    ph = np.ascontiguousarray(ph, dtype=np.float64)
+    if len(arr) == 0:
+        arr = np.zeros(1, dtype=REGION_DTYPE)
     p, dev = _ptr(out)
-    st = _lib.soap_active_spectra_jobs(ctx.handle, C.cast(arr, C.c_void_p), roff.ctypes.data, ph.ctypes.data,
-                                       poff.ctypes.data, len(job_regions), int(effect), p, dev)
+    st = _lib.soap_active_spectra_jobs(ctx.handle, arr.ctypes.data, roff.ctypes.data, ph.ctypes.data,
+                                       poff.ctypes.data, len(roff) - 1, int(effect), p, dev)
     _check(st, ctx.handle)
     return out
 
@@ -548,3 +579,15 @@ def soap_surrogate_gate(rv, n, n_ens, calib, threshold_kms, rv_kms, fallback, er
                                   _dptr(rv_kms, "rv_kms"), _dptr(err_kms, "err_kms"), _dptr(fallback, "fallback"),
                                   _stream_handle(stream))
     _sg_check(st, None)
+
+
+def soap_surrogate_rv(ctx, coef, members, base, basis, calib, threshold_kms, rv_kms, fallback, err_kms=None,
+                      rv_out=None):
+    """Fused surrogate RV + gate (see soap.h); members [n_ens][n][k]."""
+    n, k = int(coef.shape[0]), int(coef.shape[1])
+    n_ens = int(members.shape[0]) if members.dim() == 3 else int(members.shape[0]) // n
+    st = _lib.soap_surrogate_rv(ctx.handle, _dptr(coef, "coef"), _dptr(members, "members"), n, n_ens, k,
+                                _dptr(base, "base"), _dptr(basis, "basis"), float(calib), float(threshold_kms),
+                                _dptr(rv_out, "rv_out"), _dptr(rv_kms, "rv_kms"), _dptr(err_kms, "err_kms"),
+                                _dptr(fallback, "fallback"))
+    _check(st, ctx.handle)

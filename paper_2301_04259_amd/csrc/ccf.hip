@@ -293,6 +293,122 @@ __device__ bool gf_solve(const double S[20], bool newton, double lam, double x[4
   return true;
 }
 
+// Gaussian fit of one CCF held by the calling wave (y[t] = CCF point
+// lane + 64 t); returns the result record and leaves the parameters in p and
+// the last sums (gf_eval) in S.  Damped Newton / Levenberg-Marquardt as
+// described at k_ccf_fit.
+__device__ soap_rv fit_wave(const double (&y)[GF_MAXPT], int n_v, double v0, double dv, double p[4],
+                            double S[20]) {
+  const int lane = threadIdx.x & 63;
+  // start values: max, first argmin, half-depth width
+  double ymax = -1e308, ymin = 1e308;
+  int kmin = n_v;
+#pragma unroll
+  for (int t = 0; t < GF_MAXPT; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n_v) {
+      ymax = fmax(ymax, y[t]);
+      if (y[t] < ymin) {
+        ymin = y[t];
+        kmin = i;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
+    const double om = __shfl_xor(ymin, off, 64);
+    const int ok = __shfl_xor(kmin, off, 64);
+    if (om < ymin || (om == ymin && ok < kmin)) {
+      ymin = om;
+      kmin = ok;
+    }
+  }
+  const double c0 = ymax;
+  const double a0 = c0 - ymin;
+  const double half = c0 - 0.5 * a0;
+  int first = n_v, last = -1;
+#pragma unroll
+  for (int t = 0; t < GF_MAXPT; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n_v && y[t] <= half) {
+      first = min(first, i);
+      last = max(last, i);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    first = min(first, __shfl_xor(first, off, 64));
+    last = max(last, __shfl_xor(last, off, 64));
+  }
+  const double width = (last > first) ? dv * (last - first) : dv;
+  p[0] = c0;
+  p[1] = a0;
+  p[2] = v0 + dv * kmin;
+  p[3] = fmax(width, dv) / FWHM_PER_SIGMA;
+
+  soap_rv res;
+  res.status = 0;
+  if (!(a0 > 0.0) || !isfinite(c0) || !isfinite(ymin)) {
+    res.status = 2;
+    res.iters = 0;
+  } else {
+    gf_eval(y, n_v, v0, dv, p, S);
+    double lam = 1e-3;
+    int it = 0;
+    res.status = 1;
+    for (; it < 100; ++it) {
+      double x[4];
+      double Sn[20];
+      bool ok = gf_solve(S, true, lam, x) || gf_solve(S, false, lam, x);
+      bool tiny = false;
+      if (ok) {
+        const double sig = fabs(p[3]);
+        tiny = fabs(x[0]) <= 1e-10 * fabs(p[0]) && fabs(x[1]) <= 1e-10 * fabs(p[1]) &&
+               fabs(x[2]) <= 1e-10 * sig && fabs(x[3]) <= 1e-10 * sig;
+        double pn[4];
+        for (int q = 0; q < 4; ++q) pn[q] = p[q] + x[q];
+        gf_eval(y, n_v, v0, dv, pn, Sn);
+        if (Sn[0] <= S[0]) {
+          const double dchi = S[0] - Sn[0];
+          for (int q = 0; q < 4; ++q) p[q] = pn[q];
+          for (int q = 0; q < 20; ++q) S[q] = Sn[q];
+          lam = (lam > 1e-9) ? lam * 0.1 : 0.0;
+          const double sgn = fabs(p[3]);
+          const bool floor_hit =
+              dchi <= 1e-15 * S[0] && fabs(x[2]) <= 1e-9 * sgn && fabs(x[3]) <= 1e-9 * sgn;
+          if (tiny || floor_hit) {
+            res.status = 0;
+            ++it;
+            break;
+          }
+          continue;
+        }
+      }
+      if (tiny) {  // a rounding-size step that does not lower chi^2
+        res.status = 0;
+        ++it;
+        break;
+      }
+      lam = (lam > 0.0) ? lam * 10.0 : 1e-6;
+      if (lam > 1e10) {
+        res.status = 0;
+        ++it;
+        break;
+      }
+    }
+    res.iters = it;
+    res.chi2 = S[0];
+  }
+  res.rv_kms = p[2];
+  res.sigma_kms = fabs(p[3]);
+  res.fwhm_kms = FWHM_PER_SIGMA * fabs(p[3]);
+  res.c0 = p[0];
+  res.amp = p[1];
+  if (res.status == 2) res.chi2 = 0.0;
+  return res;
+}
+
 }  // namespace
 
 // One block of four waves per spectrum.  The waves first add the line
@@ -360,110 +476,8 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
     if (i < n_v) ccf[s * n_v + i] = a;
   }
   if (!fit) return;
-  // start values: max, first argmin, half-depth width
-  double ymax = -1e308, ymin = 1e308;
-  int kmin = n_v;
-#pragma unroll
-  for (int t = 0; t < GF_MAXPT; ++t) {
-    const int i = lane + 64 * t;
-    if (i < n_v) {
-      ymax = fmax(ymax, y[t]);
-      if (y[t] < ymin) {
-        ymin = y[t];
-        kmin = i;
-      }
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
-    const double om = __shfl_xor(ymin, off, 64);
-    const int ok = __shfl_xor(kmin, off, 64);
-    if (om < ymin || (om == ymin && ok < kmin)) {
-      ymin = om;
-      kmin = ok;
-    }
-  }
-  const double c0 = ymax;
-  const double a0 = c0 - ymin;
-  const double half = c0 - 0.5 * a0;
-  int first = n_v, last = -1;
-#pragma unroll
-  for (int t = 0; t < GF_MAXPT; ++t) {
-    const int i = lane + 64 * t;
-    if (i < n_v && y[t] <= half) {
-      first = min(first, i);
-      last = max(last, i);
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    first = min(first, __shfl_xor(first, off, 64));
-    last = max(last, __shfl_xor(last, off, 64));
-  }
-  const double width = (last > first) ? dv * (last - first) : dv;
-  double p[4] = {c0, a0, v0 + dv * kmin, fmax(width, dv) / FWHM_PER_SIGMA};
-
-  soap_rv res;
-  res.status = 0;
-  if (!(a0 > 0.0) || !isfinite(c0) || !isfinite(ymin)) {
-    res.status = 2;
-    res.iters = 0;
-  } else {
-    double S[20];
-    gf_eval(y, n_v, v0, dv, p, S);
-    double lam = 1e-3;
-    int it = 0;
-    res.status = 1;
-    for (; it < 100; ++it) {
-      double x[4];
-      double Sn[20];
-      bool ok = gf_solve(S, true, lam, x) || gf_solve(S, false, lam, x);
-      bool tiny = false;
-      if (ok) {
-        const double sig = fabs(p[3]);
-        tiny = fabs(x[0]) <= 1e-10 * fabs(p[0]) && fabs(x[1]) <= 1e-10 * fabs(p[1]) &&
-               fabs(x[2]) <= 1e-10 * sig && fabs(x[3]) <= 1e-10 * sig;
-        double pn[4];
-        for (int q = 0; q < 4; ++q) pn[q] = p[q] + x[q];
-        gf_eval(y, n_v, v0, dv, pn, Sn);
-        if (Sn[0] <= S[0]) {
-          const double dchi = S[0] - Sn[0];
-          for (int q = 0; q < 4; ++q) p[q] = pn[q];
-          for (int q = 0; q < 20; ++q) S[q] = Sn[q];
-          lam = (lam > 1e-9) ? lam * 0.1 : 0.0;
-          const double sgn = fabs(p[3]);
-          const bool floor_hit =
-              dchi <= 1e-15 * S[0] && fabs(x[2]) <= 1e-9 * sgn && fabs(x[3]) <= 1e-9 * sgn;
-          if (tiny || floor_hit) {
-            res.status = 0;
-            ++it;
-            break;
-          }
-          continue;
-        }
-      }
-      if (tiny) {  // a rounding-size step that does not lower chi^2
-        res.status = 0;
-        ++it;
-        break;
-      }
-      lam = (lam > 0.0) ? lam * 10.0 : 1e-6;
-      if (lam > 1e10) {
-        res.status = 0;
-        ++it;
-        break;
-      }
-    }
-    res.iters = it;
-    res.chi2 = S[0];
-  }
-  res.rv_kms = p[2];
-  res.sigma_kms = fabs(p[3]);
-  res.fwhm_kms = FWHM_PER_SIGMA * fabs(p[3]);
-  res.c0 = p[0];
-  res.amp = p[1];
-  if (res.status == 2) res.chi2 = 0.0;
+  double p[4], S[20];
+  const soap_rv res = fit_wave(y, n_v, v0, dv, p, S);
   if (lane == 0) out[s] = res;
 }
 
@@ -532,6 +546,134 @@ __global__ void __launch_bounds__(256) k_ccf_linear(int64_t n, int k, int n_v, c
     }
     if (v < n_v) ccf[i * n_v + v] = a;
   }
+}
+
+constexpr int SG_MAX_ENS = 16;
+
+// Surrogate RVs and their gate, one wave per sample (64-thread blocks):
+//   1. CCF of the ensemble-mean prediction by linearity, base + sum_k
+//      coef[i][k] basis[k] (double, increasing k: the same sums as
+//      k_ccf_linear), and its Gaussian fit (fit_wave);
+//   2. first-order RV change of each member: the fitted parameters move by
+//      dp = H^-1 J^T dy for a CCF change dy (H the Hessian of chi^2 / 2 at
+//      the fit, J the model Jacobian), so dRV = g . dy with
+//      g = J H^-1 e_mu, and dy_e = sum_k (y_e,k - coef_k) basis[k], i.e.
+//      dRV_e = sum_k h_k (y_e,k - coef_k) with h = basis g;
+//   3. err = calib x sample standard deviation of dRV_e over the members;
+//      fallback when err is not below thr or the fit did not converge.
+__global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, double v0, double dv,
+                                              const float* __restrict__ coef, const float* __restrict__ members,
+                                              const double* __restrict__ base, const double* __restrict__ basis,
+                                              double calib, double thr, soap_rv* __restrict__ out,
+                                              double* __restrict__ rv_kms, double* __restrict__ err_kms,
+                                              int* __restrict__ fallback) {
+  __shared__ double s_c[64];
+  __shared__ double s_g[GF_MAXPT * 64];
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  double y[GF_MAXPT];
+#pragma unroll
+  for (int t = 0; t < GF_MAXPT; ++t) {
+    const int v = lane + 64 * t;
+    y[t] = v < n_v ? base[v] : 0.0;
+  }
+  for (int k0 = 0; k0 < k; k0 += 64) {
+    __syncthreads();
+    if (k0 + lane < k) s_c[lane] = (double)coef[i * k + k0 + lane];
+    __syncthreads();
+    const int kn = min(64, k - k0);
+    for (int j = 0; j < kn; ++j) {
+      const double cj = s_c[j];
+      const double* bj = basis + (int64_t)(k0 + j) * n_v;
+#pragma unroll
+      for (int t = 0; t < GF_MAXPT; ++t) {
+        const int v = lane + 64 * t;
+        if (v < n_v) y[t] = fma(cj, bj[v], y[t]);
+      }
+    }
+  }
+  double p[4], S[20];
+  soap_rv res = fit_wave(y, n_v, v0, dv, p, S);
+  bool bad = res.status != 0;
+  double err = 0.0;
+  if (!bad) {
+    // z = H^-1 e_mu (full Hessian; J^T J where that is not positive definite)
+    double Sz[20];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) Sz[q] = S[q];
+    Sz[1] = 0.0;
+    Sz[2] = 0.0;
+    Sz[3] = -1.0;  // gf_solve solves A x = -S[1..4]
+    Sz[4] = 0.0;
+    double z[4];
+    bool ok = gf_solve(Sz, true, 0.0, z) || gf_solve(Sz, false, 0.0, z);
+    if (!ok) {
+      bad = true;
+    } else {
+      const double is = 1.0 / p[3];
+      const double is2 = is * is;
+#pragma unroll
+      for (int t = 0; t < GF_MAXPT; ++t) {
+        const int v = lane + 64 * t;
+        if (v < n_v) {
+          const double d = v0 + dv * v - p[2];
+          const double zz = d * d * is2;
+          const double e = exp(-0.5 * zz);
+          const double ae = p[1] * e;
+          s_g[v] = z[0] - e * z[1] - ae * d * is2 * z[2] - ae * zz * is * z[3];
+        }
+      }
+      __syncthreads();
+      // h_k = sum_v basis[k][v] g_v, then dRV_e = sum_k h_k (y_e,k - coef_k)
+      double dr[SG_MAX_ENS];
+#pragma unroll
+      for (int e = 0; e < SG_MAX_ENS; ++e) dr[e] = 0.0;
+      for (int k0 = 0; k0 < k; k0 += 64) {
+        const int kk = k0 + lane;
+        double h = 0.0;
+        if (kk < k) {
+          const double* bk = basis + (int64_t)kk * n_v;
+          for (int v = 0; v < n_v; ++v) h = fma(bk[v], s_g[v], h);
+        }
+        const double cm = kk < k ? (double)coef[i * k + kk] : 0.0;
+#pragma unroll
+        for (int e = 0; e < SG_MAX_ENS; ++e) {
+          if (e < E) {
+            const double ye = kk < k ? (double)members[((int64_t)e * n + i) * k + kk] : 0.0;
+            dr[e] += h * (ye - cm);
+          }
+        }
+      }
+      double m = 0.0;
+#pragma unroll
+      for (int e = 0; e < SG_MAX_ENS; ++e) {
+        if (e < E) {  // uniform
+          dr[e] = wave_sum_f64(dr[e]);
+          m += dr[e];
+        }
+      }
+      m /= (double)E;
+      double var = 0.0;
+#pragma unroll
+      for (int e = 0; e < SG_MAX_ENS; ++e)
+        if (e < E) var += (dr[e] - m) * (dr[e] - m);
+      err = calib * sqrt(var / (double)(E - 1));
+    }
+  }
+  if (lane == 0) {
+    if (out) out[i] = res;
+    rv_kms[i] = res.rv_kms;
+    if (err_kms) err_kms[i] = bad ? INFINITY : err;
+    fallback[i] = (bad || !(err < thr)) ? 1 : 0;
+  }
+}
+
+hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
+                        const double* d_base, const double* d_basis, double calib, double thr, soap_rv* d_rv,
+                        double* d_rv_kms, double* d_err, int* d_fallback) {
+  hipLaunchKernelGGL(k_sg_rv, dim3((unsigned)n), dim3(64), 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,
+                     c->mask_dv, d_coef, d_members, d_base, d_basis, calib, thr, d_rv, d_rv_kms, d_err, d_fallback);
+  return hipGetLastError();
 }
 
 hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, int k, const double* d_base,

@@ -711,6 +711,26 @@ SOAP_API soap_status soap_ccf_linear_rv(soap_ctx* c, const float* coef, int64_t 
   return SOAP_OK;
 }
 
+SOAP_API soap_status soap_surrogate_rv(soap_ctx* c, const float* coef, const float* members, int64_t n,
+                                       int32_t n_ens, int32_t k, const double* base, const double* basis,
+                                       double calib, double threshold_kms, soap_rv* rv_out, double* rv_kms,
+                                       double* err_kms, int32_t* fallback) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(coef && members && base && basis && rv_kms && fallback, "a required device array is NULL");
+  ARG_CHECK(n >= 1 && n <= (int64_t(1) << 24), "n must be in [1, 2^24]");
+  ARG_CHECK(k >= 1 && k <= 4096, "k must be in [1, 4096]");
+  ARG_CHECK(n_ens >= 2 && n_ens <= 16, "n_ens must be in [2, 16]");
+  ARG_CHECK(is_finite(calib) && calib >= 0.0 && !std::isnan(threshold_kms), "calib or threshold invalid");
+  if (!c->mask_valid) {
+    setf(c->err, "no mask yet: call soap_ccf_rv with the mask first");
+    return SOAP_ERR_STATE;
+  }
+  HIP_TRY(soap::launch_sg_rv(c, coef, members, n, n_ens, k, base, basis, calib, threshold_kms, rv_out, rv_kms,
+                             err_kms, fallback));
+  return SOAP_OK;
+}
+
 SOAP_API soap_status soap_profile_enable(soap_ctx* c, int32_t on) {
   if (!c) return SOAP_ERR_ARG;
   HIP_TRY(hipStreamSynchronize(c->side));

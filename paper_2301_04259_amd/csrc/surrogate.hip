@@ -17,6 +17,7 @@
 #include <cmath>
 
 #include "surrogate_internal.hpp"
+#include "wave.hpp"
 
 namespace soap {
 
@@ -93,23 +94,27 @@ __global__ void k_pack_input(int B, int n_in, int K0, const float* __restrict__ 
   X[t] = (__bf16)(k < n_in ? x[(int64_t)i * n_in + k] : 0.f);
 }
 
-// Squared error per (member, row) and dY = 2 (y - t) / (B n_out) in BF16.
-__global__ void k_mse(int B, int n_out, int E, const float* __restrict__ Y, const float* __restrict__ T,
-                      __bf16* __restrict__ dY, float* __restrict__ row_se) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Squared error per (member, row) and dY = 2 (y - t) / (B n_out) in BF16: one
+// wave per row (lanes over outputs, fixed-order wave sum), four rows a block
+__global__ void __launch_bounds__(256) k_mse(int B, int n_out, const float* __restrict__ Y,
+                                             const float* __restrict__ T, __bf16* __restrict__ dY,
+                                             float* __restrict__ row_se) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int e = blockIdx.y;
-  if (i >= B) return;
+  if (i >= B) return;  // whole wave
   const float sc = 2.0f / ((float)B * (float)n_out);
-  float se = 0.f;
   const float* y = Y + ((int64_t)e * B + i) * n_out;
   const float* t = T + (int64_t)i * n_out;
   __bf16* d = dY + ((int64_t)e * B + i) * n_out;
-  for (int j = 0; j < n_out; ++j) {
+  float se = 0.f;
+  for (int j = lane; j < n_out; j += 64) {
     const float df = y[j] - t[j];
-    se += df * df;
+    se = fmaf(df, df, se);
     d[j] = (__bf16)(sc * df);
   }
-  row_se[(int64_t)e * B + i] = se;
+  const double tot = wave_sum_f64((double)se);
+  if (lane == 0) row_se[(int64_t)e * B + i] = (float)tot;
 }
 
 // per member: loss = sum of row_se / (B n_out), rows added in order by one
@@ -129,14 +134,34 @@ __global__ void __launch_bounds__(256) k_loss_sum(int B, int n_out, const float*
   if (threadIdx.x == 0) loss[e] = s[0] / ((float)B * (float)n_out);
 }
 
-// db[j] = sum_i D[i][j] per member (rows in order)
-__global__ void k_colsum(int B, int N, const float* __restrict__ D, int64_t sD, float* __restrict__ db,
-                         int64_t sdb) {
+// db[j] = sum_i D[i][j] per member, in two fixed-order stages: partial sums
+// over chunks of SG_COLSUM_ROWS rows (block: 64 columns x 4 row phases,
+// combined in phase order), then the chunks in order
+__global__ void __launch_bounds__(256) k_colsum_part(int B, int N, const float* __restrict__ D, int64_t sD,
+                                                     float* __restrict__ part) {
+  __shared__ float s[4][64];
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  const int c = blockIdx.y, e = blockIdx.z;
+  const int r0 = c * SG_COLSUM_ROWS, r1 = min(B, r0 + SG_COLSUM_ROWS);
+  float a = 0.f;
+  if (col < N)
+    for (int i = r0 + g; i < r1; i += 4) a += D[e * sD + (int64_t)i * N + col];
+  s[g][threadIdx.x & 63] = a;
+  __syncthreads();
+  if (g == 0 && col < N) {
+    const int l = threadIdx.x;
+    part[((int64_t)e * gridDim.y + c) * N + col] = ((s[0][l] + s[1][l]) + s[2][l]) + s[3][l];
+  }
+}
+
+__global__ void k_colsum_final(int n_chunks, int N, const float* __restrict__ part, float* __restrict__ db,
+                               int64_t sdb) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int e = blockIdx.y;
   if (j >= N) return;
   float a = 0.f;
-  for (int i = 0; i < B; ++i) a += D[e * sD + (int64_t)i * N + j];
+  for (int c = 0; c < n_chunks; ++c) a += part[((int64_t)e * n_chunks + c) * N + j];
   db[e * sdb + j] = a;
 }
 
@@ -262,6 +287,16 @@ hipError_t mm(hipStream_t st, int E, int M, int N, int K, const __bf16* A, int l
 
 inline dim3 blocks(int64_t n, int t = 256) { return dim3((unsigned)((n + t - 1) / t)); }
 
+hipError_t colsum(hipStream_t st, int E, int B, int N, const float* D, int64_t sD, float* part, float* db,
+                  int64_t sdb) {
+  const int nc = (B + SG_COLSUM_ROWS - 1) / SG_COLSUM_ROWS;
+  hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, nc, E), dim3(256), 0, st, B, N, D, sD, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum_final, dim3((N + 255) / 256, E), dim3(256), 0, st, nc, N, part, db, sdb);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 #define SG_TRY(x)                              \
@@ -295,7 +330,7 @@ hipError_t sg_backward(soap_surrogate* s, const float* target, int B) {
   const int E = s->n_ens, H = s->hidden, O = s->n_out;
   hipStream_t st = s->stream;
   const int64_t sP = L.n_params, sBH = (int64_t)B * H, sBO = (int64_t)B * O;
-  hipLaunchKernelGGL(k_mse, dim3((B + 255) / 256, E), dim3(256), 0, st, B, O, E, s->Y, target, s->dY, s->row_se);
+  hipLaunchKernelGGL(k_mse, dim3((B + 3) / 4, E), dim3(256), 0, st, B, O, s->Y, target, s->dY, s->row_se);
   SG_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_loss_sum, dim3(E), dim3(256), 0, st, B, O, s->row_se, s->loss);
   SG_TRY(hipGetLastError());
@@ -305,22 +340,19 @@ hipError_t sg_backward(soap_surrogate* s, const float* target, int B) {
   hipLaunchKernelGGL(k_bf16_to_f32, blocks((int64_t)E * B * O), dim3(256), 0, st, (int64_t)E * B * O, s->dY,
                      s->dYf);
   SG_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_colsum, dim3((O + 63) / 64, E), dim3(64), 0, st, B, O, s->dYf, sBO, s->G + L.b3, sP);
-  SG_TRY(hipGetLastError());
+  SG_TRY(colsum(st, E, B, O, s->dYf, sBO, s->colpart, s->G + L.b3, sP));
   // dZ2 = (dY W3^T) SiLU'(Z2); dW2 = H1^T dZ2; db2 = colsum dZ2
   SG_TRY((mm<false, true, MM_DHIDDEN>(st, E, B, H, O, s->dY, O, sBO, s->Pb + L.W3, O, sP, nullptr, 0, s->dZf, H, sBH,
                                       s->dZb, sBH, s->Z2, sBH)));
   SG_TRY((mm<true, false, MM_PLAIN>(st, E, H, H, B, s->H1, H, sBH, s->dZb, H, sBH, nullptr, 0, s->G + L.W2, H, sP,
                                     nullptr, 0, nullptr, 0)));
-  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64, E), dim3(64), 0, st, B, H, s->dZf, sBH, s->G + L.b2, sP);
-  SG_TRY(hipGetLastError());
+  SG_TRY(colsum(st, E, B, H, s->dZf, sBH, s->colpart, s->G + L.b2, sP));
   // dZ1 = (dZ2 W2^T) SiLU'(Z1); dW1 = X^T dZ1; db1 = colsum dZ1
   SG_TRY((mm<false, true, MM_DHIDDEN>(st, E, B, H, H, s->dZb, H, sBH, s->Pb + L.W2, H, sP, nullptr, 0, s->dZf2, H,
                                       sBH, s->dZb2, sBH, s->Z1, sBH)));
   SG_TRY((mm<true, false, MM_PLAIN>(st, E, SG_K0, H, B, s->X, SG_K0, 0, s->dZb2, H, sBH, nullptr, 0, s->G + L.W1, H,
                                     sP, nullptr, 0, nullptr, 0)));
-  hipLaunchKernelGGL(k_colsum, dim3((H + 63) / 64, E), dim3(64), 0, st, B, H, s->dZf2, sBH, s->G + L.b1, sP);
-  return hipGetLastError();
+  return colsum(st, E, B, H, s->dZf2, sBH, s->colpart, s->G + L.b1, sP);
 }
 
 hipError_t sg_adam(soap_surrogate* s, float lr) {

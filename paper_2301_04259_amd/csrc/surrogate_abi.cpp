@@ -103,7 +103,7 @@ hipError_t alloc(T*& p, size_t n) {
 
 void free_all(soap_surrogate* s) {
   void* ps[] = {s->P, s->G, s->M, s->V, s->Pb, s->X, s->Z1, s->Z2, s->H1, s->H2, s->Y, s->dY, s->dYf,
-                s->dZf, s->dZf2, s->dZb, s->dZb2, s->row_se, s->loss};
+                s->dZf, s->dZf2, s->dZb, s->dZb2, s->row_se, s->loss, s->colpart};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
@@ -125,6 +125,7 @@ soap_status ensure_batch(soap_surrogate* s, int B) {
   SG_HIP(alloc(s->dZb, E * B * H));
   SG_HIP(alloc(s->dZb2, E * B * H));
   SG_HIP(alloc(s->row_se, E * B));
+  SG_HIP(alloc(s->colpart, E * (((size_t)B + soap::SG_COLSUM_ROWS - 1) / soap::SG_COLSUM_ROWS) * std::max(H, O)));
   s->cap = B;
   return SOAP_OK;
 }

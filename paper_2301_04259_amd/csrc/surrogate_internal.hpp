@@ -10,7 +10,8 @@
 
 namespace soap {
 
-constexpr int SG_K0 = 32;  // input width padded to one MFMA K step
+constexpr int SG_K0 = 32;            // input width padded to one MFMA K step
+constexpr int SG_COLSUM_ROWS = 128;  // rows per partial column sum
 
 enum { MM_PLAIN = 0, MM_HIDDEN = 1, MM_OUTPUT = 2, MM_DHIDDEN = 3 };
 
@@ -46,6 +47,7 @@ struct soap_surrogate {
   float *dZf = nullptr, *dZf2 = nullptr;  // [E][cap][H]
   __bf16 *dZb = nullptr, *dZb2 = nullptr;
   float* row_se = nullptr;  // [E][cap]
+  float* colpart = nullptr; // [E][cap / SG_COLSUM_ROWS][max(H, O)] partial column sums
   float* loss = nullptr;    // [E]
 };
 

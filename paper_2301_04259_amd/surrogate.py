@@ -16,8 +16,9 @@ section 4.1):
                   factor that turns the members' RV spread into a predicted
                   error bound (a quantile of |error| / spread)
   rv              surrogate RVs of a batch: soap_surrogate_predict ->
-                  soap_ccf_linear_rv (CCF of the quiet-plus-basis expansion,
-                  by linearity) -> soap_surrogate_gate; samples whose
+                  soap_surrogate_rv (CCF of the quiet-plus-basis expansion by
+                  linearity, its fit, the members' first-order RV spread and
+                  the gate); samples whose
                   predicted error is not below the threshold go through the
                   full synthesis (soap_active_spectra_jobs + soap_ccf_rv)
 
@@ -31,7 +32,6 @@ about unit range.
 from __future__ import annotations
 
 import math
-from collections import namedtuple
 from dataclasses import dataclass
 
 import numpy as np
@@ -41,19 +41,17 @@ from . import (
     PREC_FP32,
     RV_DTYPE,
     SPOT,
+    region_array,
     soap_active_spectra_jobs,
-    soap_ccf_linear_rv,
     soap_ccf_rv,
     soap_quiet_spectrum,
     soap_surrogate_create,
-    soap_surrogate_gate,
+    soap_surrogate_rv,
     soap_surrogate_predict,
     soap_surrogate_train_step,
 )
 
 N_FEATURES = 7
-
-Region = namedtuple("Region", "type lat_deg lon_deg radius contrast")
 
 
 def _torch():
@@ -92,11 +90,6 @@ def sample_features(samples, idx=None):
                     samples.phases.reshape(-1)[i])
 
 
-def _region(samples, k):
-    return Region(SPOT, float(samples.lat_deg[k]), float(samples.lon_deg[k]), float(samples.radius[k]),
-                  float(samples.contrast[k]))
-
-
 def synthesize(ctx, samples, out, idx=None):
     """Full synthesis of samples (all, or the sorted indices idx) into out
     [n][n_pix] (device): one soap_active_spectra_jobs call, one job per spot
@@ -109,9 +102,12 @@ def synthesize(ctx, samples, out, idx=None):
     starts = np.flatnonzero(np.r_[True, spots[1:] != spots[:-1]])
     ends = np.r_[starts[1:], len(idx)]
     ph = samples.phases.reshape(-1)
-    regions = [[_region(samples, int(spots[a]))] for a in starts]
-    phases = [ph[idx[a:b]] for a, b in zip(starts, ends)]
-    soap_active_spectra_jobs(ctx, regions, phases, EFFECT_TOT, out[: len(idx)])
+    k = spots[starts]
+    regions = region_array(SPOT, samples.lat_deg[k], samples.lon_deg[k], samples.radius[k], samples.contrast[k])
+    roff = np.arange(len(starts) + 1, dtype=np.int32)
+    poff = np.r_[starts, len(idx)].astype(np.int32)
+    soap_active_spectra_jobs(ctx, regions, ph[idx], EFFECT_TOT, out[: len(idx)], region_offsets=roff,
+                             phase_offsets=poff)
     return out
 
 
@@ -185,6 +181,33 @@ class SurrogateModel:
         coef = torch.empty((n, self.k), dtype=torch.float32, device="cuda")
         soap_pca_project(F_dev, self._centre_dev, self._V_dev, coef)
         return coef
+
+    def rv_weights(self, Yn, eps=0.05):
+        """RMS over the rows of Yn (normalised coefficients, host [m][k]) of
+        the RV change per unit change of each coefficient, by central
+        differences through soap_ccf_linear_rv."""
+        torch = self.torch
+        from . import soap_ccf_linear_rv
+
+        m, k = Yn.shape
+        rows = np.repeat(np.asarray(Yn, np.float32)[:, None, :], 2 * k, axis=1)
+        for j in range(k):
+            rows[:, 2 * j, j] += eps
+            rows[:, 2 * j + 1, j] -= eps
+        rows = rows.reshape(-1, k)
+        rv = torch.empty(len(rows) * RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        soap_ccf_linear_rv(self.ctx, torch.from_numpy(np.ascontiguousarray(rows)).cuda(), self.base_ccf,
+                           self.basis_ccf, None, rv)
+        r = np.frombuffer(rv.cpu().numpy().tobytes(), dtype=RV_DTYPE)["rv_kms"].reshape(m, k, 2)
+        return np.sqrt(np.mean(((r[:, :, 0] - r[:, :, 1]) / (2 * eps)) ** 2, axis=0))
+
+    def reweight(self, w):
+        """Rescales the normalised coefficients by w / rms(w), so that the
+        training loss weighs each coefficient by its RV sensitivity."""
+        b = self.basis
+        w = np.maximum(np.asarray(w, np.float64), 1e-6 * np.max(w))
+        b.sigma = b.sigma * np.sqrt(np.mean(w * w)) / w
+        self._build_ccf_tables()
 
     def set_basis(self, mean, V, coef_train, norm="global"):
         """Installs the basis and the normalisation of the training
@@ -271,14 +294,15 @@ class SurrogateModel:
         )
 
     def surrogate_rv(self, x_dev, bufs, calib=None, threshold_kms=None):
-        """Enqueues predict -> linear CCF fits -> gate for x_dev [n][5]."""
+        """Enqueues predict -> fused mean-CCF fit, member RV spread and gate
+        for x_dev [n][features]."""
         n = bufs["n"]
         Y = bufs["Y"]
         soap_surrogate_predict(self.net, x_dev, Y[:n], Y[n:])
-        soap_ccf_linear_rv(self.ctx, Y, self.base_ccf, self.basis_ccf, None, bufs["rv"])
-        soap_surrogate_gate(bufs["rv"], n, self.n_ens, self.calib if calib is None else calib,
-                            self.threshold_kms if threshold_kms is None else threshold_kms, bufs["rv_kms"],
-                            bufs["fallback"], err_kms=bufs["err"])
+        soap_surrogate_rv(self.ctx, Y[:n], Y[n:], self.base_ccf, self.basis_ccf,
+                          self.calib if calib is None else calib,
+                          self.threshold_kms if threshold_kms is None else threshold_kms, bufs["rv_kms"],
+                          bufs["fallback"], err_kms=bufs["err"], rv_out=bufs["rv"])
 
     def rv(self, samples, idx, bufs, threshold_kms=None):
         """Gated RVs (km/s, host float64) of samples[idx]; idx sorted, its
@@ -313,3 +337,50 @@ class SurrogateModel:
         else:
             self.calib = float(np.quantile(err / spread, 0.99))
         return err, spread
+
+
+def build(ctx, mask, train, heldout, n_components=64, hidden=256, n_ensemble=4, epochs=100, batch=512,
+          svd_subset=2048, seed=0, weighting="rv", log=None):
+    """Data set, basis, training and gate calibration of a surrogate for the
+    star of ctx (an FP32 context) from SpotSamples train / heldout.  Returns
+    the model and a dict of what it took."""
+    torch = _torch()
+    say = log or (lambda *a: None)
+    info = {}
+    model = SurrogateModel(ctx, mask, n_components, hidden, n_ensemble, seed)
+    F = torch.empty((train.n, ctx.n_pix), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t = __import__("time").perf_counter()
+    synthesize(ctx, train, F)
+    torch.cuda.synchronize()
+    info["synth_s"] = __import__("time").perf_counter() - t
+    say(f"synthesised {train.n} training spectra in {info['synth_s']:.2f} s")
+    sub = np.sort(np.random.default_rng(seed).choice(train.n, min(svd_subset, train.n), replace=False))
+    Fh = F[torch.from_numpy(sub).cuda()].cpu().numpy()
+    mean, V = fit_basis(Fh, model.Q, n_components)
+    del Fh
+    model.install_projection(mean, V)
+    coef = model.project(F).cpu().numpy()
+    del F
+    model.set_basis(mean, V, coef, norm="component")
+    if weighting == "rv":
+        sel = np.random.default_rng(seed + 1).choice(len(coef), min(512, len(coef)), replace=False)
+        w = model.rv_weights(model.normalise(coef[sel]))
+        model.reweight(w)
+        info["rv_weights"] = [float(v) for v in w[:8]]
+    X = sample_features(train)
+    Y = model.normalise(coef)
+    t = __import__("time").perf_counter()
+    losses = model.train(X, Y, epochs, batch=batch, seed=seed)
+    torch.cuda.synchronize()
+    info["train_s"] = __import__("time").perf_counter() - t
+    info["train_steps"] = epochs * (len(X) // batch)
+    info["final_loss"] = losses[-1]
+    say(f"trained {info['train_steps']} steps in {info['train_s']:.2f} s, loss {losses[-1]:.3g}")
+    rvp = plain_rv(ctx, heldout, mask)["rv_kms"]
+    n_ho = (heldout.n // 16) * 16
+    err, spread = model.calibrate(heldout, np.arange(n_ho), rvp[:n_ho], model.alloc(n_ho))
+    info["calib"] = model.calib
+    info["heldout_err_cms"] = {"median": float(np.median(err) * 1e5), "p99": float(np.quantile(err, 0.99) * 1e5),
+                               "max": float(err.max() * 1e5)}
+    return model, info

@@ -320,3 +320,57 @@ def test_threshold_zero_gives_the_full_synthesis_bit_for_bit():
     one = np.concatenate([S.plain_rv(ctx, smp, star.mask, idx=[i])["rv_kms"] for i in (0, 9, 47)])
     np.testing.assert_array_equal(one, want[[0, 9, 47]])
     L.soap_destroy(ctx)
+
+
+def test_fused_surrogate_rv_matches_linear_fit_and_oracle_spread():
+    """soap_surrogate_rv: the mean prediction's RV equals soap_ccf_linear_rv's
+    bit for bit; the first-order member spread agrees with the spread of the
+    oracle's fits of each member's CCF (members close to the mean, so the
+    linearisation holds to a few per cent)."""
+    star, ctx = _tiny_fp32_ctx()
+    m = star.mask
+    rng = np.random.default_rng(90)
+    q = np.zeros(star.n_pix, np.float32)
+    L.soap_quiet_spectrum(ctx, q)
+    k, n, E = 6, 64, 4
+    pix = np.arange(star.n_pix)
+    Bk = np.stack([0.02 * np.sin(2 * np.pi * (j + 1) * pix / star.n_pix + j) for j in range(k)]).astype(np.float32)
+    rows = np.concatenate([q[None, :], Bk]).astype(np.float32)
+    ccf_rows = torch.empty((1 + k, m.n_v), dtype=torch.float64, device="cuda")
+    L.soap_ccf_rv(ctx, _dev(rows), m, ccf_out=ccf_rows, n_spec=1 + k)
+    base, basis = ccf_rows[0].contiguous(), ccf_rows[1:].contiguous()
+    coef = rng.normal(0, 1.0, (n, k)).astype(np.float32)
+    scale = 10.0 ** rng.uniform(-3.5, -1.5, n)[None, :, None]
+    mem = (coef[None] + scale * rng.normal(size=(E, n, k))).astype(np.float32)
+    rv_kms = torch.empty(n, dtype=torch.float64, device="cuda")
+    err = torch.empty(n, dtype=torch.float64, device="cuda")
+    fb = torch.empty(n, dtype=torch.int32, device="cuda")
+    rec = torch.empty(n * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    calib, thr = 1.5, 2e-4
+    L.soap_surrogate_rv(ctx, _dev(coef), _dev(mem), base, basis, calib, thr, rv_kms, fb, err_kms=err, rv_out=rec)
+    rv_lin = torch.empty(n * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    L.soap_ccf_linear_rv(ctx, _dev(coef), base, basis, None, rv_lin)
+    torch.cuda.synchronize()
+    got = np.frombuffer(rec.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
+    lin = np.frombuffer(rv_lin.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
+    np.testing.assert_array_equal(got["rv_kms"], lin["rv_kms"])
+    np.testing.assert_array_equal(rv_kms.cpu().numpy(), lin["rv_kms"])
+    # oracle: fit every member's CCF, sample standard deviation of the RVs
+    v = W.make_velocity_grid(m.v0_kms, m.dv_kms, m.n_v)
+    R = rows.astype(np.float64)
+    mus = np.empty((E, n))
+    for e in range(E):
+        C = OC.ccf(R[0] + mem[e].astype(np.float64) @ R[1:], star.ln_lambda0, star.dln_lambda, m.ln_lambda,
+                   m.weight, m.half_width_kms, v)
+        mus[e] = [OF.gauss_fit(v, C[i])["mu"] for i in range(n)]
+    want = calib * np.std(mus, axis=0, ddof=1)
+    e_got = err.cpu().numpy()
+    rel = np.abs(e_got - want) / np.maximum(want, 1e-9)
+    _say(f"member spread vs oracle fits: median rel {np.median(rel):.2e}, max rel {rel.max():.2e}, "
+         f"spread range {want.min()*1e5:.3f}..{want.max()*1e5:.3f} cm/s")
+    assert np.all(rel <= 5e-2 + 1e-8 / np.maximum(want, 1e-12))
+    flag = fb.cpu().numpy()
+    clear = np.abs(want - thr) > 0.1 * thr
+    np.testing.assert_array_equal(flag[clear], (want[clear] >= thr).astype(np.int32))
+    assert 0 < flag.sum() < n
+    L.soap_destroy(ctx)
