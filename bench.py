@@ -198,6 +198,9 @@ def main():
         L.soap_active_spectra(ctx, regions, phases, W.EFFECT_TOT, flux)
         L.soap_ccf_rv(ctx, flux, m, ccf_out=ccf, rv_out=rv)
 
+    print("[bench] tuning the shift-and-sum shape", file=sys.stderr, flush=True)
+    tune = L.soap_autotune(ctx, regions, phases, W.EFFECT_TOT)
+
     print("[bench] warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -297,6 +300,7 @@ def main():
             for k in ("weights_ms", "compact_ms", "apply_ms", "ccf_ms", "gfit_ms")
         },
         "init_ms": init_ms,
+        "apply_shape": tune,
         "fit": {
             "mean_iters": float(rvh["iters"].mean()),
             "max_iters": int(rvh["iters"].max()),

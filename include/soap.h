@@ -233,6 +233,33 @@ soap_status soap_surrogate_rv(soap_ctx* ctx, const float* coef, const float* mem
                               double threshold_kms, soap_rv* rv_out, double* rv_kms, double* err_kms,
                               int32_t* fallback);
 
+/* Shape of the shift-and-sum kernel and its tuner.  A block of `threads`
+ * threads (64, 128, 256 or 512) covers a tile of 4 x threads pixels for one
+ * chunk of phases; `lds_win` (1 .. 48) window records are staged in LDS per
+ * pass.  Every shape gives the same result bit for bit (each pixel adds its
+ * windows in the same order); only the time differs.                        */
+typedef struct {
+  int32_t threads;
+  int32_t lds_win;
+  double apply_us;           /* measured time of one launch of the choice   */
+  int32_t from_cache;        /* 1: taken from the cache file, not timed     */
+  int32_t n_tried;           /* shapes timed                                */
+  char key[128];             /* cache key of the workload shape             */
+} soap_tune;
+
+/* Sets the shape used by later calls on ctx.                                 */
+soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t threads, int32_t lds_win);
+
+/* Runs soap_active_spectra once on the given workload (arguments as there),
+ * then times every shape on its tap lists (10 launches each, HIP events on
+ * the context's stream) and keeps the fastest for later calls.  With
+ * cache_path (may be NULL) the choice is looked up first under a key made of
+ * the precision, table mode, and the power-of-two buckets of the pixel count,
+ * phase count and windows per chunk, plus the shift range and the mu-bin
+ * count; a timed choice is written back.  Waits for the stream.             */
+soap_status soap_autotune(soap_ctx* ctx, const soap_region* regions, int32_t n_regions, const double* phases,
+                          int32_t n_phases, int32_t effect, const char* cache_path, soap_tune* out);
+
 /* Per-stage GPU time and traffic bookkeeping, for benchmarks.  With
  * profiling on, every stage kernel of soap_active_spectra and soap_ccf_rv is
  * bracketed by HIP events on the context's stream; soap_profile_read waits

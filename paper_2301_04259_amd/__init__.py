@@ -68,6 +68,8 @@ SYMBOLS = (
     "soap_ccf_linear_rv",
     "soap_active_spectra_jobs",
     "soap_surrogate_rv",
+    "soap_set_apply_shape",
+    "soap_autotune",
     "soap_surrogate_create",
     "soap_surrogate_n_params",
     "soap_surrogate_train_step",
@@ -193,6 +195,22 @@ _lib.soap_surrogate_rv.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_int64, C.
                                    C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p]
 _lib.soap_surrogate_rv.restype = C.c_int
+class TuneC(C.Structure):
+    _fields_ = [
+        ("threads", C.c_int32),
+        ("lds_win", C.c_int32),
+        ("apply_us", C.c_double),
+        ("from_cache", C.c_int32),
+        ("n_tried", C.c_int32),
+        ("key", C.c_char * 128),
+    ]
+
+
+_lib.soap_set_apply_shape.argtypes = [_ctx_p, C.c_int32, C.c_int32]
+_lib.soap_set_apply_shape.restype = C.c_int
+_lib.soap_autotune.argtypes = [_ctx_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_char_p,
+                               C.POINTER(TuneC)]
+_lib.soap_autotune.restype = C.c_int
 _lib.soap_active_spectra_jobs.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_int32, C.c_void_p, C.c_int32]
 _lib.soap_active_spectra_jobs.restype = C.c_int
@@ -591,3 +609,19 @@ def soap_surrogate_rv(ctx, coef, members, base, basis, calib, threshold_kms, rv_
                                 _dptr(rv_out, "rv_out"), _dptr(rv_kms, "rv_kms"), _dptr(err_kms, "err_kms"),
                                 _dptr(fallback, "fallback"))
     _check(st, ctx.handle)
+
+
+def soap_set_apply_shape(ctx, threads, lds_win):
+    _check(_lib.soap_set_apply_shape(ctx.handle, int(threads), int(lds_win)), ctx.handle)
+
+
+def soap_autotune(ctx, regions, phases, effect, cache_path=None):
+    """Times the shift-and-sum shapes on this workload; returns the choice."""
+    ph = np.ascontiguousarray(phases, dtype=np.float64)
+    regs = _regions(regions)
+    t = TuneC()
+    st = _lib.soap_autotune(ctx.handle, C.cast(regs, C.c_void_p), len(regions), ph.ctypes.data, len(ph), int(effect),
+                            None if cache_path is None else os.fsencode(cache_path), C.byref(t))
+    _check(st, ctx.handle)
+    return {"threads": t.threads, "lds_win": t.lds_win, "apply_us": t.apply_us, "from_cache": bool(t.from_cache),
+            "n_tried": t.n_tried, "key": t.key.decode()}

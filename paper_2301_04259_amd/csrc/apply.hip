@@ -198,8 +198,8 @@ __device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, u
 
 }  // namespace
 
-template <typename T, int R, int PC, int JW, bool PAIRED>
-__global__ void __launch_bounds__(APPLY_THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(ApplyArgs<T> A) {
+template <typename T, int R, int PC, int JW, bool PAIRED, int THREADS>
+__global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(ApplyArgs<T> A) {
   static_assert(R == 4 && JW == 8, "window loads are written for 4 pixels x 8 offsets");
   static_assert(PC % 4 == 0 && JW * PC * sizeof(T) == WIN_TAP_BYTES, "record layout");
   extern __shared__ __align__(16) unsigned char s_win[];  // [lds_win][WIN_BYTES]
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(APPLY_THREADS, sizeof(T) == 4 ? 3 : 2) k_apply
     __syncthreads();
     chunk = s_order[rank];
   }
-  const int64_t m0 = (int64_t)tile * (R * APPLY_THREADS) + (int64_t)threadIdx.x * R;
+  const int64_t m0 = (int64_t)tile * (R * THREADS) + (int64_t)threadIdx.x * R;
 
   T acc[PC][R];
 #pragma unroll
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(APPLY_THREADS, sizeof(T) == 4 ? 3 : 2) k_apply
       const int4* src = reinterpret_cast<const int4*>(gw + (int64_t)vb * WIN_BYTES);
       int4* dst = reinterpret_cast<int4*>(s_win);
       const int n16 = nb * (WIN_BYTES / 16);
-      for (int u = threadIdx.x; u < n16; u += APPLY_THREADS) dst[u] = src[u];
+      for (int u = threadIdx.x; u < n16; u += THREADS) dst[u] = src[u];
     }
     __syncthreads();
     // Two windows in flight: the loads of the next window are issued before
@@ -307,40 +307,61 @@ __global__ void __launch_bounds__(APPLY_THREADS, sizeof(T) == 4 ? 3 : 2) k_apply
   }
 }
 
+namespace {
+
+template <typename T, bool PAIRED, int PC>
+hipError_t launch_apply_t(soap_ctx* c, const Plan& pl, const ApplyArgs<T>& A0, int threads, hipStream_t st) {
+  ApplyArgs<T> A = A0;
+  const int tile = APPLY_R * threads;
+  A.n_tiles = (int)((c->P + tile - 1) / tile);
+  const int tpx = (A.n_tiles + 7) / 8;
+  const dim3 grid(8 * tpx * pl.n_chunks);
+  const size_t lds = (size_t)A.lds_win * WIN_BYTES;
+  switch (threads) {
+    case 64:
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 64>), grid, dim3(64), lds, st, A);
+      break;
+    case 128:
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 128>), grid, dim3(128), lds, st, A);
+      break;
+    case 512:
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 512>), grid, dim3(512), lds, st, A);
+      break;
+    default:
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 256>), grid, dim3(256), lds, st, A);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux) {
-  const int tpx = (c->n_tiles + 7) / 8;
-  dim3 grid(8 * tpx * pl.n_chunks);
+  return launch_apply_shape(c, pl, d_win, d_nvg, d_flux, c->tune_threads, c->tune_lds_win, c->stream);
+}
+
+hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux,
+                              int threads, int lds_win, hipStream_t st) {
   const bool vec_ok = (c->P % APPLY_R == 0) &&
                       (reinterpret_cast<uintptr_t>(d_flux) % (APPLY_R * c->esize) == 0);
-  const int lds_win = std::min(pl.vg_cap, APPLY_LDS_WIN);
-  const size_t lds = (size_t)lds_win * WIN_BYTES;
+  lds_win = std::max(1, std::min(pl.vg_cap, lds_win));
   const unsigned char* w = static_cast<const unsigned char*>(d_win);
   if (c->prec == SOAP_PREC_FP32) {
-    ApplyArgs<float> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, c->n_tiles, pl.effect, pl.paired, pl.vg_cap,
+    ApplyArgs<float> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, 0, pl.effect, pl.paired, pl.vg_cap,
                        vec_ok ? 1 : 0, lds_win,
                        (const float*)c->d_spec[0], (const float*)c->d_spec[1], (const float*)c->d_spec[2],
                        (const float*)c->d_con_spot, (const float*)c->d_con_fac, (const float*)c->d_ones, c->d_Q, w, d_nvg,
                        (float*)d_flux};
-    if (pl.paired)
-      hipLaunchKernelGGL((k_apply<float, APPLY_R, PC_F32, APPLY_JW, true>), grid, dim3(APPLY_THREADS), lds,
-                         c->stream, A);
-    else
-      hipLaunchKernelGGL((k_apply<float, APPLY_R, PC_F32, APPLY_JW, false>), grid, dim3(APPLY_THREADS), lds,
-                         c->stream, A);
-  } else {
-    ApplyArgs<double> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, c->n_tiles, pl.effect, pl.paired,
-                        pl.vg_cap, vec_ok ? 1 : 0, lds_win,
-                        (const double*)c->d_spec[0], (const double*)c->d_spec[1], (const double*)c->d_spec[2],
-                        (const double*)c->d_con_spot, (const double*)c->d_con_fac, (const double*)c->d_ones, c->d_Q, w, d_nvg,
-                        (double*)d_flux};
-    if (pl.paired)
-      hipLaunchKernelGGL((k_apply<double, APPLY_R, PC_F64, APPLY_JW, true>), grid, dim3(APPLY_THREADS), lds,
-                         c->stream, A);
-    else
-      hipLaunchKernelGGL((k_apply<double, APPLY_R, PC_F64, APPLY_JW, false>), grid, dim3(APPLY_THREADS), lds,
-                         c->stream, A);
+    return pl.paired ? launch_apply_t<float, true, PC_F32>(c, pl, A, threads, st)
+                     : launch_apply_t<float, false, PC_F32>(c, pl, A, threads, st);
   }
-  return hipGetLastError();
+  ApplyArgs<double> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, 0, pl.effect, pl.paired,
+                      pl.vg_cap, vec_ok ? 1 : 0, lds_win,
+                      (const double*)c->d_spec[0], (const double*)c->d_spec[1], (const double*)c->d_spec[2],
+                      (const double*)c->d_con_spot, (const double*)c->d_con_fac, (const double*)c->d_ones, c->d_Q, w, d_nvg,
+                      (double*)d_flux};
+  return pl.paired ? launch_apply_t<double, true, PC_F64>(c, pl, A, threads, st)
+                   : launch_apply_t<double, false, PC_F64>(c, pl, A, threads, st);
 }
 
 }  // namespace soap

@@ -232,7 +232,7 @@ hipError_t launch_contrast(soap_ctx* c) {
 }
 
 hipError_t launch_ones(soap_ctx* c) {
-  const int64_t n = (int64_t)c->n_tiles * APPLY_TILE;
+  const int64_t n = (int64_t)c->n_tiles * APPLY_TILE_MAX;
   dim3 grid((unsigned)((n + 255) / 256));
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_fill_one<float>, grid, dim3(256), 0, c->stream, n, (float*)c->d_ones);
@@ -272,7 +272,7 @@ hipError_t launch_quiet(soap_ctx* c) {
                      c->J, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t qlen = (int64_t)c->n_tiles * APPLY_TILE;
+  const int64_t qlen = (int64_t)c->n_tiles * APPLY_TILE_MAX;
   dim3 grid((unsigned)((qlen + 255) / 256));
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_quiet<float>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, qlen, c->B, c->jmin,

@@ -194,10 +194,10 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   c->hip_used = true;
   HIP_TRY(hipGetDevice(&c->device));
   c->pc = (c->prec == SOAP_PREC_FP32) ? soap::PC_F32 : soap::PC_F64;
-  c->n_tiles = (int)((c->P + soap::APPLY_TILE - 1) / soap::APPLY_TILE);
+  c->n_tiles = (int)((c->P + soap::APPLY_TILE_MAX - 1) / soap::APPLY_TILE_MAX);
   // padded rows: PAD_FRONT samples before pixel 0, and past the last tile
   // enough room for the widest window the apply kernel reads
-  const int64_t tail = (int64_t)c->n_tiles * soap::APPLY_TILE + 2 * soap::MAX_J + 64;
+  const int64_t tail = (int64_t)c->n_tiles * soap::APPLY_TILE_MAX + 2 * soap::MAX_J + 64;
   c->Pstride = ((soap::PAD_FRONT + tail + 63) / 64) * 64;
   const size_t row_bytes = (size_t)c->Pstride * c->esize;
   hipMemcpyKind kind = d->spectra_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -215,8 +215,8 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   HIP_TRY(hipMalloc((void**)&c->d_col_w, sizeof(double) * c->N));
   HIP_TRY(hipMalloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
   HIP_TRY(hipMalloc((void**)&c->d_Kq, sizeof(double) * c->B * c->J));
-  HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE));
-  HIP_TRY(hipMalloc(&c->d_ones, c->esize * c->n_tiles * soap::APPLY_TILE));
+  HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE_MAX));
+  HIP_TRY(hipMalloc(&c->d_ones, c->esize * c->n_tiles * soap::APPLY_TILE_MAX));
   if (c->cmode == SOAP_CONTRAST_PLANCK) {
     HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * (c->B + 1)));
     c->d_con_spot = static_cast<unsigned char*>(c->d_con_base) + soap::PAD_FRONT * c->esize;

@@ -23,13 +23,17 @@ constexpr int MAX_GRID = 4096;
 constexpr int MAX_PHASES = 1 << 20;
 constexpr int MAX_J = 64;  // tap offsets per table row
 
-// Apply kernel shape: 256 threads x APPLY_R consecutive pixels per tile; a
-// chunk of PC phases per block (16 in FP32, 8 in FP64); taps grouped in
-// windows of APPLY_JW offsets.
+// Apply kernel shape: THREADS threads x APPLY_R consecutive pixels per tile
+// (THREADS one of 64, 128, 256, 512, chosen per context by the tuner; 256 by
+// default); a block runs one (tile, chunk of PC phases: 16 in FP32, 8 in
+// FP64) item over the chunk's windows of APPLY_JW offsets.  Quiet spectrum and rows are padded to whole
+// tiles of the widest shape.
 constexpr int APPLY_R = 4;
 constexpr int APPLY_JW = 8;
 constexpr int APPLY_THREADS = 256;
+constexpr int APPLY_THREADS_MAX = 512;
 constexpr int APPLY_TILE = APPLY_R * APPLY_THREADS;
+constexpr int APPLY_TILE_MAX = APPLY_R * APPLY_THREADS_MAX;
 constexpr int PC_MAX = 16;
 constexpr int PC_F32 = 16;
 constexpr int PC_F64 = 8;
@@ -94,7 +98,9 @@ struct soap_ctx {
   int N = 0, B = 0;
   int64_t P = 0;
   int64_t Pstride = 0;  // padded row length (elements); row data starts at PAD_FRONT
-  int n_tiles = 0;
+  int n_tiles = 0;  // tiles of APPLY_TILE_MAX pixels (padding)
+  int tune_threads = soap::APPLY_THREADS;  // apply shape in use (the tuner's choice)
+  int tune_lds_win = soap::APPLY_LDS_WIN;
   double vsini = 0, incl = 0, u1 = 0, u2 = 0, ln0 = 0, dln = 0;
   int prec = SOAP_PREC_FP64, cmode = SOAP_CONTRAST_SCALAR;
   double teff = 0, dt_spot = 0, dt_fac[3] = {0, 0, 0};
@@ -210,6 +216,10 @@ hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int 
                           const double* d_ph, const int2* d_pj, const WeightsOut& o, hipStream_t st);
 hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o, hipStream_t st);
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux);
+// apply with an explicit shape (threads per block, windows staged per LDS
+// pass) on stream st
+hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux,
+                              int threads, int lds_win, hipStream_t st);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
                       double* d_part);

@@ -1,0 +1,183 @@
+// Tuner of the shift-and-sum kernel's shape (include/soap.h, soap_autotune):
+// times every (threads per block, windows staged per LDS pass) variant on a
+// context's real tap lists and keeps the fastest, with a file cache keyed by
+// the shape of the work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "soap_internal.hpp"
+
+#define SOAP_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+constexpr int kThreads[] = {64, 128, 256, 512};
+constexpr int kWins[] = {16, 32, 48};
+
+int ilog2_ceil(long long v) {
+  int b = 0;
+  while ((1LL << b) < v) ++b;
+  return b;
+}
+
+// cache file: one entry per line, `"key": [threads, lds_win, apply_us],`
+// inside a JSON object
+bool cache_lookup(const char* path, const std::string& key, int* th, int* lw, double* us) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  const std::string want = "\"" + key + "\"";
+  while (std::fgets(line, sizeof line, f)) {
+    const char* p = std::strstr(line, want.c_str());
+    if (!p) continue;
+    p = std::strchr(p + want.size(), '[');
+    if (p && std::sscanf(p, "[%d , %d , %lf", th, lw, us) == 3) found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+bool cache_store(const char* path, const std::string& key, int th, int lw, double us) {
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[512];
+    const std::string want = "\"" + key + "\"";
+    while (std::fgets(line, sizeof line, f)) {
+      std::string s(line);
+      while (!s.empty() && (s.back() == '\n' || s.back() == ',' || s.back() == ' ')) s.pop_back();
+      if (s.empty() || s == "{" || s == "}" || s.find(want) != std::string::npos) continue;
+      keep.push_back(s);
+    }
+    std::fclose(f);
+  }
+  char entry[512];
+  std::snprintf(entry, sizeof entry, "  \"%s\": [%d, %d, %.3f]", key.c_str(), th, lw, us);
+  keep.push_back(entry);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "{\n");
+  for (size_t i = 0; i < keep.size(); ++i) std::fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+  std::fprintf(f, "}\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+SOAP_API soap_status soap_set_apply_shape(soap_ctx* c, int32_t threads, int32_t lds_win) {
+  if (!c) return SOAP_ERR_ARG;
+  const bool t_ok = std::find(std::begin(kThreads), std::end(kThreads), threads) != std::end(kThreads);
+  if (!t_ok || lds_win < 1 || lds_win > soap::APPLY_LDS_WIN) {
+    c->err = "threads must be 64, 128, 256 or 512 and lds_win in [1, 48]";
+    return SOAP_ERR_ARG;
+  }
+  c->tune_threads = threads;
+  c->tune_lds_win = lds_win;
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_autotune(soap_ctx* c, const soap_region* regions, int32_t n_regions,
+                                   const double* phases, int32_t n_phases, int32_t effect, const char* cache_path,
+                                   soap_tune* out) {
+  if (!c) return SOAP_ERR_ARG;
+  if (!out) {
+    c->err = "out is NULL";
+    return SOAP_ERR_ARG;
+  }
+  std::memset(out, 0, sizeof *out);
+  // one ordinary call builds this workload's tap lists (and checks the
+  // arguments); they stay in the context's last table set
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, (size_t)std::max(1, n_phases) * c->P * c->esize) != hipSuccess) {
+    c->err = "autotune: no device memory for a trial output";
+    return SOAP_ERR_OOM;
+  }
+  soap_status st = soap_active_spectra(c, regions, n_regions, phases, n_phases, effect, tmp, 1);
+  auto fail = [&](soap_status s, const char* msg) {
+    if (msg) c->err = msg;
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(tmp);
+    return s;
+  };
+  if (st != SOAP_OK) return fail(st, nullptr);
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(SOAP_ERR_HIP, "autotune: stream failed");
+  soap::Plan pl;
+  pl.n_ph = c->last_phases;
+  pl.effect = c->last_effect;
+  pl.paired = c->last_paired;
+  pl.G = (pl.paired ? 2 : 3) * c->B;
+  pl.n_chunks = (pl.n_ph + c->pc - 1) / c->pc;
+  pl.vg_cap = c->last_vg_cap;
+  soap_ctx::PrepSet& S = c->prep[c->last_prep];
+  std::vector<int> nvg(pl.n_chunks);
+  if (hipMemcpy(nvg.data(), S.nvg.ptr, sizeof(int) * pl.n_chunks, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SOAP_ERR_HIP, "autotune: reading window counts failed");
+  long long tot = 0;
+  for (int v : nvg) tot += v;
+  char key[256];
+  std::snprintf(key, sizeof key, "%s|%s|P2^%d|J%d|B%d|ph2^%d|win2^%d", c->prec == SOAP_PREC_FP32 ? "f32" : "f64",
+                pl.paired ? "paired" : "split", ilog2_ceil(c->P), c->J, c->B, ilog2_ceil(pl.n_ph),
+                ilog2_ceil(std::max(1LL, tot / std::max(1, pl.n_chunks))));
+  int th = 0, lw = 0;
+  double us = 0.0;
+  if (cache_path && cache_lookup(cache_path, key, &th, &lw, &us) &&
+      soap_set_apply_shape(c, th, lw) == SOAP_OK) {
+    out->threads = th;
+    out->lds_win = lw;
+    out->apply_us = us;
+    out->from_cache = 1;
+    std::snprintf(out->key, sizeof out->key, "%s", key);
+    return fail(SOAP_OK, nullptr);
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(SOAP_ERR_HIP, "autotune: event creation failed");
+  double best = 1e300;
+  int bt = c->tune_threads, bw = c->tune_lds_win, tried = 0;
+  constexpr int kReps = 10;
+  for (int t : kThreads) {
+    for (int w : kWins) {
+      if (w > std::max(16, pl.vg_cap) && w != kWins[0]) continue;  // same as a smaller staging
+      for (int r = 0; r < 2; ++r)
+        (void)soap::launch_apply_shape(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), tmp, t, w, c->stream);
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < kReps; ++r)
+        (void)soap::launch_apply_shape(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), tmp, t, w, c->stream);
+      (void)hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(SOAP_ERR_HIP, "autotune: a trial launch failed");
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double t_us = 1e3 * ms / kReps;
+      ++tried;
+      if (t_us < best) {
+        best = t_us;
+        bt = t;
+        bw = w;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tune_threads = bt;
+  c->tune_lds_win = bw;
+  out->threads = bt;
+  out->lds_win = bw;
+  out->apply_us = best;
+  out->n_tried = tried;
+  std::snprintf(out->key, sizeof out->key, "%s", key);
+  if (cache_path && !cache_store(cache_path, key, bt, bw, best))
+    return fail(SOAP_ERR_ARG, "autotune: cannot write the cache file");
+  return fail(SOAP_OK, nullptr);
+}
