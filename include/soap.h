@@ -260,6 +260,32 @@ soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t threads, int32_t lds_win
 soap_status soap_autotune(soap_ctx* ctx, const soap_region* regions, int32_t n_regions, const double* phases,
                           int32_t n_phases, int32_t effect, const char* cache_path, soap_tune* out);
 
+/* Batch of activity configurations over many stars, replayed as one HIP
+ * graph.  Configuration i is star ctxs[i] (contexts may repeat) with regions
+ * regions[region_offsets[i] .. region_offsets[i+1]) (0 .. 64) at phases
+ * phases[phase_offsets[i] .. phase_offsets[i+1]) (at least one); its spectra
+ * go to flux[i], a device array [phases of i][n_pix of its star] in the
+ * star's float type.  Stars may differ in grid size, pixel count, mu bins,
+ * precision and contrast mode.  soap_batch_create validates everything,
+ * uploads the parameters, allocates each configuration's tables and
+ * captures every configuration's kernels (Algorithm 5 per phase: region
+ * parameters, weights, tap lists, shift-and-sum with the context's current
+ * apply shape) into one graph spread over four parallel branches;
+ * soap_batch_run then enqueues the whole batch with a single graph launch on
+ * hip_stream.  Every output row equals what soap_active_spectra gives for
+ * that configuration, bit for bit.  The contexts and flux arrays must
+ * outlive the batch and not be used by other work while a run is in flight;
+ * flux arrays must not overlap.  On error *out is NULL and
+ * soap_batch_last_error(NULL) has the message (per thread).                 */
+typedef struct soap_batch soap_batch;
+soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                              const int32_t* region_offsets, const double* phases, const int32_t* phase_offsets,
+                              int32_t effect, void* const* flux, void* hip_stream, soap_batch** out);
+soap_status soap_batch_run(soap_batch* batch);
+int64_t soap_batch_n_spectra(const soap_batch* batch);
+const char* soap_batch_last_error(const soap_batch* batch);
+void soap_batch_destroy(soap_batch* batch);
+
 /* Per-stage GPU time and traffic bookkeeping, for benchmarks.  With
  * profiling on, every stage kernel of soap_active_spectra and soap_ccf_rv is
  * bracketed by HIP events on the context's stream; soap_profile_read waits

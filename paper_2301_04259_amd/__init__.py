@@ -70,6 +70,11 @@ SYMBOLS = (
     "soap_surrogate_rv",
     "soap_set_apply_shape",
     "soap_autotune",
+    "soap_batch_create",
+    "soap_batch_run",
+    "soap_batch_n_spectra",
+    "soap_batch_last_error",
+    "soap_batch_destroy",
     "soap_surrogate_create",
     "soap_surrogate_n_params",
     "soap_surrogate_train_step",
@@ -211,6 +216,17 @@ _lib.soap_set_apply_shape.restype = C.c_int
 _lib.soap_autotune.argtypes = [_ctx_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_char_p,
                                C.POINTER(TuneC)]
 _lib.soap_autotune.restype = C.c_int
+_lib.soap_batch_create.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
+_lib.soap_batch_create.restype = C.c_int
+_lib.soap_batch_run.argtypes = [C.c_void_p]
+_lib.soap_batch_run.restype = C.c_int
+_lib.soap_batch_n_spectra.argtypes = [C.c_void_p]
+_lib.soap_batch_n_spectra.restype = C.c_int64
+_lib.soap_batch_last_error.argtypes = [C.c_void_p]
+_lib.soap_batch_last_error.restype = C.c_char_p
+_lib.soap_batch_destroy.argtypes = [C.c_void_p]
+_lib.soap_batch_destroy.restype = None
 _lib.soap_active_spectra_jobs.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                           C.c_int32, C.c_void_p, C.c_int32]
 _lib.soap_active_spectra_jobs.restype = C.c_int
@@ -625,3 +641,56 @@ def soap_autotune(ctx, regions, phases, effect, cache_path=None):
     _check(st, ctx.handle)
     return {"threads": t.threads, "lds_win": t.lds_win, "apply_us": t.apply_us, "from_cache": bool(t.from_cache),
             "n_tried": t.n_tried, "key": t.key.decode()}
+
+
+class Batch:
+    """Owns a soap_batch* and keeps its contexts and outputs alive."""
+
+    def __init__(self, handle, ctxs, outs):
+        self.handle = handle
+        self._ctxs = ctxs
+        self.outs = outs
+
+    def __del__(self, _destroy=_lib.soap_batch_destroy):
+        h = getattr(self, "handle", None)
+        if h:
+            _destroy(h)
+            self.handle = None
+
+
+def soap_batch_create(ctxs, cfg_regions, cfg_phases, effect, outs, stream=None):
+    """One configuration per (ctx, region list, phases, output tensor)."""
+    n = len(ctxs)
+    handles = (C.c_void_p * n)(*[C.cast(c.handle, C.c_void_p) for c in ctxs])
+    regs = [r for rl in cfg_regions for r in rl]
+    arr = np.zeros(max(1, len(regs)), dtype=REGION_DTYPE)
+    for i, r in enumerate(regs):
+        arr[i] = (int(r.type), 0, float(r.lat_deg), float(r.lon_deg), float(r.radius), float(r.contrast))
+    roff = np.zeros(n + 1, np.int32)
+    roff[1:] = np.cumsum([len(rl) for rl in cfg_regions])
+    ph = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64).reshape(-1) for p in cfg_phases]))
+    poff = np.zeros(n + 1, np.int32)
+    poff[1:] = np.cumsum([np.asarray(p).size for p in cfg_phases])
+    fl = (C.c_void_p * n)(*[_dptr(o, "flux") for o in outs])
+    h = C.c_void_p()
+    st = _lib.soap_batch_create(handles, n, arr.ctypes.data, roff.ctypes.data, ph.ctypes.data, poff.ctypes.data,
+                                int(effect), fl, _stream_handle(stream), C.byref(h))
+    if st != SOAP_OK:
+        raise SoapError(st, _lib.soap_batch_last_error(None).decode())
+    return Batch(h, list(ctxs), list(outs))
+
+
+def soap_batch_run(batch):
+    st = _lib.soap_batch_run(batch.handle)
+    if st != SOAP_OK:
+        raise SoapError(st, _lib.soap_batch_last_error(batch.handle).decode())
+
+
+def soap_batch_n_spectra(batch):
+    return int(_lib.soap_batch_n_spectra(batch.handle))
+
+
+def soap_batch_destroy(batch):
+    if batch.handle:
+        _lib.soap_batch_destroy(batch.handle)
+        batch.handle = None

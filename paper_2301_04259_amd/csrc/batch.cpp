@@ -1,0 +1,249 @@
+// Batched synthesis of many activity configurations of many stars
+// (include/soap.h, soap_batch_*): every configuration's kernels (region
+// parameters, weights, tap lists, shift-and-sum) are captured once into one
+// HIP graph over a few parallel branches, so a run is a single graph launch
+// with no host work per configuration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "soap_internal.hpp"
+
+#define SOAP_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+constexpr int kBranches = 4;
+
+size_t al(size_t b) { return 256 * ((b + 255) / 256); }
+
+struct CfgPlan {
+  soap_ctx* c;
+  soap::Plan pl;
+  int n_reg;
+  size_t off_reg, off_ph, off_regcopy, off_cen, off_box, off_kfx, off_k, off_mask, off_vg, off_nvg;
+  void* flux;
+};
+
+}  // namespace
+
+struct soap_batch {
+  hipStream_t launch = nullptr;                // stream the graph is launched on
+  hipStream_t origin = nullptr;                // capture origin (owned)
+  hipStream_t branch[kBranches] = {};          // owned
+  hipEvent_t fork = nullptr, join[kBranches] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* arena = nullptr;
+  int n_cfg = 0;
+  int64_t n_spectra = 0;
+  std::string err;
+};
+
+namespace {
+
+void destroy_batch(soap_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (int i = 0; i < kBranches; ++i) {
+    if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->origin) (void)hipStreamDestroy(b->origin);
+  if (b->arena) (void)hipFree(b->arena);
+  delete b;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+static thread_local std::string g_batch_err;
+
+SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                                       const int32_t* region_offsets, const double* phases,
+                                       const int32_t* phase_offsets, int32_t effect, void* const* flux,
+                                       void* hip_stream, soap_batch** out) {
+  auto bad = [](const std::string& m) {
+    g_batch_err = m;
+    return SOAP_ERR_ARG;
+  };
+  if (!out) return bad("out is NULL");
+  *out = nullptr;
+  if (!ctxs || !region_offsets || !phase_offsets || !phases || !flux) return bad("a required array is NULL");
+  if (n_cfg < 1 || n_cfg > (1 << 16)) return bad("n_cfg must be in [1, 65536]");
+  if (effect != SOAP_EFFECT_TOT && effect != SOAP_EFFECT_FLUX && effect != SOAP_EFFECT_BCONV)
+    return bad("unknown effect");
+  if (region_offsets[0] != 0 || phase_offsets[0] != 0) return bad("offsets must start at 0");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return bad("no device");
+  std::vector<CfgPlan> cp(n_cfg);
+  size_t arena = 0;
+  int64_t n_spec = 0;
+  char msg[256];
+  for (int i = 0; i < n_cfg; ++i) {
+    soap_ctx* c = ctxs[i];
+    if (!c || !flux[i]) return bad("a context or flux pointer is NULL");
+    if (c->device != dev) return bad("every context must live on the current device");
+    const int r0 = region_offsets[i], nr = region_offsets[i + 1] - r0;
+    const int p0 = phase_offsets[i], np = phase_offsets[i + 1] - p0;
+    if (nr < 0 || nr > soap::MAX_REGIONS) {
+      std::snprintf(msg, sizeof msg, "configuration %d has %d regions (0 .. %d allowed)", i, nr, soap::MAX_REGIONS);
+      return bad(msg);
+    }
+    if (np < 1 || np > soap::MAX_PHASES) {
+      std::snprintf(msg, sizeof msg, "configuration %d has %d phases", i, np);
+      return bad(msg);
+    }
+    if (nr > 0 && !regions) return bad("regions is NULL");
+    bool unit = true;
+    for (int r = r0; r < r0 + nr; ++r) {
+      const soap_region& R = regions[r];
+      if ((R.type != SOAP_SPOT && R.type != SOAP_FACULA) || !is_fin(R.lat_deg) || R.lat_deg < -90.0 ||
+          R.lat_deg > 90.0 || !is_fin(R.lon_deg) || !(R.radius > 0.0 && R.radius < 1.0) || !is_fin(R.contrast) ||
+          !(R.contrast > 0.0) || (effect != SOAP_EFFECT_FLUX && !c->has_type[R.type])) {
+        std::snprintf(msg, sizeof msg, "configuration %d: region %d is invalid for its star", i, r - r0);
+        return bad(msg);
+      }
+      unit = unit && R.contrast == 1.0;
+    }
+    for (int p = p0; p < p0 + np; ++p)
+      if (!is_fin(phases[p])) return bad("a phase is not finite");
+    CfgPlan& q = cp[i];
+    q.c = c;
+    q.n_reg = nr;
+    q.flux = flux[i];
+    soap::Plan& pl = q.pl;
+    pl.n_ph = np;
+    pl.effect = effect;
+    pl.paired = (c->cmode == SOAP_CONTRAST_PLANCK || effect == SOAP_EFFECT_BCONV || unit) ? 1 : 0;
+    pl.G = (pl.paired ? 2 : 3) * c->B;
+    pl.n_slabs = (c->N + soap::SLAB_COLS - 1) / soap::SLAB_COLS;
+    pl.n_chunks = (np + c->pc - 1) / c->pc;
+    pl.vg_cap = pl.G * ((c->J + soap::APPLY_JW - 1) / soap::APPLY_JW);
+    const size_t GJ = (size_t)pl.G * c->J;
+    auto take = [&](size_t bytes) {
+      const size_t o = arena;
+      arena += al(std::max<size_t>(bytes, 1));
+      return o;
+    };
+    q.off_reg = take(sizeof(soap::Region) * std::max(1, nr));
+    q.off_ph = take(sizeof(double) * np);
+    q.off_regcopy = take(sizeof(soap::Region) * std::max(1, nr));
+    q.off_cen = take(sizeof(double4) * (size_t)np * std::max(1, nr));
+    q.off_box = take(sizeof(int4) * (size_t)np);
+    q.off_kfx = take(sizeof(unsigned long long) * (size_t)np * GJ);
+    q.off_k = take(sizeof(double) * (size_t)np * GJ);
+    q.off_mask = take(sizeof(unsigned long long) * (size_t)np * pl.G);
+    q.off_vg = take((size_t)soap::WIN_BYTES * pl.n_chunks * pl.vg_cap);
+    q.off_nvg = take(sizeof(int) * (size_t)pl.n_chunks);
+    n_spec += np;
+  }
+
+  soap_batch* b = new soap_batch;
+  b->n_cfg = n_cfg;
+  b->n_spectra = n_spec;
+  b->launch = static_cast<hipStream_t>(hip_stream);
+  auto fail = [&](const char* what, hipError_t e) {
+    g_batch_err = std::string(what) + ": " + hipGetErrorString(e);
+    destroy_batch(b);
+    return (e == hipErrorOutOfMemory) ? SOAP_ERR_OOM : SOAP_ERR_HIP;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&b->arena, arena)) != hipSuccess) return fail("hipMalloc", e);
+  // tap accumulators start at zero (each run's tap-list kernel clears them
+  // again after reading); parameters are uploaded once
+  if ((e = hipMemset(b->arena, 0, arena)) != hipSuccess) return fail("hipMemset", e);
+  unsigned char* A = static_cast<unsigned char*>(b->arena);
+  {
+    std::vector<soap::Region> hr;
+    for (int i = 0; i < n_cfg; ++i) {
+      const CfgPlan& q = cp[i];
+      const int r0 = region_offsets[i];
+      hr.assign(std::max(1, q.n_reg), soap::Region{});
+      for (int r = 0; r < q.n_reg; ++r) {
+        const soap_region& R = regions[r0 + r];
+        hr[r] = soap::Region{R.type, 0, R.lat_deg, R.lon_deg, R.radius, R.contrast};
+      }
+      if ((e = hipMemcpy(A + q.off_reg, hr.data(), sizeof(soap::Region) * hr.size(), hipMemcpyHostToDevice)) !=
+              hipSuccess ||
+          (e = hipMemcpy(A + q.off_ph, phases + phase_offsets[i], sizeof(double) * q.pl.n_ph,
+                         hipMemcpyHostToDevice)) != hipSuccess)
+        return fail("hipMemcpy", e);
+    }
+  }
+  if ((e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
+  for (int k = 0; k < kBranches; ++k) {
+    if ((e = hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
+    if ((e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming)) != hipSuccess) return fail("event", e);
+  }
+  if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) return fail("event", e);
+  // the contexts' own work must be finished before their tables are read
+  for (int i = 0; i < n_cfg; ++i) {
+    if ((e = hipStreamSynchronize(cp[i].c->stream)) != hipSuccess) return fail("context stream", e);
+    if ((e = hipStreamSynchronize(cp[i].c->side)) != hipSuccess) return fail("context stream", e);
+  }
+
+  if ((e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed)) != hipSuccess) return fail("capture", e);
+  hipError_t ce = hipEventRecord(b->fork, b->origin);
+  for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork, 0);
+  for (int i = 0; i < n_cfg && ce == hipSuccess; ++i) {
+    const CfgPlan& q = cp[i];
+    hipStream_t st = b->branch[i % kBranches];
+    soap::WeightsOut wo;
+    wo.reg = reinterpret_cast<soap::Region*>(A + q.off_regcopy);
+    wo.pj = nullptr;
+    wo.cen = reinterpret_cast<double4*>(A + q.off_cen);
+    wo.box = reinterpret_cast<int4*>(A + q.off_box);
+    wo.Kfx = reinterpret_cast<unsigned long long*>(A + q.off_kfx);
+    wo.K = reinterpret_cast<double*>(A + q.off_k);
+    wo.mask = reinterpret_cast<unsigned long long*>(A + q.off_mask);
+    wo.wins = A + q.off_vg;
+    wo.nvg = reinterpret_cast<int*>(A + q.off_nvg);
+    ce = soap::launch_weights(q.c, q.pl, reinterpret_cast<const soap::Region*>(A + q.off_reg), q.n_reg,
+                              std::max(1, q.n_reg), reinterpret_cast<const double*>(A + q.off_ph), nullptr, wo, st);
+    if (ce == hipSuccess) ce = soap::launch_finish(q.c, q.pl, wo, st);
+    if (ce == hipSuccess)
+      ce = soap::launch_apply_shape(q.c, q.pl, wo.wins, wo.nvg, q.flux, q.c->tune_threads, q.c->tune_lds_win, st);
+  }
+  for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
+    ce = hipEventRecord(b->join[k], b->branch[k]);
+    if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join[k], 0);
+  }
+  e = hipStreamEndCapture(b->origin, &b->graph);
+  if (ce != hipSuccess) return fail("capturing the batch", ce);
+  if (e != hipSuccess) return fail("hipStreamEndCapture", e);
+  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+    return fail("hipGraphInstantiate", e);
+  *out = b;
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_batch_run(soap_batch* b) {
+  if (!b) return SOAP_ERR_ARG;
+  const hipError_t e = hipGraphLaunch(b->exec, b->launch);
+  if (e != hipSuccess) {
+    b->err = std::string("hipGraphLaunch: ") + hipGetErrorString(e);
+    return SOAP_ERR_HIP;
+  }
+  return SOAP_OK;
+}
+
+SOAP_API int64_t soap_batch_n_spectra(const soap_batch* b) { return b ? b->n_spectra : -1; }
+
+SOAP_API const char* soap_batch_last_error(const soap_batch* b) {
+  return b ? b->err.c_str() : g_batch_err.c_str();
+}
+
+SOAP_API void soap_batch_destroy(soap_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->launch);
+  destroy_batch(b);
+}

@@ -1,0 +1,101 @@
+"""Batches over many stars as one HIP graph (soap_batch_*): every
+configuration's spectra equal the single call's bit for bit, on every
+replay, and match the oracle."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import spectrum as OS
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2301_04259_amd", reason="libsoap.so not built")
+
+
+def _say(*a):
+    print("[batch]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _stars():
+    return [
+        W.make_tiny(11, n_grid=16, n_pix=700, precision=W.PREC_FP64),
+        W.make_tiny(12, n_grid=40, n_pix=3300, n_mu=6, precision=W.PREC_FP32, contrast_mode=W.CONTRAST_PLANCK),
+        W.make_tiny(13, n_grid=24, n_pix=1500, n_mu=3, precision=W.PREC_FP32),
+        W.make_tiny(14, n_grid=64, n_pix=5000, n_mu=8, precision=W.PREC_FP32, with_facula=False),
+    ]
+
+
+def test_batch_equals_single_calls_on_every_replay():
+    stars = _stars()
+    ctxs = [L.soap_grid_init(s) for s in stars]
+    rng = np.random.default_rng(7)
+    cfg_ctx, cfg_star, cfg_regs, cfg_ph, outs = [], [], [], [], []
+    for i in range(13):  # stars repeat; region lists and phase counts vary
+        k = i % len(stars)
+        s = stars[k]
+        nr = int(rng.integers(0, 4))
+        types = [W.SPOT, W.FACULA] if s.spectra[W.FACULA] is not None else [W.SPOT]
+        regs = [W.Region(int(rng.choice(types)), float(rng.uniform(-60, 60)), float(rng.uniform(0, 360)),
+                         float(rng.uniform(0.05, 0.4)), float(rng.choice([1.0, rng.uniform(0.3, 1.4)])))
+                for _ in range(nr)]
+        ph = rng.uniform(0, 1, int(rng.integers(1, 40)))
+        dt = torch.float32 if s.precision == W.PREC_FP32 else torch.float64
+        cfg_ctx.append(ctxs[k])
+        cfg_star.append(s)
+        cfg_regs.append(regs)
+        cfg_ph.append(ph)
+        outs.append(torch.full((len(ph), s.n_pix), -1.0, dtype=dt, device="cuda"))
+    b = L.soap_batch_create(cfg_ctx, cfg_regs, cfg_ph, W.EFFECT_TOT, outs)
+    assert L.soap_batch_n_spectra(b) == sum(len(p) for p in cfg_ph)
+    want = []
+    for c, s, regs, ph, o in zip(cfg_ctx, cfg_star, cfg_regs, cfg_ph, outs):
+        one = torch.empty_like(o)
+        L.soap_active_spectra(c, regs, ph, W.EFFECT_TOT, one)
+        want.append(one.cpu().numpy())
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        torch.cuda.synchronize()
+        L.soap_batch_run(b)
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            np.testing.assert_array_equal(o.cpu().numpy(), want[i], err_msg=f"replay {rep} configuration {i}")
+        # eager work on the same contexts between replays
+        L.soap_active_spectra(cfg_ctx[1], cfg_regs[1], cfg_ph[1], W.EFFECT_TOT, torch.empty_like(outs[1]))
+        torch.cuda.synchronize()
+    worst = 0.0
+    for i in (0, 1, 2, 7):
+        s = cfg_star[i]
+        f = OS.integrated(s, cfg_ph[i][0], OS.TOT, regions=cfg_regs[i])
+        e = np.max(np.abs(want[i][0] - f) / np.maximum(np.abs(f), 1e-3 * np.abs(f).max()))
+        worst = max(worst, e)
+    _say(f"13 configurations over 4 stars, worst relative error vs oracle {worst:.2e}")
+    assert worst <= 1e-6
+    L.soap_batch_destroy(b)
+    for c in ctxs:
+        L.soap_destroy(c)
+
+
+def test_batch_argument_checks():
+    s = _stars()[2]
+    c = L.soap_grid_init(s)
+    o = torch.empty((2, s.n_pix), dtype=torch.float32, device="cuda")
+    r = W.Region(W.FACULA, 10.0, 20.0, 0.2, 0.5)  # this star has no facula spectra
+    with pytest.raises(L.SoapError):
+        L.soap_batch_create([c], [[W.Region(W.SPOT, 10.0, 20.0, 1.5, 0.5)]], [np.array([0.1, 0.2])],
+                            W.EFFECT_TOT, [o])
+    s4 = _stars()[3]
+    c4 = L.soap_grid_init(s4)
+    o4 = torch.empty((1, s4.n_pix), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.SoapError):
+        L.soap_batch_create([c4], [[r]], [np.array([0.1])], W.EFFECT_TOT, [o4])
+    L.soap_destroy(c)
+    L.soap_destroy(c4)
