@@ -73,6 +73,90 @@ def cpu_baseline(star, n_sample):
     }
 
 
+def batch_leg(args, L, W, np, torch):
+    """Ragged configurations over many stars (grid 100-400, 8k-206k pixel
+    windows of the full range, 25-200 phases, T_eff 4500-6500 K, 1-4
+    regions) replayed as one HIP graph; spectra per second of the whole
+    batch, and the same configurations as one call each for comparison."""
+    import types
+
+    def say(*a):
+        print("[bench] batch:", *a, file=sys.stderr, flush=True)
+
+    cfgs = W.batch_configs(args.batch_configs)
+    teffs = (4750.0, 5250.0, 5750.0, 6250.0)
+    banks = {}
+    t0 = time.perf_counter()
+    for t in teffs:
+        ln0, dln, mu_b, sp = W.make_bank(t)
+        banks[t] = (ln0, dln, mu_b, [torch.from_numpy(a).cuda() for a in sp])
+    say(f"spectral banks in {time.perf_counter() - t0:.1f} s")
+    ctxs, regs, phs, outs = [], [], [], []
+    rng = np.random.default_rng(33)
+    t0 = time.perf_counter()
+    for c in cfgs:
+        tb = min(teffs, key=lambda t: abs(t - c["teff_k"]))
+        ln0, dln, mu_b, sp = banks[tb]
+        a, P = c["start"], c["n_pix"]
+        star = types.SimpleNamespace(
+            n_grid=c["n_grid"], mu_bins=mu_b, n_pix=P, vsini_kms=c["vsini_kms"], incl_deg=c["incl_deg"],
+            ld_u1=0.4, ld_u2=0.25, ln_lambda0=ln0 + a * dln, dln_lambda=dln,
+            spectra=[x[:, a:a + P].contiguous() for x in sp], precision=W.PREC_FP32,
+            contrast_mode=W.CONTRAST_PLANCK, teff_k=c["teff_k"], dt_spot_k=663.0, dt_fac_coef=W.stars.FACULA_DT_SUN)
+        ctxs.append(L.soap_grid_init(star))
+        regs.append(c["regions"])
+        phs.append(np.sort(rng.uniform(0.0, 1.0, c["n_phases"])))
+        outs.append(torch.empty((c["n_phases"], P), dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    say(f"{len(cfgs)} contexts in {time.perf_counter() - t0:.1f} s")
+    t0 = time.perf_counter()
+    b = L.soap_batch_create(ctxs, regs, phs, W.EFFECT_TOT, outs)
+    create_s = time.perf_counter() - t0
+    n_spec = L.soap_batch_n_spectra(b)
+    L.soap_batch_run(b)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.batch_runs):
+        L.soap_batch_run(b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) / args.batch_runs
+    ms = max(e0.elapsed_time(e1) / args.batch_runs, wall * 1e3)
+    # the same configurations as one soap_active_spectra call each
+    for c, r, p, o in zip(ctxs, regs, phs, outs):
+        L.soap_active_spectra(c, r, p, W.EFFECT_TOT, o)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for c, r, p, o in zip(ctxs, regs, phs, outs):
+        L.soap_active_spectra(c, r, p, W.EFFECT_TOT, o)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - w0) * 1e3
+    out_bytes = sum(int(o.numel()) * 4 for o in outs)
+    L.soap_batch_destroy(b)
+    res = {
+        "workload": f"{len(cfgs)} configurations: grid 100-400, 8k-206k px windows of 3800-6900 A at R=115000, "
+        "25-200 phases, T_eff 4500-6500 K (4 spectral banks), v sin i 1-5 km/s, i 30-90 deg, 1-4 spots/faculae, "
+        "Planck contrast, FP32",
+        "configs": len(cfgs),
+        "spectra": n_spec,
+        "output_gb": out_bytes / 1e9,
+        "ms_per_run": ms,
+        "spectra_per_s": n_spec / (ms * 1e-3),
+        "output_gb_per_s": out_bytes / (ms * 1e-3) / 1e9,
+        "per_call_loop_ms": loop_ms,
+        "graph_speedup_vs_calls": loop_ms / ms,
+        "create_s": create_s,
+    }
+    del outs
+    for c in ctxs:
+        L.soap_destroy(c)
+    return res
+
+
 def surrogate_leg(args, L, W, np, torch):
     """Surrogate vs full synthesis on the 20000-pixel window star: RVs per
     second of each on the same held-out test samples (all inputs resident),
@@ -142,6 +226,9 @@ def main():
     ap.add_argument("--surrogate-spots", type=int, default=12500,
                     help="training spots of the surrogate leg (8 phases each; 0 = skip the leg)")
     ap.add_argument("--surrogate-epochs", type=int, default=300)
+    ap.add_argument("--batch-configs", type=int, default=512,
+                    help="configurations of the batched-graph leg (0 = skip the leg)")
+    ap.add_argument("--batch-runs", type=int, default=5)
     ap.add_argument("--surrogate-weighting", default="rv", choices=("rv", "component"),
                     help="training-loss weight of each PCA coefficient: its RV sensitivity, or uniform after "
                     "per-coefficient normalisation")
@@ -250,6 +337,11 @@ def main():
     rvh = np.frombuffer(rv.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
     assert np.all(np.isfinite(rvh["rv_kms"])) and torch.isfinite(flux).all()
 
+    bat = None
+    if args.batch_configs > 0:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        bat = batch_leg(args, L, W, np, torch)
+
     sur = None
     if args.surrogate_spots > 0:
         print("[bench] surrogate leg", file=sys.stderr, flush=True)
@@ -307,6 +399,7 @@ def main():
             "converged": int((rvh["status"] == 0).sum()),
         },
         "cpu_baseline": cpu,
+        "batch": bat,
         "surrogate": sur,
     }
     print(json.dumps(out))

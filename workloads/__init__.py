@@ -27,6 +27,8 @@ from .stars import (  # noqa: F401
     make_cfg1,
     make_cfg2,
     make_cfg5,
+    make_bank,
+    batch_configs,
     cfg5_samples,
     SpotSamples,
     make_tiny,

@@ -478,3 +478,68 @@ def cfg5_samples(n_spots: int, n_per: int = 8, seed: int = 5) -> SpotSamples:
         contrast=rng.uniform(0.3, 0.9, n_spots),
         phases=rng.uniform(0.0, 1.0, (n_spots, n_per)),
     )
+
+
+def make_bank(teff_k: float, seed: int = 3, n_mu: int = 20):
+    """Full-range local spectra (3800-6900 A at R = 115000, 205800 px) of a
+    star of effective temperature teff_k, for windows of the batched
+    workload: 30k (5778/T)^3 lines with depths scaled by (5778/T)^1.5 (capped
+    at 0.95), convective blueshift from the cubic in T_eff (clamped to its
+    4800-6300 K range), spot spectrum with 30% deeper lines and no blueshift,
+    facula spectrum = quiet lines without blueshift.  Returns (ln_lambda0,
+    dln_lambda, mu_bins, [quiet, spot, facula]) with float32 arrays
+    [n_mu][205800]."""
+    rng = np.random.default_rng([seed, int(round(teff_k))])
+    dln = 1.0 / (3.0 * 115000.0)
+    ln0 = np.log(3800.0)
+    n_pix = int(np.floor(np.log(6900.0 / 3800.0) / dln)) + 1
+    scale = 5778.0 / teff_k
+    n_lines = int(round(30000 * scale**3))
+    centre = rng.uniform(3805.0, 6895.0, n_lines)
+    u = rng.uniform(0.0, 1.0, n_lines)
+    depth = np.minimum((0.05 + 0.85 * u * u) * scale**1.5, 0.95)
+    sigma = centre * rng.uniform(1.5, 3.0, n_lines) / C_KMS
+    gamma = np.zeros(n_lines)
+    deep = np.argsort(-depth)[: n_lines // 10]
+    gamma[deep] = 0.1 * sigma[deep]
+    mu_b = 1.0 - 0.9 * np.arange(n_mu) / (n_mu - 1)
+    amp = cb_velocity_ms(float(np.clip(teff_k, 4800.0, 6300.0)))
+    cb = cb_law_ms(mu_b, amplitude_ms=amp)
+    quiet = np.stack([_render(ln0, dln, n_pix, centre, depth, sigma, gamma, v) for v in cb]).astype(np.float32)
+    spot_one = _render(ln0, dln, n_pix, centre, np.minimum(depth * 1.3, 0.99), sigma, gamma, 0.0)
+    fac_one = _render(ln0, dln, n_pix, centre, depth, sigma, gamma, 0.0)
+    spot = np.ascontiguousarray(np.broadcast_to(spot_one, (n_mu, n_pix)), dtype=np.float32)
+    fac = np.ascontiguousarray(np.broadcast_to(fac_one, (n_mu, n_pix)), dtype=np.float32)
+    return ln0, dln, mu_b, [quiet, spot, fac]
+
+
+def batch_configs(n_cfg: int, seed: int = 3, n_pix_total: int = 205800):
+    """Ragged configurations of the batched workload: grid U{100..400},
+    pixels U[8000, 206000) in a window starting uniformly over the full
+    range, phases U{25..200}, T_eff U[4500, 6500] K, v sin i U[1, 5] km/s,
+    i U[30, 90] deg, 1-4 regions (spot or facula with probability 0.5,
+    radius U[0.01, 0.10], lat U[-60, 60], lon U[0, 360))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_cfg):
+        n_pix = int(min(rng.integers(8000, 206000), n_pix_total))
+        start = int(rng.integers(0, n_pix_total - n_pix + 1))
+        nr = int(rng.integers(1, 5))
+        regs = [
+            Region(SPOT if rng.uniform() < 0.5 else FACULA, float(rng.uniform(-60.0, 60.0)),
+                   float(rng.uniform(0.0, 360.0)), float(rng.uniform(0.01, 0.10)), 1.0)
+            for _ in range(nr)
+        ]
+        out.append(
+            dict(
+                n_grid=int(rng.integers(100, 401)),
+                n_pix=n_pix,
+                start=start,
+                n_phases=int(rng.integers(25, 201)),
+                teff_k=float(rng.uniform(4500.0, 6500.0)),
+                vsini_kms=float(rng.uniform(1.0, 5.0)),
+                incl_deg=float(rng.uniform(30.0, 90.0)),
+                regions=regs,
+            )
+        )
+    return out
