@@ -158,28 +158,43 @@ def batch_leg(args, L, W, np, torch):
 
 
 def surrogate_leg(args, L, W, np, torch):
-    """Surrogate vs full synthesis on the 20000-pixel window star: RVs per
-    second of each on the same held-out test samples (all inputs resident),
-    with the surrogate gated at 10 cm/s and its fallback samples run through
-    the full synthesis inside the timed region."""
+    """Surrogate vs full synthesis on the 20000-pixel window: stars over a
+    grid of T_eff (41 values), inclination (7) and v sin i (5), one spot per
+    sample; RVs per second of each on the same held-out test samples (inputs
+    resident), the surrogate gated at 10 cm/s with its fallback samples run
+    through the full synthesis inside the timed region."""
+    from concurrent.futures import ProcessPoolExecutor
+
     from paper_2301_04259_amd import surrogate as S
 
     def say(*a):
         print("[bench] surrogate:", *a, file=sys.stderr, flush=True)
 
-    star = W.make_cfg5()
-    ctx = L.soap_grid_init(star)
     n = args.surrogate_spots
-    train = W.cfg5_samples(n, 8, seed=5)
-    held = W.cfg5_samples(max(2, n // 10), 8, seed=6)
-    test = W.cfg5_samples(max(2, n // 10), 8, seed=7)
-    model, info = S.build(ctx, star.mask, train, held, epochs=args.surrogate_epochs,
+    train = W.cfg5_multi_samples(n, 8, seed=5)
+    held = W.cfg5_multi_samples(max(2, n // 10), 8, seed=6)
+    test = W.cfg5_multi_samples(max(2, n // 10), 8, seed=7)
+    used = np.unique(np.concatenate([train.star, held.star, test.star]))
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as pool:
+        spec = {t: W.cfg5_window_spectra(t, pool=pool) for t in W.CFG5_TEFF}
+    say(f"window spectra of {len(spec)} T_eff values in {time.perf_counter() - t0:.1f} s")
+    stars = S.Stars()
+    t0 = time.perf_counter()
+    for sid in used:
+        t, inc, vs = train.star_params(sid)
+        stars.add(sid, L.soap_grid_init(W.cfg5_star(t, inc, vs, spec[float(t)])), t, inc, vs)
+    torch.cuda.synchronize()
+    say(f"{len(used)} star contexts in {time.perf_counter() - t0:.1f} s")
+    mask = W.cfg5_mask()
+    model, info = S.build(stars, mask, train, held, n_components=args.surrogate_components,
+                          epochs=args.surrogate_epochs, svd_subset=args.surrogate_svd_subset, alpha=args.surrogate_alpha,
                           weighting=args.surrogate_weighting, log=say)
     nt = (test.n // 16) * 16
     idx = np.arange(nt)
     bufs = model.alloc(nt)
-    x = torch.from_numpy(S.sample_features(test, idx)).cuda()
-    rv_plain = S.plain_rv(ctx, test, star.mask, idx)["rv_kms"]
+    x, r = model.inputs(test, idx)
+    rv_plain = S.plain_rv(stars, test, mask, idx)["rv_kms"]
 
     def timed(fn, reps):
         fn()
@@ -190,14 +205,16 @@ def surrogate_leg(args, L, W, np, torch):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / reps, out
 
-    t_plain, _ = timed(lambda: S.plain_rv(ctx, test, star.mask, idx), 5)
-    t_kern, _ = timed(lambda: model.surrogate_rv(x, bufs), 5)
+    t_plain, _ = timed(lambda: S.plain_rv(stars, test, mask, idx), 5)
+    t_kern, _ = timed(lambda: model.surrogate_rv(x, r, bufs), 5)
     t_gated, (rv_s, fb, _) = timed(lambda: model.rv(test, idx, bufs), 5)
     e = np.abs(rv_s - rv_plain) * 1e5
     acc = ~fb
     res = {
-        "workload": "20000 px window at 5000 A (R=115000), 300x300 disk, 20 mu bins, one spot per sample "
-        "(lat, lon, radius 0.01-0.10, contrast 0.3-0.9, phase); MLP 7-256-256-64 x 4 members, 64 PCA components",
+        "workload": "20000 px window at 5000 A (R=115000), 300x300 disk, 10 mu bins; stars on a grid of T_eff "
+        "4500-6500 K (50 K), i 30-90 deg (10 deg), v sin i 1-5 km/s; one spot per sample (lat, lon, radius "
+        f"0.01-0.10, contrast 0.3-0.9, phase); MLP 12-256-256-{model.k} x 4 members, {model.k} PCA components",
+        "stars": len(used),
         "train_samples": train.n,
         "test_samples": nt,
         "plain_rv_per_s": nt / t_plain,
@@ -212,7 +229,8 @@ def surrogate_leg(args, L, W, np, torch):
         "threshold_cms": 10.0,
     }
     res.update(info)
-    L.soap_destroy(ctx)
+    for c in stars.ctxs:
+        L.soap_destroy(c)
     return res
 
 
@@ -223,12 +241,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-sample", type=int, default=16, help="phases timed on the CPU oracle (0 = skip)")
     ap.add_argument("--profile-steps", type=int, default=50)
-    ap.add_argument("--surrogate-spots", type=int, default=12500,
+    ap.add_argument("--surrogate-spots", type=int, default=50000,
                     help="training spots of the surrogate leg (8 phases each; 0 = skip the leg)")
-    ap.add_argument("--surrogate-epochs", type=int, default=300)
+    ap.add_argument("--surrogate-epochs", type=int, default=100)
+    ap.add_argument("--surrogate-components", type=int, default=128, help="PCA components (multiple of 32)")
+    ap.add_argument("--surrogate-svd-subset", type=int, default=4096)
     ap.add_argument("--batch-configs", type=int, default=512,
                     help="configurations of the batched-graph leg (0 = skip the leg)")
     ap.add_argument("--batch-runs", type=int, default=5)
+    ap.add_argument("--surrogate-alpha", type=float, default=1e-3,
+                    help="gate calibration: largest fraction of accepted held-out samples allowed to miss by "
+                    ">= 10 cm/s (0 = none)")
     ap.add_argument("--surrogate-weighting", default="rv", choices=("rv", "component"),
                     help="training-loss weight of each PCA coefficient: its RV sensitivity, or uniform after "
                     "per-coefficient normalisation")

@@ -197,8 +197,8 @@ _lib.soap_ccf_linear_rv.argtypes = [_ctx_p, C.c_void_p, C.c_int64, C.c_int32, C.
                                     C.c_void_p]
 _lib.soap_ccf_linear_rv.restype = C.c_int
 _lib.soap_surrogate_rv.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
-                                   C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
-                                   C.c_void_p]
+                                   C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p]
 _lib.soap_surrogate_rv.restype = C.c_int
 class TuneC(C.Structure):
     _fields_ = [
@@ -251,8 +251,8 @@ _lib.soap_surrogate_last_error.argtypes = [_sg_p]
 _lib.soap_surrogate_last_error.restype = C.c_char_p
 _lib.soap_surrogate_destroy.argtypes = [_sg_p]
 _lib.soap_surrogate_destroy.restype = None
-_lib.soap_pca_project.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
-                                  C.c_void_p, C.c_void_p]
+_lib.soap_pca_project.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_int32, C.c_void_p, C.c_void_p]
 _lib.soap_pca_project.restype = C.c_int
 _lib.soap_surrogate_gate.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]
@@ -598,12 +598,13 @@ def soap_surrogate_destroy(s):
         s.handle = None
 
 
-def soap_pca_project(d, mean, V, coef, n_pix=None, stream=None):
-    """coef[n][k] = (d[:, :n_pix] - mean) @ V, FP32 on the GPU."""
+def soap_pca_project(d, mean, V, coef, n_pix=None, stream=None, mean_index=None):
+    """coef[n][k] = (d[:, :n_pix] - mean) @ V, FP32 on the GPU (mean row
+    mean_index[i] of a [rows][n_pix] mean when mean_index is given)."""
     n, ld = int(d.shape[0]), int(d.shape[1])
     n_pix = ld if n_pix is None else int(n_pix)
-    st = _lib.soap_pca_project(_dptr(d, "d"), n, n_pix, ld, _dptr(mean, "mean"), _dptr(V, "V"), int(V.shape[1]),
-                               _dptr(coef, "coef"), _stream_handle(stream))
+    st = _lib.soap_pca_project(_dptr(d, "d"), n, n_pix, ld, _dptr(mean, "mean"), _dptr(mean_index, "mean_index"),
+                               _dptr(V, "V"), int(V.shape[1]), _dptr(coef, "coef"), _stream_handle(stream))
     _sg_check(st, None)
     return coef
 
@@ -616,12 +617,14 @@ def soap_surrogate_gate(rv, n, n_ens, calib, threshold_kms, rv_kms, fallback, er
 
 
 def soap_surrogate_rv(ctx, coef, members, base, basis, calib, threshold_kms, rv_kms, fallback, err_kms=None,
-                      rv_out=None):
-    """Fused surrogate RV + gate (see soap.h); members [n_ens][n][k]."""
+                      rv_out=None, base_index=None):
+    """Fused surrogate RV + gate (see soap.h); members [n_ens][n][k]; with
+    base_index (int32 [n]) base is [rows][n_v], one row per star."""
     n, k = int(coef.shape[0]), int(coef.shape[1])
     n_ens = int(members.shape[0]) if members.dim() == 3 else int(members.shape[0]) // n
     st = _lib.soap_surrogate_rv(ctx.handle, _dptr(coef, "coef"), _dptr(members, "members"), n, n_ens, k,
-                                _dptr(base, "base"), _dptr(basis, "basis"), float(calib), float(threshold_kms),
+                                _dptr(base, "base"), _dptr(base_index, "base_index"), _dptr(basis, "basis"),
+                                float(calib), float(threshold_kms),
                                 _dptr(rv_out, "rv_out"), _dptr(rv_kms, "rv_kms"), _dptr(err_kms, "err_kms"),
                                 _dptr(fallback, "fallback"))
     _check(st, ctx.handle)

@@ -551,7 +551,8 @@ __global__ void __launch_bounds__(256) k_ccf_linear(int64_t n, int k, int n_v, c
 constexpr int SG_MAX_ENS = 16;
 
 // Surrogate RVs and their gate, one wave per sample (64-thread blocks):
-//   1. CCF of the ensemble-mean prediction by linearity, base + sum_k
+//   1. CCF of the ensemble-mean prediction by linearity, base (the sample's
+//      row base[base_idx[i]] when base_idx is given) + sum_k
 //      coef[i][k] basis[k] (double, increasing k: the same sums as
 //      k_ccf_linear), and its Gaussian fit (fit_wave);
 //   2. first-order RV change of each member: the fitted parameters move by
@@ -563,19 +564,21 @@ constexpr int SG_MAX_ENS = 16;
 //      fallback when err is not below thr or the fit did not converge.
 __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, double v0, double dv,
                                               const float* __restrict__ coef, const float* __restrict__ members,
-                                              const double* __restrict__ base, const double* __restrict__ basis,
-                                              double calib, double thr, soap_rv* __restrict__ out,
+                                              const double* __restrict__ base, const int* __restrict__ base_idx,
+                                              const double* __restrict__ basis, double calib, double thr,
+                                              soap_rv* __restrict__ out,
                                               double* __restrict__ rv_kms, double* __restrict__ err_kms,
                                               int* __restrict__ fallback) {
   __shared__ double s_c[64];
   __shared__ double s_g[GF_MAXPT * 64];
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
+  const double* bs = base + (base_idx ? (int64_t)base_idx[i] * n_v : 0);
   double y[GF_MAXPT];
 #pragma unroll
   for (int t = 0; t < GF_MAXPT; ++t) {
     const int v = lane + 64 * t;
-    y[t] = v < n_v ? base[v] : 0.0;
+    y[t] = v < n_v ? bs[v] : 0.0;
   }
   for (int k0 = 0; k0 < k; k0 += 64) {
     __syncthreads();
@@ -669,10 +672,11 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
 }
 
 hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
-                        const double* d_base, const double* d_basis, double calib, double thr, soap_rv* d_rv,
-                        double* d_rv_kms, double* d_err, int* d_fallback) {
+                        const double* d_base, const int* d_base_idx, const double* d_basis, double calib,
+                        double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err, int* d_fallback) {
   hipLaunchKernelGGL(k_sg_rv, dim3((unsigned)n), dim3(64), 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,
-                     c->mask_dv, d_coef, d_members, d_base, d_basis, calib, thr, d_rv, d_rv_kms, d_err, d_fallback);
+                     c->mask_dv, d_coef, d_members, d_base, d_base_idx, d_basis, calib, thr, d_rv, d_rv_kms, d_err,
+                     d_fallback);
   return hipGetLastError();
 }
 

@@ -5,33 +5,41 @@ library's kernels).
 Pipeline (the synthesis it stands in for: Algorithm 5, Eqs. 1-4; its RV:
 section 4.1):
 
-  synthesize      runs soap_active_spectra_jobs over the single-spot samples and
-                  keeps the spectra F (device, float32)
+  synthesize      runs soap_active_spectra_jobs over the single-spot samples
+                  of each star (one context per star) and keeps the spectra F
+                  (device, float32)
   fit_basis       offline: mean and the first k principal axes of the
-                  differences F - Q from an FP64 SVD of a subset (host), then
+                  differences F - Q (Q the sample's own star's quiet
+                  spectrum) from an FP64 SVD of a subset (host), then
                   per-component normalisation of the projected coefficients
   train           Adam steps of every ensemble member on shuffled batches
                   (soap_surrogate_train_step)
   calibrate       on held-out samples with known full-synthesis RVs, the
                   factor that turns the members' RV spread into a predicted
-                  error bound (a quantile of |error| / spread)
+                  error bound
   rv              surrogate RVs of a batch: soap_surrogate_predict ->
-                  soap_surrogate_rv (CCF of the quiet-plus-basis expansion by
-                  linearity, its fit, the members' first-order RV spread and
-                  the gate); samples whose
-                  predicted error is not below the threshold go through the
-                  full synthesis (soap_active_spectra_jobs + soap_ccf_rv)
+                  soap_surrogate_rv (CCF of the star's quiet-plus-basis
+                  expansion by linearity, its fit, the members' first-order
+                  RV spread and the gate); samples whose predicted error is
+                  not below the threshold go through the full synthesis
+                  (soap_active_spectra_jobs + soap_ccf_rv)
 
-The input features of a sample are its spot latitude, the sine and cosine of
-its longitude at the observed phase (longitude + 360 deg x phase: the star
-looks the same for equal values of that sum), the same two scaled by the
-cosine of the latitude (for an equator-on star, the spot centre's position
-across the disk and its mu), its radius and its contrast, each scaled to
-about unit range.
+Stars: a `Stars` set maps star ids to contexts that share one wavelength
+window and one mask (the stars differ in T_eff, inclination and v sin i).
+Samples are SpotSamples (one star, id 0) or MultiSpotSamples (a star id per
+spot, spots ordered by star so that any sorted subset is grouped by star).
+
+Input features of a sample: spot latitude; sine and cosine of its longitude
+at the observed phase (longitude + 360 deg x phase: the star looks the same
+for equal values of that sum); the spot centre's position across the disk,
+along the projected axis and towards the observer for the star's
+inclination; radius; contrast; T_eff, inclination and v sin i of the star;
+each scaled to about unit range.
 """
 from __future__ import annotations
 
 import math
+import time
 from dataclasses import dataclass
 
 import numpy as np
@@ -46,12 +54,12 @@ from . import (
     soap_ccf_rv,
     soap_quiet_spectrum,
     soap_surrogate_create,
-    soap_surrogate_rv,
     soap_surrogate_predict,
+    soap_surrogate_rv,
     soap_surrogate_train_step,
 )
 
-N_FEATURES = 7
+N_FEATURES = 12
 
 
 def _torch():
@@ -62,70 +70,129 @@ def _torch():
     return torch
 
 
-def features(lat_deg, lon_deg, radius, contrast, phase):
-    """float32 [n][7] inputs of the network (see the module docstring)."""
+def features(lat_deg, lon_deg, radius, contrast, phase, teff_k, incl_deg, vsini_kms):
+    """float32 [n][12] inputs of the network (see the module docstring)."""
     lat = np.deg2rad(np.asarray(lat_deg, np.float64))
     th = np.deg2rad(np.asarray(lon_deg, np.float64) + 360.0 * np.asarray(phase, np.float64))
-    x = np.stack(
+    inc = np.deg2rad(np.asarray(incl_deg, np.float64))
+    cl = np.cos(lat)
+    x = cl * np.sin(th)
+    y = np.sin(lat) * np.sin(inc) - cl * np.cos(th) * np.cos(inc)
+    z = np.sin(lat) * np.cos(inc) + cl * np.cos(th) * np.sin(inc)
+    f = np.stack(
         [
             lat / np.deg2rad(60.0),
             np.sin(th),
             np.cos(th),
-            np.cos(lat) * np.sin(th),
-            np.cos(lat) * np.cos(th),
+            x,
+            y,
+            z,
             (np.asarray(radius, np.float64) - 0.055) / 0.045,
             (np.asarray(contrast, np.float64) - 0.6) / 0.3,
+            (np.asarray(teff_k, np.float64) - 5500.0) / 1000.0,
+            (np.rad2deg(inc) - 60.0) / 30.0,
+            (np.asarray(vsini_kms, np.float64) - 3.0) / 2.0,
+            np.ones_like(lat),
         ],
         axis=-1,
     )
-    return np.ascontiguousarray(x, dtype=np.float32)
+    return np.ascontiguousarray(f, dtype=np.float32)
 
 
-def sample_features(samples, idx=None):
-    """Features of samples (a SpotSamples), optionally of the indices idx."""
-    n_per = samples.n_per
+class Stars:
+    """Contexts of the stars of a data set: ids -> context and
+    (T_eff, inclination, v sin i).  All share the wavelength window."""
+
+    def __init__(self):
+        self.ids, self.ctxs, self.params = [], [], []
+        self.row = {}
+
+    def add(self, star_id, ctx, teff_k, incl_deg, vsini_kms):
+        self.row[int(star_id)] = len(self.ids)
+        self.ids.append(int(star_id))
+        self.ctxs.append(ctx)
+        self.params.append((float(teff_k), float(incl_deg), float(vsini_kms)))
+
+    @property
+    def ref(self):
+        return self.ctxs[0]
+
+    def rows(self, star_ids):
+        return np.array([self.row[int(s)] for s in np.asarray(star_ids).reshape(-1)], dtype=np.int32)
+
+
+def single_star(ctx, teff_k=5778.0):
+    s = Stars()
+    st = ctx.star
+    s.add(0, ctx, teff_k, st.incl_deg, st.vsini_kms)
+    return s
+
+
+def sample_stars(samples, idx):
+    """Star id of each sample (0 for one-star sample sets)."""
+    star = getattr(samples, "star", None)
+    k = np.asarray(idx) // samples.n_per
+    return np.zeros(len(k), np.int64) if star is None else np.asarray(star)[k]
+
+
+def sample_features(stars, samples, idx=None):
     i = np.arange(samples.n) if idx is None else np.asarray(idx)
-    k = i // n_per
+    k = i // samples.n_per
+    p = np.asarray(stars.params)[stars.rows(sample_stars(samples, i))]
     return features(samples.lat_deg[k], samples.lon_deg[k], samples.radius[k], samples.contrast[k],
-                    samples.phases.reshape(-1)[i])
+                    samples.phases.reshape(-1)[i], p[:, 0], p[:, 1], p[:, 2])
 
 
-def synthesize(ctx, samples, out, idx=None):
+def _groups(keys):
+    keys = np.asarray(keys)
+    starts = np.flatnonzero(np.r_[True, keys[1:] != keys[:-1]])
+    return starts, np.r_[starts[1:], len(keys)]
+
+
+def synthesize(stars, samples, out, idx=None):
     """Full synthesis of samples (all, or the sorted indices idx) into out
-    [n][n_pix] (device): one soap_active_spectra_jobs call, one job per spot
-    with the phases of its selected samples."""
+    [n][n_pix] (device): per star, one soap_active_spectra_jobs call, one job
+    per spot with the phases of its selected samples."""
     n_per = samples.n_per
     idx = np.arange(samples.n) if idx is None else np.asarray(idx)
     if len(idx) == 0:
         return out
-    spots = idx // n_per
-    starts = np.flatnonzero(np.r_[True, spots[1:] != spots[:-1]])
-    ends = np.r_[starts[1:], len(idx)]
+    sid = sample_stars(samples, idx)
     ph = samples.phases.reshape(-1)
-    k = spots[starts]
-    regions = region_array(SPOT, samples.lat_deg[k], samples.lon_deg[k], samples.radius[k], samples.contrast[k])
-    roff = np.arange(len(starts) + 1, dtype=np.int32)
-    poff = np.r_[starts, len(idx)].astype(np.int32)
-    soap_active_spectra_jobs(ctx, regions, ph[idx], EFFECT_TOT, out[: len(idx)], region_offsets=roff,
-                             phase_offsets=poff)
+    for a0, b0 in zip(*_groups(sid)):
+        ctx = stars.ctxs[stars.row[int(sid[a0])]]
+        sub = idx[a0:b0]
+        spots = sub // n_per
+        starts, _ = _groups(spots)
+        k = spots[starts]
+        regions = region_array(SPOT, samples.lat_deg[k], samples.lon_deg[k], samples.radius[k],
+                               samples.contrast[k])
+        roff = np.arange(len(starts) + 1, dtype=np.int32)
+        poff = np.r_[starts, len(sub)].astype(np.int32)
+        soap_active_spectra_jobs(ctx, regions, ph[sub], EFFECT_TOT, out[a0:b0], region_offsets=roff,
+                                 phase_offsets=poff)
     return out
 
 
-def plain_rv(ctx, samples, mask, idx=None, chunk=4096):
+def plain_rv(stars, samples, mask, idx=None, chunk=4096):
     """RVs of samples (or of the sorted indices idx) by the full synthesis:
-    host RV_DTYPE records."""
+    host RV_DTYPE records.  The CCF and fit of every chunk run on the
+    reference context (the stars share the wavelength window)."""
     torch = _torch()
+    if not isinstance(stars, Stars):
+        stars = single_star(stars)
     idx = np.arange(samples.n) if idx is None else np.asarray(idx)
     rv = np.zeros(len(idx), dtype=RV_DTYPE)
     if len(idx) == 0:
         return rv
-    dt = torch.float32 if ctx.precision == PREC_FP32 else torch.float64
-    buf = torch.empty((min(chunk, len(idx)), ctx.n_pix), dtype=dt, device="cuda")
+    ref = stars.ref
+    dt = torch.float32 if ref.precision == PREC_FP32 else torch.float64
+    buf = torch.empty((min(chunk, len(idx)), ref.n_pix), dtype=dt, device="cuda")
     for a in range(0, len(idx), chunk):
         b = min(len(idx), a + chunk)
-        synthesize(ctx, samples, buf[: b - a], idx[a:b])
+        synthesize(stars, samples, buf[: b - a], idx[a:b])
         part = np.zeros(b - a, dtype=RV_DTYPE)
-        soap_ccf_rv(ctx, buf[: b - a], mask, rv_out=part, n_spec=b - a)
+        soap_ccf_rv(ref, buf[: b - a], mask, rv_out=part, n_spec=b - a)
         rv[a:b] = part
     return rv
 
@@ -148,58 +215,85 @@ def quiet(ctx):
     return q.astype(np.float64)
 
 
-def fit_basis(F_host_subset, Q, k):
-    """Offline principal axes of F - Q from a host subset (FP64 SVD)."""
-    D = np.asarray(F_host_subset, np.float64) - Q
+def fit_basis(D_host_subset, k):
+    """Offline principal axes of differences D = F - Q (FP64 SVD)."""
+    D = np.asarray(D_host_subset, np.float64)
     mean = D.mean(axis=0)
     _, _, vt = np.linalg.svd(D - mean, full_matrices=False)
-    V = np.ascontiguousarray(vt[:k].T)
-    return mean, V
+    return mean, np.ascontiguousarray(vt[:k].T)
 
 
 class SurrogateModel:
-    """Trained surrogate of one star: network, basis, linear CCF tables and
-    the gate's calibration.  Device tables live on the current GPU."""
+    """Trained surrogate of a set of stars: network, basis, linear CCF
+    tables and the gate's calibration.  Device tables live on the current
+    GPU."""
 
-    def __init__(self, ctx, mask, n_components=64, hidden=256, n_ensemble=4, seed=0):
+    def __init__(self, stars, mask, n_components=64, hidden=256, n_ensemble=4, seed=0):
         self.torch = _torch()
-        self.ctx, self.mask = ctx, mask
+        if not isinstance(stars, Stars):
+            stars = single_star(stars)
+        self.stars, self.mask = stars, mask
+        self.ctx = stars.ref
         self.k, self.hidden, self.n_ens = int(n_components), int(hidden), int(n_ensemble)
         self.net = soap_surrogate_create(N_FEATURES, self.hidden, self.k, self.n_ens, seed)
-        self.Q = quiet(ctx)
+        self.Q = np.stack([quiet(c) for c in stars.ctxs])  # [rows][P]
         self.basis = None
         self.calib = 1.0
         self.threshold_kms = 1e-4  # 10 cm/s
 
     # -- data ---------------------------------------------------------------
-    def project(self, F_dev):
-        """Raw PCA coefficients [n][k] (device, float32) of spectra F."""
+    def differences_host(self, F_dev, star_ids):
+        """F - Q of device spectra (host float64), for the offline SVD."""
+        return F_dev.cpu().numpy().astype(np.float64) - self.Q[self.stars.rows(star_ids)]
+
+    def install_projection(self, mean, V):
+        """Device arrays of project(): per-star centres Q_s + mean and V
+        (float32)."""
+        torch = self.torch
+        self._centre_dev = torch.from_numpy((self.Q + np.asarray(mean)[None, :]).astype(np.float32)).cuda()
+        self._V_dev = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float32)).cuda()
+
+    def project(self, F_dev, star_ids):
+        """Raw PCA coefficients (host float64 [n][k]) of spectra F of the
+        given stars: (F - (Q_s + mean)) V, each row centred on its own
+        star."""
         torch = self.torch
         from . import soap_pca_project
 
         n = int(F_dev.shape[0])
         coef = torch.empty((n, self.k), dtype=torch.float32, device="cuda")
-        soap_pca_project(F_dev, self._centre_dev, self._V_dev, coef)
-        return coef
+        rows = torch.from_numpy(self.stars.rows(star_ids)).cuda()
+        soap_pca_project(F_dev, self._centre_dev, self._V_dev, coef, mean_index=rows)
+        return coef.cpu().numpy().astype(np.float64)
 
-    def rv_weights(self, Yn, eps=0.05):
-        """RMS over the rows of Yn (normalised coefficients, host [m][k]) of
-        the RV change per unit change of each coefficient, by central
-        differences through soap_ccf_linear_rv."""
+    def rv_weights(self, Yn, rows, eps=0.05):
+        """RMS over the rows of Yn (normalised coefficients, host [m][k], of
+        star rows `rows`) of the RV change per unit change of each
+        coefficient, by central differences through the fused RV kernel's
+        mean fit."""
         torch = self.torch
-        from . import soap_ccf_linear_rv
-
         m, k = Yn.shape
-        rows = np.repeat(np.asarray(Yn, np.float32)[:, None, :], 2 * k, axis=1)
+        X = np.repeat(np.asarray(Yn, np.float32)[:, None, :], 2 * k, axis=1)
         for j in range(k):
-            rows[:, 2 * j, j] += eps
-            rows[:, 2 * j + 1, j] -= eps
-        rows = rows.reshape(-1, k)
-        rv = torch.empty(len(rows) * RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-        soap_ccf_linear_rv(self.ctx, torch.from_numpy(np.ascontiguousarray(rows)).cuda(), self.base_ccf,
-                           self.basis_ccf, None, rv)
-        r = np.frombuffer(rv.cpu().numpy().tobytes(), dtype=RV_DTYPE)["rv_kms"].reshape(m, k, 2)
+            X[:, 2 * j, j] += eps
+            X[:, 2 * j + 1, j] -= eps
+        X = X.reshape(-1, k)
+        r = self._fit_rows(torch.from_numpy(np.ascontiguousarray(X)).cuda(),
+                           torch.from_numpy(np.repeat(np.asarray(rows, np.int32), 2 * k)).cuda(), len(X))
+        r = r.reshape(m, k, 2)
         return np.sqrt(np.mean(((r[:, :, 0] - r[:, :, 1]) / (2 * eps)) ** 2, axis=0))
+
+    def _fit_rows(self, coef_dev, rows_dev, n):
+        """RVs (host) of normalised coefficient rows, through
+        soap_surrogate_rv with two identical members (only its mean fit
+        matters here)."""
+        torch = self.torch
+        mem = torch.stack([coef_dev, coef_dev]).contiguous()
+        rv_kms = torch.empty(n, dtype=torch.float64, device="cuda")
+        fb = torch.empty(n, dtype=torch.int32, device="cuda")
+        soap_surrogate_rv(self.ctx, coef_dev, mem, self.base_ccf, self.basis_ccf, 1.0, math.inf, rv_kms, fb,
+                          base_index=rows_dev)
+        return rv_kms.cpu().numpy()
 
     def reweight(self, w):
         """Rescales the normalised coefficients by w / rms(w), so that the
@@ -209,42 +303,34 @@ class SurrogateModel:
         b.sigma = b.sigma * np.sqrt(np.mean(w * w)) / w
         self._build_ccf_tables()
 
-    def set_basis(self, mean, V, coef_train, norm="global"):
-        """Installs the basis and the normalisation of the training
-        coefficients (host [n][k]): centred, then divided by their own
-        standard deviations (norm="component") or all by the largest one
-        (norm="global", which keeps the loss proportional to the spectral
-        error)."""
+    def set_basis(self, mean, V, coef_train):
+        """Installs the basis and the per-coefficient normalisation of the
+        training coefficients (host [n][k]): centred, divided by their
+        standard deviations."""
         c = np.asarray(coef_train, np.float64)
         mu = c.mean(axis=0)
         sd = c.std(axis=0)
-        if norm == "global":
-            sd = np.full_like(sd, sd.max())
         sd = np.where(sd > 0, sd, 1.0)
         self.basis = Basis(np.asarray(mean, np.float64), np.asarray(V, np.float64), mu, sd)
         self._build_ccf_tables()
         return mu, sd
 
-    def install_projection(self, mean, V):
-        """Device arrays used by project(): centre = Q + mean, V (float32)."""
-        torch = self.torch
-        self._centre_dev = torch.from_numpy((self.Q + mean).astype(np.float32)).cuda()
-        self._V_dev = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float32)).cuda()
-
     def _build_ccf_tables(self):
-        """CCF of F0 = Q + mean + V mu and of B_k = sigma_k V_k, so that the
-        CCF of a prediction y is base + y @ basis."""
+        """CCF of F0_s = Q_s + mean + V mu for every star and of
+        B_k = sigma_k V_k, so that the CCF of a prediction y of star s is
+        base[s] + y @ basis."""
         torch = self.torch
         b = self.basis
-        f0 = self.Q + b.mean + b.V @ b.mu
-        rows = np.concatenate([f0[None, :], (b.V * b.sigma[None, :]).T], axis=0)
+        f0 = self.Q + (b.mean + b.V @ b.mu)[None, :]
+        rows = np.concatenate([f0, (b.V * b.sigma[None, :]).T], axis=0)
         dt = torch.float32 if self.ctx.precision == PREC_FP32 else torch.float64
         rows_dev = torch.from_numpy(np.ascontiguousarray(rows).astype(self.ctx.dtype)).to("cuda", dt)
         n_v = int(self.mask.n_v)
         ccf = torch.empty((rows.shape[0], n_v), dtype=torch.float64, device="cuda")
         soap_ccf_rv(self.ctx, rows_dev, self.mask, ccf_out=ccf, n_spec=rows.shape[0])
-        self.base_ccf = ccf[0].contiguous()
-        self.basis_ccf = ccf[1:].contiguous()
+        ns = len(self.Q)
+        self.base_ccf = ccf[:ns].contiguous()
+        self.basis_ccf = ccf[ns:].contiguous()
 
     def normalise(self, coef_host):
         b = self.basis
@@ -252,9 +338,9 @@ class SurrogateModel:
 
     # -- training -----------------------------------------------------------
     def train(self, X, Y, epochs, batch=512, lr=2e-3, lr_final=1e-4, seed=0, log=None):
-        """Adam over shuffled batches (X [n][5], Y [n][k] normalised, host
-        float32).  The learning rate decays geometrically from lr to
-        lr_final.  Returns the per-epoch mean losses."""
+        """Adam over shuffled batches (X [n][features], Y [n][k] normalised,
+        host float32).  The learning rate decays geometrically from lr to
+        lr_final.  Returns the last batch's loss of every epoch."""
         torch = self.torch
         rng = np.random.default_rng(seed)
         n = (len(X) // batch) * batch
@@ -286,101 +372,119 @@ class SurrogateModel:
         E = self.n_ens
         return dict(
             Y=torch.empty(((1 + E) * n, self.k), dtype=torch.float32, device="cuda"),
-            rv=torch.empty(((1 + E) * n * RV_DTYPE.itemsize,), dtype=torch.uint8, device="cuda"),
+            rv=torch.empty((n * RV_DTYPE.itemsize,), dtype=torch.uint8, device="cuda"),
             rv_kms=torch.empty((n,), dtype=torch.float64, device="cuda"),
             err=torch.empty((n,), dtype=torch.float64, device="cuda"),
             fallback=torch.empty((n,), dtype=torch.int32, device="cuda"),
             n=n,
         )
 
-    def surrogate_rv(self, x_dev, bufs, calib=None, threshold_kms=None):
+    def surrogate_rv(self, x_dev, rows_dev, bufs, calib=None, threshold_kms=None):
         """Enqueues predict -> fused mean-CCF fit, member RV spread and gate
-        for x_dev [n][features]."""
+        for x_dev [n][features] of star rows rows_dev (int32 [n], device)."""
         n = bufs["n"]
         Y = bufs["Y"]
         soap_surrogate_predict(self.net, x_dev, Y[:n], Y[n:])
         soap_surrogate_rv(self.ctx, Y[:n], Y[n:], self.base_ccf, self.basis_ccf,
                           self.calib if calib is None else calib,
                           self.threshold_kms if threshold_kms is None else threshold_kms, bufs["rv_kms"],
-                          bufs["fallback"], err_kms=bufs["err"], rv_out=bufs["rv"])
+                          bufs["fallback"], err_kms=bufs["err"], rv_out=bufs["rv"], base_index=rows_dev)
+
+    def inputs(self, samples, idx):
+        """Device features and star rows of samples[idx]."""
+        torch = self.torch
+        x = torch.from_numpy(sample_features(self.stars, samples, idx)).cuda()
+        r = torch.from_numpy(self.stars.rows(sample_stars(samples, idx))).cuda()
+        return x, r
 
     def rv(self, samples, idx, bufs, threshold_kms=None):
         """Gated RVs (km/s, host float64) of samples[idx]; idx sorted, its
         length a multiple of 16.  Returns (rv, fallback flags, predicted
         errors)."""
-        torch = self.torch
-        x = torch.from_numpy(sample_features(samples, idx)).cuda()
-        self.surrogate_rv(x, bufs, threshold_kms=threshold_kms)
+        x, r = self.inputs(samples, idx)
+        self.surrogate_rv(x, r, bufs, threshold_kms=threshold_kms)
         fb = bufs["fallback"].cpu().numpy().astype(bool)
         out = bufs["rv_kms"].cpu().numpy().copy()
         err = bufs["err"].cpu().numpy().copy()
         sel = np.asarray(idx)[fb]
         if len(sel):
-            out[fb] = plain_rv(self.ctx, samples, self.mask, sel)["rv_kms"]
+            out[fb] = plain_rv(self.stars, samples, self.mask, sel)["rv_kms"]
         return out, fb, err
 
-    def calibrate(self, samples, idx, rv_plain_kms, bufs, threshold_kms=None, margin=1.25):
+    def calibrate(self, samples, idx, rv_plain_kms, bufs, threshold_kms=None, alpha=1e-3):
         """Sets calib from held-out samples with known full-synthesis RVs:
-        the smallest factor for which every held-out sample whose surrogate
-        error reaches the threshold is predicted to reach it too (times a
-        margin; the 99th percentile of |error| / spread when no sample
-        reaches the threshold).  Returns (|error|, spread) in km/s."""
-        torch = self.torch
+        the factor that accepts the most held-out samples (predicted error
+        calib x spread below the threshold) while at most a fraction alpha
+        of the accepted ones miss the full synthesis by the threshold or
+        more (alpha = 0: none may).  Returns (|error|, spread) in km/s."""
         thr = self.threshold_kms if threshold_kms is None else threshold_kms
-        x = torch.from_numpy(sample_features(samples, idx)).cuda()
-        self.surrogate_rv(x, bufs, calib=1.0, threshold_kms=math.inf)
-        spread = np.maximum(bufs["err"].cpu().numpy(), 1e-12)
+        x, r = self.inputs(samples, idx)
+        self.surrogate_rv(x, r, bufs, calib=1.0, threshold_kms=math.inf)
+        spread = np.maximum(bufs["err"].cpu().numpy(), 1e-300)
         err = np.abs(bufs["rv_kms"].cpu().numpy() - rv_plain_kms)
-        bad = err >= thr
-        if bad.any():
-            self.calib = float(margin * np.max(thr / spread[bad]))
+        # sample i is accepted iff calib < t_i = thr / spread_i: the accepted
+        # sets are the m samples of largest t
+        t = thr / spread
+        order = np.argsort(-t, kind="stable")
+        bad = np.cumsum(err[order] >= thr)
+        m = np.arange(1, len(t) + 1)
+        ok = np.flatnonzero(bad <= alpha * m)
+        if len(ok) == 0:
+            self.calib = float(t[order[0]]) * 2.0  # accept nothing
         else:
-            self.calib = float(np.quantile(err / spread, 0.99))
+            mm = int(ok[-1]) + 1  # accept the top mm samples
+            self.calib = float(t[order[mm]]) if mm < len(t) else float(0.5 * t[order[-1]])
         return err, spread
 
-
-def build(ctx, mask, train, heldout, n_components=64, hidden=256, n_ensemble=4, epochs=100, batch=512,
-          svd_subset=2048, seed=0, weighting="rv", log=None):
-    """Data set, basis, training and gate calibration of a surrogate for the
-    star of ctx (an FP32 context) from SpotSamples train / heldout.  Returns
-    the model and a dict of what it took."""
+def build(stars, mask, train, heldout, n_components=64, hidden=256, n_ensemble=4, epochs=100, batch=512,
+          svd_subset=2048, seed=0, weighting="rv", alpha=1e-3, log=None):
+    """Data set, basis, training and gate calibration of a surrogate for a
+    Stars set (FP32 contexts; or one context) from SpotSamples or
+    MultiSpotSamples train / heldout.  Returns the model and a dict of what
+    it took."""
     torch = _torch()
     say = log or (lambda *a: None)
     info = {}
-    model = SurrogateModel(ctx, mask, n_components, hidden, n_ensemble, seed)
-    F = torch.empty((train.n, ctx.n_pix), dtype=torch.float32, device="cuda")
+    model = SurrogateModel(stars, mask, n_components, hidden, n_ensemble, seed)
+    stars = model.stars
+    F = torch.empty((train.n, model.ctx.n_pix), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
-    t = __import__("time").perf_counter()
-    synthesize(ctx, train, F)
+    t = time.perf_counter()
+    synthesize(stars, train, F)
     torch.cuda.synchronize()
-    info["synth_s"] = __import__("time").perf_counter() - t
+    info["synth_s"] = time.perf_counter() - t
     say(f"synthesised {train.n} training spectra in {info['synth_s']:.2f} s")
+    sid = sample_stars(train, np.arange(train.n))
     sub = np.sort(np.random.default_rng(seed).choice(train.n, min(svd_subset, train.n), replace=False))
-    Fh = F[torch.from_numpy(sub).cuda()].cpu().numpy()
-    mean, V = fit_basis(Fh, model.Q, n_components)
-    del Fh
+    D = model.differences_host(F[torch.from_numpy(sub).cuda()], sid[sub])
+    mean, V = fit_basis(D, n_components)
+    del D
     model.install_projection(mean, V)
-    coef = model.project(F).cpu().numpy()
+    coef = np.concatenate([model.project(F[a:a + 8192], sid[a:a + 8192]) for a in range(0, train.n, 8192)])
     del F
-    model.set_basis(mean, V, coef, norm="component")
+    model.set_basis(mean, V, coef)
+    rows = stars.rows(sid)
     if weighting == "rv":
         sel = np.random.default_rng(seed + 1).choice(len(coef), min(512, len(coef)), replace=False)
-        w = model.rv_weights(model.normalise(coef[sel]))
+        w = model.rv_weights(model.normalise(coef[sel]), rows[sel])
         model.reweight(w)
         info["rv_weights"] = [float(v) for v in w[:8]]
-    X = sample_features(train)
+    X = sample_features(stars, train)
     Y = model.normalise(coef)
-    t = __import__("time").perf_counter()
+    t = time.perf_counter()
     losses = model.train(X, Y, epochs, batch=batch, seed=seed)
     torch.cuda.synchronize()
-    info["train_s"] = __import__("time").perf_counter() - t
+    info["train_s"] = time.perf_counter() - t
     info["train_steps"] = epochs * (len(X) // batch)
     info["final_loss"] = losses[-1]
     say(f"trained {info['train_steps']} steps in {info['train_s']:.2f} s, loss {losses[-1]:.3g}")
-    rvp = plain_rv(ctx, heldout, mask)["rv_kms"]
     n_ho = (heldout.n // 16) * 16
-    err, spread = model.calibrate(heldout, np.arange(n_ho), rvp[:n_ho], model.alloc(n_ho))
+    rvp = plain_rv(stars, heldout, mask, np.arange(n_ho))["rv_kms"]
+    err, spread = model.calibrate(heldout, np.arange(n_ho), rvp, model.alloc(n_ho), alpha=alpha)
     info["calib"] = model.calib
+    acc = model.calib * spread < model.threshold_kms
+    info["heldout_accepted_frac"] = float(acc.mean())
+    info["heldout_accepted_over_thr_frac"] = float(np.mean(err[acc] >= model.threshold_kms)) if acc.any() else 0.0
     info["heldout_err_cms"] = {"median": float(np.median(err) * 1e5), "p99": float(np.quantile(err, 0.99) * 1e5),
                                "max": float(err.max() * 1e5)}
     return model, info

@@ -11,6 +11,7 @@ import workloads as W
 from oracle import ccf as OC
 from oracle import fit as OF
 from oracle import surrogate as OSG
+from oracle import spectrum as OS_spec
 
 pytestmark = pytest.mark.gpu
 
@@ -209,6 +210,22 @@ def test_host_checks_reject_bad_shapes():
         L.soap_surrogate_train_step(s, x, y, lr=1e-3)  # batch not a multiple of 32
 
 
+def test_pca_projection_with_per_row_centres():
+    rng = np.random.default_rng(65)
+    n, P, k, rows = 70, 3000, 20, 5
+    D = rng.normal(1.0, 0.1, (n, P)).astype(np.float32)
+    M = rng.normal(1.0, 0.1, (rows, P)).astype(np.float32)
+    idx = rng.integers(0, rows, n).astype(np.int32)
+    V, _ = np.linalg.qr(rng.normal(size=(P, k)))
+    V = V.astype(np.float32)
+    coef = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    L.soap_pca_project(_dev(D), _dev(M), _dev(V), coef, mean_index=torch.from_numpy(idx).cuda())
+    want = np.stack([OSG.pca_project(D[i:i + 1].astype(np.float64), M[idx[i]].astype(np.float64),
+                                     V.astype(np.float64))[0] for i in range(n)])
+    tol = 4.0 * P * 2.0**-24 * np.abs(D - M[idx]).max() * np.abs(V).max()
+    assert np.abs(coef.cpu().numpy() - want).max() <= tol
+
+
 @pytest.mark.parametrize("n,P,k", [(100, 1000, 37), (64, 64, 64), (1, 33, 1), (130, 20000, 64)])
 def test_pca_projection_matches_oracle(n, P, k):
     _say("pca", n, P, k)
@@ -296,30 +313,66 @@ def test_gate_matches_oracle():
     assert int(out_fb.sum()) == n
 
 
-def test_threshold_zero_gives_the_full_synthesis_bit_for_bit():
+def _multi_star_set(S, teffs=(5000.0, 6000.0), n_grid=64):
+    """Contexts of every grid star with the given T_eff values."""
+    stars = S.Stars()
+    spec = {t: W.cfg5_window_spectra(t) for t in teffs}
+    for ti, t in enumerate(W.CFG5_TEFF):
+        if t not in spec:
+            continue
+        for ii, inc in enumerate(W.CFG5_INCL):
+            for vi, vs in enumerate(W.CFG5_VSINI):
+                sid = (ti * len(W.CFG5_INCL) + ii) * len(W.CFG5_VSINI) + vi
+                stars.add(sid, L.soap_grid_init(W.cfg5_star(t, inc, vs, spec[t], n_grid=n_grid)), t, inc, vs)
+    return stars
+
+
+@pytest.mark.parametrize("multi", [False, True])
+def test_threshold_zero_gives_the_full_synthesis_bit_for_bit(multi):
     from paper_2301_04259_amd import surrogate as S
 
-    star = W.make_cfg5(n_grid=100)
-    ctx = L.soap_grid_init(star)
-    smp = W.cfg5_samples(6, n_per=8, seed=11)
-    model = S.SurrogateModel(ctx, star.mask, n_components=32, hidden=64, n_ensemble=2, seed=5)
-    F = torch.empty((smp.n, star.n_pix), dtype=torch.float32, device="cuda")
-    S.synthesize(ctx, smp, F)
-    Fh = F.cpu().numpy()
-    mean, V = S.fit_basis(Fh, model.Q, 32)
+    if multi:
+        stars = _multi_star_set(S)
+        mask = W.cfg5_mask()
+        smp = W.cfg5_multi_samples(12, n_per=8, seed=11, teff_subset=[5000.0, 6000.0])
+    else:
+        star = W.make_cfg5(n_grid=100)
+        stars = S.single_star(L.soap_grid_init(star))
+        mask = star.mask
+        smp = W.cfg5_samples(6, n_per=8, seed=11)
+    _say("stars", len(stars.ids), "samples", smp.n)
+    model = S.SurrogateModel(stars, mask, n_components=32, hidden=64, n_ensemble=2, seed=5)
+    F = torch.empty((smp.n, stars.ref.n_pix), dtype=torch.float32, device="cuda")
+    S.synthesize(stars, smp, F)
+    sid = S.sample_stars(smp, np.arange(smp.n))
+    mean, V = S.fit_basis(model.differences_host(F, sid), 32)
     model.install_projection(mean, V)
-    coef = model.project(F).cpu().numpy()
+    coef = model.project(F, sid)
+    # projection of F - Q_s (per-row centres in the kernel) matches the
+    # host FP64 product within FP32 rounding of 20000-term sums
+    want = (model.differences_host(F, sid) - mean) @ V
+    assert np.max(np.abs(coef - want)) <= 1e-4 * np.max(np.abs(want)) + 1e-7
     model.set_basis(mean, V, coef)
     idx = np.arange(smp.n)
     bufs = model.alloc(smp.n)
     rv, fb, _ = model.rv(smp, idx, bufs, threshold_kms=0.0)
     assert fb.all()
-    want = S.plain_rv(ctx, smp, star.mask)["rv_kms"]
+    want = S.plain_rv(stars, smp, mask)["rv_kms"]
     np.testing.assert_array_equal(rv, want)
     # and the full synthesis of each sample on its own gives the same RVs
-    one = np.concatenate([S.plain_rv(ctx, smp, star.mask, idx=[i])["rv_kms"] for i in (0, 9, 47)])
-    np.testing.assert_array_equal(one, want[[0, 9, 47]])
-    L.soap_destroy(ctx)
+    one = np.concatenate([S.plain_rv(stars, smp, mask, idx=[i])["rv_kms"] for i in (0, 9, smp.n - 1)])
+    np.testing.assert_array_equal(one, want[[0, 9, smp.n - 1]])
+    if multi:
+        # each sample against the oracle on its own star
+        i = 17
+        k = i // smp.n_per
+        t, inc, vs = smp.star_params(smp.star[k])
+        st = W.cfg5_star(t, inc, vs, W.cfg5_window_spectra(t), n_grid=64)
+        reg = [W.Region(W.SPOT, smp.lat_deg[k], smp.lon_deg[k], smp.radius[k], smp.contrast[k])]
+        f = OS_spec.integrated(st, smp.phases.reshape(-1)[i], OS_spec.TOT, regions=reg)
+        e = np.max(np.abs(F[i].cpu().numpy() - f) / np.abs(f))
+        _say(f"multi-star sample {i} vs oracle {e:.2e}")
+        assert e <= 1e-6
 
 
 def test_fused_surrogate_rv_matches_linear_fit_and_oracle_spread():

@@ -27,6 +27,14 @@ from .stars import (  # noqa: F401
     make_cfg1,
     make_cfg2,
     make_cfg5,
+    cfg5_window_spectra,
+    cfg5_mask,
+    cfg5_star,
+    cfg5_multi_samples,
+    MultiSpotSamples,
+    CFG5_TEFF,
+    CFG5_INCL,
+    CFG5_VSINI,
     make_bank,
     batch_configs,
     cfg5_samples,

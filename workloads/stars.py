@@ -543,3 +543,105 @@ def batch_configs(n_cfg: int, seed: int = 3, n_pix_total: int = 205800):
             )
         )
     return out
+
+
+# Star grid of the multi-star surrogate data set: T_eff on a 41-point grid
+# (50 K steps, so local spectra are shared), inclination and v sin i on
+# coarse grids (one context per star).
+CFG5_TEFF = np.arange(4500.0, 6500.0 + 1.0, 50.0)
+CFG5_INCL = np.arange(30.0, 90.0 + 1.0, 10.0)
+CFG5_VSINI = np.arange(1.0, 5.0 + 1.0, 1.0)
+
+
+def _cfg5_lines(seed: int = 5):
+    """Master line list of the 20000-pixel window: lines are taken in list
+    order up to the count for a given T_eff, so cooler stars keep every line
+    of hotter ones and add more."""
+    rng = np.random.default_rng([seed, 55])
+    dln = 1.0 / (3.0 * 115000.0)
+    ln0 = np.log(5000.0)
+    n_pix = 20000
+    lam_hi = float(np.exp(ln0 + dln * (n_pix - 1)))
+    n_sun = (lam_hi - 5000.0) * 30000 / 3100.0
+    n_max = int(round(n_sun * (5778.0 / 4500.0) ** 3))
+    centre = rng.uniform(5002.0, lam_hi - 2.0, n_max)
+    u = rng.uniform(0.0, 1.0, n_max)
+    sigma = centre * rng.uniform(1.5, 3.0, n_max) / C_KMS
+    return ln0, dln, n_pix, n_sun, centre, u, sigma
+
+
+def _render_row(args):
+    return _render(*args)
+
+
+def cfg5_window_spectra(teff_k: float, seed: int = 5, n_mu: int = 10, pool=None):
+    """Quiet (n_mu rows) and spot (one row, every bin) local spectra of the
+    surrogate window for T_eff: 30k (5778/T)^3-per-full-range line density,
+    depths (0.05 + 0.85 u^2) (5778/T)^1.5 capped at 0.95, blueshift from the
+    cubic in T_eff; spot lines 30% deeper, no blueshift.  Gaussian lines.
+    float32 arrays."""
+    ln0, dln, n_pix, n_sun, centre, u, sigma = _cfg5_lines(seed)
+    scale = 5778.0 / teff_k
+    n = int(round(n_sun * scale**3))
+    c, s = centre[:n], sigma[:n]
+    depth = np.minimum((0.05 + 0.85 * u[:n] ** 2) * scale**1.5, 0.95)
+    g = np.zeros(n)
+    mu_b = 1.0 - 0.9 * np.arange(n_mu) / (n_mu - 1)
+    cb = cb_law_ms(mu_b, amplitude_ms=float(cb_velocity_ms(teff_k)))
+    jobs = [(ln0, dln, n_pix, c, depth, s, g, v) for v in cb]
+    jobs.append((ln0, dln, n_pix, c, np.minimum(depth * 1.3, 0.99), s, g, 0.0))
+    rows = list(pool.map(_render_row, jobs)) if pool is not None else [_render_row(j) for j in jobs]
+    quiet = np.stack(rows[:n_mu]).astype(np.float32)
+    spot = np.ascontiguousarray(np.broadcast_to(rows[n_mu], (n_mu, n_pix)), dtype=np.float32)
+    return ln0, dln, mu_b, quiet, spot
+
+
+def cfg5_mask(seed: int = 5):
+    """CCF mask of the surrogate window: the deepest lines of the solar-T_eff
+    list (up to 400), binary weights, 161 velocities from -20 km/s."""
+    ln0, dln, n_pix, n_sun, centre, u, sigma = _cfg5_lines(seed)
+    n = int(round(n_sun))
+    mlam, _ = _select_mask_lines(centre[:n], 0.05 + 0.85 * u[:n] ** 2, sigma[:n], 400)
+    return Mask(np.log(mlam), np.ones(len(mlam)), 0.41, -20.0, 0.25, 161)
+
+
+def cfg5_star(teff_k, incl_deg, vsini_kms, spectra, n_grid: int = 300) -> StarInputs:
+    """StarInputs of one grid star from cfg5_window_spectra's output."""
+    ln0, dln, mu_b, quiet, spot = spectra
+    return StarInputs(
+        n_grid=n_grid, vsini_kms=float(vsini_kms), incl_deg=float(incl_deg), ld_u1=0.4, ld_u2=0.25,
+        ln_lambda0=ln0, dln_lambda=dln, n_pix=quiet.shape[1], mu_bins=mu_b, spectra=[quiet, spot, None],
+        precision=PREC_FP32, contrast_mode=CONTRAST_SCALAR, teff_k=float(teff_k), regions=[],
+        phases=np.zeros(0), mask=None,
+        name=f"cfg5 star T={teff_k:.0f} i={incl_deg:.0f} vsini={vsini_kms:.0f}",
+    )
+
+
+@dataclass
+class MultiSpotSamples(SpotSamples):
+    """SpotSamples whose spots each belong to a star of the grid: star[k]
+    indexes (teff, incl, vsini) = (CFG5_TEFF[ti], CFG5_INCL[ii],
+    CFG5_VSINI[vi]) with star = (ti * len(CFG5_INCL) + ii) * len(CFG5_VSINI) + vi."""
+
+    star: np.ndarray = None
+
+    def star_params(self, star):
+        nv, ni = len(CFG5_VSINI), len(CFG5_INCL)
+        star = np.asarray(star)
+        return CFG5_TEFF[star // (ni * nv)], CFG5_INCL[(star // nv) % ni], CFG5_VSINI[star % nv]
+
+
+def cfg5_multi_samples(n_spots: int, n_per: int = 8, seed: int = 5, teff_subset=None) -> MultiSpotSamples:
+    """Single-spot samples as cfg5_samples, each spot on a star drawn
+    uniformly from the grid (optionally only the T_eff values in
+    teff_subset); spots are ordered by star."""
+    base = cfg5_samples(n_spots, n_per, seed)
+    rng = np.random.default_rng([seed, n_spots, n_per, 77])
+    tis = np.arange(len(CFG5_TEFF)) if teff_subset is None else np.searchsorted(CFG5_TEFF, teff_subset)
+    ti = tis[rng.integers(0, len(tis), n_spots)]
+    ii = rng.integers(0, len(CFG5_INCL), n_spots)
+    vi = rng.integers(0, len(CFG5_VSINI), n_spots)
+    star = (ti * len(CFG5_INCL) + ii) * len(CFG5_VSINI) + vi
+    o = np.argsort(star, kind="stable")  # spots grouped by star
+    return MultiSpotSamples(base.lat_deg[o], base.lon_deg[o], base.radius[o], base.contrast[o], base.phases[o],
+                            star=star[o])
