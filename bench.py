@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "disk-integrated spectra/s (206k px, 300² grid) + % HBM roofline; surrogate×"
 HBM_PEAK_GBS = 8000.0
+# FP32 FMA without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP x 2.4 GHz
+FP32_VALU_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def _oracle_phase(args):
@@ -352,6 +354,11 @@ def main():
     apply_bytes = n_arrays * P * 4 + P * 8 + n_ph * P * 4
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
 
+    # the same launch seen as arithmetic: useful FP32 FMAs (non-zero taps and
+    # difference formations, per pixel) and those the kernel issues
+    alu_useful = 2.0 * P * (prof["taps_nonzero"] + prof["taps_offsets"])
+    alu_issued = 2.0 * P * prof["fma_issued"]
+
     # HBM bytes per launch from the committed counter summary, valid only
     # while the kernel's sources are the ones the counters were taken on
     tr = prof_summary.read_traffic(os.path.join(ROOT, "profiles", "k_apply_full_visible_r115000_traffic.txt"))
@@ -409,6 +416,13 @@ def main():
             "kernel_ms": apply_ms,
             "algorithmic_bytes": apply_bytes,
             "touched_arrays": n_arrays,
+            "alu_view": {
+                "useful_tflop_s": alu_useful / (apply_ms * 1e-3) / 1e12,
+                "issued_tflop_s": alu_issued / (apply_ms * 1e-3) / 1e12,
+                "peak_fp32_nonpacked_tflop_s": FP32_VALU_NONPACKED_TFLOPS,
+                "useful_flop": alu_useful,
+                "issued_flop": alu_issued,
+            },
         },
         "stages_ms": {
             k: prof[k] / max(1, prof["active_calls"] if k in ("weights_ms", "compact_ms", "apply_ms") else prof["ccf_calls"])

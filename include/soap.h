@@ -305,6 +305,14 @@ typedef struct {
   int64_t src_arrays;        /* last apply: distinct local spectra read     */
   int64_t con_arrays;        /* last apply: distinct contrast arrays read   */
   int64_t last_phases;       /* last apply: number of phases                */
+  /* last apply's arithmetic per output pixel, summed over its phases and
+   * windows: non-zero taps (one FMA each per pixel), window offsets with any
+   * non-zero tap (one FMA each to form the difference), and the FMAs the
+   * kernel issues (4 per (offset, four-phase group) with a non-zero tap,
+   * plus 8 difference FMAs per window)                                     */
+  int64_t taps_nonzero;
+  int64_t taps_offsets;
+  int64_t fma_issued;
 } soap_profile;
 
 soap_status soap_profile_enable(soap_ctx* ctx, int32_t on);

@@ -150,6 +150,9 @@ class ProfileC(C.Structure):
         ("src_arrays", C.c_int64),
         ("con_arrays", C.c_int64),
         ("last_phases", C.c_int64),
+        ("taps_nonzero", C.c_int64),
+        ("taps_offsets", C.c_int64),
+        ("fma_issued", C.c_int64),
     ]
 
 

@@ -768,6 +768,7 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
   out->active_calls = c->active_calls;
   out->ccf_calls = c->ccf_calls;
   out->src_arrays = out->con_arrays = 0;
+  out->taps_nonzero = out->taps_offsets = out->fma_issued = 0;
   out->last_phases = c->last_phases;
   if (c->last_phases > 0) {
     // distinct inputs the last apply walked, from its virtual-group lists
@@ -782,7 +783,33 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
     for (int ch = 0; ch < n_chunks; ++ch)
       for (int v = 0; v < nvg[ch]; ++v) {
         soap::WinHead h;
-        std::memcpy(&h, vg.data() + ((size_t)ch * c->last_vg_cap + v) * soap::WIN_BYTES, sizeof(h));
+        const unsigned char* rec = vg.data() + ((size_t)ch * c->last_vg_cap + v) * soap::WIN_BYTES;
+        std::memcpy(&h, rec, sizeof(h));
+        {
+          // taps[q][p] after the header, float or double per the precision
+          // one mask bit per (offset, four-phase group) with a non-zero tap
+          int pairs = 0;
+          for (unsigned m = h.gmask; m; m &= m - 1) ++pairs;
+          out->fma_issued += (int64_t)pairs * 4 + soap::APPLY_JW;
+          for (int q = 0; q < soap::APPLY_JW; ++q) {
+            bool any = false;
+            for (int pp = 0; pp < c->pc; ++pp) {
+              double tap;
+              if (c->prec == SOAP_PREC_FP32) {
+                float f;
+                std::memcpy(&f, rec + 16 + sizeof(float) * ((size_t)q * c->pc + pp), sizeof f);
+                tap = f;
+              } else {
+                std::memcpy(&tap, rec + 16 + sizeof(double) * ((size_t)q * c->pc + pp), sizeof tap);
+              }
+              if (tap != 0.0) {
+                ++out->taps_nonzero;
+                any = true;
+              }
+            }
+            if (any) ++out->taps_offsets;
+          }
+        }
         const int t = h.t, b = h.b;
         if (t == 0) {
           src[b] = 1;
