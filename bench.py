@@ -190,6 +190,7 @@ def surrogate_leg(args, L, W, np, torch):
     say(f"{len(used)} star contexts in {time.perf_counter() - t0:.1f} s")
     mask = W.cfg5_mask()
     model, info = S.build(stars, mask, train, held, n_components=args.surrogate_components,
+                          hidden=args.surrogate_hidden,
                           epochs=args.surrogate_epochs, svd_subset=args.surrogate_svd_subset, alpha=args.surrogate_alpha,
                           weighting=args.surrogate_weighting, log=say)
     nt = (test.n // 16) * 16
@@ -215,7 +216,8 @@ def surrogate_leg(args, L, W, np, torch):
     res = {
         "workload": "20000 px window at 5000 A (R=115000), 300x300 disk, 10 mu bins; stars on a grid of T_eff "
         "4500-6500 K (50 K), i 30-90 deg (10 deg), v sin i 1-5 km/s; one spot per sample (lat, lon, radius "
-        f"0.01-0.10, contrast 0.3-0.9, phase); MLP 12-256-256-{model.k} x 4 members, {model.k} PCA components",
+        f"0.01-0.10, contrast 0.3-0.9, phase); MLP 12-{model.hidden}-{model.hidden}-{model.k} x 4 members, "
+        f"{model.k} PCA components",
         "stars": len(used),
         "train_samples": train.n,
         "test_samples": nt,
@@ -247,6 +249,7 @@ def main():
                     help="training spots of the surrogate leg (8 phases each; 0 = skip the leg)")
     ap.add_argument("--surrogate-epochs", type=int, default=100)
     ap.add_argument("--surrogate-components", type=int, default=128, help="PCA components (multiple of 32)")
+    ap.add_argument("--surrogate-hidden", type=int, default=256, help="hidden width (multiple of 32)")
     ap.add_argument("--surrogate-svd-subset", type=int, default=4096)
     ap.add_argument("--batch-configs", type=int, default=512,
                     help="configurations of the batched-graph leg (0 = skip the leg)")
