@@ -30,6 +30,9 @@
 // one tile on one XCD so their shared input windows hit the same L2, and
 // starts the chunks with the most windows first.  The final combine adds Q
 // in double.
+#include <algorithm>
+#include <vector>
+
 #include "soap_internal.hpp"
 
 namespace soap {
@@ -198,43 +201,10 @@ __device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, u
 
 }  // namespace
 
+// One (tile, chunk) item: the chunk's windows over the tile's pixels, then
+// the final combine with Q.  s_win is the block's LDS window staging.
 template <typename T, int R, int PC, int JW, bool PAIRED, int THREADS>
-__global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(ApplyArgs<T> A) {
-  static_assert(R == 4 && JW == 8, "window loads are written for 4 pixels x 8 offsets");
-  static_assert(PC % 4 == 0 && JW * PC * sizeof(T) == WIN_TAP_BYTES, "record layout");
-  extern __shared__ __align__(16) unsigned char s_win[];  // [lds_win][WIN_BYTES]
-  __shared__ int s_order[APPLY_RANKED];
-  // Blocks are dealt to the 8 XCDs in turn (blockIdx mod 8).  Each XCD owns
-  // a contiguous range of tiles, so the chunks of a tile share its L2, and
-  // walks its (chunk, tile) items heaviest chunk first (most windows), so
-  // that the long blocks start early and the short ones fill the end.
-  const int bid = blockIdx.x;
-  const int xcd = bid & 7;
-  const int seq = bid >> 3;
-  const int tpx = (A.n_tiles + 7) / 8;
-  const int t0 = xcd * tpx;
-  const int nt = min(A.n_tiles, t0 + tpx) - t0;
-  if (nt <= 0 || seq >= nt * A.n_chunks) return;
-  const int rank = seq / nt;
-  const int tile = t0 + (seq - rank * nt);
-  int chunk = rank;
-  if (A.n_chunks <= APPLY_RANKED) {
-    // rank of each chunk by window count (ties in chunk order)
-    const int c = threadIdx.x;
-    const int wc = c < A.n_chunks ? A.nvg[c] : 0;
-    if (c < A.n_chunks) s_order[c] = wc;  // window counts, then the order
-    __syncthreads();
-    int r = 0;
-    if (c < A.n_chunks)
-      for (int d = 0; d < A.n_chunks; ++d) {
-        const int wd = s_order[d];
-        r += (wd > wc || (wd == wc && d < c)) ? 1 : 0;
-      }
-    __syncthreads();
-    if (c < A.n_chunks) s_order[r] = c;
-    __syncthreads();
-    chunk = s_order[rank];
-  }
+__device__ __forceinline__ void apply_item(const ApplyArgs<T>& A, int tile, int chunk, unsigned char* s_win) {
   const int64_t m0 = (int64_t)tile * (R * THREADS) + (int64_t)threadIdx.x * R;
 
   T acc[PC][R];
@@ -307,6 +277,77 @@ __global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(Apply
   }
 }
 
+
+// Blocks are dealt to the 8 XCDs in turn (block index mod 8).  Each XCD
+// owns a contiguous range of tiles, so the chunks of a tile share its L2,
+// and walks its (chunk, tile) items heaviest chunk first (most windows), so
+// that the long blocks start early and the short ones fill the end.  seq8 is
+// the block's index within the configuration's 8 * ceil(n_tiles / 8) *
+// n_chunks slots; returns false for a slot with no item.
+template <typename T>
+__device__ __forceinline__ bool map_item(const ApplyArgs<T>& A, int seq8, int* s_order, int* tile, int* chunk) {
+  const int xcd = seq8 & 7;
+  const int seq = seq8 >> 3;
+  const int tpx = (A.n_tiles + 7) / 8;
+  const int t0 = xcd * tpx;
+  const int nt = min(A.n_tiles, t0 + tpx) - t0;
+  if (nt <= 0 || seq >= nt * A.n_chunks) return false;
+  const int rank = seq / nt;
+  *tile = t0 + (seq - rank * nt);
+  *chunk = rank;
+  if (A.n_chunks <= APPLY_RANKED) {
+    // rank of each chunk by window count (ties in chunk order)
+    const int c = threadIdx.x;
+    const int wc = c < A.n_chunks ? A.nvg[c] : 0;
+    if (c < A.n_chunks) s_order[c] = wc;  // window counts, then the order
+    __syncthreads();
+    int r = 0;
+    if (c < A.n_chunks)
+      for (int d = 0; d < A.n_chunks; ++d) {
+        const int wd = s_order[d];
+        r += (wd > wc || (wd == wc && d < c)) ? 1 : 0;
+      }
+    __syncthreads();
+    if (c < A.n_chunks) s_order[r] = c;
+    __syncthreads();
+    *chunk = s_order[rank];
+  }
+  return true;
+}
+
+template <typename T, int R, int PC, int JW, bool PAIRED, int THREADS>
+__global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(ApplyArgs<T> A) {
+  static_assert(R == 4 && JW == 8, "window loads are written for 4 pixels x 8 offsets");
+  static_assert(PC % 4 == 0 && JW * PC * sizeof(T) == WIN_TAP_BYTES, "record layout");
+  extern __shared__ __align__(16) unsigned char s_win[];  // [lds_win][WIN_BYTES]
+  __shared__ int s_order[APPLY_RANKED];
+  int tile, chunk;
+  if (!map_item(A, blockIdx.x, s_order, &tile, &chunk)) return;
+  apply_item<T, R, PC, JW, PAIRED, THREADS>(A, tile, chunk, s_win);
+}
+
+// Batched form: one launch over the items of many configurations (each with
+// its own arguments).  Configuration i owns the slots item_off[i] ..
+// item_off[i+1] - 1, a multiple of 8 starting at a multiple of 8, mapped as
+// in k_apply.
+template <typename T, int R, int PC, int JW, bool PAIRED, int THREADS>
+__global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2)
+    k_apply_batch(const ApplyArgs<T>* __restrict__ args, const int* __restrict__ item_off, int n_cfg) {
+  extern __shared__ __align__(16) unsigned char s_win[];
+  __shared__ int s_order[APPLY_RANKED];
+  const int b = blockIdx.x;
+  int lo = 0, hi = n_cfg;  // last cfg with item_off[cfg] <= b
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (item_off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const ApplyArgs<T> A = args[lo];
+  int tile, chunk;
+  if (!map_item(A, b - item_off[lo], s_order, &tile, &chunk)) return;
+  apply_item<T, R, PC, JW, PAIRED, THREADS>(A, tile, chunk, s_win);
+}
+
 namespace {
 
 template <typename T, bool PAIRED, int PC>
@@ -362,6 +403,81 @@ hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, co
                       (double*)d_flux};
   return pl.paired ? launch_apply_t<double, true, PC_F64>(c, pl, A, threads, st)
                    : launch_apply_t<double, false, PC_F64>(c, pl, A, threads, st);
+}
+
+// ---- batched shift-and-sum over many configurations ------------------------
+
+namespace {
+
+template <typename T>
+ApplyArgs<T> make_args(const ApplyBatchCfg& q) {
+  soap_ctx* c = q.c;
+  const bool vec_ok =
+      (c->P % APPLY_R == 0) && (reinterpret_cast<uintptr_t>(q.flux) % (APPLY_R * c->esize) == 0);
+  ApplyArgs<T> A{c->P, c->Pstride, c->B, q.pl.n_ph, q.pl.n_chunks, (int)((c->P + APPLY_TILE - 1) / APPLY_TILE),
+                 q.pl.effect, q.pl.paired, q.pl.vg_cap, vec_ok ? 1 : 0,
+                 std::max(1, std::min(q.pl.vg_cap, APPLY_LDS_WIN)),
+                 (const T*)c->d_spec[0], (const T*)c->d_spec[1], (const T*)c->d_spec[2], (const T*)c->d_con_spot,
+                 (const T*)c->d_con_fac, (const T*)c->d_ones, c->d_Q, static_cast<const unsigned char*>(q.win), q.nvg,
+                 (T*)q.flux};
+  return A;
+}
+
+template <typename T>
+hipError_t upload_t(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGroup* g) {
+  std::vector<ApplyArgs<T>> args(n);
+  std::vector<int> off(n + 1, 0);
+  int lw = 1;
+  for (int i = 0; i < n; ++i) {
+    args[i] = make_args<T>(cfgs[i]);
+    off[i + 1] = off[i] + 8 * ((args[i].n_tiles + 7) / 8) * args[i].n_chunks;  // whole XCD rounds
+    lw = std::max(lw, args[i].lds_win);
+  }
+  g->n_cfg = n;
+  g->n_items = off[n];
+  g->lds_win = lw;
+  g->args = d_buf;
+  g->off = static_cast<unsigned char*>(d_buf) + 256 * ((sizeof(ApplyArgs<T>) * n + 255) / 256);
+  hipError_t e = hipMemcpy(g->args, args.data(), sizeof(ApplyArgs<T>) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(g->off, off.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+size_t apply_batch_bytes(int n) {
+  return 256 * ((sizeof(ApplyArgs<double>) * n + 255) / 256) + sizeof(int) * (n + 1) + 256;
+}
+
+hipError_t apply_batch_upload(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGroup* g) {
+  g->fp32 = cfgs[0].c->prec == SOAP_PREC_FP32;
+  g->paired = cfgs[0].pl.paired != 0;
+  return g->fp32 ? upload_t<float>(cfgs, n, d_buf, g) : upload_t<double>(cfgs, n, d_buf, g);
+}
+
+hipError_t apply_batch_launch(const ApplyBatchGroup& g, hipStream_t st) {
+  if (g.n_items <= 0) return hipSuccess;
+  const dim3 grid((unsigned)g.n_items), block(APPLY_THREADS);
+  const size_t lds = (size_t)g.lds_win * WIN_BYTES;
+  const int* off = static_cast<const int*>(g.off);
+  if (g.fp32) {
+    const auto* a = static_cast<const ApplyArgs<float>*>(g.args);
+    if (g.paired)
+      hipLaunchKernelGGL((k_apply_batch<float, APPLY_R, PC_F32, APPLY_JW, true, APPLY_THREADS>), grid, block, lds,
+                         st, a, off, g.n_cfg);
+    else
+      hipLaunchKernelGGL((k_apply_batch<float, APPLY_R, PC_F32, APPLY_JW, false, APPLY_THREADS>), grid, block, lds,
+                         st, a, off, g.n_cfg);
+  } else {
+    const auto* a = static_cast<const ApplyArgs<double>*>(g.args);
+    if (g.paired)
+      hipLaunchKernelGGL((k_apply_batch<double, APPLY_R, PC_F64, APPLY_JW, true, APPLY_THREADS>), grid, block, lds,
+                         st, a, off, g.n_cfg);
+    else
+      hipLaunchKernelGGL((k_apply_batch<double, APPLY_R, PC_F64, APPLY_JW, false, APPLY_THREADS>), grid, block,
+                         lds, st, a, off, g.n_cfg);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace soap

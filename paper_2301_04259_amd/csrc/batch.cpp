@@ -1,8 +1,10 @@
 // Batched synthesis of many activity configurations of many stars
-// (include/soap.h, soap_batch_*): every configuration's kernels (region
-// parameters, weights, tap lists, shift-and-sum) are captured once into one
-// HIP graph over a few parallel branches, so a run is a single graph launch
-// with no host work per configuration.
+// (include/soap.h, soap_batch_*): every configuration's table kernels (region
+// parameters, weights, tap lists) are captured once into one HIP graph over a
+// few parallel branches, followed by one shift-and-sum launch per precision
+// and table mode whose blocks walk the (configuration, tile, phase chunk)
+// work list of all configurations, so a run is a single graph launch with no
+// host work per configuration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -146,6 +148,17 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     q.off_nvg = take(sizeof(int) * (size_t)pl.n_chunks);
     n_spec += np;
   }
+  // the shift-and-sum runs as one launch per (precision, table mode) over
+  // every configuration's (tile, chunk) items
+  std::vector<std::vector<int>> groups(4);
+  for (int i = 0; i < n_cfg; ++i)
+    groups[(cp[i].c->prec == SOAP_PREC_FP32 ? 0 : 2) + (cp[i].pl.paired ? 0 : 1)].push_back(i);
+  std::vector<size_t> group_off(4, 0);
+  for (int g = 0; g < 4; ++g)
+    if (!groups[g].empty()) {
+      group_off[g] = arena;
+      arena += al(soap::apply_batch_bytes((int)groups[g].size()));
+    }
 
   soap_batch* b = new soap_batch;
   b->n_cfg = n_cfg;
@@ -179,6 +192,16 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
         return fail("hipMemcpy", e);
     }
   }
+  std::vector<soap::ApplyBatchGroup> ag(4);
+  for (int g = 0; g < 4; ++g) {
+    if (groups[g].empty()) continue;
+    std::vector<soap::ApplyBatchCfg> ac;
+    for (int i : groups[g])
+      ac.push_back(soap::ApplyBatchCfg{cp[i].c, cp[i].pl, A + cp[i].off_vg,
+                                       reinterpret_cast<const int*>(A + cp[i].off_nvg), cp[i].flux});
+    if ((e = soap::apply_batch_upload(ac.data(), (int)ac.size(), A + group_off[g], &ag[g])) != hipSuccess)
+      return fail("uploading the shift-and-sum work list", e);
+  }
   if ((e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
   for (int k = 0; k < kBranches; ++k) {
     if ((e = hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
@@ -210,13 +233,13 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     ce = soap::launch_weights(q.c, q.pl, reinterpret_cast<const soap::Region*>(A + q.off_reg), q.n_reg,
                               std::max(1, q.n_reg), reinterpret_cast<const double*>(A + q.off_ph), nullptr, wo, st);
     if (ce == hipSuccess) ce = soap::launch_finish(q.c, q.pl, wo, st);
-    if (ce == hipSuccess)
-      ce = soap::launch_apply_shape(q.c, q.pl, wo.wins, wo.nvg, q.flux, q.c->tune_threads, q.c->tune_lds_win, st);
   }
   for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
     ce = hipEventRecord(b->join[k], b->branch[k]);
     if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join[k], 0);
   }
+  for (int g = 0; g < 4 && ce == hipSuccess; ++g)
+    if (!groups[g].empty()) ce = soap::apply_batch_launch(ag[g], b->origin);
   e = hipStreamEndCapture(b->origin, &b->graph);
   if (ce != hipSuccess) return fail("capturing the batch", ce);
   if (e != hipSuccess) return fail("hipStreamEndCapture", e);

@@ -220,6 +220,25 @@ hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const in
 // pass) on stream st
 hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux,
                               int threads, int lds_win, hipStream_t st);
+
+// batched shift-and-sum: one launch over the (tile, chunk) items of many
+// configurations of one precision and table mode (256-thread blocks)
+struct ApplyBatchCfg {
+  soap_ctx* c;
+  Plan pl;
+  const void* win;
+  const int* nvg;
+  void* flux;
+};
+struct ApplyBatchGroup {
+  bool fp32 = true, paired = true;
+  int n_cfg = 0, n_items = 0, lds_win = 1;
+  void* args = nullptr;  // device ApplyArgs[n_cfg]
+  void* off = nullptr;   // device item offsets [n_cfg + 1]
+};
+size_t apply_batch_bytes(int n);
+hipError_t apply_batch_upload(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGroup* g);
+hipError_t apply_batch_launch(const ApplyBatchGroup& g, hipStream_t st);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
                       double* d_part);
