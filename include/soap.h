@@ -238,11 +238,17 @@ soap_status soap_surrogate_rv(soap_ctx* ctx, const float* coef, const float* mem
 /* Shape of the shift-and-sum kernel and its tuner.  A block of `threads`
  * threads (64, 128, 256 or 512) covers a tile of 4 x threads pixels for one
  * chunk of phases; `lds_win` (1 .. 48) window records are staged in LDS per
- * pass.  Every shape gives the same result bit for bit (each pixel adds its
- * windows in the same order); only the time differs.                        */
+ * pass.  With `staged`, the block first copies each window's source spans
+ * (the tile's samples plus 12, its quiet samples and contrast values) to LDS
+ * with coalesced loads, double-buffered, and threads read their windows
+ * from there.  Every shape gives the same result bit for bit (each pixel
+ * adds its windows in the same order); only the time differs.               */
 typedef struct {
   int32_t threads;
   int32_t lds_win;
+  int32_t staged;            /* 1: the block stages each window's source
+                                spans in LDS (256 threads only)             */
+  int32_t reserved0;
   double apply_us;           /* measured time of one launch of the choice   */
   int32_t from_cache;        /* 1: taken from the cache file, not timed     */
   int32_t n_tried;           /* shapes timed                                */
@@ -250,7 +256,7 @@ typedef struct {
 } soap_tune;
 
 /* Sets the shape used by later calls on ctx.                                 */
-soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t threads, int32_t lds_win);
+soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t threads, int32_t lds_win, int32_t staged);
 
 /* Runs soap_active_spectra once on the given workload (arguments as there),
  * then times every shape on its tap lists (10 launches each, HIP events on

@@ -207,6 +207,8 @@ class TuneC(C.Structure):
     _fields_ = [
         ("threads", C.c_int32),
         ("lds_win", C.c_int32),
+        ("staged", C.c_int32),
+        ("reserved0", C.c_int32),
         ("apply_us", C.c_double),
         ("from_cache", C.c_int32),
         ("n_tried", C.c_int32),
@@ -214,7 +216,7 @@ class TuneC(C.Structure):
     ]
 
 
-_lib.soap_set_apply_shape.argtypes = [_ctx_p, C.c_int32, C.c_int32]
+_lib.soap_set_apply_shape.argtypes = [_ctx_p, C.c_int32, C.c_int32, C.c_int32]
 _lib.soap_set_apply_shape.restype = C.c_int
 _lib.soap_autotune.argtypes = [_ctx_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_char_p,
                                C.POINTER(TuneC)]
@@ -633,8 +635,8 @@ def soap_surrogate_rv(ctx, coef, members, base, basis, calib, threshold_kms, rv_
     _check(st, ctx.handle)
 
 
-def soap_set_apply_shape(ctx, threads, lds_win):
-    _check(_lib.soap_set_apply_shape(ctx.handle, int(threads), int(lds_win)), ctx.handle)
+def soap_set_apply_shape(ctx, threads, lds_win, staged=False):
+    _check(_lib.soap_set_apply_shape(ctx.handle, int(threads), int(lds_win), 1 if staged else 0), ctx.handle)
 
 
 def soap_autotune(ctx, regions, phases, effect, cache_path=None):
@@ -645,7 +647,8 @@ def soap_autotune(ctx, regions, phases, effect, cache_path=None):
     st = _lib.soap_autotune(ctx.handle, C.cast(regs, C.c_void_p), len(regions), ph.ctypes.data, len(ph), int(effect),
                             None if cache_path is None else os.fsencode(cache_path), C.byref(t))
     _check(st, ctx.handle)
-    return {"threads": t.threads, "lds_win": t.lds_win, "apply_us": t.apply_us, "from_cache": bool(t.from_cache),
+    return {"threads": t.threads, "lds_win": t.lds_win, "staged": bool(t.staged), "apply_us": t.apply_us,
+            "from_cache": bool(t.from_cache),
             "n_tried": t.n_tried, "key": t.key.decode()}
 
 

@@ -120,13 +120,15 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // stay in flight while the current window is consumed.  Without a contrast
 // the c operand comes from a resident row of ones; for the flux effect the
 // active operand is the quiet row itself, loaded a second time.
-template <typename T, int R, int JW, bool PAIRED>
-__device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int4 hr, int64_t m0) {
-  const int t = uni(hr.x), b = uni(hr.y), jlo = uni(hr.z);
+// rows a window reads: active (or quiet) source, quiet source, contrast
+template <typename T>
+__device__ __forceinline__ void window_rows(const ApplyArgs<T>& A, int4 hr, const T*& src, const T*& sq,
+                                            const T*& con, int& jlo) {
+  const int t = uni(hr.x), b = uni(hr.y);
+  jlo = uni(hr.z);
   const int64_t rs = A.Pstride;  // stride between mu-bin rows
-  const T* sq = A.Sq + (int64_t)b * rs;
-  const T* src;
-  const T* con = A.ones;
+  sq = A.Sq + (int64_t)b * rs;
+  con = A.ones;
   if (t == 0) {
     src = sq;
   } else {
@@ -140,6 +142,13 @@ __device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int
       if (A.effect == SOAP_EFFECT_TOT) con = ct;
     }
   }
+}
+
+template <typename T, int R, int JW, bool PAIRED>
+__device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int4 hr, int64_t m0) {
+  const T *src, *sq, *con;
+  int jlo;
+  window_rows(A, hr, src, sq, con, jlo);
   // window start m0 - jlo - (JW - 1)
   const int64_t at = m0 - jlo - (JW - 1);
   load12(o.a, src + at);
@@ -201,6 +210,37 @@ __device__ __forceinline__ void consume(T (&acc)[PC][R], const Operands<T>& o, u
 
 }  // namespace
 
+// final combine of one item: Q (double) plus the accumulated differences,
+// written with 16-byte stores where the row allows
+template <typename T, int R, int PC>
+__device__ __forceinline__ void store_item(const ApplyArgs<T>& A, const T (&acc)[PC][R], int chunk, int64_t m0) {
+  double Qr[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) Qr[r] = A.Q[m0 + r];  // Q is padded to whole tiles
+  const int p0 = chunk * PC;
+  const bool full = A.vec_ok && (m0 + R <= A.P);
+#pragma unroll
+  for (int p = 0; p < PC; ++p) {
+    if (p0 + p >= A.n_ph) break;
+    T* row = A.out + (int64_t)(p0 + p) * A.P;
+    T vals[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) vals[r] = (T)(Qr[r] + (double)acc[p][r]);
+    if (full) {
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(row + m0) = make_float4(vals[0], vals[1], vals[2], vals[3]);
+      } else {
+        reinterpret_cast<double2*>(row + m0)[0] = make_double2(vals[0], vals[1]);
+        reinterpret_cast<double2*>(row + m0)[1] = make_double2(vals[2], vals[3]);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (m0 + r < A.P) row[m0 + r] = vals[r];
+    }
+  }
+}
+
 // One (tile, chunk) item: the chunk's windows over the tile's pixels, then
 // the final combine with Q.  s_win is the block's LDS window staging.
 template <typename T, int R, int PC, int JW, bool PAIRED, int THREADS>
@@ -250,33 +290,155 @@ __device__ __forceinline__ void apply_item(const ApplyArgs<T>& A, int tile, int 
     }
   }
 
-  double Qr[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) Qr[r] = A.Q[m0 + r];  // Q is padded to whole tiles
-  const int p0 = chunk * PC;
-  const bool full = A.vec_ok && (m0 + R <= A.P);
-#pragma unroll
-  for (int p = 0; p < PC; ++p) {
-    if (p0 + p >= A.n_ph) break;
-    T* row = A.out + (int64_t)(p0 + p) * A.P;
-    T vals[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) vals[r] = (T)(Qr[r] + (double)acc[p][r]);
-    if (full) {
-      if constexpr (sizeof(T) == 4) {
-        *reinterpret_cast<float4*>(row + m0) = make_float4(vals[0], vals[1], vals[2], vals[3]);
-      } else {
-        reinterpret_cast<double2*>(row + m0)[0] = make_double2(vals[0], vals[1]);
-        reinterpret_cast<double2*>(row + m0)[1] = make_double2(vals[2], vals[3]);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (m0 + r < A.P) row[m0 + r] = vals[r];
-    }
+  store_item<T, R, PC>(A, acc, chunk, m0);
+}
+
+// ---- staged variant --------------------------------------------------------
+// The block stages each window's source spans in LDS once (coalesced 16-byte
+// loads of the tile's 1024 + 12 source samples, quiet samples and 1024
+// contrast values), double-buffered: the next window's spans are loaded into
+// registers while the current window is consumed from LDS, then written to
+// the other buffer.  Threads read their 12-sample windows from LDS instead
+// of loading overlapping windows from memory.  Tile of APPLY_TILE pixels
+// (256 threads).
+constexpr int STG_SPAN = APPLY_TILE + 16;  // 1024 + 12 samples, 16-byte rows
+
+template <typename T>
+__device__ __forceinline__ void load4e(T (&x)[4], const T* p) {
+  if constexpr (sizeof(T) == 4) {
+    const f4e f = *reinterpret_cast<const f4e*>(p);
+    x[0] = f.x;
+    x[1] = f.y;
+    x[2] = f.z;
+    x[3] = f.w;
+  } else {
+    const d2e u = *reinterpret_cast<const d2e*>(p);
+    const d2e w = *reinterpret_cast<const d2e*>(p + 2);
+    x[0] = u.x;
+    x[1] = u.y;
+    x[2] = w.x;
+    x[3] = w.y;
   }
 }
 
+// 4 consecutive elements to / from 16-byte-aligned LDS
+template <typename T>
+__device__ __forceinline__ void lds_put4(T* p, const T* x) {
+  if constexpr (sizeof(T) == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(x[0], x[1], x[2], x[3]);
+  } else {
+    reinterpret_cast<double2*>(p)[0] = make_double2(x[0], x[1]);
+    reinterpret_cast<double2*>(p)[1] = make_double2(x[2], x[3]);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_get4(T* x, const T* p) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    x[0] = f.x;
+    x[1] = f.y;
+    x[2] = f.z;
+    x[3] = f.w;
+  } else {
+    const double2 u = reinterpret_cast<const double2*>(p)[0];
+    const double2 w = reinterpret_cast<const double2*>(p)[1];
+    x[0] = u.x;
+    x[1] = u.y;
+    x[2] = w.x;
+    x[3] = w.y;
+  }
+}
+
+// one thread's share of a window's spans: a[0..3] (and a[4..7], the 12
+// samples past the tile, for threads 0..2), the same for the quiet row b,
+// and 4 contrast values
+template <typename T>
+struct Stage {
+  T a[8], b[8], c[4];
+};
+
+template <typename T, int JW, bool PAIRED>
+__device__ __forceinline__ void stage_load(Stage<T>& g, const ApplyArgs<T>& A, int4 hr, int64_t mt) {
+  const T *src, *sq, *con;
+  int jlo;
+  window_rows(A, hr, src, sq, con, jlo);
+  const int64_t at = mt - jlo - (JW - 1);
+  const int i = 4 * threadIdx.x;
+  load4e(*reinterpret_cast<T(*)[4]>(&g.a[0]), src + at + i);
+  if (PAIRED) load4e(*reinterpret_cast<T(*)[4]>(&g.b[0]), sq + at + i);
+  if (threadIdx.x < 3) {
+    load4e(*reinterpret_cast<T(*)[4]>(&g.a[4]), src + at + APPLY_TILE + i);
+    if (PAIRED) load4e(*reinterpret_cast<T(*)[4]>(&g.b[4]), sq + at + APPLY_TILE + i);
+  }
+  load4e(g.c, con + mt + i);
+}
+
+template <typename T, bool PAIRED>
+__device__ __forceinline__ void stage_store(T* buf, const Stage<T>& g) {
+  const int i = 4 * threadIdx.x;
+  lds_put4(buf + i, &g.a[0]);
+  if (PAIRED) lds_put4(buf + STG_SPAN + i, &g.b[0]);
+  if (threadIdx.x < 3) {
+    lds_put4(buf + APPLY_TILE + i, &g.a[4]);
+    if (PAIRED) lds_put4(buf + STG_SPAN + APPLY_TILE + i, &g.b[4]);
+  }
+  lds_put4(buf + 2 * STG_SPAN + i, &g.c[0]);
+}
+
+template <typename T, bool PAIRED>
+__device__ __forceinline__ void stage_read(Operands<T>& o, const T* buf) {
+  const int i = 4 * threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lds_get4(&o.a.v[4 * k], buf + i + 4 * k);
+    if (PAIRED) lds_get4(&o.b.v[4 * k], buf + STG_SPAN + i + 4 * k);
+  }
+  lds_get4(&o.c[0], buf + 2 * STG_SPAN + i);
+}
+
+template <typename T, int R, int PC, int JW, bool PAIRED>
+__device__ __forceinline__ void apply_item_staged(const ApplyArgs<T>& A, int tile, int chunk, unsigned char* s_win) {
+  const int64_t mt = (int64_t)tile * APPLY_TILE;
+  const int64_t m0 = mt + (int64_t)threadIdx.x * R;
+  T* stg = reinterpret_cast<T*>(s_win + (size_t)A.lds_win * WIN_BYTES);
+  constexpr int BUF = 2 * STG_SPAN + APPLY_TILE;
+
+  T acc[PC][R];
+#pragma unroll
+  for (int p = 0; p < PC; ++p)
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[p][r] = T(0);
+
+  const int nv = A.nvg[chunk];
+  const unsigned char* gw = A.wins + (int64_t)chunk * A.vg_cap * WIN_BYTES;
+  for (int vb = 0; vb < nv; vb += A.lds_win) {
+    const int nb = min(A.lds_win, nv - vb);
+    if (vb) __syncthreads();  // every wave is done with the previous pass
+    {
+      const int4* src = reinterpret_cast<const int4*>(gw + (int64_t)vb * WIN_BYTES);
+      int4* dst = reinterpret_cast<int4*>(s_win);
+      const int n16 = nb * (WIN_BYTES / 16);
+      for (int u = threadIdx.x; u < n16; u += APPLY_THREADS) dst[u] = src[u];
+    }
+    __syncthreads();
+    Stage<T> g;
+    stage_load<T, JW, PAIRED>(g, A, head_raw(s_win, 0), mt);
+    stage_store<T, PAIRED>(stg, g);
+    __syncthreads();
+    for (int v = 0; v < nb; ++v) {
+      const bool more = v + 1 < nb;  // uniform
+      if (more) stage_load<T, JW, PAIRED>(g, A, head_raw(s_win, v + 1), mt);
+      Operands<T> o;
+      stage_read<T, PAIRED>(o, stg + (v & 1) * BUF);
+      consume<T, R, PC, JW, PAIRED>(acc, o, (unsigned)uni(head_raw(s_win, v).w),
+                                    reinterpret_cast<const T*>(s_win + v * WIN_BYTES + 16));
+      if (more) stage_store<T, PAIRED>(stg + ((v + 1) & 1) * BUF, g);
+      __syncthreads();
+    }
+  }
+  store_item<T, R, PC>(A, acc, chunk, m0);
+}
 
 // Blocks are dealt to the 8 XCDs in turn (block index mod 8).  Each XCD
 // owns a contiguous range of tiles, so the chunks of a tile share its L2,
@@ -315,7 +477,7 @@ __device__ __forceinline__ bool map_item(const ApplyArgs<T>& A, int seq8, int* s
   return true;
 }
 
-template <typename T, int R, int PC, int JW, bool PAIRED, int THREADS>
+template <typename T, int R, int PC, int JW, bool PAIRED, int THREADS, bool STAGED>
 __global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(ApplyArgs<T> A) {
   static_assert(R == 4 && JW == 8, "window loads are written for 4 pixels x 8 offsets");
   static_assert(PC % 4 == 0 && JW * PC * sizeof(T) == WIN_TAP_BYTES, "record layout");
@@ -323,7 +485,10 @@ __global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) k_apply(Apply
   __shared__ int s_order[APPLY_RANKED];
   int tile, chunk;
   if (!map_item(A, blockIdx.x, s_order, &tile, &chunk)) return;
-  apply_item<T, R, PC, JW, PAIRED, THREADS>(A, tile, chunk, s_win);
+  if constexpr (STAGED)
+    apply_item_staged<T, R, PC, JW, PAIRED>(A, tile, chunk, s_win);
+  else
+    apply_item<T, R, PC, JW, PAIRED, THREADS>(A, tile, chunk, s_win);
 }
 
 // Batched form: one launch over the items of many configurations (each with
@@ -351,25 +516,35 @@ __global__ void __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2)
 namespace {
 
 template <typename T, bool PAIRED, int PC>
-hipError_t launch_apply_t(soap_ctx* c, const Plan& pl, const ApplyArgs<T>& A0, int threads, hipStream_t st) {
+hipError_t launch_apply_t(soap_ctx* c, const Plan& pl, const ApplyArgs<T>& A0, int threads, bool staged,
+                          hipStream_t st) {
   ApplyArgs<T> A = A0;
+  if (staged) threads = APPLY_THREADS;
   const int tile = APPLY_R * threads;
   A.n_tiles = (int)((c->P + tile - 1) / tile);
   const int tpx = (A.n_tiles + 7) / 8;
   const dim3 grid(8 * tpx * pl.n_chunks);
+  if (staged) {
+    // the staging buffers take their share of at most 60 KB per block
+    const size_t stg = 2 * (2 * (size_t)STG_SPAN + APPLY_TILE) * sizeof(T);
+    A.lds_win = std::max(1, std::min<int>(A.lds_win, (int)((60 * 1024 - stg) / WIN_BYTES)));
+    const size_t lds = (size_t)A.lds_win * WIN_BYTES + stg;
+    hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 256, true>), grid, dim3(256), lds, st, A);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)A.lds_win * WIN_BYTES;
   switch (threads) {
     case 64:
-      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 64>), grid, dim3(64), lds, st, A);
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 64, false>), grid, dim3(64), lds, st, A);
       break;
     case 128:
-      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 128>), grid, dim3(128), lds, st, A);
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 128, false>), grid, dim3(128), lds, st, A);
       break;
     case 512:
-      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 512>), grid, dim3(512), lds, st, A);
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 512, false>), grid, dim3(512), lds, st, A);
       break;
     default:
-      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 256>), grid, dim3(256), lds, st, A);
+      hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 256, false>), grid, dim3(256), lds, st, A);
       break;
   }
   return hipGetLastError();
@@ -378,11 +553,12 @@ hipError_t launch_apply_t(soap_ctx* c, const Plan& pl, const ApplyArgs<T>& A0, i
 }  // namespace
 
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux) {
-  return launch_apply_shape(c, pl, d_win, d_nvg, d_flux, c->tune_threads, c->tune_lds_win, c->stream);
+  return launch_apply_shape(c, pl, d_win, d_nvg, d_flux, c->tune_threads, c->tune_lds_win, c->tune_staged != 0,
+                            c->stream);
 }
 
 hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux,
-                              int threads, int lds_win, hipStream_t st) {
+                              int threads, int lds_win, bool staged, hipStream_t st) {
   const bool vec_ok = (c->P % APPLY_R == 0) &&
                       (reinterpret_cast<uintptr_t>(d_flux) % (APPLY_R * c->esize) == 0);
   lds_win = std::max(1, std::min(pl.vg_cap, lds_win));
@@ -393,16 +569,16 @@ hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, co
                        (const float*)c->d_spec[0], (const float*)c->d_spec[1], (const float*)c->d_spec[2],
                        (const float*)c->d_con_spot, (const float*)c->d_con_fac, (const float*)c->d_ones, c->d_Q, w, d_nvg,
                        (float*)d_flux};
-    return pl.paired ? launch_apply_t<float, true, PC_F32>(c, pl, A, threads, st)
-                     : launch_apply_t<float, false, PC_F32>(c, pl, A, threads, st);
+    return pl.paired ? launch_apply_t<float, true, PC_F32>(c, pl, A, threads, staged, st)
+                     : launch_apply_t<float, false, PC_F32>(c, pl, A, threads, staged, st);
   }
   ApplyArgs<double> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, 0, pl.effect, pl.paired,
                       pl.vg_cap, vec_ok ? 1 : 0, lds_win,
                       (const double*)c->d_spec[0], (const double*)c->d_spec[1], (const double*)c->d_spec[2],
                       (const double*)c->d_con_spot, (const double*)c->d_con_fac, (const double*)c->d_ones, c->d_Q, w, d_nvg,
                       (double*)d_flux};
-  return pl.paired ? launch_apply_t<double, true, PC_F64>(c, pl, A, threads, st)
-                   : launch_apply_t<double, false, PC_F64>(c, pl, A, threads, st);
+  return pl.paired ? launch_apply_t<double, true, PC_F64>(c, pl, A, threads, staged, st)
+                   : launch_apply_t<double, false, PC_F64>(c, pl, A, threads, staged, st);
 }
 
 // ---- batched shift-and-sum over many configurations ------------------------

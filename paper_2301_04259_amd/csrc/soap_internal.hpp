@@ -101,6 +101,7 @@ struct soap_ctx {
   int n_tiles = 0;  // tiles of APPLY_TILE_MAX pixels (padding)
   int tune_threads = soap::APPLY_THREADS;  // apply shape in use (the tuner's choice)
   int tune_lds_win = soap::APPLY_LDS_WIN;
+  int tune_staged = 0;  // 1: source spans staged in LDS (256-thread tiles)
   double vsini = 0, incl = 0, u1 = 0, u2 = 0, ln0 = 0, dln = 0;
   int prec = SOAP_PREC_FP64, cmode = SOAP_CONTRAST_SCALAR;
   double teff = 0, dt_spot = 0, dt_fac[3] = {0, 0, 0};
@@ -219,7 +220,7 @@ hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const in
 // apply with an explicit shape (threads per block, windows staged per LDS
 // pass) on stream st
 hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux,
-                              int threads, int lds_win, hipStream_t st);
+                              int threads, int lds_win, bool staged, hipStream_t st);
 
 // batched shift-and-sum: one launch over the (tile, chunk) items of many
 // configurations of one precision and table mode (256-thread blocks)
