@@ -226,14 +226,16 @@ soap_status soap_ccf_linear_rv(soap_ctx* ctx, const float* coef, int64_t n, int3
  *     converge (err_kms is then +inf), else 0.
  * coef[n][k], members[n_ens][n][k] float; base[n_v] double, or with
  * base_index (int32 [n], may be NULL) one base row per sample,
- * base[base_index[i]][n_v] (several stars sharing the basis); basis[k][n_v]
+ * base[base_index[i]][n_v] of n_base rows (several stars sharing the basis;
+ * a sample whose index is outside [0, n_base) gets status 2 and goes to the
+ * fallback); basis[k][n_v]
  * double; all on the context's mask grid (which must exist); outputs device
  * arrays (rv_out and err_kms may be NULL).  n 1 .. 1<<24, n_ens 2 .. 16.
  * Enqueues only.                                                             */
 soap_status soap_surrogate_rv(soap_ctx* ctx, const float* coef, const float* members, int64_t n, int32_t n_ens,
-                              int32_t k, const double* base, const int32_t* base_index, const double* basis,
-                              double calib, double threshold_kms, soap_rv* rv_out, double* rv_kms,
-                              double* err_kms, int32_t* fallback);
+                              int32_t k, const double* base, const int32_t* base_index, int32_t n_base,
+                              const double* basis, double calib, double threshold_kms, soap_rv* rv_out,
+                              double* rv_kms, double* err_kms, int32_t* fallback);
 
 /* Shape of the shift-and-sum kernel and its tuner.  A block of `threads`
  * threads (64, 128, 256 or 512) covers a tile of 4 x threads pixels for one
@@ -407,11 +409,13 @@ void soap_surrogate_destroy(soap_surrogate* s);
 /* Projection onto a PCA basis: coef[i][j] = sum_p (d[i][p] - m_i[p]) V[p][j]
  * for i < n, j < k, in FP32, with m_i = mean[0 .. n_pix), or, with
  * mean_index (int32 [n], may be NULL), row mean_index[i] of mean
- * [rows][n_pix] (a per-star centre).  d rows have stride ld >= n_pix
+ * [n_mean][n_pix] (a per-star centre; a row whose index is outside
+ * [0, n_mean) gets NaN coefficients).  d rows have stride ld >= n_pix
  * floats; all arrays are device memory.  n 1 .. 2^25, k 1 .. 4096.
  * Enqueues on hip_stream.                                                    */
 soap_status soap_pca_project(const float* d, int64_t n, int64_t n_pix, int64_t ld, const float* mean,
-                             const int32_t* mean_index, const float* V, int32_t k, float* coef, void* hip_stream);
+                             const int32_t* mean_index, int32_t n_mean, const float* V, int32_t k, float* coef,
+                             void* hip_stream);
 
 /* Ensemble gate.  rv[(1 + n_ens) n] (device) holds the fits of the
  * ensemble-mean prediction (rows 0 .. n-1) and then of member e (rows

@@ -200,8 +200,8 @@ _lib.soap_ccf_linear_rv.argtypes = [_ctx_p, C.c_void_p, C.c_int64, C.c_int32, C.
                                     C.c_void_p]
 _lib.soap_ccf_linear_rv.restype = C.c_int
 _lib.soap_surrogate_rv.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
-                                   C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_void_p, C.c_void_p,
-                                   C.c_void_p, C.c_void_p]
+                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.soap_surrogate_rv.restype = C.c_int
 class TuneC(C.Structure):
     _fields_ = [
@@ -256,8 +256,8 @@ _lib.soap_surrogate_last_error.argtypes = [_sg_p]
 _lib.soap_surrogate_last_error.restype = C.c_char_p
 _lib.soap_surrogate_destroy.argtypes = [_sg_p]
 _lib.soap_surrogate_destroy.restype = None
-_lib.soap_pca_project.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
-                                  C.c_int32, C.c_void_p, C.c_void_p]
+_lib.soap_pca_project.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                                  C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
 _lib.soap_pca_project.restype = C.c_int
 _lib.soap_surrogate_gate.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]
@@ -608,8 +608,9 @@ def soap_pca_project(d, mean, V, coef, n_pix=None, stream=None, mean_index=None)
     mean_index[i] of a [rows][n_pix] mean when mean_index is given)."""
     n, ld = int(d.shape[0]), int(d.shape[1])
     n_pix = ld if n_pix is None else int(n_pix)
+    n_mean = int(mean.shape[0]) if (mean_index is not None and mean.dim() == 2) else 1
     st = _lib.soap_pca_project(_dptr(d, "d"), n, n_pix, ld, _dptr(mean, "mean"), _dptr(mean_index, "mean_index"),
-                               _dptr(V, "V"), int(V.shape[1]), _dptr(coef, "coef"), _stream_handle(stream))
+                               n_mean, _dptr(V, "V"), int(V.shape[1]), _dptr(coef, "coef"), _stream_handle(stream))
     _sg_check(st, None)
     return coef
 
@@ -628,7 +629,8 @@ def soap_surrogate_rv(ctx, coef, members, base, basis, calib, threshold_kms, rv_
     n, k = int(coef.shape[0]), int(coef.shape[1])
     n_ens = int(members.shape[0]) if members.dim() == 3 else int(members.shape[0]) // n
     st = _lib.soap_surrogate_rv(ctx.handle, _dptr(coef, "coef"), _dptr(members, "members"), n, n_ens, k,
-                                _dptr(base, "base"), _dptr(base_index, "base_index"), _dptr(basis, "basis"),
+                                _dptr(base, "base"), _dptr(base_index, "base_index"),
+                                int(base.shape[0]) if base_index is not None else 1, _dptr(basis, "basis"),
                                 float(calib), float(threshold_kms),
                                 _dptr(rv_out, "rv_out"), _dptr(rv_kms, "rv_kms"), _dptr(err_kms, "err_kms"),
                                 _dptr(fallback, "fallback"))

@@ -565,15 +565,27 @@ constexpr int SG_MAX_ENS = 16;
 __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, double v0, double dv,
                                               const float* __restrict__ coef, const float* __restrict__ members,
                                               const double* __restrict__ base, const int* __restrict__ base_idx,
-                                              const double* __restrict__ basis, double calib, double thr,
-                                              soap_rv* __restrict__ out,
+                                              int n_base, const double* __restrict__ basis, double calib,
+                                              double thr, soap_rv* __restrict__ out,
                                               double* __restrict__ rv_kms, double* __restrict__ err_kms,
                                               int* __restrict__ fallback) {
   __shared__ double s_c[64];
   __shared__ double s_g[GF_MAXPT * 64];
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
-  const double* bs = base + (base_idx ? (int64_t)base_idx[i] * n_v : 0);
+  const int brow = base_idx ? base_idx[i] : 0;
+  if (brow < 0 || brow >= n_base) {  // no such star: no surrogate RV
+    if (lane == 0) {
+      soap_rv bad{};
+      bad.status = 2;
+      if (out) out[i] = bad;
+      rv_kms[i] = 0.0;
+      if (err_kms) err_kms[i] = INFINITY;
+      fallback[i] = 1;
+    }
+    return;
+  }
+  const double* bs = base + (int64_t)brow * n_v;
   double y[GF_MAXPT];
 #pragma unroll
   for (int t = 0; t < GF_MAXPT; ++t) {
@@ -672,11 +684,12 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
 }
 
 hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
-                        const double* d_base, const int* d_base_idx, const double* d_basis, double calib,
-                        double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err, int* d_fallback) {
+                        const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
+                        double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
+                        int* d_fallback) {
   hipLaunchKernelGGL(k_sg_rv, dim3((unsigned)n), dim3(64), 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,
-                     c->mask_dv, d_coef, d_members, d_base, d_base_idx, d_basis, calib, thr, d_rv, d_rv_kms, d_err,
-                     d_fallback);
+                     c->mask_dv, d_coef, d_members, d_base, d_base_idx, d_base_idx ? n_base : 1, d_basis, calib,
+                     thr, d_rv, d_rv_kms, d_err, d_fallback);
   return hipGetLastError();
 }
 

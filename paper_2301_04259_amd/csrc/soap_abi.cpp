@@ -713,8 +713,8 @@ SOAP_API soap_status soap_ccf_linear_rv(soap_ctx* c, const float* coef, int64_t 
 
 SOAP_API soap_status soap_surrogate_rv(soap_ctx* c, const float* coef, const float* members, int64_t n,
                                        int32_t n_ens, int32_t k, const double* base, const int32_t* base_index,
-                                       const double* basis, double calib, double threshold_kms, soap_rv* rv_out,
-                                       double* rv_kms, double* err_kms, int32_t* fallback) {
+                                       int32_t n_base, const double* basis, double calib, double threshold_kms,
+                                       soap_rv* rv_out, double* rv_kms, double* err_kms, int32_t* fallback) {
   if (!c) return SOAP_ERR_ARG;
   std::string& err = c->err;
   ARG_CHECK(coef && members && base && basis && rv_kms && fallback, "a required device array is NULL");
@@ -726,8 +726,9 @@ SOAP_API soap_status soap_surrogate_rv(soap_ctx* c, const float* coef, const flo
     setf(c->err, "no mask yet: call soap_ccf_rv with the mask first");
     return SOAP_ERR_STATE;
   }
-  HIP_TRY(soap::launch_sg_rv(c, coef, members, n, n_ens, k, base, base_index, basis, calib, threshold_kms, rv_out,
-                             rv_kms, err_kms, fallback));
+  ARG_CHECK(!base_index || n_base >= 1, "n_base must be >= 1 with base_index");
+  HIP_TRY(soap::launch_sg_rv(c, coef, members, n, n_ens, k, base, base_index, n_base, basis, calib, threshold_kms,
+                             rv_out, rv_kms, err_kms, fallback));
   return SOAP_OK;
 }
 

@@ -249,8 +249,9 @@ hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_
 hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, int k, const double* d_base,
                                  const double* d_basis, double* d_lin, double* d_ccf, soap_rv* d_rv);
 hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
-                        const double* d_base, const int* d_base_idx, const double* d_basis, double calib,
-                        double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err, int* d_fallback);
+                        const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
+                        double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
+                        int* d_fallback);
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask);
 
 int ccf_line_blocks(int n_lines);

@@ -232,7 +232,7 @@ __global__ void k_gate(int64_t n, int E, double calib, double thr, const soap_rv
 // 256 threads (4 x 4 outputs each), K in steps of 32 through LDS, FP32
 __global__ void __launch_bounds__(256) k_pca_project(int n, int P, int k, const float* __restrict__ D,
                                                      int64_t ldd, const float* __restrict__ mean,
-                                                     const int* __restrict__ mean_idx,
+                                                     const int* __restrict__ mean_idx, int n_mean,
                                                      const float* __restrict__ V, float* __restrict__ coef) {
   __shared__ float sA[32][64 + 1];
   __shared__ float sB[32][64 + 1];
@@ -243,8 +243,11 @@ __global__ void __launch_bounds__(256) k_pca_project(int n, int P, int k, const 
     for (int t = threadIdx.x; t < 32 * 64; t += 256) {
       const int pp = t & 31, rr = t >> 5;  // A: row rr, pixel pp (coalesced over pixels)
       const int row = r0 + rr, pix = p0 + pp;
-      const float* mrow = mean + (mean_idx && row < n ? (int64_t)mean_idx[row] * P : 0);
-      sA[pp][rr] = (row < n && pix < P) ? D[(int64_t)row * ldd + pix] - mrow[pix] : 0.f;
+      int mi = (mean_idx && row < n) ? mean_idx[row] : 0;
+      const bool bad = mi < 0 || mi >= n_mean;  // no such centre: the row's coefficients are NaN
+      mi = bad ? 0 : mi;
+      const float* mrow = mean + (int64_t)mi * P;
+      sA[pp][rr] = (row < n && pix < P) ? (bad ? __builtin_nanf("") : D[(int64_t)row * ldd + pix] - mrow[pix]) : 0.f;
       const int cc = t & 63, pq = t >> 6;  // B: pixel pq < 32, component cc
       const int pb = p0 + pq, col = c0 + cc;
       sB[pq][cc] = (pb < P && col < k) ? V[(int64_t)pb * k + col] : 0.f;
@@ -387,9 +390,10 @@ hipError_t sg_gate(hipStream_t st, const soap_rv* rv, int64_t n, int E, double c
 }
 
 hipError_t sg_pca_project(hipStream_t st, int n, int P, int k, const float* D, int64_t ldd, const float* mean,
-                          const int* mean_idx, const float* V, float* coef) {
+                          const int* mean_idx, int n_mean, const float* V, float* coef) {
   dim3 grid((n + 63) / 64, (k + 63) / 64);
-  hipLaunchKernelGGL(k_pca_project, grid, dim3(256), 0, st, n, P, k, D, ldd, mean, mean_idx, V, coef);
+  hipLaunchKernelGGL(k_pca_project, grid, dim3(256), 0, st, n, P, k, D, ldd, mean, mean_idx,
+                     mean_idx ? n_mean : 1, V, coef);
   return hipGetLastError();
 }
 

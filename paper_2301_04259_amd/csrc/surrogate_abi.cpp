@@ -335,15 +335,16 @@ SOAP_API void soap_surrogate_destroy(soap_surrogate* s) {
 }
 
 SOAP_API soap_status soap_pca_project(const float* d_dev, int64_t n, int64_t n_pix, int64_t ld, const float* mean_dev,
-                                      const int32_t* mean_index, const float* basis_dev, int32_t k, float* coef_dev,
-                                      void* hip_stream) {
+                                      const int32_t* mean_index, int32_t n_mean, const float* basis_dev, int32_t k,
+                                      float* coef_dev, void* hip_stream) {
   if (!d_dev || !mean_dev || !basis_dev || !coef_dev) return SOAP_ERR_ARG;
   if (n < 1 || n > (int64_t(1) << 31) / 64 || n_pix < 1 || n_pix > (int64_t(1) << 30) || ld < n_pix || k < 1 ||
       k > 4096)
     return SOAP_ERR_ARG;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (soap::sg_pca_project(st, (int)n, (int)n_pix, k, d_dev, ld, mean_dev, mean_index, basis_dev, coef_dev) !=
-      hipSuccess)
+  if (mean_index && n_mean < 1) return SOAP_ERR_ARG;
+  if (soap::sg_pca_project(st, (int)n, (int)n_pix, k, d_dev, ld, mean_dev, mean_index, n_mean, basis_dev,
+                           coef_dev) != hipSuccess)
     return SOAP_ERR_HIP;
   return SOAP_OK;
 }

@@ -60,5 +60,5 @@ hipError_t sg_ens_mean(soap_surrogate* s, int B, float* mean);
 hipError_t sg_gate(hipStream_t st, const soap_rv* rv, int64_t n, int E, double calib, double thr, double* rv_kms,
                    double* err_kms, int* fallback);
 hipError_t sg_pca_project(hipStream_t st, int n, int P, int k, const float* D, int64_t ldd, const float* mean,
-                          const int* mean_idx, const float* V, float* coef);
+                          const int* mean_idx, int n_mean, const float* V, float* coef);
 }  // namespace soap

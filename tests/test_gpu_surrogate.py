@@ -224,6 +224,14 @@ def test_pca_projection_with_per_row_centres():
                                      V.astype(np.float64))[0] for i in range(n)])
     tol = 4.0 * P * 2.0**-24 * np.abs(D - M[idx]).max() * np.abs(V).max()
     assert np.abs(coef.cpu().numpy() - want).max() <= tol
+    # an index past the centre rows gives that row NaN coefficients, the rest unchanged
+    bad = idx.copy()
+    bad[5] = rows
+    coef2 = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    L.soap_pca_project(_dev(D), _dev(M), _dev(V), coef2, mean_index=torch.from_numpy(bad).cuda())
+    c2 = coef2.cpu().numpy()
+    assert np.all(np.isnan(c2[5]))
+    np.testing.assert_array_equal(np.delete(c2, 5, axis=0), np.delete(coef.cpu().numpy(), 5, axis=0))
 
 
 @pytest.mark.parametrize("n,P,k", [(100, 1000, 37), (64, 64, 64), (1, 33, 1), (130, 20000, 64)])
@@ -426,6 +434,21 @@ def test_fused_surrogate_rv_matches_linear_fit_and_oracle_spread():
     clear = np.abs(want - thr) > 0.1 * thr
     np.testing.assert_array_equal(flag[clear], (want[clear] >= thr).astype(np.int32))
     assert 0 < flag.sum() < n
+    # per-sample base rows: one table row per sample here; an index past the
+    # table sends its sample to the fallback with status 2
+    bases = torch.stack([base, base]).contiguous()
+    bidx = np.zeros(n, np.int32)
+    bidx[3] = 2
+    fb2 = torch.empty(n, dtype=torch.int32, device="cuda")
+    rv2 = torch.empty(n, dtype=torch.float64, device="cuda")
+    rec2 = torch.empty(n * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    L.soap_surrogate_rv(ctx, _dev(coef), _dev(mem), bases, basis, calib, thr, rv2, fb2, rv_out=rec2,
+                        base_index=torch.from_numpy(bidx).cuda())
+    torch.cuda.synchronize()
+    g2 = np.frombuffer(rec2.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
+    assert fb2.cpu().numpy()[3] == 1 and g2["status"][3] == 2
+    keep = np.arange(n) != 3
+    np.testing.assert_array_equal(rv2.cpu().numpy()[keep], got["rv_kms"][keep])
     L.soap_destroy(ctx)
 
 
