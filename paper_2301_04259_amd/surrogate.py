@@ -197,6 +197,29 @@ def plain_rv(stars, samples, mask, idx=None, chunk=4096):
     return rv
 
 
+def calib_for_miss_rate(err, spread, thr, alpha):
+    """The gate factor c that accepts the most samples (c * spread < thr)
+    while at most a fraction alpha of the accepted ones have err >= thr.
+    Sample i is accepted iff c < t_i = thr / spread_i, so the candidate
+    accepted sets are the m samples of largest t; c is then the (m+1)-th
+    largest t, moved to the geometric midpoint between the m-th and the
+    (m+1)-th so that rounding of c * spread cannot move the boundary (half
+    the smallest t when every sample is accepted, twice the largest when none
+    can be)."""
+    err = np.asarray(err, np.float64)
+    t = thr / np.maximum(np.asarray(spread, np.float64), 1e-300)
+    order = np.argsort(-t, kind="stable")
+    bad = np.cumsum(err[order] >= thr)
+    m = np.arange(1, len(t) + 1)
+    ok = np.flatnonzero(bad <= alpha * m)
+    if len(ok) == 0:
+        return float(t[order[0]]) * 2.0
+    mm = int(ok[-1]) + 1
+    if mm == len(t):
+        return float(0.5 * t[order[-1]])
+    return float(np.sqrt(t[order[mm - 1]] * t[order[mm]]))
+
+
 @dataclass
 class Basis:
     """PCA basis of F - Q: mean [P] and V [P][k] (float64 host copies), and
@@ -422,18 +445,7 @@ class SurrogateModel:
         self.surrogate_rv(x, r, bufs, calib=1.0, threshold_kms=math.inf)
         spread = np.maximum(bufs["err"].cpu().numpy(), 1e-300)
         err = np.abs(bufs["rv_kms"].cpu().numpy() - rv_plain_kms)
-        # sample i is accepted iff calib < t_i = thr / spread_i: the accepted
-        # sets are the m samples of largest t
-        t = thr / spread
-        order = np.argsort(-t, kind="stable")
-        bad = np.cumsum(err[order] >= thr)
-        m = np.arange(1, len(t) + 1)
-        ok = np.flatnonzero(bad <= alpha * m)
-        if len(ok) == 0:
-            self.calib = float(t[order[0]]) * 2.0  # accept nothing
-        else:
-            mm = int(ok[-1]) + 1  # accept the top mm samples
-            self.calib = float(t[order[mm]]) if mm < len(t) else float(0.5 * t[order[-1]])
+        self.calib = calib_for_miss_rate(err, spread, thr, alpha)
         return err, spread
 
 def build(stars, mask, train, heldout, n_components=64, hidden=256, n_ensemble=4, epochs=100, batch=512,

@@ -1,0 +1,74 @@
+"""Host logic of the surrogate driver (no GPU): the gate calibration rule,
+input features and the grouping of samples by star and spot."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+S = pytest.importorskip("paper_2301_04259_amd.surrogate", reason="libsoap.so not built")
+
+
+def _accepted(c, spread, thr):
+    return c * np.asarray(spread) < thr
+
+
+def test_calibration_meets_the_miss_rate_and_accepts_the_most():
+    rng = np.random.default_rng(0)
+    n, thr = 4000, 1e-4
+    spread = 10.0 ** rng.uniform(-7, -3.5, n)
+    err = np.abs(rng.normal(0, 1, n)) * spread * 3.0
+    for alpha in (0.0, 1e-3, 1e-2):
+        c = S.calib_for_miss_rate(err, spread, thr, alpha)
+        acc = _accepted(c, spread, thr)
+        assert acc.any()
+        assert np.sum(err[acc] >= thr) <= alpha * acc.sum()
+        # brute force over factors between consecutive sample thresholds:
+        # none accepts more within the rate
+        ts = np.sort(thr / spread)
+        cands = np.concatenate([[0.5 * ts[0]], np.sqrt(ts[:-1] * ts[1:]), [2.0 * ts[-1]]])
+        best = 0
+        for cc in cands:
+            a = _accepted(cc, spread, thr)
+            if a.sum() > best and np.sum(err[a] >= thr) <= alpha * a.sum():
+                best = a.sum()
+        assert acc.sum() == best
+
+
+def test_calibration_edge_cases():
+    thr = 1.0
+    # every sample fine: all accepted
+    c = S.calib_for_miss_rate([0.1, 0.2, 0.3], [1.0, 2.0, 3.0], thr, 0.0)
+    assert _accepted(c, [1.0, 2.0, 3.0], thr).all()
+    # the most confident sample is wrong and alpha = 0: nothing accepted
+    c = S.calib_for_miss_rate([5.0, 0.1], [0.1, 1.0], thr, 0.0)
+    assert not _accepted(c, [0.1, 1.0], thr).any()
+
+
+def test_features_geometry():
+    # a spot at the disk centre of an equator-on star: x = y = 0, z = 1
+    f = S.features([0.0], [0.0], [0.055], [0.6], [0.0], [5500.0], [90.0], [3.0])[0]
+    assert f.shape == (12,)
+    np.testing.assert_allclose(f[[0, 1, 2, 3, 4, 5]], [0, 0, 1, 0, 0, 1], atol=1e-7)
+    np.testing.assert_allclose(f[[6, 7, 8, 9, 10, 11]], [0, 0, 0, 1, 0, 1], atol=1e-7)
+    # longitude and phase enter only through lon + 360 phase
+    a = S.features([20.0], [100.0], [0.05], [0.5], [0.25], [5000.0], [60.0], [2.0])
+    b = S.features([20.0], [190.0], [0.05], [0.5], [0.0], [5000.0], [60.0], [2.0])
+    np.testing.assert_allclose(a, b, atol=1e-6)
+    # pole-on star: the pole sits at the disk centre
+    p = S.features([90.0], [37.0], [0.05], [0.5], [0.3], [5000.0], [0.0], [2.0])[0]
+    np.testing.assert_allclose(p[[3, 4, 5]], [0.0, 0.0, 1.0], atol=1e-7)
+
+
+def test_samples_grouped_by_star_and_spot():
+    smp = W.cfg5_multi_samples(40, n_per=8, seed=3)
+    assert np.all(np.diff(smp.star) >= 0)  # spots ordered by star
+    idx = np.sort(np.random.default_rng(1).choice(smp.n, 100, replace=False))
+    sid = S.sample_stars(smp, idx)
+    assert np.all(np.diff(sid) >= 0)  # any sorted subset stays grouped
+    starts, ends = S._groups(sid)
+    assert starts[0] == 0 and ends[-1] == len(idx)
+    for a, b in zip(starts, ends):
+        assert len(set(sid[a:b])) == 1
+    t, i, v = smp.star_params(smp.star)
+    assert set(np.unique(t)) <= set(W.CFG5_TEFF) and set(np.unique(i)) <= set(W.CFG5_INCL)
+    assert set(np.unique(v)) <= set(W.CFG5_VSINI)
