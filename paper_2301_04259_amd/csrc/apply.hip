@@ -294,17 +294,20 @@ __device__ __forceinline__ void apply_item(const ApplyArgs<T>& A, int tile, int 
 }
 
 // ---- staged variant --------------------------------------------------------
-// The block stages each window's source spans in LDS once (coalesced 16-byte
-// loads of the tile's 1024 + 12 source samples, quiet samples and 1024
-// contrast values), double-buffered: the next window's spans are loaded into
+// Each wave stages its own window spans in LDS (the wave's 256 pixels + 12
+// source samples, the quiet samples, 256 contrast values) with coalesced
+// 16-byte loads, double-buffered: the next window's spans are loaded into
 // registers while the current window is consumed from LDS, then written to
-// the other buffer.  Threads read their 12-sample windows from LDS instead
-// of loading overlapping windows from memory.  Tile of APPLY_TILE pixels
-// (256 threads).
-constexpr int STG_SPAN = APPLY_TILE + 16;  // 1024 + 12 samples, 16-byte rows
+// the other buffer.  Lanes read their 12-sample windows from LDS instead of
+// loading overlapping windows from memory.  The spans are private to the
+// wave, so no block barrier is needed per window.  Tile of APPLY_TILE pixels
+// (256 threads, 4 waves).
+constexpr int WV_PIX = 64 * APPLY_R;   // pixels of one wave
+constexpr int WV_SPAN = WV_PIX + 16;   // + 12 samples, 16-byte rows
+constexpr int WV_BUF = 2 * WV_SPAN + WV_PIX;
 
 template <typename T>
-__device__ __forceinline__ void load4e(T (&x)[4], const T* p) {
+__device__ __forceinline__ void load4e(T* x, const T* p) {
   if constexpr (sizeof(T) == 4) {
     const f4e f = *reinterpret_cast<const f4e*>(p);
     x[0] = f.x;
@@ -350,59 +353,66 @@ __device__ __forceinline__ void lds_get4(T* x, const T* p) {
   }
 }
 
-// one thread's share of a window's spans: a[0..3] (and a[4..7], the 12
-// samples past the tile, for threads 0..2), the same for the quiet row b,
-// and 4 contrast values
+// one lane's share of its wave's spans: a[0..3] (and a[4..7], the 12
+// samples past the wave's pixels, for lanes 0..2), the same for the quiet
+// row b, and 4 contrast values
 template <typename T>
 struct Stage {
   T a[8], b[8], c[4];
 };
 
 template <typename T, int JW, bool PAIRED>
-__device__ __forceinline__ void stage_load(Stage<T>& g, const ApplyArgs<T>& A, int4 hr, int64_t mt) {
+__device__ __forceinline__ void stage_load(Stage<T>& g, const ApplyArgs<T>& A, int4 hr, int64_t mw, int lane) {
   const T *src, *sq, *con;
   int jlo;
   window_rows(A, hr, src, sq, con, jlo);
-  const int64_t at = mt - jlo - (JW - 1);
-  const int i = 4 * threadIdx.x;
-  load4e(*reinterpret_cast<T(*)[4]>(&g.a[0]), src + at + i);
-  if (PAIRED) load4e(*reinterpret_cast<T(*)[4]>(&g.b[0]), sq + at + i);
-  if (threadIdx.x < 3) {
-    load4e(*reinterpret_cast<T(*)[4]>(&g.a[4]), src + at + APPLY_TILE + i);
-    if (PAIRED) load4e(*reinterpret_cast<T(*)[4]>(&g.b[4]), sq + at + APPLY_TILE + i);
+  const int64_t at = mw - jlo - (JW - 1);
+  const int i = 4 * lane;
+  load4e(&g.a[0], src + at + i);
+  if (PAIRED) load4e(&g.b[0], sq + at + i);
+  if (lane < 3) {
+    load4e(&g.a[4], src + at + WV_PIX + i);
+    if (PAIRED) load4e(&g.b[4], sq + at + WV_PIX + i);
   }
-  load4e(g.c, con + mt + i);
+  load4e(&g.c[0], con + mw + i);
 }
 
 template <typename T, bool PAIRED>
-__device__ __forceinline__ void stage_store(T* buf, const Stage<T>& g) {
-  const int i = 4 * threadIdx.x;
+__device__ __forceinline__ void stage_store(T* buf, const Stage<T>& g, int lane) {
+  const int i = 4 * lane;
   lds_put4(buf + i, &g.a[0]);
-  if (PAIRED) lds_put4(buf + STG_SPAN + i, &g.b[0]);
-  if (threadIdx.x < 3) {
-    lds_put4(buf + APPLY_TILE + i, &g.a[4]);
-    if (PAIRED) lds_put4(buf + STG_SPAN + APPLY_TILE + i, &g.b[4]);
+  if (PAIRED) lds_put4(buf + WV_SPAN + i, &g.b[0]);
+  if (lane < 3) {
+    lds_put4(buf + WV_PIX + i, &g.a[4]);
+    if (PAIRED) lds_put4(buf + WV_SPAN + WV_PIX + i, &g.b[4]);
   }
-  lds_put4(buf + 2 * STG_SPAN + i, &g.c[0]);
+  lds_put4(buf + 2 * WV_SPAN + i, &g.c[0]);
 }
 
 template <typename T, bool PAIRED>
-__device__ __forceinline__ void stage_read(Operands<T>& o, const T* buf) {
-  const int i = 4 * threadIdx.x;
+__device__ __forceinline__ void stage_read(Operands<T>& o, const T* buf, int lane) {
+  const int i = 4 * lane;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     lds_get4(&o.a.v[4 * k], buf + i + 4 * k);
-    if (PAIRED) lds_get4(&o.b.v[4 * k], buf + STG_SPAN + i + 4 * k);
+    if (PAIRED) lds_get4(&o.b.v[4 * k], buf + WV_SPAN + i + 4 * k);
   }
-  lds_get4(&o.c[0], buf + 2 * STG_SPAN + i);
+  lds_get4(&o.c[0], buf + 2 * WV_SPAN + i);
+}
+
+// the wave's own LDS writes are visible to its later reads
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename T, int R, int PC, int JW, bool PAIRED>
 __device__ __forceinline__ void apply_item_staged(const ApplyArgs<T>& A, int tile, int chunk, unsigned char* s_win) {
-  const int64_t mt = (int64_t)tile * APPLY_TILE;
-  const int64_t m0 = mt + (int64_t)threadIdx.x * R;
-  T* stg = reinterpret_cast<T*>(s_win + (size_t)A.lds_win * WIN_BYTES);
-  constexpr int BUF = 2 * STG_SPAN + APPLY_TILE;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t mw = (int64_t)tile * APPLY_TILE + (int64_t)wave * WV_PIX;
+  const int64_t m0 = mw + (int64_t)lane * R;
+  T* stg = reinterpret_cast<T*>(s_win + (size_t)A.lds_win * WIN_BYTES) + (size_t)wave * 2 * WV_BUF;
 
   T acc[PC][R];
 #pragma unroll
@@ -423,18 +433,18 @@ __device__ __forceinline__ void apply_item_staged(const ApplyArgs<T>& A, int til
     }
     __syncthreads();
     Stage<T> g;
-    stage_load<T, JW, PAIRED>(g, A, head_raw(s_win, 0), mt);
-    stage_store<T, PAIRED>(stg, g);
-    __syncthreads();
+    stage_load<T, JW, PAIRED>(g, A, head_raw(s_win, 0), mw, lane);
+    stage_store<T, PAIRED>(stg, g, lane);
+    wave_sync();
     for (int v = 0; v < nb; ++v) {
       const bool more = v + 1 < nb;  // uniform
-      if (more) stage_load<T, JW, PAIRED>(g, A, head_raw(s_win, v + 1), mt);
+      if (more) stage_load<T, JW, PAIRED>(g, A, head_raw(s_win, v + 1), mw, lane);
       Operands<T> o;
-      stage_read<T, PAIRED>(o, stg + (v & 1) * BUF);
+      stage_read<T, PAIRED>(o, stg + (v & 1) * WV_BUF, lane);
       consume<T, R, PC, JW, PAIRED>(acc, o, (unsigned)uni(head_raw(s_win, v).w),
                                     reinterpret_cast<const T*>(s_win + v * WIN_BYTES + 16));
-      if (more) stage_store<T, PAIRED>(stg + ((v + 1) & 1) * BUF, g);
-      __syncthreads();
+      if (more) stage_store<T, PAIRED>(stg + ((v + 1) & 1) * WV_BUF, g, lane);
+      wave_sync();
     }
   }
   store_item<T, R, PC>(A, acc, chunk, m0);
@@ -526,7 +536,7 @@ hipError_t launch_apply_t(soap_ctx* c, const Plan& pl, const ApplyArgs<T>& A0, i
   const dim3 grid(8 * tpx * pl.n_chunks);
   if (staged) {
     // the staging buffers take their share of at most 60 KB per block
-    const size_t stg = 2 * (2 * (size_t)STG_SPAN + APPLY_TILE) * sizeof(T);
+    const size_t stg = (size_t)(APPLY_THREADS / 64) * 2 * WV_BUF * sizeof(T);
     A.lds_win = std::max(1, std::min<int>(A.lds_win, (int)((60 * 1024 - stg) / WIN_BYTES)));
     const size_t lds = (size_t)A.lds_win * WIN_BYTES + stg;
     hipLaunchKernelGGL((k_apply<T, APPLY_R, PC, APPLY_JW, PAIRED, 256, true>), grid, dim3(256), lds, st, A);
