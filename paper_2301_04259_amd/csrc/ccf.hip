@@ -197,7 +197,8 @@ constexpr int CCF_FIN_THREADS = 256;
 // (mu, sigma), (sigma, sigma) (the only second derivatives that are not
 // zero), with f = c0 - amp e, e = exp(-(v - mu)^2 / (2 sigma^2)), r = f - y
 // and parameters ordered (c0, amp, mu, sigma).
-__device__ void gf_eval(const double (&y)[GF_MAXPT], int n_v, double v0, double dv, const double p[4],
+template <int NPT>
+__device__ void gf_eval(const double (&y)[NPT], int n_v, double v0, double dv, const double p[4],
                         double S[20]) {
   const int lane = threadIdx.x;
   double v[16], w[16];
@@ -206,7 +207,7 @@ __device__ void gf_eval(const double (&y)[GF_MAXPT], int n_v, double v0, double 
   const double is = 1.0 / p[3];
   const double is2 = is * is;
 #pragma unroll
-  for (int t = 0; t < GF_MAXPT; ++t) {
+  for (int t = 0; t < NPT; ++t) {
     if (64 * t >= n_v) break;  // uniform
     const int i = lane + 64 * t;
     if (i < n_v) {
@@ -297,14 +298,15 @@ __device__ bool gf_solve(const double S[20], bool newton, double lam, double x[4
 // lane + 64 t); returns the result record and leaves the parameters in p and
 // the last sums (gf_eval) in S.  Damped Newton / Levenberg-Marquardt as
 // described at k_ccf_fit.
-__device__ soap_rv fit_wave(const double (&y)[GF_MAXPT], int n_v, double v0, double dv, double p[4],
+template <int NPT>
+__device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double dv, double p[4],
                             double S[20]) {
   const int lane = threadIdx.x & 63;
   // start values: max, first argmin, half-depth width
   double ymax = -1e308, ymin = 1e308;
   int kmin = n_v;
 #pragma unroll
-  for (int t = 0; t < GF_MAXPT; ++t) {
+  for (int t = 0; t < NPT; ++t) {
     const int i = lane + 64 * t;
     if (i < n_v) {
       ymax = fmax(ymax, y[t]);
@@ -329,7 +331,7 @@ __device__ soap_rv fit_wave(const double (&y)[GF_MAXPT], int n_v, double v0, dou
   const double half = c0 - 0.5 * a0;
   int first = n_v, last = -1;
 #pragma unroll
-  for (int t = 0; t < GF_MAXPT; ++t) {
+  for (int t = 0; t < NPT; ++t) {
     const int i = lane + 64 * t;
     if (i < n_v && y[t] <= half) {
       first = min(first, i);
@@ -430,44 +432,46 @@ __device__ soap_rv fit_wave(const double (&y)[GF_MAXPT], int n_v, double v0, dou
 // chi^2 and moves the centre and width by at most 1e-9 sigma; a run of
 // rejected steps that drives the damping past 1e10 means no downhill step
 // exists at this precision, which is also the minimum.
+template <int NPT>
 __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n_spec, int n_v, double v0,
                                                              double dv, const double* __restrict__ part,
                                                              double* __restrict__ ccf, int fit,
                                                              soap_rv* __restrict__ out) {
-  __shared__ double s_sum[CCF_FIN_THREADS / 64][GF_MAXPT * 64];
+  __shared__ double s_sum[CCF_FIN_THREADS / 64][NPT * 64];
   const int64_t s = blockIdx.x;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   constexpr int NW = CCF_FIN_THREADS / 64;
+  constexpr int RB = NPT <= 3 ? 16 : (NPT <= 6 ? 8 : 4);  // rows in flight per wave
   {
-    double acc[GF_MAXPT];
+    double acc[NPT];
 #pragma unroll
-    for (int t = 0; t < GF_MAXPT; ++t) acc[t] = 0.0;
-    for (int lb0 = wave; lb0 < n_lb; lb0 += 4 * NW) {
-      double v[4][GF_MAXPT];
+    for (int t = 0; t < NPT; ++t) acc[t] = 0.0;
+    for (int lb0 = wave; lb0 < n_lb; lb0 += RB * NW) {
+      double v[RB][NPT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < RB; ++u) {
         const int lb = lb0 + u * NW;
         const double* src = part + ((int64_t)lb * n_spec + s) * n_v;
 #pragma unroll
-        for (int t = 0; t < GF_MAXPT; ++t) {
+        for (int t = 0; t < NPT; ++t) {
           const int i = lane + 64 * t;
           v[u][t] = (lb < n_lb && i < n_v) ? src[i] : 0.0;
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < RB; ++u)
 #pragma unroll
-        for (int t = 0; t < GF_MAXPT; ++t) acc[t] += v[u][t];
+        for (int t = 0; t < NPT; ++t) acc[t] += v[u][t];
     }
 #pragma unroll
-    for (int t = 0; t < GF_MAXPT; ++t) s_sum[wave][lane + 64 * t] = acc[t];
+    for (int t = 0; t < NPT; ++t) s_sum[wave][lane + 64 * t] = acc[t];
   }
   __syncthreads();
   if (wave != 0) return;
-  double y[GF_MAXPT];
+  double y[NPT];
 #pragma unroll
-  for (int t = 0; t < GF_MAXPT; ++t) {
+  for (int t = 0; t < NPT; ++t) {
     const int i = lane + 64 * t;
     double a = 0.0;
 #pragma unroll
@@ -518,12 +522,28 @@ hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const dou
   return hipGetLastError();
 }
 
+// the fit kernel for the mask's points per lane
+static hipError_t launch_fit_npt(soap_ctx* c, int nlb, int64_t n_spec, const double* d_part, double* d_ccf,
+                                 soap_rv* d_rv) {
+  const int npt = (c->mask_nv + 63) / 64;
+#define FIT_CASE(N)                                                                                           \
+  case N:                                                                                                     \
+    hipLaunchKernelGGL(k_ccf_fit<N>, dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, c->stream, nlb, n_spec, \
+                       c->mask_nv, c->mask_v0, c->mask_dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);                \
+    break;
+  switch (npt) {
+    FIT_CASE(1) FIT_CASE(2) FIT_CASE(3) FIT_CASE(4) FIT_CASE(5) FIT_CASE(6)
+    FIT_CASE(7) FIT_CASE(8) FIT_CASE(9) FIT_CASE(10) FIT_CASE(11) FIT_CASE(12)
+    default: return hipErrorInvalidValue;
+  }
+#undef FIT_CASE
+  return hipGetLastError();
+}
+
 hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_t n_spec, double* d_ccf,
                           soap_rv* d_rv) {
   const int nlb = ccf_line_blocks(n_lines);
-  hipLaunchKernelGGL(k_ccf_fit, dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, c->stream, nlb, n_spec,
-                     c->mask_nv, c->mask_v0, c->mask_dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);
-  return hipGetLastError();
+  return launch_fit_npt(c, nlb, n_spec, d_part, d_ccf, d_rv);
 }
 
 // ccf[i][v] = base[v] + sum_k coef[i][k] basis[k][v] (double, increasing k):
@@ -562,6 +582,7 @@ constexpr int SG_MAX_ENS = 16;
 //      dRV_e = sum_k h_k (y_e,k - coef_k) with h = basis g;
 //   3. err = calib x sample standard deviation of dRV_e over the members;
 //      fallback when err is not below thr or the fit did not converge.
+template <int NPT>
 __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, double v0, double dv,
                                               const float* __restrict__ coef, const float* __restrict__ members,
                                               const double* __restrict__ base, const int* __restrict__ base_idx,
@@ -570,7 +591,7 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
                                               double* __restrict__ rv_kms, double* __restrict__ err_kms,
                                               int* __restrict__ fallback) {
   __shared__ double s_c[64];
-  __shared__ double s_g[GF_MAXPT * 64];
+  __shared__ double s_g[NPT * 64];
   const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
   const int brow = base_idx ? base_idx[i] : 0;
@@ -586,9 +607,9 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
     return;
   }
   const double* bs = base + (int64_t)brow * n_v;
-  double y[GF_MAXPT];
+  double y[NPT];
 #pragma unroll
-  for (int t = 0; t < GF_MAXPT; ++t) {
+  for (int t = 0; t < NPT; ++t) {
     const int v = lane + 64 * t;
     y[t] = v < n_v ? bs[v] : 0.0;
   }
@@ -601,7 +622,7 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
       const double cj = s_c[j];
       const double* bj = basis + (int64_t)(k0 + j) * n_v;
 #pragma unroll
-      for (int t = 0; t < GF_MAXPT; ++t) {
+      for (int t = 0; t < NPT; ++t) {
         const int v = lane + 64 * t;
         if (v < n_v) y[t] = fma(cj, bj[v], y[t]);
       }
@@ -628,7 +649,7 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
       const double is = 1.0 / p[3];
       const double is2 = is * is;
 #pragma unroll
-      for (int t = 0; t < GF_MAXPT; ++t) {
+      for (int t = 0; t < NPT; ++t) {
         const int v = lane + 64 * t;
         if (v < n_v) {
           const double d = v0 + dv * v - p[2];
@@ -687,9 +708,19 @@ hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members
                         const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
                         double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
                         int* d_fallback) {
-  hipLaunchKernelGGL(k_sg_rv, dim3((unsigned)n), dim3(64), 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,
-                     c->mask_dv, d_coef, d_members, d_base, d_base_idx, d_base_idx ? n_base : 1, d_basis, calib,
-                     thr, d_rv, d_rv_kms, d_err, d_fallback);
+  const int npt = (c->mask_nv + 63) / 64;
+#define SG_CASE(N)                                                                                              \
+  case N:                                                                                                       \
+    hipLaunchKernelGGL(k_sg_rv<N>, dim3((unsigned)n), dim3(64), 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,  \
+                       c->mask_dv, d_coef, d_members, d_base, d_base_idx, d_base_idx ? n_base : 1, d_basis,     \
+                       calib, thr, d_rv, d_rv_kms, d_err, d_fallback);                                          \
+    break;
+  switch (npt) {
+    SG_CASE(1) SG_CASE(2) SG_CASE(3) SG_CASE(4) SG_CASE(5) SG_CASE(6)
+    SG_CASE(7) SG_CASE(8) SG_CASE(9) SG_CASE(10) SG_CASE(11) SG_CASE(12)
+    default: return hipErrorInvalidValue;
+  }
+#undef SG_CASE
   return hipGetLastError();
 }
 
@@ -700,9 +731,7 @@ hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, in
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the rows are complete CCFs: one "block of lines" for the fit kernel
-  hipLaunchKernelGGL(k_ccf_fit, dim3((unsigned)n), dim3(CCF_FIN_THREADS), 0, c->stream, 1, n, c->mask_nv,
-                     c->mask_v0, c->mask_dv, d_lin, d_ccf, d_rv ? 1 : 0, d_rv);
-  return hipGetLastError();
+  return launch_fit_npt(c, 1, n, d_lin, d_ccf, d_rv);
 }
 
 hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask) {
