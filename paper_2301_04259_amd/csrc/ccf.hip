@@ -6,10 +6,13 @@
 // coordinate; at trial velocity v_k its hole spans [u_l + a_k^-, u_l + a_k^+]
 // with a_k^+- = atanh((v_k +- h)/c)/dln (the ln of the Eq. 6 factor).
 // CCF_k = sum_l w_l sum_m F_m * overlap(bin m, hole), existing pixels only.
-// Layout: one block per (block of lines, block of SB spectra), one thread per
-// velocity; each thread keeps SB double accumulators and reuses its hole
-// geometry for every spectrum of the block.  Partial sums per line block are
-// added in a fixed order by the fit kernel, so results repeat bit for bit.
+// The line positions, the hole edges per velocity and the split of the mask
+// into blocks of lines and batches of nearby lines are built on the host
+// once per mask.  Layout: one block per (block of lines, block of SB
+// spectra), one thread per velocity; each thread keeps SB double
+// accumulators and reuses its hole geometry for every spectrum of the block.
+// Partial sums per line block are added in a fixed order by the fit kernel,
+// so results repeat bit for bit.
 //
 // Fit: one wave64 per CCF; damped Newton (Levenberg-Marquardt damping) in
 // double on the unweighted least squares of c0 - a exp(-(v - mu)^2 /
@@ -17,178 +20,253 @@
 // reductions, the 4 x 4 damped system is solved by Cholesky in every lane.
 // Start values: c0 = max, a = c0 - min, mu = v at the min, sigma from the
 // half-depth width.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
 #include "soap_internal.hpp"
 #include "wave.hpp"
 
 namespace soap {
 
-constexpr int CCF_LINES = 64;  // lines per block (partial sums per block)
-constexpr int CCF_SB = 8;      // spectra per block
-constexpr int CCF_THREADS = 192;
-constexpr int CCF_SPAN = 512;  // staged pixels per spectrum (double, 32 KB per block)
+constexpr int CCF_LB = 32;        // mask lines per block (one partial CCF row each)
+constexpr int CCF_SB = 8;         // spectra per block
+constexpr int CCF_THREADS = 192;  // one thread per velocity (A velocities each past 192)
+constexpr int CCF_STG_MAX = 512;  // widest staged span of a batch, in pixels
 // a line's hole centre, in pixels, is kept within this margin of the grid:
 // lines further out reach no pixel
 constexpr double CCF_U_MARGIN = 4096.0;
 
-int ccf_line_blocks(int n_lines) { return (n_lines + CCF_LINES - 1) / CCF_LINES; }
-int ccf_span_pixels(bool) { return CCF_SPAN; }
+int ccf_line_blocks(int n_lines) { return (n_lines + CCF_LB - 1) / CCF_LB; }
+int ccf_span_pixels(bool) { return CCF_STG_MAX; }
 
-__global__ void k_mask_prep(int n, double ln0, double dln, double P, const double* __restrict__ lnl,
-                            const double* __restrict__ w, double2* __restrict__ out) {
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < n) {
-    const double u = (lnl[l] - ln0) / dln + 0.5;
-    out[l] = make_double2(fmin(fmax(u, -CCF_U_MARGIN), P + CCF_U_MARGIN), w[l]);
+namespace {
+
+// 4 consecutive elements of 16-byte-aligned memory as doubles
+template <typename T>
+__device__ __forceinline__ void get4(double* x, const T* p) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+  } else {
+    const double2 a = reinterpret_cast<const double2*>(p)[0];
+    const double2 b = reinterpret_cast<const double2*>(p)[1];
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = b.x;
+    x[3] = b.y;
   }
 }
 
-// One block per (64 mask lines, 8 spectra).  The block's lines go to LDS
-// and are split once into batches whose holes, at any trial velocity, reach
-// a pixel span that fits the LDS stage.  Batch by batch the span of the
-// block's spectra is staged in double (coalesced loads; the next two
-// batches' loads are in flight in registers while one is used), then one
-// thread per velocity computes each hole's pixel overlaps once and applies
-// them to every staged spectrum, accumulating in double.
-template <typename T, int A, int NPX>
+}  // namespace
+
+// One block per (CCF_LB mask lines, CCF_SB spectra).  The block walks the
+// batches of its lines (host-built: consecutive lines whose holes, at every
+// trial velocity, stay inside a span of STG pixels).  A batch's span of the
+// block's spectra is staged pixel-major in LDS, [pixel][spectrum], so that
+// one thread reads the SB values of a pixel with 16-byte loads; two stage
+// buffers alternate, the next batch's loads are in flight while one is
+// used, and one barrier per batch separates them.  Pixels outside the
+// spectrum are staged as zeros.  Each thread computes its holes' pixel
+// overlaps once per line and applies them to every staged spectrum with
+// FP64 FMAs.
+template <typename T, int A, int NPX, int STG>
 __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, const T* __restrict__ F,
-                                                     int n_lines, const double2* __restrict__ mask, int n_v,
-                                                     double v0, double dv, double h, double dln,
+                                                     const double2* __restrict__ lines,
+                                                     const double2* __restrict__ edges,
+                                                     const int4* __restrict__ batches,
+                                                     const int* __restrict__ bfirst, int n_v,
                                                      double* __restrict__ part) {
-  constexpr int U = (CCF_SPAN + CCF_THREADS - 1) / CCF_THREADS;  // staged elements per thread and spectrum
-  constexpr int UNR = A * NPX <= 10 ? NPX : 1;                   // unrolled hole pixels
-  __shared__ double st[CCF_SB][CCF_SPAN];
-  __shared__ double2 s_mask[CCF_LINES];
-  __shared__ int s_lo[CCF_LINES], s_len[CCF_LINES], s_end[CCF_LINES];
-  __shared__ int s_nb;
+  constexpr int SB = CCF_SB;
+  constexpr int R = (STG + CCF_THREADS - 1) / CCF_THREADS;  // staged pixels per thread
+  static_assert(SB % 4 == 0, "16-byte stage rows");
+  __shared__ __align__(16) T st[2][STG][SB];
+  __shared__ double2 s_line[CCF_LB];
+  __shared__ double2 s_ed[A * CCF_THREADS];
   const int tid = threadIdx.x;
   const int lb = blockIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.y * CCF_SB;
-  const int l0 = lb * CCF_LINES;
-  const int nl = min(CCF_LINES, n_lines - l0);
-  const int ns = (int)min<int64_t>(CCF_SB, n_spec - s0);
-  if (tid < nl) s_mask[tid] = mask[l0 + tid];
-  // extreme edges over the velocity grid bound the staged span
-  const double alo_min = atanh((v0 - h) / C_KMS) / dln;
-  const double ahi_max = atanh((v0 + dv * (n_v - 1) + h) / C_KMS) / dln;
-  // hole edges of the velocities this thread handles: tid + a * CCF_THREADS
-  double alo[A], ahi[A], acc[A][CCF_SB];
+  const int64_t s0 = (int64_t)blockIdx.y * SB;
+  const int ns = (int)min<int64_t>(SB, n_spec - s0);
+  const int b0 = bfirst[lb], b1 = bfirst[lb + 1];
+  const int l0 = batches[b0].y;
+  const int nl = batches[b1 - 1].z - l0;
+  if (tid < nl) s_line[tid] = lines[l0 + tid];
+  // lanes past the velocity grid repeat its last velocity (results dropped);
+  // the edges go through LDS so that no global load is pending in the loop
+#pragma unroll
+  for (int a = 0; a < A; ++a) s_ed[tid + a * CCF_THREADS] = edges[min(tid + a * CCF_THREADS, n_v - 1)];
+  __syncthreads();
+  double alo[A], ahi[A], acc[A][SB];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
-    const double vk = v0 + dv * (tid + a * CCF_THREADS);
-    alo[a] = atanh((vk - h) / C_KMS) / dln;
-    ahi[a] = atanh((vk + h) / C_KMS) / dln;
+    const double2 e = s_ed[tid + a * CCF_THREADS];
+    alo[a] = e.x;
+    ahi[a] = e.y;
 #pragma unroll
-    for (int s = 0; s < CCF_SB; ++s) acc[a][s] = 0.0;
+    for (int s = 0; s < SB; ++s) acc[a][s] = 0.0;
   }
-  __syncthreads();
-  if (tid == 0) {
-    // batches of consecutive lines whose joint reach fits the stage
-    int nb = 0;
-    int lo = (int)floor(s_mask[0].x + alo_min);
-    int hi = (int)floor(s_mask[0].x + ahi_max) + 1;
-    for (int l = 1; l < nl; ++l) {
-      const int llo = (int)floor(s_mask[l].x + alo_min);
-      const int lhi = (int)floor(s_mask[l].x + ahi_max) + 1;
-      const int nlo = min(lo, llo), nhi = max(hi, lhi);
-      if (nhi - nlo + 1 > CCF_SPAN) {
-        s_lo[nb] = lo;
-        s_len[nb] = min(CCF_SPAN, hi - lo + 1);
-        s_end[nb] = l;
-        ++nb;
-        lo = llo;
-        hi = lhi;
-      } else {
-        lo = nlo;
-        hi = nhi;
-      }
+  T vals[R][SB];
+  auto load = [&](int bi) {
+    if (bi >= b1) return;
+    const int lo = batches[bi].x;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int m = min(max(lo + tid + r * CCF_THREADS, 0), P - 1);
+#pragma unroll
+      for (int s = 0; s < SB; ++s) vals[r][s] = F[(s0 + min(s, ns - 1)) * (int64_t)P + m];
     }
-    s_lo[nb] = lo;
-    s_len[nb] = min(CCF_SPAN, hi - lo + 1);
-    s_end[nb] = nl;
-    s_nb = nb + 1;
-  }
-  __syncthreads();
-  const int nb = s_nb;
-  // two batches in flight: while batch bi is used, the loads of bi + 1 and
-  // bi + 2 are outstanding in two register buffers
-  T va[CCF_SB][U], vb[CCF_SB][U];
-  auto load = [&](T (&vals)[CCF_SB][U], int bi) {
-    if (bi >= nb) return;
-    const int lo = s_lo[bi];
-    const int len = s_len[bi];
+  };
+  auto put = [&](int bi) {
+    if (bi >= b1) return;
+    const int lo = batches[bi].x;
+    T(*sb)[SB] = st[(bi - b0) & 1];
 #pragma unroll
-    for (int s = 0; s < CCF_SB; ++s) {
-      const T* row = F + (s0 + s) * (int64_t)P;
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = tid + u * CCF_THREADS;
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + r * CCF_THREADS;
+      if (r < R - 1 || i < STG) {
         const int m = lo + i;
-        vals[s][u] = (s < ns && i < len && m >= 0 && m < P) ? row[m] : T(0);
+        const bool ok = m >= 0 && m < P;
+#pragma unroll
+        for (int s = 0; s < SB; ++s) sb[i][s] = ok ? vals[r][s] : T(0);
       }
     }
   };
-  auto batch = [&](T (&vals)[CCF_SB][U], int bi) {
-    const int lo = s_lo[bi];
-    const int len = s_len[bi];
-    const int lbeg = bi ? s_end[bi - 1] : 0;
-    const int lend = s_end[bi];
-    if (bi) __syncthreads();  // every thread is done with the previous stage
-#pragma unroll
-    for (int s = 0; s < CCF_SB; ++s)
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int i = tid + u * CCF_THREADS;
-        if (i < len) st[s][i] = (double)vals[s][u];
-      }
-    __syncthreads();
-    load(vals, bi + 2);
-    for (int l = lbeg; l < lend; ++l) {
-      const double2 mw = s_mask[l];
+  load(b0);
+  put(b0);
+  load(b0 + 1);
+  __syncthreads();
+  for (int bi = b0; bi < b1; ++bi) {
+    const int4 B = batches[bi];
+    const T(*sb)[SB] = st[(bi - b0) & 1];
+    for (int l = B.y; l < B.z; ++l) {
+      const double2 mw = s_line[l - l0];
 #pragma unroll
       for (int a = 0; a < A; ++a) {
-        const int k = tid + a * CCF_THREADS;
-        if (k >= n_v) break;
         const double qlo = mw.x + alo[a];
         const double qhi = mw.x + ahi[a];
         const double fa = floor(qlo);
-        const int i0 = (int)fa - lo;  // stage index of the first pixel
-        // A hole narrower than NPX - 1 pixels meets at most NPX pixels; the
-        // pixels past its end get a zero weight (an exact no-op).  Pixels
-        // outside the spectrum are staged as zeros, and the first pixel's
-        // lower edge is the hole's (every later pixel starts inside it).
-#pragma unroll UNR
-        for (int px = 0; px < NPX; ++px) {
-          const double mlo = fa + (double)px;
-          const double ov = fmin(qhi, mlo + 1.0) - (px == 0 ? qlo : mlo);
-          const double wo = mw.y * fmax(ov, 0.0);
-          const int ii = min(i0 + px, len - 1);
+        const int i0 = (int)fa - B.x;
+        double w[NPX];
+        if constexpr (NPX == 2) {
+          // a hole narrower than a pixel: the first pixel takes the part of
+          // the hole below fa + 1, the second the rest
+          const double e1 = fa + 1.0;
+          w[0] = mw.y * (fmin(qhi, e1) - qlo);
+          w[1] = mw.y * fmax(qhi - e1, 0.0);
+        } else {
+          // pixel px covers [fa + px, fa + px + 1); the first pixel's lower
+          // edge is the hole's, pixels past the hole get weight zero
 #pragma unroll
-          for (int s = 0; s < CCF_SB; ++s) acc[a][s] = fma(wo, st[s][ii], acc[a][s]);
+          for (int px = 0; px < NPX; ++px) {
+            const double mlo = fa + (double)px;
+            w[px] = mw.y * fmax(fmin(qhi, mlo + 1.0) - (px == 0 ? qlo : mlo), 0.0);
+          }
+        }
+#pragma unroll
+        for (int px = 0; px < NPX; ++px) {
+          double f[SB];
+#pragma unroll
+          for (int c = 0; c < SB / 4; ++c) get4(&f[4 * c], &sb[i0 + px][4 * c]);
+#pragma unroll
+          for (int s = 0; s < SB; ++s) acc[a][s] = fma(w[px], f[s], acc[a][s]);
         }
       }
     }
-  };
-  load(va, 0);
-  load(vb, 1);
-  for (int bi = 0; bi < nb; bi += 2) {
-    batch(va, bi);
-    if (bi + 1 < nb) batch(vb, bi + 1);
+    put(bi + 1);
+    load(bi + 2);
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < A; ++a) {
     const int k = tid + a * CCF_THREADS;
     if (k >= n_v) break;
 #pragma unroll
-    for (int s = 0; s < CCF_SB; ++s)
+    for (int s = 0; s < SB; ++s)
       if (s < ns) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = acc[a][s];
   }
 }
 
+// Host tables of one mask (section 4.1's CCF with the holes of Eq. 6),
+// appended to blob with 16-byte-aligned sections: lines (u, w) double2[nl],
+// hole edges (a^-, a^+) double2[n_v], batches int4 {first staged pixel,
+// first line, end line, 0}, and per line block the index of its first batch
+// (int[n_lb + 1]).  Batches hold consecutive lines whose reads, from the
+// floor of the lowest hole edge to NPX pixels past the floor of the highest,
+// fit a span of STG pixels.
+bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, std::vector<unsigned char>& blob,
+                      std::string& err) {
+  const int nv = c->mask_nv;
+  std::vector<double2> ln(nl), ed(nv);
+  for (int l = 0; l < nl; ++l) {
+    const double u = (lnl[l] - c->ln0) / c->dln + 0.5;
+    ln[l] = make_double2(std::fmin(std::fmax(u, -CCF_U_MARGIN), (double)c->P + CCF_U_MARGIN), wl[l]);
+  }
+  double wmax = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    const double vk = c->mask_v0 + c->mask_dv * k;
+    ed[k] = make_double2(std::atanh((vk - c->mask_h) / C_KMS) / c->dln, std::atanh((vk + c->mask_h) / C_KMS) / c->dln);
+    wmax = std::fmax(wmax, ed[k].y - ed[k].x);
+  }
+  const int npx = wmax < 1.0 ? 2 : (wmax < 2.0 ? 3 : (wmax < 4.0 ? 5 : 10));
+  // the edges grow with k (atanh is increasing), so these bound every hole
+  const double amin = ed[0].x, amax = ed[nv - 1].y;
+  auto span_lo = [&](int l) { return (int)std::floor(ln[l].x + amin); };
+  auto span_end = [&](int l) { return (int)std::floor(ln[l].x + amax) + npx; };
+  int widest = 0;
+  for (int l = 0; l < nl; ++l) widest = std::max(widest, span_end(l) - span_lo(l));
+  if (widest > CCF_STG_MAX) {
+    err = "the velocity grid and holes span " + std::to_string(widest) + " pixels, beyond the supported " +
+          std::to_string(CCF_STG_MAX);
+    return false;
+  }
+  const int stg = widest <= 256 ? 256 : CCF_STG_MAX;
+  const int nlb = ccf_line_blocks(nl);
+  std::vector<int4> bat;
+  std::vector<int> bfirst(nlb + 1);
+  for (int b = 0; b < nlb; ++b) {
+    bfirst[b] = (int)bat.size();
+    const int l0 = b * CCF_LB, l1 = std::min(nl, l0 + CCF_LB);
+    int lo = span_lo(l0), hi = span_end(l0), beg = l0;
+    for (int l = l0 + 1; l < l1; ++l) {
+      const int nlo = std::min(lo, span_lo(l)), nhi = std::max(hi, span_end(l));
+      if (nhi - nlo > stg) {
+        bat.push_back(make_int4(lo, beg, l, 0));
+        lo = span_lo(l);
+        hi = span_end(l);
+        beg = l;
+      } else {
+        lo = nlo;
+        hi = nhi;
+      }
+    }
+    bat.push_back(make_int4(lo, beg, l1, 0));
+  }
+  bfirst[nlb] = (int)bat.size();
+  auto al16 = [](size_t v) { return (v + 15) & ~size_t(15); };
+  const size_t o_ed = al16(sizeof(double2) * nl);
+  const size_t o_bat = al16(o_ed + sizeof(double2) * nv);
+  const size_t o_bf = al16(o_bat + sizeof(int4) * bat.size());
+  blob.assign(al16(o_bf + sizeof(int) * bfirst.size()), 0);
+  std::memcpy(blob.data(), ln.data(), sizeof(double2) * nl);
+  std::memcpy(blob.data() + o_ed, ed.data(), sizeof(double2) * nv);
+  std::memcpy(blob.data() + o_bat, bat.data(), sizeof(int4) * bat.size());
+  std::memcpy(blob.data() + o_bf, bfirst.data(), sizeof(int) * bfirst.size());
+  c->ccf_off_edges = o_ed;
+  c->ccf_off_batch = o_bat;
+  c->ccf_off_bfirst = o_bf;
+  c->ccf_nbatch = (int)bat.size();
+  c->ccf_npx = npx;
+  c->ccf_stg = stg;
+  c->mask_hole_px = wmax;
+  return true;
+}
 
 namespace {
 
 constexpr double FWHM_PER_SIGMA = 2.3548200450309493;  // 2 sqrt(2 ln 2)
-constexpr int GF_MAXPT = 12;                            // points per lane (n_v <= 768)
 constexpr int CCF_FIN_THREADS = 256;
 
 // Sums of the fit at p, identical in every lane: S[0] = chi^2,
@@ -485,40 +563,45 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
   if (lane == 0) out[s] = res;
 }
 
-template <typename T, int A, int NPX>
-static void launch_ccf_a(soap_ctx* c, dim3 grid, const T* F, int64_t n_spec, const double2* M, int n_lines) {
-  hipLaunchKernelGGL((k_ccf<T, A, NPX>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec, F, n_lines, M,
-                     c->mask_nv, c->mask_v0, c->mask_dv, c->mask_h, c->dln, c->ccf_part);
+template <typename T, int A, int NPX, int STG>
+static void launch_ccf_a(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
+  const unsigned char* base = static_cast<const unsigned char*>(c->ws_mask.ptr);
+  hipLaunchKernelGGL((k_ccf<T, A, NPX, STG>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec,
+                     static_cast<const T*>(d_flux), reinterpret_cast<const double2*>(base),
+                     reinterpret_cast<const double2*>(base + c->ccf_off_edges),
+                     reinterpret_cast<const int4*>(base + c->ccf_off_batch),
+                     reinterpret_cast<const int*>(base + c->ccf_off_bfirst), c->mask_nv, d_part);
 }
 
-template <typename T, int NPX>
-static void launch_ccf_n(soap_ctx* c, dim3 grid, const T* F, int64_t n_spec, const double2* M, int n_lines) {
+template <typename T, int NPX, int STG>
+static void launch_ccf_n(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
   const int nv = c->mask_nv;
-  if (nv <= CCF_THREADS) launch_ccf_a<T, 1, NPX>(c, grid, F, n_spec, M, n_lines);
-  else if (nv <= 2 * CCF_THREADS) launch_ccf_a<T, 2, NPX>(c, grid, F, n_spec, M, n_lines);
-  else launch_ccf_a<T, 4, NPX>(c, grid, F, n_spec, M, n_lines);
+  if (nv <= CCF_THREADS) launch_ccf_a<T, 1, NPX, STG>(c, grid, d_flux, n_spec, d_part);
+  else if (nv <= 2 * CCF_THREADS) launch_ccf_a<T, 2, NPX, STG>(c, grid, d_flux, n_spec, d_part);
+  else launch_ccf_a<T, 4, NPX, STG>(c, grid, d_flux, n_spec, d_part);
+}
+
+template <typename T, int STG>
+static void launch_ccf_s(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
+  switch (c->ccf_npx) {
+    case 2: launch_ccf_n<T, 2, STG>(c, grid, d_flux, n_spec, d_part); break;
+    case 3: launch_ccf_n<T, 3, STG>(c, grid, d_flux, n_spec, d_part); break;
+    case 5: launch_ccf_n<T, 5, STG>(c, grid, d_flux, n_spec, d_part); break;
+    default: launch_ccf_n<T, 10, STG>(c, grid, d_flux, n_spec, d_part); break;
+  }
 }
 
 template <typename T>
-static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, const double* d_mask,
-                         int n_lines) {
-  const T* F = static_cast<const T*>(d_flux);
-  const double2* M = reinterpret_cast<const double2*>(d_mask);
-  // pixels a hole can meet: its width (at the widest velocity) plus two
-  const double wpx = c->mask_hole_px;
-  if (wpx < 1.0) launch_ccf_n<T, 2>(c, grid, F, n_spec, M, n_lines);
-  else if (wpx < 2.0) launch_ccf_n<T, 3>(c, grid, F, n_spec, M, n_lines);
-  else if (wpx < 4.0) launch_ccf_n<T, 5>(c, grid, F, n_spec, M, n_lines);
-  else launch_ccf_n<T, 10>(c, grid, F, n_spec, M, n_lines);
+static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
+  if (c->ccf_stg <= 256) launch_ccf_s<T, 256>(c, grid, d_flux, n_spec, d_part);
+  else launch_ccf_s<T, CCF_STG_MAX>(c, grid, d_flux, n_spec, d_part);
 }
 
-hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
-                      double* d_part) {
+hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, double* d_part) {
   const int nlb = ccf_line_blocks(n_lines);
   dim3 grid(nlb, (unsigned)((n_spec + CCF_SB - 1) / CCF_SB));
-  c->ccf_part = d_part;
-  if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_mask, n_lines);
-  else launch_ccf_t<double>(c, grid, d_flux, n_spec, d_mask, n_lines);
+  if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_part);
+  else launch_ccf_t<double>(c, grid, d_flux, n_spec, d_part);
   return hipGetLastError();
 }
 
@@ -734,11 +817,6 @@ hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, in
   return launch_fit_npt(c, 1, n, d_lin, d_ccf, d_rv);
 }
 
-hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask) {
-  hipLaunchKernelGGL(k_mask_prep, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, c->ln0, c->dln,
-                     (double)c->P, d_lnl, d_w, (double2*)d_mask);
-  return hipGetLastError();
-}
 
 
 }  // namespace soap

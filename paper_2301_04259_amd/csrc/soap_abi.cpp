@@ -613,31 +613,21 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
               std::memcmp(c->mask_w.data(), mask->weight, sizeof(double) * nl) == 0;
   if (!same) {
     c->mask_valid = false;
-    HIP_TRY(grow(c->ws_mask, sizeof(double) * 4 * (size_t)nl));
-    std::vector<double> host(2 * (size_t)nl);
-    std::memcpy(host.data(), mask->ln_lambda, sizeof(double) * nl);
-    std::memcpy(host.data() + nl, mask->weight, sizeof(double) * nl);
-    double* raw = static_cast<double*>(c->ws_mask.ptr) + 2 * (size_t)nl;  // staging half
-    soap_status st = stage_to_device(c, host.data(), sizeof(double) * 2 * nl, raw);
-    if (st != SOAP_OK) return st;
-    HIP_TRY(soap::launch_mask_prep(c, raw, raw + nl, nl, static_cast<double*>(c->ws_mask.ptr)));
-    c->mask_lnl.assign(mask->ln_lambda, mask->ln_lambda + nl);
-    c->mask_w.assign(mask->weight, mask->weight + nl);
     c->mask_h = mask->half_width_kms;
     c->mask_v0 = mask->v0_kms;
     c->mask_dv = mask->dv_kms;
     c->mask_nv = mask->n_v;
-    {
-      // widest hole over the grid: the hole edges are Doppler-shifted
-      // (Eq. 6), so its width in pixels grows with |v|
-      double w = 0.0;
-      for (int k : {0, mask->n_v - 1}) {
-        const double vk = mask->v0_kms + mask->dv_kms * k;
-        w = std::max(w, (std::atanh((vk + mask->half_width_kms) / soap::C_KMS) -
-                         std::atanh((vk - mask->half_width_kms) / soap::C_KMS)) / c->dln);
-      }
-      c->mask_hole_px = w;
+    std::vector<unsigned char> blob;
+    std::string terr;
+    if (!soap::ccf_build_tables(c, mask->ln_lambda, mask->weight, nl, blob, terr)) {
+      c->err = terr;
+      return SOAP_ERR_UNSUPPORTED;
     }
+    HIP_TRY(grow(c->ws_mask, blob.size()));
+    soap_status st = stage_to_device(c, blob.data(), blob.size(), c->ws_mask.ptr);
+    if (st != SOAP_OK) return st;
+    c->mask_lnl.assign(mask->ln_lambda, mask->ln_lambda + nl);
+    c->mask_w.assign(mask->weight, mask->weight + nl);
     c->mask_valid = true;
   }
 
@@ -658,8 +648,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   }
   {
     StageTimer t(c, ST_CCF);
-    HIP_TRY(soap::launch_ccf(c, dflux, n_spec, static_cast<const double*>(c->ws_mask.ptr), nl,
-                             static_cast<double*>(c->ws_ccf.ptr)));
+    HIP_TRY(soap::launch_ccf(c, dflux, n_spec, nl, static_cast<double*>(c->ws_ccf.ptr)));
     t.done();
   }
   c->ccf_calls++;

@@ -177,8 +177,11 @@ struct soap_ctx {
   std::vector<double> mask_lnl, mask_w;
   double mask_h = 0, mask_v0 = 0, mask_dv = 0;
   double mask_hole_px = 0;  // widest hole of the velocity grid, in pixels
-  double* ccf_part = nullptr;  // partial CCFs of the launch being enqueued
   int mask_nv = 0;
+  // CCF tables of the cached mask in ws_mask (built by ccf_build_tables):
+  // byte offsets of the sections, batch count, pixels per hole, stage span
+  size_t ccf_off_edges = 0, ccf_off_batch = 0, ccf_off_bfirst = 0;
+  int ccf_nbatch = 0, ccf_npx = 2, ccf_stg = 256;
   bool mask_valid = false;
 };
 
@@ -241,8 +244,11 @@ size_t apply_batch_bytes(int n);
 hipError_t apply_batch_upload(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGroup* g);
 hipError_t apply_batch_launch(const ApplyBatchGroup& g, hipStream_t st);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
-hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, const double* d_mask, int n_lines,
-                      double* d_part);
+// host tables of a mask (soap_ctx::ws_mask layout); false with err set when
+// the velocity grid does not fit the kernel
+bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, std::vector<unsigned char>& blob,
+                      std::string& err);
+hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, double* d_part);
 // sums the partial CCFs into d_ccf and, when d_rv is not null, fits them
 hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_t n_spec, double* d_ccf,
                           soap_rv* d_rv);
@@ -252,7 +258,6 @@ hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members
                         const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
                         double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
                         int* d_fallback);
-hipError_t launch_mask_prep(soap_ctx* c, const double* d_lnl, const double* d_w, int n, double* d_mask);
 
 int ccf_line_blocks(int n_lines);
 int ccf_span_pixels(bool fp32);
