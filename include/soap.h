@@ -193,9 +193,12 @@ soap_status soap_active_spectra_jobs(soap_ctx* ctx, const soap_region* regions, 
 /* CCF of n_spec spectra flux[n_spec][n_pix] (the context's grid and float
  * type) against `mask`, then a Gaussian fit per CCF (section 4.1).
  * ccf_out[n_spec][n_v] (double, may be NULL) and rv_out[n_spec] (may be
- * NULL) are host or device memory as flagged.  The mask is uploaded and its
- * pixel overlaps precomputed on the first call with a new mask (the context
- * compares against the last one).                                            */
+ * NULL) are host or device memory as flagged.  On the first call with a new
+ * mask (the context compares against the last one) the line positions, the
+ * hole edges per velocity and the batches of nearby lines are built on the
+ * host and uploaded.  SOAP_ERR_UNSUPPORTED when a line's holes over the grid
+ * reach more than 512 pixels (the velocity span plus the pixels a hole can
+ * touch).                                                                   */
 soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device, int64_t n_spec,
                         const soap_mask* mask, double* ccf_out, int32_t ccf_on_device,
                         soap_rv* rv_out, int32_t rv_on_device);

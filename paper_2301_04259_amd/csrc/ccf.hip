@@ -278,7 +278,7 @@ constexpr int CCF_FIN_THREADS = 256;
 template <int NPT>
 __device__ void gf_eval(const double (&y)[NPT], int n_v, double v0, double dv, const double p[4],
                         double S[20]) {
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   double v[16], w[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) v[q] = w[q] = 0.0;
