@@ -1,0 +1,63 @@
+"""CCF (section 4.1, holes Doppler-shifted by Eq. 6) against the oracle over
+the kernel's shape variants: holes one to eight pixels wide, velocity grids
+wider than one thread per velocity and than the narrow stage, FP64 flux,
+mask lines near, past and far past the spectrum ends, an unsorted mask and
+a spectrum count that is not a multiple of the spectra per block.  The flux
+rows are seeded uniform values, so every pixel's contribution counts."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2301_04259_amd as L
+import workloads as W
+from oracle import ccf as OC
+
+pytestmark = pytest.mark.gpu
+
+C_KMS = 299792.458
+
+# (seed, precision, hole width in pixels, n_v, velocity span in pixels,
+#  lines past the ends, shuffled mask)
+CASES = [
+    (31, W.PREC_FP32, 1.5, 61, 40.0, False, False),
+    (32, W.PREC_FP32, 3.0, 61, 60.0, False, False),
+    (33, W.PREC_FP32, 6.0, 41, 80.0, False, False),
+    (34, W.PREC_FP32, 0.9, 300, 200.0, False, False),
+    (35, W.PREC_FP32, 0.9, 500, 300.0, False, False),
+    (36, W.PREC_FP64, 0.9, 161, 46.0, False, False),
+    (37, W.PREC_FP64, 2.5, 250, 400.0, False, False),
+    (38, W.PREC_FP32, 0.9, 161, 46.0, True, True),
+]
+
+
+@pytest.mark.parametrize("seed,prec,hole_px,n_v,span_px,edge,shuffle", CASES)
+def test_ccf_shapes_match_oracle(seed, prec, hole_px, n_v, span_px, edge, shuffle):
+    n_pix, n_spec, n_lines = 3000, 13, 70
+    star = W.make_tiny(seed, n_grid=8, n_pix=n_pix, n_mu=2, precision=prec, n_phases=1)
+    print(f"[ccf-shapes] seed {seed} prec {prec} hole {hole_px} px n_v {n_v} span {span_px} px", flush=True)
+    ctx = L.soap_grid_init(star)
+    rng = np.random.default_rng(seed)
+    px_kms = C_KMS * star.dln_lambda
+    h = 0.5 * hole_px * px_kms
+    dv = span_px * px_kms / (n_v - 1)
+    v0 = -0.5 * dv * (n_v - 1)
+    q = np.sort(rng.uniform(0.0, n_pix, n_lines))
+    if edge:
+        q[:3] = [-0.3 * span_px, -2.0, -1.0e5]
+        q[-3:] = [n_pix + 1.5, n_pix + 0.4 * span_px, n_pix + 1.0e5]
+    if shuffle:
+        q = q[rng.permutation(n_lines)]
+    ln_l = star.ln_lambda0 + (q - 0.5) * star.dln_lambda
+    mask = W.Mask(ln_l, rng.uniform(0.5, 1.5, n_lines), h, v0, dv, n_v)
+    dt = np.float64 if prec == W.PREC_FP64 else np.float32
+    flux_h = rng.uniform(0.2, 1.0, (n_spec, n_pix)).astype(dt)
+    flux = torch.from_numpy(flux_h).cuda()
+    ccf = torch.empty((n_spec, n_v), dtype=torch.float64, device="cuda")
+    L.soap_ccf_rv(ctx, flux, mask, ccf_out=ccf)
+    torch.cuda.synchronize()
+    v = W.make_velocity_grid(v0, dv, n_v)
+    c_or = OC.ccf(flux_h.astype(np.float64), star.ln_lambda0, star.dln_lambda, ln_l, mask.weight, h, v)
+    got = ccf.cpu().numpy()
+    # hole edges: ~1e-16 in ln(lambda) on either side, ~1e-10 pixel
+    rel = np.max(np.abs(got - c_or) / np.abs(c_or))
+    assert rel < 1e-9, rel
