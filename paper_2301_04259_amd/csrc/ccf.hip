@@ -18,8 +18,9 @@
 // double on the unweighted least squares of c0 - a exp(-(v - mu)^2 /
 // (2 sigma^2)); the gradient, J^T J and the second-derivative sums are wave
 // reductions, the 4 x 4 damped system is solved by Cholesky in every lane.
-// Start values: c0 = max, a = c0 - min, mu = v at the min, sigma from the
-// half-depth width.
+// Start values: c0 = max, a = c0 - min, mu at the vertex of the parabola
+// through the minimum and its neighbours, sigma from the half-depth width
+// with the crossings interpolated between samples.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -421,10 +422,35 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
     first = min(first, __shfl_xor(first, off, 64));
     last = max(last, __shfl_xor(last, off, 64));
   }
-  const double width = (last > first) ? dv * (last - first) : dv;
+  // sample i of the CCF in every lane (i uniform, 0 <= i < n_v)
+  auto at = [&](int i) {
+    double v = y[0];
+#pragma unroll
+    for (int t = 1; t < NPT; ++t)
+      if ((i >> 6) == t) v = y[t];
+    return __shfl(v, i & 63, 64);
+  };
+  // half-depth crossings interpolated between samples, and the minimum's
+  // position from the parabola through it and its neighbours
+  double xl = first, xr = last;
+  if (first > 0 && first < n_v) {
+    const double ya = at(first - 1), yb = at(first);
+    if (ya > yb) xl = (first - 1) + (ya - half) / (ya - yb);
+  }
+  if (last >= 0 && last + 1 < n_v) {
+    const double ya = at(last), yb = at(last + 1);
+    if (yb > ya) xr = last + (half - ya) / (yb - ya);
+  }
+  double kc = kmin;
+  if (kmin > 0 && kmin + 1 < n_v) {
+    const double ym = at(kmin - 1), y0 = at(kmin), yp = at(kmin + 1);
+    const double den = ym - 2.0 * y0 + yp;
+    if (den > 0.0) kc += fmin(fmax(0.5 * (ym - yp) / den, -0.5), 0.5);
+  }
+  const double width = (xr > xl) ? dv * (xr - xl) : dv;
   p[0] = c0;
   p[1] = a0;
-  p[2] = v0 + dv * kmin;
+  p[2] = v0 + dv * kc;
   p[3] = fmax(width, dv) / FWHM_PER_SIGMA;
 
   soap_rv res;
@@ -446,6 +472,14 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
         const double sig = fabs(p[3]);
         tiny = fabs(x[0]) <= 1e-10 * fabs(p[0]) && fabs(x[1]) <= 1e-10 * fabs(p[1]) &&
                fabs(x[2]) <= 1e-10 * sig && fabs(x[3]) <= 1e-10 * sig;
+        if (tiny) {
+          // a step of rounding size: take it without another pass (chi2
+          // stays that of the last evaluated point)
+          for (int q = 0; q < 4; ++q) p[q] += x[q];
+          res.status = 0;
+          ++it;
+          break;
+        }
         double pn[4];
         for (int q = 0; q < 4; ++q) pn[q] = p[q] + x[q];
         gf_eval(y, n_v, v0, dv, pn, Sn);
@@ -504,9 +538,9 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
 // converges only linearly) and falls back to H = J^T J where the full one
 // is not positive definite.  A trial step is evaluated with all its sums,
 // so an accepted step costs one pass over the CCF.  The fit has converged
-// when a step, accepted or not, moves every parameter by at most 1e-10 of
-// its scale (sigma for the centre and width; at that size a rejection only
-// reflects rounding of chi^2), or when an accepted step no longer lowers
+// when a step moves every parameter by at most 1e-10 of its scale (sigma
+// for the centre and width; at that size its chi^2 only reflects rounding,
+// so it is taken without a pass), or when an accepted step no longer lowers
 // chi^2 and moves the centre and width by at most 1e-9 sigma; a run of
 // rejected steps that drives the damping past 1e10 means no downhill step
 // exists at this precision, which is also the minimum.
