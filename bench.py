@@ -193,6 +193,26 @@ def surrogate_leg(args, L, W, np, torch):
                           hidden=args.surrogate_hidden,
                           epochs=args.surrogate_epochs, svd_subset=args.surrogate_svd_subset, alpha=args.surrogate_alpha,
                           weighting=args.surrogate_weighting, log=say)
+    res = {
+        "workload": "20000 px window at 5000 A (R=115000), 300x300 disk, 10 mu bins; stars on a grid of T_eff "
+        "4500-6500 K (50 K), i 30-90 deg (10 deg), v sin i 1-5 km/s; one spot per sample (lat, lon, radius "
+        f"0.01-0.10, contrast 0.3-0.9, phase); MLP 12-{model.hidden}-{model.hidden}-{model.k} x 4 members, "
+        f"{model.k} PCA components",
+        "stars": len(used),
+        "train_samples": train.n,
+    }
+    res.update(_surrogate_timing(S, np, torch, model, stars, mask, test))
+    res.update(info)
+    for c in stars.ctxs:
+        L.soap_destroy(c)
+    return res
+
+
+def _surrogate_timing(S, np, torch, model, stars, mask, test):
+    """RV/s of the full synthesis, of the surrogate kernels alone and of the
+    gated surrogate (fallback samples through the full synthesis inside the
+    timed region) on the same resident test samples, and the accepted
+    samples' error against the full synthesis."""
     nt = (test.n // 16) * 16
     idx = np.arange(nt)
     bufs = model.alloc(nt)
@@ -213,13 +233,7 @@ def surrogate_leg(args, L, W, np, torch):
     t_gated, (rv_s, fb, _) = timed(lambda: model.rv(test, idx, bufs), 5)
     e = np.abs(rv_s - rv_plain) * 1e5
     acc = ~fb
-    res = {
-        "workload": "20000 px window at 5000 A (R=115000), 300x300 disk, 10 mu bins; stars on a grid of T_eff "
-        "4500-6500 K (50 K), i 30-90 deg (10 deg), v sin i 1-5 km/s; one spot per sample (lat, lon, radius "
-        f"0.01-0.10, contrast 0.3-0.9, phase); MLP 12-{model.hidden}-{model.hidden}-{model.k} x 4 members, "
-        f"{model.k} PCA components",
-        "stars": len(used),
-        "train_samples": train.n,
+    return {
         "test_samples": nt,
         "plain_rv_per_s": nt / t_plain,
         "surrogate_kernels_rv_per_s": nt / t_kern,
@@ -232,9 +246,38 @@ def surrogate_leg(args, L, W, np, torch):
         "fallback_bit_exact": bool(np.array_equal(rv_s[fb], rv_plain[fb])),
         "threshold_cms": 10.0,
     }
-    res.update(info)
-    for c in stars.ctxs:
-        L.soap_destroy(c)
+
+
+def surrogate_single_leg(args, L, W, np, torch):
+    """The same comparison on one star (the 20000-pixel window star, v sin i
+    2 km/s, i = 90 deg): one full-synthesis call covers every sample, so the
+    full synthesis runs at its per-sample cost rather than at a per-star
+    call's."""
+    from paper_2301_04259_amd import surrogate as S
+
+    def say(*a):
+        print("[bench] surrogate (one star):", *a, file=sys.stderr, flush=True)
+
+    n = max(16, args.surrogate_spots // 4)
+    star = W.make_cfg5()
+    ctx = L.soap_grid_init(star)
+    train = W.cfg5_samples(n, 8, seed=5)
+    held = W.cfg5_samples(max(2, n // 10), 8, seed=6)
+    test = W.cfg5_samples(max(2, n // 10), 8, seed=7)
+    model, info = S.build(ctx, star.mask, train, held, n_components=args.surrogate_components,
+                          hidden=args.surrogate_hidden, epochs=max(1, args.surrogate_epochs // 2),
+                          svd_subset=args.surrogate_svd_subset, alpha=args.surrogate_alpha,
+                          weighting=args.surrogate_weighting, log=say)
+    res = {
+        "workload": "one star: 20000 px window at 5000 A (R=115000), 300x300 disk, 20 mu bins, v sin i 2 km/s, "
+        f"i 90 deg; one spot per sample; MLP {S.N_FEATURES}-{model.hidden}-{model.hidden}-{model.k} x 4 members, "
+        f"{model.k} PCA components",
+        "train_samples": train.n,
+        "epochs": max(1, args.surrogate_epochs // 2),
+    }
+    res.update(_surrogate_timing(S, np, torch, model, model.stars, star.mask, test))
+    res.update({k: info[k] for k in ("calib", "heldout_accepted_frac", "train_s") if k in info})
+    L.soap_destroy(ctx)
     return res
 
 
@@ -375,10 +418,12 @@ def main():
         print("[bench] batched leg", file=sys.stderr, flush=True)
         bat = batch_leg(args, L, W, np, torch)
 
-    sur = None
+    sur = sur1 = None
     if args.surrogate_spots > 0:
         print("[bench] surrogate leg", file=sys.stderr, flush=True)
         sur = surrogate_leg(args, L, W, np, torch)
+        print("[bench] surrogate leg, one star", file=sys.stderr, flush=True)
+        sur1 = surrogate_single_leg(args, L, W, np, torch)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -441,6 +486,7 @@ def main():
         "cpu_baseline": cpu,
         "batch": bat,
         "surrogate": sur,
+        "surrogate_single_star": sur1,
     }
     print(json.dumps(out))
 
