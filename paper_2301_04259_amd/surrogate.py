@@ -106,19 +106,37 @@ class Stars:
     def __init__(self):
         self.ids, self.ctxs, self.params = [], [], []
         self.row = {}
+        self._lut = None  # (sorted ids, their rows), rebuilt after add
 
     def add(self, star_id, ctx, teff_k, incl_deg, vsini_kms):
         self.row[int(star_id)] = len(self.ids)
         self.ids.append(int(star_id))
         self.ctxs.append(ctx)
         self.params.append((float(teff_k), float(incl_deg), float(vsini_kms)))
+        self._lut = None
 
     @property
     def ref(self):
         return self.ctxs[0]
 
     def rows(self, star_ids):
-        return np.array([self.row[int(s)] for s in np.asarray(star_ids).reshape(-1)], dtype=np.int32)
+        """Row of each star id (KeyError for an id not added)."""
+        if self._lut is None:
+            ids = np.fromiter(self.row.keys(), dtype=np.int64, count=len(self.row))
+            rows = np.fromiter(self.row.values(), dtype=np.int32, count=len(self.row))
+            order = np.argsort(ids, kind="stable")
+            self._lut = (ids[order], rows[order])
+        ids, rows = self._lut
+        s = np.asarray(star_ids, dtype=np.int64).reshape(-1)
+        if len(ids) == 0:
+            if len(s):
+                raise KeyError(int(s[0]))
+            return np.zeros(0, np.int32)
+        pos = np.minimum(np.searchsorted(ids, s), len(ids) - 1)
+        bad = ids[pos] != s
+        if bad.any():
+            raise KeyError(int(s[np.flatnonzero(bad)[0]]))
+        return rows[pos]
 
 
 def single_star(ctx, teff_k=5778.0):

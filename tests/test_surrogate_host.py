@@ -72,3 +72,19 @@ def test_samples_grouped_by_star_and_spot():
     t, i, v = smp.star_params(smp.star)
     assert set(np.unique(t)) <= set(W.CFG5_TEFF) and set(np.unique(i)) <= set(W.CFG5_INCL)
     assert set(np.unique(v)) <= set(W.CFG5_VSINI)
+
+
+def test_star_rows_lookup_matches_the_id_map():
+    st = S.Stars()
+    rng = np.random.default_rng(3)
+    ids = rng.permutation(5000)[:300]
+    for i, sid in enumerate(ids):
+        st.add(int(sid), None, 5000.0 + i, 60.0, 2.0)
+    q = rng.choice(ids, 2000)
+    assert np.array_equal(st.rows(q), np.array([st.row[int(v)] for v in q], dtype=np.int32))
+    st.add(int(ids[0]), None, 1.0, 1.0, 1.0)  # re-added id: the latest row wins, as in the map
+    assert st.rows([ids[0]])[0] == st.row[int(ids[0])] == 300
+    missing = int(np.setdiff1d(np.arange(5000), ids)[0])
+    with pytest.raises(KeyError):
+        st.rows([ids[1], missing])
+    assert len(S.Stars().rows([])) == 0
