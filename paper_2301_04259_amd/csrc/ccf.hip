@@ -313,12 +313,12 @@ __device__ void gf_eval(const double (&y)[NPT], int n_v, double v0, double dv, c
       w[4] += r * (-ae * z * (z - 3.0) * is2);       // (sigma, sigma)
     }
   }
-  const double tv = butterfly16(v, lane);
-  const double tw = butterfly16(w, lane);
+  const double tv = butterfly16_rows(v, lane);
+  const double tw = butterfly16_rows(w, lane);
 #pragma unroll
-  for (int q = 0; q < 15; ++q) S[q] = read_lane(tv, 4 * q);
+  for (int q = 0; q < 15; ++q) S[q] = read_lane(tv, q);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) S[15 + q] = read_lane(tw, 4 * q);
+  for (int q = 0; q < 5; ++q) S[15 + q] = read_lane(tw, q);
 }
 
 // Solves (H + lam diag(J^T J)) x = -g by Cholesky, H = J^T J (+ the

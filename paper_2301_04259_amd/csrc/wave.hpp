@@ -5,41 +5,6 @@
 
 namespace soap {
 
-// Sum v[0..15] over the 64 lanes of a wave; lane l ends with the total of
-// slot (l >> 2) & 15.  Each butterfly step sends half of the remaining slots
-// to the partner lane and keeps the other half, so the 16 sums cost 17
-// shuffles instead of 96.  The order of additions is fixed.
-__device__ __forceinline__ double butterfly16(double (&v)[16], int lane) {
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    double send = b5 ? v[i] : v[i + 8];
-    double keep = b5 ? v[i + 8] : v[i];
-    v[i] = keep + __shfl_xor(send, 32, 64);
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double send = b4 ? v[i] : v[i + 4];
-    double keep = b4 ? v[i + 4] : v[i];
-    v[i] = keep + __shfl_xor(send, 16, 64);
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    double send = b3 ? v[i] : v[i + 2];
-    double keep = b3 ? v[i + 2] : v[i];
-    v[i] = keep + __shfl_xor(send, 8, 64);
-  }
-  {
-    double send = b2 ? v[0] : v[1];
-    double keep = b2 ? v[1] : v[0];
-    v[0] = keep + __shfl_xor(send, 4, 64);
-  }
-  double s = v[0];
-  s += __shfl_xor(s, 2, 64);
-  s += __shfl_xor(s, 1, 64);
-  return s;
-}
-
 // value of a double held by one lane, in every lane (scalar registers)
 __device__ __forceinline__ double read_lane(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -70,6 +35,44 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
   v += dpp_f64<DPP_HALF_MIRROR>(v);
   v += dpp_f64<DPP_MIRROR>(v);
   return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
+}
+
+// Sum v[0..15] over the 64 lanes of a wave (all lanes active); lane l ends
+// with the total of slot l & 15.  The four in-row levels are transposed
+// butterflies on DPP exchanges, partner lanes differing in one lane-index
+// bit within the row (row mirror: bit 3, half-row mirror: bit 2, quad swaps:
+// bits 1 and 0); each level sends half of the remaining slots to the
+// partner and keeps the other half.  The last value is then added over the
+// four rows with two shuffles.  The order of additions is fixed.
+__device__ __forceinline__ double butterfly16_rows(double (&v)[16], int lane) {
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double send = b3 ? v[i] : v[i + 8];
+    const double keep = b3 ? v[i + 8] : v[i];
+    v[i] = keep + dpp_f64<DPP_MIRROR>(send);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double send = b2 ? v[i] : v[i + 4];
+    const double keep = b2 ? v[i + 4] : v[i];
+    v[i] = keep + dpp_f64<DPP_HALF_MIRROR>(send);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = b1 ? v[i] : v[i + 2];
+    const double keep = b1 ? v[i + 2] : v[i];
+    v[i] = keep + dpp_f64<DPP_QUAD>(send);
+  }
+  {
+    const double send = b0 ? v[0] : v[1];
+    const double keep = b0 ? v[1] : v[0];
+    v[0] = keep + dpp_f64<DPP_PAIR>(send);
+  }
+  double s = v[0];
+  s += __shfl_xor(s, 16, 64);
+  s += __shfl_xor(s, 32, 64);
+  return s;
 }
 
 // OR over the 64 lanes of a wave (all lanes active): in-row swaps by DPP
