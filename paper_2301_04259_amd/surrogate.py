@@ -257,10 +257,19 @@ def quiet(ctx):
 
 
 def fit_basis(D_host_subset, k):
-    """Offline principal axes of differences D = F - Q (FP64 SVD)."""
+    """Offline principal axes of differences D = F - Q (FP64 SVD).  LAPACK's
+    divide-and-conquer SVD can fail to converge on some inputs; the QR-based
+    one is tried then."""
     D = np.asarray(D_host_subset, np.float64)
+    if not np.all(np.isfinite(D)):
+        raise ValueError("fit_basis: differences are not finite")
     mean = D.mean(axis=0)
-    _, _, vt = np.linalg.svd(D - mean, full_matrices=False)
+    try:
+        _, _, vt = np.linalg.svd(D - mean, full_matrices=False)
+    except np.linalg.LinAlgError:
+        import scipy.linalg
+
+        _, _, vt = scipy.linalg.svd(D - mean, full_matrices=False, lapack_driver="gesvd")
     return mean, np.ascontiguousarray(vt[:k].T)
 
 

@@ -88,3 +88,20 @@ def test_star_rows_lookup_matches_the_id_map():
     with pytest.raises(KeyError):
         st.rows([ids[1], missing])
     assert len(S.Stars().rows([])) == 0
+
+
+def test_fit_basis_falls_back_when_the_svd_does_not_converge(monkeypatch):
+    rng = np.random.default_rng(4)
+    D = rng.standard_normal((40, 30)) @ np.diag(np.linspace(3.0, 0.1, 30))
+    mean0, V0 = S.fit_basis(D, 5)
+
+    def fail(*a, **k):
+        raise np.linalg.LinAlgError("SVD did not converge")
+
+    monkeypatch.setattr(np.linalg, "svd", fail)
+    mean1, V1 = S.fit_basis(D, 5)
+    assert np.array_equal(mean0, mean1)
+    # the same axes up to sign
+    assert np.allclose(np.abs(np.sum(V0 * V1, axis=0)), 1.0, atol=1e-10)
+    with pytest.raises(ValueError):
+        S.fit_basis(np.full((3, 4), np.nan), 2)
