@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--surrogate-spots", type=int, default=50000,
                     help="training spots of the surrogate leg (8 phases each; 0 = skip the leg)")
     ap.add_argument("--surrogate-epochs", type=int, default=100)
+    ap.add_argument("--surrogate-single-star", type=int, default=1,
+                    help="also run the one-star surrogate comparison (0 = skip)")
     ap.add_argument("--surrogate-components", type=int, default=128, help="PCA components (multiple of 32)")
     ap.add_argument("--surrogate-hidden", type=int, default=256, help="hidden width (multiple of 32)")
     ap.add_argument("--surrogate-svd-subset", type=int, default=4096)
@@ -422,8 +424,9 @@ def main():
     if args.surrogate_spots > 0:
         print("[bench] surrogate leg", file=sys.stderr, flush=True)
         sur = surrogate_leg(args, L, W, np, torch)
-        print("[bench] surrogate leg, one star", file=sys.stderr, flush=True)
-        sur1 = surrogate_single_leg(args, L, W, np, torch)
+        if args.surrogate_single_star:
+            print("[bench] surrogate leg, one star", file=sys.stderr, flush=True)
+            sur1 = surrogate_single_leg(args, L, W, np, torch)
 
     cpu = None
     if args.cpu_sample > 0:
