@@ -205,8 +205,24 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
     if (!d->spectra[t]) continue;
     HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B));
     c->d_spec[t] = static_cast<unsigned char*>(c->d_spec_base[t]) + soap::PAD_FRONT * c->esize;
-    HIP_TRY(hipMemcpy2DAsync(c->d_spec[t], row_bytes, d->spectra[t], (size_t)c->P * c->esize,
-                             (size_t)c->P * c->esize, c->B, kind, c->stream));
+    const size_t src_bytes = (size_t)c->P * c->esize * c->B;
+    const void* src = d->spectra[t];
+    void* pinned = nullptr;
+    if (kind == hipMemcpyHostToDevice) {
+      // host rows go through pinned memory, so the copy is one DMA from
+      // memory that stays valid until it has completed
+      HIP_TRY(hipHostMalloc(&pinned, src_bytes, hipHostMallocDefault));
+      std::memcpy(pinned, d->spectra[t], src_bytes);
+      src = pinned;
+    }
+    hipError_t ce = hipMemcpy2DAsync(c->d_spec[t], row_bytes, src, (size_t)c->P * c->esize,
+                                     (size_t)c->P * c->esize, c->B, kind, c->stream);
+    if (pinned) {
+      const hipError_t se = hipStreamSynchronize(c->stream);
+      (void)hipHostFree(pinned);
+      if (ce == hipSuccess) ce = se;
+    }
+    HIP_TRY(ce);
     c->has_type[t] = true;
   }
   HIP_TRY(hipMalloc((void**)&c->d_mu, sizeof(double) * c->B));
