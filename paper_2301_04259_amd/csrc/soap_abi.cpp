@@ -226,7 +226,7 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
     c->has_type[t] = true;
   }
   HIP_TRY(hipMalloc((void**)&c->d_mu, sizeof(double) * c->B));
-  HIP_TRY(hipMemcpyAsync(c->d_mu, d->mu_bins, sizeof(double) * c->B, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpy(c->d_mu, d->mu_bins, sizeof(double) * c->B, hipMemcpyHostToDevice));
   HIP_TRY(hipMalloc((void**)&c->d_col_c, sizeof(int) * c->N));
   HIP_TRY(hipMalloc((void**)&c->d_col_w, sizeof(double) * c->N));
   HIP_TRY(hipMalloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
@@ -651,7 +651,10 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   const size_t in_bytes = (size_t)n_spec * c->P * c->esize;
   if (!flux_on_device) {
     HIP_TRY(grow(c->ws_specin, in_bytes));
-    HIP_TRY(hipMemcpyAsync(c->ws_specin.ptr, flux, in_bytes, hipMemcpyHostToDevice, c->stream));
+    // through the context's pinned staging, not an asynchronous copy from
+    // pageable memory
+    soap_status st = stage_to_device(c, flux, in_bytes, c->ws_specin.ptr);
+    if (st != SOAP_OK) return st;
     dflux = c->ws_specin.ptr;
   }
   const int nlb = soap::ccf_line_blocks(nl);
