@@ -80,13 +80,12 @@ def batch_leg(args, L, W, np, torch):
     windows of the full range, 25-200 phases, T_eff 4500-6500 K, 1-4
     regions) replayed as one HIP graph; spectra per second of the whole
     batch, and the same configurations as one call each for comparison."""
-    import types
 
     def say(*a):
         print("[bench] batch:", *a, file=sys.stderr, flush=True)
 
     cfgs = W.batch_configs(args.batch_configs)
-    teffs = (4750.0, 5250.0, 5750.0, 6250.0)
+    teffs = W.BANK_TEFF
     banks = {}
     t0 = time.perf_counter()
     for t in teffs:
@@ -97,14 +96,9 @@ def batch_leg(args, L, W, np, torch):
     rng = np.random.default_rng(33)
     t0 = time.perf_counter()
     for c in cfgs:
-        tb = min(teffs, key=lambda t: abs(t - c["teff_k"]))
-        ln0, dln, mu_b, sp = banks[tb]
-        a, P = c["start"], c["n_pix"]
-        star = types.SimpleNamespace(
-            n_grid=c["n_grid"], mu_bins=mu_b, n_pix=P, vsini_kms=c["vsini_kms"], incl_deg=c["incl_deg"],
-            ld_u1=0.4, ld_u2=0.25, ln_lambda0=ln0 + a * dln, dln_lambda=dln,
-            spectra=[x[:, a:a + P].contiguous() for x in sp], precision=W.PREC_FP32,
-            contrast_mode=W.CONTRAST_PLANCK, teff_k=c["teff_k"], dt_spot_k=663.0, dt_fac_coef=W.stars.FACULA_DT_SUN)
+        star = W.batch_star(c, banks[W.bank_for(c["teff_k"])])
+        star.spectra = [x.contiguous() for x in star.spectra]
+        P = c["n_pix"]
         ctxs.append(L.soap_grid_init(star))
         regs.append(c["regions"])
         phs.append(np.sort(rng.uniform(0.0, 1.0, c["n_phases"])))

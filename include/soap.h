@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SOAP_ABI_VERSION 1
+#define SOAP_ABI_VERSION 2
 
 typedef enum {
   SOAP_OK = 0,
@@ -75,8 +75,12 @@ enum { SOAP_PREC_FP64 = 0, SOAP_PREC_FP32 = 1 };
  *   PLANCK  per pixel B_lambda(T_act) / B_lambda(T_eff), T_act = T_eff - dT_spot
  *           for spots and T_eff + dT_f(mu_b) for faculae, with
  *           dT_f(mu) = c0 + c1 mu + c2 mu^2 evaluated at the mu bin; it
- *           multiplies the spectrum after the Doppler shift                 */
-enum { SOAP_CONTRAST_SCALAR = 0, SOAP_CONTRAST_PLANCK = 1 };
+ *           multiplies the spectrum after the Doppler shift
+ *   ARRAY   per pixel and mu bin, given by the caller in
+ *           soap_star_desc.contrast (section 4.3.3, the SED and limb-brightening
+ *           factors of Eqs. 12-14: LB(mu_b) x SED_active / SED_quiet); it
+ *           multiplies the shifted active spectrum at the output pixel     */
+enum { SOAP_CONTRAST_SCALAR = 0, SOAP_CONTRAST_PLANCK = 1, SOAP_CONTRAST_ARRAY = 2 };
 
 typedef struct soap_ctx soap_ctx;
 
@@ -109,6 +113,12 @@ typedef struct {
   double teff_k;             /* PLANCK mode: quiet effective temperature    */
   double dt_spot_k;          /* PLANCK mode: spot temperature deficit       */
   double dt_fac_coef[3];     /* PLANCK mode: facula dT_f(mu) coefficients   */
+  const void* contrast[3];   /* ARRAY mode: [n_mu][n_pix] per active type,
+                                same float type and location as spectra;
+                                contrast[SOAP_QUIET] must be NULL (the quiet
+                                SED is part of the quiet spectra) and
+                                contrast[t] is required where spectra[t] is
+                                given; finite values.  NULL in other modes.  */
 } soap_star_desc;
 
 /* One circular active region (section 2.1 region parameters).  Its centre
@@ -145,8 +155,14 @@ typedef struct {
 } soap_mask;
 
 /* Result of the Gaussian fit c0 - amp exp(-(v - rv)^2 / (2 sigma^2)) of one
- * CCF (section 4.1: RV = the fitted mean).  status 0 = converged,
- * 1 = iteration limit reached, 2 = degenerate CCF.                           */
+ * CCF (section 4.1: RV = the fitted mean).  status:
+ *   0  converged;
+ *   1  iteration limit reached;
+ *   2  degenerate CCF: a non-finite sample, or no depth (max == min);
+ *   3  failed: no damped step lowers chi^2 from a point that is not a
+ *      minimum (no step was ever accepted, the sums are singular or not
+ *      finite, or the undamped Newton step there is not of rounding size).
+ * Every non-zero status means the RV is not a fitted mean.                   */
 typedef struct {
   double rv_kms;
   double fwhm_kms;           /* 2 sqrt(2 ln 2) |sigma|                      */
@@ -162,8 +178,14 @@ typedef struct {
  * device, computes the per-column Doppler shift, interpolation weights
  * (Eqs. 6, 9-11 on the log grid), the contrast arrays (PLANCK mode) and the
  * quiet integrated spectrum of Algorithm 1, all on `hip_stream` (a
- * hipStream_t; NULL = the null stream).  The context owns all device
- * workspace until soap_destroy.  On error *out is set to NULL.              */
+ * hipStream_t; NULL = the null stream).  The device copies of the spectra,
+ * contrast arrays and the quiet spectrum are then checked on the device:
+ * a non-finite value is SOAP_ERR_ARG for device inputs and SOAP_ERR_HIP
+ * (a corrupted upload) for host inputs, which are checked on the host first.
+ * SOAP_ERR_UNSUPPORTED when the limb-darkened disk weight, sum of
+ * (2/n_grid)^2 |I(mu)| over the cells, reaches 3.99 (the range of the
+ * fixed-point tap sums).  The context owns all device workspace until
+ * soap_destroy.  On error *out is set to NULL.                              */
 soap_status soap_grid_init(const soap_star_desc* desc, void* hip_stream, soap_ctx** out);
 
 /* Copies the quiet integrated spectrum (Algorithm 1) to out[n_pix].          */
@@ -173,7 +195,9 @@ soap_status soap_quiet_spectrum(soap_ctx* ctx, void* out, int32_t out_on_device)
  * (Algorithm 5, Eqs. 1-4): flux[n_phases][n_pix], row-major.  regions and
  * phases are host arrays (n_regions 0 .. 64, n_phases 1 .. 1<<20); phase is
  * in rotations (longitude advances 360 deg per unit).  Types present in
- * regions must have spectra.                                                 */
+ * regions must have spectra.  In SCALAR mode with contrasts other than one
+ * (flux and total effects), SOAP_ERR_UNSUPPORTED when the disk weight times
+ * the largest contrast reaches 3.99 (the fixed-point range of the sums).    */
 soap_status soap_active_spectra(soap_ctx* ctx, const soap_region* regions, int32_t n_regions,
                                 const double* phases, int32_t n_phases, int32_t effect,
                                 void* flux, int32_t flux_on_device);

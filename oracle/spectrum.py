@@ -23,8 +23,11 @@ Follows, in FP64:
   chromatic mode, the ratio of two Planck functions B_lambda(T_act) /
   B_lambda(T_eff) per pixel, with T_act = T_eff - dT_spot for spots and
   T_eff + dT_f(mu_b) for faculae (dT_f the facula law of section 4.3.3,
-  evaluated at the bin's mu).  It multiplies the spectrum after the shift, on
-  the common grid (Eqs. 3, 13 and 14 apply it to shifted spectra).
+  evaluated at the bin's mu), or, in the array mode, a per-pixel array per
+  (type, mu bin) given with the star (section 4.3.3, Eqs. 12-14: the limb
+  brightening times the active-to-quiet SED ratio).  It multiplies the
+  spectrum after the shift, on the common grid (Eqs. 3, 13 and 14 apply it to
+  shifted spectra).
 
 Two formulations are provided and pinned against each other:
 ``integrated_bruteforce`` walks the cells one by one exactly as Algorithms 1
@@ -39,8 +42,9 @@ import numpy as np
 from . import disk
 
 C_KMS = 299792.458
-# second radiation constant h c / k_B in m K (exact in SI 2019)
-C2_MK = 1.438776877e-2
+# second radiation constant h c / k_B in m K, from the exact SI 2019 values of
+# h, c and k_B
+C2_MK = 6.62607015e-34 * 299792458.0 / 1.380649e-23
 
 TOT, FLUX, BCONV = 0, 1, 2
 QUIET, SPOT, FACULA = 0, 1, 2
@@ -129,9 +133,11 @@ def facula_dt(mu, coef):
 
 def contrast_array(star, typ: int, b: int, lam):
     """Per-pixel contrast of surface type ``typ`` in mu bin ``b`` (chromatic
-    mode), or None in scalar mode."""
+    or array mode), or None in scalar mode."""
     if star.contrast_mode == 0:
         return None
+    if star.contrast_mode == 2:
+        return np.asarray(star.contrast[typ][b], dtype=np.float64)
     if typ == SPOT:
         return planck_ratio(lam, star.teff_k - star.dt_spot_k, star.teff_k)
     return planck_ratio(lam, star.teff_k + facula_dt(star.mu_bins[b], star.dt_fac_coef), star.teff_k)
@@ -210,7 +216,7 @@ def integrated(star, phase: float, effect: int = TOT, regions=None) -> np.ndarra
     w = wcell.copy()
     for r_idx, reg in enumerate(regions):
         sel = owner == r_idx
-        scal = 1.0 if star.contrast_mode == 1 else reg.contrast
+        scal = reg.contrast if star.contrast_mode == 0 else 1.0
         if effect == FLUX:
             con_t[sel] = reg.type
             w[sel] = wcell[sel] * scal
@@ -239,7 +245,7 @@ def integrated(star, phase: float, effect: int = TOT, regions=None) -> np.ndarra
             sh.accumulate(acc[key], wsum[col, cd], srcs[key[:2]])
     out = np.zeros(star.n_pix)
     for key, a in sorted(acc.items()):
-        if key[2] >= 0 and star.contrast_mode == 1:
+        if key[2] >= 0 and star.contrast_mode != 0:
             out += contrast_array(star, key[2], key[1], lam) * a
         else:
             out += a

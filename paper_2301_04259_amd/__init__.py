@@ -48,10 +48,11 @@ except ImportError:  # host-only use (argument checks, symbol tests)
 _lib = C.CDLL(LIB_PATH)
 
 SOAP_OK = 0
+SOAP_ERR_ARG, SOAP_ERR_OOM, SOAP_ERR_HIP, SOAP_ERR_STATE, SOAP_ERR_NOCONV, SOAP_ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 QUIET, SPOT, FACULA = 0, 1, 2
 EFFECT_TOT, EFFECT_FLUX, EFFECT_BCONV = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
-CONTRAST_SCALAR, CONTRAST_PLANCK = 0, 1
+CONTRAST_SCALAR, CONTRAST_PLANCK, CONTRAST_ARRAY = 0, 1, 2
 
 SYMBOLS = (
     "soap_grid_init",
@@ -111,6 +112,7 @@ class StarDesc(C.Structure):
         ("teff_k", C.c_double),
         ("dt_spot_k", C.c_double),
         ("dt_fac_coef", C.c_double * 3),
+        ("contrast", C.c_void_p * 3),
     ]
 
 
@@ -358,6 +360,19 @@ def soap_grid_init(star, stream=None):
     d.spectra_on_device = int(on_dev or 0)
     d.precision = int(star.precision)
     d.contrast_mode = int(getattr(star, "contrast_mode", CONTRAST_SCALAR))
+    con = getattr(star, "contrast", None) or [None, None, None]
+    for t in range(3):
+        a = con[t] if d.contrast_mode == CONTRAST_ARRAY else None
+        if a is None:
+            d.contrast[t] = None
+            continue
+        if not _is_tensor(a):
+            a = np.ascontiguousarray(a, dtype=want)
+        keep.append(a)
+        p, dev = _ptr(a)
+        if dev != d.spectra_on_device:
+            raise ValueError("contrast arrays must sit where the spectra are (host or device)")
+        d.contrast[t] = p
     d.teff_k = float(getattr(star, "teff_k", 5778.0))
     d.dt_spot_k = float(getattr(star, "dt_spot_k", 0.0))
     coef = tuple(getattr(star, "dt_fac_coef", (0.0, 0.0, 0.0)))

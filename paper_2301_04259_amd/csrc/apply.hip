@@ -100,6 +100,7 @@ struct Operands {
 template <typename T>
 struct ApplyArgs {
   int64_t P, Pstride;
+  int64_t cs_stride;  // stride of the spot contrast rows per bin (0: one row)
   int B, n_ph, n_chunks, n_tiles, effect, paired, vg_cap, vec_ok, lds_win;
   const T *Sq, *Ss, *Sf, *Cs, *Cf, *ones;
   const double* Q;
@@ -133,7 +134,7 @@ __device__ __forceinline__ void window_rows(const ApplyArgs<T>& A, int4 hr, cons
     src = sq;
   } else {
     const T* ct = A.ones;
-    if (A.Cs) ct = (t == SOAP_SPOT) ? A.Cs : A.Cf + (int64_t)b * A.Pstride;
+    if (A.Cs) ct = (t == SOAP_SPOT) ? A.Cs + (int64_t)b * A.cs_stride : A.Cf + (int64_t)b * A.Pstride;
     if (A.effect == SOAP_EFFECT_FLUX) {
       src = sq;
       con = ct;
@@ -574,7 +575,7 @@ hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, co
   lds_win = std::max(1, std::min(pl.vg_cap, lds_win));
   const unsigned char* w = static_cast<const unsigned char*>(d_win);
   if (c->prec == SOAP_PREC_FP32) {
-    ApplyArgs<float> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, 0, pl.effect, pl.paired, pl.vg_cap,
+    ApplyArgs<float> A{c->P, c->Pstride, c->con_spot_stride, c->B, pl.n_ph, pl.n_chunks, 0, pl.effect, pl.paired, pl.vg_cap,
                        vec_ok ? 1 : 0, lds_win,
                        (const float*)c->d_spec[0], (const float*)c->d_spec[1], (const float*)c->d_spec[2],
                        (const float*)c->d_con_spot, (const float*)c->d_con_fac, (const float*)c->d_ones, c->d_Q, w, d_nvg,
@@ -582,7 +583,7 @@ hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, co
     return pl.paired ? launch_apply_t<float, true, PC_F32>(c, pl, A, threads, staged, st)
                      : launch_apply_t<float, false, PC_F32>(c, pl, A, threads, staged, st);
   }
-  ApplyArgs<double> A{c->P, c->Pstride, c->B, pl.n_ph, pl.n_chunks, 0, pl.effect, pl.paired,
+  ApplyArgs<double> A{c->P, c->Pstride, c->con_spot_stride, c->B, pl.n_ph, pl.n_chunks, 0, pl.effect, pl.paired,
                       pl.vg_cap, vec_ok ? 1 : 0, lds_win,
                       (const double*)c->d_spec[0], (const double*)c->d_spec[1], (const double*)c->d_spec[2],
                       (const double*)c->d_con_spot, (const double*)c->d_con_fac, (const double*)c->d_ones, c->d_Q, w, d_nvg,
@@ -600,7 +601,7 @@ ApplyArgs<T> make_args(const ApplyBatchCfg& q) {
   soap_ctx* c = q.c;
   const bool vec_ok =
       (c->P % APPLY_R == 0) && (reinterpret_cast<uintptr_t>(q.flux) % (APPLY_R * c->esize) == 0);
-  ApplyArgs<T> A{c->P, c->Pstride, c->B, q.pl.n_ph, q.pl.n_chunks, (int)((c->P + APPLY_TILE - 1) / APPLY_TILE),
+  ApplyArgs<T> A{c->P, c->Pstride, c->con_spot_stride, c->B, q.pl.n_ph, q.pl.n_chunks, (int)((c->P + APPLY_TILE - 1) / APPLY_TILE),
                  q.pl.effect, q.pl.paired, q.pl.vg_cap, vec_ok ? 1 : 0,
                  std::max(1, std::min(q.pl.vg_cap, APPLY_LDS_WIN)),
                  (const T*)c->d_spec[0], (const T*)c->d_spec[1], (const T*)c->d_spec[2], (const T*)c->d_con_spot,

@@ -73,9 +73,9 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
                                        const int32_t* region_offsets, const double* phases,
                                        const int32_t* phase_offsets, int32_t effect, void* const* flux,
                                        void* hip_stream, soap_batch** out) {
-  auto bad = [](const std::string& m) {
+  auto bad = [](const std::string& m, soap_status st = SOAP_ERR_ARG) {
     g_batch_err = m;
-    return SOAP_ERR_ARG;
+    return st;
   };
   if (!out) return bad("out is NULL");
   *out = nullptr;
@@ -106,6 +106,7 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     }
     if (nr > 0 && !regions) return bad("regions is NULL");
     bool unit = true;
+    double cmax = 1.0;
     for (int r = r0; r < r0 + nr; ++r) {
       const soap_region& R = regions[r];
       if ((R.type != SOAP_SPOT && R.type != SOAP_FACULA) || !is_fin(R.lat_deg) || R.lat_deg < -90.0 ||
@@ -115,6 +116,7 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
         return bad(msg);
       }
       unit = unit && R.contrast == 1.0;
+      cmax = std::max(cmax, R.contrast);
     }
     for (int p = p0; p < p0 + np; ++p)
       if (!is_fin(phases[p])) return bad("a phase is not finite");
@@ -125,7 +127,13 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     soap::Plan& pl = q.pl;
     pl.n_ph = np;
     pl.effect = effect;
-    pl.paired = (c->cmode == SOAP_CONTRAST_PLANCK || effect == SOAP_EFFECT_BCONV || unit) ? 1 : 0;
+    pl.paired = (c->cmode != SOAP_CONTRAST_SCALAR || effect == SOAP_EFFECT_BCONV || unit) ? 1 : 0;
+    if (!pl.paired && !(c->disk_weight * cmax < 3.99)) {
+      // split tables scale the active rows by the contrasts: the fixed-point
+      // tap sums hold |x| < 4
+      std::snprintf(msg, sizeof msg, "configuration %d: disk weight x contrast reaches the fixed-point range", i);
+      return bad(msg, SOAP_ERR_UNSUPPORTED);
+    }
     pl.G = (pl.paired ? 2 : 3) * c->B;
     pl.n_slabs = (c->N + soap::SLAB_COLS - 1) / soap::SLAB_COLS;
     pl.n_chunks = (np + c->pc - 1) / c->pc;

@@ -453,15 +453,24 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
   p[2] = v0 + dv * kc;
   p[3] = fmax(width, dv) / FWHM_PER_SIGMA;
 
+  // every sample finite: max and min skip NaN, so test each one
+  bool bad_sample = false;
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    const int i = lane + 64 * t;
+    if (i < n_v && !isfinite(y[t])) bad_sample = true;
+  }
+  const bool any_bad = __ballot(bad_sample) != 0ull;
+
   soap_rv res;
   res.status = 0;
-  if (!(a0 > 0.0) || !isfinite(c0) || !isfinite(ymin)) {
+  if (any_bad || !(a0 > 0.0) || !isfinite(c0) || !isfinite(ymin)) {
     res.status = 2;
     res.iters = 0;
   } else {
     gf_eval(y, n_v, v0, dv, p, S);
     double lam = 1e-3;
-    int it = 0;
+    int it = 0, accepted = 0;
     res.status = 1;
     for (; it < 100; ++it) {
       double x[4];
@@ -487,6 +496,7 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
           const double dchi = S[0] - Sn[0];
           for (int q = 0; q < 4; ++q) p[q] = pn[q];
           for (int q = 0; q < 20; ++q) S[q] = Sn[q];
+          ++accepted;
           lam = (lam > 1e-9) ? lam * 0.1 : 0.0;
           const double sgn = fabs(p[3]);
           const bool floor_hit =
@@ -506,7 +516,22 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
       }
       lam = (lam > 0.0) ? lam * 10.0 : 1e-6;
       if (lam > 1e10) {
-        res.status = 0;
+        // No damped step lowers chi^2.  That is the minimum at this
+        // precision only when the point came from an accepted step and the
+        // undamped Newton step there is of rounding size (at most 1e-7 of
+        // each parameter's scale) or predicts a decrease of chi^2 / 2 below
+        // 1e-12 of chi^2; otherwise (singular or non-finite sums, no step
+        // ever accepted) the fit failed.
+        bool conv = false;
+        double xn[4];
+        if (accepted > 0 && (gf_solve(S, true, 0.0, xn) || gf_solve(S, false, 0.0, xn))) {
+          const double sg = fabs(p[3]);
+          const bool small = fabs(xn[0]) <= 1e-7 * fabs(p[0]) && fabs(xn[1]) <= 1e-7 * fabs(p[1]) &&
+                             fabs(xn[2]) <= 1e-7 * sg && fabs(xn[3]) <= 1e-7 * sg;
+          const double dec = -0.5 * (S[1] * xn[0] + S[2] * xn[1] + S[3] * xn[2] + S[4] * xn[3]);
+          conv = small || (isfinite(dec) && dec <= 1e-12 * S[0]);
+        }
+        res.status = conv ? 0 : 3;
         ++it;
         break;
       }
@@ -543,7 +568,10 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
 // so it is taken without a pass), or when an accepted step no longer lowers
 // chi^2 and moves the centre and width by at most 1e-9 sigma; a run of
 // rejected steps that drives the damping past 1e10 means no downhill step
-// exists at this precision, which is also the minimum.
+// exists at this precision, which is the minimum only when an earlier step
+// was accepted and the undamped Newton step there is of rounding size
+// (status 0); otherwise the fit failed (status 3).  A CCF with a non-finite
+// sample or no depth is degenerate (status 2).
 template <int NPT>
 __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n_spec, int n_v, double v0,
                                                              double dv, const double* __restrict__ part,

@@ -90,6 +90,19 @@ __global__ void k_pad(int64_t P, int64_t Pstride, int rows, T* __restrict__ base
   else if (m >= P) r[i] = r[PAD_FRONT + P - 1];
 }
 
+// flags a non-finite value in `rows` padded rows (and optionally Q)
+template <typename T>
+__global__ void k_check_finite(int64_t n, const T* __restrict__ base, int64_t nq, const double* __restrict__ Q,
+                               int* __restrict__ flag) {
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    bad = bad || !isfinite((double)base[i]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += stride)
+    bad = bad || !isfinite(Q[i]);
+  if (bad) flag[0] = 1;
+}
+
 // one wave64 per disk column: W[i][b] = sum_{cells of column i in bin b} A I
 template <bool KAHAN32>
 __global__ void __launch_bounds__(64) k_quiet_colsum(int N, int B, double u1, double u2,
@@ -256,6 +269,29 @@ hipError_t launch_pad(soap_ctx* c) {
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_pad_rows(soap_ctx* c, void* base, int rows) {
+  if (!base || rows <= 0) return hipSuccess;
+  dim3 grid((unsigned)((c->Pstride + 255) / 256), rows);
+  if (c->prec == SOAP_PREC_FP32)
+    hipLaunchKernelGGL(k_pad<float>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, rows, (float*)base);
+  else
+    hipLaunchKernelGGL(k_pad<double>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, rows, (double*)base);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(soap_ctx* c, const void* base, int rows, bool with_q, int* d_flag) {
+  const int64_t n = base ? (int64_t)rows * c->Pstride : 0;
+  const int64_t nq = with_q ? (int64_t)c->n_tiles * APPLY_TILE_MAX : 0;
+  if (n == 0 && nq == 0) return hipSuccess;
+  const dim3 grid(1024), block(256);
+  if (c->prec == SOAP_PREC_FP32)
+    hipLaunchKernelGGL(k_check_finite<float>, grid, block, 0, c->stream, n, (const float*)base, nq, c->d_Q, d_flag);
+  else
+    hipLaunchKernelGGL(k_check_finite<double>, grid, block, 0, c->stream, n, (const double*)base, nq, c->d_Q,
+                       d_flag);
+  return hipGetLastError();
 }
 
 hipError_t launch_quiet(soap_ctx* c) {

@@ -68,7 +68,8 @@ soap_status validate_desc(const soap_star_desc* d, std::string& err) {
             (long long)d->n_pix);
   ARG_CHECK(d->precision == SOAP_PREC_FP32 || d->precision == SOAP_PREC_FP64, "unknown precision %d",
             d->precision);
-  ARG_CHECK(d->contrast_mode == SOAP_CONTRAST_SCALAR || d->contrast_mode == SOAP_CONTRAST_PLANCK,
+  ARG_CHECK(d->contrast_mode == SOAP_CONTRAST_SCALAR || d->contrast_mode == SOAP_CONTRAST_PLANCK ||
+                d->contrast_mode == SOAP_CONTRAST_ARRAY,
             "unknown contrast_mode %d", d->contrast_mode);
   ARG_CHECK(is_finite(d->vsini_kms) && std::fabs(d->vsini_kms) < 0.1 * soap::C_KMS, "vsini_kms out of range");
   ARG_CHECK(is_finite(d->incl_deg) && d->incl_deg >= 0.0 && d->incl_deg <= 180.0, "incl_deg must be in [0, 180]");
@@ -90,6 +91,20 @@ soap_status validate_desc(const soap_star_desc* d, std::string& err) {
                                                  : all_finite_host<double>(d->spectra[t], n);
       ARG_CHECK(ok, "spectra[%d] holds a non-finite value", t);
     }
+  }
+  if (d->contrast_mode == SOAP_CONTRAST_ARRAY) {
+    ARG_CHECK(d->contrast[SOAP_QUIET] == nullptr, "contrast[SOAP_QUIET] must be NULL");
+    for (int t = 1; t < 3; ++t) {
+      ARG_CHECK(!d->spectra[t] || d->contrast[t], "contrast[%d] is required with spectra[%d]", t, t);
+      if (d->contrast[t] && !d->spectra_on_device) {
+        const size_t n = (size_t)d->n_mu * (size_t)d->n_pix;
+        bool ok = (d->precision == SOAP_PREC_FP32) ? all_finite_host<float>(d->contrast[t], n)
+                                                   : all_finite_host<double>(d->contrast[t], n);
+        ARG_CHECK(ok, "contrast[%d] holds a non-finite value", t);
+      }
+    }
+  } else {
+    for (int t = 0; t < 3; ++t) ARG_CHECK(d->contrast[t] == nullptr, "contrast[%d] must be NULL outside ARRAY mode", t);
   }
   if (d->contrast_mode == SOAP_CONTRAST_PLANCK) {
     ARG_CHECK(is_finite(d->teff_k) && d->teff_k > 100.0, "teff_k must be > 100 K");
@@ -156,6 +171,48 @@ void destroy_ctx(soap_ctx* c) {
   delete c;
 }
 
+// copies n_rows rows of P samples (host or device) into padded device rows
+// starting at dst; host rows go through pinned memory, so the copy is one
+// DMA from memory that stays valid until it has completed
+hipError_t upload_rows(soap_ctx* c, void* dst, const void* src, int n_rows, bool on_device) {
+  const size_t row_bytes = (size_t)c->Pstride * c->esize;
+  const size_t src_bytes = (size_t)c->P * c->esize * n_rows;
+  void* pinned = nullptr;
+  if (!on_device) {
+    hipError_t e = hipHostMalloc(&pinned, src_bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    std::memcpy(pinned, src, src_bytes);
+    src = pinned;
+  }
+  hipError_t ce = hipMemcpy2DAsync(dst, row_bytes, src, (size_t)c->P * c->esize, (size_t)c->P * c->esize, n_rows,
+                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+  if (pinned) {
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    (void)hipHostFree(pinned);
+    if (ce == hipSuccess) ce = se;
+  }
+  return ce;
+}
+
+// sum over the visible cells of (2/N)^2 |I(mu)|: bounds every tap and
+// column sum of the fixed-point accumulators
+double disk_weight(int N, double u1, double u2) {
+  const double area = (2.0 / N) * (2.0 / N);
+  double tot = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double x = soap::cell_coord(i, N);
+    for (int k = 0; k < N; ++k) {
+      const double y = soap::cell_coord(k, N);
+      const double r2 = x * x + y * y;
+      if (r2 < 1.0) tot += area * std::fabs(soap::limb_dark(std::sqrt(1.0 - r2), u1, u2));
+    }
+  }
+  return tot;
+}
+
+// the fixed-point tap sums hold |x| < 4 (units of 2^-61 in 64 bits)
+constexpr double FX_RANGE = 3.99;
+
 soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   c->N = d->n_grid;
   c->B = d->n_mu;
@@ -184,6 +241,12 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   c->J = c->jmax - c->jmin + 1;
   std::string& err = c->err;
   ARG_CHECK(c->J <= 64, "rotation shift of %.1f pixels exceeds the supported 30 pixels", smax);
+  c->disk_weight = disk_weight(c->N, c->u1, c->u2);
+  if (!(c->disk_weight < FX_RANGE)) {
+    setf(c->err, "limb darkening gives a disk weight of %.3f, beyond the fixed-point range of the tap sums (%.2f)",
+         c->disk_weight, FX_RANGE);
+    return SOAP_ERR_UNSUPPORTED;
+  }
   ARG_CHECK(c->P >= 2 * (int64_t)c->J + 4, "n_pix must be at least 2 * (max shift + 3) + 4");
   const size_t gj_bytes = (size_t)3 * c->B * c->J * sizeof(double) + 192 * sizeof(int);
   if (gj_bytes > 60 * 1024) {
@@ -200,29 +263,12 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   const int64_t tail = (int64_t)c->n_tiles * soap::APPLY_TILE_MAX + 2 * soap::MAX_J + 64;
   c->Pstride = ((soap::PAD_FRONT + tail + 63) / 64) * 64;
   const size_t row_bytes = (size_t)c->Pstride * c->esize;
-  hipMemcpyKind kind = d->spectra_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const bool on_dev = d->spectra_on_device != 0;
   for (int t = 0; t < 3; ++t) {
     if (!d->spectra[t]) continue;
     HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B));
     c->d_spec[t] = static_cast<unsigned char*>(c->d_spec_base[t]) + soap::PAD_FRONT * c->esize;
-    const size_t src_bytes = (size_t)c->P * c->esize * c->B;
-    const void* src = d->spectra[t];
-    void* pinned = nullptr;
-    if (kind == hipMemcpyHostToDevice) {
-      // host rows go through pinned memory, so the copy is one DMA from
-      // memory that stays valid until it has completed
-      HIP_TRY(hipHostMalloc(&pinned, src_bytes, hipHostMallocDefault));
-      std::memcpy(pinned, d->spectra[t], src_bytes);
-      src = pinned;
-    }
-    hipError_t ce = hipMemcpy2DAsync(c->d_spec[t], row_bytes, src, (size_t)c->P * c->esize,
-                                     (size_t)c->P * c->esize, c->B, kind, c->stream);
-    if (pinned) {
-      const hipError_t se = hipStreamSynchronize(c->stream);
-      (void)hipHostFree(pinned);
-      if (ce == hipSuccess) ce = se;
-    }
-    HIP_TRY(ce);
+    HIP_TRY(upload_rows(c, c->d_spec[t], d->spectra[t], c->B, on_dev));
     c->has_type[t] = true;
   }
   HIP_TRY(hipMalloc((void**)&c->d_mu, sizeof(double) * c->B));
@@ -234,9 +280,25 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE_MAX));
   HIP_TRY(hipMalloc(&c->d_ones, c->esize * c->n_tiles * soap::APPLY_TILE_MAX));
   if (c->cmode == SOAP_CONTRAST_PLANCK) {
-    HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * (c->B + 1)));
+    // one spot row for every bin, one facula row per bin
+    c->con_rows = c->B + 1;
+    HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * c->con_rows));
     c->d_con_spot = static_cast<unsigned char*>(c->d_con_base) + soap::PAD_FRONT * c->esize;
     c->d_con_fac = static_cast<unsigned char*>(c->d_con_spot) + row_bytes;
+    c->con_spot_stride = 0;
+  } else if (c->cmode == SOAP_CONTRAST_ARRAY) {
+    // the caller's rows: spot [B], then facula [B]; a type without spectra
+    // keeps rows of zeros (never read)
+    c->con_rows = 2 * c->B;
+    HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * c->con_rows));
+    c->d_con_spot = static_cast<unsigned char*>(c->d_con_base) + soap::PAD_FRONT * c->esize;
+    c->d_con_fac = static_cast<unsigned char*>(c->d_con_spot) + row_bytes * c->B;
+    c->con_spot_stride = c->Pstride;
+    for (int t = 1; t < 3; ++t) {
+      void* dst = t == SOAP_SPOT ? c->d_con_spot : c->d_con_fac;
+      if (d->contrast[t]) HIP_TRY(upload_rows(c, dst, d->contrast[t], c->B, on_dev));
+      else HIP_TRY(hipMemsetAsync(dst, 0, row_bytes * c->B - soap::PAD_FRONT * c->esize, c->stream));
+    }
   }
   HIP_TRY(hipEventCreateWithFlags(&c->pinned_done, hipEventDisableTiming));
   for (int k = 0; k < soap_ctx::NSLOT; ++k) HIP_TRY(hipEventCreateWithFlags(&c->slot_done[k], hipEventDisableTiming));
@@ -250,9 +312,37 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   HIP_TRY(soap::launch_geom(c));
   HIP_TRY(soap::launch_ones(c));
   if (c->cmode == SOAP_CONTRAST_PLANCK) HIP_TRY(soap::launch_contrast(c));
+  if (c->cmode == SOAP_CONTRAST_ARRAY) HIP_TRY(soap::launch_pad_rows(c, c->d_con_base, c->con_rows));
   HIP_TRY(soap::launch_quiet(c));
+  // the device copies must be finite: device inputs were not checked on the
+  // host, and a host input that was finite there yet is not here means the
+  // upload went wrong
+  int* d_flag = nullptr;
+  HIP_TRY(hipMalloc((void**)&d_flag, sizeof(int)));
+  int h_flag[2] = {0, 0};
+  hipError_t fe = hipMemsetAsync(d_flag, 0, sizeof(int), c->stream);
+  for (int t = 0; t < 3 && fe == hipSuccess; ++t)
+    if (c->d_spec_base[t]) fe = soap::launch_check_finite(c, c->d_spec_base[t], c->B, false, d_flag);
+  if (fe == hipSuccess && c->d_con_base) fe = soap::launch_check_finite(c, c->d_con_base, c->con_rows, false, d_flag);
+  if (fe == hipSuccess) fe = hipMemcpyAsync(&h_flag[0], d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (fe == hipSuccess) fe = hipMemsetAsync(d_flag, 0, sizeof(int), c->stream);
+  if (fe == hipSuccess) fe = soap::launch_check_finite(c, nullptr, 0, true, d_flag);
+  if (fe == hipSuccess) fe = hipMemcpyAsync(&h_flag[1], d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   // host arrays (mu bins, spectra) may be released once the call returns
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  const hipError_t se = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_flag);
+  HIP_TRY(fe);
+  HIP_TRY(se);
+  if (h_flag[0] || h_flag[1]) {
+    const char* what = h_flag[0] ? "the device copy of the local spectra or contrast arrays"
+                                 : "the quiet integrated spectrum";
+    if (on_dev) {
+      setf(c->err, "%s holds a non-finite value (device inputs)", what);
+      return SOAP_ERR_ARG;
+    }
+    setf(c->err, "%s holds a non-finite value although the host inputs are finite: the upload failed", what);
+    return SOAP_ERR_HIP;
+  }
   return SOAP_OK;
 }
 
@@ -389,7 +479,17 @@ soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regio
   pl.effect = effect;
   bool unit = true;
   for (int r = 0; r < n_regions; ++r) unit = unit && regions[r].contrast == 1.0;
-  pl.paired = (c->cmode == SOAP_CONTRAST_PLANCK || effect == SOAP_EFFECT_BCONV || unit) ? 1 : 0;
+  pl.paired = (c->cmode != SOAP_CONTRAST_SCALAR || effect == SOAP_EFFECT_BCONV || unit) ? 1 : 0;
+  if (!pl.paired) {
+    // split tables scale the active rows by the region contrasts
+    double cmax = 1.0;
+    for (int r = 0; r < n_regions; ++r) cmax = std::max(cmax, regions[r].contrast);
+    if (!(c->disk_weight * cmax < FX_RANGE)) {
+      setf(c->err, "disk weight %.3f x contrast %.3f reaches the fixed-point range of the tap sums (%.2f)",
+           c->disk_weight, cmax, FX_RANGE);
+      return SOAP_ERR_UNSUPPORTED;
+    }
+  }
   pl.G = (pl.paired ? 2 : 3) * c->B;
   pl.n_slabs = (c->N + soap::SLAB_COLS - 1) / soap::SLAB_COLS;
   pl.n_chunks = (n_phases + c->pc - 1) / c->pc;
@@ -788,7 +888,8 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
     HIP_TRY(hipMemcpy(nvg.data(), S.nvg.ptr, sizeof(int) * n_chunks, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(vg.data(), S.vg.ptr, vg.size(), hipMemcpyDeviceToHost));
     std::vector<char> src(3 * c->B, 0), con(3 * c->B, 0);
-    const bool planck = c->cmode == SOAP_CONTRAST_PLANCK;
+    const bool per_pixel = c->cmode != SOAP_CONTRAST_SCALAR;
+    const bool spot_rows = c->con_spot_stride != 0;  // one spot contrast row per bin
     for (int ch = 0; ch < n_chunks; ++ch)
       for (int v = 0; v < nvg[ch]; ++v) {
         soap::WinHead h;
@@ -828,7 +929,8 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
         if (c->last_effect == SOAP_EFFECT_FLUX) src[b] = 1;
         else src[t * c->B + b] = 1;
         // spot contrast is one array for every bin, facula one per bin
-        if (planck && c->last_effect != SOAP_EFFECT_BCONV) con[t == SOAP_SPOT ? SOAP_SPOT * c->B : t * c->B + b] = 1;
+        if (per_pixel && c->last_effect != SOAP_EFFECT_BCONV)
+          con[(t == SOAP_SPOT && !spot_rows) ? SOAP_SPOT * c->B : t * c->B + b] = 1;
       }
     for (char x : src) out->src_arrays += x;
     for (char x : con) out->con_arrays += x;

@@ -13,8 +13,9 @@
 namespace soap {
 
 constexpr double C_KMS = 299792.458;
-// second radiation constant h c / k_B, m K (exact in SI 2019)
-constexpr double C2_MK = 1.438776877e-2;
+// second radiation constant h c / k_B in m K, from the exact SI 2019 values
+// h = 6.62607015e-34 J s, c = 299792458 m/s, k_B = 1.380649e-23 J/K
+constexpr double C2_MK = 1.4387768775039337e-2;
 constexpr double DEG = 3.14159265358979323846 / 180.0;
 
 constexpr int MAX_REGIONS = 64;
@@ -121,8 +122,11 @@ struct soap_ctx {
   double* d_Kq = nullptr;                          // [B][J] quiet taps
   double* d_Q = nullptr;                           // [n_tiles * TILE]
   void* d_con_base = nullptr;
-  void* d_con_spot = nullptr;                      // [Pstride] (PLANCK)
-  void* d_con_fac = nullptr;                       // [B][Pstride] (PLANCK)
+  void* d_con_spot = nullptr;                      // [Pstride] (PLANCK) or [B][Pstride] (ARRAY)
+  void* d_con_fac = nullptr;                       // [B][Pstride] (PLANCK, ARRAY)
+  int con_rows = 0;                                // rows of d_con_base
+  int64_t con_spot_stride = 0;                     // 0: one spot row for every bin (PLANCK)
+  double disk_weight = 0.0;                        // sum over cells of (2/N)^2 |I(mu)|
   void* d_ones = nullptr;                          // [n_tiles * TILE] of 1 (no-contrast operand)
 
   // per-call workspace (grown on demand, freed by soap_destroy)
@@ -244,6 +248,12 @@ size_t apply_batch_bytes(int n);
 hipError_t apply_batch_upload(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGroup* g);
 hipError_t apply_batch_launch(const ApplyBatchGroup& g, hipStream_t st);
 hipError_t launch_q_convert(soap_ctx* c, void* out);
+// pads of `rows` padded rows starting at base (end samples held)
+hipError_t launch_pad_rows(soap_ctx* c, void* base, int rows);
+// sets *d_flag (device int, zeroed by the caller) when any of `rows` padded
+// rows at base (float or double per the context) or, with Q set, the quiet
+// spectrum holds a non-finite value
+hipError_t launch_check_finite(soap_ctx* c, const void* base, int rows, bool with_q, int* d_flag);
 // host tables of a mask (soap_ctx::ws_mask layout); false with err set when
 // the velocity grid does not fit the kernel
 bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, std::vector<unsigned char>& blob,

@@ -39,7 +39,7 @@ def test_exports_nothing_else():
 
 
 def test_abi_version_and_status_strings():
-    assert L.abi_version() == 1
+    assert L.abi_version() == 2
     assert L._lib.soap_status_string(0) == b"SOAP_OK"
     assert L._lib.soap_status_string(-1) == b"SOAP_ERR_ARG"
 
@@ -50,7 +50,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(L.RegionC) == 40
     assert ctypes.sizeof(L.MaskC) == 56
     assert L.RV_DTYPE.itemsize == 56
-    assert ctypes.sizeof(L.StarDesc) == 8 * 2 + 8 * 6 + 8 + 24 + 16 + 16 + 24
+    assert ctypes.sizeof(L.StarDesc) == 8 * 2 + 8 * 6 + 8 + 24 + 16 + 16 + 24 + 24
 
 
 def _bad(**kw):
@@ -96,5 +96,26 @@ def test_grid_init_rejects_nan_spectrum():
     q = st.spectra[0].copy()
     q[1, 17] = np.nan
     st.spectra = [q, st.spectra[1], st.spectra[2]]
+    with pytest.raises(L.SoapError, match="non-finite"):
+        L.soap_grid_init(st)
+
+
+def test_grid_init_rejects_disk_weight_beyond_fixed_point_range():
+    # I(mu) = 1 + 1.5 (1 - mu) gives a disk weight near 4.7: beyond the
+    # |x| < 4 range of the fixed-point tap sums (checked before any device call)
+    st = _bad(ld_u1=-1.5, ld_u2=0.0)
+    with pytest.raises(L.SoapError, match="fixed-point") as e:
+        L.soap_grid_init(st)
+    assert e.value.status == L.SOAP_ERR_UNSUPPORTED
+
+
+def test_grid_init_rejects_array_mode_without_rows_and_rows_outside_it():
+    st = W.make_tiny(2, n_grid=8, n_pix=256, n_mu=3, contrast_mode=W.CONTRAST_ARRAY)
+    st.contrast = [None, None, st.contrast[2]]
+    with pytest.raises(L.SoapError, match=r"contrast\[1\]"):
+        L.soap_grid_init(st)
+    st = W.make_tiny(2, n_grid=8, n_pix=256, n_mu=3, contrast_mode=W.CONTRAST_ARRAY)
+    st.contrast[2] = st.contrast[2].copy()
+    st.contrast[2][0, 5] = np.inf
     with pytest.raises(L.SoapError, match="non-finite"):
         L.soap_grid_init(st)

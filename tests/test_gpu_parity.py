@@ -75,6 +75,8 @@ TINY = [
     (4, 40, 4099, 6, W.PREC_FP32, W.CONTRAST_PLANCK, 17),
     (5, 7, 333, 2, W.PREC_FP32, W.CONTRAST_SCALAR, 1),
     (6, 64, 2048, 8, W.PREC_FP64, W.CONTRAST_PLANCK, 8),
+    (23, 29, 1777, 4, W.PREC_FP32, W.CONTRAST_ARRAY, 7),
+    (24, 20, 900, 3, W.PREC_FP64, W.CONTRAST_ARRAY, 6),
 ]
 
 

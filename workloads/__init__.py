@@ -18,6 +18,7 @@ from .stars import (  # noqa: F401
     FACULA,
     CONTRAST_SCALAR,
     CONTRAST_PLANCK,
+    CONTRAST_ARRAY,
     EFFECT_TOT,
     EFFECT_FLUX,
     EFFECT_BCONV,
@@ -37,6 +38,9 @@ from .stars import (  # noqa: F401
     CFG5_VSINI,
     make_bank,
     batch_configs,
+    batch_star,
+    bank_for,
+    BANK_TEFF,
     cfg5_samples,
     SpotSamples,
     make_tiny,

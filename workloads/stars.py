@@ -25,7 +25,7 @@ C_KMS = 299792.458
 C_MS = C_KMS * 1e3
 
 QUIET, SPOT, FACULA = 0, 1, 2
-CONTRAST_SCALAR, CONTRAST_PLANCK = 0, 1
+CONTRAST_SCALAR, CONTRAST_PLANCK, CONTRAST_ARRAY = 0, 1, 2
 EFFECT_TOT, EFFECT_FLUX, EFFECT_BCONV = 0, 1, 2
 PREC_FP64, PREC_FP32 = 0, 1
 
@@ -84,6 +84,9 @@ class StarInputs:
     phases: np.ndarray = field(default_factory=lambda: np.zeros(0))
     mask: Optional[Mask] = None
     name: str = ""
+    # CONTRAST_ARRAY mode: per active type a (B, P) array of contrasts applied
+    # after the shift (index QUIET stays None)
+    contrast: List[Optional[np.ndarray]] = field(default_factory=lambda: [None, None, None])
 
     @property
     def n_mu(self) -> int:
@@ -188,6 +191,9 @@ def input_digest(star: StarInputs) -> str:
     if star.mask is not None:
         h.update(star.mask.ln_lambda.tobytes())
         h.update(star.mask.weight.tobytes())
+    for arr in star.contrast:
+        if arr is not None:
+            h.update(np.ascontiguousarray(arr).tobytes())
     return h.hexdigest()
 
 
@@ -373,6 +379,23 @@ def make_tiny(
     order = np.argsort(-depth)[: max(2, n_lines // 2)]
     mlam = np.sort(centre[order])
     mask = Mask(np.log(mlam), rng.uniform(0.5, 1.0, len(mlam)), 0.41, -15.0, 0.5, 61)
+    contrast: List[Optional[np.ndarray]] = [None, None, None]
+    if contrast_mode == CONTRAST_ARRAY:
+        # per (type, bin): a limb-brightening factor times a smooth SED ratio
+        # with a tilt and a ripple, different in every row and pixel (drawn
+        # after everything else, so the other inputs do not depend on the mode)
+        xm = np.arange(n_pix, dtype=np.float64)
+        for t in types[1:]:
+            lb = rng.uniform(0.5, 1.3, n_mu)
+            tilt = rng.uniform(-0.3, 0.3, n_mu)
+            amp = rng.uniform(0.0, 0.05, n_mu)
+            per = rng.uniform(20.0, 200.0, n_mu)
+            ph0 = rng.uniform(0.0, 2.0 * np.pi, n_mu)
+            contrast[t] = (
+                lb[:, None]
+                * (1.0 + tilt[:, None] * (xm / n_pix - 0.5)[None, :]
+                   + amp[:, None] * np.sin(2.0 * np.pi * xm[None, :] / per[:, None] + ph0[:, None]))
+            ).astype(dt)
     return StarInputs(
         n_grid=n_grid,
         vsini_kms=vsini_kms,
@@ -393,6 +416,7 @@ def make_tiny(
         phases=phases,
         mask=mask,
         name=f"tiny seed={seed} N={n_grid} P={n_pix} B={n_mu}",
+        contrast=contrast,
     )
 
 
@@ -543,6 +567,31 @@ def batch_configs(n_cfg: int, seed: int = 3, n_pix_total: int = 205800):
             )
         )
     return out
+
+
+BANK_TEFF = (4750.0, 5250.0, 5750.0, 6250.0)
+
+
+def batch_star(cfg, bank, precision: int = PREC_FP32) -> StarInputs:
+    """The star of one batched configuration: its pixel window of the
+    nearest spectral bank (ln_lambda0, dln, mu_bins, [quiet, spot, facula]),
+    its grid, rotation and regions, limb darkening (0.4, 0.25), Planck
+    contrast at its T_eff.  Spectra stay whatever array type the bank holds
+    (sliced, not copied, for numpy banks)."""
+    ln0, dln, mu_b, sp = bank
+    a, n = cfg["start"], cfg["n_pix"]
+    return StarInputs(
+        n_grid=cfg["n_grid"], vsini_kms=cfg["vsini_kms"], incl_deg=cfg["incl_deg"], ld_u1=0.4, ld_u2=0.25,
+        ln_lambda0=ln0 + a * dln, dln_lambda=dln, n_pix=n, mu_bins=np.asarray(mu_b),
+        spectra=[x[:, a:a + n] for x in sp], precision=precision, contrast_mode=CONTRAST_PLANCK,
+        teff_k=cfg["teff_k"], dt_spot_k=663.0, dt_fac_coef=FACULA_DT_SUN, regions=list(cfg["regions"]),
+        name=f"batch N={cfg['n_grid']} P={n} T={cfg['teff_k']:.0f}",
+    )
+
+
+def bank_for(teff_k: float) -> float:
+    """T_eff of the spectral bank that serves a configuration."""
+    return min(BANK_TEFF, key=lambda t: abs(t - teff_k))
 
 
 # Star grid of the multi-star surrogate data set: T_eff on a 41-point grid
