@@ -214,6 +214,46 @@ soap_status soap_active_spectra_jobs(soap_ctx* ctx, const soap_region* regions, 
                                      const double* phases, const int32_t* phase_offsets, int32_t n_jobs,
                                      int32_t effect, void* flux, int32_t flux_on_device);
 
+/* Size evolution of an active region (section 4.2.1): a linear growing
+ * phase, a linear decaying phase, or growth and decay shaped as an
+ * asymmetric Gaussian.  Sizes are in millionths of the solar hemisphere
+ * (MSH); time t = phase x prot_days.  With d = t - t0_days:
+ *   NONE          A = size0_msh
+ *   LINEAR_GROWTH A = size0_msh + rate_msh_day d for d >= 0, size0_msh before
+ *   LINEAR_DECAY  A = max(0, size0_msh - rate_msh_day d) for d >= 0,
+ *                 size0_msh before
+ *   ASYM_GAUSS    A = size0_msh exp(-d^2 / (2 w^2)), w = sigma (1 + asym_per_day d),
+ *                 sigma = fwhm_days / (2 sqrt(2 ln 2)); A = 0 where w <= 0
+ *                 (asym_per_day > 0: fast growth, slow decay)
+ * A region of A MSH is a cap covering the fraction f = A 1e-6 of the
+ * hemisphere, 1 - cos(alpha) = f, so its radius is sin(alpha) =
+ * sqrt(f (2 - f)); a region of size 0 is absent at that time.               */
+enum { SOAP_EVOLVE_NONE = 0, SOAP_EVOLVE_LINEAR_GROWTH = 1, SOAP_EVOLVE_LINEAR_DECAY = 2,
+       SOAP_EVOLVE_ASYM_GAUSS = 3 };
+typedef struct {
+  int32_t mode;              /* SOAP_EVOLVE_*                               */
+  int32_t reserved0;
+  double t0_days;            /* start (linear) or peak (Gaussian) time      */
+  double size0_msh;          /* size at t0, > 0, below 1e6 (the hemisphere) */
+  double rate_msh_day;       /* linear modes: growth / decay rate, >= 0     */
+  double fwhm_days;          /* ASYM_GAUSS: full width at half maximum, > 0 */
+  double asym_per_day;       /* ASYM_GAUSS: asymmetry factor                */
+} soap_evolution;
+
+/* Size in MSH of a region following `law` at time t_days (NaN for an
+ * invalid law).                                                             */
+double soap_evolution_size(const soap_evolution* law, double t_days);
+
+/* Integrated spectra of a star whose active regions change size with time
+ * (section 4.2.1 with Algorithm 5): region r follows laws[r]; at phase p its
+ * radius is the cap radius of its size at t = phases[p] x prot_days (the
+ * region's own radius field is ignored), and regions of size 0 are left out.
+ * Arguments and flux layout as in soap_active_spectra; prot_days > 0.  Every
+ * row equals what soap_active_spectra gives for that phase's region list.   */
+soap_status soap_active_spectra_evolving(soap_ctx* ctx, const soap_region* regions, const soap_evolution* laws,
+                                         int32_t n_regions, const double* phases, int32_t n_phases,
+                                         double prot_days, int32_t effect, void* flux, int32_t flux_on_device);
+
 /* CCF of n_spec spectra flux[n_spec][n_pix] (the context's grid and float
  * type) against `mask`, then a Gaussian fit per CCF (section 4.1).
  * ccf_out[n_spec][n_v] (double, may be NULL) and rv_out[n_spec] (may be

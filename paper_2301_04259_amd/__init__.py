@@ -89,6 +89,8 @@ SYMBOLS = (
     "soap_surrogate_destroy",
     "soap_pca_project",
     "soap_surrogate_gate",
+    "soap_evolution_size",
+    "soap_active_spectra_evolving",
 )
 
 
@@ -451,6 +453,60 @@ def soap_active_spectra_jobs(ctx, job_regions, job_phases, effect, out, region_o
     p, dev = _ptr(out)
     st = _lib.soap_active_spectra_jobs(ctx.handle, arr.ctypes.data, roff.ctypes.data, ph.ctypes.data,
                                        poff.ctypes.data, len(roff) - 1, int(effect), p, dev)
+    _check(st, ctx.handle)
+    return out
+
+
+EVOLVE_NONE, EVOLVE_LINEAR_GROWTH, EVOLVE_LINEAR_DECAY, EVOLVE_ASYM_GAUSS = 0, 1, 2, 3
+
+
+class EvolutionC(C.Structure):
+    _fields_ = [
+        ("mode", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("t0_days", C.c_double),
+        ("size0_msh", C.c_double),
+        ("rate_msh_day", C.c_double),
+        ("fwhm_days", C.c_double),
+        ("asym_per_day", C.c_double),
+    ]
+
+
+_lib.soap_evolution_size.argtypes = [C.POINTER(EvolutionC), C.c_double]
+_lib.soap_evolution_size.restype = C.c_double
+_lib.soap_active_spectra_evolving.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                              C.c_double, C.c_int32, C.c_void_p, C.c_int32]
+_lib.soap_active_spectra_evolving.restype = C.c_int
+
+
+def _law(law):
+    e = EvolutionC()
+    e.mode = int(law["mode"])
+    e.t0_days = float(law["t0_days"])
+    e.size0_msh = float(law["size0_msh"])
+    e.rate_msh_day = float(law.get("rate_msh_day", 0.0))
+    e.fwhm_days = float(law.get("fwhm_days", 1.0))
+    e.asym_per_day = float(law.get("asym_per_day", 0.0))
+    return e
+
+
+def soap_evolution_size(law, t_days):
+    """Size in MSH of a region following ``law`` (a dict of soap_evolution's
+    fields) at time t_days."""
+    e = _law(law)
+    return float(_lib.soap_evolution_size(C.byref(e), float(t_days)))
+
+
+def soap_active_spectra_evolving(ctx, regions, laws, phases, prot_days, effect, out):
+    """Spectra of regions whose sizes follow ``laws`` (one dict per region)."""
+    ph = np.ascontiguousarray(phases, dtype=np.float64)
+    regs = _regions(regions)
+    arr = (EvolutionC * max(1, len(laws)))()
+    for i, law in enumerate(laws):
+        arr[i] = _law(law)
+    p, dev = _ptr(out)
+    st = _lib.soap_active_spectra_evolving(ctx.handle, regs, arr, len(regions), ph.ctypes.data, len(ph),
+                                           float(prot_days), int(effect), p, dev)
     _check(st, ctx.handle)
     return out
 

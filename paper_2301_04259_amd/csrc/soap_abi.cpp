@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "soap_internal.hpp"
 
@@ -688,6 +689,83 @@ SOAP_API soap_status soap_active_spectra_jobs(soap_ctx* c, const soap_region* re
       pj[p] = make_int2(region_offsets[j], region_offsets[j + 1] - region_offsets[j]);
   return active_impl(c, regions, (int32_t)n_regions, max_reg, pj.data(), phases, (int32_t)n_phases, effect, flux,
                      flux_on_device);
+}
+
+namespace {
+
+bool law_ok(const soap_evolution& e) {
+  if (!is_finite(e.t0_days) || !is_finite(e.size0_msh) || !(e.size0_msh > 0.0) || !(e.size0_msh < 1e6)) return false;
+  switch (e.mode) {
+    case SOAP_EVOLVE_NONE: return true;
+    case SOAP_EVOLVE_LINEAR_GROWTH:
+    case SOAP_EVOLVE_LINEAR_DECAY: return is_finite(e.rate_msh_day) && e.rate_msh_day >= 0.0;
+    case SOAP_EVOLVE_ASYM_GAUSS:
+      return is_finite(e.fwhm_days) && e.fwhm_days > 0.0 && is_finite(e.asym_per_day);
+  }
+  return false;
+}
+
+double law_size(const soap_evolution& e, double t) {
+  const double d = t - e.t0_days;
+  switch (e.mode) {
+    case SOAP_EVOLVE_LINEAR_GROWTH: return d >= 0.0 ? e.size0_msh + e.rate_msh_day * d : e.size0_msh;
+    case SOAP_EVOLVE_LINEAR_DECAY: return d >= 0.0 ? std::max(0.0, e.size0_msh - e.rate_msh_day * d) : e.size0_msh;
+    case SOAP_EVOLVE_ASYM_GAUSS: {
+      const double sigma = e.fwhm_days / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+      const double w = sigma * (1.0 + e.asym_per_day * d);
+      return w > 0.0 ? e.size0_msh * std::exp(-(d * d) / (2.0 * w * w)) : 0.0;
+    }
+    default: return e.size0_msh;
+  }
+}
+
+}  // namespace
+
+SOAP_API double soap_evolution_size(const soap_evolution* law, double t_days) {
+  if (!law || !law_ok(*law) || !is_finite(t_days)) return std::nan("");
+  return law_size(*law, t_days);
+}
+
+SOAP_API soap_status soap_active_spectra_evolving(soap_ctx* c, const soap_region* regions,
+                                                  const soap_evolution* laws, int32_t n_regions,
+                                                  const double* phases, int32_t n_phases, double prot_days,
+                                                  int32_t effect, void* flux, int32_t flux_on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(n_regions >= 0 && n_regions <= soap::MAX_REGIONS, "n_regions must be in [0, %d]", soap::MAX_REGIONS);
+  ARG_CHECK(n_regions == 0 || (regions != nullptr && laws != nullptr), "regions or laws is NULL");
+  ARG_CHECK(is_finite(prot_days) && prot_days > 0.0, "prot_days must be > 0");
+  soap_status st = check_common(c, phases, n_phases, effect, flux);
+  if (st != SOAP_OK) return st;
+  for (int r = 0; r < n_regions; ++r) {
+    ARG_CHECK(law_ok(laws[r]), "laws[%d] is invalid (mode, size0 in (0, 1e6), rate >= 0, fwhm > 0)", r);
+    soap_region probe = regions[r];
+    probe.radius = 0.5;  // the radius comes from the law
+    if ((st = check_region(c, probe, r, effect)) != SOAP_OK) return st;
+  }
+  // per-phase region lists: the regions of non-zero size with their radii
+  std::vector<soap_region> flat;
+  flat.reserve((size_t)n_regions * n_phases);
+  std::vector<int2> pj((size_t)n_phases);
+  int max_reg = 0;
+  for (int p = 0; p < n_phases; ++p) {
+    const double t = phases[p] * prot_days;
+    const int first = (int)flat.size();
+    for (int r = 0; r < n_regions; ++r) {
+      const double a = law_size(laws[r], t);
+      if (!(a > 0.0)) continue;
+      const double f = std::min(1.0, a * 1e-6);
+      soap_region g = regions[r];
+      g.radius = std::sqrt(f * (2.0 - f));
+      ARG_CHECK(g.radius < 1.0, "region %d reaches the whole hemisphere at phase %d", r, p);
+      flat.push_back(g);
+    }
+    pj[p] = make_int2(first, (int)flat.size() - first);
+    max_reg = std::max(max_reg, pj[p].y);
+  }
+  ARG_CHECK(flat.size() <= (size_t(1) << 22), "at most 2^22 regions over all phases");
+  return active_impl(c, flat.empty() ? regions : flat.data(), (int32_t)flat.size(), max_reg, pj.data(), phases,
+                     n_phases, effect, flux, flux_on_device);
 }
 
 SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_device, int64_t n_spec,
