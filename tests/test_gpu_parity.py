@@ -356,3 +356,20 @@ def test_cfg2_full_size_sampled_phases():
     q = torch.empty(star.n_pix, dtype=torch.float32, device="cuda")
     L.soap_quiet_spectrum(ctx, q)
     assert torch.isfinite(out).all()
+
+
+def test_bisector_injected_star_matches_oracle():
+    """Local spectra with mu-dependent bisectors injected (section 4.3.2):
+    the synthesis path is unchanged, so the rows and RVs match the oracle
+    as for any other inputs."""
+    star = W.make_bisector_star()
+    _say("bisector star")
+    ctx, out = _gpu(star, W.EFFECT_TOT)
+    m = star.mask
+    rv = L.rv_records(len(star.phases))
+    L.soap_ccf_rv(ctx, out, m, rv_out=rv)
+    torch.cuda.synchronize()
+    want = _oracle_rows(star, W.EFFECT_TOT, star.phases)
+    assert _flux_err(out.cpu().numpy(), want) <= FLUX_REL
+    _, rv_or = _rv_oracle(star, want)
+    assert np.max(np.abs(rv["rv_kms"] - rv_or)) * 1e5 < RV_CMS

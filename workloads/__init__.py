@@ -8,6 +8,7 @@ here.  The paper's own inputs (Kitt Peak atlases, PHOENIX spectra, the SOAP 2.0
 CCF mask) are not available, so line-list spectra of the same shape stand in
 for them.
 """
+from . import bisectors  # noqa: F401
 from .stars import (  # noqa: F401
     C_KMS,
     StarInputs,
@@ -44,6 +45,7 @@ from .stars import (  # noqa: F401
     cfg5_samples,
     SpotSamples,
     make_tiny,
+    make_bisector_star,
     make_velocity_grid,
     input_digest,
 )

@@ -569,6 +569,50 @@ def batch_configs(n_cfg: int, seed: int = 3, n_pix_total: int = 205800):
     return out
 
 
+def make_bisector_star(seed: int = 9, n_grid: int = 60, n_pix: int = 3000, n_mu: int = 6,
+                       precision: int = PREC_FP32, n_phases: int = 12) -> StarInputs:
+    """A star whose local spectra carry depth-dependent bisectors per mu bin
+    (section 4.3.2, synthetic shapes of workloads.bisectors): symmetric
+    Gaussian lines rendered without a shift, then the quiet rows injected
+    with a C-shaped bisector scaled by the bin's convective blueshift and the
+    spot and facula rows with the inhibited (straight) active bisector.
+    Planck contrast, a facula with a spot inside and a second spot."""
+    from . import bisectors as BI
+
+    rng = np.random.default_rng(seed)
+    dln = 1.0 / (3.0 * 115000.0)
+    ln0 = np.log(5000.0)
+    lam_hi = np.exp(ln0 + dln * (n_pix - 1))
+    n_lines = max(4, n_pix // 60)
+    centre = rng.uniform(5000.0 + 1.0, lam_hi - 1.0, n_lines)
+    depth = rng.uniform(0.2, 0.85, n_lines)
+    sigma = centre * rng.uniform(2.0, 3.5, n_lines) / C_KMS
+    gamma = np.zeros(n_lines)
+    mu_b = 1.0 - 0.9 * np.arange(n_mu) / (n_mu - 1)
+    cb = cb_law_ms(mu_b)
+    dt = np.float64 if precision == PREC_FP64 else np.float32
+    base = {
+        QUIET: _render(ln0, dln, n_pix, centre, depth, sigma, gamma, 0.0),
+        SPOT: _render(ln0, dln, n_pix, centre, np.minimum(depth * 1.3, 0.99), sigma, gamma, 0.0),
+        FACULA: _render(ln0, dln, n_pix, centre, depth, sigma, gamma, 0.0),
+    }
+    spectra = [np.stack([base[t]] * n_mu) for t in (QUIET, SPOT, FACULA)]
+    regs = [Region(FACULA, 25.0, 180.0, 0.3, 1.0), Region(SPOT, 25.0, 180.0, 0.12, 1.0),
+            Region(SPOT, -10.0, 40.0, 0.15, 1.0)]
+    order = np.argsort(-depth)[: max(2, n_lines // 2)]
+    mlam = np.sort(centre[order])
+    star = StarInputs(
+        n_grid=n_grid, vsini_kms=2.0, incl_deg=90.0, ld_u1=0.4, ld_u2=0.25, ln_lambda0=ln0, dln_lambda=dln,
+        n_pix=n_pix, mu_bins=mu_b, spectra=spectra, precision=precision, contrast_mode=CONTRAST_PLANCK,
+        teff_k=5778.0, dt_spot_k=663.0, dt_fac_coef=FACULA_DT_SUN, regions=regs,
+        phases=np.linspace(0.0, 1.0, n_phases, endpoint=False),
+        mask=Mask(np.log(mlam), np.ones(len(mlam)), 0.41, -20.0, 0.25, 161),
+        name=f"bisector star seed={seed} N={n_grid} P={n_pix} B={n_mu}",
+    )
+    star.spectra = [a.astype(dt) for a in BI.inject_star(star, cb)]
+    return star
+
+
 BANK_TEFF = (4750.0, 5250.0, 5750.0, 6250.0)
 
 
