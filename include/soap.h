@@ -254,6 +254,26 @@ soap_status soap_active_spectra_evolving(soap_ctx* ctx, const soap_region* regio
                                          int32_t n_regions, const double* phases, int32_t n_phases,
                                          double prot_days, int32_t effect, void* flux, int32_t flux_on_device);
 
+/* Resolution lowering (the last step of Algorithms 2 and 5: each final
+ * spectrum is lowered to the spectrograph's resolution).  The line-spread
+ * function is a Gaussian of full width at half maximum lambda / resolution,
+ * sigma = 1 / (resolution dln 2 sqrt(2 ln 2)) pixels on the log-uniform grid;
+ * the kernel is that Gaussian sampled at whole pixels |k| <= ceil(4 sigma)
+ * and normalised to sum 1, and out[m] = sum_k w_k in[clamp(m - k)] (end
+ * values held).  in and out are [n_spec][n_pix] in the context's float type,
+ * both host or both device memory (on_device), and must not overlap.
+ * SOAP_ERR_UNSUPPORTED when the kernel would reach more than 32 pixels each
+ * side.  Enqueues only for device memory.                                    */
+soap_status soap_instrument_lsf(soap_ctx* ctx, const void* in, void* out, int64_t n_spec, double resolution,
+                                int32_t on_device);
+
+/* Makes later soap_active_spectra, soap_active_spectra_jobs and
+ * soap_active_spectra_evolving calls on ctx return their spectra lowered to
+ * `resolution` as soap_instrument_lsf does (the synthesis goes to a context
+ * workspace first); 0 switches the lowering off (the default).  Batches
+ * (soap_batch_*) are not affected.                                           */
+soap_status soap_set_instrument(soap_ctx* ctx, double resolution);
+
 /* CCF of n_spec spectra flux[n_spec][n_pix] (the context's grid and float
  * type) against `mask`, then a Gaussian fit per CCF (section 4.1).
  * ccf_out[n_spec][n_v] (double, may be NULL) and rv_out[n_spec] (may be
@@ -375,6 +395,7 @@ typedef struct {
   double apply_ms;           /* shift-and-sum of the final spectra          */
   double ccf_ms;             /* CCF partial sums per block of mask lines    */
   double gfit_ms;            /* fixed-order sum of the partials + fits      */
+  double lsf_ms;             /* resolution lowering                         */
   int64_t active_calls;
   int64_t ccf_calls;
   int64_t src_arrays;        /* last apply: distinct local spectra read     */

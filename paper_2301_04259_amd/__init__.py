@@ -91,6 +91,8 @@ SYMBOLS = (
     "soap_surrogate_gate",
     "soap_evolution_size",
     "soap_active_spectra_evolving",
+    "soap_instrument_lsf",
+    "soap_set_instrument",
 )
 
 
@@ -149,6 +151,7 @@ class ProfileC(C.Structure):
         ("apply_ms", C.c_double),
         ("ccf_ms", C.c_double),
         ("gfit_ms", C.c_double),
+        ("lsf_ms", C.c_double),
         ("active_calls", C.c_int64),
         ("ccf_calls", C.c_int64),
         ("src_arrays", C.c_int64),
@@ -509,6 +512,29 @@ def soap_active_spectra_evolving(ctx, regions, laws, phases, prot_days, effect, 
                                            float(prot_days), int(effect), p, dev)
     _check(st, ctx.handle)
     return out
+
+
+_lib.soap_instrument_lsf.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32]
+_lib.soap_instrument_lsf.restype = C.c_int
+_lib.soap_set_instrument.argtypes = [_ctx_p, C.c_double]
+_lib.soap_set_instrument.restype = C.c_int
+
+
+def soap_instrument_lsf(ctx, flux, out, resolution):
+    """Lowers the rows of flux ([n_spec][n_pix]) to ``resolution`` into out."""
+    pi, di = _ptr(flux)
+    po, do = _ptr(out)
+    if di != do:
+        raise ValueError("flux and out must both be host arrays or both device tensors")
+    n = int(flux.shape[0]) if len(flux.shape) == 2 else 1
+    _check(_lib.soap_instrument_lsf(ctx.handle, pi, po, n, float(resolution), di), ctx.handle)
+    return out
+
+
+def soap_set_instrument(ctx, resolution):
+    """Later active-spectra calls return spectra lowered to ``resolution``
+    (0 = off)."""
+    _check(_lib.soap_set_instrument(ctx.handle, float(resolution)), ctx.handle)
 
 
 def _mask(mask):

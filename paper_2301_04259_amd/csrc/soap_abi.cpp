@@ -150,7 +150,8 @@ void destroy_ctx(soap_ctx* c) {
   void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base, c->d_ones};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
-  soap::Workspace* ws[] = {&c->ws_flux, &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin};
+  soap::Workspace* ws[] = {&c->ws_flux, &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin,
+                           &c->ws_lsf};
   for (auto* w : ws) free_ws(*w);
   for (auto& S : c->prep) {
     soap::Workspace* pw[] = {&S.par, &S.Kfx, &S.K, &S.mask64, &S.vg, &S.nvg};
@@ -389,7 +390,7 @@ struct StageTimer {
   }
 };
 
-enum { ST_WEIGHTS = 0, ST_COMPACT = 1, ST_APPLY = 2, ST_CCF = 3, ST_GFIT = 4 };
+enum { ST_WEIGHTS = 0, ST_COMPACT = 1, ST_APPLY = 2, ST_CCF = 3, ST_GFIT = 4, ST_LSF = 5 };
 
 }  // namespace
 
@@ -544,6 +545,20 @@ soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regio
     HIP_TRY(grow(c->ws_flux, out_bytes));
     dflux = c->ws_flux.ptr;
   }
+  // with resolution lowering the synthesis goes to a workspace first
+  void* dsyn = dflux;
+  const bool lower = c->lsf_resolution > 0.0;
+  if (lower && n_phases > soap::lsf_max_spectra(c->P)) {
+    setf(c->err, "resolution lowering takes at most %lld spectra per call", (long long)soap::lsf_max_spectra(c->P));
+    return SOAP_ERR_UNSUPPORTED;
+  }
+  if (lower) {
+    if (c->ws_lsf.bytes < out_bytes) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      HIP_TRY(grow(c->ws_lsf, out_bytes));
+    }
+    dsyn = c->ws_lsf.ptr;
+  }
   const int k = c->slot_next;
   c->slot_next = (k + 1) % soap_ctx::NSLOT;
   HIP_TRY(hipEventSynchronize(c->slot_done[k]));
@@ -602,10 +617,15 @@ soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regio
   HIP_TRY(hipStreamWaitEvent(c->stream, S.prep_done, 0));
   {
     StageTimer t(c, ST_APPLY);
-    HIP_TRY(soap::launch_apply(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), dflux));
+    HIP_TRY(soap::launch_apply(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), dsyn));
     t.done();
   }
   HIP_TRY(hipEventRecord(S.apply_done, c->stream));
+  if (lower) {
+    StageTimer t(c, ST_LSF);
+    HIP_TRY(soap::launch_lsf(c, c->lsf, dsyn, dflux, n_phases, c->stream));
+    t.done();
+  }
   c->last_prep = sidx;
   c->active_calls++;
   c->last_phases = n_phases;
@@ -766,6 +786,64 @@ SOAP_API soap_status soap_active_spectra_evolving(soap_ctx* c, const soap_region
   ARG_CHECK(flat.size() <= (size_t(1) << 22), "at most 2^22 regions over all phases");
   return active_impl(c, flat.empty() ? regions : flat.data(), (int32_t)flat.size(), max_reg, pj.data(), phases,
                      n_phases, effect, flux, flux_on_device);
+}
+
+SOAP_API soap_status soap_set_instrument(soap_ctx* c, double resolution) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(is_finite(resolution) && resolution >= 0.0, "resolution must be >= 0");
+  if (resolution == 0.0) {
+    c->lsf_resolution = 0.0;
+    return SOAP_OK;
+  }
+  soap::LsfPlan pl;
+  if (!soap::lsf_plan(resolution, c->dln, &pl)) {
+    setf(c->err, "resolution %.6g gives a line-spread function wider than %d pixels each side", resolution,
+         soap::LSF_KMAX);
+    return SOAP_ERR_UNSUPPORTED;
+  }
+  c->lsf = pl;
+  c->lsf_resolution = resolution;
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_instrument_lsf(soap_ctx* c, const void* in, void* out, int64_t n_spec, double resolution,
+                                         int32_t on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(in != nullptr && out != nullptr, "in or out is NULL");
+  ARG_CHECK(n_spec >= 1 && n_spec <= soap::lsf_max_spectra(c->P), "n_spec must be in [1, %lld]",
+            (long long)soap::lsf_max_spectra(c->P));
+  ARG_CHECK(is_finite(resolution) && resolution > 0.0, "resolution must be > 0");
+  const size_t bytes = (size_t)n_spec * c->P * c->esize;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+  ARG_CHECK(a + bytes <= b || b + bytes <= a, "in and out overlap");
+  soap::LsfPlan pl;
+  if (!soap::lsf_plan(resolution, c->dln, &pl)) {
+    setf(c->err, "resolution %.6g gives a line-spread function wider than %d pixels each side", resolution,
+         soap::LSF_KMAX);
+    return SOAP_ERR_UNSUPPORTED;
+  }
+  const void* din = in;
+  void* dout = out;
+  if (!on_device) {
+    HIP_TRY(grow(c->ws_specin, bytes));
+    soap_status st = stage_to_device(c, in, bytes, c->ws_specin.ptr);
+    if (st != SOAP_OK) return st;
+    din = c->ws_specin.ptr;
+    HIP_TRY(grow(c->ws_lsf, bytes));
+    dout = c->ws_lsf.ptr;
+  }
+  {
+    StageTimer t(c, ST_LSF);
+    HIP_TRY(soap::launch_lsf(c, pl, din, dout, n_spec, c->stream));
+    t.done();
+  }
+  if (!on_device) {
+    HIP_TRY(hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  return SOAP_OK;
 }
 
 SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_device, int64_t n_spec,
@@ -952,6 +1030,7 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
   out->apply_ms = c->stage_ms[ST_APPLY];
   out->ccf_ms = c->stage_ms[ST_CCF];
   out->gfit_ms = c->stage_ms[ST_GFIT];
+  out->lsf_ms = c->stage_ms[ST_LSF];
   out->active_calls = c->active_calls;
   out->ccf_calls = c->ccf_calls;
   out->src_arrays = out->con_arrays = 0;

@@ -45,6 +45,9 @@ constexpr int PC_F64 = 8;
 // the interpolation comes for free.
 constexpr int PAD_FRONT = 128;
 
+// widest line-spread function of the resolution lowering, in pixels each side
+constexpr int LSF_KMAX = 32;
+
 // Column slabs of the per-phase weight kernel (one wave per column).
 constexpr int SLAB_COLS = 4;
 constexpr int WEIGHT_WAVES = 4;
@@ -85,6 +88,13 @@ constexpr int APPLY_RANKED = 64;
 struct Workspace {
   void* ptr = nullptr;
   size_t bytes = 0;
+};
+
+// Line-spread function of the resolution lowering: w[k + K] for |k| <= K
+struct LsfPlan {
+  int K = 0;
+  double sigma = 0.0;
+  double w[2 * LSF_KMAX + 1] = {};
 };
 
 }  // namespace soap
@@ -173,8 +183,12 @@ struct soap_ctx {
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
-  double stage_ms[5] = {0, 0, 0, 0, 0};
+  double stage_ms[6] = {0, 0, 0, 0, 0, 0};
   int64_t active_calls = 0, ccf_calls = 0;
+  // resolution lowering of the synthesised spectra (0: off)
+  double lsf_resolution = 0.0;
+  soap::LsfPlan lsf;
+  soap::Workspace ws_lsf;  // synthesis output before the lowering
   int last_phases = 0, last_effect = 0, last_vg_cap = 0, last_paired = 0;
 
   // cached mask
@@ -268,6 +282,13 @@ hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members
                         const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
                         double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
                         int* d_fallback);
+
+// resolution lowering: kernel weights of a resolving power on the grid
+// (false when the kernel would be wider than LSF_KMAX pixels each side), the
+// largest spectrum count one launch takes, and the launch (in != out)
+bool lsf_plan(double resolution, double dln, LsfPlan* pl);
+int64_t lsf_max_spectra(int64_t P);
+hipError_t launch_lsf(soap_ctx* c, const LsfPlan& pl, const void* in, void* out, int64_t n_spec, hipStream_t st);
 
 int ccf_line_blocks(int n_lines);
 int ccf_span_pixels(bool fp32);
