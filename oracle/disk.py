@@ -13,6 +13,16 @@ readings used here are:
 * solid-body rotation: the line-of-sight velocity is v sin i * x, positive
   (receding) for x > 0.
 
+Section 3.4 (differential rotation): the angular velocity depends on the
+latitude theta, omega = omega_0 + omega_1 sin^2(theta).  The paper's
+"omega_1 = DIFF_ROT * PROT" contradicts its own solar numbers; the
+consistent reading is omega_1 = DIFF_ROT * omega_0 (-0.18 x 14.371 deg/day =
+-2.587 deg/day).  A cell's velocity is then scaled by omega / omega_0:
+v = v sin i * x * (1 + DIFF_ROT sin^2(theta)), with sin(theta) = y sin i +
+mu cos i the cell's height along the rotation axis, and a region advances in
+longitude at the rate of its own latitude: 360 deg * phase * (1 + DIFF_ROT
+sin^2(lat)) per unit phase (phase counts equatorial rotations).
+
 Section 4.3.2: each cell takes the local spectrum of the mu bin closest to
 its own mu (ties go to the larger mu bin, i.e. the lower index).
 
@@ -64,6 +74,20 @@ def los_velocity(x, vsini_kms: float):
     return vsini_kms * np.asarray(x, dtype=np.float64)
 
 
+def sin_latitude(y, mu, incl_deg: float):
+    """Height of a surface point (x, y, mu) along the rotation axis, whose
+    direction in the observer frame is (0, sin i, cos i)."""
+    inc = np.deg2rad(incl_deg)
+    return np.asarray(y, dtype=np.float64) * np.sin(inc) + np.asarray(mu, dtype=np.float64) * np.cos(inc)
+
+
+def cell_velocity(x, y, mu, vsini_kms: float, incl_deg: float, diff_rot: float = 0.0):
+    """Differential rotation (section 3.4): v = v sin i * x * (1 + DIFF_ROT
+    sin^2(theta)); DIFF_ROT = 0 is solid-body rotation."""
+    st = sin_latitude(y, mu, incl_deg)
+    return vsini_kms * np.asarray(x, dtype=np.float64) * (1.0 + diff_rot * st * st)
+
+
 def mu_bin(mu, mu_bins) -> np.ndarray:
     """Index of the closest mu bin; ties to the lower index."""
     mu = np.atleast_1d(np.asarray(mu, dtype=np.float64))
@@ -71,17 +95,20 @@ def mu_bin(mu, mu_bins) -> np.ndarray:
     return np.argmin(d, axis=1)
 
 
-def region_centre(lat_deg: float, lon_deg: float, phase: float, incl_deg: float) -> np.ndarray:
+def region_centre(lat_deg: float, lon_deg: float, phase: float, incl_deg: float,
+                  diff_rot: float = 0.0) -> np.ndarray:
     """Unit vector of a region centre in the observer frame (x right, y up,
     z towards the observer) at a rotation phase.
 
-    Star frame: longitude psi = lon + 360 deg * phase, latitude theta,
+    Star frame: longitude psi = lon + 360 deg * phase * (1 + DIFF_ROT
+    sin^2(lat)) (the region turns at its latitude's rate), latitude theta,
     (X, Y, Z) = (cos th sin psi, sin th, cos th cos psi), rotation axis +Y.
     Observer frame: the axis is tilted towards the observer by 90 deg - i:
     x = X, y = Y sin i - Z cos i, z = Y cos i + Z sin i.
     """
     th = np.deg2rad(lat_deg)
-    psi = np.deg2rad(lon_deg + 360.0 * phase)
+    sl = np.sin(th)
+    psi = np.deg2rad(lon_deg + 360.0 * phase * (1.0 + diff_rot * sl * sl))
     inc = np.deg2rad(incl_deg)
     X = np.cos(th) * np.sin(psi)
     Y = np.sin(th)
@@ -89,12 +116,12 @@ def region_centre(lat_deg: float, lon_deg: float, phase: float, incl_deg: float)
     return np.array([X, Y * np.sin(inc) - Z * np.cos(inc), Y * np.cos(inc) + Z * np.sin(inc)])
 
 
-def owner_map(x, y, mu, regions, phase: float, incl_deg: float) -> np.ndarray:
+def owner_map(x, y, mu, regions, phase: float, incl_deg: float, diff_rot: float = 0.0) -> np.ndarray:
     """InfoMap: index of the last listed region covering each cell, else -1."""
     x = np.asarray(x, dtype=np.float64)
     owner = np.full(x.shape, -1, dtype=np.int64)
     for r_idx, reg in enumerate(regions):
-        c = region_centre(reg.lat_deg, reg.lon_deg, phase, incl_deg)
+        c = region_centre(reg.lat_deg, reg.lon_deg, phase, incl_deg, diff_rot)
         cos_a = np.sqrt(1.0 - reg.radius * reg.radius)
         dot = x * c[0] + y * c[1] + mu * c[2]
         owner[dot >= cos_a] = r_idx

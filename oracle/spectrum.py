@@ -29,11 +29,18 @@ Follows, in FP64:
   spectrum after the shift, on the common grid (Eqs. 3, 13 and 14 apply it to
   shifted spectra).
 
-Two formulations are provided and pinned against each other:
+* Section 3.4 (differential rotation, DIFF_ROT = star.diff_rot, 0 when
+  absent): each cell's velocity is scaled by omega(theta) / omega_0 and
+  regions advance at their latitude's rate (see disk.py).
+
+Three formulations are provided and pinned against each other:
 ``integrated_bruteforce`` walks the cells one by one exactly as Algorithms 1
-and 5 do (for small grids), and ``integrated`` sums the final spectrum
-directly (no quiet-minus-difference step) with cells of one disk column
-grouped, which is exact because the velocity depends on x only.
+and 5 do (for small grids); ``integrated`` sums the final spectrum directly
+(no quiet-minus-difference step) with cells of equal velocity grouped (one
+disk column under solid-body rotation, because the velocity depends on x
+only; the cells of one exact velocity value under differential rotation);
+``integrated_pixels`` evaluates the same per-cell sum at chosen pixels only,
+for workloads too large for the full spectrum.
 """
 from __future__ import annotations
 
@@ -147,6 +154,18 @@ def _spec(star, typ, b):
     return np.asarray(star.spectra[typ][b], dtype=np.float64)
 
 
+def _diff_rot(star) -> float:
+    return float(getattr(star, "diff_rot", 0.0) or 0.0)
+
+
+def _velocities(star, x, y, mu):
+    """Per-cell line-of-sight velocity: solid body, or differential rotation."""
+    a = _diff_rot(star)
+    if a == 0.0:
+        return disk.los_velocity(x, star.vsini_kms)
+    return disk.cell_velocity(x, y, mu, star.vsini_kms, star.incl_deg, a)
+
+
 def quiet_bruteforce(star) -> np.ndarray:
     """Algorithm 1, one cell at a time."""
     lam = wavelengths(star.ln_lambda0, star.dln_lambda, star.n_pix)
@@ -154,10 +173,10 @@ def quiet_bruteforce(star) -> np.ndarray:
     area = disk.cell_area(star.n_grid)
     inten = disk.limb_darkening(mu, star.ld_u1, star.ld_u2)
     bins = disk.mu_bin(mu, star.mu_bins)
+    vel = _velocities(star, x, y, mu)
     out = np.zeros(star.n_pix)
     for c in range(len(x)):
-        v = disk.los_velocity(x[c], star.vsini_kms)
-        out += area * inten[c] * shift_spectrum(_spec(star, QUIET, bins[c]), lam, v)
+        out += area * inten[c] * shift_spectrum(_spec(star, QUIET, bins[c]), lam, vel[c])
     return out
 
 
@@ -170,13 +189,14 @@ def integrated_bruteforce(star, phase: float, effect: int = TOT, regions=None) -
     area = disk.cell_area(star.n_grid)
     inten = disk.limb_darkening(mu, star.ld_u1, star.ld_u2)
     bins = disk.mu_bin(mu, star.mu_bins)
-    owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg)
+    owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg, _diff_rot(star))
+    vel = _velocities(star, x, y, mu)
     s_quiet = quiet_bruteforce(star)
     diff = np.zeros(star.n_pix)
     for c in np.nonzero(owner >= 0)[0]:
         reg = regions[owner[c]]
         b = bins[c]
-        v = disk.los_velocity(x[c], star.vsini_kms)
+        v = vel[c]
         w = area * inten[c]
         sq = w * shift_spectrum(_spec(star, QUIET, b), lam, v)
         sa = w * shift_spectrum(_spec(star, reg.type, b), lam, v)
@@ -207,7 +227,7 @@ def integrated(star, phase: float, effect: int = TOT, regions=None) -> np.ndarra
     area = disk.cell_area(star.n_grid)
     inten = disk.limb_darkening(mu, star.ld_u1, star.ld_u2)
     bins = disk.mu_bin(mu, star.mu_bins)
-    owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg)
+    owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg, _diff_rot(star))
     wcell = area * inten
     # per cell: the (source type, bin, contrast type or -1) its term uses and
     # its weight, then summed per (column, key)
@@ -229,13 +249,21 @@ def integrated(star, phase: float, effect: int = TOT, regions=None) -> np.ndarra
     nb = len(star.mu_bins)
     code = (src_t * nb + bins) * 4 + (con_t + 1)
     ncode = 3 * nb * 4
-    n = star.n_grid
-    wsum = np.bincount(ix * ncode + code, weights=w, minlength=n * ncode).reshape(n, ncode)
+    if _diff_rot(star) == 0.0:
+        # one velocity per disk column
+        n = star.n_grid
+        group = ix
+        xs = disk.cell_centres(n)
+        gvel = disk.los_velocity(xs, star.vsini_kms)
+    else:
+        # one group per distinct cell velocity
+        gvel, group = np.unique(_velocities(star, x, y, mu), return_inverse=True)
+        n = len(gvel)
+    wsum = np.bincount(group * ncode + code, weights=w, minlength=n * ncode).reshape(n, ncode)
     acc = {}
     srcs = {}
-    xs = disk.cell_centres(n)
     for col in np.nonzero(wsum.any(axis=1))[0]:
-        sh = Shift(lam, disk.los_velocity(xs[col], star.vsini_kms))
+        sh = Shift(lam, gvel[col])
         for cd in np.nonzero(wsum[col])[0]:
             key = (int(cd // 4 // nb), int(cd // 4 % nb), int(cd % 4) - 1)
             if key[:2] not in srcs:
@@ -249,6 +277,83 @@ def integrated(star, phase: float, effect: int = TOT, regions=None) -> np.ndarra
             out += contrast_array(star, key[2], key[1], lam) * a
         else:
             out += a
+    return out
+
+
+def integrated_pixels(star, phase: float, pixels, effect: int = TOT, regions=None) -> np.ndarray:
+    """The final spectrum of ``integrated`` at the chosen output pixels only:
+    every visible cell's term evaluated at each pixel m by Eqs. 9-11 (the
+    bracketing n with lambda'_n <= lambda_m < lambda'_{n+1} found among the
+    shifted wavelengths around m, end values held), times its weight and,
+    for active cells, its contrast at m."""
+    regions = star.regions if regions is None else regions
+    pixels = np.asarray(pixels, dtype=np.int64)
+    p = star.n_pix
+    lam = wavelengths(star.ln_lambda0, star.dln_lambda, p)
+    _, _, x, y, mu = disk.disk_cells(star.n_grid)
+    area = disk.cell_area(star.n_grid)
+    inten = disk.limb_darkening(mu, star.ld_u1, star.ld_u2)
+    bins = disk.mu_bin(mu, star.mu_bins)
+    owner = disk.owner_map(x, y, mu, regions, phase, star.incl_deg, _diff_rot(star))
+    fac = doppler_factor(_velocities(star, x, y, mu))
+    nb = len(star.mu_bins)
+    # per cell: source row (type, bin), contrast kind and weight, as in integrated
+    src_t = np.zeros(len(x), dtype=np.int64)
+    con_t = np.full(len(x), -1, dtype=np.int64)
+    w = area * inten
+    for r_idx, reg in enumerate(regions):
+        sel = owner == r_idx
+        scal = reg.contrast if star.contrast_mode == 0 else 1.0
+        if effect == FLUX:
+            con_t[sel] = reg.type
+            w[sel] = w[sel] * scal
+        elif effect == BCONV:
+            src_t[sel] = reg.type
+        else:
+            src_t[sel] = reg.type
+            con_t[sel] = reg.type
+            w[sel] = w[sel] * scal
+    rows = np.zeros((3, nb, p))
+    for t in range(3):
+        if star.spectra[t] is not None:
+            rows[t] = np.asarray(star.spectra[t], dtype=np.float64)
+    row_of = src_t * nb + bins
+    flat = rows.reshape(3 * nb, p)
+    # contrast at the output pixels per (type, bin), 1 where none applies
+    cons = np.ones((3, nb, len(pixels)))
+    if star.contrast_mode != 0 and effect != BCONV:
+        for t in (SPOT, FACULA):
+            for b in range(nb):
+                ca = contrast_array(star, t, b, lam)
+                if ca is not None:
+                    cons[t, b] = ca[pixels]
+    half = int(np.ceil(np.max(np.abs(np.log(fac))) / star.dln_lambda)) + 3
+    out = np.zeros(len(pixels))
+    for i, m in enumerate(pixels):
+        n0 = max(0, m - half)
+        n1 = min(p - 1, m + half)
+        cand = np.arange(n0, n1 + 1)
+        lam_s = lam[cand][None, :] * fac[:, None]  # lambda'_n per cell
+        k = (lam_s <= lam[m]).sum(axis=1) - 1  # index in cand of the last lambda'_n <= lambda_m
+        n = n0 + k
+        val = np.empty(len(x))
+        lo = n < 0
+        hi = n >= p - 1
+        mid = ~(lo | hi)
+        rm = row_of[mid]
+        nm = n[mid]
+        ls = lam_s[mid]
+        km = k[mid]
+        a = ls[np.arange(len(km)), km]
+        b = ls[np.arange(len(km)), km + 1]
+        frac = (lam[m] - a) / (b - a)
+        s_lo = flat[rm, nm]
+        s_hi = flat[rm, nm + 1]
+        val[mid] = (s_hi - s_lo) * frac + s_lo
+        val[lo] = flat[row_of[lo], 0]
+        val[hi] = flat[row_of[hi], p - 1]
+        cvec = np.where(con_t >= 0, cons[np.maximum(con_t, 0), bins, i], 1.0)
+        out[i] = np.sum(w * cvec * val)
     return out
 
 

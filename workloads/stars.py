@@ -87,6 +87,8 @@ class StarInputs:
     # CONTRAST_ARRAY mode: per active type a (B, P) array of contrasts applied
     # after the shift (index QUIET stays None)
     contrast: List[Optional[np.ndarray]] = field(default_factory=lambda: [None, None, None])
+    # differential rotation (section 3.4): omega = omega_0 (1 + diff_rot sin^2 latitude)
+    diff_rot: float = 0.0
 
     @property
     def n_mu(self) -> int:
@@ -194,6 +196,8 @@ def input_digest(star: StarInputs) -> str:
     for arr in star.contrast:
         if arr is not None:
             h.update(np.ascontiguousarray(arr).tobytes())
+    if star.diff_rot:
+        h.update(np.float64(star.diff_rot).tobytes())
     return h.hexdigest()
 
 
