@@ -88,7 +88,8 @@ typedef struct soap_ctx soap_ctx;
  * x_i = -1 + (2i+1)/n_grid (same for y); a cell is on the disk when
  * x^2 + y^2 < 1; mu = sqrt(1 - x^2 - y^2); weight (2/n_grid)^2 * I(mu) with
  * I(mu) = 1 - ld_u1 (1-mu) - ld_u2 (1-mu)^2; line-of-sight velocity
- * vsini_kms * x (receding for x > 0).  Wavelength grid: log-uniform,
+ * vsini_kms * x (receding for x > 0) under solid-body rotation (diff_rot
+ * below for differential rotation).  Wavelength grid: log-uniform,
  * ln(lambda_m / Angstrom) = ln_lambda0 + m * dln_lambda, m = 0..n_pix-1.
  * Local spectra: spectra[t] holds n_mu rows of n_pix samples, row b for the
  * mu bin mu_bins[b]; a cell takes the row of the closest mu bin (ties to the
@@ -119,10 +120,20 @@ typedef struct {
                                 SED is part of the quiet spectra) and
                                 contrast[t] is required where spectra[t] is
                                 given; finite values.  NULL in other modes.  */
+  double diff_rot;           /* differential rotation (section 3.4), |x| < 1:
+                                omega(theta) = omega_0 (1 + diff_rot
+                                sin^2 theta), theta the latitude; 0 = solid
+                                body.  A cell's velocity becomes
+                                vsini_kms x (1 + diff_rot sin^2 theta) with
+                                sin theta = y sin i + mu cos i, and a region
+                                advances 360 deg x phase x (1 + diff_rot
+                                sin^2 lat) in longitude.  With it, n_mu times
+                                the shift range (2 max|s| + 4) is at most 512 */
 } soap_star_desc;
 
 /* One circular active region (section 2.1 region parameters).  Its centre
- * sits at latitude lat_deg and longitude lon_deg + 360 deg * phase; the cap
+ * sits at latitude lat_deg and longitude lon_deg + 360 deg * phase (times
+ * 1 + diff_rot sin^2 lat_deg under differential rotation); the cap
  * has angular radius asin(radius).  Regions are written into the disk map in
  * list order, so the last listed region covering a cell owns it
  * (section 3.3).  contrast is the scalar I_active / I_quiet used in

@@ -117,6 +117,7 @@ class StarDesc(C.Structure):
         ("dt_spot_k", C.c_double),
         ("dt_fac_coef", C.c_double * 3),
         ("contrast", C.c_void_p * 3),
+        ("diff_rot", C.c_double),
     ]
 
 
@@ -383,6 +384,7 @@ def soap_grid_init(star, stream=None):
     coef = tuple(getattr(star, "dt_fac_coef", (0.0, 0.0, 0.0)))
     for i in range(3):
         d.dt_fac_coef[i] = float(coef[i])
+    d.diff_rot = float(getattr(star, "diff_rot", 0.0) or 0.0)
     h = _ctx_p()
     st = _lib.soap_grid_init(C.byref(d), _stream_handle(stream), C.byref(h))
     _check(st, None)

@@ -194,6 +194,56 @@ __global__ void k_quiet_collapse(int N, int B, int jmin, int J, const int* __res
   Kq[t] = acc;
 }
 
+// Differential rotation: quiet taps K[b][j] from per-cell shifts.  One wave
+// per disk column; each visible cell splits A I(mu) onto its two offsets
+// (Eq. 11) in an LDS table [B][J] of exact 64-bit fixed-point sums, which the
+// wave adds to the global fixed-point table (order-free, so the totals repeat
+// bit for bit).
+__global__ void __launch_bounds__(64) k_quiet_dr(int N, int B, int J, int jmin, double u1, double u2,
+                                                 double vsini, double diff_rot, double sin_i, double cos_i,
+                                                 double dln, const double* __restrict__ mu_b,
+                                                 unsigned long long* __restrict__ Kfx) {
+  extern __shared__ unsigned long long s_q[];  // [B * J]
+  const int i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int BJ = B * J;
+  for (int e = lane; e < BJ; e += 64) s_q[e] = 0ull;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const double x = cell_coord(i, N);
+  const double area = (2.0 / N) * (2.0 / N);
+  for (int k = lane; k < N; k += 64) {
+    const double y = cell_coord(k, N);
+    double r2;
+    {
+#pragma clang fp contract(off)
+      r2 = x * x + y * y;
+    }
+    if (!(r2 < 1.0)) continue;
+    const double mu = sqrt(1.0 - r2);
+    const int b = nearest_bin(mu, mu_b, B);
+    int cc;
+    double w;
+    cell_shift(x, y, mu, vsini, diff_rot, sin_i, cos_i, dln, &cc, &w);
+    const int ja = cc - jmin, jb = cc - 1 - jmin;
+    if (jb < 0 || ja >= J) continue;  // unreachable: the offset range bounds every shift
+    const double aw = area * limb_dark(mu, u1, u2);
+    atomicAdd(&s_q[b * J + ja], (unsigned long long)__double2ll_rn((1.0 - w) * aw * FX_ONE));
+    atomicAdd(&s_q[b * J + jb], (unsigned long long)__double2ll_rn(w * aw * FX_ONE));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int e = lane; e < BJ; e += 64) {
+    const unsigned long long v = s_q[e];
+    if (v) atomicAdd(Kfx + e, v);
+  }
+}
+
+__global__ void k_quiet_dr_convert(int n, const unsigned long long* __restrict__ Kfx, double* __restrict__ Kq) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) Kq[t] = (double)(long long)Kfx[t] * FX_INV;
+}
+
 template <typename T>
 __global__ void k_quiet(int64_t P, int64_t Pstride, int64_t Qlen, int B, int jmin, int J,
                         const double* __restrict__ Kq, const T* __restrict__ S, double* __restrict__ Q) {
@@ -295,6 +345,26 @@ hipError_t launch_check_finite(soap_ctx* c, const void* base, int rows, bool wit
 }
 
 hipError_t launch_quiet(soap_ctx* c) {
+  if (c->diff_rot != 0.0) {
+    const int nt = c->B * c->J;
+    hipLaunchKernelGGL(k_quiet_dr, dim3(c->N), dim3(64), (size_t)nt * sizeof(unsigned long long), c->stream, c->N,
+                       c->B, c->J, c->jmin, c->u1, c->u2, c->vsini, c->diff_rot, c->sin_i, c->cos_i, c->dln, c->d_mu,
+                       c->d_Kq_fx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_quiet_dr_convert, dim3((nt + 255) / 256), dim3(256), 0, c->stream, nt, c->d_Kq_fx, c->d_Kq);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t qlen = (int64_t)c->n_tiles * APPLY_TILE_MAX;
+    dim3 grid((unsigned)((qlen + 255) / 256));
+    if (c->prec == SOAP_PREC_FP32)
+      hipLaunchKernelGGL(k_quiet<float>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, qlen, c->B, c->jmin,
+                         c->J, c->d_Kq, (const float*)c->d_spec[SOAP_QUIET], c->d_Q);
+    else
+      hipLaunchKernelGGL(k_quiet<double>, grid, dim3(256), 0, c->stream, c->P, c->Pstride, qlen, c->B, c->jmin,
+                         c->J, c->d_Kq, (const double*)c->d_spec[SOAP_QUIET], c->d_Q);
+    return hipGetLastError();
+  }
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_quiet_colsum<true>, dim3(c->N), dim3(64), 0, c->stream, c->N, c->B, c->u1, c->u2,
                        c->d_mu, c->d_colW);

@@ -75,6 +75,7 @@ soap_status validate_desc(const soap_star_desc* d, std::string& err) {
   ARG_CHECK(is_finite(d->vsini_kms) && std::fabs(d->vsini_kms) < 0.1 * soap::C_KMS, "vsini_kms out of range");
   ARG_CHECK(is_finite(d->incl_deg) && d->incl_deg >= 0.0 && d->incl_deg <= 180.0, "incl_deg must be in [0, 180]");
   ARG_CHECK(is_finite(d->ld_u1) && is_finite(d->ld_u2), "limb-darkening coefficients must be finite");
+  ARG_CHECK(is_finite(d->diff_rot) && std::fabs(d->diff_rot) < 1.0, "diff_rot must be in (-1, 1)");
   ARG_CHECK(is_finite(d->ln_lambda0), "ln_lambda0 must be finite");
   ARG_CHECK(is_finite(d->dln_lambda) && d->dln_lambda > 0.0 && d->dln_lambda < 1.0, "dln_lambda must be in (0, 1)");
   ARG_CHECK(d->mu_bins != nullptr, "mu_bins is NULL");
@@ -147,7 +148,7 @@ void destroy_ctx(soap_ctx* c) {
   }
   for (int t = 0; t < 3; ++t)
     if (c->d_spec_base[t]) (void)hipFree(c->d_spec_base[t]);
-  void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Q, c->d_con_base, c->d_ones};
+  void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Kq_fx, c->d_Q, c->d_con_base, c->d_ones};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   soap::Workspace* ws[] = {&c->ws_flux, &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin,
@@ -225,6 +226,9 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   c->u2 = d->ld_u2;
   c->ln0 = d->ln_lambda0;
   c->dln = d->dln_lambda;
+  c->diff_rot = d->diff_rot;
+  c->sin_i = std::sin(c->incl * soap::DEG);
+  c->cos_i = std::cos(c->incl * soap::DEG);
   c->prec = d->precision;
   c->cmode = d->contrast_mode;
   c->teff = d->teff_k;
@@ -236,8 +240,11 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   // tap offset range: a bound on the column shifts |s| <= atanh(|vsini| x_max / c) / dln
   // with one offset of margin on each side, so rounding of the device's
   // own shift can never leave the table
+  // (differential rotation scales a cell's velocity by 1 + diff_rot sin^2,
+  // at most max(1, 1 + diff_rot) in size)
   const double xmax = 1.0 - 1.0 / c->N;
-  const double smax = std::atanh(std::fabs(c->vsini) * xmax / soap::C_KMS) / c->dln;
+  const double vscale = std::max(1.0, 1.0 + c->diff_rot);
+  const double smax = std::atanh(std::fabs(c->vsini) * xmax * vscale / soap::C_KMS) / c->dln;
   c->jmin = -(int)std::floor(smax) - 2;
   c->jmax = (int)std::ceil(smax) + 1;
   c->J = c->jmax - c->jmin + 1;
@@ -250,6 +257,11 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
     return SOAP_ERR_UNSUPPORTED;
   }
   ARG_CHECK(c->P >= 2 * (int64_t)c->J + 4, "n_pix must be at least 2 * (max shift + 3) + 4");
+  if (c->diff_rot != 0.0 && 3 * c->B * c->J > soap::DR_TAB_MAX) {
+    setf(c->err, "differential rotation supports n_mu x shift range up to %d, got %d x %d", soap::DR_TAB_MAX / 3,
+         c->B, c->J);
+    return SOAP_ERR_UNSUPPORTED;
+  }
   const size_t gj_bytes = (size_t)3 * c->B * c->J * sizeof(double) + 192 * sizeof(int);
   if (gj_bytes > 60 * 1024) {
     setf(c->err, "n_mu x shift range too large for the per-phase tap table (%zu bytes)", gj_bytes);
@@ -279,6 +291,10 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   HIP_TRY(hipMalloc((void**)&c->d_col_w, sizeof(double) * c->N));
   HIP_TRY(hipMalloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
   HIP_TRY(hipMalloc((void**)&c->d_Kq, sizeof(double) * c->B * c->J));
+  if (c->diff_rot != 0.0) {
+    HIP_TRY(hipMalloc((void**)&c->d_Kq_fx, sizeof(unsigned long long) * c->B * c->J));
+    HIP_TRY(hipMemsetAsync(c->d_Kq_fx, 0, sizeof(unsigned long long) * c->B * c->J, c->stream));
+  }
   HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE_MAX));
   HIP_TRY(hipMalloc(&c->d_ones, c->esize * c->n_tiles * soap::APPLY_TILE_MAX));
   if (c->cmode == SOAP_CONTRAST_PLANCK) {

@@ -48,6 +48,11 @@ constexpr int PAD_FRONT = 128;
 // widest line-spread function of the resolution lowering, in pixels each side
 constexpr int LSF_KMAX = 32;
 
+// With differential rotation each cell has its own shift, so the per-wave
+// tables of the weight and quiet kernels hold [rows][offsets]; their size
+// bounds n_mu x shift range (3 rows per bin in split tables).
+constexpr int DR_TAB_MAX = 1536;
+
 // Column slabs of the per-phase weight kernel (one wave per column).
 constexpr int SLAB_COLS = 4;
 constexpr int WEIGHT_WAVES = 4;
@@ -114,6 +119,8 @@ struct soap_ctx {
   int tune_lds_win = soap::APPLY_LDS_WIN;
   int tune_staged = 0;  // 1: source spans staged in LDS (256-thread tiles)
   double vsini = 0, incl = 0, u1 = 0, u2 = 0, ln0 = 0, dln = 0;
+  double diff_rot = 0;  // omega(theta) = omega_0 (1 + diff_rot sin^2 theta)
+  double sin_i = 0, cos_i = 1;
   int prec = SOAP_PREC_FP64, cmode = SOAP_CONTRAST_SCALAR;
   double teff = 0, dt_spot = 0, dt_fac[3] = {0, 0, 0};
   std::vector<double> mu_bins;
@@ -130,6 +137,7 @@ struct soap_ctx {
   double* d_col_w = nullptr;                       // [N]
   double* d_colW = nullptr;                        // [N][B] quiet column weights
   double* d_Kq = nullptr;                          // [B][J] quiet taps
+  unsigned long long* d_Kq_fx = nullptr;           // [B][J] fixed-point quiet taps (differential rotation)
   double* d_Q = nullptr;                           // [n_tiles * TILE]
   void* d_con_base = nullptr;
   void* d_con_spot = nullptr;                      // [Pstride] (PLANCK) or [B][Pstride] (ARRAY)
@@ -333,12 +341,16 @@ SOAP_DEV int nearest_bin(double mu, const double* mu_b, int B) {
   return (db < da) ? lo : lo - 1;
 }
 
-// observer-frame unit vector of a region centre at a rotation phase
-SOAP_DEV void region_centre(double lat, double lon, double phase, double incl, double* cx, double* cy,
-                            double* cz) {
+// observer-frame unit vector of a region centre at a rotation phase; under
+// differential rotation the region turns at its own latitude's rate,
+// 1 + diff_rot sin^2(lat) equatorial turns per unit phase (exactly one for
+// diff_rot = 0)
+SOAP_DEV void region_centre(double lat, double lon, double phase, double incl, double diff_rot, double* cx,
+                            double* cy, double* cz) {
 #pragma clang fp contract(off)
   double th = lat * DEG;
-  double psi = (lon + 360.0 * phase) * DEG;
+  const double sl = sin(th);
+  double psi = (lon + 360.0 * phase * (1.0 + diff_rot * sl * sl)) * DEG;
   double inc = incl * DEG;
   double X = cos(th) * sin(psi);
   double Y = sin(th);
@@ -346,6 +358,21 @@ SOAP_DEV void region_centre(double lat, double lon, double phase, double incl, d
   *cx = X;
   *cy = Y * sin(inc) - Z * cos(inc);
   *cz = Y * cos(inc) + Z * sin(inc);
+}
+
+// Shift of a cell in pixels and its interpolation split (Eqs. 6, 9-11 on
+// the log grid): s = atanh(v / c) / dln with v = vsini x (1 + diff_rot
+// sin^2 theta), sin theta = y sin i + mu cos i; the cell adds (1 - w) of its
+// weight at offset ceil(s) and w at ceil(s) - 1, w = expm1(u dln) /
+// expm1(dln), u = ceil(s) - s.
+SOAP_DEV void cell_shift(double x, double y, double mu, double vsini, double diff_rot, double sin_i, double cos_i,
+                         double dln, int* c, double* w) {
+  const double st = y * sin_i + mu * cos_i;
+  const double v = vsini * x * (1.0 + diff_rot * st * st);
+  const double s = atanh(v / C_KMS) / dln;
+  const double cc = ceil(s);
+  *c = (int)cc;
+  *w = expm1((cc - s) * dln) / expm1(dln);
 }
 
 }  // namespace soap

@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int
 // and the disk-cell bounding box of the caps that reach the visible
 // hemisphere.  The regions and phases are read once from the caller's
 // parameter block, so the weight kernel's many blocks read device memory.
-__global__ void __launch_bounds__(128) k_params(int N, int n_reg, int max_reg, int n_ph, double incl,
+__global__ void __launch_bounds__(128) k_params(int N, int n_reg, int max_reg, int n_ph, double incl, double diff_rot,
                                                 const Region* __restrict__ reg,
                                                 const double* __restrict__ phases, const int2* __restrict__ pj,
                                                 Region* __restrict__ reg_out, int2* __restrict__ pj_out,
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(128) k_params(int N, int n_reg, int max_reg, i
   for (int r = 0; r < rl.y; ++r) {
     const Region g = R[r];
     double cx, cy, cz, rc;
-    region_centre(g.lat_deg, g.lon_deg, phase, incl, &cx, &cy, &cz);
+    region_centre(g.lat_deg, g.lon_deg, phase, incl, diff_rot, &cx, &cy, &cz);
     {
 #pragma clang fp contract(off)
       rc = sqrt(1.0 - g.radius * g.radius);
@@ -445,14 +445,139 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
   }
 }
 
+// Differential rotation: the cells of one column no longer share a shift, so
+// every active cell splits its weight A I (times the owner's scale in split
+// tables) onto its own two offsets (Eq. 11) in a per-wave LDS table
+// [G][J] of exact 64-bit fixed-point sums (the removal rows of split tables
+// likewise), which the wave adds to the phase's tap table once it has walked
+// all its columns.  Ownership, bins and the rows each column can reach are
+// decided as in k_weights.  Per-cell weights are products in double in both
+// precisions; the fixed-point sums are exact, so the totals do not depend
+// on the order of cells, lanes or columns.
+__global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights_dr(
+    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, int effect, double vsini,
+    double diff_rot, double sin_i, double cos_i, double dln, const double* __restrict__ mu_b,
+    const Region* __restrict__ reg, int n_reg_all, int max_reg, const int2* __restrict__ pj,
+    const double4* __restrict__ cen, const int4* __restrict__ pbox, unsigned long long* __restrict__ Kfx) {
+  __shared__ double rcx[MAX_REGIONS], rcy[MAX_REGIONS], rcz[MAX_REGIONS], rcos[MAX_REGIONS],
+      rscal[MAX_REGIONS], rreach[MAX_REGIONS];
+  __shared__ double s_mub[MAX_MU];
+  __shared__ int rtype[MAX_REGIONS];
+  extern __shared__ unsigned long long s_drtab[];  // [WEIGHT_WAVES][G * J]
+
+  const int ph = blockIdx.x / n_slabs;
+  const int slab = blockIdx.x - ph * n_slabs;
+  const int nw = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int GJ = G * J;
+  const double area = (2.0 / N) * (2.0 / N);
+
+  const int4 bx = pbox[ph];
+  const int i0 = max(bx.x, slab * SLAB_COLS);
+  const int i1 = min(bx.y, min(N, (slab + 1) * SLAB_COLS) - 1);
+  const int k0 = bx.z, k1 = bx.w;
+  if (i0 > i1 || k0 > k1) return;  // nothing of this slab is covered
+  for (int b = threadIdx.x; b < B; b += blockDim.x) s_mub[b] = mu_b[b];
+  int rbase = 0, n_reg = n_reg_all;
+  if (pj) {
+    const int2 rl = pj[ph];
+    rbase = rl.x;
+    n_reg = rl.y;
+  }
+  if (threadIdx.x < n_reg) {
+    const double4 c4 = cen[(int64_t)ph * max_reg + threadIdx.x];
+    const Region& g = reg[rbase + threadIdx.x];
+    rcx[threadIdx.x] = c4.x;
+    rcy[threadIdx.x] = c4.y;
+    rcz[threadIdx.x] = c4.z;
+    rcos[threadIdx.x] = c4.w;
+    rtype[threadIdx.x] = g.type;
+    rscal[threadIdx.x] = (!paired && effect != SOAP_EFFECT_BCONV) ? g.contrast : 1.0;
+    const double rad = sqrt(fmax(0.0, 1.0 - c4.w * c4.w));
+    rreach[threadIdx.x] = (c4.z <= -rad - 1e-12) ? -1.0 : sqrt(fmax(0.0, 2.0 - 2.0 * c4.w)) + 1e-9;
+  }
+  unsigned long long* tab = s_drtab + (size_t)wave * GJ;
+  for (int e = lane; e < GJ; e += 64) tab[e] = 0ull;
+  __syncthreads();
+
+  for (int i = i0 + wave; i <= i1; i += nw) {
+    const double x = cell_coord(i, N);
+    double ylo = 2.0, yhi = -2.0;
+    for (int r = 0; r < n_reg; ++r) {
+      const double d = rreach[r];
+      const double dx = x - rcx[r];
+      if (d < 0.0 || fabs(dx) > d) continue;
+      const double h = sqrt(fmax(0.0, d * d - dx * dx));
+      ylo = fmin(ylo, rcy[r] - h);
+      yhi = fmax(yhi, rcy[r] + h);
+    }
+    if (ylo > yhi) continue;  // uniform
+    const int kc0 = max(k0, (int)floor((ylo + 1.0) * 0.5 * N) - 1);
+    const int kc1 = min(k1, (int)ceil((yhi + 1.0) * 0.5 * N) + 1);
+    for (int k = kc0 + lane; k <= kc1; k += 64) {
+      const double y = cell_coord(k, N);
+      double r2;
+      {
+#pragma clang fp contract(off)
+        r2 = x * x + y * y;
+      }
+      if (!(r2 < 1.0)) continue;
+      const double mu = sqrt(1.0 - r2);
+      int own = -1;
+      for (int r = 0; r < n_reg; ++r) {
+        double dot;
+        {
+#pragma clang fp contract(off)
+          dot = x * rcx[r] + y * rcy[r] + mu * rcz[r];
+        }
+        if (dot >= rcos[r]) own = r;
+      }
+      if (own < 0) continue;
+      const int b = nearest_bin(mu, s_mub, B);
+      const int t = rtype[own];
+      int cc;
+      double w;
+      cell_shift(x, y, mu, vsini, diff_rot, sin_i, cos_i, dln, &cc, &w);
+      const int ja = cc - jmin, jb = cc - 1 - jmin;
+      if (jb < 0 || ja >= J) continue;  // unreachable: the offset range bounds every shift
+      const double aw = area * limb_dark(mu, u1, u2);
+      const int g = paired ? (t - 1) * B + b : t * B + b;
+      const double W = aw * rscal[own];
+      atomicAdd(&tab[g * J + ja], to_fx((1.0 - w) * W));
+      atomicAdd(&tab[g * J + jb], to_fx(w * W));
+      if (!paired) {
+        // removal entry (row = bin, weight -A I)
+        atomicAdd(&tab[b * J + ja], to_fx(-(1.0 - w) * aw));
+        atomicAdd(&tab[b * J + jb], to_fx(-w * aw));
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  unsigned long long* Kph = Kfx + (int64_t)ph * GJ;
+  for (int e = lane; e < GJ; e += 64) {
+    const unsigned long long v = tab[e];
+    if (v) atomicAdd(Kph + e, v);
+  }
+}
+
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, int max_reg,
                           const double* d_ph, const int2* d_pj, const WeightsOut& o, hipStream_t st) {
   hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, st, c->N, n_reg, max_reg,
-                     pl.n_ph, c->incl, d_reg, d_ph, d_pj, o.reg, o.pj, o.cen, o.box);
+                     pl.n_ph, c->incl, c->diff_rot, d_reg, d_ph, d_pj, o.reg, o.pj, o.cen, o.box);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int2* pj = d_pj ? o.pj : nullptr;
   dim3 grid((unsigned)pl.n_slabs * (unsigned)pl.n_ph);
+  if (c->diff_rot != 0.0) {
+    const size_t lds = (size_t)WEIGHT_WAVES * pl.G * c->J * sizeof(unsigned long long);
+    if (pl.G * c->J > DR_TAB_MAX) return hipErrorInvalidValue;  // refused at init
+    hipLaunchKernelGGL(k_weights_dr, grid, dim3(64 * WEIGHT_WAVES), lds, st, c->N, c->B, c->J, c->jmin, pl.G,
+                       pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->vsini, c->diff_rot, c->sin_i, c->cos_i,
+                       c->dln, c->d_mu, o.reg, n_reg, max_reg, pj, o.cen, o.box, o.Kfx);
+    return hipGetLastError();
+  }
   if (c->prec == SOAP_PREC_FP32)
     hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, st, c->N, c->B, c->J, c->jmin,
                        pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,

@@ -50,7 +50,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(L.RegionC) == 40
     assert ctypes.sizeof(L.MaskC) == 56
     assert L.RV_DTYPE.itemsize == 56
-    assert ctypes.sizeof(L.StarDesc) == 8 * 2 + 8 * 6 + 8 + 24 + 16 + 16 + 24 + 24
+    assert ctypes.sizeof(L.StarDesc) == 8 * 2 + 8 * 6 + 8 + 24 + 16 + 16 + 24 + 24 + 8
 
 
 def _bad(**kw):
