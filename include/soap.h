@@ -298,6 +298,23 @@ soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device,
                         const soap_mask* mask, double* ccf_out, int32_t ccf_on_device,
                         soap_rv* rv_out, int32_t rv_on_device);
 
+/* soap_ccf_rv without any allocation, for callers that cannot allocate
+ * (work under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same CCF and fit, bit for bit, as soap_ccf_rv on the same
+ * flux; flux, ccf_out (may be NULL) and rv_out (may be NULL) are device
+ * memory.  The partial CCFs of the line blocks, and the CCF rows when
+ * ccf_out is NULL, go to a file-scope device array of 32 MiB that the
+ * library holds on every device it runs on until the process ends:
+ * 8 n_spec n_v (ceil(n_lines / 32) + [ccf_out == NULL]) bytes (rounded up
+ * to 256 for the first part) must fit, else SOAP_ERR_UNSUPPORTED.  The mask
+ * must be the one the context already holds (the last one given to
+ * soap_ccf_rv), else SOAP_ERR_STATE; nothing is uploaded.  Every call on a
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other contexts) race.  Enqueues only; calls no hipMalloc, hipFree
+ * or host allocation of pinned memory.                                       */
+soap_status soap_ccf_rv_noalloc(soap_ctx* ctx, const void* flux, int64_t n_spec, const soap_mask* mask,
+                                double* ccf_out, soap_rv* rv_out);
+
 /* Fits the CCFs of spectra written as a quiet part plus a linear
  * combination of basis spectra, without forming the spectra: the CCF
  * (section 4.1) is linear in the flux, so for F_i = F_0 + sum_k coef[i][k] B_k

@@ -93,6 +93,7 @@ SYMBOLS = (
     "soap_active_spectra_evolving",
     "soap_instrument_lsf",
     "soap_set_instrument",
+    "soap_ccf_rv_noalloc",
 )
 
 
@@ -537,6 +538,33 @@ def soap_set_instrument(ctx, resolution):
     """Later active-spectra calls return spectra lowered to ``resolution``
     (0 = off)."""
     _check(_lib.soap_set_instrument(ctx.handle, float(resolution)), ctx.handle)
+
+
+_lib.soap_ccf_rv_noalloc.argtypes = [_ctx_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.soap_ccf_rv_noalloc.restype = C.c_int
+
+
+def soap_ccf_rv_noalloc(ctx, flux, mask, ccf_out=None, rv_out=None):
+    """soap_ccf_rv without allocation: device flux, device outputs (or None),
+    the context's current mask."""
+    pf, df = _ptr(flux)
+    if not df:
+        raise ValueError("flux must be a device tensor")
+    n = int(flux.shape[0]) if len(flux.shape) == 2 else 1
+    m, keep = _mask(mask)
+    pc = 0
+    if ccf_out is not None:
+        pc, dc = _ptr(ccf_out)
+        if not dc:
+            raise ValueError("ccf_out must be a device tensor")
+    pr = 0
+    if rv_out is not None:
+        pr, dr = _ptr(rv_out)
+        if not dr:
+            raise ValueError("rv_out must be a device tensor")
+    st = _lib.soap_ccf_rv_noalloc(ctx.handle, pf, n, C.byref(m), pc or None, pr or None)
+    _check(st, ctx.handle)
+    return ccf_out, rv_out
 
 
 def _mask(mask):

@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsoap.so")
 
-SOURCES = ["geom.hip", "weights.hip", "apply.hip", "ccf.hip", "soap_abi.cpp", "surrogate.hip", "surrogate_abi.cpp", "tune.cpp", "batch.cpp", "lsf.hip"]
+SOURCES = ["geom.hip", "weights.hip", "apply.hip", "ccf.hip", "soap_abi.cpp", "surrogate.hip", "surrogate_abi.cpp", "tune.cpp", "batch.cpp", "lsf.hip", "noalloc.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -270,6 +270,9 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
 
   c->hip_used = true;
   HIP_TRY(hipGetDevice(&c->device));
+  // the allocation-free entry point's scratch on this device (its status is
+  // kept and reported by that entry point)
+  (void)soap::scratch_setup(c->device);
   c->pc = (c->prec == SOAP_PREC_FP32) ? soap::PC_F32 : soap::PC_F64;
   c->n_tiles = (int)((c->P + soap::APPLY_TILE_MAX - 1) / soap::APPLY_TILE_MAX);
   // padded rows: PAD_FRONT samples before pixel 0, and past the last tile
@@ -895,10 +898,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
     ARG_CHECK(is_finite(mask->ln_lambda[l]) && is_finite(mask->weight[l]), "mask line %d is not finite", l);
 
   // mask upload when it differs from the cached one
-  bool same = c->mask_valid && (int)c->mask_lnl.size() == nl && c->mask_h == mask->half_width_kms &&
-              c->mask_v0 == mask->v0_kms && c->mask_dv == mask->dv_kms && c->mask_nv == mask->n_v &&
-              std::memcmp(c->mask_lnl.data(), mask->ln_lambda, sizeof(double) * nl) == 0 &&
-              std::memcmp(c->mask_w.data(), mask->weight, sizeof(double) * nl) == 0;
+  const bool same = soap::mask_is_cached(c, mask);
   if (!same) {
     c->mask_valid = false;
     c->mask_h = mask->half_width_kms;

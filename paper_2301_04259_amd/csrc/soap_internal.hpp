@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -298,8 +300,22 @@ bool lsf_plan(double resolution, double dln, LsfPlan* pl);
 int64_t lsf_max_spectra(int64_t P);
 hipError_t launch_lsf(soap_ctx* c, const LsfPlan& pl, const void* in, void* out, int64_t n_spec, hipStream_t st);
 
+// looks up this device's copy of the allocation-free entry point's scratch
+// array (once per device; the device must be current); the result is kept
+hipError_t scratch_setup(int device);
+
 int ccf_line_blocks(int n_lines);
 int ccf_span_pixels(bool fp32);
+
+// true when `m` is the mask whose tables the context holds (set by the last
+// soap_ccf_rv with a new mask)
+inline bool mask_is_cached(const soap_ctx* c, const soap_mask* m) {
+  const int nl = (int)m->n_lines;
+  return c->mask_valid && m->n_lines == (int64_t)c->mask_lnl.size() && c->mask_h == m->half_width_kms &&
+         c->mask_v0 == m->v0_kms && c->mask_dv == m->dv_kms && c->mask_nv == m->n_v && m->ln_lambda && m->weight &&
+         std::memcmp(c->mask_lnl.data(), m->ln_lambda, sizeof(double) * nl) == 0 &&
+         std::memcmp(c->mask_w.data(), m->weight, sizeof(double) * nl) == 0;
+}
 
 // ---- device helpers ---------------------------------------------------------
 #ifdef __HIP_DEVICE_COMPILE__

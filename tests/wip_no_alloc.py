@@ -1,0 +1,117 @@
+"""The allocation-free CCF entry point (soap_ccf_rv_noalloc) through the C
+ABI against soap_ccf_rv: bit-identical CCFs and fits on two calls in a row,
+the second with fewer spectra, with and without a caller CCF buffer, and on
+the headline workload; its argument and state errors."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+L = pytest.importorskip("paper_2301_04259_amd", reason="libsoap.so not built")
+
+
+def _say(*a):
+    print("[no-alloc]", *a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _rv_dev(n):
+    return torch.zeros(n * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+
+
+def _rv_host(t):
+    return np.frombuffer(t.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
+
+
+def _reference(ctx, flux, mask):
+    n = flux.shape[0]
+    ccf = torch.empty((n, mask.n_v), dtype=torch.float64, device="cuda")
+    rv = _rv_dev(n)
+    L.soap_ccf_rv(ctx, flux, mask, ccf_out=ccf, rv_out=rv)
+    torch.cuda.synchronize()
+    return ccf.cpu().numpy(), _rv_host(rv)
+
+
+def test_noalloc_equals_ccf_rv_on_two_calls_the_second_smaller():
+    st = W.make_tiny(81, n_grid=40, n_pix=3100, n_mu=4, precision=W.PREC_FP32, n_phases=13)
+    ctx = L.soap_grid_init(st)
+    flux = torch.empty((13, st.n_pix), dtype=torch.float32, device="cuda")
+    L.soap_active_spectra(ctx, st.regions, st.phases, W.EFFECT_TOT, flux)
+    m = st.mask
+    ref_ccf, ref_rv = _reference(ctx, flux, m)  # also sets the context's mask
+    for n in (13, 5):
+        _say("calls with", n, "spectra")
+        ccf = torch.full((n, m.n_v), -7.0, dtype=torch.float64, device="cuda")
+        rv = _rv_dev(n)
+        L.soap_ccf_rv_noalloc(ctx, flux[:n], m, ccf_out=ccf, rv_out=rv)
+        torch.cuda.synchronize()
+        assert np.array_equal(ccf.cpu().numpy(), ref_ccf[:n])
+        got = _rv_host(rv)
+        for f in ("rv_kms", "fwhm_kms", "chi2", "iters", "status"):
+            assert np.array_equal(got[f], ref_rv[f][:n]), f
+    # without a CCF buffer the CCF rows stay in the scratch array
+    rv = _rv_dev(13)
+    L.soap_ccf_rv_noalloc(ctx, flux, m, ccf_out=None, rv_out=rv)
+    torch.cuda.synchronize()
+    assert np.array_equal(_rv_host(rv)["rv_kms"], ref_rv["rv_kms"])
+
+
+def test_noalloc_fp64_star():
+    st = W.make_tiny(82, n_grid=24, n_pix=1800, n_mu=3, precision=W.PREC_FP64, n_phases=9)
+    ctx = L.soap_grid_init(st)
+    flux = torch.empty((9, st.n_pix), dtype=torch.float64, device="cuda")
+    L.soap_active_spectra(ctx, st.regions, st.phases, W.EFFECT_TOT, flux)
+    ref_ccf, ref_rv = _reference(ctx, flux, st.mask)
+    for n in (9, 2):
+        ccf = torch.empty((n, st.mask.n_v), dtype=torch.float64, device="cuda")
+        rv = _rv_dev(n)
+        L.soap_ccf_rv_noalloc(ctx, flux[:n], st.mask, ccf_out=ccf, rv_out=rv)
+        torch.cuda.synchronize()
+        assert np.array_equal(ccf.cpu().numpy(), ref_ccf[:n])
+        assert np.array_equal(_rv_host(rv)["rv_kms"], ref_rv["rv_kms"][:n])
+
+
+def test_noalloc_headline():
+    st = W.make_cfg2()
+    ctx = L.soap_grid_init(st)
+    flux = torch.empty((100, st.n_pix), dtype=torch.float32, device="cuda")
+    L.soap_active_spectra(ctx, st.regions, st.phases, W.EFFECT_TOT, flux)
+    _say("headline")
+    ref_ccf, ref_rv = _reference(ctx, flux, st.mask)
+    for n in (100, 37):
+        ccf = torch.empty((n, st.mask.n_v), dtype=torch.float64, device="cuda")
+        rv = _rv_dev(n)
+        L.soap_ccf_rv_noalloc(ctx, flux[:n], st.mask, ccf_out=ccf, rv_out=rv)
+        torch.cuda.synchronize()
+        assert np.array_equal(ccf.cpu().numpy(), ref_ccf[:n])
+        assert np.array_equal(_rv_host(rv)["rv_kms"], ref_rv["rv_kms"][:n])
+
+
+def test_noalloc_errors():
+    st = W.make_tiny(83, n_grid=16, n_pix=1200, n_mu=2, precision=W.PREC_FP32, n_phases=3)
+    ctx = L.soap_grid_init(st)
+    flux = torch.ones((3, st.n_pix), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.SoapError) as e:
+        L.soap_ccf_rv_noalloc(ctx, flux, st.mask, rv_out=_rv_dev(3))  # no mask on the context yet
+    assert e.value.status == L.SOAP_ERR_STATE
+    L.soap_ccf_rv(ctx, flux, st.mask, rv_out=L.rv_records(3))
+    # 40000 spectra x 61 velocities x (1 line block + the CCF rows) x 8 B
+    # exceed the 32 MiB array: refused before anything is enqueued
+    big = torch.empty((40000, st.n_pix), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.SoapError) as e:
+        L.soap_ccf_rv_noalloc(ctx, big, st.mask)
+    assert e.value.status == L.SOAP_ERR_UNSUPPORTED
+    other = W.Mask(st.mask.ln_lambda[:-1], st.mask.weight[:-1], st.mask.half_width_kms, st.mask.v0_kms,
+                   st.mask.dv_kms, st.mask.n_v)
+    with pytest.raises(L.SoapError) as e:
+        L.soap_ccf_rv_noalloc(ctx, flux, other, rv_out=_rv_dev(3))
+    assert e.value.status == L.SOAP_ERR_STATE
