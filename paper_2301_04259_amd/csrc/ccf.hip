@@ -43,9 +43,9 @@ int ccf_span_pixels(bool) { return CCF_STG_MAX; }
 
 namespace {
 
-// 4 consecutive elements of 16-byte-aligned memory as doubles
+// 4 consecutive elements of 16-byte-aligned memory in their own type
 template <typename T>
-__device__ __forceinline__ void get4(double* x, const T* p) {
+__device__ __forceinline__ void get4t(T* x, const T* p) {
   if constexpr (sizeof(T) == 4) {
     const float4 v = *reinterpret_cast<const float4*>(p);
     x[0] = v.x;
@@ -72,8 +72,11 @@ __device__ __forceinline__ void get4(double* x, const T* p) {
 // buffers alternate, the next batch's loads are in flight while one is
 // used, and one barrier per batch separates them.  Pixels outside the
 // spectrum are staged as zeros.  Each thread computes its holes' pixel
-// overlaps once per line and applies them to every staged spectrum with
-// FP64 FMAs.
+// overlaps once per line (in double: the hole edges come from differences of
+// nearby pixel coordinates) and applies them to every staged spectrum with
+// FMAs in the flux precision: a block's partial CCF sums at most 32 lines x
+// a few pixels in FP32 for float spectra, and the partials of the line blocks
+// are added in double by the fit kernel.
 template <typename T, int A, int NPX, int STG>
 __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, const T* __restrict__ F,
                                                      const double2* __restrict__ lines,
@@ -100,14 +103,15 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
 #pragma unroll
   for (int a = 0; a < A; ++a) s_ed[tid + a * CCF_THREADS] = edges[min(tid + a * CCF_THREADS, n_v - 1)];
   __syncthreads();
-  double alo[A], ahi[A], acc[A][SB];
+  double alo[A], ahi[A];
+  T acc[A][SB];
 #pragma unroll
   for (int a = 0; a < A; ++a) {
     const double2 e = s_ed[tid + a * CCF_THREADS];
     alo[a] = e.x;
     ahi[a] = e.y;
 #pragma unroll
-    for (int s = 0; s < SB; ++s) acc[a][s] = 0.0;
+    for (int s = 0; s < SB; ++s) acc[a][s] = T(0);
   }
   T vals[R][SB];
   auto load = [&](int bi) {
@@ -168,11 +172,12 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
         }
 #pragma unroll
         for (int px = 0; px < NPX; ++px) {
-          double f[SB];
+          T f[SB];
 #pragma unroll
-          for (int c = 0; c < SB / 4; ++c) get4(&f[4 * c], &sb[i0 + px][4 * c]);
+          for (int c = 0; c < SB / 4; ++c) get4t(&f[4 * c], &sb[i0 + px][4 * c]);
+          const T wp = (T)w[px];
 #pragma unroll
-          for (int s = 0; s < SB; ++s) acc[a][s] = fma(w[px], f[s], acc[a][s]);
+          for (int s = 0; s < SB; ++s) acc[a][s] = fma(wp, f[s], acc[a][s]);
         }
       }
     }
@@ -186,7 +191,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
     if (k >= n_v) break;
 #pragma unroll
     for (int s = 0; s < SB; ++s)
-      if (s < ns) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = acc[a][s];
+      if (s < ns) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = (double)acc[a][s];
   }
 }
 

@@ -58,6 +58,9 @@ def test_ccf_shapes_match_oracle(seed, prec, hole_px, n_v, span_px, edge, shuffl
     v = W.make_velocity_grid(v0, dv, n_v)
     c_or = OC.ccf(flux_h.astype(np.float64), star.ln_lambda0, star.dln_lambda, ln_l, mask.weight, h, v)
     got = ccf.cpu().numpy()
-    # hole edges: ~1e-16 in ln(lambda) on either side, ~1e-10 pixel
+    # FP64: hole edges ~1e-16 in ln(lambda) on either side, ~1e-10 pixel.
+    # FP32 spectra are accumulated in FP32 per block of 32 lines: at most
+    # 32 lines x 10 pixels of FMAs into one partial, each rounding by 2^-24
+    # of the running (positive) sum, bounds the error by 2e-5 relative
     rel = np.max(np.abs(got - c_or) / np.abs(c_or))
-    assert rel < 1e-9, rel
+    assert rel < (1e-9 if prec == W.PREC_FP64 else 2e-5), rel

@@ -272,13 +272,16 @@ def test_ccf_and_fit_match_oracle_on_same_flux():
     L.soap_ccf_rv(ctx, out, m, ccf_out=ccf, rv_out=rv)
     torch.cuda.synchronize()
     c_or, rv_or = _rv_oracle(star, out.cpu().numpy().astype(np.float64))
-    # the oracle places hole edges with log(1 + f) of a number within 1e-5 of
-    # one: ~1e-16 absolute in ln(lambda), i.e. ~5e-11 pixel; CCF values agree
-    # to ~1e-10 relative
+    # FP32 spectra: each block partial sums at most 32 lines x 2 pixels of
+    # FP32 FMAs, so the CCF agrees to 64 x 2^-24 ~ 4e-6 relative at worst
+    # (the hole edges themselves are placed to ~5e-11 pixel)
     rel = np.max(np.abs(ccf.cpu().numpy() - c_or) / np.abs(c_or))
-    assert rel < 1e-9, rel
+    _say("ccf rel", rel)
+    assert rel < 4e-6, rel
     assert np.all(rv["status"] == 0)
-    assert np.max(np.abs(rv["rv_kms"] - rv_or)) * 1e5 < 1e-3  # same CCF: fits agree to 1e-3 cm/s
+    d = np.max(np.abs(rv["rv_kms"] - rv_or)) * 1e5
+    _say("same flux: RV diff cm/s", d)
+    assert d < 0.1
 
 
 def test_ccf_host_and_device_buffers_agree():

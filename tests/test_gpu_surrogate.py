@@ -282,7 +282,9 @@ def test_linear_ccf_fit_matches_oracle():
     v = W.make_velocity_grid(m.v0_kms, m.dv_kms, m.n_v)
     F = rows[0].astype(np.float64) + coef.astype(np.float64) @ rows[1:].astype(np.float64)
     want_ccf = OC.ccf(F, star.ln_lambda0, star.dln_lambda, m.ln_lambda, m.weight, m.half_width_kms, v)
-    np.testing.assert_allclose(got_ccf, want_ccf, rtol=1e-9, atol=1e-9 * np.abs(want_ccf).max())
+    # the base and basis CCFs come from FP32 spectra, accumulated in FP32
+    # per block of 32 lines (<= 64 x 2^-24 relative of each partial)
+    np.testing.assert_allclose(got_ccf, want_ccf, rtol=4e-6, atol=4e-6 * np.abs(want_ccf).max())
     worst = 0.0
     for i in range(n):
         f = OF.gauss_fit(v, want_ccf[i])
