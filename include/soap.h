@@ -169,7 +169,8 @@ typedef struct {
  * CCF (section 4.1: RV = the fitted mean).  status:
  *   0  converged;
  *   1  iteration limit reached;
- *   2  degenerate CCF: a non-finite sample, or no depth (max == min);
+ *   2  degenerate CCF: a non-finite sample, or no depth (max - min at most
+ *      1e-12 of max);
  *   3  failed: no damped step lowers chi^2 from a point that is not a
  *      minimum (no step was ever accepted, the sums are singular or not
  *      finite, or the undamped Newton step there is not of rounding size).
@@ -194,7 +195,7 @@ typedef struct {
  * a non-finite value is SOAP_ERR_ARG for device inputs and SOAP_ERR_HIP
  * (a corrupted upload) for host inputs, which are checked on the host first.
  * SOAP_ERR_UNSUPPORTED when the limb-darkened disk weight, sum of
- * (2/n_grid)^2 |I(mu)| over the cells, reaches 3.99 (the range of the
+ * (2/n_grid)^2 |I(mu)| over the cells, reaches 15.9 (the range of the
  * fixed-point tap sums).  The context owns all device workspace until
  * soap_destroy.  On error *out is set to NULL.                              */
 soap_status soap_grid_init(const soap_star_desc* desc, void* hip_stream, soap_ctx** out);
@@ -208,7 +209,7 @@ soap_status soap_quiet_spectrum(soap_ctx* ctx, void* out, int32_t out_on_device)
  * in rotations (longitude advances 360 deg per unit).  Types present in
  * regions must have spectra.  In SCALAR mode with contrasts other than one
  * (flux and total effects), SOAP_ERR_UNSUPPORTED when the disk weight times
- * the largest contrast reaches 3.99 (the fixed-point range of the sums).    */
+ * the largest contrast reaches 15.9 (the fixed-point range of the sums).    */
 soap_status soap_active_spectra(soap_ctx* ctx, const soap_region* regions, int32_t n_regions,
                                 const double* phases, int32_t n_phases, int32_t effect,
                                 void* flux, int32_t flux_on_device);

@@ -311,6 +311,7 @@ class Context:
     """Owns a soap_ctx* and the host objects its pointers were made from."""
 
     def __init__(self, handle, star, keep):
+        self._pid = os.getpid()
         self.handle = handle
         self.star = star
         self._keep = keep
@@ -319,6 +320,8 @@ class Context:
         self.dtype = np.float32 if self.precision == PREC_FP32 else np.float64
 
     def __del__(self, _destroy=_lib.soap_destroy):
+        if getattr(self, "_pid", None) != os.getpid():
+            return  # a forked child must not touch its parent's device state
         h = getattr(self, "handle", None)
         if h:
             _destroy(h)
@@ -649,10 +652,13 @@ class Surrogate:
     """Owns a soap_surrogate*."""
 
     def __init__(self, handle, n_in, hidden, n_out, n_ens):
+        self._pid = os.getpid()
         self.handle = handle
         self.n_in, self.hidden, self.n_out, self.n_ens = n_in, hidden, n_out, n_ens
 
     def __del__(self, _destroy=_lib.soap_surrogate_destroy):
+        if getattr(self, "_pid", None) != os.getpid():
+            return  # a forked child must not touch its parent's device state
         h = getattr(self, "handle", None)
         if h:
             _destroy(h)
@@ -785,11 +791,14 @@ class Batch:
     """Owns a soap_batch* and keeps its contexts and outputs alive."""
 
     def __init__(self, handle, ctxs, outs):
+        self._pid = os.getpid()
         self.handle = handle
         self._ctxs = ctxs
         self.outs = outs
 
     def __del__(self, _destroy=_lib.soap_batch_destroy):
+        if getattr(self, "_pid", None) != os.getpid():
+            return  # a forked child must not touch its parent's device state
         h = getattr(self, "handle", None)
         if h:
             _destroy(h)

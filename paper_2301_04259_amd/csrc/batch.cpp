@@ -128,9 +128,9 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     pl.n_ph = np;
     pl.effect = effect;
     pl.paired = (c->cmode != SOAP_CONTRAST_SCALAR || effect == SOAP_EFFECT_BCONV || unit) ? 1 : 0;
-    if (!pl.paired && !(c->disk_weight * cmax < 3.99)) {
+    if (!pl.paired && !(c->disk_weight * cmax < soap::FX_RANGE)) {
       // split tables scale the active rows by the contrasts: the fixed-point
-      // tap sums hold |x| < 4
+      // tap sums hold |x| < 16
       std::snprintf(msg, sizeof msg, "configuration %d: disk weight x contrast reaches the fixed-point range", i);
       return bad(msg, SOAP_ERR_UNSUPPORTED);
     }

@@ -469,7 +469,7 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
 
   soap_rv res;
   res.status = 0;
-  if (any_bad || !(a0 > 0.0) || !isfinite(c0) || !isfinite(ymin)) {
+  if (any_bad || !(a0 > 1e-12 * fabs(c0)) || !isfinite(c0) || !isfinite(ymin)) {
     res.status = 2;
     res.iters = 0;
   } else {

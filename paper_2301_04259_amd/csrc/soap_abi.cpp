@@ -213,8 +213,7 @@ double disk_weight(int N, double u1, double u2) {
   return tot;
 }
 
-// the fixed-point tap sums hold |x| < 4 (units of 2^-61 in 64 bits)
-constexpr double FX_RANGE = 3.99;
+using soap::FX_RANGE;
 
 soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   c->N = d->n_grid;

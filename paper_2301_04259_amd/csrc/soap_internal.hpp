@@ -60,8 +60,11 @@ constexpr int SLAB_COLS = 4;
 constexpr int WEIGHT_WAVES = 4;
 constexpr int FINISH_THREADS = 512;
 // fixed-point unit of the per-phase tap accumulators
-constexpr double FX_ONE = 2305843009213693952.0;        // 2^61
-constexpr double FX_INV = 1.0 / 2305843009213693952.0;  // 2^-61
+// (2^-59: sums up to |x| < 16, quantum 1.7e-18)
+constexpr double FX_ONE = 576460752303423488.0;        // 2^59
+constexpr double FX_INV = 1.0 / 576460752303423488.0;  // 2^-59
+// largest disk weight x contrast the fixed-point sums accept
+constexpr double FX_RANGE = 15.9;
 
 // region record as the kernels read it (device view of soap_region)
 struct Region {

@@ -41,7 +41,7 @@ namespace {
 
 constexpr int MAXC = 4;   // cells per lane per row pass (256 rows)
 
-// taps are accumulated as 64-bit fixed point in units of 2^-61 (|tap| < 4):
+// taps are accumulated as 64-bit fixed point in units of 2^-59 (|tap| < 16):
 // integer addition is exact, so the totals do not depend on the order in
 // which columns arrive
 __device__ __forceinline__ unsigned long long to_fx(double x) {

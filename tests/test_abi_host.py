@@ -101,9 +101,9 @@ def test_grid_init_rejects_nan_spectrum():
 
 
 def test_grid_init_rejects_disk_weight_beyond_fixed_point_range():
-    # I(mu) = 1 + 1.5 (1 - mu) gives a disk weight near 4.7: beyond the
-    # |x| < 4 range of the fixed-point tap sums (checked before any device call)
-    st = _bad(ld_u1=-1.5, ld_u2=0.0)
+    # I(mu) = 1 + 15 (1 - mu) gives a disk weight near 6 pi: beyond the
+    # |x| < 16 range of the fixed-point tap sums (checked before any device call)
+    st = _bad(ld_u1=-15.0, ld_u2=0.0)
     with pytest.raises(L.SoapError, match="fixed-point") as e:
         L.soap_grid_init(st)
     assert e.value.status == L.SOAP_ERR_UNSUPPORTED

@@ -69,17 +69,17 @@ def test_non_finite_device_spectrum_is_an_argument_error():
 
 
 def test_contrast_beyond_fixed_point_range_is_rejected():
-    # disk weight ~2.6 (limb darkening of a solar-like star) x contrast 1.6
-    # reaches the |x| < 4 range of the fixed-point tap sums in split tables
+    # disk weight ~3.0 (limb darkening u1 = 0.1) x contrast 6 reaches the
+    # |x| < 16 range of the fixed-point tap sums in split tables
     star = W.make_tiny(28, n_grid=40, n_pix=600, n_mu=3, precision=W.PREC_FP64, n_phases=3)
     star.ld_u1, star.ld_u2 = 0.1, 0.0
     ctx = L.soap_grid_init(star)
     out = torch.empty((3, star.n_pix), dtype=torch.float64, device="cuda")
-    big = [W.Region(W.FACULA, 0.0, 0.0, 0.9, 1.6)]
+    big = [W.Region(W.FACULA, 0.0, 0.0, 0.9, 6.0)]
     with pytest.raises(L.SoapError) as e:
         L.soap_active_spectra(ctx, big, star.phases, W.EFFECT_TOT, out)
     assert e.value.status == L.SOAP_ERR_UNSUPPORTED
-    ok = [W.Region(W.FACULA, 0.0, 0.0, 0.9, 1.2)]
+    ok = [W.Region(W.FACULA, 0.0, 0.0, 0.9, 4.5)]
     L.soap_active_spectra(ctx, ok, star.phases, W.EFFECT_TOT, out)
     torch.cuda.synchronize()
     want = np.stack([OS.integrated(star, p, OS.TOT, ok) for p in star.phases])
@@ -92,8 +92,8 @@ def test_fit_status_of_nan_and_flat_ccfs():
     q = np.zeros(star.n_pix)
     L.soap_quiet_spectrum(ctx, q)
     m = star.mask
-    # a NaN inside the first mask line's holes, a flat spectrum, and the
-    # quiet spectrum itself
+    # a NaN inside a mask line's holes, a flat spectrum (its CCF is flat to
+    # rounding: depth below 1e-12 of the continuum), and the quiet spectrum
     lnl = star.ln_lambda0 + star.dln_lambda * np.arange(star.n_pix)
     k = int(np.argmin(np.abs(lnl - m.ln_lambda[len(m.ln_lambda) // 2])))
     rows = np.stack([q.copy(), np.full(star.n_pix, 2.5), q.copy()])
