@@ -153,6 +153,80 @@ def batch_leg(args, L, W, np, torch):
     return res
 
 
+def extra_legs(args, L, W, np, torch, star, dev_spectra, flux):
+    """The headline step under the solar differential rotation (section 3.4,
+    DIFF_ROT = -0.18: per-cell shifts in the weight kernels), and the
+    resolution lowering to R = 115000 (Algorithms 2 and 5, last step) on the
+    headline's 100 spectra, each timed with HIP events on the context
+    stream."""
+    import dataclasses
+
+    n_ph, P = flux.shape
+    dr = dataclasses.replace(star, diff_rot=-0.18, spectra=dev_spectra)
+    ctx = L.soap_grid_init(dr)
+    out = torch.empty_like(flux)
+    m = star.mask
+    ccf = torch.empty((n_ph, m.n_v), dtype=torch.float64, device="cuda")
+    rv = torch.empty(n_ph * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+
+    def step():
+        L.soap_active_spectra(ctx, dr.regions, dr.phases, W.EFFECT_TOT, out)
+        L.soap_ccf_rv(ctx, out, m, ccf_out=ccf, rv_out=rv)
+
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    reps = max(20, args.steps // 4)
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(st)
+    for _ in range(reps):
+        step()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = max(e0.elapsed_time(e1) / reps, (time.perf_counter() - w0) * 1e3 / reps)
+    L.soap_profile_enable(ctx, True)
+    for _ in range(20):
+        step()
+    prof = L.soap_profile_read(ctx)
+    L.soap_profile_enable(ctx, False)
+    diffrot = {
+        "workload": "the headline workload with DIFF_ROT = -0.18 (omega = omega_0 (1 - 0.18 sin^2 latitude)), "
+        "synthesis + CCF + fit per step",
+        "diff_rot": -0.18,
+        "ms_per_step": ms,
+        "spectra_per_s": n_ph / (ms * 1e-3),
+        "stages_ms": {k: prof[k] / 20 for k in ("weights_ms", "compact_ms", "apply_ms", "ccf_ms", "gfit_ms")},
+    }
+    L.soap_destroy(ctx)
+    # resolution lowering of the headline's spectra, out of place
+    lctx = L.soap_grid_init(dataclasses.replace(star, spectra=dev_spectra))
+    low = torch.empty_like(flux)
+    for _ in range(5):
+        L.soap_instrument_lsf(lctx, flux, low, 115000.0)
+    torch.cuda.synchronize()
+    L.soap_profile_enable(lctx, True)
+    for _ in range(50):
+        L.soap_instrument_lsf(lctx, flux, low, 115000.0)
+    lp = L.soap_profile_read(lctx)
+    L.soap_profile_enable(lctx, False)
+    lsf_ms = lp["lsf_ms"] / 50
+    nbytes = 2 * n_ph * P * 4
+    gbs = nbytes / (lsf_ms * 1e-3) / 1e9
+    lsf = {
+        "workload": "100 spectra of 205800 px (FP32) lowered to R = 115000: Gaussian LSF sigma 1.27 px, 13 taps",
+        "kernel": "k_lsf",
+        "kernel_ms": lsf_ms,
+        "spectra_per_s": n_ph / (lsf_ms * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": nbytes},
+    }
+    L.soap_destroy(lctx)
+    return {"diffrot": diffrot, "lsf": lsf}
+
+
 def surrogate_leg(args, L, W, np, torch):
     """Surrogate vs full synthesis on the 20000-pixel window: stars over a
     grid of T_eff (41 values), inclination (7) and v sin i (5), one spot per
@@ -293,6 +367,9 @@ def main():
     ap.add_argument("--batch-configs", type=int, default=512,
                     help="configurations of the batched-graph leg (0 = skip the leg)")
     ap.add_argument("--batch-runs", type=int, default=5)
+    ap.add_argument("--extra-legs", type=int, default=1,
+                    help="time the headline step with the solar differential rotation and the resolution "
+                    "lowering kernel (0 = skip)")
     ap.add_argument("--surrogate-alpha", type=float, default=1e-3,
                     help="gate calibration: largest fraction of accepted held-out samples allowed to miss by "
                     ">= 10 cm/s (0 = none)")
@@ -409,6 +486,11 @@ def main():
     rvh = np.frombuffer(rv.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
     assert np.all(np.isfinite(rvh["rv_kms"])) and torch.isfinite(flux).all()
 
+    extra = None
+    if args.extra_legs:
+        print("[bench] differential rotation and resolution lowering legs", file=sys.stderr, flush=True)
+        extra = extra_legs(args, L, W, np, torch, star, dev_spectra, flux)
+
     bat = None
     if args.batch_configs > 0:
         print("[bench] batched leg", file=sys.stderr, flush=True)
@@ -484,6 +566,8 @@ def main():
         "batch": bat,
         "surrogate": sur,
         "surrogate_single_star": sur1,
+        "diffrot": extra["diffrot"] if extra else None,
+        "lsf": extra["lsf"] if extra else None,
     }
     print(json.dumps(out))
 

@@ -306,8 +306,9 @@ soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device,
  * memory.  The partial CCFs of the line blocks, and the CCF rows when
  * ccf_out is NULL, go to a file-scope device array of 32 MiB that the
  * library holds on every device it runs on until the process ends:
- * 8 n_spec n_v (ceil(n_lines / 32) + [ccf_out == NULL]) bytes (rounded up
- * to 256 for the first part) must fit, else SOAP_ERR_UNSUPPORTED.  The mask
+ * n_spec n_v (e ceil(n_lines / 32) + 8 [ccf_out == NULL]) bytes, e the size
+ * of the context's float type, the first part rounded up to 256, must fit,
+ * else SOAP_ERR_UNSUPPORTED.  The mask
  * must be the one the context already holds (the last one given to
  * soap_ccf_rv), else SOAP_ERR_STATE; nothing is uploaded.  Every call on a
  * device shares that device's array: calls that overlap on one device (other

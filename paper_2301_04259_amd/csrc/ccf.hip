@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
                                                      const double2* __restrict__ edges,
                                                      const int4* __restrict__ batches,
                                                      const int* __restrict__ bfirst, int n_v,
-                                                     double* __restrict__ part) {
+                                                     T* __restrict__ part) {
   constexpr int SB = CCF_SB;
   constexpr int R = (STG + CCF_THREADS - 1) / CCF_THREADS;  // staged pixels per thread
   static_assert(SB % 4 == 0, "16-byte stage rows");
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
     if (k >= n_v) break;
 #pragma unroll
     for (int s = 0; s < SB; ++s)
-      if (s < ns) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = (double)acc[a][s];
+      if (s < ns) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = acc[a][s];
   }
 }
 
@@ -577,9 +577,9 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
 // was accepted and the undamped Newton step there is of rounding size
 // (status 0); otherwise the fit failed (status 3).  A CCF with a non-finite
 // sample or no depth is degenerate (status 2).
-template <int NPT>
+template <int NPT, typename PT>
 __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n_spec, int n_v, double v0,
-                                                             double dv, const double* __restrict__ part,
+                                                             double dv, const PT* __restrict__ part,
                                                              double* __restrict__ ccf, int fit,
                                                              soap_rv* __restrict__ out) {
   __shared__ double s_sum[CCF_FIN_THREADS / 64][NPT * 64];
@@ -597,11 +597,11 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
         const int lb = lb0 + u * NW;
-        const double* src = part + ((int64_t)lb * n_spec + s) * n_v;
+        const PT* src = part + ((int64_t)lb * n_spec + s) * n_v;
 #pragma unroll
         for (int t = 0; t < NPT; ++t) {
           const int i = lane + 64 * t;
-          v[u][t] = (lb < n_lb && i < n_v) ? src[i] : 0.0;
+          v[u][t] = (lb < n_lb && i < n_v) ? (double)src[i] : 0.0;
         }
       }
 #pragma unroll
@@ -631,17 +631,17 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
 }
 
 template <typename T, int A, int NPX, int STG>
-static void launch_ccf_a(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
+static void launch_ccf_a(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
   const unsigned char* base = static_cast<const unsigned char*>(c->ws_mask.ptr);
   hipLaunchKernelGGL((k_ccf<T, A, NPX, STG>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec,
                      static_cast<const T*>(d_flux), reinterpret_cast<const double2*>(base),
                      reinterpret_cast<const double2*>(base + c->ccf_off_edges),
                      reinterpret_cast<const int4*>(base + c->ccf_off_batch),
-                     reinterpret_cast<const int*>(base + c->ccf_off_bfirst), c->mask_nv, d_part);
+                     reinterpret_cast<const int*>(base + c->ccf_off_bfirst), c->mask_nv, static_cast<T*>(d_part));
 }
 
 template <typename T, int NPX, int STG>
-static void launch_ccf_n(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
+static void launch_ccf_n(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
   const int nv = c->mask_nv;
   if (nv <= CCF_THREADS) launch_ccf_a<T, 1, NPX, STG>(c, grid, d_flux, n_spec, d_part);
   else if (nv <= 2 * CCF_THREADS) launch_ccf_a<T, 2, NPX, STG>(c, grid, d_flux, n_spec, d_part);
@@ -649,7 +649,7 @@ static void launch_ccf_n(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_s
 }
 
 template <typename T, int STG>
-static void launch_ccf_s(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
+static void launch_ccf_s(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
   switch (c->ccf_npx) {
     case 2: launch_ccf_n<T, 2, STG>(c, grid, d_flux, n_spec, d_part); break;
     case 3: launch_ccf_n<T, 3, STG>(c, grid, d_flux, n_spec, d_part); break;
@@ -659,12 +659,12 @@ static void launch_ccf_s(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_s
 }
 
 template <typename T>
-static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, double* d_part) {
+static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
   if (c->ccf_stg <= 256) launch_ccf_s<T, 256>(c, grid, d_flux, n_spec, d_part);
   else launch_ccf_s<T, CCF_STG_MAX>(c, grid, d_flux, n_spec, d_part);
 }
 
-hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, double* d_part) {
+hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, void* d_part) {
   const int nlb = ccf_line_blocks(n_lines);
   dim3 grid(nlb, (unsigned)((n_spec + CCF_SB - 1) / CCF_SB));
   if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_part);
@@ -673,12 +673,13 @@ hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lin
 }
 
 // the fit kernel for the mask's points per lane
-static hipError_t launch_fit_npt(soap_ctx* c, int nlb, int64_t n_spec, const double* d_part, double* d_ccf,
+template <typename PT>
+static hipError_t launch_fit_npt(soap_ctx* c, int nlb, int64_t n_spec, const PT* d_part, double* d_ccf,
                                  soap_rv* d_rv) {
   const int npt = (c->mask_nv + 63) / 64;
 #define FIT_CASE(N)                                                                                           \
   case N:                                                                                                     \
-    hipLaunchKernelGGL(k_ccf_fit<N>, dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, c->stream, nlb, n_spec, \
+    hipLaunchKernelGGL((k_ccf_fit<N, PT>), dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, c->stream, nlb, n_spec, \
                        c->mask_nv, c->mask_v0, c->mask_dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);                \
     break;
   switch (npt) {
@@ -690,10 +691,11 @@ static hipError_t launch_fit_npt(soap_ctx* c, int nlb, int64_t n_spec, const dou
   return hipGetLastError();
 }
 
-hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_t n_spec, double* d_ccf,
+hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const void* d_part, int64_t n_spec, double* d_ccf,
                           soap_rv* d_rv) {
   const int nlb = ccf_line_blocks(n_lines);
-  return launch_fit_npt(c, nlb, n_spec, d_part, d_ccf, d_rv);
+  if (c->prec == SOAP_PREC_FP32) return launch_fit_npt(c, nlb, n_spec, static_cast<const float*>(d_part), d_ccf, d_rv);
+  return launch_fit_npt(c, nlb, n_spec, static_cast<const double*>(d_part), d_ccf, d_rv);
 }
 
 // ccf[i][v] = base[v] + sum_k coef[i][k] basis[k][v] (double, increasing k):

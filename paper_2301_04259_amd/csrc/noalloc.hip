@@ -17,8 +17,8 @@
 
 namespace {
 
-// 32 MiB: the partial CCFs of the headline mask (125 line blocks x 161
-// velocities) for about 200 spectra
+// 32 MiB: the FP32 partial CCFs of the headline mask (125 line blocks x 161
+// velocities) for about 400 spectra
 constexpr size_t SCRATCH_BYTES = size_t(32) << 20;
 constexpr int MAX_DEVICES = 64;
 
@@ -80,7 +80,7 @@ SOAP_API soap_status soap_ccf_rv_noalloc(soap_ctx* c, const void* flux, int64_t 
   }
   const int nl = (int)c->mask_lnl.size();
   const size_t rows = (size_t)n_spec * c->mask_nv;
-  const size_t part_bytes = sizeof(double) * rows * soap::ccf_line_blocks(nl);
+  const size_t part_bytes = c->esize * rows * soap::ccf_line_blocks(nl);
   const size_t ccf_bytes = ccf_out ? 0 : sizeof(double) * rows;
   const size_t part_al = (part_bytes + 255) / 256 * 256;
   if (part_al + ccf_bytes > SCRATCH_BYTES) {
@@ -91,7 +91,7 @@ SOAP_API soap_status soap_ccf_rv_noalloc(soap_ctx* c, const void* flux, int64_t 
     c->err = msg;
     return SOAP_ERR_UNSUPPORTED;
   }
-  double* part = static_cast<double*>(base);
+  void* part = base;
   double* ccf = ccf_out ? ccf_out : reinterpret_cast<double*>(static_cast<unsigned char*>(base) + part_al);
   hipError_t e = soap::launch_ccf(c, flux, n_spec, nl, part);
   if (e == hipSuccess) e = soap::launch_ccf_fit(c, nl, part, n_spec, ccf, rv_out);

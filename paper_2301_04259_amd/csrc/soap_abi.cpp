@@ -930,7 +930,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   }
   const int nlb = soap::ccf_line_blocks(nl);
   const size_t ccf_elems = (size_t)n_spec * c->mask_nv;
-  HIP_TRY(grow(c->ws_ccf, sizeof(double) * ccf_elems * nlb));
+  HIP_TRY(grow(c->ws_ccf, c->esize * ccf_elems * nlb));
   double* dccf = (ccf_out && ccf_on_device) ? ccf_out : nullptr;
   if (!dccf) {
     HIP_TRY(grow(c->ws_ccfout, sizeof(double) * ccf_elems));
@@ -938,7 +938,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   }
   {
     StageTimer t(c, ST_CCF);
-    HIP_TRY(soap::launch_ccf(c, dflux, n_spec, nl, static_cast<double*>(c->ws_ccf.ptr)));
+    HIP_TRY(soap::launch_ccf(c, dflux, n_spec, nl, c->ws_ccf.ptr));
     t.done();
   }
   c->ccf_calls++;
@@ -953,7 +953,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
   }
   {
     StageTimer t(c, ST_GFIT);
-    HIP_TRY(soap::launch_ccf_fit(c, nl, static_cast<const double*>(c->ws_ccf.ptr), n_spec, dccf, drv));
+    HIP_TRY(soap::launch_ccf_fit(c, nl, c->ws_ccf.ptr, n_spec, dccf, drv));
     t.done();
   }
   if (rv_out && !rv_on_device) {

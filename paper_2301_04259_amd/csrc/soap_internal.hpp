@@ -285,9 +285,12 @@ hipError_t launch_check_finite(soap_ctx* c, const void* base, int rows, bool wit
 // the velocity grid does not fit the kernel
 bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, std::vector<unsigned char>& blob,
                       std::string& err);
-hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, double* d_part);
-// sums the partial CCFs into d_ccf and, when d_rv is not null, fits them
-hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const double* d_part, int64_t n_spec, double* d_ccf,
+// partial CCFs per line block, [n_lb][n_spec][n_v] in the flux type (a block's
+// partial is a sum in that type)
+hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, void* d_part);
+// sums the partial CCFs (in double) into d_ccf and, when d_rv is not null,
+// fits them
+hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const void* d_part, int64_t n_spec, double* d_ccf,
                           soap_rv* d_rv);
 hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, int k, const double* d_base,
                                  const double* d_basis, double* d_lin, double* d_ccf, soap_rv* d_rv);
