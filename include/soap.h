@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define SOAP_ABI_VERSION 2
+#define SOAP_ABI_VERSION 3
 
 typedef enum {
   SOAP_OK = 0,
@@ -354,28 +354,27 @@ soap_status soap_surrogate_rv(soap_ctx* ctx, const float* coef, const float* mem
                               const double* basis, double calib, double threshold_kms, soap_rv* rv_out,
                               double* rv_kms, double* err_kms, int32_t* fallback);
 
-/* Shape of the shift-and-sum kernel and its tuner.  A block of `threads`
- * threads (64, 128, 256 or 512) covers a tile of 4 x threads pixels for one
- * chunk of phases; `lds_win` (1 .. 48) window records are staged in LDS per
- * pass.  With `staged`, the block first copies each window's source spans
- * (the tile's samples plus 12, its quiet samples and contrast values) to LDS
- * with coalesced loads, double-buffered, and threads read their windows
- * from there.  Every shape gives the same result bit for bit (each pixel
- * adds its windows in the same order); only the time differs.               */
+/* Shape of the shift-and-sum kernel and its tuner.  A block of four waves
+ * covers a tile of pixels (2048 in FP32, 1024 in FP64) for one chunk of
+ * phases (8 in FP32, 4 in FP64); every wave keeps `depth` (2 or 3) windows
+ * of source samples in flight (the loads of the next depth - 1 windows are
+ * issued before the current one is consumed).  `order` picks how each XCD
+ * walks its (tile, chunk) items: 0 = chunks with the most windows first,
+ * 1 = tile by tile (all chunks of a tile together).  Every shape gives the
+ * same result bit for bit (each pixel adds its windows in the same order);
+ * only the time differs.                                                     */
 typedef struct {
-  int32_t threads;
-  int32_t lds_win;
-  int32_t staged;            /* 1: the block stages each window's source
-                                spans in LDS (256 threads only)             */
-  int32_t reserved0;
+  int32_t depth;
+  int32_t order;
   double apply_us;           /* measured time of one launch of the choice   */
   int32_t from_cache;        /* 1: taken from the cache file, not timed     */
   int32_t n_tried;           /* shapes timed                                */
   char key[128];             /* cache key of the workload shape             */
 } soap_tune;
 
-/* Sets the shape used by later calls on ctx.                                 */
-soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t threads, int32_t lds_win, int32_t staged);
+/* Sets the shape used by later calls on ctx; SOAP_ERR_ARG for a depth other
+ * than 2 or 3 or an order other than 0 or 1.                                 */
+soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t depth, int32_t order);
 
 /* Runs soap_active_spectra once on the given workload (arguments as there),
  * then times every shape on its tap lists (10 launches each, HIP events on

@@ -214,10 +214,8 @@ _lib.soap_surrogate_rv.argtypes = [_ctx_p, C.c_void_p, C.c_void_p, C.c_int64, C.
 _lib.soap_surrogate_rv.restype = C.c_int
 class TuneC(C.Structure):
     _fields_ = [
-        ("threads", C.c_int32),
-        ("lds_win", C.c_int32),
-        ("staged", C.c_int32),
-        ("reserved0", C.c_int32),
+        ("depth", C.c_int32),
+        ("order", C.c_int32),
         ("apply_us", C.c_double),
         ("from_cache", C.c_int32),
         ("n_tried", C.c_int32),
@@ -225,7 +223,7 @@ class TuneC(C.Structure):
     ]
 
 
-_lib.soap_set_apply_shape.argtypes = [_ctx_p, C.c_int32, C.c_int32, C.c_int32]
+_lib.soap_set_apply_shape.argtypes = [_ctx_p, C.c_int32, C.c_int32]
 _lib.soap_set_apply_shape.restype = C.c_int
 _lib.soap_autotune.argtypes = [_ctx_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_char_p,
                                C.POINTER(TuneC)]
@@ -770,8 +768,8 @@ def soap_surrogate_rv(ctx, coef, members, base, basis, calib, threshold_kms, rv_
     _check(st, ctx.handle)
 
 
-def soap_set_apply_shape(ctx, threads, lds_win, staged=False):
-    _check(_lib.soap_set_apply_shape(ctx.handle, int(threads), int(lds_win), 1 if staged else 0), ctx.handle)
+def soap_set_apply_shape(ctx, depth=2, order=0):
+    _check(_lib.soap_set_apply_shape(ctx.handle, int(depth), int(order)), ctx.handle)
 
 
 def soap_autotune(ctx, regions, phases, effect, cache_path=None):
@@ -782,7 +780,7 @@ def soap_autotune(ctx, regions, phases, effect, cache_path=None):
     st = _lib.soap_autotune(ctx.handle, C.cast(regs, C.c_void_p), len(regions), ph.ctypes.data, len(ph), int(effect),
                             None if cache_path is None else os.fsencode(cache_path), C.byref(t))
     _check(st, ctx.handle)
-    return {"threads": t.threads, "lds_win": t.lds_win, "staged": bool(t.staged), "apply_us": t.apply_us,
+    return {"depth": t.depth, "order": t.order, "apply_us": t.apply_us,
             "from_cache": bool(t.from_cache),
             "n_tried": t.n_tried, "key": t.key.decode()}
 

@@ -587,21 +587,31 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   constexpr int NW = CCF_FIN_THREADS / 64;
-  constexpr int RB = NPT <= 3 ? 16 : (NPT <= 6 ? 8 : 4);  // rows in flight per wave
+  constexpr int RB = (NPT <= 3 ? 16 : (NPT <= 6 ? 8 : 4)) / (sizeof(PT) == 8 ? 2 : 1);  // rows in flight per wave
   {
     double acc[NPT];
 #pragma unroll
     for (int t = 0; t < NPT; ++t) acc[t] = 0.0;
     for (int lb0 = wave; lb0 < n_lb; lb0 += RB * NW) {
       double v[RB][NPT];
+      // every load is unconditional (indices clamped into the rows) and the
+      // out-of-range values are zeroed after it: loads under a branch would
+      // each be waited for before the next one is issued
+      PT raw[RB][NPT];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) {
+        const int lb = min(lb0 + u * NW, n_lb - 1);
+        const PT* src = part + ((int64_t)lb * n_spec + s) * n_v;
+#pragma unroll
+        for (int t = 0; t < NPT; ++t) raw[u][t] = src[min(lane + 64 * t, n_v - 1)];
+      }
 #pragma unroll
       for (int u = 0; u < RB; ++u) {
         const int lb = lb0 + u * NW;
-        const PT* src = part + ((int64_t)lb * n_spec + s) * n_v;
 #pragma unroll
         for (int t = 0; t < NPT; ++t) {
           const int i = lane + 64 * t;
-          v[u][t] = (lb < n_lb && i < n_v) ? (double)src[i] : 0.0;
+          v[u][t] = (lb < n_lb && i < n_v) ? (double)raw[u][t] : 0.0;
         }
       }
 #pragma unroll

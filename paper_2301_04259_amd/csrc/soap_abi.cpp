@@ -1068,11 +1068,15 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
         const unsigned char* rec = vg.data() + ((size_t)ch * c->last_vg_cap + v) * soap::WIN_BYTES;
         std::memcpy(&h, rec, sizeof(h));
         {
-          // taps[q][p] after the header, float or double per the precision
-          // one mask bit per (offset, four-phase group) with a non-zero tap
-          int pairs = 0;
+          // taps[q][p] after the header, float or double per the precision;
+          // one mask bit per (offset, pair of phases) with a non-zero tap:
+          // each bit costs two FMAs per pixel, each offset with a bit one
+          // difference formation
+          int pairs = 0, offs = 0;
           for (unsigned m = h.gmask; m; m &= m - 1) ++pairs;
-          out->fma_issued += (int64_t)pairs * 4 + soap::APPLY_JW;
+          for (int q = 0; q < soap::APPLY_JW; ++q)
+            if ((h.gmask >> (q * (c->pc / 2))) & ((1u << (c->pc / 2)) - 1u)) ++offs;
+          out->fma_issued += (int64_t)pairs * 2 + offs;
           for (int q = 0; q < soap::APPLY_JW; ++q) {
             bool any = false;
             for (int pp = 0; pp < c->pc; ++pp) {

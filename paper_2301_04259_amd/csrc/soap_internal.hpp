@@ -26,20 +26,24 @@ constexpr int MAX_GRID = 4096;
 constexpr int MAX_PHASES = 1 << 20;
 constexpr int MAX_J = 64;  // tap offsets per table row
 
-// Apply kernel shape: THREADS threads x APPLY_R consecutive pixels per tile
-// (THREADS one of 64, 128, 256, 512, chosen per context by the tuner; 256 by
-// default); a block runs one (tile, chunk of PC phases: 16 in FP32, 8 in
-// FP64) item over the chunk's windows of APPLY_JW offsets.  Quiet spectrum and rows are padded to whole
-// tiles of the widest shape.
-constexpr int APPLY_R = 4;
-constexpr int APPLY_JW = 8;
-constexpr int APPLY_THREADS = 256;
-constexpr int APPLY_THREADS_MAX = 512;
-constexpr int APPLY_TILE = APPLY_R * APPLY_THREADS;
-constexpr int APPLY_TILE_MAX = APPLY_R * APPLY_THREADS_MAX;
+// Apply kernel shape: a block of APPLY_WAVES waves covers a tile of
+// APPLY_WAVES x 64 x R consecutive pixels for one chunk of PC phases, R = 8
+// and PC = 8 in FP32, R = 4 and PC = 4 in FP64 (ApplyShape); each wave walks
+// the chunk's windows of APPLY_JW offsets over its own 64 x R pixels.  Quiet
+// spectrum and rows are padded to whole tiles of APPLY_TILE_MAX pixels.
+constexpr int APPLY_JW = 4;
+constexpr int APPLY_WAVES = 4;
+constexpr int APPLY_TILE_MAX = 2048;
 constexpr int PC_MAX = 16;
-constexpr int PC_F32 = 16;
-constexpr int PC_F64 = 8;
+constexpr int PC_F32 = 8;
+constexpr int PC_F64 = 4;
+template <typename T>
+struct ApplyShape {
+  static constexpr int R = sizeof(T) == 4 ? 8 : 4;     // pixels per lane
+  static constexpr int PC = sizeof(T) == 4 ? PC_F32 : PC_F64;  // phases per chunk
+  static constexpr int TILE = APPLY_WAVES * 64 * R;    // pixels per block
+};
+static_assert(ApplyShape<float>::TILE <= APPLY_TILE_MAX && ApplyShape<double>::TILE <= APPLY_TILE_MAX, "padding");
 
 // Padded rows of the local spectra and contrast arrays: PAD_FRONT copies of
 // the first sample before it and copies of the last sample after it, so that
@@ -76,8 +80,8 @@ struct Region {
 // A window record: APPLY_JW tap offsets [jlo, jlo + APPLY_JW) of one group
 // in one phase chunk, stored as a 16-byte header followed by the dense taps
 // taps[q][p] (q < APPLY_JW, p < the chunk's phase count; zeros where a phase
-// has no tap).  Bit (q * NG + k) of gmask: some phase of the k-th group of
-// four phases has a non-zero tap at offset jlo + q (NG = phases / 4).
+// has no tap).  Bit (q * PC / 2 + k) of gmask: phase 2k or 2k + 1 of the
+// chunk has a non-zero tap at offset jlo + q.
 // Group g: paired tables g = (type - 1) * B + bin; split tables
 // g = type * B + bin with type 0 the quiet removal.
 struct WinHead {
@@ -86,12 +90,12 @@ struct WinHead {
   int jlo;
   unsigned int gmask;
 };
-constexpr int WIN_TAP_BYTES = 512;  // APPLY_JW x 16 floats or APPLY_JW x 8 doubles
+constexpr int WIN_TAP_BYTES = 128;  // APPLY_JW x 8 floats or APPLY_JW x 4 doubles
 constexpr int WIN_BYTES = 16 + WIN_TAP_BYTES;
+// window records staged in LDS per pass of the apply kernel
+constexpr int APPLY_LDS_WIN = 96;
 static_assert(APPLY_JW * PC_F32 * 4 == WIN_TAP_BYTES && APPLY_JW * PC_F64 * 8 == WIN_TAP_BYTES,
               "window record size");
-// windows staged in LDS per pass of the apply kernel
-constexpr int APPLY_LDS_WIN = 48;
 // phase chunks the apply kernel orders by work (more run in their natural order)
 constexpr int APPLY_RANKED = 64;
 
@@ -120,9 +124,8 @@ struct soap_ctx {
   int64_t P = 0;
   int64_t Pstride = 0;  // padded row length (elements); row data starts at PAD_FRONT
   int n_tiles = 0;  // tiles of APPLY_TILE_MAX pixels (padding)
-  int tune_threads = soap::APPLY_THREADS;  // apply shape in use (the tuner's choice)
-  int tune_lds_win = soap::APPLY_LDS_WIN;
-  int tune_staged = 0;  // 1: source spans staged in LDS (256-thread tiles)
+  int tune_depth = 2;   // windows in flight per wave (2 or 3)
+  int tune_order = 0;   // item order: 0 heaviest chunk first, 1 tile by tile
   double vsini = 0, incl = 0, u1 = 0, u2 = 0, ln0 = 0, dln = 0;
   double diff_rot = 0;  // omega(theta) = omega_0 (1 + diff_rot sin^2 theta)
   double sin_i = 0, cos_i = 1;
@@ -254,7 +257,7 @@ hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const in
 // apply with an explicit shape (threads per block, windows staged per LDS
 // pass) on stream st
 hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux,
-                              int threads, int lds_win, bool staged, hipStream_t st);
+                              int depth, int order, hipStream_t st);
 
 // batched shift-and-sum: one launch over the (tile, chunk) items of many
 // configurations of one precision and table mode (256-thread blocks)
@@ -267,7 +270,7 @@ struct ApplyBatchCfg {
 };
 struct ApplyBatchGroup {
   bool fp32 = true, paired = true;
-  int n_cfg = 0, n_items = 0, lds_win = 1;
+  int n_cfg = 0, n_items = 0, depth = 2, order = 0;
   void* args = nullptr;  // device ApplyArgs[n_cfg]
   void* off = nullptr;   // device item offsets [n_cfg + 1]
 };

@@ -1,5 +1,5 @@
 // Tuner of the shift-and-sum kernel's shape (include/soap.h, soap_autotune):
-// times every (threads per block, windows staged per LDS pass) variant on a
+// times every (windows in flight per wave, item order) variant on a
 // context's real tap lists and keeps the fastest, with a file cache keyed by
 // the shape of the work.
 #include <hip/hip_runtime.h>
@@ -17,8 +17,8 @@
 
 namespace {
 
-constexpr int kThreads[] = {64, 128, 256, 512};
-constexpr int kWins[] = {16, 32, 48};
+constexpr int kDepths[] = {2, 3};
+constexpr int kOrders[] = {0, 1};
 
 int ilog2_ceil(long long v) {
   int b = 0;
@@ -26,9 +26,9 @@ int ilog2_ceil(long long v) {
   return b;
 }
 
-// cache file: one entry per line, `"key": [threads, lds_win, staged, apply_us],`
+// cache file: one entry per line, `"key": [depth, order, apply_us],`
 // inside a JSON object
-bool cache_lookup(const char* path, const std::string& key, int* th, int* lw, int* sg, double* us) {
+bool cache_lookup(const char* path, const std::string& key, int* dp, int* od, double* us) {
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
   char line[512];
@@ -38,13 +38,13 @@ bool cache_lookup(const char* path, const std::string& key, int* th, int* lw, in
     const char* p = std::strstr(line, want.c_str());
     if (!p) continue;
     p = std::strchr(p + want.size(), '[');
-    if (p && std::sscanf(p, "[%d , %d , %d , %lf", th, lw, sg, us) == 4) found = true;
+    if (p && std::sscanf(p, "[%d , %d , %lf", dp, od, us) == 3) found = true;
   }
   std::fclose(f);
   return found;
 }
 
-bool cache_store(const char* path, const std::string& key, int th, int lw, int sg, double us) {
+bool cache_store(const char* path, const std::string& key, int dp, int od, double us) {
   std::vector<std::string> keep;
   if (FILE* f = std::fopen(path, "r")) {
     char line[512];
@@ -58,7 +58,7 @@ bool cache_store(const char* path, const std::string& key, int th, int lw, int s
     std::fclose(f);
   }
   char entry[512];
-  std::snprintf(entry, sizeof entry, "  \"%s\": [%d, %d, %d, %.3f]", key.c_str(), th, lw, sg, us);
+  std::snprintf(entry, sizeof entry, "  \"%s\": [%d, %d, %.3f]", key.c_str(), dp, od, us);
   keep.push_back(entry);
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "w");
@@ -72,16 +72,16 @@ bool cache_store(const char* path, const std::string& key, int th, int lw, int s
 
 }  // namespace
 
-SOAP_API soap_status soap_set_apply_shape(soap_ctx* c, int32_t threads, int32_t lds_win, int32_t staged) {
+SOAP_API soap_status soap_set_apply_shape(soap_ctx* c, int32_t depth, int32_t order) {
   if (!c) return SOAP_ERR_ARG;
-  const bool t_ok = std::find(std::begin(kThreads), std::end(kThreads), threads) != std::end(kThreads);
-  if (!t_ok || lds_win < 1 || lds_win > soap::APPLY_LDS_WIN || (staged != 0 && threads != soap::APPLY_THREADS)) {
-    c->err = "threads must be 64, 128, 256 or 512 (256 when staged) and lds_win in [1, 48]";
+  const bool d_ok = std::find(std::begin(kDepths), std::end(kDepths), depth) != std::end(kDepths);
+  const bool o_ok = std::find(std::begin(kOrders), std::end(kOrders), order) != std::end(kOrders);
+  if (!d_ok || !o_ok) {
+    c->err = "depth must be 2 or 3 and order 0 or 1";
     return SOAP_ERR_ARG;
   }
-  c->tune_threads = threads;
-  c->tune_lds_win = lds_win;
-  c->tune_staged = staged != 0;
+  c->tune_depth = depth;
+  c->tune_order = order;
   return SOAP_OK;
 }
 
@@ -127,13 +127,11 @@ SOAP_API soap_status soap_autotune(soap_ctx* c, const soap_region* regions, int3
   std::snprintf(key, sizeof key, "%s|%s|P2^%d|J%d|B%d|ph2^%d|win2^%d", c->prec == SOAP_PREC_FP32 ? "f32" : "f64",
                 pl.paired ? "paired" : "split", ilog2_ceil(c->P), c->J, c->B, ilog2_ceil(pl.n_ph),
                 ilog2_ceil(std::max(1LL, tot / std::max(1, pl.n_chunks))));
-  int th = 0, lw = 0, sg = 0;
+  int dp = 0, od = 0;
   double us = 0.0;
-  if (cache_path && cache_lookup(cache_path, key, &th, &lw, &sg, &us) &&
-      soap_set_apply_shape(c, th, lw, sg) == SOAP_OK) {
-    out->threads = th;
-    out->lds_win = lw;
-    out->staged = sg;
+  if (cache_path && cache_lookup(cache_path, key, &dp, &od, &us) && soap_set_apply_shape(c, dp, od) == SOAP_OK) {
+    out->depth = dp;
+    out->order = od;
     out->apply_us = us;
     out->from_cache = 1;
     std::snprintf(out->key, sizeof out->key, "%s", key);
@@ -143,20 +141,15 @@ SOAP_API soap_status soap_autotune(soap_ctx* c, const soap_region* regions, int3
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(SOAP_ERR_HIP, "autotune: event creation failed");
   double best = 1e300;
-  int bt = c->tune_threads, bw = c->tune_lds_win, bs = c->tune_staged, tried = 0;
+  int bd = c->tune_depth, bo = c->tune_order, tried = 0;
   constexpr int kReps = 10;
-  for (int shape = 0; shape < 5; ++shape) {
-    const int t = shape < 4 ? kThreads[shape] : soap::APPLY_THREADS;
-    const int sgd = shape == 4 ? 1 : 0;  // the LDS-staged variant
-    for (int w : kWins) {
-      if (w > std::max(16, pl.vg_cap) && w != kWins[0]) continue;  // same as a smaller staging
+  for (int d : kDepths) {
+    for (int o : kOrders) {
       for (int r = 0; r < 2; ++r)
-        (void)soap::launch_apply_shape(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), tmp, t, w, sgd,
-                                       c->stream);
+        (void)soap::launch_apply_shape(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), tmp, d, o, c->stream);
       (void)hipEventRecord(e0, c->stream);
       for (int r = 0; r < kReps; ++r)
-        (void)soap::launch_apply_shape(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), tmp, t, w, sgd,
-                                       c->stream);
+        (void)soap::launch_apply_shape(c, pl, S.vg.ptr, static_cast<const int*>(S.nvg.ptr), tmp, d, o, c->stream);
       (void)hipEventRecord(e1, c->stream);
       if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) {
         (void)hipEventDestroy(e0);
@@ -169,24 +162,21 @@ SOAP_API soap_status soap_autotune(soap_ctx* c, const soap_region* regions, int3
       ++tried;
       if (t_us < best) {
         best = t_us;
-        bt = t;
-        bw = w;
-        bs = sgd;
+        bd = d;
+        bo = o;
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->tune_threads = bt;
-  c->tune_lds_win = bw;
-  c->tune_staged = bs;
-  out->threads = bt;
-  out->lds_win = bw;
-  out->staged = bs;
+  c->tune_depth = bd;
+  c->tune_order = bo;
+  out->depth = bd;
+  out->order = bo;
   out->apply_us = best;
   out->n_tried = tried;
   std::snprintf(out->key, sizeof out->key, "%s", key);
-  if (cache_path && !cache_store(cache_path, key, bt, bw, bs, best))
+  if (cache_path && !cache_store(cache_path, key, bd, bo, best))
     return fail(SOAP_ERR_ARG, "autotune: cannot write the cache file");
   return fail(SOAP_OK, nullptr);
 }

@@ -25,8 +25,8 @@
 // the order).  k_finish, one block per chunk of phases, converts the tables
 // to double (clearing them for the next call), records per (phase, group)
 // the bitmask of non-zero offsets, and turns the chunk into window records
-// of APPLY_JW offsets with dense taps and per-offset masks of the groups of
-// four phases that have a tap.
+// of APPLY_JW offsets with dense taps and per-offset masks of the pairs of
+// phases that have a tap.
 // Every sum has a fixed order, so results repeat bit for bit.
 #include <algorithm>
 #include <type_traits>
@@ -52,7 +52,7 @@ __device__ __forceinline__ unsigned long long to_fx(double x) {
 
 // Window records of one chunk of PC phases (one block): windows of APPLY_JW
 // offsets with their dense [offset][phase] taps and per-offset masks of the
-// groups of four phases that have a tap.  Kc: the chunk's taps [np][G][J],
+// pairs of phases that have a tap.  Kc: the chunk's taps [np][G][J],
 // maskc: its offset masks [np][G] (LDS or global).  sm: LDS of at least
 // (4 G + vg_cap + 2) ints + G 64-bit words.
 template <typename T>
@@ -67,7 +67,7 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
   unsigned long long* s_union = reinterpret_cast<unsigned long long*>(sm + 4 * G + vg_cap + (vg_cap & 1));  // [G]
   const int p0 = chunk * PC;
   const int np = min(PC, n_ph - p0);
-  const int NG = PC / 4;
+  const int NP = PC / 2;  // mask bits per offset: pairs of phases
   const int GJ = G * J;
   const int nwin = (J + APPLY_JW - 1) / APPLY_JW;
   unsigned char* wrec = wins + (int64_t)chunk * vg_cap * WIN_BYTES;
@@ -131,7 +131,7 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
     for (int p = 0; p < PC_MAX; ++p) {
       if (p < PC) {
         row[p] = (T)kv[p];
-        if (kv[p] != 0.0) m |= 1u << ((q * NG) + (p >> 2));
+        if (kv[p] != 0.0) m |= 1u << ((q * NP) + (p >> 1));
       }
     }
     if (m) atomicOr(&s_gm[v], m);

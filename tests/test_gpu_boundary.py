@@ -92,8 +92,11 @@ def test_fit_status_of_nan_and_flat_ccfs():
     q = np.zeros(star.n_pix)
     L.soap_quiet_spectrum(ctx, q)
     m = star.mask
-    # a NaN inside a mask line's holes, a flat spectrum (its CCF is flat to
-    # rounding: depth below 1e-12 of the continuum), and the quiet spectrum
+    # a NaN inside a mask line's holes, a flat spectrum, and the quiet
+    # spectrum.  The flat spectrum's CCF is not flat to rounding: each hole
+    # spans atanh((v + h)/c) - atanh((v - h)/c) in ln(lambda), which grows
+    # with |v| relatively by about (v/c)^2 (4e-9 at 20 km/s), so its fit has
+    # nothing to converge to and must not report success (status 1 or 2).
     lnl = star.ln_lambda0 + star.dln_lambda * np.arange(star.n_pix)
     k = int(np.argmin(np.abs(lnl - m.ln_lambda[len(m.ln_lambda) // 2])))
     rows = np.stack([q.copy(), np.full(star.n_pix, 2.5), q.copy()])
@@ -104,5 +107,7 @@ def test_fit_status_of_nan_and_flat_ccfs():
     L.soap_ccf_rv(ctx, rows, m, ccf_out=ccf, rv_out=rv)
     assert not np.all(np.isfinite(ccf[0]))
     assert rv["status"][0] == 2, rv
-    assert rv["status"][1] == 2, rv
+    c1 = ccf[1]
+    assert np.all(np.isfinite(c1)) and (c1.max() - c1.min()) <= 1e-7 * c1.max()
+    assert rv["status"][1] in (1, 2), rv
     assert rv["status"][2] == 0, rv
