@@ -104,9 +104,12 @@ def test_noalloc_errors():
         L.soap_ccf_rv_noalloc(ctx, flux, st.mask, rv_out=_rv_dev(3))  # no mask on the context yet
     assert e.value.status == L.SOAP_ERR_STATE
     L.soap_ccf_rv(ctx, flux, st.mask, rv_out=L.rv_records(3))
-    # 40000 spectra x 61 velocities x (1 line block + the CCF rows) x 8 B
-    # exceed the 32 MiB array: refused before anything is enqueued
-    big = torch.empty((40000, st.n_pix), dtype=torch.float32, device="cuda")
+    # n spectra need n n_v (4 ceil(lines / 32) + 8) bytes without a CCF
+    # buffer (FP32 partials, double CCF rows): past the 32 MiB array for this
+    # n, so the call is refused before anything is enqueued
+    n_lb = -(-len(st.mask.ln_lambda) // 32)
+    n = (32 << 20) // (st.mask.n_v * (4 * n_lb + 8)) + 64
+    big = torch.empty((n, st.n_pix), dtype=torch.float32, device="cuda")
     with pytest.raises(L.SoapError) as e:
         L.soap_ccf_rv_noalloc(ctx, big, st.mask)
     assert e.value.status == L.SOAP_ERR_UNSUPPORTED
