@@ -367,6 +367,9 @@ def main():
     ap.add_argument("--batch-configs", type=int, default=512,
                     help="configurations of the batched-graph leg (0 = skip the leg)")
     ap.add_argument("--batch-runs", type=int, default=5)
+    ap.add_argument("--tune", type=int, default=1,
+                    help="time the shift-and-sum shapes first and keep the fastest (0 = the default shape, so that "
+                    "a kernel trace holds only the timed shape's launches)")
     ap.add_argument("--extra-legs", type=int, default=1,
                     help="time the headline step with the solar differential rotation and the resolution "
                     "lowering kernel (0 = skip)")
@@ -429,8 +432,10 @@ def main():
         L.soap_active_spectra(ctx, regions, phases, W.EFFECT_TOT, flux)
         L.soap_ccf_rv(ctx, flux, m, ccf_out=ccf, rv_out=rv)
 
-    print("[bench] tuning the shift-and-sum shape", file=sys.stderr, flush=True)
-    tune = L.soap_autotune(ctx, regions, phases, W.EFFECT_TOT)
+    tune = None
+    if args.tune:
+        print("[bench] tuning the shift-and-sum shape", file=sys.stderr, flush=True)
+        tune = L.soap_autotune(ctx, regions, phases, W.EFFECT_TOT)
 
     print("[bench] warmup", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
