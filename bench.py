@@ -269,14 +269,14 @@ def surrogate_leg(args, L, W, np, torch):
         "stars": len(used),
         "train_samples": train.n,
     }
-    res.update(_surrogate_timing(S, np, torch, model, stars, mask, test))
+    res.update(_surrogate_timing(S, np, torch, model, stars, mask, test, info.get("calib_alpha0")))
     res.update(info)
     for c in stars.ctxs:
         L.soap_destroy(c)
     return res
 
 
-def _surrogate_timing(S, np, torch, model, stars, mask, test):
+def _surrogate_timing(S, np, torch, model, stars, mask, test, calib_alpha0=None):
     """RV/s of the full synthesis, of the surrogate kernels alone and of the
     gated surrogate (fallback samples through the full synthesis inside the
     timed region) on the same resident test samples, and the accepted
@@ -301,6 +301,16 @@ def _surrogate_timing(S, np, torch, model, stars, mask, test):
     t_gated, (rv_s, fb, _) = timed(lambda: model.rv(test, idx, bufs), 5)
     e = np.abs(rv_s - rv_plain) * 1e5
     acc = ~fb
+    alpha0 = None
+    if calib_alpha0 is not None:
+        # the same gate with the factor that let no held-out sample miss
+        t0g, (rv0, fb0, _) = timed(lambda: model.rv(test, idx, bufs, calib=calib_alpha0), 5)
+        e0 = np.abs(rv0 - rv_plain) * 1e5
+        a0 = ~fb0
+        alpha0 = {"calib": calib_alpha0, "gated_rv_per_s": nt / t0g, "surrogate_x": t_plain / t0g,
+                  "accepted_frac": float(a0.mean()),
+                  "accepted_err_cms_max": float(e0[a0].max()) if a0.any() else None,
+                  "accepted_frac_over_10": float(np.mean(e0[a0] > 10.0)) if a0.any() else None}
     return {
         "test_samples": nt,
         "plain_rv_per_s": nt / t_plain,
@@ -313,6 +323,7 @@ def _surrogate_timing(S, np, torch, model, stars, mask, test):
                              "frac_over_10": float(np.mean(e[acc] > 10.0)) if acc.any() else None},
         "fallback_bit_exact": bool(np.array_equal(rv_s[fb], rv_plain[fb])),
         "threshold_cms": 10.0,
+        "gate_alpha0": alpha0,
     }
 
 
@@ -343,7 +354,7 @@ def surrogate_single_leg(args, L, W, np, torch):
         "train_samples": train.n,
         "epochs": max(1, args.surrogate_epochs // 2),
     }
-    res.update(_surrogate_timing(S, np, torch, model, model.stars, star.mask, test))
+    res.update(_surrogate_timing(S, np, torch, model, model.stars, star.mask, test, info.get("calib_alpha0")))
     res.update({k: info[k] for k in ("calib", "heldout_accepted_frac", "train_s") if k in info})
     L.soap_destroy(ctx)
     return res

@@ -362,8 +362,8 @@ __global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, EFF, DEP
 // its own arguments).  Configuration i owns the slots item_off[i] ..
 // item_off[i+1] - 1, a multiple of 8 starting at a multiple of 8, mapped as
 // in k_apply.
-template <typename T, bool PAIRED, int DEP>
-__global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, -1, DEP>()))
+template <typename T, bool PAIRED, int EFF, int DEP>
+__global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, EFF, DEP>()))
     k_apply_batch(const ApplyArgs<T>* __restrict__ args, const int* __restrict__ item_off, int n_cfg) {
   __shared__ __align__(16) unsigned char lds[APPLY_LDS_WIN * WIN_BYTES];
   const int b = blockIdx.x;
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, -1, DEP>
   const ApplyArgs<T> A = args[lo];
   int tile, chunk;
   if (!map_item(A, b - item_off[lo], &tile, &chunk)) return;
-  apply_item<T, PAIRED, -1, DEP>(A, tile, chunk, lds);
+  apply_item<T, PAIRED, EFF, DEP>(A, tile, chunk, lds);
 }
 
 namespace {
@@ -454,15 +454,31 @@ hipError_t upload_t(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGro
   return hipMemcpy(g->off, off.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
 }
 
-template <typename T, bool PAIRED>
-void launch_batch_t(const ApplyBatchGroup& g, hipStream_t st) {
+template <typename T, bool PAIRED, int EFF>
+void launch_batch_e(const ApplyBatchGroup& g, hipStream_t st) {
   const dim3 grid((unsigned)g.n_items), block(APPLY_WAVES * 64);
   const auto* a = static_cast<const ApplyArgs<T>*>(g.args);
   const int* off = static_cast<const int*>(g.off);
   if (g.depth >= 3)
-    hipLaunchKernelGGL((k_apply_batch<T, PAIRED, 3>), grid, block, 0, st, a, off, g.n_cfg);
+    hipLaunchKernelGGL((k_apply_batch<T, PAIRED, EFF, 3>), grid, block, 0, st, a, off, g.n_cfg);
   else
-    hipLaunchKernelGGL((k_apply_batch<T, PAIRED, 2>), grid, block, 0, st, a, off, g.n_cfg);
+    hipLaunchKernelGGL((k_apply_batch<T, PAIRED, EFF, 2>), grid, block, 0, st, a, off, g.n_cfg);
+}
+
+// every configuration of a batch group has the group's effect
+template <typename T, bool PAIRED>
+void launch_batch_t(const ApplyBatchGroup& g, hipStream_t st) {
+  switch (g.effect) {
+    case SOAP_EFFECT_FLUX:
+      launch_batch_e<T, PAIRED, SOAP_EFFECT_FLUX>(g, st);
+      break;
+    case SOAP_EFFECT_BCONV:
+      launch_batch_e<T, PAIRED, SOAP_EFFECT_BCONV>(g, st);
+      break;
+    default:
+      launch_batch_e<T, PAIRED, SOAP_EFFECT_TOT>(g, st);
+      break;
+  }
 }
 
 }  // namespace
@@ -475,6 +491,9 @@ hipError_t apply_batch_upload(const ApplyBatchCfg* cfgs, int n, void* d_buf, App
   g->fp32 = cfgs[0].c->prec == SOAP_PREC_FP32;
   g->paired = cfgs[0].pl.paired != 0;
   g->depth = cfgs[0].c->tune_depth;
+  g->effect = cfgs[0].pl.effect;
+  for (int i = 1; i < n; ++i)
+    if (cfgs[i].pl.effect != g->effect) return hipErrorInvalidValue;  // one effect per group
   return g->fp32 ? upload_t<float>(cfgs, n, d_buf, g) : upload_t<double>(cfgs, n, d_buf, g);
 }
 

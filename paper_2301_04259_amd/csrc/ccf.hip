@@ -768,25 +768,35 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
     }
     return;
   }
+  // Loads are unconditional, with indices clamped into the rows (the lanes
+  // past the grid compute values that are never used): a load under a
+  // branch is waited for before the next one is issued.
   const double* bs = base + (int64_t)brow * n_v;
+  int vc[NPT];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) vc[t] = min(lane + 64 * t, n_v - 1);
   double y[NPT];
 #pragma unroll
-  for (int t = 0; t < NPT; ++t) {
-    const int v = lane + 64 * t;
-    y[t] = v < n_v ? bs[v] : 0.0;
-  }
+  for (int t = 0; t < NPT; ++t) y[t] = bs[vc[t]];
+  constexpr int JU = 8;  // basis rows in flight
   for (int k0 = 0; k0 < k; k0 += 64) {
     __syncthreads();
-    if (k0 + lane < k) s_c[lane] = (double)coef[i * k + k0 + lane];
+    s_c[lane] = k0 + lane < k ? (double)coef[i * k + min(k0 + lane, k - 1)] : 0.0;
     __syncthreads();
     const int kn = min(64, k - k0);
-    for (int j = 0; j < kn; ++j) {
-      const double cj = s_c[j];
-      const double* bj = basis + (int64_t)(k0 + j) * n_v;
+    for (int j0 = 0; j0 < kn; j0 += JU) {
+      double b[JU][NPT];
 #pragma unroll
-      for (int t = 0; t < NPT; ++t) {
-        const int v = lane + 64 * t;
-        if (v < n_v) y[t] = fma(cj, bj[v], y[t]);
+      for (int u = 0; u < JU; ++u) {
+        const double* bj = basis + (int64_t)(k0 + min(j0 + u, kn - 1)) * n_v;
+#pragma unroll
+        for (int t = 0; t < NPT; ++t) b[u][t] = bj[vc[t]];
+      }
+#pragma unroll
+      for (int u = 0; u < JU; ++u) {
+        const double cj = j0 + u < kn ? s_c[j0 + u] : 0.0;  // rows past kn add zero
+#pragma unroll
+        for (int t = 0; t < NPT; ++t) y[t] = fma(cj, b[u][t], y[t]);
       }
     }
   }
@@ -828,16 +838,25 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
       for (int e = 0; e < SG_MAX_ENS; ++e) dr[e] = 0.0;
       for (int k0 = 0; k0 < k; k0 += 64) {
         const int kk = k0 + lane;
-        double h = 0.0;
-        if (kk < k) {
-          const double* bk = basis + (int64_t)kk * n_v;
-          for (int v = 0; v < n_v; ++v) h = fma(bk[v], s_g[v], h);
+        const int kc = min(kk, k - 1);
+        const double* bk = basis + (int64_t)kc * n_v;
+        // four partial sums over v (16 samples in flight), added in a fixed order
+        double h4[4] = {0.0, 0.0, 0.0, 0.0};
+        int v = 0;
+        for (; v + 16 <= n_v; v += 16) {
+          double bv[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) bv[u] = bk[v + u];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) h4[u & 3] = fma(bv[u], s_g[v + u], h4[u & 3]);
         }
-        const double cm = kk < k ? (double)coef[i * k + kk] : 0.0;
+        for (; v < n_v; ++v) h4[0] = fma(bk[v], s_g[v], h4[0]);
+        const double h = kk < k ? (h4[0] + h4[1]) + (h4[2] + h4[3]) : 0.0;
+        const double cm = (double)coef[i * k + kc];
 #pragma unroll
         for (int e = 0; e < SG_MAX_ENS; ++e) {
           if (e < E) {
-            const double ye = kk < k ? (double)members[((int64_t)e * n + i) * k + kk] : 0.0;
+            const double ye = (double)members[((int64_t)e * n + i) * k + kc];
             dr[e] += h * (ye - cm);
           }
         }

@@ -270,7 +270,7 @@ struct ApplyBatchCfg {
 };
 struct ApplyBatchGroup {
   bool fp32 = true, paired = true;
-  int n_cfg = 0, n_items = 0, depth = 2, order = 0;
+  int n_cfg = 0, n_items = 0, depth = 2, order = 0, effect = SOAP_EFFECT_TOT;
   void* args = nullptr;  // device ApplyArgs[n_cfg]
   void* off = nullptr;   // device item offsets [n_cfg + 1]
 };

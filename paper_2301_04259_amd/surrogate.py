@@ -447,15 +447,19 @@ class SurrogateModel:
         r = torch.from_numpy(self.stars.rows(sample_stars(samples, idx))).cuda()
         return x, r
 
-    def rv(self, samples, idx, bufs, threshold_kms=None):
+    def rv(self, samples, idx, bufs, threshold_kms=None, calib=None):
         """Gated RVs (km/s, host float64) of samples[idx]; idx sorted, its
         length a multiple of 16.  Returns (rv, fallback flags, predicted
-        errors)."""
+        errors).  One device-to-host read brings back the flags, RVs and
+        errors together."""
+        torch = self.torch
         x, r = self.inputs(samples, idx)
-        self.surrogate_rv(x, r, bufs, threshold_kms=threshold_kms)
-        fb = bufs["fallback"].cpu().numpy().astype(bool)
-        out = bufs["rv_kms"].cpu().numpy().copy()
-        err = bufs["err"].cpu().numpy().copy()
+        self.surrogate_rv(x, r, bufs, calib=calib, threshold_kms=threshold_kms)
+        n = bufs["n"]
+        host = torch.stack([bufs["rv_kms"][:n], bufs["err"][:n], bufs["fallback"][:n].to(torch.float64)]).cpu().numpy()
+        out = host[0].copy()
+        err = host[1].copy()
+        fb = host[2] != 0.0
         sel = np.asarray(idx)[fb]
         if len(sel):
             out[fb] = plain_rv(self.stars, samples, self.mask, sel)["rv_kms"]
@@ -521,6 +525,9 @@ def build(stars, mask, train, heldout, n_components=64, hidden=256, n_ensemble=4
     rvp = plain_rv(stars, heldout, mask, np.arange(n_ho))["rv_kms"]
     err, spread = model.calibrate(heldout, np.arange(n_ho), rvp, model.alloc(n_ho), alpha=alpha)
     info["calib"] = model.calib
+    # the factor for no tolerated miss on the held-out set, for reporting
+    # the gate at alpha = 0 beside the chosen alpha
+    info["calib_alpha0"] = calib_for_miss_rate(err, spread, model.threshold_kms, 0.0)
     acc = model.calib * spread < model.threshold_kms
     info["heldout_accepted_frac"] = float(acc.mean())
     info["heldout_accepted_over_thr_frac"] = float(np.mean(err[acc] >= model.threshold_kms)) if acc.any() else 0.0
