@@ -31,6 +31,13 @@
  *   - Floating-point arrays of spectra and fluxes are float in SOAP_PREC_FP32
  *     contexts and double in SOAP_PREC_FP64 contexts.
  *   - A context is used by one host thread at a time.
+ *   - Every device allocation of the library counts against the cap set by
+ *     the environment variable SOAP_MAX_DEVICE_BYTES (bytes; unset, empty or
+ *     0 = no cap), read at each allocation.  An allocation that would take
+ *     the bytes the process holds past it fails as SOAP_ERR_OOM, with the
+ *     cap and the bytes held in the message; a value that is not a byte
+ *     count refuses every allocation.  soap_device_bytes reports the bytes
+ *     held.
  */
 #ifndef SOAP_H
 #define SOAP_H
@@ -460,6 +467,12 @@ const char* soap_status_string(soap_status status);
 
 /* SOAP_ABI_VERSION of the built library.                                      */
 int32_t soap_abi_version(void);
+
+/* Bytes of device memory the library holds in this process now (contexts,
+ * batches, surrogates and their workspaces; the fixed array of the
+ * allocation-free entry point is not an allocation and is not counted).
+ * Needs no device.                                                          */
+uint64_t soap_device_bytes(void);
 
 /* ---- learned surrogate --------------------------------------------------
  * Simulations at scale feed data-driven activity models (PCA of line-profile

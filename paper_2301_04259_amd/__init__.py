@@ -28,7 +28,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsoap.so")
+# SOAP_LIB names another build of the same library (the host-sanitizer
+# build); by default the in-tree libsoap.so is loaded
+LIB_PATH = os.environ.get("SOAP_LIB") or os.path.join(_HERE, "libsoap.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -64,6 +66,7 @@ SYMBOLS = (
     "soap_last_error",
     "soap_status_string",
     "soap_abi_version",
+    "soap_device_bytes",
     "soap_profile_enable",
     "soap_profile_read",
     "soap_ccf_linear_rv",
@@ -205,6 +208,8 @@ _lib.soap_profile_read.argtypes = [_ctx_p, C.POINTER(ProfileC)]
 _lib.soap_profile_read.restype = C.c_int
 _lib.soap_abi_version.argtypes = []
 _lib.soap_abi_version.restype = C.c_int32
+_lib.soap_device_bytes.argtypes = []
+_lib.soap_device_bytes.restype = C.c_uint64
 _lib.soap_ccf_linear_rv.argtypes = [_ctx_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
 _lib.soap_ccf_linear_rv.restype = C.c_int
@@ -333,6 +338,11 @@ def _check(st, ctx_handle):
 
 def abi_version():
     return int(_lib.soap_abi_version())
+
+
+def device_bytes():
+    """Bytes of device memory the library holds in this process."""
+    return int(_lib.soap_device_bytes())
 
 
 def soap_grid_init(star, stream=None):

@@ -1,6 +1,7 @@
 """Builds libsoap.so in-tree with hipcc for gfx950.
 
-    python paper_2301_04259_amd/build.py
+    python paper_2301_04259_amd/build.py              # libsoap.so
+    python paper_2301_04259_amd/build.py --sanitize   # _build_san/libsoap_san.so
 
 (run by path: importing the package would load the library being rebuilt)
 
@@ -22,7 +23,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsoap.so")
 
-SOURCES = ["geom.hip", "weights.hip", "apply.hip", "ccf.hip", "soap_abi.cpp", "surrogate.hip", "surrogate_abi.cpp", "tune.cpp", "batch.cpp", "lsf.hip", "noalloc.hip"]
+SOURCES = ["geom.hip", "weights.hip", "apply.hip", "ccf.hip", "soap_abi.cpp", "surrogate.hip", "surrogate_abi.cpp", "tune.cpp", "batch.cpp", "lsf.hip", "noalloc.hip", "devmem.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",
@@ -40,6 +41,9 @@ FLAGS = [
     "-I" + CSRC,
 ]
 
+# roctx ranges per stage (marker traces)
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+
 
 def hipcc() -> str:
     for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
@@ -48,9 +52,33 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+# Host-side AddressSanitizer and UndefinedBehaviorSanitizer for the runtime
+# and the C ABI (device code is built as usual): each flag applies to the host
+# pass only.  The result needs the sanitizer runtime loaded first
+# (LD_PRELOAD of SAN_RUNTIME) and is loaded through SOAP_LIB.
+SAN_FLAGS = [
+    "-Xarch_host", "-fsanitize=address",
+    "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined",
+    "-Xarch_host", "-fno-omit-frame-pointer",
+    "-Xarch_host", "-g",
+]
+SAN_BUILD = os.path.join(PKG, "_build_san")
+SAN_LIB = os.path.join(SAN_BUILD, "libsoap_san.so")
+
+
+def san_runtime() -> str:
+    """Path of clang's shared ASan runtime (it carries UBSan's handlers)."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("clang's shared ASan runtime not found")
+    return path
+
+
+def _compile(src: str, out_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc()] + FLAGS + list(extra) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -67,7 +95,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + LIBS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
@@ -77,5 +105,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    """libsoap_san.so: the same sources with host-side ASan and UBSan."""
+    os.makedirs(SAN_BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(lambda src: _compile(src, SAN_BUILD, SAN_FLAGS), SOURCES))
+    tmp = SAN_LIB + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libsan",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-o", tmp] + objs + LIBS
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, SAN_LIB)
+    if verbose:
+        print("built", SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--sanitize" in sys.argv[1:]:
+        build_sanitized(verbose=True)
+    else:
+        build(verbose=True)

@@ -15,28 +15,26 @@
 //   negative taps on S_{q,b} and active rows with contrast-scaled taps on A.
 // The contrast multiplies after the shift, at the output pixel m.
 //
-// Work split: one block of APPLY_WAVES waves per (tile of 64 x APPLY_R
-// pixels, chunk of PC phases).  Every wave covers the whole tile, with
-// PC x APPLY_R accumulators per lane in registers, and takes every
-// APPLY_WAVES-th window of the chunk's list (window v goes to wave
-// v mod APPLY_WAVES); the waves' partial sums are then added in LDS in a
-// fixed order.  A chunk's windows are thus walked by four waves at once: the
-// time of an item, which is bound by the chain of one wave's windows, is a
-// quarter of what one wave would take.  The block copies the chunk's window
-// records (header and dense taps of APPLY_JW offsets, built by the
-// compaction kernel) into LDS, so the taps reach every lane as broadcast LDS
-// reads.  For each of its windows a lane loads its 8-sample source windows
-// with two 16-byte loads (rows are padded with their end samples, so no load
+// Work split: one block of APPLY_WAVES waves per (tile of APPLY_WAVES x 64
+// x R pixels, chunk of PC phases); each wave owns 64 x R consecutive pixels
+// of the tile (R per lane) and walks every window of the chunk's list over
+// them, with R x PC accumulators per lane in registers.  The block copies
+// the chunk's window records (header and dense taps of APPLY_JW offsets,
+// built by the compaction kernel) into LDS, APPLY_LDS_WIN records per pass
+// with a barrier between passes, so the taps reach every lane as broadcast
+// LDS reads.  For each window a lane loads the R + APPLY_JW - 1 source
+// samples its pixels need (and as many quiet samples for paired tables) and
+// its R contrast values (rows are padded with their end samples, so no load
 // needs a bounds check and the end-value hold of the interpolation is built
 // in); then, offset by offset, each pair of phases with a tap there adds
 // k * D with fused multiply-adds, and a wave-uniform mask test skips the
 // other pairs.  The loads of the next DEP - 1 windows are in flight while a
 // window is consumed.  The block-to-work mapping keeps the chunks of one
-// tile on one XCD so their shared input windows hit the same L2, and starts
-// the chunks with the most windows first.  The final combine adds Q in
-// double.  Every pixel's sum has one fixed order (window order within each
-// wave's share, then the fixed combination of the four shares), so results
-// repeat bit for bit whatever the launch shape.
+// tile on one XCD so their shared input windows hit the same L2, and either
+// starts the chunks with the most windows first or walks the tiles in
+// order.  The final store adds Q in double.  Every pixel's sum runs over the
+// windows in list order, so results repeat bit for bit whatever the
+// pipeline depth or item order.
 #include <algorithm>
 #include <vector>
 

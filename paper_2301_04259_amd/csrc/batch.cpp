@@ -59,7 +59,7 @@ void destroy_batch(soap_batch* b) {
   }
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->origin) (void)hipStreamDestroy(b->origin);
-  if (b->arena) (void)hipFree(b->arena);
+  if (b->arena) (void)soap::dev_free(b->arena);
   delete b;
 }
 
@@ -173,12 +173,13 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
   b->n_spectra = n_spec;
   b->launch = static_cast<hipStream_t>(hip_stream);
   auto fail = [&](const char* what, hipError_t e) {
-    g_batch_err = std::string(what) + ": " + hipGetErrorString(e);
+    g_batch_err = std::string(what) + ": " + hipGetErrorString(e) +
+                  (e == hipErrorOutOfMemory ? soap::dev_cap_note() : "");
     destroy_batch(b);
     return (e == hipErrorOutOfMemory) ? SOAP_ERR_OOM : SOAP_ERR_HIP;
   };
   hipError_t e;
-  if ((e = hipMalloc(&b->arena, arena)) != hipSuccess) return fail("hipMalloc", e);
+  if ((e = soap::dev_malloc(&b->arena, arena)) != hipSuccess) return fail("hipMalloc", e);
   // tap accumulators start at zero (each run's tap-list kernel clears them
   // again after reading); parameters are uploaded once
   if ((e = hipMemset(b->arena, 0, arena)) != hipSuccess) return fail("hipMemset", e);

@@ -5,6 +5,7 @@
 // the method runs in the kernels of geom.hip, weights.hip, apply.hip and
 // ccf.hip.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <cmath>
@@ -44,9 +45,9 @@ void setf(std::string& dst, const char* fmt, ...) {
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
     if (e_ != hipSuccess) {                                                            \
-      setf(c->err, "%s failed: %s", #expr, hipGetErrorString(e_));                     \
-      return (e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation) ? SOAP_ERR_OOM \
-                                                                           : SOAP_ERR_HIP; \
+      const bool oom_ = e_ == hipErrorOutOfMemory || e_ == hipErrorMemoryAllocation;  \
+      setf(c->err, "%s failed: %s%s", #expr, hipGetErrorString(e_), oom_ ? soap::dev_cap_note() : ""); \
+      return oom_ ? SOAP_ERR_OOM : SOAP_ERR_HIP;                                        \
     }                                                                                  \
   } while (0)
 
@@ -123,19 +124,19 @@ soap_status validate_desc(const soap_star_desc* d, std::string& err) {
 hipError_t grow(soap::Workspace& w, size_t bytes) {
   if (w.bytes >= bytes) return hipSuccess;
   if (w.ptr) {
-    hipError_t e = hipFree(w.ptr);
+    hipError_t e = soap::dev_free(w.ptr);
     if (e != hipSuccess) return e;
     w.ptr = nullptr;
     w.bytes = 0;
   }
   size_t want = std::max<size_t>(bytes, 256);
-  hipError_t e = hipMalloc(&w.ptr, want);
+  hipError_t e = soap::dev_malloc(&w.ptr, want);
   if (e == hipSuccess) w.bytes = want;
   return e;
 }
 
 void free_ws(soap::Workspace& w) {
-  if (w.ptr) (void)hipFree(w.ptr);
+  if (w.ptr) (void)soap::dev_free(w.ptr);
   w.ptr = nullptr;
   w.bytes = 0;
 }
@@ -147,10 +148,10 @@ void destroy_ctx(soap_ctx* c) {
     if (c->side) (void)hipStreamSynchronize(c->side);
   }
   for (int t = 0; t < 3; ++t)
-    if (c->d_spec_base[t]) (void)hipFree(c->d_spec_base[t]);
+    if (c->d_spec_base[t]) (void)soap::dev_free(c->d_spec_base[t]);
   void* bufs[] = {c->d_mu, c->d_col_c, c->d_col_w, c->d_colW, c->d_Kq, c->d_Kq_fx, c->d_Q, c->d_con_base, c->d_ones};
   for (void* p : bufs)
-    if (p) (void)hipFree(p);
+    if (p) (void)soap::dev_free(p);
   soap::Workspace* ws[] = {&c->ws_flux, &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin,
                            &c->ws_lsf};
   for (auto* w : ws) free_ws(*w);
@@ -282,27 +283,27 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   const bool on_dev = d->spectra_on_device != 0;
   for (int t = 0; t < 3; ++t) {
     if (!d->spectra[t]) continue;
-    HIP_TRY(hipMalloc(&c->d_spec_base[t], row_bytes * c->B));
+    HIP_TRY(soap::dev_malloc(&c->d_spec_base[t], row_bytes * c->B));
     c->d_spec[t] = static_cast<unsigned char*>(c->d_spec_base[t]) + soap::PAD_FRONT * c->esize;
     HIP_TRY(upload_rows(c, c->d_spec[t], d->spectra[t], c->B, on_dev));
     c->has_type[t] = true;
   }
-  HIP_TRY(hipMalloc((void**)&c->d_mu, sizeof(double) * c->B));
+  HIP_TRY(soap::dev_malloc((void**)&c->d_mu, sizeof(double) * c->B));
   HIP_TRY(hipMemcpy(c->d_mu, d->mu_bins, sizeof(double) * c->B, hipMemcpyHostToDevice));
-  HIP_TRY(hipMalloc((void**)&c->d_col_c, sizeof(int) * c->N));
-  HIP_TRY(hipMalloc((void**)&c->d_col_w, sizeof(double) * c->N));
-  HIP_TRY(hipMalloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
-  HIP_TRY(hipMalloc((void**)&c->d_Kq, sizeof(double) * c->B * c->J));
+  HIP_TRY(soap::dev_malloc((void**)&c->d_col_c, sizeof(int) * c->N));
+  HIP_TRY(soap::dev_malloc((void**)&c->d_col_w, sizeof(double) * c->N));
+  HIP_TRY(soap::dev_malloc((void**)&c->d_colW, sizeof(double) * c->N * c->B));
+  HIP_TRY(soap::dev_malloc((void**)&c->d_Kq, sizeof(double) * c->B * c->J));
   if (c->diff_rot != 0.0) {
-    HIP_TRY(hipMalloc((void**)&c->d_Kq_fx, sizeof(unsigned long long) * c->B * c->J));
+    HIP_TRY(soap::dev_malloc((void**)&c->d_Kq_fx, sizeof(unsigned long long) * c->B * c->J));
     HIP_TRY(hipMemsetAsync(c->d_Kq_fx, 0, sizeof(unsigned long long) * c->B * c->J, c->stream));
   }
-  HIP_TRY(hipMalloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE_MAX));
-  HIP_TRY(hipMalloc(&c->d_ones, c->esize * c->n_tiles * soap::APPLY_TILE_MAX));
+  HIP_TRY(soap::dev_malloc((void**)&c->d_Q, sizeof(double) * c->n_tiles * soap::APPLY_TILE_MAX));
+  HIP_TRY(soap::dev_malloc(&c->d_ones, c->esize * c->n_tiles * soap::APPLY_TILE_MAX));
   if (c->cmode == SOAP_CONTRAST_PLANCK) {
     // one spot row for every bin, one facula row per bin
     c->con_rows = c->B + 1;
-    HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * c->con_rows));
+    HIP_TRY(soap::dev_malloc(&c->d_con_base, row_bytes * c->con_rows));
     c->d_con_spot = static_cast<unsigned char*>(c->d_con_base) + soap::PAD_FRONT * c->esize;
     c->d_con_fac = static_cast<unsigned char*>(c->d_con_spot) + row_bytes;
     c->con_spot_stride = 0;
@@ -310,7 +311,7 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
     // the caller's rows: spot [B], then facula [B]; a type without spectra
     // keeps rows of zeros (never read)
     c->con_rows = 2 * c->B;
-    HIP_TRY(hipMalloc(&c->d_con_base, row_bytes * c->con_rows));
+    HIP_TRY(soap::dev_malloc(&c->d_con_base, row_bytes * c->con_rows));
     c->d_con_spot = static_cast<unsigned char*>(c->d_con_base) + soap::PAD_FRONT * c->esize;
     c->d_con_fac = static_cast<unsigned char*>(c->d_con_spot) + row_bytes * c->B;
     c->con_spot_stride = c->Pstride;
@@ -338,7 +339,7 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   // host, and a host input that was finite there yet is not here means the
   // upload went wrong
   int* d_flag = nullptr;
-  HIP_TRY(hipMalloc((void**)&d_flag, sizeof(int)));
+  HIP_TRY(soap::dev_malloc((void**)&d_flag, sizeof(int)));
   int h_flag[2] = {0, 0};
   hipError_t fe = hipMemsetAsync(d_flag, 0, sizeof(int), c->stream);
   for (int t = 0; t < 3 && fe == hipSuccess; ++t)
@@ -350,7 +351,7 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   if (fe == hipSuccess) fe = hipMemcpyAsync(&h_flag[1], d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
   // host arrays (mu bins, spectra) may be released once the call returns
   const hipError_t se = hipStreamSynchronize(c->stream);
-  (void)hipFree(d_flag);
+  (void)soap::dev_free(d_flag);
   HIP_TRY(fe);
   HIP_TRY(se);
   if (h_flag[0] || h_flag[1]) {
@@ -386,16 +387,27 @@ soap_status stage_to_device(soap_ctx* c, const void* src, size_t bytes, void* ds
   return SOAP_OK;
 }
 
-// brackets one stage with events on the context stream when profiling is on
+const char* const kStageName[] = {"soap:weights", "soap:compact", "soap:apply", "soap:ccf", "soap:fit", "soap:lsf"};
+
+// Brackets one stage with events on the context stream when profiling is on,
+// and always with a roctx range named after the stage (the host-side span of
+// its enqueue, seen by a marker trace).
 struct StageTimer {
   soap_ctx* c;
   int stage;
   hipStream_t st;
   hipEvent_t a = nullptr;
+  bool open = true;
   StageTimer(soap_ctx* c_, int s, hipStream_t st_ = nullptr) : c(c_), stage(s), st(st_ ? st_ : c_->stream) {
+    roctxRangePushA(kStageName[s]);
     if (c->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
   }
+  ~StageTimer() {
+    if (open) roctxRangePop();
+  }
   void done() {
+    if (open) roctxRangePop();
+    open = false;
     if (!a) return;
     hipEvent_t b = nullptr;
     if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st) == hipSuccess) {
@@ -413,6 +425,8 @@ enum { ST_WEIGHTS = 0, ST_COMPACT = 1, ST_APPLY = 2, ST_CCF = 3, ST_GFIT = 4, ST
 }  // namespace
 
 SOAP_API int32_t soap_abi_version(void) { return SOAP_ABI_VERSION; }
+
+SOAP_API uint64_t soap_device_bytes(void) { return soap::dev_bytes_held(); }
 
 SOAP_API const char* soap_status_string(soap_status s) {
   switch (s) {

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "devmem.hpp"
 #include "soap.h"
 
 namespace soap {

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <vector>
 
+#include "devmem.hpp"
 #include "surrogate_internal.hpp"
 
 #define SOAP_API extern "C" __attribute__((visibility("default")))
@@ -33,7 +34,8 @@ void sg_setf(std::string& err, const char* fmt, ...) {
   do {                                                                             \
     hipError_t e_ = (x);                                                           \
     if (e_ != hipSuccess) {                                                        \
-      sg_setf(s->err, "%s failed: %s", #x, hipGetErrorString(e_));               \
+      sg_setf(s->err, "%s failed: %s%s", #x, hipGetErrorString(e_),              \
+              e_ == hipErrorOutOfMemory ? soap::dev_cap_note() : "");              \
       return e_ == hipErrorOutOfMemory ? SOAP_ERR_OOM : SOAP_ERR_HIP;              \
     }                                                                              \
   } while (0)
@@ -96,16 +98,16 @@ void to_natural_layout(const soap_surrogate* s, const std::vector<float>& dev, f
 
 template <typename T>
 hipError_t alloc(T*& p, size_t n) {
-  if (p) (void)hipFree(p);
+  if (p) (void)soap::dev_free(p);
   p = nullptr;
-  return hipMalloc((void**)&p, sizeof(T) * std::max<size_t>(n, 1));
+  return soap::dev_malloc((void**)&p, sizeof(T) * std::max<size_t>(n, 1));
 }
 
 void free_all(soap_surrogate* s) {
   void* ps[] = {s->P, s->G, s->M, s->V, s->Pb, s->X, s->Z1, s->Z2, s->H1, s->H2, s->Y, s->dY, s->dYf,
                 s->dZf, s->dZf2, s->dZb, s->dZb2, s->row_se, s->loss, s->colpart};
   for (void* p : ps)
-    if (p) (void)hipFree(p);
+    if (p) (void)soap::dev_free(p);
 }
 
 soap_status ensure_batch(soap_surrogate* s, int B) {

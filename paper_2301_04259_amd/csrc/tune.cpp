@@ -97,15 +97,15 @@ SOAP_API soap_status soap_autotune(soap_ctx* c, const soap_region* regions, int3
   // one ordinary call builds this workload's tap lists (and checks the
   // arguments); they stay in the context's last table set
   void* tmp = nullptr;
-  if (hipMalloc(&tmp, (size_t)std::max(1, n_phases) * c->P * c->esize) != hipSuccess) {
-    c->err = "autotune: no device memory for a trial output";
+  if (soap::dev_malloc(&tmp, (size_t)std::max(1, n_phases) * c->P * c->esize) != hipSuccess) {
+    c->err = std::string("autotune: no device memory for a trial output") + soap::dev_cap_note();
     return SOAP_ERR_OOM;
   }
   soap_status st = soap_active_spectra(c, regions, n_regions, phases, n_phases, effect, tmp, 1);
   auto fail = [&](soap_status s, const char* msg) {
     if (msg) c->err = msg;
     (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(tmp);
+    (void)soap::dev_free(tmp);
     return s;
   };
   if (st != SOAP_OK) return fail(st, nullptr);

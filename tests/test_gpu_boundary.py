@@ -111,3 +111,46 @@ def test_fit_status_of_nan_and_flat_ccfs():
     assert np.all(np.isfinite(c1)) and (c1.max() - c1.min()) <= 1e-7 * c1.max()
     assert rv["status"][1] in (1, 2), rv
     assert rv["status"][2] == 0, rv
+
+
+def test_device_byte_cap_refuses_cleanly_and_leaks_nothing(monkeypatch):
+    import gc
+
+    gc.collect()
+    torch.cuda.synchronize()
+    base = L.device_bytes()
+    star = W.make_tiny(31, n_grid=20, n_pix=900, n_mu=3, precision=W.PREC_FP32, n_phases=6)
+    _say("device byte cap: init refused under a 4 KiB allowance")
+    monkeypatch.setenv("SOAP_MAX_DEVICE_BYTES", str(base + 4096))
+    with pytest.raises(L.SoapError) as ei:
+        L.soap_grid_init(star)
+    assert ei.value.status == L.SOAP_ERR_OOM and "SOAP_MAX_DEVICE_BYTES" in str(ei.value)
+    assert L.device_bytes() == base
+    monkeypatch.setenv("SOAP_MAX_DEVICE_BYTES", "12x")
+    with pytest.raises(L.SoapError) as ei:
+        L.soap_grid_init(star)
+    assert ei.value.status == L.SOAP_ERR_OOM and "not a byte count" in str(ei.value)
+    assert L.device_bytes() == base
+
+    monkeypatch.delenv("SOAP_MAX_DEVICE_BYTES")
+    ctx = L.soap_grid_init(star)
+    held = L.device_bytes()
+    assert held > base
+    n_ph = len(star.phases)
+    out = torch.empty((n_ph, star.n_pix), dtype=torch.float32, device="cuda")
+    _say("device byte cap: first synthesis refused, context usable after the cap is lifted")
+    monkeypatch.setenv("SOAP_MAX_DEVICE_BYTES", str(held))
+    with pytest.raises(L.SoapError) as ei:
+        L.soap_active_spectra(ctx, star.regions, star.phases, W.EFFECT_TOT, out)
+    assert ei.value.status == L.SOAP_ERR_OOM
+    monkeypatch.delenv("SOAP_MAX_DEVICE_BYTES")
+    L.soap_active_spectra(ctx, star.regions, star.phases, W.EFFECT_TOT, out)
+    torch.cuda.synchronize()
+    fresh = L.soap_grid_init(star)
+    ref = torch.empty_like(out)
+    L.soap_active_spectra(fresh, star.regions, star.phases, W.EFFECT_TOT, ref)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    L.soap_destroy(fresh)
+    L.soap_destroy(ctx)
+    assert L.device_bytes() == base
