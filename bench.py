@@ -105,6 +105,23 @@ def batch_leg(args, L, W, np, torch):
         outs.append(torch.empty((c["n_phases"], P), dtype=torch.float32, device="cuda"))
     torch.cuda.synchronize()
     say(f"{len(cfgs)} contexts in {time.perf_counter() - t0:.1f} s")
+    # shape tuner per pixel-count bucket (powers of two): the median
+    # configuration of each bucket is timed, its choice set on the bucket
+    shapes = {}
+    t0 = time.perf_counter()
+    if args.tune:
+        buckets = {}
+        for i, c in enumerate(cfgs):
+            buckets.setdefault(int(np.ceil(np.log2(c["n_pix"]))), []).append(i)
+        for key in sorted(buckets):
+            idx = sorted(buckets[key], key=lambda i: cfgs[i]["n_pix"] * cfgs[i]["n_phases"])
+            rep = idx[len(idx) // 2]
+            t = L.soap_autotune(ctxs[rep], regs[rep], phs[rep], W.EFFECT_TOT)
+            for i in idx:
+                L.soap_set_apply_shape(ctxs[i], t["depth"], t["order"], t["phases_per_chunk"])
+            shapes[f"P<=2^{key}"] = {"configs": len(idx), "phases_per_chunk": t["phases_per_chunk"],
+                                     "depth": t["depth"], "order": t["order"]}
+        say(f"shapes per pixel bucket in {time.perf_counter() - t0:.1f} s: {shapes}")
     t0 = time.perf_counter()
     b = L.soap_batch_create(ctxs, regs, phs, W.EFFECT_TOT, outs)
     create_s = time.perf_counter() - t0
@@ -132,6 +149,17 @@ def batch_leg(args, L, W, np, torch):
     torch.cuda.synchronize()
     loop_ms = (time.perf_counter() - w0) * 1e3
     out_bytes = sum(int(o.numel()) * 4 for o in outs)
+    # algorithmic bytes of each configuration: the distinct local-spectrum
+    # and contrast rows its shift-and-sum reads (once), the quiet spectrum
+    # (FP64) and its output spectra (untimed pass, one profiled call each)
+    alg = 0
+    for c, r, p, o in zip(ctxs, regs, phs, outs):
+        L.soap_profile_enable(c, True)
+        L.soap_active_spectra(c, r, p, W.EFFECT_TOT, o)
+        pr = L.soap_profile_read(c)
+        L.soap_profile_enable(c, False)
+        P = int(o.shape[1])
+        alg += (pr["src_arrays"] + pr["con_arrays"]) * P * 4 + P * 8 + int(o.numel()) * 4
     L.soap_batch_destroy(b)
     res = {
         "workload": f"{len(cfgs)} configurations: grid 100-400, 8k-206k px windows of 3800-6900 A at R=115000, "
@@ -146,6 +174,10 @@ def batch_leg(args, L, W, np, torch):
         "per_call_loop_ms": loop_ms,
         "graph_speedup_vs_calls": loop_ms / ms,
         "create_s": create_s,
+        "roofline": {"bound": "hbm", "scope": "whole graph run (tables and shift-and-sum)",
+                     "algorithmic_bytes": alg, "achieved": alg / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": alg / (ms * 1e-3) / 8e12},
+        "shapes": shapes,
     }
     del outs
     for c in ctxs:

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SOAP_ABI_VERSION 3
+#define SOAP_ABI_VERSION 4
 
 typedef enum {
   SOAP_OK = 0,
@@ -362,34 +362,45 @@ soap_status soap_surrogate_rv(soap_ctx* ctx, const float* coef, const float* mem
                               double* rv_kms, double* err_kms, int32_t* fallback);
 
 /* Shape of the shift-and-sum kernel and its tuner.  A block of four waves
- * covers a tile of pixels (2048 in FP32, 1024 in FP64) for one chunk of
- * phases (8 in FP32, 4 in FP64); every wave keeps `depth` (2 or 3) windows
- * of source samples in flight (the loads of the next depth - 1 windows are
- * issued before the current one is consumed).  `order` picks how each XCD
- * walks its (tile, chunk) items: 0 = chunks with the most windows first,
- * 1 = tile by tile (all chunks of a tile together).  Every shape gives the
- * same result bit for bit (each pixel adds its windows in the same order);
- * only the time differs.                                                     */
+ * covers a tile of pixels for one chunk of `phases_per_chunk` phases: 8
+ * (tiles of 2048 pixels) or 16 (1024 pixels) in FP32, 4 (1024 pixels) or 8
+ * (512 pixels) in FP64; the first of each pair is the default.  More phases
+ * per chunk read each source window once for more phases (fewer loads per
+ * tap), fewer keep more pixels per lane (fewer empty phase slots where
+ * regions are visible for only part of a chunk).  Phases per chunk is the
+ * layout of the tap tables that the next soap_active_spectra call builds.
+ * Every wave keeps `depth` (2 or 3) windows of source samples in flight
+ * (the loads of the next depth - 1 windows are issued before the current one
+ * is consumed).  `order` picks how each XCD walks its (tile, chunk) items:
+ * 0 = chunks with the most windows first, 1 = tile by tile (all chunks of a
+ * tile together).  Every shape gives the same result bit for bit (each
+ * pixel adds the non-zero taps of its phase in the same window order, and a
+ * tap slot that is zero adds exactly zero); only the time differs.          */
 typedef struct {
   int32_t depth;
   int32_t order;
-  double apply_us;           /* measured time of one launch of the choice   */
+  int32_t phases_per_chunk;
   int32_t from_cache;        /* 1: taken from the cache file, not timed     */
+  double apply_us;           /* measured time of one launch of the choice   */
   int32_t n_tried;           /* shapes timed                                */
+  int32_t reserved;
   char key[128];             /* cache key of the workload shape             */
 } soap_tune;
 
 /* Sets the shape used by later calls on ctx; SOAP_ERR_ARG for a depth other
- * than 2 or 3 or an order other than 0 or 1.                                 */
-soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t depth, int32_t order);
+ * than 2 or 3, an order other than 0 or 1, or phases per chunk other than
+ * the two of the context's precision (0 = the default one).                 */
+soap_status soap_set_apply_shape(soap_ctx* ctx, int32_t depth, int32_t order, int32_t phases_per_chunk);
 
-/* Runs soap_active_spectra once on the given workload (arguments as there),
- * then times every shape on its tap lists (10 launches each, HIP events on
- * the context's stream) and keeps the fastest for later calls.  With
- * cache_path (may be NULL) the choice is looked up first under a key made of
- * the precision, table mode, and the power-of-two buckets of the pixel count,
- * phase count and windows per chunk, plus the shift range and the mu-bin
- * count; a timed choice is written back.  Waits for the stream.             */
+/* Runs soap_active_spectra on the given workload (arguments as there) once
+ * per phases-per-chunk value, times every (depth, order) shape on each
+ * call's tap lists (10 launches each, HIP events on the context's stream)
+ * and keeps the fastest for later calls.  With cache_path (may be NULL) the
+ * choice is looked up first under a key made of the precision, table mode,
+ * and the power-of-two buckets of the pixel count, phase count and windows
+ * per chunk (default layout), plus the shift range and the mu-bin count; a
+ * timed choice is written back.  On error the context keeps its previous
+ * phases per chunk.  Waits for the stream.                                  */
 soap_status soap_autotune(soap_ctx* ctx, const soap_region* regions, int32_t n_regions, const double* phases,
                           int32_t n_phases, int32_t effect, const char* cache_path, soap_tune* out);
 
@@ -403,7 +414,9 @@ soap_status soap_autotune(soap_ctx* ctx, const soap_region* regions, int32_t n_r
  * uploads the parameters, allocates each configuration's tables and
  * captures every configuration's kernels (Algorithm 5 per phase: region
  * parameters, weights, tap lists, shift-and-sum with the context's current
- * apply shape) into one graph spread over four parallel branches;
+ * apply shape, one launch per group of configurations sharing precision,
+ * table mode, phases per chunk and depth) into one graph spread over four
+ * parallel branches;
  * soap_batch_run then enqueues the whole batch with a single graph launch on
  * hip_stream.  Every output row equals what soap_active_spectra gives for
  * that configuration, bit for bit.  The contexts and flux arrays must

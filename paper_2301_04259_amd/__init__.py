@@ -221,14 +221,16 @@ class TuneC(C.Structure):
     _fields_ = [
         ("depth", C.c_int32),
         ("order", C.c_int32),
-        ("apply_us", C.c_double),
+        ("phases_per_chunk", C.c_int32),
         ("from_cache", C.c_int32),
+        ("apply_us", C.c_double),
         ("n_tried", C.c_int32),
+        ("reserved", C.c_int32),
         ("key", C.c_char * 128),
     ]
 
 
-_lib.soap_set_apply_shape.argtypes = [_ctx_p, C.c_int32, C.c_int32]
+_lib.soap_set_apply_shape.argtypes = [_ctx_p, C.c_int32, C.c_int32, C.c_int32]
 _lib.soap_set_apply_shape.restype = C.c_int
 _lib.soap_autotune.argtypes = [_ctx_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_char_p,
                                C.POINTER(TuneC)]
@@ -778,8 +780,9 @@ def soap_surrogate_rv(ctx, coef, members, base, basis, calib, threshold_kms, rv_
     _check(st, ctx.handle)
 
 
-def soap_set_apply_shape(ctx, depth=2, order=0):
-    _check(_lib.soap_set_apply_shape(ctx.handle, int(depth), int(order)), ctx.handle)
+def soap_set_apply_shape(ctx, depth=2, order=0, phases_per_chunk=0):
+    """Shape of later shift-and-sum calls; phases_per_chunk 0 = the default."""
+    _check(_lib.soap_set_apply_shape(ctx.handle, int(depth), int(order), int(phases_per_chunk)), ctx.handle)
 
 
 def soap_autotune(ctx, regions, phases, effect, cache_path=None):
@@ -790,7 +793,7 @@ def soap_autotune(ctx, regions, phases, effect, cache_path=None):
     st = _lib.soap_autotune(ctx.handle, C.cast(regs, C.c_void_p), len(regions), ph.ctypes.data, len(ph), int(effect),
                             None if cache_path is None else os.fsencode(cache_path), C.byref(t))
     _check(st, ctx.handle)
-    return {"depth": t.depth, "order": t.order, "apply_us": t.apply_us,
+    return {"depth": t.depth, "order": t.order, "phases_per_chunk": t.phases_per_chunk, "apply_us": t.apply_us,
             "from_cache": bool(t.from_cache),
             "n_tried": t.n_tried, "key": t.key.decode()}
 

@@ -54,14 +54,14 @@ typedef float f4e __attribute__((ext_vector_type(4), aligned(4)));
 typedef float f3e __attribute__((ext_vector_type(3), aligned(4)));
 typedef double d2e __attribute__((ext_vector_type(2), aligned(8)));
 
-template <typename T>
+template <typename T, int PC>
 constexpr int win_n() {
-  return ApplyShape<T>::R + APPLY_JW - 1;
+  return ApplyShape<T, PC>::R + APPLY_JW - 1;
 }
 
-template <typename T>
-__device__ __forceinline__ void load_win(T (&w)[win_n<T>()], const T* p) {
-  constexpr int N = win_n<T>();
+template <typename T, int PC>
+__device__ __forceinline__ void load_win(T (&w)[(win_n<T, PC>())], const T* p) {
+  constexpr int N = win_n<T, PC>();
   if constexpr (sizeof(T) == 4) {
     static_assert(N % 4 == 3, "16-byte loads and one 12-byte load");
 #pragma unroll
@@ -89,9 +89,9 @@ __device__ __forceinline__ void load_win(T (&w)[win_n<T>()], const T* p) {
 }
 
 // R consecutive elements from 16-byte-aligned memory
-template <typename T>
-__device__ __forceinline__ void load_px(T (&c)[ApplyShape<T>::R], const T* p) {
-  constexpr int R = ApplyShape<T>::R;
+template <typename T, int PC>
+__device__ __forceinline__ void load_px(T (&c)[(ApplyShape<T, PC>::R)], const T* p) {
+  constexpr int R = ApplyShape<T, PC>::R;
   if constexpr (sizeof(T) == 4) {
 #pragma unroll
     for (int k = 0; k < R; k += 4) {
@@ -113,10 +113,10 @@ __device__ __forceinline__ void load_px(T (&c)[ApplyShape<T>::R], const T* p) {
 
 // operands of one window: D[q][r] = Ca[r] * A[m_r - j] - B[m_r - j],
 // j = jlo + q, with window sample s = r - q + APPLY_JW - 1
-template <typename T>
+template <typename T, int PC>
 struct Operands {
-  T a[win_n<T>()], b[win_n<T>()];  // b is used by paired tables only (D = C A - B)
-  T c[ApplyShape<T>::R];
+  T a[(win_n<T, PC>())], b[(win_n<T, PC>())];  // b is used by paired tables only (D = C A - B)
+  T c[(ApplyShape<T, PC>::R)];
 };
 
 template <typename T>
@@ -161,26 +161,26 @@ __device__ __forceinline__ void window_rows(const ApplyArgs<T>& A, int4 hr, cons
 // mt: first pixel of the tile (uniform); lo: the lane's first pixel within
 // it.  The uniform part of every address is formed in SGPRs, so each load
 // takes a scalar base and a 32-bit per-lane offset.
-template <typename T, int EFF, bool PAIRED>
-__device__ __forceinline__ void fetch(Operands<T>& o, const ApplyArgs<T>& A, int4 hr, int64_t mt, unsigned lo) {
+template <typename T, int PC, int EFF, bool PAIRED>
+__device__ __forceinline__ void fetch(Operands<T, PC>& o, const ApplyArgs<T>& A, int4 hr, int64_t mt, unsigned lo) {
   const T *src, *sq, *con;
   int jlo;
   window_rows<T, EFF>(A, hr, src, sq, con, jlo);
   // window start m - jlo - (JW - 1)
   const int64_t at = mt - jlo - (APPLY_JW - 1);
-  load_win<T>(o.a, (src + at) + lo);
-  if (PAIRED) load_win<T>(o.b, (sq + at) + lo);
-  load_px<T>(o.c, (con + mt) + lo);
+  load_win<T, PC>(o.a, (src + at) + lo);
+  if (PAIRED) load_win<T, PC>(o.b, (sq + at) + lo);
+  load_px<T, PC>(o.c, (con + mt) + lo);
 }
 
 // One window: for every offset q with a tap in the chunk, read the taps of
 // all phases at that offset from LDS (every lane reads the same address),
 // form the difference row, and let each pair of phases with a tap there add
 // k * D with fused multiply-adds.
-template <typename T, bool PAIRED>
-__device__ __forceinline__ void consume(T (&acc)[ApplyShape<T>::PC][ApplyShape<T>::R], const Operands<T>& o,
-                                        unsigned gm, const T* tw) {
-  constexpr int R = ApplyShape<T>::R, PC = ApplyShape<T>::PC, JW = APPLY_JW, NP = PC / 2;
+template <typename T, int PC, bool PAIRED>
+__device__ __forceinline__ void consume(T (&acc)[PC][(ApplyShape<T, PC>::R)], const Operands<T, PC>& o, unsigned gm,
+                                        const T* tw) {
+  constexpr int R = ApplyShape<T, PC>::R, JW = APPLY_JW, NP = PC / 2;
   constexpr unsigned PMASK = (1u << NP) - 1u;
 #pragma unroll
   for (int q = 0; q < JW; ++q) {
@@ -211,10 +211,10 @@ __device__ __forceinline__ void consume(T (&acc)[ApplyShape<T>::PC][ApplyShape<T
 
 // final combine of one item: Q (double) plus the accumulated differences,
 // written with 16-byte stores where the row allows
-template <typename T>
-__device__ __forceinline__ void store_item(const ApplyArgs<T>& A, const T (&acc)[ApplyShape<T>::PC][ApplyShape<T>::R],
-                                           int chunk, int64_t m0) {
-  constexpr int R = ApplyShape<T>::R, PC = ApplyShape<T>::PC;
+template <typename T, int PC>
+__device__ __forceinline__ void store_item(const ApplyArgs<T>& A, const T (&acc)[PC][(ApplyShape<T, PC>::R)], int chunk,
+                                           int64_t m0) {
+  constexpr int R = ApplyShape<T, PC>::R;
   double Qr[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Qr[r] = A.Q[m0 + r];  // Q is padded to whole tiles
@@ -251,10 +251,10 @@ __device__ __forceinline__ void store_item(const ApplyArgs<T>& A, const T (&acc)
 // consumed, so the compiler can count outstanding loads exactly; each header
 // is read one step ahead of its fetch).  The block stages the records
 // APPLY_LDS_WIN at a time.  Then Q is added and the spectra stored.
-template <typename T, bool PAIRED, int EFF, int DEP>
+template <typename T, int PC, bool PAIRED, int EFF, int DEP>
 __device__ __forceinline__ void apply_item(const ApplyArgs<T>& A, int tile, int chunk, unsigned char* lds) {
-  constexpr int R = ApplyShape<T>::R, PC = ApplyShape<T>::PC;
-  const int64_t mt = (int64_t)tile * ApplyShape<T>::TILE;
+  constexpr int R = ApplyShape<T, PC>::R, WB = ApplyShape<T, PC>::WB;
+  const int64_t mt = (int64_t)tile * ApplyShape<T, PC>::TILE;
   const unsigned lo = threadIdx.x * R;
 
   T acc[PC][R];
@@ -264,38 +264,38 @@ __device__ __forceinline__ void apply_item(const ApplyArgs<T>& A, int tile, int 
     for (int r = 0; r < R; ++r) acc[p][r] = T(0);
 
   const int nv = A.nvg[chunk];
-  const unsigned char* gw = A.wins + (int64_t)chunk * A.vg_cap * WIN_BYTES;
+  const unsigned char* gw = A.wins + (int64_t)chunk * A.vg_cap * WB;
   for (int vb = 0; vb < nv; vb += APPLY_LDS_WIN) {
     const int nb = min(APPLY_LDS_WIN, nv - vb);
     if (vb) __syncthreads();  // every wave is done with the previous pass
     {
-      const int4* src = reinterpret_cast<const int4*>(gw + (int64_t)vb * WIN_BYTES);
+      const int4* src = reinterpret_cast<const int4*>(gw + (int64_t)vb * WB);
       int4* dst = reinterpret_cast<int4*>(lds);
-      const int n16 = nb * (WIN_BYTES / 16);
+      const int n16 = nb * (WB / 16);
       for (int u = threadIdx.x; u < n16; u += APPLY_WAVES * 64) dst[u] = src[u];
     }
     __syncthreads();
     const int last = nb - 1;
-    auto head = [&](int v) { return *reinterpret_cast<const int4*>(lds + min(v, last) * WIN_BYTES); };
-    Operands<T> o[DEP];
+    auto head = [&](int v) { return *reinterpret_cast<const int4*>(lds + min(v, last) * WB); };
+    Operands<T, PC> o[DEP];
     int4 h[DEP];
 #pragma unroll
     for (int i = 0; i < DEP; ++i) h[i] = head(i);
 #pragma unroll
-    for (int i = 0; i + 1 < DEP; ++i) fetch<T, EFF, PAIRED>(o[i], A, h[i], mt, lo);
+    for (int i = 0; i + 1 < DEP; ++i) fetch<T, PC, EFF, PAIRED>(o[i], A, h[i], mt, lo);
     for (int v0 = 0; v0 < nb; v0 += DEP) {
 #pragma unroll
       for (int d = 0; d < DEP; ++d) {
         const int nxt = (d + DEP - 1) % DEP;  // slot of window v0 + d + DEP - 1
-        fetch<T, EFF, PAIRED>(o[nxt], A, h[nxt], mt, lo);
+        fetch<T, PC, EFF, PAIRED>(o[nxt], A, h[nxt], mt, lo);
         const int4 hc = h[d];
         h[d] = head(v0 + d + DEP);
         if (v0 + d < nb)
-          consume<T, PAIRED>(acc, o[d], (unsigned)uni(hc.w), reinterpret_cast<const T*>(lds + (v0 + d) * WIN_BYTES + 16));
+          consume<T, PC, PAIRED>(acc, o[d], (unsigned)uni(hc.w), reinterpret_cast<const T*>(lds + (v0 + d) * WB + 16));
       }
     }
   }
-  store_item<T>(A, acc, chunk, mt + lo);
+  store_item<T, PC>(A, acc, chunk, mt + lo);
 }
 
 // Blocks are dealt to the 8 XCDs in turn (block index mod 8).  Each XCD
@@ -338,32 +338,31 @@ __device__ __forceinline__ bool map_item(const ApplyArgs<T>& A, int seq8, int* t
   return true;
 }
 
-// waves per SIMD the register budget is sized for: three for the FP32
-// kernels with two windows in flight, two where more registers are needed
-// (FP64, a third window in flight, the effect read at run time)
-template <typename T, int EFF, int DEP>
+// waves per SIMD the register budget is sized for: three with two windows
+// in flight (FP32, or FP64 with its 2-pixel lanes), two where more registers
+// are needed (FP64 with 4-pixel lanes, a third window in flight, the effect
+// read at run time)
+template <typename T, int PC, int EFF, int DEP>
 constexpr int apply_occupancy() {
-  return (sizeof(T) == 4 && DEP == 2 && EFF >= 0) ? 3 : 2;
+  return ((sizeof(T) == 4 || PC == PC_F64_WIDE) && DEP == 2 && EFF >= 0) ? 3 : 2;
 }
 
-template <typename T, bool PAIRED, int EFF, int DEP>
-__global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, EFF, DEP>())) k_apply(ApplyArgs<T> A) {
-  static_assert(APPLY_JW * ApplyShape<T>::PC / 2 <= 32 && APPLY_JW * ApplyShape<T>::PC * sizeof(T) == WIN_TAP_BYTES,
-                "record layout");
-  __shared__ __align__(16) unsigned char lds[APPLY_LDS_WIN * WIN_BYTES];
+template <typename T, int PC, bool PAIRED, int EFF, int DEP>
+__global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, PC, EFF, DEP>())) k_apply(ApplyArgs<T> A) {
+  __shared__ __align__(16) unsigned char lds[APPLY_LDS_WIN * ApplyShape<T, PC>::WB];
   int tile, chunk;
   if (!map_item(A, blockIdx.x, &tile, &chunk)) return;
-  apply_item<T, PAIRED, EFF, DEP>(A, tile, chunk, lds);
+  apply_item<T, PC, PAIRED, EFF, DEP>(A, tile, chunk, lds);
 }
 
 // Batched form: one launch over the items of many configurations (each with
-// its own arguments).  Configuration i owns the slots item_off[i] ..
-// item_off[i+1] - 1, a multiple of 8 starting at a multiple of 8, mapped as
-// in k_apply.
-template <typename T, bool PAIRED, int EFF, int DEP>
-__global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, EFF, DEP>()))
+// its own arguments, all with PC phases per chunk).  Configuration i owns the
+// slots item_off[i] .. item_off[i+1] - 1, a multiple of 8 starting at a
+// multiple of 8, mapped as in k_apply.
+template <typename T, int PC, bool PAIRED, int EFF, int DEP>
+__global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, PC, EFF, DEP>()))
     k_apply_batch(const ApplyArgs<T>* __restrict__ args, const int* __restrict__ item_off, int n_cfg) {
-  __shared__ __align__(16) unsigned char lds[APPLY_LDS_WIN * WIN_BYTES];
+  __shared__ __align__(16) unsigned char lds[APPLY_LDS_WIN * ApplyShape<T, PC>::WB];
   const int b = blockIdx.x;
   int lo = 0, hi = n_cfg;  // last cfg with item_off[cfg] <= b
   while (hi - lo > 1) {
@@ -374,38 +373,38 @@ __global__ void __launch_bounds__(APPLY_WAVES * 64, (apply_occupancy<T, EFF, DEP
   const ApplyArgs<T> A = args[lo];
   int tile, chunk;
   if (!map_item(A, b - item_off[lo], &tile, &chunk)) return;
-  apply_item<T, PAIRED, EFF, DEP>(A, tile, chunk, lds);
+  apply_item<T, PC, PAIRED, EFF, DEP>(A, tile, chunk, lds);
 }
 
 namespace {
 
-template <typename T, bool PAIRED, int EFF>
+template <typename T, int PC, bool PAIRED, int EFF>
 hipError_t launch_eff(const ApplyArgs<T>& A, int depth, dim3 grid, hipStream_t st) {
   const dim3 block(APPLY_WAVES * 64);
   if (depth >= 3)
-    hipLaunchKernelGGL((k_apply<T, PAIRED, EFF, 3>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((k_apply<T, PC, PAIRED, EFF, 3>), grid, block, 0, st, A);
   else
-    hipLaunchKernelGGL((k_apply<T, PAIRED, EFF, 2>), grid, block, 0, st, A);
+    hipLaunchKernelGGL((k_apply<T, PC, PAIRED, EFF, 2>), grid, block, 0, st, A);
   return hipGetLastError();
 }
 
-template <typename T, bool PAIRED>
+template <typename T, int PC, bool PAIRED>
 hipError_t launch_apply_t(const Plan& pl, const ApplyArgs<T>& A, int depth, hipStream_t st) {
   const int tpx = (A.n_tiles + 7) / 8;
   const dim3 grid(8 * tpx * pl.n_chunks);
   switch (pl.effect) {
     case SOAP_EFFECT_FLUX:
-      return launch_eff<T, PAIRED, SOAP_EFFECT_FLUX>(A, depth, grid, st);
+      return launch_eff<T, PC, PAIRED, SOAP_EFFECT_FLUX>(A, depth, grid, st);
     case SOAP_EFFECT_BCONV:
-      return launch_eff<T, PAIRED, SOAP_EFFECT_BCONV>(A, depth, grid, st);
+      return launch_eff<T, PC, PAIRED, SOAP_EFFECT_BCONV>(A, depth, grid, st);
     default:
-      return launch_eff<T, PAIRED, SOAP_EFFECT_TOT>(A, depth, grid, st);
+      return launch_eff<T, PC, PAIRED, SOAP_EFFECT_TOT>(A, depth, grid, st);
   }
 }
 
-template <typename T>
+template <typename T, int PC>
 ApplyArgs<T> make_args(soap_ctx* c, const Plan& pl, const void* win, const int* nvg, void* flux, int order) {
-  constexpr int R = ApplyShape<T>::R, TILE = ApplyShape<T>::TILE;
+  constexpr int R = ApplyShape<T, PC>::R, TILE = ApplyShape<T, PC>::TILE;
   const bool vec_ok = (c->P % R == 0) && (reinterpret_cast<uintptr_t>(flux) % 16 == 0);
   ApplyArgs<T> A{c->P, c->Pstride, c->con_spot_stride, c->B, pl.n_ph, pl.n_chunks, (int)((c->P + TILE - 1) / TILE),
                  pl.effect, pl.paired, pl.vg_cap, vec_ok ? 1 : 0, order,
@@ -413,6 +412,13 @@ ApplyArgs<T> make_args(soap_ctx* c, const Plan& pl, const void* win, const int* 
                  (const T*)c->d_con_fac, (const T*)c->d_ones, c->d_Q, static_cast<const unsigned char*>(win), nvg,
                  (T*)flux};
   return A;
+}
+
+template <typename T, int PC>
+hipError_t launch_apply_pc(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux, int depth,
+                           int order, hipStream_t st) {
+  const ApplyArgs<T> A = make_args<T, PC>(c, pl, d_win, d_nvg, d_flux, order);
+  return pl.paired ? launch_apply_t<T, PC, true>(pl, A, depth, st) : launch_apply_t<T, PC, false>(pl, A, depth, st);
 }
 
 }  // namespace
@@ -423,24 +429,25 @@ hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const in
 
 hipError_t launch_apply_shape(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux,
                               int depth, int order, hipStream_t st) {
-  if (c->prec == SOAP_PREC_FP32) {
-    const ApplyArgs<float> A = make_args<float>(c, pl, d_win, d_nvg, d_flux, order);
-    return pl.paired ? launch_apply_t<float, true>(pl, A, depth, st) : launch_apply_t<float, false>(pl, A, depth, st);
-  }
-  const ApplyArgs<double> A = make_args<double>(c, pl, d_win, d_nvg, d_flux, order);
-  return pl.paired ? launch_apply_t<double, true>(pl, A, depth, st) : launch_apply_t<double, false>(pl, A, depth, st);
+  const bool fp32 = c->prec == SOAP_PREC_FP32;
+  if (!pc_valid(fp32, pl.pc)) return hipErrorInvalidValue;
+  if (fp32)
+    return pl.pc == PC_F32_WIDE ? launch_apply_pc<float, PC_F32_WIDE>(c, pl, d_win, d_nvg, d_flux, depth, order, st)
+                                : launch_apply_pc<float, PC_F32>(c, pl, d_win, d_nvg, d_flux, depth, order, st);
+  return pl.pc == PC_F64_WIDE ? launch_apply_pc<double, PC_F64_WIDE>(c, pl, d_win, d_nvg, d_flux, depth, order, st)
+                              : launch_apply_pc<double, PC_F64>(c, pl, d_win, d_nvg, d_flux, depth, order, st);
 }
 
 // ---- batched shift-and-sum over many configurations ------------------------
 
 namespace {
 
-template <typename T>
+template <typename T, int PC>
 hipError_t upload_t(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGroup* g) {
   std::vector<ApplyArgs<T>> args(n);
   std::vector<int> off(n + 1, 0);
   for (int i = 0; i < n; ++i) {
-    args[i] = make_args<T>(cfgs[i].c, cfgs[i].pl, cfgs[i].win, cfgs[i].nvg, cfgs[i].flux, cfgs[i].c->tune_order);
+    args[i] = make_args<T, PC>(cfgs[i].c, cfgs[i].pl, cfgs[i].win, cfgs[i].nvg, cfgs[i].flux, cfgs[i].c->tune_order);
     off[i + 1] = off[i] + 8 * ((args[i].n_tiles + 7) / 8) * args[i].n_chunks;  // whole XCD rounds
   }
   g->n_cfg = n;
@@ -452,31 +459,39 @@ hipError_t upload_t(const ApplyBatchCfg* cfgs, int n, void* d_buf, ApplyBatchGro
   return hipMemcpy(g->off, off.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice);
 }
 
-template <typename T, bool PAIRED, int EFF>
+template <typename T, int PC, bool PAIRED, int EFF>
 void launch_batch_e(const ApplyBatchGroup& g, hipStream_t st) {
   const dim3 grid((unsigned)g.n_items), block(APPLY_WAVES * 64);
   const auto* a = static_cast<const ApplyArgs<T>*>(g.args);
   const int* off = static_cast<const int*>(g.off);
   if (g.depth >= 3)
-    hipLaunchKernelGGL((k_apply_batch<T, PAIRED, EFF, 3>), grid, block, 0, st, a, off, g.n_cfg);
+    hipLaunchKernelGGL((k_apply_batch<T, PC, PAIRED, EFF, 3>), grid, block, 0, st, a, off, g.n_cfg);
   else
-    hipLaunchKernelGGL((k_apply_batch<T, PAIRED, EFF, 2>), grid, block, 0, st, a, off, g.n_cfg);
+    hipLaunchKernelGGL((k_apply_batch<T, PC, PAIRED, EFF, 2>), grid, block, 0, st, a, off, g.n_cfg);
 }
 
 // every configuration of a batch group has the group's effect
-template <typename T, bool PAIRED>
+template <typename T, int PC, bool PAIRED>
 void launch_batch_t(const ApplyBatchGroup& g, hipStream_t st) {
   switch (g.effect) {
     case SOAP_EFFECT_FLUX:
-      launch_batch_e<T, PAIRED, SOAP_EFFECT_FLUX>(g, st);
+      launch_batch_e<T, PC, PAIRED, SOAP_EFFECT_FLUX>(g, st);
       break;
     case SOAP_EFFECT_BCONV:
-      launch_batch_e<T, PAIRED, SOAP_EFFECT_BCONV>(g, st);
+      launch_batch_e<T, PC, PAIRED, SOAP_EFFECT_BCONV>(g, st);
       break;
     default:
-      launch_batch_e<T, PAIRED, SOAP_EFFECT_TOT>(g, st);
+      launch_batch_e<T, PC, PAIRED, SOAP_EFFECT_TOT>(g, st);
       break;
   }
+}
+
+template <typename T, int PC>
+void launch_batch_pc(const ApplyBatchGroup& g, hipStream_t st) {
+  if (g.paired)
+    launch_batch_t<T, PC, true>(g, st);
+  else
+    launch_batch_t<T, PC, false>(g, st);
 }
 
 }  // namespace
@@ -490,23 +505,30 @@ hipError_t apply_batch_upload(const ApplyBatchCfg* cfgs, int n, void* d_buf, App
   g->paired = cfgs[0].pl.paired != 0;
   g->depth = cfgs[0].c->tune_depth;
   g->effect = cfgs[0].pl.effect;
+  g->pc = cfgs[0].pl.pc;
+  if (!pc_valid(g->fp32, g->pc)) return hipErrorInvalidValue;
+  // one precision, table mode, effect, phases per chunk and depth per group
   for (int i = 1; i < n; ++i)
-    if (cfgs[i].pl.effect != g->effect) return hipErrorInvalidValue;  // one effect per group
-  return g->fp32 ? upload_t<float>(cfgs, n, d_buf, g) : upload_t<double>(cfgs, n, d_buf, g);
+    if ((cfgs[i].c->prec == SOAP_PREC_FP32) != g->fp32 || (cfgs[i].pl.paired != 0) != g->paired ||
+        cfgs[i].pl.effect != g->effect || cfgs[i].pl.pc != g->pc || cfgs[i].c->tune_depth != g->depth)
+      return hipErrorInvalidValue;
+  if (g->fp32)
+    return g->pc == PC_F32_WIDE ? upload_t<float, PC_F32_WIDE>(cfgs, n, d_buf, g) : upload_t<float, PC_F32>(cfgs, n, d_buf, g);
+  return g->pc == PC_F64_WIDE ? upload_t<double, PC_F64_WIDE>(cfgs, n, d_buf, g) : upload_t<double, PC_F64>(cfgs, n, d_buf, g);
 }
 
 hipError_t apply_batch_launch(const ApplyBatchGroup& g, hipStream_t st) {
   if (g.n_items <= 0) return hipSuccess;
   if (g.fp32) {
-    if (g.paired)
-      launch_batch_t<float, true>(g, st);
+    if (g.pc == PC_F32_WIDE)
+      launch_batch_pc<float, PC_F32_WIDE>(g, st);
     else
-      launch_batch_t<float, false>(g, st);
+      launch_batch_pc<float, PC_F32>(g, st);
   } else {
-    if (g.paired)
-      launch_batch_t<double, true>(g, st);
+    if (g.pc == PC_F64_WIDE)
+      launch_batch_pc<double, PC_F64_WIDE>(g, st);
     else
-      launch_batch_t<double, false>(g, st);
+      launch_batch_pc<double, PC_F64>(g, st);
   }
   return hipGetLastError();
 }

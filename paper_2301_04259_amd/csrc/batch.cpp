@@ -136,7 +136,8 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     }
     pl.G = (pl.paired ? 2 : 3) * c->B;
     pl.n_slabs = (c->N + soap::SLAB_COLS - 1) / soap::SLAB_COLS;
-    pl.n_chunks = (np + c->pc - 1) / c->pc;
+    pl.pc = c->pc;
+    pl.n_chunks = (np + pl.pc - 1) / pl.pc;
     pl.vg_cap = pl.G * ((c->J + soap::APPLY_JW - 1) / soap::APPLY_JW);
     const size_t GJ = (size_t)pl.G * c->J;
     auto take = [&](size_t bytes) {
@@ -152,21 +153,35 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     q.off_kfx = take(sizeof(unsigned long long) * (size_t)np * GJ);
     q.off_k = take(sizeof(double) * (size_t)np * GJ);
     q.off_mask = take(sizeof(unsigned long long) * (size_t)np * pl.G);
-    q.off_vg = take((size_t)soap::WIN_BYTES * pl.n_chunks * pl.vg_cap);
+    q.off_vg = take((size_t)soap::win_bytes(pl.pc, (int)c->esize) * pl.n_chunks * pl.vg_cap);
     q.off_nvg = take(sizeof(int) * (size_t)pl.n_chunks);
     n_spec += np;
   }
-  // the shift-and-sum runs as one launch per (precision, table mode) over
-  // every configuration's (tile, chunk) items
-  std::vector<std::vector<int>> groups(4);
-  for (int i = 0; i < n_cfg; ++i)
-    groups[(cp[i].c->prec == SOAP_PREC_FP32 ? 0 : 2) + (cp[i].pl.paired ? 0 : 1)].push_back(i);
-  std::vector<size_t> group_off(4, 0);
-  for (int g = 0; g < 4; ++g)
-    if (!groups[g].empty()) {
-      group_off[g] = arena;
-      arena += al(soap::apply_batch_bytes((int)groups[g].size()));
+  // the shift-and-sum runs as one launch per (precision, table mode, phases
+  // per chunk, windows in flight) over every configuration's (tile, chunk)
+  // items, in order of first appearance
+  std::vector<std::vector<int>> groups;
+  {
+    std::vector<long long> keys;
+    for (int i = 0; i < n_cfg; ++i) {
+      const soap_ctx* c = cp[i].c;
+      const long long k = ((long long)(c->prec == SOAP_PREC_FP32) << 40) | ((long long)cp[i].pl.paired << 32) |
+                          ((long long)cp[i].pl.pc << 8) | (long long)c->tune_depth;
+      size_t g = 0;
+      while (g < keys.size() && keys[g] != k) ++g;
+      if (g == keys.size()) {
+        keys.push_back(k);
+        groups.emplace_back();
+      }
+      groups[g].push_back(i);
     }
+  }
+  const int n_groups = (int)groups.size();
+  std::vector<size_t> group_off(n_groups, 0);
+  for (int g = 0; g < n_groups; ++g) {
+    group_off[g] = arena;
+    arena += al(soap::apply_batch_bytes((int)groups[g].size()));
+  }
 
   soap_batch* b = new soap_batch;
   b->n_cfg = n_cfg;
@@ -201,9 +216,8 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
         return fail("hipMemcpy", e);
     }
   }
-  std::vector<soap::ApplyBatchGroup> ag(4);
-  for (int g = 0; g < 4; ++g) {
-    if (groups[g].empty()) continue;
+  std::vector<soap::ApplyBatchGroup> ag(n_groups);
+  for (int g = 0; g < n_groups; ++g) {
     std::vector<soap::ApplyBatchCfg> ac;
     for (int i : groups[g])
       ac.push_back(soap::ApplyBatchCfg{cp[i].c, cp[i].pl, A + cp[i].off_vg,
@@ -247,8 +261,7 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     ce = hipEventRecord(b->join[k], b->branch[k]);
     if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join[k], 0);
   }
-  for (int g = 0; g < 4 && ce == hipSuccess; ++g)
-    if (!groups[g].empty()) ce = soap::apply_batch_launch(ag[g], b->origin);
+  for (int g = 0; g < n_groups && ce == hipSuccess; ++g) ce = soap::apply_batch_launch(ag[g], b->origin);
   e = hipStreamEndCapture(b->origin, &b->graph);
   if (ce != hipSuccess) return fail("capturing the batch", ce);
   if (e != hipSuccess) return fail("hipStreamEndCapture", e);

@@ -526,7 +526,8 @@ soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regio
   }
   pl.G = (pl.paired ? 2 : 3) * c->B;
   pl.n_slabs = (c->N + soap::SLAB_COLS - 1) / soap::SLAB_COLS;
-  pl.n_chunks = (n_phases + c->pc - 1) / c->pc;
+  pl.pc = c->pc;
+  pl.n_chunks = (n_phases + pl.pc - 1) / pl.pc;
   pl.vg_cap = pl.G * ((c->J + soap::APPLY_JW - 1) / soap::APPLY_JW);
   const size_t GJ = (size_t)pl.G * c->J;
 
@@ -548,7 +549,7 @@ soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regio
   const size_t kfx_bytes = sizeof(unsigned long long) * (size_t)n_phases * GJ;
   const size_t k_bytes = sizeof(double) * (size_t)n_phases * GJ;
   const size_t m_bytes = sizeof(unsigned long long) * (size_t)n_phases * pl.G;
-  const size_t vg_bytes = (size_t)soap::WIN_BYTES * pl.n_chunks * pl.vg_cap;
+  const size_t vg_bytes = (size_t)soap::win_bytes(pl.pc, (int)c->esize) * pl.n_chunks * pl.vg_cap;
   const size_t nvg_bytes = sizeof(int) * (size_t)pl.n_chunks;
   const bool regrow = S.par.bytes < par_dev || S.Kfx.bytes < kfx_bytes || S.K.bytes < k_bytes ||
                       S.mask64.bytes < m_bytes || S.vg.bytes < vg_bytes || S.nvg.bytes < nvg_bytes;
@@ -663,6 +664,7 @@ soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regio
   c->last_phases = n_phases;
   c->last_effect = effect;
   c->last_vg_cap = pl.vg_cap;
+  c->last_pc = pl.pc;
   c->last_paired = pl.paired;
   if (dflux != flux) {
     HIP_TRY(hipMemcpyAsync(flux, dflux, out_bytes, hipMemcpyDeviceToHost, c->stream));
@@ -1067,9 +1069,10 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
   out->last_phases = c->last_phases;
   if (c->last_phases > 0) {
     // distinct inputs the last apply walked, from its virtual-group lists
-    const int n_chunks = (c->last_phases + c->pc - 1) / c->pc;
+    const int n_chunks = (c->last_phases + c->last_pc - 1) / c->last_pc;
+    const size_t wb = (size_t)soap::win_bytes(c->last_pc, (int)c->esize);
     std::vector<int> nvg(n_chunks);
-    std::vector<unsigned char> vg((size_t)n_chunks * c->last_vg_cap * soap::WIN_BYTES);
+    std::vector<unsigned char> vg((size_t)n_chunks * c->last_vg_cap * wb);
     const soap_ctx::PrepSet& S = c->prep[c->last_prep];
     HIP_TRY(hipMemcpy(nvg.data(), S.nvg.ptr, sizeof(int) * n_chunks, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(vg.data(), S.vg.ptr, vg.size(), hipMemcpyDeviceToHost));
@@ -1079,7 +1082,7 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
     for (int ch = 0; ch < n_chunks; ++ch)
       for (int v = 0; v < nvg[ch]; ++v) {
         soap::WinHead h;
-        const unsigned char* rec = vg.data() + ((size_t)ch * c->last_vg_cap + v) * soap::WIN_BYTES;
+        const unsigned char* rec = vg.data() + ((size_t)ch * c->last_vg_cap + v) * wb;
         std::memcpy(&h, rec, sizeof(h));
         {
           // taps[q][p] after the header, float or double per the precision;
@@ -1089,18 +1092,18 @@ SOAP_API soap_status soap_profile_read(soap_ctx* c, soap_profile* out) {
           int pairs = 0, offs = 0;
           for (unsigned m = h.gmask; m; m &= m - 1) ++pairs;
           for (int q = 0; q < soap::APPLY_JW; ++q)
-            if ((h.gmask >> (q * (c->pc / 2))) & ((1u << (c->pc / 2)) - 1u)) ++offs;
+            if ((h.gmask >> (q * (c->last_pc / 2))) & ((1u << (c->last_pc / 2)) - 1u)) ++offs;
           out->fma_issued += (int64_t)pairs * 2 + offs;
           for (int q = 0; q < soap::APPLY_JW; ++q) {
             bool any = false;
-            for (int pp = 0; pp < c->pc; ++pp) {
+            for (int pp = 0; pp < c->last_pc; ++pp) {
               double tap;
               if (c->prec == SOAP_PREC_FP32) {
                 float f;
-                std::memcpy(&f, rec + 16 + sizeof(float) * ((size_t)q * c->pc + pp), sizeof f);
+                std::memcpy(&f, rec + 16 + sizeof(float) * ((size_t)q * c->last_pc + pp), sizeof f);
                 tap = f;
               } else {
-                std::memcpy(&tap, rec + 16 + sizeof(double) * ((size_t)q * c->pc + pp), sizeof tap);
+                std::memcpy(&tap, rec + 16 + sizeof(double) * ((size_t)q * c->last_pc + pp), sizeof tap);
               }
               if (tap != 0.0) {
                 ++out->taps_nonzero;

@@ -28,23 +28,35 @@ constexpr int MAX_PHASES = 1 << 20;
 constexpr int MAX_J = 64;  // tap offsets per table row
 
 // Apply kernel shape: a block of APPLY_WAVES waves covers a tile of
-// APPLY_WAVES x 64 x R consecutive pixels for one chunk of PC phases, R = 8
-// and PC = 8 in FP32, R = 4 and PC = 4 in FP64 (ApplyShape); each wave walks
-// the chunk's windows of APPLY_JW offsets over its own 64 x R pixels.  Quiet
-// spectrum and rows are padded to whole tiles of APPLY_TILE_MAX pixels.
+// APPLY_WAVES x 64 x R consecutive pixels for one chunk of PC phases; each
+// wave walks the chunk's windows of APPLY_JW offsets over its own 64 x R
+// pixels with R x PC accumulators per lane (64 floats or 16 doubles), so
+// R = 64 / PC in FP32 (PC = 8 or 16) and R = 16 / PC in FP64 (PC = 4 or 8).
+// PC is a property of the context's tap tables, chosen per context (the
+// first value of each pair is the default).  Quiet spectrum and rows are
+// padded to whole tiles of APPLY_TILE_MAX pixels.
 constexpr int APPLY_JW = 4;
 constexpr int APPLY_WAVES = 4;
 constexpr int APPLY_TILE_MAX = 2048;
 constexpr int PC_MAX = 16;
-constexpr int PC_F32 = 8;
-constexpr int PC_F64 = 4;
-template <typename T>
+constexpr int PC_F32 = 8, PC_F32_WIDE = 16;
+constexpr int PC_F64 = 4, PC_F64_WIDE = 8;
+inline bool pc_valid(bool fp32, int pc) {
+  return fp32 ? (pc == PC_F32 || pc == PC_F32_WIDE) : (pc == PC_F64 || pc == PC_F64_WIDE);
+}
+// bytes of a window record (16-byte header, APPLY_JW x pc taps)
+constexpr int win_bytes(int pc, int esize) { return 16 + APPLY_JW * pc * esize; }
+constexpr int WIN_BYTES_MAX = 16 + APPLY_JW * PC_F32_WIDE * 4;
+template <typename T, int PC>
 struct ApplyShape {
-  static constexpr int R = sizeof(T) == 4 ? 8 : 4;     // pixels per lane
-  static constexpr int PC = sizeof(T) == 4 ? PC_F32 : PC_F64;  // phases per chunk
-  static constexpr int TILE = APPLY_WAVES * 64 * R;    // pixels per block
+  static_assert((sizeof(T) == 4 && (PC == PC_F32 || PC == PC_F32_WIDE)) ||
+                    (sizeof(T) == 8 && (PC == PC_F64 || PC == PC_F64_WIDE)),
+                "phases per chunk");
+  static constexpr int R = (sizeof(T) == 4 ? 64 : 16) / PC;  // pixels per lane
+  static constexpr int TILE = APPLY_WAVES * 64 * R;           // pixels per block
+  static constexpr int WB = win_bytes(PC, (int)sizeof(T));    // window record bytes
+  static_assert(TILE <= APPLY_TILE_MAX && WB <= WIN_BYTES_MAX && APPLY_JW * PC / 2 <= 32, "shape");
 };
-static_assert(ApplyShape<float>::TILE <= APPLY_TILE_MAX && ApplyShape<double>::TILE <= APPLY_TILE_MAX, "padding");
 
 // Padded rows of the local spectra and contrast arrays: PAD_FRONT copies of
 // the first sample before it and copies of the last sample after it, so that
@@ -91,12 +103,8 @@ struct WinHead {
   int jlo;
   unsigned int gmask;
 };
-constexpr int WIN_TAP_BYTES = 128;  // APPLY_JW x 8 floats or APPLY_JW x 4 doubles
-constexpr int WIN_BYTES = 16 + WIN_TAP_BYTES;
 // window records staged in LDS per pass of the apply kernel
 constexpr int APPLY_LDS_WIN = 96;
-static_assert(APPLY_JW * PC_F32 * 4 == WIN_TAP_BYTES && APPLY_JW * PC_F64 * 8 == WIN_TAP_BYTES,
-              "window record size");
 // phase chunks the apply kernel orders by work (more run in their natural order)
 constexpr int APPLY_RANKED = 64;
 
@@ -136,7 +144,7 @@ struct soap_ctx {
   bool has_type[3] = {false, false, false};
   int jmin = 0, jmax = 0, J = 0;  // tap offset range [jmin, jmax], J = jmax - jmin + 1
   size_t esize = 8;               // element size of spectra / flux
-  int pc = soap::PC_F64;          // phases per apply chunk
+  int pc = soap::PC_F64;          // phases per apply chunk of the next call's tables
 
   // resident device state (row pointers point at pixel 0 of row 0)
   void* d_spec_base[3] = {nullptr, nullptr, nullptr};
@@ -166,7 +174,7 @@ struct soap_ctx {
     soap::Workspace Kfx;     // [n_phases][G][J] fixed-point tap accumulators (kept zero)
     soap::Workspace K;       // [n_phases][G][J] double
     soap::Workspace mask64;  // [n_phases][G] bitmask of nonzero offsets
-    soap::Workspace vg;      // [n_chunks][vg_cap] window records (WIN_BYTES each)
+    soap::Workspace vg;      // [n_chunks][vg_cap] window records (win_bytes(pc) each)
     soap::Workspace nvg;     // [n_chunks] int
     bool kfx_dirty = false;  // a call stopped between accumulation and clearing
     hipEvent_t prep_done = nullptr;   // side stream: this set's tables are built
@@ -206,7 +214,7 @@ struct soap_ctx {
   double lsf_resolution = 0.0;
   soap::LsfPlan lsf;
   soap::Workspace ws_lsf;  // synthesis output before the lowering
-  int last_phases = 0, last_effect = 0, last_vg_cap = 0, last_paired = 0;
+  int last_phases = 0, last_effect = 0, last_vg_cap = 0, last_paired = 0, last_pc = 0;
 
   // cached mask
   std::vector<double> mask_lnl, mask_w;
@@ -231,6 +239,7 @@ struct Plan {
   int n_slabs = 0;
   int n_chunks = 0;
   int vg_cap = 0;   // virtual groups per chunk
+  int pc = 0;       // phases per chunk of the tables
 };
 
 // ---- launchers (each enqueues on ctx->stream; return hipError_t) ----------
@@ -271,7 +280,7 @@ struct ApplyBatchCfg {
 };
 struct ApplyBatchGroup {
   bool fp32 = true, paired = true;
-  int n_cfg = 0, n_items = 0, depth = 2, order = 0, effect = SOAP_EFFECT_TOT;
+  int n_cfg = 0, n_items = 0, depth = 2, order = 0, effect = SOAP_EFFECT_TOT, pc = 0;
   void* args = nullptr;  // device ApplyArgs[n_cfg]
   void* off = nullptr;   // device item offsets [n_cfg + 1]
 };

@@ -70,7 +70,8 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
   const int NP = PC / 2;  // mask bits per offset: pairs of phases
   const int GJ = G * J;
   const int nwin = (J + APPLY_JW - 1) / APPLY_JW;
-  unsigned char* wrec = wins + (int64_t)chunk * vg_cap * WIN_BYTES;
+  const int wb = win_bytes(PC, (int)sizeof(T));  // record bytes
+  unsigned char* wrec = wins + (int64_t)chunk * vg_cap * wb;
 
   for (int g = threadIdx.x; g < G; g += blockDim.x) {
     unsigned long long u = 0;
@@ -112,7 +113,7 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
     int v = s_base[g];
     for (int b = s_lo[g]; b < a; b += APPLY_JW)
       if ((u >> b) & ((1ull << APPLY_JW) - 1)) ++v;
-    unsigned char* rec = wrec + (int64_t)v * WIN_BYTES;
+    unsigned char* rec = wrec + (int64_t)v * wb;
     if (q == 0) {
       WinHead h;
       h.t = paired ? g / B + 1 : g / B;
@@ -139,7 +140,7 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
   __syncthreads();
   const int nv = *s_nv;
   for (int v = threadIdx.x; v < nv; v += blockDim.x)
-    reinterpret_cast<WinHead*>(wrec + (int64_t)v * WIN_BYTES)->gmask = s_gm[v];
+    reinterpret_cast<WinHead*>(wrec + (int64_t)v * wb)->gmask = s_gm[v];
 }
 
 // One block per chunk of PC phases: the phases' taps K[ph][g][j] from the
@@ -591,24 +592,25 @@ hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int 
 
 hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o, hipStream_t st) {
   const size_t cmp = (size_t)(6 * pl.G + pl.vg_cap + 2) * sizeof(int);
-  const size_t tab = (size_t)c->pc * ((size_t)pl.G * c->J + pl.G) * sizeof(double);
+  const size_t tab = (size_t)pl.pc * ((size_t)pl.G * c->J + pl.G) * sizeof(double);
+  if (!pc_valid(c->prec == SOAP_PREC_FP32, pl.pc)) return hipErrorInvalidValue;
   const bool in_lds = tab + cmp <= 60 * 1024;
   const size_t lds = in_lds ? tab + cmp : cmp;
   if (lds > 60 * 1024) return hipErrorInvalidValue;
   const dim3 grid(pl.n_chunks), block(FINISH_THREADS);
   if (c->prec == SOAP_PREC_FP32) {
     if (in_lds)
-      hipLaunchKernelGGL((k_finish<float, true>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J, c->jmin,
+      hipLaunchKernelGGL((k_finish<float, true>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J, c->jmin,
                          c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
     else
-      hipLaunchKernelGGL((k_finish<float, false>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J,
+      hipLaunchKernelGGL((k_finish<float, false>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J,
                          c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
   } else {
     if (in_lds)
-      hipLaunchKernelGGL((k_finish<double, true>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J,
+      hipLaunchKernelGGL((k_finish<double, true>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J,
                          c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
     else
-      hipLaunchKernelGGL((k_finish<double, false>), grid, block, lds, st, pl.n_ph, c->pc, pl.G, c->J,
+      hipLaunchKernelGGL((k_finish<double, false>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J,
                          c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
   }
   return hipGetLastError();

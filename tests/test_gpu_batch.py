@@ -36,6 +36,10 @@ def _stars():
 def test_batch_equals_single_calls_on_every_replay():
     stars = _stars()
     ctxs = [L.soap_grid_init(s) for s in stars]
+    # stars on different apply shapes: one launch per group of equal shape
+    L.soap_set_apply_shape(ctxs[0], 2, 0, 8)
+    L.soap_set_apply_shape(ctxs[2], 3, 0, 16)
+    L.soap_set_apply_shape(ctxs[3], 2, 1, 16)
     rng = np.random.default_rng(7)
     cfg_ctx, cfg_star, cfg_regs, cfg_ph, outs = [], [], [], [], []
     for i in range(13):  # stars repeat; region lists and phase counts vary
