@@ -1,10 +1,12 @@
 // Batched synthesis of many activity configurations of many stars
-// (include/soap.h, soap_batch_*): every configuration's table kernels (region
-// parameters, weights, tap lists) are captured once into one HIP graph over a
-// few parallel branches, followed by one shift-and-sum launch per precision
-// and table mode whose blocks walk the (configuration, tile, phase chunk)
-// work list of all configurations, so a run is a single graph launch with no
-// host work per configuration.
+// (include/soap.h, soap_batch_*): the table kernels (region parameters,
+// weights, tap lists) of every configuration run as work-list launches (one
+// per kernel and precision; configurations with differential rotation get
+// one launch each, on parallel branches), followed by one shift-and-sum
+// launch per group of equal shape whose blocks walk the (configuration, tile,
+// phase chunk) work list of its configurations; all of it is captured once
+// into a HIP graph, so a run is a single graph launch with no host work per
+// configuration.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -182,6 +184,13 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     group_off[g] = arena;
     arena += al(soap::apply_batch_bytes((int)groups[g].size()));
   }
+  // the table kernels of configurations with solid-body rotation run as
+  // work-list launches; those with differential rotation keep one launch
+  // each, spread over the branches
+  std::vector<int> listed, single;
+  for (int i = 0; i < n_cfg; ++i) (cp[i].c->diff_rot != 0.0 ? single : listed).push_back(i);
+  const size_t table_off = arena;
+  if (!listed.empty()) arena += al(soap::table_batch_bytes((int)listed.size()));
 
   soap_batch* b = new soap_batch;
   b->n_cfg = n_cfg;
@@ -225,6 +234,31 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     if ((e = soap::apply_batch_upload(ac.data(), (int)ac.size(), A + group_off[g], &ag[g])) != hipSuccess)
       return fail("uploading the shift-and-sum work list", e);
   }
+  auto outs_of = [&](const CfgPlan& q) {
+    soap::WeightsOut wo;
+    wo.reg = reinterpret_cast<soap::Region*>(A + q.off_regcopy);
+    wo.pj = nullptr;
+    wo.cen = reinterpret_cast<double4*>(A + q.off_cen);
+    wo.box = reinterpret_cast<int4*>(A + q.off_box);
+    wo.Kfx = reinterpret_cast<unsigned long long*>(A + q.off_kfx);
+    wo.K = reinterpret_cast<double*>(A + q.off_k);
+    wo.mask = reinterpret_cast<unsigned long long*>(A + q.off_mask);
+    wo.wins = A + q.off_vg;
+    wo.nvg = reinterpret_cast<int*>(A + q.off_nvg);
+    return wo;
+  };
+  soap::TableBatch tb;
+  if (!listed.empty()) {
+    std::vector<soap::TableBatchCfg> tc;
+    for (int i : listed) {
+      const CfgPlan& q = cp[i];
+      tc.push_back(soap::TableBatchCfg{q.c, q.pl, reinterpret_cast<const soap::Region*>(A + q.off_reg), q.n_reg,
+                                       std::max(1, q.n_reg), reinterpret_cast<const double*>(A + q.off_ph),
+                                       outs_of(q)});
+    }
+    if ((e = soap::table_batch_upload(tc.data(), (int)tc.size(), A + table_off, &tb)) != hipSuccess)
+      return fail("uploading the table work lists", e);
+  }
   if ((e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
   for (int k = 0; k < kBranches; ++k) {
     if ((e = hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
@@ -240,23 +274,15 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
   if ((e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed)) != hipSuccess) return fail("capture", e);
   hipError_t ce = hipEventRecord(b->fork, b->origin);
   for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork, 0);
-  for (int i = 0; i < n_cfg && ce == hipSuccess; ++i) {
-    const CfgPlan& q = cp[i];
-    hipStream_t st = b->branch[i % kBranches];
-    soap::WeightsOut wo;
-    wo.reg = reinterpret_cast<soap::Region*>(A + q.off_regcopy);
-    wo.pj = nullptr;
-    wo.cen = reinterpret_cast<double4*>(A + q.off_cen);
-    wo.box = reinterpret_cast<int4*>(A + q.off_box);
-    wo.Kfx = reinterpret_cast<unsigned long long*>(A + q.off_kfx);
-    wo.K = reinterpret_cast<double*>(A + q.off_k);
-    wo.mask = reinterpret_cast<unsigned long long*>(A + q.off_mask);
-    wo.wins = A + q.off_vg;
-    wo.nvg = reinterpret_cast<int*>(A + q.off_nvg);
+  for (size_t u = 0; u < single.size() && ce == hipSuccess; ++u) {
+    const CfgPlan& q = cp[single[u]];
+    hipStream_t st = b->branch[u % kBranches];
+    const soap::WeightsOut wo = outs_of(q);
     ce = soap::launch_weights(q.c, q.pl, reinterpret_cast<const soap::Region*>(A + q.off_reg), q.n_reg,
                               std::max(1, q.n_reg), reinterpret_cast<const double*>(A + q.off_ph), nullptr, wo, st);
     if (ce == hipSuccess) ce = soap::launch_finish(q.c, q.pl, wo, st);
   }
+  if (ce == hipSuccess && !listed.empty()) ce = soap::table_batch_launch(tb, b->origin);
   for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
     ce = hipEventRecord(b->join[k], b->branch[k]);
     if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join[k], 0);

@@ -263,6 +263,71 @@ struct WeightsOut {
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, int max_reg,
                           const double* d_ph, const int2* d_pj, const WeightsOut& o, hipStream_t st);
 hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o, hipStream_t st);
+
+// Arguments of the table kernels for one configuration (region parameters,
+// weights, tap lists); the batched forms take an array of them.
+struct ParamsArgs {
+  int N, n_reg, max_reg, n_ph;
+  double incl, diff_rot;
+  const Region* reg;
+  const double* phases;
+  const int2* pj;
+  Region* reg_out;
+  int2* pj_out;
+  double4* cen;
+  int4* box;
+};
+struct WeightsArgs {
+  int N, B, J, jmin, G, paired, n_slabs, effect, n_reg_all, max_reg;
+  double u1, u2;
+  const double* mu_b;
+  const int* col_c;
+  const double* col_w;
+  const Region* reg;
+  const int2* pj;
+  const double4* cen;
+  const int4* pbox;
+  unsigned long long* Kfx;
+};
+struct FinishArgs {
+  int n_ph, PC, G, J, jmin, B, paired, vg_cap;
+  unsigned long long* Kfx;
+  double* K;
+  unsigned long long* mask;
+  unsigned char* wins;
+  int* nvg;
+};
+
+// Table kernels of many configurations as work-list launches: one launch per
+// kernel (and per precision, and per finish mode), each block finding its
+// configuration by a binary search over the configurations' block offsets.
+// Configurations with differential rotation are not batched here (their
+// weight kernel takes per-cell shifts); table_batch_add refuses them.
+struct TableBatchCfg {
+  soap_ctx* c;
+  Plan pl;
+  const Region* d_reg;
+  int n_reg, max_reg;
+  const double* d_ph;
+  WeightsOut o;
+};
+struct TableBatch {
+  // [kernel][variant]: params (1 variant), weights (FP32, FP64), finish
+  // (FP32 / FP64 x tables in LDS or not)
+  struct Launch {
+    int n_cfg = 0, n_blocks = 0;
+    size_t lds = 0;
+    void* args = nullptr;  // device argument structs
+    int* off = nullptr;    // device block offsets [n_cfg + 1]
+  };
+  Launch params, weights[2], finish[4];
+};
+size_t table_batch_bytes(int n_cfg);
+// builds the work lists of cfgs (none with differential rotation) in d_buf
+// (table_batch_bytes(n) bytes) and uploads them
+hipError_t table_batch_upload(const TableBatchCfg* cfgs, int n, void* d_buf, TableBatch* tb);
+// enqueues params, then weights, then finish (three dependent phases)
+hipError_t table_batch_launch(const TableBatch& tb, hipStream_t st);
 hipError_t launch_apply(soap_ctx* c, const Plan& pl, const void* d_win, const int* d_nvg, void* d_flux);
 // apply with an explicit shape (threads per block, windows staged per LDS
 // pass) on stream st

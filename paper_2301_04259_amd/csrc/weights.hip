@@ -30,6 +30,7 @@
 // Every sum has a fixed order, so results repeat bit for bit.
 #include <algorithm>
 #include <type_traits>
+#include <vector>
 
 #include "soap_internal.hpp"
 #include "wave.hpp"
@@ -149,14 +150,14 @@ __device__ void compact_chunk(int chunk, int n_ph, int PC, int G, int J, int jmi
 // records.  With IN_LDS the chunk's taps and masks stay in LDS; otherwise
 // they go through K and mask in global memory.
 template <typename T, bool IN_LDS>
-__global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int G, int J, int jmin, int B,
-                                                           int paired, int vg_cap,
-                                                           unsigned long long* __restrict__ Kfx,
-                                                           double* __restrict__ K,
-                                                           unsigned long long* __restrict__ mask,
-                                                           unsigned char* __restrict__ wins, int* __restrict__ nvg) {
-  extern __shared__ __align__(16) unsigned char fin_lds[];
-  const int chunk = blockIdx.x;
+__device__ __forceinline__ void finish_block(const FinishArgs& a, int chunk, unsigned char* fin_lds) {
+  const int n_ph = a.n_ph, PC = a.PC, G = a.G, J = a.J, jmin = a.jmin, B = a.B, paired = a.paired,
+            vg_cap = a.vg_cap;
+  unsigned long long* __restrict__ Kfx = a.Kfx;
+  double* __restrict__ K = a.K;
+  unsigned long long* __restrict__ mask = a.mask;
+  unsigned char* __restrict__ wins = a.wins;
+  int* __restrict__ nvg = a.nvg;
   const int p0 = chunk * PC;
   const int np = min(PC, n_ph - p0);
   const int GJ = G * J;
@@ -195,24 +196,36 @@ __global__ void __launch_bounds__(FINISH_THREADS) k_finish(int n_ph, int PC, int
   compact_chunk<T>(chunk, n_ph, PC, G, J, jmin, B, paired, Kc, maskc, wins, nvg, vg_cap, sm);
 }
 
+template <typename T, bool IN_LDS>
+__global__ void __launch_bounds__(FINISH_THREADS) k_finish(FinishArgs a) {
+  extern __shared__ __align__(16) unsigned char fin_lds[];
+  finish_block<T, IN_LDS>(a, blockIdx.x, fin_lds);
+}
+
 // Per phase (one thread each): every region centre rotated to the phase
 // (longitude + 360 deg * phase, axis tilted by the inclination), cos(alpha),
 // and the disk-cell bounding box of the caps that reach the visible
 // hemisphere.  The regions and phases are read once from the caller's
 // parameter block, so the weight kernel's many blocks read device memory.
-__global__ void __launch_bounds__(128) k_params(int N, int n_reg, int max_reg, int n_ph, double incl, double diff_rot,
-                                                const Region* __restrict__ reg,
-                                                const double* __restrict__ phases, const int2* __restrict__ pj,
-                                                Region* __restrict__ reg_out, int2* __restrict__ pj_out,
-                                                double4* __restrict__ cen, int4* __restrict__ box) {
+// Block bid of nblk (128 threads each).
+__device__ __forceinline__ void params_block(const ParamsArgs& a, int bid, int nblk) {
+  const int N = a.N, n_reg = a.n_reg, max_reg = a.max_reg, n_ph = a.n_ph;
+  const double incl = a.incl, diff_rot = a.diff_rot;
+  const Region* __restrict__ reg = a.reg;
+  const double* __restrict__ phases = a.phases;
+  const int2* __restrict__ pj = a.pj;
+  Region* __restrict__ reg_out = a.reg_out;
+  int2* __restrict__ pj_out = a.pj_out;
+  double4* __restrict__ cen = a.cen;
+  int4* __restrict__ box = a.box;
   // one region list for every phase (pj == NULL): staged in LDS; per-phase
   // lists (pj[ph] = first region, count): read from the parameter block
   __shared__ Region s_reg[MAX_REGIONS];
   if (!pj)
     for (int r = threadIdx.x; r < n_reg; r += blockDim.x) s_reg[r] = reg[r];
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_reg; r += gridDim.x * blockDim.x) reg_out[r] = reg[r];
+  for (int r = bid * blockDim.x + threadIdx.x; r < n_reg; r += nblk * blockDim.x) reg_out[r] = reg[r];
   __syncthreads();
-  const int ph = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ph = bid * blockDim.x + threadIdx.x;
   if (ph >= n_ph) return;
   const double phase = phases[ph];
   int2 rl = make_int2(0, n_reg);
@@ -248,20 +261,29 @@ __global__ void __launch_bounds__(128) k_params(int N, int n_reg, int max_reg, i
   box[ph] = make_int4(i0, i1, max(k0, 0), min(k1, N - 1));
 }
 
+__global__ void __launch_bounds__(128) k_params(ParamsArgs a) { params_block(a, blockIdx.x, gridDim.x); }
+
 template <bool KAHAN32>
-__global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
-    int N, int B, int J, int jmin, int G, int paired, int n_slabs, double u1, double u2, int effect,
-    const double* __restrict__ mu_b, const int* __restrict__ col_c, const double* __restrict__ col_w,
-    const Region* __restrict__ reg, int n_reg_all, int max_reg, const int2* __restrict__ pj,
-    const double4* __restrict__ cen, const int4* __restrict__ pbox, unsigned long long* __restrict__ Kfx) {
+__device__ __forceinline__ void weights_block(const WeightsArgs& a, int bid) {
+  const int N = a.N, B = a.B, J = a.J, jmin = a.jmin, G = a.G, paired = a.paired, n_slabs = a.n_slabs,
+            effect = a.effect, n_reg_all = a.n_reg_all, max_reg = a.max_reg;
+  const double u1 = a.u1, u2 = a.u2;
+  const double* __restrict__ mu_b = a.mu_b;
+  const int* __restrict__ col_c = a.col_c;
+  const double* __restrict__ col_w = a.col_w;
+  const Region* __restrict__ reg = a.reg;
+  const int2* __restrict__ pj = a.pj;
+  const double4* __restrict__ cen = a.cen;
+  const int4* __restrict__ pbox = a.pbox;
+  unsigned long long* __restrict__ Kfx = a.Kfx;
   __shared__ double rcx[MAX_REGIONS], rcy[MAX_REGIONS], rcz[MAX_REGIONS], rcos[MAX_REGIONS],
       rscal[MAX_REGIONS], rreach[MAX_REGIONS];
   __shared__ double s_mub[MAX_MU];
   __shared__ int rtype[MAX_REGIONS];
   __shared__ unsigned long long s_tab[WEIGHT_WAVES][3 * MAX_MU];  // per-wave column table
 
-  const int ph = blockIdx.x / n_slabs;
-  const int slab = blockIdx.x - ph * n_slabs;
+  const int ph = bid / n_slabs;
+  const int slab = bid - ph * n_slabs;
   const int nw = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -446,6 +468,11 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(
   }
 }
 
+template <bool KAHAN32>
+__global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(WeightsArgs a) {
+  weights_block<KAHAN32>(a, blockIdx.x);
+}
+
 // Differential rotation: the cells of one column no longer share a shift, so
 // every active cell splits its weight A I (times the owner's scale in split
 // tables) onto its own two offsets (Eq. 11) in a per-wave LDS table
@@ -563,10 +590,76 @@ __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights_dr(
   }
 }
 
+namespace {
+
+ParamsArgs params_args(const soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, int max_reg,
+                       const double* d_ph, const int2* d_pj, const WeightsOut& o) {
+  return ParamsArgs{c->N, n_reg, max_reg, pl.n_ph, c->incl, c->diff_rot, d_reg, d_ph, d_pj, o.reg, o.pj, o.cen, o.box};
+}
+
+WeightsArgs weights_args(const soap_ctx* c, const Plan& pl, int n_reg, int max_reg, const int2* pj,
+                         const WeightsOut& o) {
+  return WeightsArgs{c->N,     c->B,  c->J,       c->jmin,    pl.G,      pl.paired, pl.n_slabs,
+                     pl.effect, n_reg, max_reg,   c->u1,      c->u2,     c->d_mu,   c->d_col_c,
+                     c->d_col_w, o.reg, pj,       o.cen,      o.box,     o.Kfx};
+}
+
+FinishArgs finish_args(const soap_ctx* c, const Plan& pl, const WeightsOut& o) {
+  return FinishArgs{pl.n_ph, pl.pc, pl.G, c->J, c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins,
+                    o.nvg};
+}
+
+// dynamic LDS of the finish kernel and whether the chunk's taps fit in it;
+// false when even the compaction scratch does not fit
+bool finish_lds(const soap_ctx* c, const Plan& pl, size_t* lds, bool* in_lds) {
+  const size_t cmp = (size_t)(6 * pl.G + pl.vg_cap + 2) * sizeof(int);
+  const size_t tab = (size_t)pl.pc * ((size_t)pl.G * c->J + pl.G) * sizeof(double);
+  *in_lds = tab + cmp <= 60 * 1024;
+  *lds = *in_lds ? tab + cmp : cmp;
+  return *lds <= 60 * 1024;
+}
+
+__device__ __forceinline__ int find_cfg(const int* __restrict__ off, int n, int b) {
+  int lo = 0, hi = n;  // last configuration with off[cfg] <= b
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace
+
+// Work-list forms: configuration i owns blocks off[i] .. off[i + 1] - 1.
+__global__ void __launch_bounds__(128) k_params_batch(const ParamsArgs* __restrict__ args, const int* __restrict__ off,
+                                                      int n) {
+  const int i = find_cfg(off, n, blockIdx.x);
+  const ParamsArgs a = args[i];
+  params_block(a, blockIdx.x - off[i], off[i + 1] - off[i]);
+}
+
+template <bool KAHAN32>
+__global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights_batch(const WeightsArgs* __restrict__ args,
+                                                                     const int* __restrict__ off, int n) {
+  const int i = find_cfg(off, n, blockIdx.x);
+  const WeightsArgs a = args[i];
+  weights_block<KAHAN32>(a, blockIdx.x - off[i]);
+}
+
+template <typename T, bool IN_LDS>
+__global__ void __launch_bounds__(FINISH_THREADS) k_finish_batch(const FinishArgs* __restrict__ args,
+                                                                 const int* __restrict__ off, int n) {
+  extern __shared__ __align__(16) unsigned char fin_lds[];
+  const int i = find_cfg(off, n, blockIdx.x);
+  const FinishArgs a = args[i];
+  finish_block<T, IN_LDS>(a, blockIdx.x - off[i], fin_lds);
+}
+
 hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int n_reg, int max_reg,
                           const double* d_ph, const int2* d_pj, const WeightsOut& o, hipStream_t st) {
-  hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, st, c->N, n_reg, max_reg,
-                     pl.n_ph, c->incl, c->diff_rot, d_reg, d_ph, d_pj, o.reg, o.pj, o.cen, o.box);
+  hipLaunchKernelGGL(k_params, dim3((unsigned)((pl.n_ph + 127) / 128)), dim3(128), 0, st,
+                     params_args(c, pl, d_reg, n_reg, max_reg, d_ph, d_pj, o));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int2* pj = d_pj ? o.pj : nullptr;
@@ -579,40 +672,129 @@ hipError_t launch_weights(soap_ctx* c, const Plan& pl, const Region* d_reg, int 
                        c->dln, c->d_mu, o.reg, n_reg, max_reg, pj, o.cen, o.box, o.Kfx);
     return hipGetLastError();
   }
+  const WeightsArgs wa = weights_args(c, pl, n_reg, max_reg, pj, o);
   if (c->prec == SOAP_PREC_FP32)
-    hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, st, c->N, c->B, c->J, c->jmin,
-                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
-                       o.reg, n_reg, max_reg, pj, o.cen, o.box, o.Kfx);
+    hipLaunchKernelGGL(k_weights<true>, grid, dim3(64 * WEIGHT_WAVES), 0, st, wa);
   else
-    hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * WEIGHT_WAVES), 0, st, c->N, c->B, c->J, c->jmin,
-                       pl.G, pl.paired, pl.n_slabs, c->u1, c->u2, pl.effect, c->d_mu, c->d_col_c, c->d_col_w,
-                       o.reg, n_reg, max_reg, pj, o.cen, o.box, o.Kfx);
+    hipLaunchKernelGGL(k_weights<false>, grid, dim3(64 * WEIGHT_WAVES), 0, st, wa);
   return hipGetLastError();
 }
 
 hipError_t launch_finish(soap_ctx* c, const Plan& pl, const WeightsOut& o, hipStream_t st) {
-  const size_t cmp = (size_t)(6 * pl.G + pl.vg_cap + 2) * sizeof(int);
-  const size_t tab = (size_t)pl.pc * ((size_t)pl.G * c->J + pl.G) * sizeof(double);
   if (!pc_valid(c->prec == SOAP_PREC_FP32, pl.pc)) return hipErrorInvalidValue;
-  const bool in_lds = tab + cmp <= 60 * 1024;
-  const size_t lds = in_lds ? tab + cmp : cmp;
-  if (lds > 60 * 1024) return hipErrorInvalidValue;
+  size_t lds = 0;
+  bool in_lds = false;
+  if (!finish_lds(c, pl, &lds, &in_lds)) return hipErrorInvalidValue;
   const dim3 grid(pl.n_chunks), block(FINISH_THREADS);
+  const FinishArgs fa = finish_args(c, pl, o);
   if (c->prec == SOAP_PREC_FP32) {
     if (in_lds)
-      hipLaunchKernelGGL((k_finish<float, true>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J, c->jmin,
-                         c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+      hipLaunchKernelGGL((k_finish<float, true>), grid, block, lds, st, fa);
     else
-      hipLaunchKernelGGL((k_finish<float, false>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J,
-                         c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+      hipLaunchKernelGGL((k_finish<float, false>), grid, block, lds, st, fa);
   } else {
     if (in_lds)
-      hipLaunchKernelGGL((k_finish<double, true>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J,
-                         c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+      hipLaunchKernelGGL((k_finish<double, true>), grid, block, lds, st, fa);
     else
-      hipLaunchKernelGGL((k_finish<double, false>), grid, block, lds, st, pl.n_ph, pl.pc, pl.G, c->J,
-                         c->jmin, c->B, pl.paired, pl.vg_cap, o.Kfx, o.K, o.mask, o.wins, o.nvg);
+      hipLaunchKernelGGL((k_finish<double, false>), grid, block, lds, st, fa);
   }
+  return hipGetLastError();
+}
+
+// ---- table kernels of many configurations ----------------------------------
+
+namespace {
+
+size_t al256(size_t b) { return 256 * ((b + 255) / 256); }
+
+// one launch's argument array and block offsets, appended to the buffer
+template <typename A>
+hipError_t upload_launch(const std::vector<A>& args, const std::vector<int>& blocks, unsigned char* base,
+                         size_t* used, TableBatch::Launch* L) {
+  L->n_cfg = (int)args.size();
+  L->n_blocks = 0;
+  if (args.empty()) return hipSuccess;
+  std::vector<int> off(args.size() + 1, 0);
+  for (size_t i = 0; i < args.size(); ++i) off[i + 1] = off[i] + blocks[i];
+  L->n_blocks = off.back();
+  L->args = base + *used;
+  *used += al256(sizeof(A) * args.size());
+  L->off = reinterpret_cast<int*>(base + *used);
+  *used += al256(sizeof(int) * off.size());
+  hipError_t e = hipMemcpy(L->args, args.data(), sizeof(A) * args.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(L->off, off.data(), sizeof(int) * off.size(), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+size_t table_batch_bytes(int n) {
+  // every configuration appears in params, one weights list and one finish list
+  return al256(sizeof(ParamsArgs) * n) + al256(sizeof(WeightsArgs) * n) * 2 + al256(sizeof(FinishArgs) * n) * 4 +
+         7 * al256(sizeof(int) * (n + 1));
+}
+
+hipError_t table_batch_upload(const TableBatchCfg* cfgs, int n, void* d_buf, TableBatch* tb) {
+  std::vector<ParamsArgs> pa;
+  std::vector<int> pb;
+  std::vector<WeightsArgs> wa[2];
+  std::vector<int> wb[2];
+  std::vector<FinishArgs> fa[4];
+  std::vector<int> fb[4];
+  size_t flds[4] = {0, 0, 0, 0};
+  for (int i = 0; i < n; ++i) {
+    const TableBatchCfg& q = cfgs[i];
+    const soap_ctx* c = q.c;
+    if (c->diff_rot != 0.0 || !pc_valid(c->prec == SOAP_PREC_FP32, q.pl.pc)) return hipErrorInvalidValue;
+    pa.push_back(params_args(c, q.pl, q.d_reg, q.n_reg, q.max_reg, q.d_ph, nullptr, q.o));
+    pb.push_back((q.pl.n_ph + 127) / 128);
+    const int w = c->prec == SOAP_PREC_FP32 ? 0 : 1;
+    wa[w].push_back(weights_args(c, q.pl, q.n_reg, q.max_reg, nullptr, q.o));
+    wb[w].push_back(q.pl.n_slabs * q.pl.n_ph);
+    size_t lds = 0;
+    bool in_lds = false;
+    if (!finish_lds(c, q.pl, &lds, &in_lds)) return hipErrorInvalidValue;
+    const int f = 2 * w + (in_lds ? 0 : 1);
+    fa[f].push_back(finish_args(c, q.pl, q.o));
+    fb[f].push_back(q.pl.n_chunks);
+    flds[f] = std::max(flds[f], lds);
+  }
+  unsigned char* base = static_cast<unsigned char*>(d_buf);
+  size_t used = 0;
+  hipError_t e = upload_launch(pa, pb, base, &used, &tb->params);
+  for (int w = 0; w < 2 && e == hipSuccess; ++w) e = upload_launch(wa[w], wb[w], base, &used, &tb->weights[w]);
+  for (int f = 0; f < 4 && e == hipSuccess; ++f) {
+    e = upload_launch(fa[f], fb[f], base, &used, &tb->finish[f]);
+    tb->finish[f].lds = flds[f];
+  }
+  return e;
+}
+
+hipError_t table_batch_launch(const TableBatch& tb, hipStream_t st) {
+  if (tb.params.n_blocks > 0)
+    hipLaunchKernelGGL(k_params_batch, dim3((unsigned)tb.params.n_blocks), dim3(128), 0, st,
+                       static_cast<const ParamsArgs*>(tb.params.args), tb.params.off, tb.params.n_cfg);
+  const dim3 wblock(64 * WEIGHT_WAVES), fblock(FINISH_THREADS);
+  const TableBatch::Launch* W = tb.weights;
+  if (W[0].n_blocks > 0)
+    hipLaunchKernelGGL(k_weights_batch<true>, dim3((unsigned)W[0].n_blocks), wblock, 0, st,
+                       static_cast<const WeightsArgs*>(W[0].args), W[0].off, W[0].n_cfg);
+  if (W[1].n_blocks > 0)
+    hipLaunchKernelGGL(k_weights_batch<false>, dim3((unsigned)W[1].n_blocks), wblock, 0, st,
+                       static_cast<const WeightsArgs*>(W[1].args), W[1].off, W[1].n_cfg);
+  const TableBatch::Launch* F = tb.finish;
+  if (F[0].n_blocks > 0)
+    hipLaunchKernelGGL((k_finish_batch<float, true>), dim3((unsigned)F[0].n_blocks), fblock, F[0].lds, st,
+                       static_cast<const FinishArgs*>(F[0].args), F[0].off, F[0].n_cfg);
+  if (F[1].n_blocks > 0)
+    hipLaunchKernelGGL((k_finish_batch<float, false>), dim3((unsigned)F[1].n_blocks), fblock, F[1].lds, st,
+                       static_cast<const FinishArgs*>(F[1].args), F[1].off, F[1].n_cfg);
+  if (F[2].n_blocks > 0)
+    hipLaunchKernelGGL((k_finish_batch<double, true>), dim3((unsigned)F[2].n_blocks), fblock, F[2].lds, st,
+                       static_cast<const FinishArgs*>(F[2].args), F[2].off, F[2].n_cfg);
+  if (F[3].n_blocks > 0)
+    hipLaunchKernelGGL((k_finish_batch<double, false>), dim3((unsigned)F[3].n_blocks), fblock, F[3].lds, st,
+                       static_cast<const FinishArgs*>(F[3].args), F[3].off, F[3].n_cfg);
   return hipGetLastError();
 }
 
