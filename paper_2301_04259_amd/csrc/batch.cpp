@@ -189,8 +189,23 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
   // each, spread over the branches
   std::vector<int> listed, single;
   for (int i = 0; i < n_cfg; ++i) (cp[i].c->diff_rot != 0.0 ? single : listed).push_back(i);
+  // host copies of every configuration's regions (kernel layout)
+  std::vector<std::vector<soap::Region>> hregs(n_cfg);
+  for (int i = 0; i < n_cfg; ++i) {
+    const int r0 = region_offsets[i];
+    hregs[i].assign(std::max(1, cp[i].n_reg), soap::Region{});
+    for (int r = 0; r < cp[i].n_reg; ++r) {
+      const soap_region& R = regions[r0 + r];
+      hregs[i][r] = soap::Region{R.type, 0, R.lat_deg, R.lon_deg, R.radius, R.contrast};
+    }
+  }
+  // work-list entries (device pointers filled in once the arena exists)
+  std::vector<soap::TableBatchCfg> tc;
+  for (int i : listed)
+    tc.push_back(soap::TableBatchCfg{cp[i].c, cp[i].pl, nullptr, cp[i].n_reg, std::max(1, cp[i].n_reg), nullptr,
+                                     soap::WeightsOut{}, hregs[i].data(), phases + phase_offsets[i]});
   const size_t table_off = arena;
-  if (!listed.empty()) arena += al(soap::table_batch_bytes((int)listed.size()));
+  if (!listed.empty()) arena += al(soap::table_batch_bytes(tc.data(), (int)tc.size()));
 
   soap_batch* b = new soap_batch;
   b->n_cfg = n_cfg;
@@ -209,15 +224,9 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
   if ((e = hipMemset(b->arena, 0, arena)) != hipSuccess) return fail("hipMemset", e);
   unsigned char* A = static_cast<unsigned char*>(b->arena);
   {
-    std::vector<soap::Region> hr;
     for (int i = 0; i < n_cfg; ++i) {
       const CfgPlan& q = cp[i];
-      const int r0 = region_offsets[i];
-      hr.assign(std::max(1, q.n_reg), soap::Region{});
-      for (int r = 0; r < q.n_reg; ++r) {
-        const soap_region& R = regions[r0 + r];
-        hr[r] = soap::Region{R.type, 0, R.lat_deg, R.lon_deg, R.radius, R.contrast};
-      }
+      const std::vector<soap::Region>& hr = hregs[i];
       if ((e = hipMemcpy(A + q.off_reg, hr.data(), sizeof(soap::Region) * hr.size(), hipMemcpyHostToDevice)) !=
               hipSuccess ||
           (e = hipMemcpy(A + q.off_ph, phases + phase_offsets[i], sizeof(double) * q.pl.n_ph,
@@ -249,12 +258,11 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
   };
   soap::TableBatch tb;
   if (!listed.empty()) {
-    std::vector<soap::TableBatchCfg> tc;
-    for (int i : listed) {
-      const CfgPlan& q = cp[i];
-      tc.push_back(soap::TableBatchCfg{q.c, q.pl, reinterpret_cast<const soap::Region*>(A + q.off_reg), q.n_reg,
-                                       std::max(1, q.n_reg), reinterpret_cast<const double*>(A + q.off_ph),
-                                       outs_of(q)});
+    for (size_t u = 0; u < listed.size(); ++u) {
+      const CfgPlan& q = cp[listed[u]];
+      tc[u].d_reg = reinterpret_cast<const soap::Region*>(A + q.off_reg);
+      tc[u].d_ph = reinterpret_cast<const double*>(A + q.off_ph);
+      tc[u].o = outs_of(q);
     }
     if ((e = soap::table_batch_upload(tc.data(), (int)tc.size(), A + table_off, &tb)) != hipSuccess)
       return fail("uploading the table work lists", e);

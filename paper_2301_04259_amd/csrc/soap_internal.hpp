@@ -310,6 +310,8 @@ struct TableBatchCfg {
   int n_reg, max_reg;
   const double* d_ph;
   WeightsOut o;
+  const Region* h_reg;  // host copies of the regions and phases: the weight
+  const double* h_ph;   // launch lists only the slabs the caps can reach
 };
 struct TableBatch {
   // [kernel][variant]: params (1 variant), weights (FP32, FP64), finish
@@ -318,11 +320,12 @@ struct TableBatch {
     int n_cfg = 0, n_blocks = 0;
     size_t lds = 0;
     void* args = nullptr;  // device argument structs
-    int* off = nullptr;    // device block offsets [n_cfg + 1]
+    int* off = nullptr;    // device block offsets [n_cfg + 1] (params, finish)
+    int4* blk = nullptr;   // device (cfg, phase, slab) per block (weights)
   };
   Launch params, weights[2], finish[4];
 };
-size_t table_batch_bytes(int n_cfg);
+size_t table_batch_bytes(const TableBatchCfg* cfgs, int n_cfg);
 // builds the work lists of cfgs (none with differential rotation) in d_buf
 // (table_batch_bytes(n) bytes) and uploads them
 hipError_t table_batch_upload(const TableBatchCfg* cfgs, int n, void* d_buf, TableBatch* tb);

@@ -29,6 +29,7 @@
 // phases that have a tap.
 // Every sum has a fixed order, so results repeat bit for bit.
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -264,9 +265,9 @@ __device__ __forceinline__ void params_block(const ParamsArgs& a, int bid, int n
 __global__ void __launch_bounds__(128) k_params(ParamsArgs a) { params_block(a, blockIdx.x, gridDim.x); }
 
 template <bool KAHAN32>
-__device__ __forceinline__ void weights_block(const WeightsArgs& a, int bid) {
-  const int N = a.N, B = a.B, J = a.J, jmin = a.jmin, G = a.G, paired = a.paired, n_slabs = a.n_slabs,
-            effect = a.effect, n_reg_all = a.n_reg_all, max_reg = a.max_reg;
+__device__ __forceinline__ void weights_block(const WeightsArgs& a, int ph, int slab) {
+  const int N = a.N, B = a.B, J = a.J, jmin = a.jmin, G = a.G, paired = a.paired, effect = a.effect,
+            n_reg_all = a.n_reg_all, max_reg = a.max_reg;
   const double u1 = a.u1, u2 = a.u2;
   const double* __restrict__ mu_b = a.mu_b;
   const int* __restrict__ col_c = a.col_c;
@@ -282,8 +283,6 @@ __device__ __forceinline__ void weights_block(const WeightsArgs& a, int bid) {
   __shared__ int rtype[MAX_REGIONS];
   __shared__ unsigned long long s_tab[WEIGHT_WAVES][3 * MAX_MU];  // per-wave column table
 
-  const int ph = bid / n_slabs;
-  const int slab = bid - ph * n_slabs;
   const int nw = blockDim.x >> 6;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -470,7 +469,8 @@ __device__ __forceinline__ void weights_block(const WeightsArgs& a, int bid) {
 
 template <bool KAHAN32>
 __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights(WeightsArgs a) {
-  weights_block<KAHAN32>(a, blockIdx.x);
+  const int ph = blockIdx.x / a.n_slabs;
+  weights_block<KAHAN32>(a, ph, blockIdx.x - ph * a.n_slabs);
 }
 
 // Differential rotation: the cells of one column no longer share a shift, so
@@ -639,12 +639,13 @@ __global__ void __launch_bounds__(128) k_params_batch(const ParamsArgs* __restri
   params_block(a, blockIdx.x - off[i], off[i + 1] - off[i]);
 }
 
+// one block per listed (configuration, phase, slab): blk[b] = (cfg, ph, slab)
 template <bool KAHAN32>
 __global__ void __launch_bounds__(WEIGHT_WAVES * 64) k_weights_batch(const WeightsArgs* __restrict__ args,
-                                                                     const int* __restrict__ off, int n) {
-  const int i = find_cfg(off, n, blockIdx.x);
-  const WeightsArgs a = args[i];
-  weights_block<KAHAN32>(a, blockIdx.x - off[i]);
+                                                                     const int4* __restrict__ blk) {
+  const int4 t = blk[blockIdx.x];
+  const WeightsArgs a = args[t.x];
+  weights_block<KAHAN32>(a, t.y, t.z);
 }
 
 template <typename T, bool IN_LDS>
@@ -728,17 +729,48 @@ hipError_t upload_launch(const std::vector<A>& args, const std::vector<int>& blo
 
 }  // namespace
 
-size_t table_batch_bytes(int n) {
+// Slabs of disk columns that the visible caps of a configuration can reach
+// at one phase, from the region centres computed on the host with the
+// kernels' formulas and widened by one slab on each side (so host/device
+// rounding cannot drop a column; the kernel applies the exact bounds).
+void reachable_slabs(const TableBatchCfg& q, int ph, std::vector<int4>& out, int cfg) {
+#ifndef __HIP_DEVICE_COMPILE__  // host code (region_centre is host-callable in the host pass only)
+  const soap_ctx* c = q.c;
+  double xlo = 2.0, xhi = -2.0;
+  for (int r = 0; r < q.n_reg; ++r) {
+    const Region& g = q.h_reg[r];
+    double cx, cy, cz;
+    region_centre(g.lat_deg, g.lon_deg, q.h_ph[ph], c->incl, c->diff_rot, &cx, &cy, &cz);
+    const double rc = std::sqrt(1.0 - g.radius * g.radius);
+    const double rad = std::sqrt(std::fmax(0.0, 1.0 - rc * rc));
+    if (cz <= -rad - 1e-6) continue;  // the kernels drop it below -rad - 1e-12
+    const double d = std::sqrt(std::fmax(0.0, 2.0 - 2.0 * rc)) + 1e-6;
+    xlo = std::fmin(xlo, cx - d);
+    xhi = std::fmax(xhi, cx + d);
+  }
+  if (xlo > xhi) return;
+  const int N = c->N;
+  const int i0 = std::max(0, (int)std::floor((xlo + 1.0) * 0.5 * N) - 2);
+  const int i1 = std::min(N - 1, (int)std::ceil((xhi + 1.0) * 0.5 * N) + 2);
+  if (i0 > i1) return;
+  const int s0 = std::max(0, i0 / SLAB_COLS - 1), s1 = std::min(q.pl.n_slabs - 1, i1 / SLAB_COLS + 1);
+  for (int sl = s0; sl <= s1; ++sl) out.push_back(make_int4(cfg, ph, sl, 0));
+#endif
+}
+
+size_t table_batch_bytes(const TableBatchCfg* cfgs, int n) {
+  size_t blocks = 0;
+  for (int i = 0; i < n; ++i) blocks += (size_t)cfgs[i].pl.n_ph * cfgs[i].pl.n_slabs;  // upper bound
   // every configuration appears in params, one weights list and one finish list
   return al256(sizeof(ParamsArgs) * n) + al256(sizeof(WeightsArgs) * n) * 2 + al256(sizeof(FinishArgs) * n) * 4 +
-         7 * al256(sizeof(int) * (n + 1));
+         5 * al256(sizeof(int) * (n + 1)) + 2 * al256(sizeof(int4) * blocks);
 }
 
 hipError_t table_batch_upload(const TableBatchCfg* cfgs, int n, void* d_buf, TableBatch* tb) {
   std::vector<ParamsArgs> pa;
   std::vector<int> pb;
   std::vector<WeightsArgs> wa[2];
-  std::vector<int> wb[2];
+  std::vector<int4> wblk[2];
   std::vector<FinishArgs> fa[4];
   std::vector<int> fb[4];
   size_t flds[4] = {0, 0, 0, 0};
@@ -749,8 +781,9 @@ hipError_t table_batch_upload(const TableBatchCfg* cfgs, int n, void* d_buf, Tab
     pa.push_back(params_args(c, q.pl, q.d_reg, q.n_reg, q.max_reg, q.d_ph, nullptr, q.o));
     pb.push_back((q.pl.n_ph + 127) / 128);
     const int w = c->prec == SOAP_PREC_FP32 ? 0 : 1;
+    const int wi = (int)wa[w].size();
     wa[w].push_back(weights_args(c, q.pl, q.n_reg, q.max_reg, nullptr, q.o));
-    wb[w].push_back(q.pl.n_slabs * q.pl.n_ph);
+    for (int ph = 0; ph < q.pl.n_ph; ++ph) reachable_slabs(q, ph, wblk[w], wi);
     size_t lds = 0;
     bool in_lds = false;
     if (!finish_lds(c, q.pl, &lds, &in_lds)) return hipErrorInvalidValue;
@@ -762,7 +795,21 @@ hipError_t table_batch_upload(const TableBatchCfg* cfgs, int n, void* d_buf, Tab
   unsigned char* base = static_cast<unsigned char*>(d_buf);
   size_t used = 0;
   hipError_t e = upload_launch(pa, pb, base, &used, &tb->params);
-  for (int w = 0; w < 2 && e == hipSuccess; ++w) e = upload_launch(wa[w], wb[w], base, &used, &tb->weights[w]);
+  for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+    TableBatch::Launch& L = tb->weights[w];
+    L.n_cfg = (int)wa[w].size();
+    L.n_blocks = (int)wblk[w].size();
+    if (wa[w].empty() || wblk[w].empty()) {
+      L.n_blocks = 0;
+      continue;
+    }
+    L.args = base + used;
+    used += al256(sizeof(WeightsArgs) * wa[w].size());
+    L.blk = reinterpret_cast<int4*>(base + used);
+    used += al256(sizeof(int4) * wblk[w].size());
+    e = hipMemcpy(L.args, wa[w].data(), sizeof(WeightsArgs) * wa[w].size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(L.blk, wblk[w].data(), sizeof(int4) * wblk[w].size(), hipMemcpyHostToDevice);
+  }
   for (int f = 0; f < 4 && e == hipSuccess; ++f) {
     e = upload_launch(fa[f], fb[f], base, &used, &tb->finish[f]);
     tb->finish[f].lds = flds[f];
@@ -778,10 +825,10 @@ hipError_t table_batch_launch(const TableBatch& tb, hipStream_t st) {
   const TableBatch::Launch* W = tb.weights;
   if (W[0].n_blocks > 0)
     hipLaunchKernelGGL(k_weights_batch<true>, dim3((unsigned)W[0].n_blocks), wblock, 0, st,
-                       static_cast<const WeightsArgs*>(W[0].args), W[0].off, W[0].n_cfg);
+                       static_cast<const WeightsArgs*>(W[0].args), W[0].blk);
   if (W[1].n_blocks > 0)
     hipLaunchKernelGGL(k_weights_batch<false>, dim3((unsigned)W[1].n_blocks), wblock, 0, st,
-                       static_cast<const WeightsArgs*>(W[1].args), W[1].off, W[1].n_cfg);
+                       static_cast<const WeightsArgs*>(W[1].args), W[1].blk);
   const TableBatch::Launch* F = tb.finish;
   if (F[0].n_blocks > 0)
     hipLaunchKernelGGL((k_finish_batch<float, true>), dim3((unsigned)F[0].n_blocks), fblock, F[0].lds, st,
