@@ -560,6 +560,17 @@ soap_status soap_pca_project(const float* d, int64_t n, int64_t n_pix, int64_t l
                              const int32_t* mean_index, int32_t n_mean, const float* V, int32_t k, float* coef,
                              void* hip_stream);
 
+/* Network inputs of n samples from their raw descriptions, on the device:
+ * raw[i] = (spot latitude deg, longitude deg, radius R*, contrast, rotation
+ * phase, T_eff K, inclination deg, v sin i km/s) (double [n][8]); x[i] =
+ * 12 floats: latitude / 60 deg, sine and cosine of the rotated longitude
+ * (longitude + 360 deg x phase), the spot centre on the sky (x; y along the
+ * projected axis; z towards the observer), radius, contrast, T_eff,
+ * inclination and v sin i each centred and scaled over their sampled ranges
+ * ((r - 0.055) / 0.045, (c - 0.6) / 0.3, (T - 5500) / 1000, (i - 60) / 30,
+ * (v - 3) / 2), and 1.  n 1 .. 2^26.  Enqueues on hip_stream.              */
+soap_status soap_surrogate_features(const double* raw, int64_t n, float* x, void* hip_stream);
+
 /* Ensemble gate.  rv[(1 + n_ens) n] (device) holds the fits of the
  * ensemble-mean prediction (rows 0 .. n-1) and then of member e (rows
  * (1 + e) n ..).  For sample i: rv_kms[i] = the mean prediction's RV,

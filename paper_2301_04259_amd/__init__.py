@@ -92,6 +92,7 @@ SYMBOLS = (
     "soap_surrogate_destroy",
     "soap_pca_project",
     "soap_surrogate_gate",
+    "soap_surrogate_features",
     "soap_evolution_size",
     "soap_active_spectra_evolving",
     "soap_instrument_lsf",
@@ -273,6 +274,8 @@ _lib.soap_surrogate_destroy.restype = None
 _lib.soap_pca_project.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
                                   C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
 _lib.soap_pca_project.restype = C.c_int
+_lib.soap_surrogate_features.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+_lib.soap_surrogate_features.restype = C.c_int
 _lib.soap_surrogate_gate.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_double, C.c_double, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.soap_surrogate_gate.restype = C.c_int
@@ -756,6 +759,17 @@ def soap_pca_project(d, mean, V, coef, n_pix=None, stream=None, mean_index=None)
                                n_mean, _dptr(V, "V"), int(V.shape[1]), _dptr(coef, "coef"), _stream_handle(stream))
     _sg_check(st, None)
     return coef
+
+
+def soap_surrogate_features(raw, x, stream=None):
+    """Network inputs x [n][12] (float32, device) of raw sample descriptions
+    raw [n][8] (float64, device; see soap.h)."""
+    n = int(raw.shape[0])
+    if tuple(raw.shape) != (n, 8) or tuple(x.shape) != (n, 12):
+        raise ValueError("raw must be [n][8] and x [n][12]")
+    st = _lib.soap_surrogate_features(_dptr(raw, "raw"), n, _dptr(x, "x"), _stream_handle(stream))
+    _sg_check(st, None)
+    return x
 
 
 def soap_surrogate_gate(rv, n, n_ens, calib, threshold_kms, rv_kms, fallback, err_kms=None, stream=None):

@@ -338,22 +338,24 @@ soap_status init_impl(const soap_star_desc* d, soap_ctx* c) {
   // the device copies must be finite: device inputs were not checked on the
   // host, and a host input that was finite there yet is not here means the
   // upload went wrong
+  // d_flag[0]: rows, d_flag[1]: quiet spectrum; read back with a blocking
+  // copy once the stream is idle
   int* d_flag = nullptr;
-  HIP_TRY(soap::dev_malloc((void**)&d_flag, sizeof(int)));
+  HIP_TRY(soap::dev_malloc((void**)&d_flag, 2 * sizeof(int)));
   int h_flag[2] = {0, 0};
-  hipError_t fe = hipMemsetAsync(d_flag, 0, sizeof(int), c->stream);
+  hipError_t fe = hipMemsetAsync(d_flag, 0, 2 * sizeof(int), c->stream);
   for (int t = 0; t < 3 && fe == hipSuccess; ++t)
     if (c->d_spec_base[t]) fe = soap::launch_check_finite(c, c->d_spec_base[t], c->B, false, d_flag);
   if (fe == hipSuccess && c->d_con_base) fe = soap::launch_check_finite(c, c->d_con_base, c->con_rows, false, d_flag);
-  if (fe == hipSuccess) fe = hipMemcpyAsync(&h_flag[0], d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
-  if (fe == hipSuccess) fe = hipMemsetAsync(d_flag, 0, sizeof(int), c->stream);
-  if (fe == hipSuccess) fe = soap::launch_check_finite(c, nullptr, 0, true, d_flag);
-  if (fe == hipSuccess) fe = hipMemcpyAsync(&h_flag[1], d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (fe == hipSuccess) fe = soap::launch_check_finite(c, nullptr, 0, true, d_flag + 1);
   // host arrays (mu bins, spectra) may be released once the call returns
   const hipError_t se = hipStreamSynchronize(c->stream);
+  const hipError_t me =
+      (fe == hipSuccess && se == hipSuccess) ? hipMemcpy(h_flag, d_flag, sizeof h_flag, hipMemcpyDeviceToHost) : fe;
   (void)soap::dev_free(d_flag);
   HIP_TRY(fe);
   HIP_TRY(se);
+  HIP_TRY(me);
   if (h_flag[0] || h_flag[1]) {
     const char* what = h_flag[0] ? "the device copy of the local spectra or contrast arrays"
                                  : "the quiet integrated spectrum";
@@ -491,8 +493,8 @@ SOAP_API soap_status soap_quiet_spectrum(soap_ctx* c, void* out, int32_t out_on_
   else
     HIP_TRY(soap::launch_q_convert(c, dst));
   if (!out_on_device) {
-    HIP_TRY(hipMemcpyAsync(out, dst, bytes, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(out, dst, bytes, hipMemcpyDeviceToHost));
   }
   return SOAP_OK;
 }
@@ -667,8 +669,8 @@ soap_status active_impl(soap_ctx* c, const soap_region* regions, int32_t n_regio
   c->last_pc = pl.pc;
   c->last_paired = pl.paired;
   if (dflux != flux) {
-    HIP_TRY(hipMemcpyAsync(flux, dflux, out_bytes, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(flux, dflux, out_bytes, hipMemcpyDeviceToHost));
   }
   return SOAP_OK;
 }
@@ -874,8 +876,8 @@ SOAP_API soap_status soap_instrument_lsf(soap_ctx* c, const void* in, void* out,
     t.done();
   }
   if (!on_device) {
-    HIP_TRY(hipMemcpyAsync(out, dout, bytes, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(out, dout, bytes, hipMemcpyDeviceToHost));
   }
   return SOAP_OK;
 }
@@ -958,7 +960,6 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
     t.done();
   }
   c->ccf_calls++;
-  bool sync = false;
   soap_rv* drv = nullptr;
   if (rv_out) {
     drv = rv_on_device ? rv_out : nullptr;
@@ -972,15 +973,11 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
     HIP_TRY(soap::launch_ccf_fit(c, nl, c->ws_ccf.ptr, n_spec, dccf, drv));
     t.done();
   }
-  if (rv_out && !rv_on_device) {
-    HIP_TRY(hipMemcpyAsync(rv_out, drv, sizeof(soap_rv) * n_spec, hipMemcpyDeviceToHost, c->stream));
-    sync = true;
-  }
-  if (ccf_out && !ccf_on_device) {
-    HIP_TRY(hipMemcpyAsync(ccf_out, dccf, sizeof(double) * ccf_elems, hipMemcpyDeviceToHost, c->stream));
-    sync = true;
-  }
-  if (sync || !flux_on_device) HIP_TRY(hipStreamSynchronize(c->stream));
+  // host outputs: blocking copies once the stream is idle
+  const bool rv_host = rv_out && !rv_on_device, ccf_host = ccf_out && !ccf_on_device;
+  if (rv_host || ccf_host || !flux_on_device) HIP_TRY(hipStreamSynchronize(c->stream));
+  if (rv_host) HIP_TRY(hipMemcpy(rv_out, drv, sizeof(soap_rv) * n_spec, hipMemcpyDeviceToHost));
+  if (ccf_host) HIP_TRY(hipMemcpy(ccf_out, dccf, sizeof(double) * ccf_elems, hipMemcpyDeviceToHost));
   return SOAP_OK;
 }
 

@@ -230,6 +230,36 @@ __global__ void k_gate(int64_t n, int E, double calib, double thr, const soap_rv
 // coef[n][k] = sum_p (D[n][p] - mean[p]) V[p][k] (mean row mean_idx[n] when
 // given): 64 x 64 tile per block of
 // 256 threads (4 x 4 outputs each), K in steps of 32 through LDS, FP32
+// Network inputs of one sample from its raw description r = (lat, lon,
+// radius, contrast, phase, T_eff, inclination, v sin i) in degrees, R*, K
+// and km/s: the spot latitude scaled to +-60 deg, the sine and cosine of
+// its rotated longitude, its centre on the sky (x, y, z; y up the projected
+// axis, z towards the observer), and the scalar parameters centred and
+// scaled over their sampled ranges, then a constant 1.
+__global__ void __launch_bounds__(256) k_features(int64_t n, const double* __restrict__ raw, float* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* r = raw + i * SG_RAW;
+  constexpr double D2R = 3.14159265358979323846 / 180.0;
+  const double lat = r[0] * D2R;
+  const double th = (r[1] + 360.0 * r[4]) * D2R;
+  const double inc = r[6] * D2R;
+  const double cl = cos(lat), sl = sin(lat), st = sin(th), ct = cos(th), si = sin(inc), ci = cos(inc);
+  float* o = x + i * SG_FEATURES;
+  o[0] = (float)(lat / (60.0 * D2R));
+  o[1] = (float)st;
+  o[2] = (float)ct;
+  o[3] = (float)(cl * st);
+  o[4] = (float)(sl * si - cl * ct * ci);
+  o[5] = (float)(sl * ci + cl * ct * si);
+  o[6] = (float)((r[2] - 0.055) / 0.045);
+  o[7] = (float)((r[3] - 0.6) / 0.3);
+  o[8] = (float)((r[5] - 5500.0) / 1000.0);
+  o[9] = (float)((r[6] - 60.0) / 30.0);
+  o[10] = (float)((r[7] - 3.0) / 2.0);
+  o[11] = 1.0f;
+}
+
 __global__ void __launch_bounds__(256) k_pca_project(int n, int P, int k, const float* __restrict__ D,
                                                      int64_t ldd, const float* __restrict__ mean,
                                                      const int* __restrict__ mean_idx, int n_mean,
@@ -386,6 +416,12 @@ hipError_t sg_ens_mean(soap_surrogate* s, int B, float* mean) {
 hipError_t sg_gate(hipStream_t st, const soap_rv* rv, int64_t n, int E, double calib, double thr, double* rv_kms,
                    double* err_kms, int* fallback) {
   hipLaunchKernelGGL(k_gate, blocks(n), dim3(256), 0, st, n, E, calib, thr, rv, rv_kms, err_kms, fallback);
+  return hipGetLastError();
+}
+
+hipError_t sg_features(hipStream_t st, int64_t n, const double* raw, float* x) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, raw, x);
   return hipGetLastError();
 }
 

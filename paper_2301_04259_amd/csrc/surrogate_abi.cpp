@@ -207,8 +207,8 @@ SOAP_API soap_status soap_surrogate_train_step(soap_surrogate* s, const float* x
   SG_HIP(soap::sg_adam(s, lr));
   if (loss_out) {
     std::vector<float> l(s->n_ens);
-    SG_HIP(hipMemcpyAsync(l.data(), s->loss, sizeof(float) * s->n_ens, hipMemcpyDeviceToHost, s->stream));
     SG_HIP(hipStreamSynchronize(s->stream));
+    SG_HIP(hipMemcpy(l.data(), s->loss, sizeof(float) * s->n_ens, hipMemcpyDeviceToHost));
     double a = 0.0;
     for (float v : l) a += v;
     *loss_out = (float)(a / s->n_ens);
@@ -348,6 +348,12 @@ SOAP_API soap_status soap_pca_project(const float* d_dev, int64_t n, int64_t n_p
   if (soap::sg_pca_project(st, (int)n, (int)n_pix, k, d_dev, ld, mean_dev, mean_index, n_mean, basis_dev,
                            coef_dev) != hipSuccess)
     return SOAP_ERR_HIP;
+  return SOAP_OK;
+}
+
+SOAP_API soap_status soap_surrogate_features(const double* raw_dev, int64_t n, float* x_dev, void* hip_stream) {
+  if (!raw_dev || !x_dev || n < 1 || n > (int64_t(1) << 26)) return SOAP_ERR_ARG;
+  if (soap::sg_features(static_cast<hipStream_t>(hip_stream), n, raw_dev, x_dev) != hipSuccess) return SOAP_ERR_HIP;
   return SOAP_OK;
 }
 

@@ -11,6 +11,8 @@
 namespace soap {
 
 constexpr int SG_K0 = 32;            // input width padded to one MFMA K step
+constexpr int SG_RAW = 8;            // raw sample description (soap_surrogate_features)
+constexpr int SG_FEATURES = 12;      // network inputs made from it
 constexpr int SG_COLSUM_ROWS = 128;  // rows per partial column sum
 
 enum { MM_PLAIN = 0, MM_HIDDEN = 1, MM_OUTPUT = 2, MM_DHIDDEN = 3 };
@@ -59,6 +61,8 @@ hipError_t sg_sync_bf16(soap_surrogate* s);
 hipError_t sg_ens_mean(soap_surrogate* s, int B, float* mean);
 hipError_t sg_gate(hipStream_t st, const soap_rv* rv, int64_t n, int E, double calib, double thr, double* rv_kms,
                    double* err_kms, int* fallback);
+// network inputs [n][SG_FEATURES] of raw sample descriptions [n][SG_RAW]
+hipError_t sg_features(hipStream_t st, int64_t n, const double* raw, float* x);
 hipError_t sg_pca_project(hipStream_t st, int n, int P, int k, const float* D, int64_t ldd, const float* mean,
                           const int* mean_idx, int n_mean, const float* V, float* coef);
 }  // namespace soap

@@ -54,6 +54,7 @@ from . import (
     soap_ccf_rv,
     soap_quiet_spectrum,
     soap_surrogate_create,
+    soap_surrogate_features,
     soap_surrogate_predict,
     soap_surrogate_rv,
     soap_surrogate_train_step,
@@ -114,6 +115,13 @@ class Stars:
         self.ctxs.append(ctx)
         self.params.append((float(teff_k), float(incl_deg), float(vsini_kms)))
         self._lut = None
+        self._pa = None
+
+    def param_array(self):
+        """(T_eff, inclination, v sin i) per row, float64 [rows][3]."""
+        if getattr(self, "_pa", None) is None or len(self._pa) != len(self.params):
+            self._pa = np.asarray(self.params, np.float64).reshape(-1, 3)
+        return self._pa
 
     @property
     def ref(self):
@@ -159,6 +167,25 @@ def sample_features(stars, samples, idx=None):
     p = np.asarray(stars.params)[stars.rows(sample_stars(samples, i))]
     return features(samples.lat_deg[k], samples.lon_deg[k], samples.radius[k], samples.contrast[k],
                     samples.phases.reshape(-1)[i], p[:, 0], p[:, 1], p[:, 2])
+
+
+def sample_raw(stars, samples, idx=None, rows=None):
+    """Raw descriptions [n][8] (float64) of samples[idx] for
+    soap_surrogate_features: spot lat, lon, radius, contrast, phase and the
+    star's T_eff, inclination, v sin i (rows: the samples' star rows, if
+    already known)."""
+    i = np.arange(samples.n) if idx is None else np.asarray(idx)
+    k = i // samples.n_per
+    if rows is None:
+        rows = stars.rows(sample_stars(samples, i))
+    out = np.empty((len(i), 8), np.float64)
+    out[:, 0] = samples.lat_deg[k]
+    out[:, 1] = samples.lon_deg[k]
+    out[:, 2] = samples.radius[k]
+    out[:, 3] = samples.contrast[k]
+    out[:, 4] = samples.phases.reshape(-1)[i]
+    out[:, 5:8] = stars.param_array()[rows]
+    return out
 
 
 def _groups(keys):
@@ -441,11 +468,14 @@ class SurrogateModel:
                           bufs["fallback"], err_kms=bufs["err"], rv_out=bufs["rv"], base_index=rows_dev)
 
     def inputs(self, samples, idx):
-        """Device features and star rows of samples[idx]."""
+        """Device features (computed on the device from the samples' raw
+        descriptions) and star rows of samples[idx]."""
         torch = self.torch
-        x = torch.from_numpy(sample_features(self.stars, samples, idx)).cuda()
-        r = torch.from_numpy(self.stars.rows(sample_stars(samples, idx))).cuda()
-        return x, r
+        rows = self.stars.rows(sample_stars(samples, idx))
+        raw = torch.from_numpy(sample_raw(self.stars, samples, idx, rows)).cuda()
+        x = torch.empty((len(rows), N_FEATURES), dtype=torch.float32, device="cuda")
+        soap_surrogate_features(raw, x)
+        return x, torch.from_numpy(rows).cuda()
 
     def rv(self, samples, idx, bufs, threshold_kms=None, calib=None):
         """Gated RVs (km/s, host float64) of samples[idx]; idx sorted, its
@@ -512,7 +542,7 @@ def build(stars, mask, train, heldout, n_components=64, hidden=256, n_ensemble=4
         w = model.rv_weights(model.normalise(coef[sel]), rows[sel])
         model.reweight(w)
         info["rv_weights"] = [float(v) for v in w[:8]]
-    X = sample_features(stars, train)
+    X = model.inputs(train, np.arange(train.n))[0].cpu().numpy()
     Y = model.normalise(coef)
     t = time.perf_counter()
     losses = model.train(X, Y, epochs, batch=batch, seed=seed)

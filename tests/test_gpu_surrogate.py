@@ -457,19 +457,20 @@ def test_fused_surrogate_rv_matches_linear_fit_and_oracle_spread():
 def test_trained_surrogate_gain_over_full_synthesis():
     """What the trained network gains: on held-out samples of one star it
     replaces the full synthesis for most samples within 10 cm/s (the gate
-    calibrated to a 1% miss rate on a separate held-out set), and its kernels
-    deliver RVs faster than the full synthesis does."""
+    calibrated to a 1% miss rate on a separate held-out set), and both its
+    kernels and the gated path end to end (fallback samples through the full
+    synthesis included) deliver RVs faster than the full synthesis does."""
     import time
 
     from paper_2301_04259_amd import surrogate as S
 
-    star = W.make_cfg5(n_grid=150)
+    star = W.make_cfg5()
     stars = S.single_star(L.soap_grid_init(star))
-    train = W.cfg5_samples(2500, 8, seed=21)
-    held = W.cfg5_samples(256, 8, seed=22)
-    test = W.cfg5_samples(256, 8, seed=23)
-    model, info = S.build(stars, star.mask, train, held, n_components=64, hidden=128, n_ensemble=4, epochs=60,
-                          svd_subset=1024, alpha=1e-2)
+    train = W.cfg5_samples(8000, 8, seed=21)
+    held = W.cfg5_samples(800, 8, seed=22)
+    test = W.cfg5_samples(1024, 8, seed=23)
+    model, info = S.build(stars, star.mask, train, held, n_components=64, hidden=128, n_ensemble=4, epochs=40,
+                          svd_subset=2048, alpha=1e-2)
     n = (test.n // 16) * 16
     idx = np.arange(n)
     bufs = model.alloc(n)
@@ -490,11 +491,31 @@ def test_trained_surrogate_gain_over_full_synthesis():
 
     r_plain = rate(lambda: S.plain_rv(stars, test, star.mask, idx))
     r_sur = rate(lambda: model.surrogate_rv(x, r, bufs))
+    # the gated path end to end: features, prediction, fits and gate, the
+    # read-back, then the full synthesis, CCF and fit of the fallback samples
+    r_gated = rate(lambda: model.rv(test, idx, bufs))
     _say(f"trained surrogate: loss {info['final_loss']:.3g}, accepted {acc.mean():.3f}, accepted error rms "
          f"{np.sqrt(np.mean(e[acc] ** 2)):.3f} max {e[acc].max():.3f} cm/s, over 10 cm/s {np.mean(e[acc] >= 10):.4f}; "
-         f"full synthesis {r_plain:.3g} RV/s, surrogate kernels {r_sur:.3g} RV/s")
+         f"full synthesis {r_plain:.3g} RV/s, surrogate kernels {r_sur:.3g} RV/s, gated {r_gated:.3g} RV/s "
+         f"(x{r_gated / r_plain:.2f})")
     assert np.array_equal(rv[fb], rv_plain[fb])
     assert acc.mean() >= 0.5
     assert np.mean(e[acc] >= 10.0) <= 0.02
     assert r_sur > r_plain
+    assert r_gated > r_plain
     L.soap_destroy(stars.ref)
+
+
+def test_device_features_match_host_features():
+    from paper_2301_04259_amd import surrogate as S
+
+    rng = np.random.default_rng(3)
+    n = 1000
+    raw = np.column_stack([rng.uniform(-60, 60, n), rng.uniform(0, 360, n), rng.uniform(0.01, 0.1, n),
+                           rng.uniform(0.3, 0.9, n), rng.uniform(0, 1, n), rng.uniform(4500, 6500, n),
+                           rng.uniform(30, 90, n), rng.uniform(1, 5, n)])
+    want = S.features(*raw.T)
+    x = torch.empty((n, 12), dtype=torch.float32, device="cuda")
+    L.soap_surrogate_features(torch.from_numpy(raw).cuda(), x)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(x.cpu().numpy(), want, rtol=0, atol=2e-6)
