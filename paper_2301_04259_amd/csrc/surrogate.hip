@@ -38,52 +38,102 @@ __device__ __forceinline__ float silu_grad(float z) {
 // C[M][N] = op(A)[M][K] op(B)[K][N] for every ensemble member (grid z), BF16
 // in, FP32 accumulate.  op(A)(i, k) = TA ? A[k lda + i] : A[i lda + k];
 // op(B)(k, j) = TB ? B[j ldb + k] : B[k ldb + j].  M, N multiples of 16, K a
-// multiple of 32.  A 64-thread block computes one 16 x 16 tile: lane l holds
-// A(l % 16, 8 (l / 16) + e) and B(8 (l / 16) + e, l % 16), e < 8, and ends
-// with C(4 (l / 16) + r, l % 16), r < 4.
+// multiple of 32, lda and ldb multiples of 8 (16-byte rows of 8 elements).
+// A block of four waves computes a 64 x 64 tile of C, each wave a 32 x 32
+// quarter as 2 x 2 MFMA tiles of 16 x 16 (v_mfma_f32_16x16x32_bf16: lane l
+// holds A(l % 16, 8 (l / 16) + e) and B(8 (l / 16) + e, l % 16), e < 8, and
+// ends with C(4 (l / 16) + r, l % 16), r < 4).  Per K step of 32 the block
+// stages the 64 x 32 slices of op(A) and op(B)^T in LDS with 16-byte global
+// loads (one per thread and operand), so every lane reads its 8 operands as
+// one 16-byte LDS read; rows past M or N read a clamped row and are not
+// stored.  Each output adds its K steps in order, as one MFMA chain.
+constexpr int MM_T = 64;        // block tile
+constexpr int MM_LDK = 32 + 8;  // LDS row of 32 k values, padded against bank conflicts
+
 template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(64) k_mm_bf16(int M, int N, int K, const __bf16* __restrict__ A, int lda,
-                                                int64_t sA, const __bf16* __restrict__ B, int ldb, int64_t sB,
-                                                const float* __restrict__ bias, int64_t sBias, float* __restrict__ Cf,
-                                                int ldc, int64_t sC, __bf16* __restrict__ Cb, int64_t sCb,
-                                                const float* __restrict__ Z, int64_t sZ) {
-  const int l = threadIdx.x;
-  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+__global__ void __launch_bounds__(256) k_mm_bf16(int M, int N, int K, const __bf16* __restrict__ A, int lda,
+                                                 int64_t sA, const __bf16* __restrict__ B, int ldb, int64_t sB,
+                                                 const float* __restrict__ bias, int64_t sBias, float* __restrict__ Cf,
+                                                 int ldc, int64_t sC, __bf16* __restrict__ Cb, int64_t sCb,
+                                                 const float* __restrict__ Z, int64_t sZ) {
+  __shared__ __align__(16) __bf16 As[MM_T][MM_LDK];  // op(A) rows i, k contiguous
+  __shared__ __align__(16) __bf16 Bs[MM_T][MM_LDK];  // op(B) columns j, k contiguous
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const int i0 = blockIdx.y * MM_T, j0 = blockIdx.x * MM_T;
   const int e_ = blockIdx.z;
   A += e_ * sA;
   B += e_ * sB;
-  const int ia = i0 + (l & 15), jb = j0 + (l & 15), kq = 8 * (l >> 4);
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  // staging: thread t moves 8 elements of each operand per K step
+  //   k-contiguous source: row t / 4 of the tile, k = 8 (t % 4) .. + 8
+  //   row-contiguous source: k = t / 8, rows 8 (t % 8) .. + 8
+  const int r_kc = t >> 2, k_kc = 8 * (t & 3);
+  const int k_rc = t >> 3, r_rc = 8 * (t & 7);
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8 a, b;
+    if (k0) __syncthreads();  // every wave is done with the previous slices
+    if constexpr (!TA) {
+      const int i = min(i0 + r_kc, M - 1);
+      *reinterpret_cast<bf16x8*>(&As[r_kc][k_kc]) =
+          *reinterpret_cast<const bf16x8*>(A + (int64_t)i * lda + k0 + k_kc);
+    } else {
+      const int i = min(i0 + r_rc, M - 8);  // M is a multiple of 16, so the 8 rows stay in range
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(A + (int64_t)(k0 + k_rc) * lda + i);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + kq + e;
-      a[e] = TA ? A[(int64_t)k * lda + ia] : A[(int64_t)ia * lda + k];
-      b[e] = TB ? B[(int64_t)jb * ldb + k] : B[(int64_t)k * ldb + jb];
+      for (int e = 0; e < 8; ++e) As[i - i0 + e < MM_T ? i - i0 + e : MM_T - 1][k_rc] = v[e];
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-  }
-  const int j = j0 + (l & 15);
+    if constexpr (TB) {
+      const int j = min(j0 + r_kc, N - 1);
+      *reinterpret_cast<bf16x8*>(&Bs[r_kc][k_kc]) =
+          *reinterpret_cast<const bf16x8*>(B + (int64_t)j * ldb + k0 + k_kc);
+    } else {
+      const int j = min(j0 + r_rc, N - 8);
+      const bf16x8 v = *reinterpret_cast<const bf16x8*>(B + (int64_t)(k0 + k_rc) * ldb + j);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int i = i0 + 4 * (l >> 4) + r;
-    const int64_t o = (int64_t)i * ldc + j;
-    const float v = acc[r];
-    if constexpr (EPI == MM_HIDDEN) {  // z = v + b, keep z, emit SiLU(z) in BF16
-      const float z = v + bias[e_ * sBias + j];
-      Cf[e_ * sC + o] = z;
-      Cb[e_ * sCb + o] = (__bf16)silu(z);
-    } else if constexpr (EPI == MM_OUTPUT) {  // y = v + b
-      Cf[e_ * sC + o] = v + bias[e_ * sBias + j];
-    } else if constexpr (EPI == MM_DHIDDEN) {  // dz = v SiLU'(z), in FP32 and BF16
-      const float dz = v * silu_grad(Z[e_ * sZ + o]);
-      Cf[e_ * sC + o] = dz;
-      Cb[e_ * sCb + o] = (__bf16)dz;
-    } else {  // MM_PLAIN: weight gradient
-      Cf[e_ * sC + o] = v;
+      for (int e = 0; e < 8; ++e) Bs[j - j0 + e < MM_T ? j - j0 + e : MM_T - 1][k_rc] = v[e];
     }
+    __syncthreads();
+    bf16x8 av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * a + (l & 15)][8 * (l >> 4)]);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * b + (l & 15)][8 * (l >> 4)]);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0, 0);
   }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = j0 + wn + 16 * b + (l & 15);
+      if (j >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wm + 16 * a + 4 * (l >> 4) + r;
+        if (i >= M) continue;
+        const int64_t o = (int64_t)i * ldc + j;
+        const float v = acc[a][b][r];
+        if constexpr (EPI == MM_HIDDEN) {  // z = v + b, keep z, emit SiLU(z) in BF16
+          const float z = v + bias[e_ * sBias + j];
+          Cf[e_ * sC + o] = z;
+          Cb[e_ * sCb + o] = (__bf16)silu(z);
+        } else if constexpr (EPI == MM_OUTPUT) {  // y = v + b
+          Cf[e_ * sC + o] = v + bias[e_ * sBias + j];
+        } else if constexpr (EPI == MM_DHIDDEN) {  // dz = v SiLU'(z), in FP32 and BF16
+          const float dz = v * silu_grad(Z[e_ * sZ + o]);
+          Cf[e_ * sC + o] = dz;
+          Cb[e_ * sCb + o] = (__bf16)dz;
+        } else {  // MM_PLAIN: weight gradient
+          Cf[e_ * sC + o] = v;
+        }
+      }
+    }
 }
 
 // x[B][n_in] (FP32) -> X[B][K0] (BF16, zero padded)
@@ -315,8 +365,9 @@ template <bool TA, bool TB, int EPI>
 hipError_t mm(hipStream_t st, int E, int M, int N, int K, const __bf16* A, int lda, int64_t sA, const __bf16* B,
               int ldb, int64_t sB, const float* bias, int64_t sBias, float* Cf, int ldc, int64_t sC, __bf16* Cb,
               int64_t sCb, const float* Z, int64_t sZ) {
-  dim3 grid(N / 16, M / 16, E);
-  hipLaunchKernelGGL((k_mm_bf16<TA, TB, EPI>), grid, dim3(64), 0, st, M, N, K, A, lda, sA, B, ldb, sB, bias,
+  if (M % 16 || N % 16 || K % 32 || lda % 8 || ldb % 8) return hipErrorInvalidValue;
+  dim3 grid((N + MM_T - 1) / MM_T, (M + MM_T - 1) / MM_T, E);
+  hipLaunchKernelGGL((k_mm_bf16<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, sA, B, ldb, sB, bias,
                      sBias, Cf, ldc, sC, Cb, sCb, Z, sZ);
   return hipGetLastError();
 }
