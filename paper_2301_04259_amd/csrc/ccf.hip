@@ -732,7 +732,19 @@ __global__ void __launch_bounds__(256) k_ccf_linear(int64_t n, int k, int n_v, c
 
 constexpr int SG_MAX_ENS = 16;
 
-// Surrogate RVs and their gate, one wave per sample (64-thread blocks):
+// samples per wave of k_sg_rv (they share every basis row it loads) and
+// basis rows in flight, by CCF points per lane
+template <int NPT>
+constexpr int sg_samples() {
+  return NPT <= 3 ? 4 : (NPT <= 6 ? 2 : 1);
+}
+template <int NPT>
+constexpr int sg_rows_in_flight() {
+  return NPT <= 3 ? 8 : (NPT <= 6 ? 4 : 2);
+}
+
+// Surrogate RVs and their gate, SS = sg_samples consecutive samples per wave
+// (64-thread blocks), each basis row loaded once for all of them:
 //   1. CCF of the ensemble-mean prediction by linearity, base (the sample's
 //      row base[base_idx[i]] when base_idx is given) + sum_k
 //      coef[i][k] basis[k] (double, increasing k: the same sums as
@@ -744,7 +756,9 @@ constexpr int SG_MAX_ENS = 16;
 //      dRV_e = sum_k h_k (y_e,k - coef_k) with h = basis g;
 //   3. err = calib x sample standard deviation of dRV_e over the members;
 //      fallback when err is not below thr or the fit did not converge.
-template <int NPT>
+// Every sum of one sample has the order it would have alone.  EB bounds the
+// member count (registers for the members' RV changes).
+template <int NPT, int EB>
 __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, double v0, double dv,
                                               const float* __restrict__ coef, const float* __restrict__ members,
                                               const double* __restrict__ base, const int* __restrict__ base_idx,
@@ -752,36 +766,39 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
                                               double thr, soap_rv* __restrict__ out,
                                               double* __restrict__ rv_kms, double* __restrict__ err_kms,
                                               int* __restrict__ fallback) {
-  __shared__ double s_c[64];
-  __shared__ double s_g[NPT * 64];
-  const int64_t i = blockIdx.x;
+  constexpr int SS = sg_samples<NPT>();
+  constexpr int JU = sg_rows_in_flight<NPT>();
+  __shared__ double s_c[SS][64];
+  __shared__ double s_g[SS][NPT * 64];
   const int lane = threadIdx.x;
-  const int brow = base_idx ? base_idx[i] : 0;
-  if (brow < 0 || brow >= n_base) {  // no such star: no surrogate RV
-    if (lane == 0) {
-      soap_rv bad{};
-      bad.status = 2;
-      if (out) out[i] = bad;
-      rv_kms[i] = 0.0;
-      if (err_kms) err_kms[i] = INFINITY;
-      fallback[i] = 1;
-    }
-    return;
-  }
+  const int64_t i0 = (int64_t)blockIdx.x * SS;
   // Loads are unconditional, with indices clamped into the rows (the lanes
-  // past the grid compute values that are never used): a load under a
-  // branch is waited for before the next one is issued.
-  const double* bs = base + (int64_t)brow * n_v;
+  // past the grid, and the samples past n, compute values that are never
+  // used): a load under a branch is waited for before the next one is
+  // issued.  A sample whose star row does not exist reads row 0 and is
+  // reported without a surrogate RV.
+  int64_t ii[SS];
+  bool row_ok[SS];
+  const double* bs[SS];
+#pragma unroll
+  for (int s = 0; s < SS; ++s) {
+    ii[s] = min(i0 + s, n - 1);
+    const int brow = base_idx ? base_idx[ii[s]] : 0;
+    row_ok[s] = brow >= 0 && brow < n_base;
+    bs[s] = base + (int64_t)(row_ok[s] ? brow : 0) * n_v;
+  }
   int vc[NPT];
 #pragma unroll
   for (int t = 0; t < NPT; ++t) vc[t] = min(lane + 64 * t, n_v - 1);
-  double y[NPT];
+  double y[SS][NPT];
 #pragma unroll
-  for (int t = 0; t < NPT; ++t) y[t] = bs[vc[t]];
-  constexpr int JU = 8;  // basis rows in flight
+  for (int s = 0; s < SS; ++s)
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) y[s][t] = bs[s][vc[t]];
   for (int k0 = 0; k0 < k; k0 += 64) {
     __syncthreads();
-    s_c[lane] = k0 + lane < k ? (double)coef[i * k + min(k0 + lane, k - 1)] : 0.0;
+#pragma unroll
+    for (int s = 0; s < SS; ++s) s_c[s][lane] = k0 + lane < k ? (double)coef[ii[s] * k + min(k0 + lane, k - 1)] : 0.0;
     __syncthreads();
     const int kn = min(64, k - k0);
     for (int j0 = 0; j0 < kn; j0 += JU) {
@@ -793,108 +810,162 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
         for (int t = 0; t < NPT; ++t) b[u][t] = bj[vc[t]];
       }
 #pragma unroll
-      for (int u = 0; u < JU; ++u) {
-        const double cj = j0 + u < kn ? s_c[j0 + u] : 0.0;  // rows past kn add zero
+      for (int u = 0; u < JU; ++u)
 #pragma unroll
-        for (int t = 0; t < NPT; ++t) y[t] = fma(cj, b[u][t], y[t]);
+        for (int s = 0; s < SS; ++s) {
+          const double cj = j0 + u < kn ? s_c[s][j0 + u] : 0.0;  // rows past kn add zero
+#pragma unroll
+          for (int t = 0; t < NPT; ++t) y[s][t] = fma(cj, b[u][t], y[s][t]);
+        }
+    }
+  }
+  bool bad[SS];
+#pragma unroll
+  for (int s = 0; s < SS; ++s) {
+    double p[4], S[20];
+    soap_rv res = fit_wave(y[s], n_v, v0, dv, p, S);
+    bad[s] = res.status != 0 || !row_ok[s];
+    if (lane == 0 && i0 + s < n) {  // the fit's record and RV now; the gate after the spreads
+      if (!row_ok[s]) {
+        res = soap_rv{};
+        res.status = 2;
+      }
+      if (out) out[i0 + s] = res;
+      rv_kms[i0 + s] = row_ok[s] ? res.rv_kms : 0.0;
+    }
+    // g = J H^-1 e_mu at the fit (full Hessian; J^T J where that is not
+    // positive definite); zero for a sample that has none
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!bad[s]) {
+      double Sz[20];
+#pragma unroll
+      for (int q = 0; q < 20; ++q) Sz[q] = S[q];
+      Sz[1] = 0.0;
+      Sz[2] = 0.0;
+      Sz[3] = -1.0;  // gf_solve solves A x = -S[1..4]
+      Sz[4] = 0.0;
+      if (!(gf_solve(Sz, true, 0.0, z) || gf_solve(Sz, false, 0.0, z))) bad[s] = true;
+    }
+    const double is = 1.0 / p[3];
+    const double is2 = is * is;
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+      const int v = lane + 64 * t;
+      if (v < n_v) {
+        const double d = v0 + dv * v - p[2];
+        const double zz = d * d * is2;
+        const double e = exp(-0.5 * zz);
+        const double ae = p[1] * e;
+        s_g[s][v] = bad[s] ? 0.0 : z[0] - e * z[1] - ae * d * is2 * z[2] - ae * zz * is * z[3];
       }
     }
   }
-  double p[4], S[20];
-  soap_rv res = fit_wave(y, n_v, v0, dv, p, S);
-  bool bad = res.status != 0;
-  double err = 0.0;
-  if (!bad) {
-    // z = H^-1 e_mu (full Hessian; J^T J where that is not positive definite)
-    double Sz[20];
+  __syncthreads();
+  // h_k = sum_v basis[k][v] g_v, then dRV_e = sum_k h_k (y_e,k - coef_k)
+  double dr[SS][EB];
 #pragma unroll
-    for (int q = 0; q < 20; ++q) Sz[q] = S[q];
-    Sz[1] = 0.0;
-    Sz[2] = 0.0;
-    Sz[3] = -1.0;  // gf_solve solves A x = -S[1..4]
-    Sz[4] = 0.0;
-    double z[4];
-    bool ok = gf_solve(Sz, true, 0.0, z) || gf_solve(Sz, false, 0.0, z);
-    if (!ok) {
-      bad = true;
-    } else {
-      const double is = 1.0 / p[3];
-      const double is2 = is * is;
+  for (int s = 0; s < SS; ++s)
 #pragma unroll
-      for (int t = 0; t < NPT; ++t) {
-        const int v = lane + 64 * t;
-        if (v < n_v) {
-          const double d = v0 + dv * v - p[2];
-          const double zz = d * d * is2;
-          const double e = exp(-0.5 * zz);
-          const double ae = p[1] * e;
-          s_g[v] = z[0] - e * z[1] - ae * d * is2 * z[2] - ae * zz * is * z[3];
+    for (int e = 0; e < EB; ++e) dr[s][e] = 0.0;
+  for (int k0 = 0; k0 < k; k0 += 64) {
+    const int kk = k0 + lane;
+    const int kc = min(kk, k - 1);
+    const double* bk = basis + (int64_t)kc * n_v;
+    // four partial sums over v per sample (16 samples of the row in flight),
+    // added in a fixed order
+    double h4[SS][4];
+#pragma unroll
+    for (int s = 0; s < SS; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h4[s][q] = 0.0;
+    int v = 0;
+    for (; v + 16 <= n_v; v += 16) {
+      double bv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) bv[u] = bk[v + u];
+#pragma unroll
+      for (int s = 0; s < SS; ++s)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) h4[s][u & 3] = fma(bv[u], s_g[s][v + u], h4[s][u & 3]);
+    }
+    for (; v < n_v; ++v) {
+      const double bvv = bk[v];
+#pragma unroll
+      for (int s = 0; s < SS; ++s) h4[s][0] = fma(bvv, s_g[s][v], h4[s][0]);
+    }
+#pragma unroll
+    for (int s = 0; s < SS; ++s) {
+      const double h = kk < k ? (h4[s][0] + h4[s][1]) + (h4[s][2] + h4[s][3]) : 0.0;
+      const double cm = (double)coef[ii[s] * k + kc];
+#pragma unroll
+      for (int e = 0; e < EB; ++e) {
+        if (e < E) {
+          const double ye = (double)members[((int64_t)e * n + ii[s]) * k + kc];
+          dr[s][e] += h * (ye - cm);
         }
       }
-      __syncthreads();
-      // h_k = sum_v basis[k][v] g_v, then dRV_e = sum_k h_k (y_e,k - coef_k)
-      double dr[SG_MAX_ENS];
+    }
+  }
 #pragma unroll
-      for (int e = 0; e < SG_MAX_ENS; ++e) dr[e] = 0.0;
-      for (int k0 = 0; k0 < k; k0 += 64) {
-        const int kk = k0 + lane;
-        const int kc = min(kk, k - 1);
-        const double* bk = basis + (int64_t)kc * n_v;
-        // four partial sums over v (16 samples in flight), added in a fixed order
-        double h4[4] = {0.0, 0.0, 0.0, 0.0};
-        int v = 0;
-        for (; v + 16 <= n_v; v += 16) {
-          double bv[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) bv[u] = bk[v + u];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) h4[u & 3] = fma(bv[u], s_g[v + u], h4[u & 3]);
-        }
-        for (; v < n_v; ++v) h4[0] = fma(bk[v], s_g[v], h4[0]);
-        const double h = kk < k ? (h4[0] + h4[1]) + (h4[2] + h4[3]) : 0.0;
-        const double cm = (double)coef[i * k + kc];
-#pragma unroll
-        for (int e = 0; e < SG_MAX_ENS; ++e) {
-          if (e < E) {
-            const double ye = (double)members[((int64_t)e * n + i) * k + kc];
-            dr[e] += h * (ye - cm);
-          }
-        }
-      }
+  for (int s = 0; s < SS; ++s) {
+    double err = 0.0;
+    if (!bad[s]) {
       double m = 0.0;
 #pragma unroll
-      for (int e = 0; e < SG_MAX_ENS; ++e) {
+      for (int e = 0; e < EB; ++e) {
         if (e < E) {  // uniform
-          dr[e] = wave_sum_f64(dr[e]);
-          m += dr[e];
+          dr[s][e] = wave_sum_f64(dr[s][e]);
+          m += dr[s][e];
         }
       }
       m /= (double)E;
       double var = 0.0;
 #pragma unroll
-      for (int e = 0; e < SG_MAX_ENS; ++e)
-        if (e < E) var += (dr[e] - m) * (dr[e] - m);
+      for (int e = 0; e < EB; ++e)
+        if (e < E) var += (dr[s][e] - m) * (dr[s][e] - m);
       err = calib * sqrt(var / (double)(E - 1));
     }
-  }
-  if (lane == 0) {
-    if (out) out[i] = res;
-    rv_kms[i] = res.rv_kms;
-    if (err_kms) err_kms[i] = bad ? INFINITY : err;
-    fallback[i] = (bad || !(err < thr)) ? 1 : 0;
+    if (lane == 0 && i0 + s < n) {
+      if (err_kms) err_kms[i0 + s] = bad[s] ? INFINITY : err;
+      fallback[i0 + s] = (bad[s] || !(err < thr)) ? 1 : 0;
+    }
   }
 }
+
+namespace {
+
+template <int NPT>
+void launch_sg_rv_n(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
+                    const double* d_base, const int* d_base_idx, int n_base, const double* d_basis, double calib,
+                    double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err, int* d_fallback) {
+  const dim3 grid((unsigned)((n + sg_samples<NPT>() - 1) / sg_samples<NPT>())), block(64);
+  const int nb = d_base_idx ? n_base : 1;
+  if (E <= 4)
+    hipLaunchKernelGGL((k_sg_rv<NPT, 4>), grid, block, 0, c->stream, n, k, E, c->mask_nv, c->mask_v0, c->mask_dv,
+                       d_coef, d_members, d_base, d_base_idx, nb, d_basis, calib, thr, d_rv, d_rv_kms, d_err,
+                       d_fallback);
+  else if (E <= 8)
+    hipLaunchKernelGGL((k_sg_rv<NPT, 8>), grid, block, 0, c->stream, n, k, E, c->mask_nv, c->mask_v0, c->mask_dv,
+                       d_coef, d_members, d_base, d_base_idx, nb, d_basis, calib, thr, d_rv, d_rv_kms, d_err,
+                       d_fallback);
+  else
+    hipLaunchKernelGGL((k_sg_rv<NPT, SG_MAX_ENS>), grid, block, 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,
+                       c->mask_dv, d_coef, d_members, d_base, d_base_idx, nb, d_basis, calib, thr, d_rv, d_rv_kms,
+                       d_err, d_fallback);
+}
+
+}  // namespace
 
 hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
                         const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
                         double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
                         int* d_fallback) {
+  if (E < 2 || E > SG_MAX_ENS) return hipErrorInvalidValue;
   const int npt = (c->mask_nv + 63) / 64;
 #define SG_CASE(N)                                                                                              \
   case N:                                                                                                       \
-    hipLaunchKernelGGL(k_sg_rv<N>, dim3((unsigned)n), dim3(64), 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,  \
-                       c->mask_dv, d_coef, d_members, d_base, d_base_idx, d_base_idx ? n_base : 1, d_basis,     \
-                       calib, thr, d_rv, d_rv_kms, d_err, d_fallback);                                          \
+    launch_sg_rv_n<N>(c, d_coef, d_members, n, E, k, d_base, d_base_idx, n_base, d_basis, calib, thr, d_rv,     \
+                      d_rv_kms, d_err, d_fallback);                                                             \
     break;
   switch (npt) {
     SG_CASE(1) SG_CASE(2) SG_CASE(3) SG_CASE(4) SG_CASE(5) SG_CASE(6)
