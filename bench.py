@@ -75,7 +75,7 @@ def cpu_baseline(star, n_sample):
     }
 
 
-def batch_leg(args, L, W, np, torch):
+def batch_leg(args, L, W, np, torch, mask=None):
     """Ragged configurations over many stars (grid 100-400, 8k-206k pixel
     windows of the full range, 25-200 phases, T_eff 4500-6500 K, 1-4
     regions) replayed as one HIP graph; spectra per second of the whole
@@ -139,6 +139,23 @@ def batch_leg(args, L, W, np, torch):
     torch.cuda.synchronize()
     wall = (time.perf_counter() - w0) / args.batch_runs
     ms = max(e0.elapsed_time(e1) / args.batch_runs, wall * 1e3)
+    # the same batch with every configuration's CCF and Gaussian fit in the
+    # graph (the headline's 4000-line mask over each configuration's window)
+    rv_ms = None
+    if mask is not None:
+        L.soap_batch_destroy(b)
+        rvb = [torch.zeros(len(p) * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda") for p in phs]
+        b = L.soap_batch_create(ctxs, regs, phs, W.EFFECT_TOT, outs, mask=mask, rv_outs=rvb)
+        L.soap_batch_run(b)
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.batch_runs):
+            L.soap_batch_run(b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rv_ms = max(e0.elapsed_time(e1) / args.batch_runs, (time.perf_counter() - w0) / args.batch_runs * 1e3)
+        say(f"graph with CCF + fit: {rv_ms:.2f} ms per run")
     # the same configurations as one soap_active_spectra call each
     for c, r, p, o in zip(ctxs, regs, phs, outs):
         L.soap_active_spectra(c, r, p, W.EFFECT_TOT, o)
@@ -174,6 +191,8 @@ def batch_leg(args, L, W, np, torch):
         "per_call_loop_ms": loop_ms,
         "graph_speedup_vs_calls": loop_ms / ms,
         "create_s": create_s,
+        "ms_per_run_with_ccf_fit": rv_ms,
+        "spectra_per_s_with_ccf_fit": None if rv_ms is None else n_spec / (rv_ms * 1e-3),
         "roofline": {"bound": "hbm", "scope": "whole graph run (tables and shift-and-sum)",
                      "algorithmic_bytes": alg, "achieved": alg / (ms * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
                      "frac": alg / (ms * 1e-3) / 8e12},
@@ -542,7 +561,7 @@ def main():
     bat = None
     if args.batch_configs > 0:
         print("[bench] batched leg", file=sys.stderr, flush=True)
-        bat = batch_leg(args, L, W, np, torch)
+        bat = batch_leg(args, L, W, np, torch, mask=star.mask)
 
     sur = sur1 = None
     if args.surrogate_spots > 0:

@@ -427,6 +427,18 @@ typedef struct soap_batch soap_batch;
 soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
                               const int32_t* region_offsets, const double* phases, const int32_t* phase_offsets,
                               int32_t effect, void* const* flux, void* hip_stream, soap_batch** out);
+/* The same batch with the CCF and Gaussian fit of every configuration's
+ * spectra added to the graph (section 4.1): mask as for soap_ccf_rv (it is
+ * set on every context, and the batch keeps its own copy of each context's
+ * mask tables); ccf (may be NULL, or hold NULLs) device arrays
+ * [phases of i][n_v] double; rv (may be NULL, or hold NULLs) device arrays of
+ * soap_rv per phase.  The CCF and fit of configuration i read flux[i] after
+ * its shift-and-sum; every row equals soap_ccf_rv on that flux, bit for
+ * bit.  Mask errors are those of soap_ccf_rv.                                */
+soap_status soap_batch_create_rv(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                                 const int32_t* region_offsets, const double* phases, const int32_t* phase_offsets,
+                                 int32_t effect, void* const* flux, const soap_mask* mask, double* const* ccf,
+                                 soap_rv* const* rv, void* hip_stream, soap_batch** out);
 soap_status soap_batch_run(soap_batch* batch);
 int64_t soap_batch_n_spectra(const soap_batch* batch);
 const char* soap_batch_last_error(const soap_batch* batch);

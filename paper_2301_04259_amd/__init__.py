@@ -75,6 +75,7 @@ SYMBOLS = (
     "soap_set_apply_shape",
     "soap_autotune",
     "soap_batch_create",
+    "soap_batch_create_rv",
     "soap_batch_run",
     "soap_batch_n_spectra",
     "soap_batch_last_error",
@@ -239,6 +240,10 @@ _lib.soap_autotune.restype = C.c_int
 _lib.soap_batch_create.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                    C.c_void_p, C.c_void_p, C.POINTER(C.c_void_p)]
 _lib.soap_batch_create.restype = C.c_int
+_lib.soap_batch_create_rv.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_int32, C.c_void_p, C.POINTER(MaskC), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_void_p)]
+_lib.soap_batch_create_rv.restype = C.c_int
 _lib.soap_batch_run.argtypes = [C.c_void_p]
 _lib.soap_batch_run.restype = C.c_int
 _lib.soap_batch_n_spectra.argtypes = [C.c_void_p]
@@ -830,8 +835,12 @@ class Batch:
             self.handle = None
 
 
-def soap_batch_create(ctxs, cfg_regions, cfg_phases, effect, outs, stream=None):
-    """One configuration per (ctx, region list, phases, output tensor)."""
+def soap_batch_create(ctxs, cfg_regions, cfg_phases, effect, outs, stream=None, mask=None, ccf_outs=None,
+                      rv_outs=None):
+    """One configuration per (ctx, region list, phases, output tensor).
+    With mask, each run also computes every configuration's CCF (ccf_outs:
+    device [phases][n_v] float64 tensors, or None) and Gaussian-fit RVs
+    (rv_outs: device RV_DTYPE buffers, or None)."""
     n = len(ctxs)
     handles = (C.c_void_p * n)(*[C.cast(c.handle, C.c_void_p) for c in ctxs])
     regs = [r for rl in cfg_regions for r in rl]
@@ -845,11 +854,25 @@ def soap_batch_create(ctxs, cfg_regions, cfg_phases, effect, outs, stream=None):
     poff[1:] = np.cumsum([np.asarray(p).size for p in cfg_phases])
     fl = (C.c_void_p * n)(*[_dptr(o, "flux") for o in outs])
     h = C.c_void_p()
-    st = _lib.soap_batch_create(handles, n, arr.ctypes.data, roff.ctypes.data, ph.ctypes.data, poff.ctypes.data,
-                                int(effect), fl, _stream_handle(stream), C.byref(h))
+    if mask is None:
+        st = _lib.soap_batch_create(handles, n, arr.ctypes.data, roff.ctypes.data, ph.ctypes.data, poff.ctypes.data,
+                                    int(effect), fl, _stream_handle(stream), C.byref(h))
+        keep = []
+    else:
+        m, mkeep = _mask(mask)
+        cc = (C.c_void_p * n)(*[None if ccf_outs is None or ccf_outs[i] is None else _dptr(ccf_outs[i], "ccf")
+                                for i in range(n)])
+        rr = (C.c_void_p * n)(*[None if rv_outs is None or rv_outs[i] is None else _dptr(rv_outs[i], "rv")
+                                for i in range(n)])
+        st = _lib.soap_batch_create_rv(handles, n, arr.ctypes.data, roff.ctypes.data, ph.ctypes.data,
+                                       poff.ctypes.data, int(effect), fl, C.byref(m), cc, rr, _stream_handle(stream),
+                                       C.byref(h))
+        keep = [mkeep, ccf_outs, rv_outs]
     if st != SOAP_OK:
         raise SoapError(st, _lib.soap_batch_last_error(None).decode())
-    return Batch(h, list(ctxs), list(outs))
+    b = Batch(h, list(ctxs), list(outs))
+    b._keep = keep
+    return b
 
 
 def soap_batch_run(batch):

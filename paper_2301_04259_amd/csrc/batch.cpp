@@ -41,6 +41,7 @@ struct soap_batch {
   hipStream_t origin = nullptr;                // capture origin (owned)
   hipStream_t branch[kBranches] = {};          // owned
   hipEvent_t fork = nullptr, join[kBranches] = {};
+  hipEvent_t fork2 = nullptr, join2[kBranches] = {};  // around the CCF stage
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* arena = nullptr;
@@ -56,10 +57,12 @@ void destroy_batch(soap_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (int i = 0; i < kBranches; ++i) {
+    if (b->join2[i]) (void)hipEventDestroy(b->join2[i]);
     if (b->join[i]) (void)hipEventDestroy(b->join[i]);
     if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
   }
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->fork2) (void)hipEventDestroy(b->fork2);
   if (b->origin) (void)hipStreamDestroy(b->origin);
   if (b->arena) (void)soap::dev_free(b->arena);
   delete b;
@@ -71,10 +74,10 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 static thread_local std::string g_batch_err;
 
-SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
-                                       const int32_t* region_offsets, const double* phases,
-                                       const int32_t* phase_offsets, int32_t effect, void* const* flux,
-                                       void* hip_stream, soap_batch** out) {
+static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                               const int32_t* region_offsets, const double* phases, const int32_t* phase_offsets,
+                               int32_t effect, void* const* flux, const soap_mask* mask, double* const* ccf,
+                               soap_rv* const* rv, void* hip_stream, soap_batch** out) {
   auto bad = [](const std::string& m, soap_status st = SOAP_ERR_ARG) {
     g_batch_err = m;
     return st;
@@ -206,6 +209,36 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
                                      soap::WeightsOut{}, hregs[i].data(), phases + phase_offsets[i]});
   const size_t table_off = arena;
   if (!listed.empty()) arena += al(soap::table_batch_bytes(tc.data(), (int)tc.size()));
+  // CCF + fit stage: each distinct context's mask tables are copied into the
+  // arena (the batch must not depend on a later mask of the context), and
+  // every configuration gets its line-block partials (and CCF rows when the
+  // caller gives none)
+  std::vector<soap_ctx*> uctx;           // distinct contexts
+  std::vector<size_t> tab_off;           // their table copies
+  std::vector<int> ucfg(n_cfg, -1);      // configuration -> distinct context
+  std::vector<size_t> part_off(n_cfg, 0), ccf_off(n_cfg, 0);
+  if (mask) {
+    for (int i = 0; i < n_cfg; ++i) {
+      soap_ctx* c = cp[i].c;
+      size_t u = 0;
+      while (u < uctx.size() && uctx[u] != c) ++u;
+      if (u == uctx.size()) {
+        const soap_status ms = soap::ctx_set_mask(c, mask);
+        if (ms != SOAP_OK) return bad("configuration " + std::to_string(i) + ": " + c->err, ms);
+        uctx.push_back(c);
+        tab_off.push_back(arena);
+        arena += al(c->mask_blob_bytes);
+      }
+      ucfg[i] = (int)u;
+      const size_t nlb = (size_t)soap::ccf_line_blocks((int)mask->n_lines);
+      part_off[i] = arena;
+      arena += al(c->esize * nlb * (size_t)cp[i].pl.n_ph * c->mask_nv);
+      if (!ccf || !ccf[i]) {
+        ccf_off[i] = arena;
+        arena += al(sizeof(double) * (size_t)cp[i].pl.n_ph * c->mask_nv);
+      }
+    }
+  }
 
   soap_batch* b = new soap_batch;
   b->n_cfg = n_cfg;
@@ -233,6 +266,13 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
                          hipMemcpyHostToDevice)) != hipSuccess)
         return fail("hipMemcpy", e);
     }
+  }
+  std::vector<soap::CcfPlan> cplan(uctx.size());
+  for (size_t u = 0; u < uctx.size(); ++u) {
+    soap_ctx* c = uctx[u];
+    if ((e = hipMemcpy(A + tab_off[u], c->ws_mask.ptr, c->mask_blob_bytes, hipMemcpyDeviceToDevice)) != hipSuccess)
+      return fail("copying the mask tables", e);
+    cplan[u] = soap::ccf_plan(c, (int)mask->n_lines, A + tab_off[u]);
   }
   std::vector<soap::ApplyBatchGroup> ag(n_groups);
   for (int g = 0; g < n_groups; ++g) {
@@ -273,6 +313,11 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     if ((e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming)) != hipSuccess) return fail("event", e);
   }
   if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) return fail("event", e);
+  if (mask) {
+    if ((e = hipEventCreateWithFlags(&b->fork2, hipEventDisableTiming)) != hipSuccess) return fail("event", e);
+    for (int k = 0; k < kBranches; ++k)
+      if ((e = hipEventCreateWithFlags(&b->join2[k], hipEventDisableTiming)) != hipSuccess) return fail("event", e);
+  }
   // the contexts' own work must be finished before their tables are read
   for (int i = 0; i < n_cfg; ++i) {
     if ((e = hipStreamSynchronize(cp[i].c->stream)) != hipSuccess) return fail("context stream", e);
@@ -296,6 +341,22 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join[k], 0);
   }
   for (int g = 0; g < n_groups && ce == hipSuccess; ++g) ce = soap::apply_batch_launch(ag[g], b->origin);
+  if (mask && ce == hipSuccess) {
+    // CCF and fit of every configuration's spectra, spread over the branches
+    ce = hipEventRecord(b->fork2, b->origin);
+    for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork2, 0);
+    for (int i = 0; i < n_cfg && ce == hipSuccess; ++i) {
+      hipStream_t st = b->branch[i % kBranches];
+      const soap::CcfPlan& q = cplan[ucfg[i]];
+      double* dccf = (ccf && ccf[i]) ? ccf[i] : reinterpret_cast<double*>(A + ccf_off[i]);
+      ce = soap::launch_ccf_p(q, st, cp[i].flux, cp[i].pl.n_ph, A + part_off[i]);
+      if (ce == hipSuccess) ce = soap::launch_ccf_fit_p(q, st, A + part_off[i], cp[i].pl.n_ph, dccf, rv ? rv[i] : nullptr);
+    }
+    for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
+      ce = hipEventRecord(b->join2[k], b->branch[k]);
+      if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join2[k], 0);
+    }
+  }
   e = hipStreamEndCapture(b->origin, &b->graph);
   if (ce != hipSuccess) return fail("capturing the batch", ce);
   if (e != hipSuccess) return fail("hipStreamEndCapture", e);
@@ -303,6 +364,28 @@ SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, con
     return fail("hipGraphInstantiate", e);
   *out = b;
   return SOAP_OK;
+}
+
+SOAP_API soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                                       const int32_t* region_offsets, const double* phases,
+                                       const int32_t* phase_offsets, int32_t effect, void* const* flux,
+                                       void* hip_stream, soap_batch** out) {
+  return create_impl(ctxs, n_cfg, regions, region_offsets, phases, phase_offsets, effect, flux, nullptr, nullptr,
+                     nullptr, hip_stream, out);
+}
+
+SOAP_API soap_status soap_batch_create_rv(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                                          const int32_t* region_offsets, const double* phases,
+                                          const int32_t* phase_offsets, int32_t effect, void* const* flux,
+                                          const soap_mask* mask, double* const* ccf, soap_rv* const* rv,
+                                          void* hip_stream, soap_batch** out) {
+  if (!mask) {
+    if (out) *out = nullptr;
+    g_batch_err = "mask is NULL";
+    return SOAP_ERR_ARG;
+  }
+  return create_impl(ctxs, n_cfg, regions, region_offsets, phases, phase_offsets, effect, flux, mask, ccf, rv,
+                     hip_stream, out);
 }
 
 SOAP_API soap_status soap_batch_run(soap_batch* b) {

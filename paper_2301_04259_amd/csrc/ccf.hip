@@ -641,56 +641,80 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
 }
 
 template <typename T, int A, int NPX, int STG>
-static void launch_ccf_a(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
-  const unsigned char* base = static_cast<const unsigned char*>(c->ws_mask.ptr);
-  hipLaunchKernelGGL((k_ccf<T, A, NPX, STG>), grid, dim3(CCF_THREADS), 0, c->stream, (int)c->P, n_spec,
+static void launch_ccf_a(const CcfPlan& q, hipStream_t st, dim3 grid, const void* d_flux, int64_t n_spec,
+                         void* d_part) {
+  const unsigned char* base = q.tables;
+  hipLaunchKernelGGL((k_ccf<T, A, NPX, STG>), grid, dim3(CCF_THREADS), 0, st, (int)q.P, n_spec,
                      static_cast<const T*>(d_flux), reinterpret_cast<const double2*>(base),
-                     reinterpret_cast<const double2*>(base + c->ccf_off_edges),
-                     reinterpret_cast<const int4*>(base + c->ccf_off_batch),
-                     reinterpret_cast<const int*>(base + c->ccf_off_bfirst), c->mask_nv, static_cast<T*>(d_part));
+                     reinterpret_cast<const double2*>(base + q.off_edges),
+                     reinterpret_cast<const int4*>(base + q.off_batch),
+                     reinterpret_cast<const int*>(base + q.off_bfirst), q.nv, static_cast<T*>(d_part));
 }
 
 template <typename T, int NPX, int STG>
-static void launch_ccf_n(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
-  const int nv = c->mask_nv;
-  if (nv <= CCF_THREADS) launch_ccf_a<T, 1, NPX, STG>(c, grid, d_flux, n_spec, d_part);
-  else if (nv <= 2 * CCF_THREADS) launch_ccf_a<T, 2, NPX, STG>(c, grid, d_flux, n_spec, d_part);
-  else launch_ccf_a<T, 4, NPX, STG>(c, grid, d_flux, n_spec, d_part);
+static void launch_ccf_n(const CcfPlan& q, hipStream_t st, dim3 grid, const void* d_flux, int64_t n_spec,
+                         void* d_part) {
+  if (q.nv <= CCF_THREADS) launch_ccf_a<T, 1, NPX, STG>(q, st, grid, d_flux, n_spec, d_part);
+  else if (q.nv <= 2 * CCF_THREADS) launch_ccf_a<T, 2, NPX, STG>(q, st, grid, d_flux, n_spec, d_part);
+  else launch_ccf_a<T, 4, NPX, STG>(q, st, grid, d_flux, n_spec, d_part);
 }
 
 template <typename T, int STG>
-static void launch_ccf_s(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
-  switch (c->ccf_npx) {
-    case 2: launch_ccf_n<T, 2, STG>(c, grid, d_flux, n_spec, d_part); break;
-    case 3: launch_ccf_n<T, 3, STG>(c, grid, d_flux, n_spec, d_part); break;
-    case 5: launch_ccf_n<T, 5, STG>(c, grid, d_flux, n_spec, d_part); break;
-    default: launch_ccf_n<T, 10, STG>(c, grid, d_flux, n_spec, d_part); break;
+static void launch_ccf_s(const CcfPlan& q, hipStream_t st, dim3 grid, const void* d_flux, int64_t n_spec,
+                         void* d_part) {
+  switch (q.npx) {
+    case 2: launch_ccf_n<T, 2, STG>(q, st, grid, d_flux, n_spec, d_part); break;
+    case 3: launch_ccf_n<T, 3, STG>(q, st, grid, d_flux, n_spec, d_part); break;
+    case 5: launch_ccf_n<T, 5, STG>(q, st, grid, d_flux, n_spec, d_part); break;
+    default: launch_ccf_n<T, 10, STG>(q, st, grid, d_flux, n_spec, d_part); break;
   }
 }
 
 template <typename T>
-static void launch_ccf_t(soap_ctx* c, dim3 grid, const void* d_flux, int64_t n_spec, void* d_part) {
-  if (c->ccf_stg <= 256) launch_ccf_s<T, 256>(c, grid, d_flux, n_spec, d_part);
-  else launch_ccf_s<T, CCF_STG_MAX>(c, grid, d_flux, n_spec, d_part);
+static void launch_ccf_t(const CcfPlan& q, hipStream_t st, dim3 grid, const void* d_flux, int64_t n_spec,
+                         void* d_part) {
+  if (q.stg <= 256) launch_ccf_s<T, 256>(q, st, grid, d_flux, n_spec, d_part);
+  else launch_ccf_s<T, CCF_STG_MAX>(q, st, grid, d_flux, n_spec, d_part);
+}
+
+CcfPlan ccf_plan(const soap_ctx* c, int n_lines, const void* tables) {
+  CcfPlan q;
+  q.tables = static_cast<const unsigned char*>(tables);
+  q.off_edges = c->ccf_off_edges;
+  q.off_batch = c->ccf_off_batch;
+  q.off_bfirst = c->ccf_off_bfirst;
+  q.npx = c->ccf_npx;
+  q.stg = c->ccf_stg;
+  q.nv = c->mask_nv;
+  q.n_lines = n_lines;
+  q.v0 = c->mask_v0;
+  q.dv = c->mask_dv;
+  q.fp32 = c->prec == SOAP_PREC_FP32;
+  q.P = c->P;
+  return q;
+}
+
+hipError_t launch_ccf_p(const CcfPlan& q, hipStream_t st, const void* d_flux, int64_t n_spec, void* d_part) {
+  const int nlb = ccf_line_blocks(q.n_lines);
+  dim3 grid(nlb, (unsigned)((n_spec + CCF_SB - 1) / CCF_SB));
+  if (q.fp32) launch_ccf_t<float>(q, st, grid, d_flux, n_spec, d_part);
+  else launch_ccf_t<double>(q, st, grid, d_flux, n_spec, d_part);
+  return hipGetLastError();
 }
 
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, void* d_part) {
-  const int nlb = ccf_line_blocks(n_lines);
-  dim3 grid(nlb, (unsigned)((n_spec + CCF_SB - 1) / CCF_SB));
-  if (c->prec == SOAP_PREC_FP32) launch_ccf_t<float>(c, grid, d_flux, n_spec, d_part);
-  else launch_ccf_t<double>(c, grid, d_flux, n_spec, d_part);
-  return hipGetLastError();
+  return launch_ccf_p(ccf_plan(c, n_lines, c->ws_mask.ptr), c->stream, d_flux, n_spec, d_part);
 }
 
 // the fit kernel for the mask's points per lane
 template <typename PT>
-static hipError_t launch_fit_npt(soap_ctx* c, int nlb, int64_t n_spec, const PT* d_part, double* d_ccf,
-                                 soap_rv* d_rv) {
-  const int npt = (c->mask_nv + 63) / 64;
-#define FIT_CASE(N)                                                                                           \
-  case N:                                                                                                     \
-    hipLaunchKernelGGL((k_ccf_fit<N, PT>), dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, c->stream, nlb, n_spec, \
-                       c->mask_nv, c->mask_v0, c->mask_dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);                \
+static hipError_t launch_fit_npt(const CcfPlan& q, hipStream_t st, int nlb, int64_t n_spec, const PT* d_part,
+                                 double* d_ccf, soap_rv* d_rv) {
+  const int npt = (q.nv + 63) / 64;
+#define FIT_CASE(N)                                                                                         \
+  case N:                                                                                                   \
+    hipLaunchKernelGGL((k_ccf_fit<N, PT>), dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, st, nlb, n_spec, \
+                       q.nv, q.v0, q.dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);                                \
     break;
   switch (npt) {
     FIT_CASE(1) FIT_CASE(2) FIT_CASE(3) FIT_CASE(4) FIT_CASE(5) FIT_CASE(6)
@@ -701,11 +725,16 @@ static hipError_t launch_fit_npt(soap_ctx* c, int nlb, int64_t n_spec, const PT*
   return hipGetLastError();
 }
 
+hipError_t launch_ccf_fit_p(const CcfPlan& q, hipStream_t st, const void* d_part, int64_t n_spec, double* d_ccf,
+                            soap_rv* d_rv) {
+  const int nlb = ccf_line_blocks(q.n_lines);
+  if (q.fp32) return launch_fit_npt(q, st, nlb, n_spec, static_cast<const float*>(d_part), d_ccf, d_rv);
+  return launch_fit_npt(q, st, nlb, n_spec, static_cast<const double*>(d_part), d_ccf, d_rv);
+}
+
 hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const void* d_part, int64_t n_spec, double* d_ccf,
                           soap_rv* d_rv) {
-  const int nlb = ccf_line_blocks(n_lines);
-  if (c->prec == SOAP_PREC_FP32) return launch_fit_npt(c, nlb, n_spec, static_cast<const float*>(d_part), d_ccf, d_rv);
-  return launch_fit_npt(c, nlb, n_spec, static_cast<const double*>(d_part), d_ccf, d_rv);
+  return launch_ccf_fit_p(ccf_plan(c, n_lines, c->ws_mask.ptr), c->stream, d_part, n_spec, d_ccf, d_rv);
 }
 
 // ccf[i][v] = base[v] + sum_k coef[i][k] basis[k][v] (double, increasing k):
@@ -983,7 +1012,7 @@ hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, in
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // the rows are complete CCFs: one "block of lines" for the fit kernel
-  return launch_fit_npt(c, 1, n, d_lin, d_ccf, d_rv);
+  return launch_fit_npt(ccf_plan(c, 1, c->ws_mask.ptr), c->stream, 1, n, d_lin, d_ccf, d_rv);
 }
 
 

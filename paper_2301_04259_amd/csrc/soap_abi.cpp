@@ -882,13 +882,12 @@ SOAP_API soap_status soap_instrument_lsf(soap_ctx* c, const void* in, void* out,
   return SOAP_OK;
 }
 
-SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_device, int64_t n_spec,
-                                 const soap_mask* mask, double* ccf_out, int32_t ccf_on_device, soap_rv* rv_out,
-                                 int32_t rv_on_device) {
-  if (!c) return SOAP_ERR_ARG;
+namespace soap {
+
+// Validates a mask for the context and uploads its CCF tables unless they are
+// the cached ones (soap_ccf_rv, batches with a CCF stage).
+soap_status ctx_set_mask(soap_ctx* c, const soap_mask* mask) {
   std::string& err = c->err;
-  ARG_CHECK(flux != nullptr, "flux is NULL");
-  ARG_CHECK(n_spec >= 1 && n_spec <= (int64_t(1) << 24), "n_spec must be in [1, 2^24]");
   ARG_CHECK(mask != nullptr, "mask is NULL");
   ARG_CHECK(mask->n_lines >= 1 && mask->n_lines <= (int64_t(1) << 20), "mask.n_lines must be in [1, 2^20]");
   ARG_CHECK(mask->ln_lambda != nullptr && mask->weight != nullptr, "mask arrays are NULL");
@@ -929,12 +928,31 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
       return SOAP_ERR_UNSUPPORTED;
     }
     HIP_TRY(grow(c->ws_mask, blob.size()));
+    c->mask_blob_bytes = blob.size();
     soap_status st = stage_to_device(c, blob.data(), blob.size(), c->ws_mask.ptr);
     if (st != SOAP_OK) return st;
     c->mask_lnl.assign(mask->ln_lambda, mask->ln_lambda + nl);
     c->mask_w.assign(mask->weight, mask->weight + nl);
     c->mask_valid = true;
   }
+
+  return SOAP_OK;
+}
+
+}  // namespace soap
+
+SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_device, int64_t n_spec,
+                                 const soap_mask* mask, double* ccf_out, int32_t ccf_on_device, soap_rv* rv_out,
+                                 int32_t rv_on_device) {
+  if (!c) return SOAP_ERR_ARG;
+  std::string& err = c->err;
+  ARG_CHECK(flux != nullptr, "flux is NULL");
+  ARG_CHECK(n_spec >= 1 && n_spec <= (int64_t(1) << 24), "n_spec must be in [1, 2^24]");
+  {
+    const soap_status ms = soap::ctx_set_mask(c, mask);
+    if (ms != SOAP_OK) return ms;
+  }
+  const int nl = (int)mask->n_lines;
 
   const void* dflux = flux;
   const size_t in_bytes = (size_t)n_spec * c->P * c->esize;

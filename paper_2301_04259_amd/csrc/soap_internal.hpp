@@ -225,6 +225,7 @@ struct soap_ctx {
   // byte offsets of the sections, batch count, pixels per hole, stage span
   size_t ccf_off_edges = 0, ccf_off_batch = 0, ccf_off_bfirst = 0;
   int ccf_nbatch = 0, ccf_npx = 2, ccf_stg = 256;
+  size_t mask_blob_bytes = 0;  // bytes of the mask's tables in ws_mask
   bool mask_valid = false;
 };
 
@@ -369,6 +370,21 @@ bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, 
 // partial CCFs per line block, [n_lb][n_spec][n_v] in the flux type (a block's
 // partial is a sum in that type)
 hipError_t launch_ccf(soap_ctx* c, const void* d_flux, int64_t n_spec, int n_lines, void* d_part);
+// a mask's CCF launch parameters (the context's layout of its tables, with
+// the tables at `tables`), so that a batch can keep its own copy of them
+struct CcfPlan {
+  const unsigned char* tables = nullptr;
+  size_t off_edges = 0, off_batch = 0, off_bfirst = 0;
+  int npx = 2, stg = 256, nv = 0, n_lines = 0;
+  double v0 = 0.0, dv = 0.0;
+  bool fp32 = true;
+  int64_t P = 0;
+};
+CcfPlan ccf_plan(const soap_ctx* c, int n_lines, const void* tables);
+soap_status ctx_set_mask(soap_ctx* c, const soap_mask* mask);
+hipError_t launch_ccf_p(const CcfPlan& q, hipStream_t st, const void* d_flux, int64_t n_spec, void* d_part);
+hipError_t launch_ccf_fit_p(const CcfPlan& q, hipStream_t st, const void* d_part, int64_t n_spec, double* d_ccf,
+                            soap_rv* d_rv);
 // sums the partial CCFs (in double) into d_ccf and, when d_rv is not null,
 // fits them
 hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const void* d_part, int64_t n_spec, double* d_ccf,

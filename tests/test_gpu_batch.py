@@ -107,3 +107,49 @@ def test_batch_argument_checks():
         L.soap_batch_create([c4], [[r]], [np.array([0.1])], W.EFFECT_TOT, [o4])
     L.soap_destroy(c)
     L.soap_destroy(c4)
+
+
+def test_batch_ccf_and_fit_equal_single_calls():
+    """The CCF + fit stage of a batch graph gives, on every replay, what
+    soap_ccf_rv gives on the same spectra, bit for bit (section 4.1)."""
+    stars = [W.make_tiny(21, n_grid=30, n_pix=2600, n_mu=4, precision=W.PREC_FP32, contrast_mode=W.CONTRAST_PLANCK),
+             W.make_tiny(21, n_grid=44, n_pix=2600, n_mu=4, precision=W.PREC_FP32)]
+    mask = stars[0].mask
+    ctxs = [L.soap_grid_init(s) for s in stars]
+    L.soap_set_apply_shape(ctxs[1], 2, 0, 16)
+    rng = np.random.default_rng(9)
+    cfg_ctx, cfg_regs, cfg_ph, outs, ccfs, rvs = [], [], [], [], [], []
+    for i in range(7):
+        k = i % 2
+        regs = [W.Region(W.SPOT, float(rng.uniform(-50, 50)), float(rng.uniform(0, 360)), float(rng.uniform(0.1, 0.3)),
+                         0.6)]
+        ph = np.sort(rng.uniform(0, 1, int(rng.integers(3, 30))))
+        cfg_ctx.append(ctxs[k])
+        cfg_regs.append(regs)
+        cfg_ph.append(ph)
+        outs.append(torch.empty((len(ph), stars[k].n_pix), dtype=torch.float32, device="cuda"))
+        ccfs.append(torch.full((len(ph), mask.n_v), -1.0, dtype=torch.float64, device="cuda") if i != 3 else None)
+        rvs.append(torch.zeros(len(ph) * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda") if i != 5 else None)
+    _say("batch with CCF + fit: 7 configurations over 2 stars")
+    b = L.soap_batch_create(cfg_ctx, cfg_regs, cfg_ph, W.EFFECT_TOT, outs, mask=mask, ccf_outs=ccfs, rv_outs=rvs)
+    for rep in range(2):
+        for o in outs:
+            o.fill_(-1.0)
+        torch.cuda.synchronize()
+        L.soap_batch_run(b)
+        torch.cuda.synchronize()
+        for i in range(7):
+            c1 = torch.empty((len(cfg_ph[i]), mask.n_v), dtype=torch.float64, device="cuda")
+            r1 = torch.zeros(len(cfg_ph[i]) * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+            L.soap_ccf_rv(cfg_ctx[i], outs[i], mask, ccf_out=c1, rv_out=r1)
+            torch.cuda.synchronize()
+            if ccfs[i] is not None:
+                np.testing.assert_array_equal(ccfs[i].cpu().numpy(), c1.cpu().numpy(), err_msg=f"replay {rep} ccf {i}")
+            if rvs[i] is not None:
+                got = np.frombuffer(rvs[i].cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
+                want = np.frombuffer(r1.cpu().numpy().tobytes(), dtype=L.RV_DTYPE)
+                np.testing.assert_array_equal(got["rv_kms"], want["rv_kms"], err_msg=f"replay {rep} rv {i}")
+                assert np.array_equal(got["status"], want["status"])
+    L.soap_batch_destroy(b)
+    for c in ctxs:
+        L.soap_destroy(c)
