@@ -439,6 +439,17 @@ soap_status soap_batch_create_rv(soap_ctx* const* ctxs, int32_t n_cfg, const soa
                                  const int32_t* region_offsets, const double* phases, const int32_t* phase_offsets,
                                  int32_t effect, void* const* flux, const soap_mask* mask, double* const* ccf,
                                  soap_rv* const* rv, void* hip_stream, soap_batch** out);
+/* The configurations of soap_batch_create (same arguments and checks) run
+ * once, without a graph: the same work-list launches enqueued on
+ * hip_stream, then the call waits for the stream.  For many small
+ * configurations over many stars (one call instead of one per star).  The
+ * device arena is kept by the library between calls (reused, grown when a
+ * call needs more) and calls are serialised on it.  Errors as for
+ * soap_batch_create; the message is soap_batch_last_error(NULL).            */
+soap_status soap_active_spectra_multi(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                                      const int32_t* region_offsets, const double* phases,
+                                      const int32_t* phase_offsets, int32_t effect, void* const* flux,
+                                      void* hip_stream);
 soap_status soap_batch_run(soap_batch* batch);
 int64_t soap_batch_n_spectra(const soap_batch* batch);
 const char* soap_batch_last_error(const soap_batch* batch);

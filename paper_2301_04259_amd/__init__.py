@@ -76,6 +76,7 @@ SYMBOLS = (
     "soap_autotune",
     "soap_batch_create",
     "soap_batch_create_rv",
+    "soap_active_spectra_multi",
     "soap_batch_run",
     "soap_batch_n_spectra",
     "soap_batch_last_error",
@@ -244,6 +245,9 @@ _lib.soap_batch_create_rv.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_voi
                                       C.c_int32, C.c_void_p, C.POINTER(MaskC), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_void_p)]
 _lib.soap_batch_create_rv.restype = C.c_int
+_lib.soap_active_spectra_multi.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_int32, C.c_void_p, C.c_void_p]
+_lib.soap_active_spectra_multi.restype = C.c_int
 _lib.soap_batch_run.argtypes = [C.c_void_p]
 _lib.soap_batch_run.restype = C.c_int
 _lib.soap_batch_n_spectra.argtypes = [C.c_void_p]
@@ -873,6 +877,53 @@ def soap_batch_create(ctxs, cfg_regions, cfg_phases, effect, outs, stream=None, 
     b = Batch(h, list(ctxs), list(outs))
     b._keep = keep
     return b
+
+
+def _batch_arrays(ctxs, cfg_regions, cfg_phases, outs):
+    n = len(ctxs)
+    handles = (C.c_void_p * n)(*[C.cast(c.handle, C.c_void_p) for c in ctxs])
+    regs = [r for rl in cfg_regions for r in rl]
+    arr = np.zeros(max(1, len(regs)), dtype=REGION_DTYPE)
+    for i, r in enumerate(regs):
+        arr[i] = (int(r.type), 0, float(r.lat_deg), float(r.lon_deg), float(r.radius), float(r.contrast))
+    roff = np.zeros(n + 1, np.int32)
+    roff[1:] = np.cumsum([len(rl) for rl in cfg_regions])
+    ph = np.ascontiguousarray(np.concatenate([np.asarray(p, np.float64).reshape(-1) for p in cfg_phases]))
+    poff = np.zeros(n + 1, np.int32)
+    poff[1:] = np.cumsum([np.asarray(p).size for p in cfg_phases])
+    fl = (C.c_void_p * n)(*[_dptr(o, "flux") for o in outs])
+    return handles, arr, roff, ph, poff, fl
+
+
+def soap_active_spectra_multi(ctxs, cfg_regions, cfg_phases, effect, outs, stream=None):
+    """One synthesis call over many configurations of many stars (ctx, region
+    list, phases, device output each); waits for the stream."""
+    n = len(ctxs)
+    handles, arr, roff, ph, poff, fl = _batch_arrays(ctxs, cfg_regions, cfg_phases, outs)
+    st = _lib.soap_active_spectra_multi(handles, n, arr.ctypes.data, roff.ctypes.data, ph.ctypes.data,
+                                        poff.ctypes.data, int(effect), fl, _stream_handle(stream))
+    if st != SOAP_OK:
+        raise SoapError(st, _lib.soap_batch_last_error(None).decode())
+
+
+def soap_active_spectra_multi_arrays(handles, regions, region_offsets, phases, phase_offsets, effect, flux_ptrs,
+                                     stream=None):
+    """The same call from prepared arrays: context handles and flux row
+    pointers as uint64 arrays, REGION_DTYPE regions with int32 offsets,
+    float64 phases with int32 offsets (no per-configuration Python work)."""
+    h = np.ascontiguousarray(handles, dtype=np.uint64)
+    regs = np.ascontiguousarray(regions)
+    roff = np.ascontiguousarray(region_offsets, dtype=np.int32)
+    ph = np.ascontiguousarray(phases, dtype=np.float64)
+    poff = np.ascontiguousarray(phase_offsets, dtype=np.int32)
+    fl = np.ascontiguousarray(flux_ptrs, dtype=np.uint64)
+    n = len(h)
+    if len(fl) != n or len(roff) != n + 1 or len(poff) != n + 1:
+        raise ValueError("one handle, flux pointer and region / phase range per configuration")
+    st = _lib.soap_active_spectra_multi(h.ctypes.data, n, regs.ctypes.data, roff.ctypes.data, ph.ctypes.data,
+                                        poff.ctypes.data, int(effect), fl.ctypes.data, _stream_handle(stream))
+    if st != SOAP_OK:
+        raise SoapError(st, _lib.soap_batch_last_error(None).decode())
 
 
 def soap_batch_run(batch):

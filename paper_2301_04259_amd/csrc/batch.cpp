@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,16 +75,29 @@ bool is_fin(double v) { return std::isfinite(v); }
 
 static thread_local std::string g_batch_err;
 
+// Arena of the one-shot calls (soap_active_spectra_multi): kept between calls
+// and reused under a lock, since each call waits for its stream.
+struct DirectArena {
+  std::mutex mu;
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int dev = -1;
+};
+static DirectArena g_direct;
+
+// Builds a batch (a graph of every configuration's work) or, with direct,
+// enqueues the same launches once on hip_stream, waits for them and keeps
+// nothing but the reusable arena.
 static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
                                const int32_t* region_offsets, const double* phases, const int32_t* phase_offsets,
                                int32_t effect, void* const* flux, const soap_mask* mask, double* const* ccf,
-                               soap_rv* const* rv, void* hip_stream, soap_batch** out) {
+                               soap_rv* const* rv, void* hip_stream, soap_batch** out, bool direct = false) {
   auto bad = [](const std::string& m, soap_status st = SOAP_ERR_ARG) {
     g_batch_err = m;
     return st;
   };
-  if (!out) return bad("out is NULL");
-  *out = nullptr;
+  if (!direct && !out) return bad("out is NULL");
+  if (out) *out = nullptr;
   if (!ctxs || !region_offsets || !phase_offsets || !phases || !flux) return bad("a required array is NULL");
   if (n_cfg < 1 || n_cfg > (1 << 16)) return bad("n_cfg must be in [1, 65536]");
   if (effect != SOAP_EFFECT_TOT && effect != SOAP_EFFECT_FLUX && effect != SOAP_EFFECT_BCONV)
@@ -92,7 +106,7 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return bad("no device");
   std::vector<CfgPlan> cp(n_cfg);
-  size_t arena = 0;
+  size_t arena = 0, params_bytes = 0;
   int64_t n_spec = 0;
   char msg[256];
   for (int i = 0; i < n_cfg; ++i) {
@@ -150,8 +164,15 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
       arena += al(std::max<size_t>(bytes, 1));
       return o;
     };
-    q.off_reg = take(sizeof(soap::Region) * std::max(1, nr));
-    q.off_ph = take(sizeof(double) * np);
+    // regions and phases of every configuration form the arena's first
+    // section (one upload); the other offsets are shifted past it below
+    auto ptake = [&](size_t bytes) {
+      const size_t o = params_bytes;
+      params_bytes += al(std::max<size_t>(bytes, 1));
+      return o;
+    };
+    q.off_reg = ptake(sizeof(soap::Region) * std::max(1, nr));
+    q.off_ph = ptake(sizeof(double) * np);
     q.off_regcopy = take(sizeof(soap::Region) * std::max(1, nr));
     q.off_cen = take(sizeof(double4) * (size_t)np * std::max(1, nr));
     q.off_box = take(sizeof(int4) * (size_t)np);
@@ -162,6 +183,11 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     q.off_nvg = take(sizeof(int) * (size_t)pl.n_chunks);
     n_spec += np;
   }
+  for (CfgPlan& q : cp) {
+    size_t* offs[] = {&q.off_regcopy, &q.off_cen, &q.off_box, &q.off_kfx, &q.off_k, &q.off_mask, &q.off_vg, &q.off_nvg};
+    for (size_t* o : offs) *o += params_bytes;
+  }
+  arena += params_bytes;
   // the shift-and-sum runs as one launch per (precision, table mode, phases
   // per chunk, windows in flight) over every configuration's (tile, chunk)
   // items, in order of first appearance
@@ -251,21 +277,35 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     return (e == hipErrorOutOfMemory) ? SOAP_ERR_OOM : SOAP_ERR_HIP;
   };
   hipError_t e;
-  if ((e = soap::dev_malloc(&b->arena, arena)) != hipSuccess) return fail("hipMalloc", e);
+  std::unique_lock<std::mutex> direct_lock;
+  unsigned char* A = nullptr;
+  if (direct) {
+    direct_lock = std::unique_lock<std::mutex>(g_direct.mu);
+    if (g_direct.bytes < arena || g_direct.dev != dev) {
+      if (g_direct.ptr) (void)soap::dev_free(g_direct.ptr);
+      g_direct.ptr = nullptr;
+      g_direct.bytes = 0;
+      if ((e = soap::dev_malloc(&g_direct.ptr, arena)) != hipSuccess) return fail("hipMalloc", e);
+      g_direct.bytes = arena;
+      g_direct.dev = dev;
+    }
+    A = static_cast<unsigned char*>(g_direct.ptr);
+  } else {
+    if ((e = soap::dev_malloc(&b->arena, arena)) != hipSuccess) return fail("hipMalloc", e);
+    A = static_cast<unsigned char*>(b->arena);
+  }
   // tap accumulators start at zero (each run's tap-list kernel clears them
   // again after reading); parameters are uploaded once
-  if ((e = hipMemset(b->arena, 0, arena)) != hipSuccess) return fail("hipMemset", e);
-  unsigned char* A = static_cast<unsigned char*>(b->arena);
+  if ((e = hipMemset(A, 0, arena)) != hipSuccess) return fail("hipMemset", e);
   {
+    std::vector<unsigned char> hp(params_bytes, 0);
     for (int i = 0; i < n_cfg; ++i) {
       const CfgPlan& q = cp[i];
       const std::vector<soap::Region>& hr = hregs[i];
-      if ((e = hipMemcpy(A + q.off_reg, hr.data(), sizeof(soap::Region) * hr.size(), hipMemcpyHostToDevice)) !=
-              hipSuccess ||
-          (e = hipMemcpy(A + q.off_ph, phases + phase_offsets[i], sizeof(double) * q.pl.n_ph,
-                         hipMemcpyHostToDevice)) != hipSuccess)
-        return fail("hipMemcpy", e);
+      std::memcpy(hp.data() + q.off_reg, hr.data(), sizeof(soap::Region) * hr.size());
+      std::memcpy(hp.data() + q.off_ph, phases + phase_offsets[i], sizeof(double) * q.pl.n_ph);
     }
+    if ((e = hipMemcpy(A, hp.data(), params_bytes, hipMemcpyHostToDevice)) != hipSuccess) return fail("hipMemcpy", e);
   }
   std::vector<soap::CcfPlan> cplan(uctx.size());
   for (size_t u = 0; u < uctx.size(); ++u) {
@@ -307,6 +347,66 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     if ((e = soap::table_batch_upload(tc.data(), (int)tc.size(), A + table_off, &tb)) != hipSuccess)
       return fail("uploading the table work lists", e);
   }
+  // the contexts' own work must be finished before their tables are read
+  for (int i = 0; i < n_cfg; ++i) {
+    if ((e = hipStreamSynchronize(cp[i].c->stream)) != hipSuccess) return fail("context stream", e);
+    if ((e = hipStreamSynchronize(cp[i].c->side)) != hipSuccess) return fail("context stream", e);
+  }
+  // Every launch of one run: with fork_join, work per configuration spreads
+  // over the branch streams (forked from and joined to org); without, it all
+  // goes on org in order.
+  auto enqueue = [&](hipStream_t org, bool fork_join) -> hipError_t {
+    auto lane = [&](size_t u) { return fork_join ? b->branch[u % kBranches] : org; };
+    hipError_t ce = hipSuccess;
+    if (fork_join) {
+      ce = hipEventRecord(b->fork, org);
+      for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork, 0);
+    }
+    for (size_t u = 0; u < single.size() && ce == hipSuccess; ++u) {
+      const CfgPlan& q = cp[single[u]];
+      const soap::WeightsOut wo = outs_of(q);
+      ce = soap::launch_weights(q.c, q.pl, reinterpret_cast<const soap::Region*>(A + q.off_reg), q.n_reg,
+                                std::max(1, q.n_reg), reinterpret_cast<const double*>(A + q.off_ph), nullptr, wo,
+                                lane(u));
+      if (ce == hipSuccess) ce = soap::launch_finish(q.c, q.pl, wo, lane(u));
+    }
+    if (ce == hipSuccess && !listed.empty()) ce = soap::table_batch_launch(tb, org);
+    if (fork_join)
+      for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
+        ce = hipEventRecord(b->join[k], b->branch[k]);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(org, b->join[k], 0);
+      }
+    for (int g = 0; g < n_groups && ce == hipSuccess; ++g) ce = soap::apply_batch_launch(ag[g], org);
+    if (mask && ce == hipSuccess) {
+      // CCF and fit of every configuration's spectra
+      if (fork_join) {
+        ce = hipEventRecord(b->fork2, org);
+        for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork2, 0);
+      }
+      for (int i = 0; i < n_cfg && ce == hipSuccess; ++i) {
+        const soap::CcfPlan& q = cplan[ucfg[i]];
+        double* dccf = (ccf && ccf[i]) ? ccf[i] : reinterpret_cast<double*>(A + ccf_off[i]);
+        ce = soap::launch_ccf_p(q, lane(i), cp[i].flux, cp[i].pl.n_ph, A + part_off[i]);
+        if (ce == hipSuccess)
+          ce = soap::launch_ccf_fit_p(q, lane(i), A + part_off[i], cp[i].pl.n_ph, dccf, rv ? rv[i] : nullptr);
+      }
+      if (fork_join)
+        for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
+          ce = hipEventRecord(b->join2[k], b->branch[k]);
+          if (ce == hipSuccess) ce = hipStreamWaitEvent(org, b->join2[k], 0);
+        }
+    }
+    return ce;
+  };
+  if (direct) {
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipError_t ce = enqueue(st, false);
+    const hipError_t se = hipStreamSynchronize(st);
+    if (ce != hipSuccess) return fail("enqueueing the configurations", ce);
+    if (se != hipSuccess) return fail("hipStreamSynchronize", se);
+    destroy_batch(b);
+    return SOAP_OK;
+  }
   if ((e = hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
   for (int k = 0; k < kBranches; ++k) {
     if ((e = hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking)) != hipSuccess) return fail("stream", e);
@@ -318,45 +418,8 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     for (int k = 0; k < kBranches; ++k)
       if ((e = hipEventCreateWithFlags(&b->join2[k], hipEventDisableTiming)) != hipSuccess) return fail("event", e);
   }
-  // the contexts' own work must be finished before their tables are read
-  for (int i = 0; i < n_cfg; ++i) {
-    if ((e = hipStreamSynchronize(cp[i].c->stream)) != hipSuccess) return fail("context stream", e);
-    if ((e = hipStreamSynchronize(cp[i].c->side)) != hipSuccess) return fail("context stream", e);
-  }
-
   if ((e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed)) != hipSuccess) return fail("capture", e);
-  hipError_t ce = hipEventRecord(b->fork, b->origin);
-  for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork, 0);
-  for (size_t u = 0; u < single.size() && ce == hipSuccess; ++u) {
-    const CfgPlan& q = cp[single[u]];
-    hipStream_t st = b->branch[u % kBranches];
-    const soap::WeightsOut wo = outs_of(q);
-    ce = soap::launch_weights(q.c, q.pl, reinterpret_cast<const soap::Region*>(A + q.off_reg), q.n_reg,
-                              std::max(1, q.n_reg), reinterpret_cast<const double*>(A + q.off_ph), nullptr, wo, st);
-    if (ce == hipSuccess) ce = soap::launch_finish(q.c, q.pl, wo, st);
-  }
-  if (ce == hipSuccess && !listed.empty()) ce = soap::table_batch_launch(tb, b->origin);
-  for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
-    ce = hipEventRecord(b->join[k], b->branch[k]);
-    if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join[k], 0);
-  }
-  for (int g = 0; g < n_groups && ce == hipSuccess; ++g) ce = soap::apply_batch_launch(ag[g], b->origin);
-  if (mask && ce == hipSuccess) {
-    // CCF and fit of every configuration's spectra, spread over the branches
-    ce = hipEventRecord(b->fork2, b->origin);
-    for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork2, 0);
-    for (int i = 0; i < n_cfg && ce == hipSuccess; ++i) {
-      hipStream_t st = b->branch[i % kBranches];
-      const soap::CcfPlan& q = cplan[ucfg[i]];
-      double* dccf = (ccf && ccf[i]) ? ccf[i] : reinterpret_cast<double*>(A + ccf_off[i]);
-      ce = soap::launch_ccf_p(q, st, cp[i].flux, cp[i].pl.n_ph, A + part_off[i]);
-      if (ce == hipSuccess) ce = soap::launch_ccf_fit_p(q, st, A + part_off[i], cp[i].pl.n_ph, dccf, rv ? rv[i] : nullptr);
-    }
-    for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
-      ce = hipEventRecord(b->join2[k], b->branch[k]);
-      if (ce == hipSuccess) ce = hipStreamWaitEvent(b->origin, b->join2[k], 0);
-    }
-  }
+  const hipError_t ce = enqueue(b->origin, true);
   e = hipStreamEndCapture(b->origin, &b->graph);
   if (ce != hipSuccess) return fail("capturing the batch", ce);
   if (e != hipSuccess) return fail("hipStreamEndCapture", e);
@@ -386,6 +449,14 @@ SOAP_API soap_status soap_batch_create_rv(soap_ctx* const* ctxs, int32_t n_cfg, 
   }
   return create_impl(ctxs, n_cfg, regions, region_offsets, phases, phase_offsets, effect, flux, mask, ccf, rv,
                      hip_stream, out);
+}
+
+SOAP_API soap_status soap_active_spectra_multi(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
+                                               const int32_t* region_offsets, const double* phases,
+                                               const int32_t* phase_offsets, int32_t effect, void* const* flux,
+                                               void* hip_stream) {
+  return create_impl(ctxs, n_cfg, regions, region_offsets, phases, phase_offsets, effect, flux, nullptr, nullptr,
+                     nullptr, hip_stream, nullptr, true);
 }
 
 SOAP_API soap_status soap_batch_run(soap_batch* b) {

@@ -51,6 +51,7 @@ from . import (
     SPOT,
     region_array,
     soap_active_spectra_jobs,
+    soap_active_spectra_multi_arrays,
     soap_ccf_rv,
     soap_quiet_spectrum,
     soap_surrogate_create,
@@ -116,6 +117,12 @@ class Stars:
         self.params.append((float(teff_k), float(incl_deg), float(vsini_kms)))
         self._lut = None
         self._pa = None
+
+    def handle_array(self):
+        """Context handle per row, uint64."""
+        if getattr(self, "_ha", None) is None or len(self._ha) != len(self.ctxs):
+            self._ha = np.array([c.handle.value for c in self.ctxs], dtype=np.uint64)
+        return self._ha
 
     def param_array(self):
         """(T_eff, inclination, v sin i) per row, float64 [rows][3]."""
@@ -196,14 +203,34 @@ def _groups(keys):
 
 def synthesize(stars, samples, out, idx=None):
     """Full synthesis of samples (all, or the sorted indices idx) into out
-    [n][n_pix] (device): per star, one soap_active_spectra_jobs call, one job
-    per spot with the phases of its selected samples."""
+    [n][n_pix] (device).  One star: one soap_active_spectra_jobs call, one job
+    per spot with the phases of its selected samples.  Several stars: one
+    soap_active_spectra_multi call, one configuration per spot (its star's
+    context, its phases, its rows of out)."""
     n_per = samples.n_per
     idx = np.arange(samples.n) if idx is None else np.asarray(idx)
     if len(idx) == 0:
         return out
     sid = sample_stars(samples, idx)
     ph = samples.phases.reshape(-1)
+    starts_star, _ = _groups(sid)
+    if len(starts_star) > 1:
+        spots = idx // n_per
+        sst, _ = _groups(spots)
+        k = spots[sst]
+        handles = stars.handle_array()[stars.rows(sid[sst])]
+        regions = region_array(SPOT, samples.lat_deg[k], samples.lon_deg[k], samples.radius[k], samples.contrast[k])
+        roff = np.arange(len(sst) + 1, dtype=np.int32)
+        poff = np.r_[sst, len(idx)].astype(np.int32)
+        row_bytes = out.shape[1] * out.element_size()
+        assert out.is_contiguous()
+        ptrs = np.uint64(out.data_ptr()) + sst.astype(np.uint64) * np.uint64(row_bytes)
+        for a in range(0, len(sst), 65536):  # the call takes at most 65536 configurations
+            b = min(len(sst), a + 65536)
+            soap_active_spectra_multi_arrays(handles[a:b], regions[a:b], roff[a:b + 1] - roff[a],
+                                             ph[idx[poff[a]:poff[b]]], poff[a:b + 1] - poff[a], EFFECT_TOT,
+                                             ptrs[a:b])
+        return out
     for a0, b0 in zip(*_groups(sid)):
         ctx = stars.ctxs[stars.row[int(sid[a0])]]
         sub = idx[a0:b0]

@@ -153,3 +153,36 @@ def test_batch_ccf_and_fit_equal_single_calls():
     L.soap_batch_destroy(b)
     for c in ctxs:
         L.soap_destroy(c)
+
+
+def test_multi_context_call_equals_single_calls():
+    """soap_active_spectra_multi: one call over configurations of several
+    stars gives every configuration's single-call spectra bit for bit; a
+    second, larger call reuses and grows the library's arena."""
+    stars = _stars()
+    ctxs = [L.soap_grid_init(s) for s in stars]
+    rng = np.random.default_rng(17)
+    for n_cfg in (6, 23):
+        cfg_ctx, cfg_star, cfg_regs, cfg_ph, outs = [], [], [], [], []
+        for i in range(n_cfg):
+            k = int(rng.integers(0, len(stars)))
+            s = stars[k]
+            types = [W.SPOT, W.FACULA] if s.spectra[W.FACULA] is not None else [W.SPOT]
+            regs = [W.Region(int(rng.choice(types)), float(rng.uniform(-60, 60)), float(rng.uniform(0, 360)),
+                             float(rng.uniform(0.05, 0.3)), 1.0) for _ in range(int(rng.integers(0, 3)))]
+            ph = rng.uniform(0, 1, int(rng.integers(1, 20)))
+            dt = torch.float32 if s.precision == W.PREC_FP32 else torch.float64
+            cfg_ctx.append(ctxs[k])
+            cfg_star.append(s)
+            cfg_regs.append(regs)
+            cfg_ph.append(ph)
+            outs.append(torch.full((len(ph), s.n_pix), -1.0, dtype=dt, device="cuda"))
+        _say(f"multi-context call: {n_cfg} configurations")
+        L.soap_active_spectra_multi(cfg_ctx, cfg_regs, cfg_ph, W.EFFECT_TOT, outs)
+        for i in range(n_cfg):
+            one = torch.empty_like(outs[i])
+            L.soap_active_spectra(cfg_ctx[i], cfg_regs[i], cfg_ph[i], W.EFFECT_TOT, one)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(outs[i].cpu().numpy(), one.cpu().numpy(), err_msg=f"{n_cfg}: cfg {i}")
+    for c in ctxs:
+        L.soap_destroy(c)
