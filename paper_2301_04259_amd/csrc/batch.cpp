@@ -310,6 +310,8 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
   std::vector<soap::CcfPlan> cplan(uctx.size());
   for (size_t u = 0; u < uctx.size(); ++u) {
     soap_ctx* c = uctx[u];
+    // the mask upload is enqueued on the context's stream
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return fail("context stream", e);
     if ((e = hipMemcpy(A + tab_off[u], c->ws_mask.ptr, c->mask_blob_bytes, hipMemcpyDeviceToDevice)) != hipSuccess)
       return fail("copying the mask tables", e);
     cplan[u] = soap::ccf_plan(c, (int)mask->n_lines, A + tab_off[u]);
@@ -347,10 +349,20 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     if ((e = soap::table_batch_upload(tc.data(), (int)tc.size(), A + table_off, &tb)) != hipSuccess)
       return fail("uploading the table work lists", e);
   }
-  // the contexts' own work must be finished before their tables are read
-  for (int i = 0; i < n_cfg; ++i) {
-    if ((e = hipStreamSynchronize(cp[i].c->stream)) != hipSuccess) return fail("context stream", e);
-    if ((e = hipStreamSynchronize(cp[i].c->side)) != hipSuccess) return fail("context stream", e);
+  // The tables the launches read (local spectra, contrast rows, Q) are
+  // written only by soap_grid_init, which waits for its work before it
+  // returns; a batch graph, replayed later, also waits here once for every
+  // distinct context's streams.  The one-shot call does not wait (per
+  // configuration that cost more than its kernels).
+  if (!direct) {
+    std::vector<soap_ctx*> seen;
+    for (int i = 0; i < n_cfg; ++i) {
+      soap_ctx* c = cp[i].c;
+      if (std::find(seen.begin(), seen.end(), c) != seen.end()) continue;
+      seen.push_back(c);
+      if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return fail("context stream", e);
+      if ((e = hipStreamSynchronize(c->side)) != hipSuccess) return fail("context stream", e);
+    }
   }
   // Every launch of one run: with fork_join, work per configuration spreads
   // over the branch streams (forked from and joined to org); without, it all
