@@ -444,8 +444,10 @@ soap_status soap_batch_create_rv(soap_ctx* const* ctxs, int32_t n_cfg, const soa
  * hip_stream, then the call waits for the stream.  For many small
  * configurations over many stars (one call instead of one per star).  The
  * device arena is kept by the library between calls (reused, grown when a
- * call needs more) and calls are serialised on it.  Errors as for
- * soap_batch_create; the message is soap_batch_last_error(NULL).            */
+ * call needs more) and calls are serialised on it.  It does not wait for
+ * the contexts' own streams: the tables it reads are complete when
+ * soap_grid_init returns.  Errors as for soap_batch_create; the message is
+ * soap_batch_last_error(NULL).                                              */
 soap_status soap_active_spectra_multi(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
                                       const int32_t* region_offsets, const double* phases,
                                       const int32_t* phase_offsets, int32_t effect, void* const* flux,
