@@ -299,9 +299,10 @@ soap_status soap_set_instrument(soap_ctx* ctx, double resolution);
  * NULL) are host or device memory as flagged.  On the first call with a new
  * mask (the context compares against the last one) the line positions, the
  * hole edges per velocity and the batches of nearby lines are built on the
- * host and uploaded.  SOAP_ERR_UNSUPPORTED when a line's holes over the grid
- * reach more than 512 pixels (the velocity span plus the pixels a hole can
- * touch).                                                                   */
+ * host and uploaded; lines whose holes at every velocity fall outside the
+ * spectrum add nothing and are left out of the tables.  SOAP_ERR_UNSUPPORTED
+ * when a line's holes over the grid reach more than 512 pixels (the velocity
+ * span plus the pixels a hole can touch).                                   */
 soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device, int64_t n_spec,
                         const soap_mask* mask, double* ccf_out, int32_t ccf_on_device,
                         soap_rv* rv_out, int32_t rv_on_device);
@@ -314,7 +315,8 @@ soap_status soap_ccf_rv(soap_ctx* ctx, const void* flux, int32_t flux_on_device,
  * ccf_out is NULL, go to a file-scope device array of 32 MiB that the
  * library holds on every device it runs on until the process ends:
  * n_spec n_v (e ceil(n_lines / 32) + 8 [ccf_out == NULL]) bytes, e the size
- * of the context's float type, the first part rounded up to 256, must fit,
+ * of the context's float type, n_lines the mask lines whose reads reach the
+ * spectrum (see soap_ccf_rv), the first part rounded up to 256, must fit,
  * else SOAP_ERR_UNSUPPORTED.  The mask
  * must be the one the context already holds (the last one given to
  * soap_ccf_rv), else SOAP_ERR_STATE; nothing is uploaded.  Every call on a

@@ -256,7 +256,7 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
         arena += al(c->mask_blob_bytes);
       }
       ucfg[i] = (int)u;
-      const size_t nlb = (size_t)soap::ccf_line_blocks((int)mask->n_lines);
+      const size_t nlb = (size_t)soap::ccf_line_blocks(c->ccf_nl);
       part_off[i] = arena;
       arena += al(c->esize * nlb * (size_t)cp[i].pl.n_ph * c->mask_nv);
       if (!ccf || !ccf[i]) {
@@ -314,7 +314,7 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return fail("context stream", e);
     if ((e = hipMemcpy(A + tab_off[u], c->ws_mask.ptr, c->mask_blob_bytes, hipMemcpyDeviceToDevice)) != hipSuccess)
       return fail("copying the mask tables", e);
-    cplan[u] = soap::ccf_plan(c, (int)mask->n_lines, A + tab_off[u]);
+    cplan[u] = soap::ccf_plan(c, c->ccf_nl, A + tab_off[u]);
   }
   std::vector<soap::ApplyBatchGroup> ag(n_groups);
   for (int g = 0; g < n_groups; ++g) {

@@ -221,6 +221,19 @@ bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, 
   const double amin = ed[0].x, amax = ed[nv - 1].y;
   auto span_lo = [&](int l) { return (int)std::floor(ln[l].x + amin); };
   auto span_end = [&](int l) { return (int)std::floor(ln[l].x + amax) + npx; };
+  // lines whose reads all fall outside the spectrum add exactly zero to
+  // every velocity (their staged pixels are zeros): they are left out of the
+  // tables (one is kept when none reaches the spectrum, so that there is a
+  // line block)
+  {
+    int kept = 0;
+    for (int l = 0; l < nl; ++l)
+      if (span_end(l) > 0 && span_lo(l) < (int64_t)c->P) ln[kept++] = ln[l];
+    if (kept == 0) kept = 1;
+    nl = kept;
+    ln.resize(nl);
+  }
+  c->ccf_nl = nl;
   int widest = 0;
   for (int l = 0; l < nl; ++l) widest = std::max(widest, span_end(l) - span_lo(l));
   if (widest > CCF_STG_MAX) {

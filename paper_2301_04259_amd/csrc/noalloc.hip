@@ -78,7 +78,7 @@ SOAP_API soap_status soap_ccf_rv_noalloc(soap_ctx* c, const void* flux, int64_t 
     }
     base = d.ptr;
   }
-  const int nl = (int)c->mask_lnl.size();
+  const int nl = c->ccf_nl;  // the lines in the tables (those that reach the spectrum)
   const size_t rows = (size_t)n_spec * c->mask_nv;
   const size_t part_bytes = c->esize * rows * soap::ccf_line_blocks(nl);
   const size_t ccf_bytes = ccf_out ? 0 : sizeof(double) * rows;

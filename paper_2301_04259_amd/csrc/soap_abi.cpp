@@ -952,7 +952,7 @@ SOAP_API soap_status soap_ccf_rv(soap_ctx* c, const void* flux, int32_t flux_on_
     const soap_status ms = soap::ctx_set_mask(c, mask);
     if (ms != SOAP_OK) return ms;
   }
-  const int nl = (int)mask->n_lines;
+  const int nl = c->ccf_nl;  // the lines in the tables
 
   const void* dflux = flux;
   const size_t in_bytes = (size_t)n_spec * c->P * c->esize;

@@ -226,6 +226,7 @@ struct soap_ctx {
   size_t ccf_off_edges = 0, ccf_off_batch = 0, ccf_off_bfirst = 0;
   int ccf_nbatch = 0, ccf_npx = 2, ccf_stg = 256;
   size_t mask_blob_bytes = 0;  // bytes of the mask's tables in ws_mask
+  int ccf_nl = 0;              // mask lines in the tables (those that reach the spectrum)
   bool mask_valid = false;
 };
 
