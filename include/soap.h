@@ -435,8 +435,9 @@ soap_status soap_batch_create(soap_ctx* const* ctxs, int32_t n_cfg, const soap_r
  * mask tables); ccf (may be NULL, or hold NULLs) device arrays
  * [phases of i][n_v] double; rv (may be NULL, or hold NULLs) device arrays of
  * soap_rv per phase.  The CCF and fit of configuration i read flux[i] after
- * its shift-and-sum; every row equals soap_ccf_rv on that flux, bit for
- * bit.  Mask errors are those of soap_ccf_rv.                                */
+ * its shift-and-sum (work-list launches over every configuration sharing a
+ * mask layout); every row equals soap_ccf_rv on that flux, bit for bit.
+ * Mask errors are those of soap_ccf_rv.                                      */
 soap_status soap_batch_create_rv(soap_ctx* const* ctxs, int32_t n_cfg, const soap_region* regions,
                                  const int32_t* region_offsets, const double* phases, const int32_t* phase_offsets,
                                  int32_t effect, void* const* flux, const soap_mask* mask, double* const* ccf,

@@ -42,7 +42,6 @@ struct soap_batch {
   hipStream_t origin = nullptr;                // capture origin (owned)
   hipStream_t branch[kBranches] = {};          // owned
   hipEvent_t fork = nullptr, join[kBranches] = {};
-  hipEvent_t fork2 = nullptr, join2[kBranches] = {};  // around the CCF stage
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* arena = nullptr;
@@ -58,12 +57,10 @@ void destroy_batch(soap_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (int i = 0; i < kBranches; ++i) {
-    if (b->join2[i]) (void)hipEventDestroy(b->join2[i]);
     if (b->join[i]) (void)hipEventDestroy(b->join[i]);
     if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
   }
   if (b->fork) (void)hipEventDestroy(b->fork);
-  if (b->fork2) (void)hipEventDestroy(b->fork2);
   if (b->origin) (void)hipStreamDestroy(b->origin);
   if (b->arena) (void)soap::dev_free(b->arena);
   delete b;
@@ -243,6 +240,8 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
   std::vector<size_t> tab_off;           // their table copies
   std::vector<int> ucfg(n_cfg, -1);      // configuration -> distinct context
   std::vector<size_t> part_off(n_cfg, 0), ccf_off(n_cfg, 0);
+  std::vector<std::vector<int>> ccf_groups;  // configurations per CCF layout
+  std::vector<size_t> ccf_group_off;
   if (mask) {
     for (int i = 0; i < n_cfg; ++i) {
       soap_ctx* c = cp[i].c;
@@ -263,6 +262,27 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
         ccf_off[i] = arena;
         arena += al(sizeof(double) * (size_t)cp[i].pl.n_ph * c->mask_nv);
       }
+    }
+    // one work-list CCF + fit launch pair per mask layout (float type,
+    // pixels per hole, stage width)
+    std::vector<soap::CcfPlan> shape(uctx.size());
+    for (size_t u = 0; u < uctx.size(); ++u) shape[u] = soap::ccf_plan(uctx[u], uctx[u]->ccf_nl, nullptr);
+    for (int i = 0; i < n_cfg; ++i) {
+      const soap::CcfPlan& q = shape[ucfg[i]];
+      size_t g = 0;
+      while (g < ccf_groups.size() && !soap::ccf_same_layout(shape[ucfg[ccf_groups[g][0]]], q)) ++g;
+      if (g == ccf_groups.size()) ccf_groups.emplace_back();
+      ccf_groups[g].push_back(i);
+    }
+    for (const auto& grp : ccf_groups) {
+      std::vector<soap::CcfPlan> pl;
+      std::vector<int64_t> ns;
+      for (int i : grp) {
+        pl.push_back(shape[ucfg[i]]);
+        ns.push_back(cp[i].pl.n_ph);
+      }
+      ccf_group_off.push_back(arena);
+      arena += al(soap::ccf_batch_bytes(pl.data(), ns.data(), (int)grp.size()));
     }
   }
 
@@ -315,6 +335,24 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     if ((e = hipMemcpy(A + tab_off[u], c->ws_mask.ptr, c->mask_blob_bytes, hipMemcpyDeviceToDevice)) != hipSuccess)
       return fail("copying the mask tables", e);
     cplan[u] = soap::ccf_plan(c, c->ccf_nl, A + tab_off[u]);
+  }
+  std::vector<soap::CcfBatch> cbat(ccf_groups.size());
+  for (size_t g = 0; g < ccf_groups.size(); ++g) {
+    std::vector<soap::CcfPlan> pl;
+    std::vector<soap::CcfBatchSet> sets;
+    for (int i : ccf_groups[g]) {
+      pl.push_back(cplan[ucfg[i]]);
+      soap::CcfBatchSet cs{};
+      cs.flux = cp[i].flux;
+      cs.part = A + part_off[i];
+      cs.ccf = (ccf && ccf[i]) ? ccf[i] : reinterpret_cast<double*>(A + ccf_off[i]);
+      cs.rv = rv ? rv[i] : nullptr;
+      cs.n_spec = cp[i].pl.n_ph;
+      sets.push_back(cs);
+    }
+    if ((e = soap::ccf_batch_upload(pl.data(), sets.data(), (int)sets.size(), A + ccf_group_off[g], &cbat[g])) !=
+        hipSuccess)
+      return fail("uploading the CCF work lists", e);
   }
   std::vector<soap::ApplyBatchGroup> ag(n_groups);
   for (int g = 0; g < n_groups; ++g) {
@@ -389,25 +427,9 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
         if (ce == hipSuccess) ce = hipStreamWaitEvent(org, b->join[k], 0);
       }
     for (int g = 0; g < n_groups && ce == hipSuccess; ++g) ce = soap::apply_batch_launch(ag[g], org);
-    if (mask && ce == hipSuccess) {
-      // CCF and fit of every configuration's spectra
-      if (fork_join) {
-        ce = hipEventRecord(b->fork2, org);
-        for (int k = 0; k < kBranches && ce == hipSuccess; ++k) ce = hipStreamWaitEvent(b->branch[k], b->fork2, 0);
-      }
-      for (int i = 0; i < n_cfg && ce == hipSuccess; ++i) {
-        const soap::CcfPlan& q = cplan[ucfg[i]];
-        double* dccf = (ccf && ccf[i]) ? ccf[i] : reinterpret_cast<double*>(A + ccf_off[i]);
-        ce = soap::launch_ccf_p(q, lane(i), cp[i].flux, cp[i].pl.n_ph, A + part_off[i]);
-        if (ce == hipSuccess)
-          ce = soap::launch_ccf_fit_p(q, lane(i), A + part_off[i], cp[i].pl.n_ph, dccf, rv ? rv[i] : nullptr);
-      }
-      if (fork_join)
-        for (int k = 0; k < kBranches && ce == hipSuccess; ++k) {
-          ce = hipEventRecord(b->join2[k], b->branch[k]);
-          if (ce == hipSuccess) ce = hipStreamWaitEvent(org, b->join2[k], 0);
-        }
-    }
+    // CCF and fit of every configuration's spectra: one work-list pair per
+    // mask layout
+    for (size_t g = 0; g < cbat.size() && ce == hipSuccess; ++g) ce = soap::ccf_batch_launch(cbat[g], org);
     return ce;
   };
   if (direct) {
@@ -425,11 +447,6 @@ static soap_status create_impl(soap_ctx* const* ctxs, int32_t n_cfg, const soap_
     if ((e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming)) != hipSuccess) return fail("event", e);
   }
   if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) return fail("event", e);
-  if (mask) {
-    if ((e = hipEventCreateWithFlags(&b->fork2, hipEventDisableTiming)) != hipSuccess) return fail("event", e);
-    for (int k = 0; k < kBranches; ++k)
-      if ((e = hipEventCreateWithFlags(&b->join2[k], hipEventDisableTiming)) != hipSuccess) return fail("event", e);
-  }
   if ((e = hipStreamBeginCapture(b->origin, hipStreamCaptureModeRelaxed)) != hipSuccess) return fail("capture", e);
   const hipError_t ce = enqueue(b->origin, true);
   e = hipStreamEndCapture(b->origin, &b->graph);

@@ -77,13 +77,12 @@ __device__ __forceinline__ void get4t(T* x, const T* p) {
 // FMAs in the flux precision: a block's partial CCF sums at most 32 lines x
 // a few pixels in FP32 for float spectra, and the partials of the line blocks
 // are added in double by the fit kernel.
+// Line block lb, spectrum block sb.
 template <typename T, int A, int NPX, int STG>
-__global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, const T* __restrict__ F,
-                                                     const double2* __restrict__ lines,
-                                                     const double2* __restrict__ edges,
-                                                     const int4* __restrict__ batches,
-                                                     const int* __restrict__ bfirst, int n_v,
-                                                     T* __restrict__ part) {
+__device__ __forceinline__ void ccf_block(int P, int64_t n_spec, const T* __restrict__ F,
+                                          const double2* __restrict__ lines, const double2* __restrict__ edges,
+                                          const int4* __restrict__ batches, const int* __restrict__ bfirst,
+                                          int n_v, T* __restrict__ part, int lb, int sb) {
   constexpr int SB = CCF_SB;
   constexpr int R = (STG + CCF_THREADS - 1) / CCF_THREADS;  // staged pixels per thread
   static_assert(SB % 4 == 0, "16-byte stage rows");
@@ -91,8 +90,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
   __shared__ double2 s_line[CCF_LB];
   __shared__ double2 s_ed[A * CCF_THREADS];
   const int tid = threadIdx.x;
-  const int lb = blockIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.y * SB;
+  const int64_t s0 = (int64_t)sb * SB;
   const int ns = (int)min<int64_t>(SB, n_spec - s0);
   const int b0 = bfirst[lb], b1 = bfirst[lb + 1];
   const int l0 = batches[b0].y;
@@ -193,6 +191,30 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, cons
     for (int s = 0; s < SB; ++s)
       if (s < ns) part[((int64_t)lb * n_spec + s0 + s) * n_v + k] = acc[a][s];
   }
+}
+
+template <typename T, int A, int NPX, int STG>
+__global__ void __launch_bounds__(CCF_THREADS) k_ccf(int P, int64_t n_spec, const T* __restrict__ F,
+                                                     const double2* __restrict__ lines,
+                                                     const double2* __restrict__ edges,
+                                                     const int4* __restrict__ batches,
+                                                     const int* __restrict__ bfirst, int n_v,
+                                                     T* __restrict__ part) {
+  ccf_block<T, A, NPX, STG>(P, n_spec, F, lines, edges, batches, bfirst, n_v, part, blockIdx.x, blockIdx.y);
+}
+
+// Work-list form over many spectra sets with one mask layout: blk[b] =
+// (set, line block, spectrum block).
+template <typename T, int A, int NPX, int STG>
+__global__ void __launch_bounds__(CCF_THREADS) k_ccf_batch(const CcfBatchSet* __restrict__ sets,
+                                                           const int4* __restrict__ blk, int n_v) {
+  const int4 t = blk[blockIdx.x];
+  const CcfBatchSet c = sets[t.x];
+  const unsigned char* tb = c.tables;
+  ccf_block<T, A, NPX, STG>(c.P, c.n_spec, static_cast<const T*>(c.flux), reinterpret_cast<const double2*>(tb),
+                            reinterpret_cast<const double2*>(tb + c.off_edges),
+                            reinterpret_cast<const int4*>(tb + c.off_batch),
+                            reinterpret_cast<const int*>(tb + c.off_bfirst), n_v, static_cast<T*>(c.part), t.y, t.z);
 }
 
 // Host tables of one mask (section 4.1's CCF with the holes of Eq. 6),
@@ -591,12 +613,10 @@ __device__ soap_rv fit_wave(const double (&y)[NPT], int n_v, double v0, double d
 // (status 0); otherwise the fit failed (status 3).  A CCF with a non-finite
 // sample or no depth is degenerate (status 2).
 template <int NPT, typename PT>
-__global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n_spec, int n_v, double v0,
-                                                             double dv, const PT* __restrict__ part,
-                                                             double* __restrict__ ccf, int fit,
-                                                             soap_rv* __restrict__ out) {
+__device__ __forceinline__ void fit_block(int n_lb, int64_t n_spec, int n_v, double v0, double dv,
+                                          const PT* __restrict__ part, double* __restrict__ ccf, int fit,
+                                          soap_rv* __restrict__ out, int64_t s) {
   __shared__ double s_sum[CCF_FIN_THREADS / 64][NPT * 64];
-  const int64_t s = blockIdx.x;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   constexpr int NW = CCF_FIN_THREADS / 64;
@@ -651,6 +671,24 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
   double p[4], S[20];
   const soap_rv res = fit_wave(y, n_v, v0, dv, p, S);
   if (lane == 0) out[s] = res;
+}
+
+template <int NPT, typename PT>
+__global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n_spec, int n_v, double v0,
+                                                             double dv, const PT* __restrict__ part,
+                                                             double* __restrict__ ccf, int fit,
+                                                             soap_rv* __restrict__ out) {
+  fit_block<NPT, PT>(n_lb, n_spec, n_v, v0, dv, part, ccf, fit, out, blockIdx.x);
+}
+
+// Work-list form: blk[b] = (set, spectrum).
+template <int NPT, typename PT>
+__global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit_batch(const CcfBatchSet* __restrict__ sets,
+                                                                   const int2* __restrict__ blk, int n_v, double v0,
+                                                                   double dv) {
+  const int2 t = blk[blockIdx.x];
+  const CcfBatchSet c = sets[t.x];
+  fit_block<NPT, PT>(c.nlb, c.n_spec, n_v, v0, dv, static_cast<const PT*>(c.part), c.ccf, c.rv ? 1 : 0, c.rv, t.y);
 }
 
 template <typename T, int A, int NPX, int STG>
@@ -748,6 +786,120 @@ hipError_t launch_ccf_fit_p(const CcfPlan& q, hipStream_t st, const void* d_part
 hipError_t launch_ccf_fit(soap_ctx* c, int n_lines, const void* d_part, int64_t n_spec, double* d_ccf,
                           soap_rv* d_rv) {
   return launch_ccf_fit_p(ccf_plan(c, n_lines, c->ws_mask.ptr), c->stream, d_part, n_spec, d_ccf, d_rv);
+}
+
+// ---- work-list CCF + fit over many spectra sets ------------------------------
+
+bool ccf_same_layout(const CcfPlan& a, const CcfPlan& b) {
+  return a.fp32 == b.fp32 && a.npx == b.npx && (a.stg <= 256) == (b.stg <= 256) && a.nv == b.nv && a.v0 == b.v0 &&
+         a.dv == b.dv;
+}
+
+namespace {
+
+size_t al256c(size_t b) { return 256 * ((b + 255) / 256); }
+
+template <typename T, int A, int NPX, int STG>
+void launch_ccf_batch_a(const CcfBatch& cb, hipStream_t st) {
+  hipLaunchKernelGGL((k_ccf_batch<T, A, NPX, STG>), dim3((unsigned)cb.n_ccf_blocks), dim3(CCF_THREADS), 0, st,
+                     cb.sets, cb.ccf_blk, cb.shape.nv);
+}
+
+template <typename T, int NPX, int STG>
+void launch_ccf_batch_n(const CcfBatch& cb, hipStream_t st) {
+  if (cb.shape.nv <= CCF_THREADS) launch_ccf_batch_a<T, 1, NPX, STG>(cb, st);
+  else if (cb.shape.nv <= 2 * CCF_THREADS) launch_ccf_batch_a<T, 2, NPX, STG>(cb, st);
+  else launch_ccf_batch_a<T, 4, NPX, STG>(cb, st);
+}
+
+template <typename T, int STG>
+void launch_ccf_batch_s(const CcfBatch& cb, hipStream_t st) {
+  switch (cb.shape.npx) {
+    case 2: launch_ccf_batch_n<T, 2, STG>(cb, st); break;
+    case 3: launch_ccf_batch_n<T, 3, STG>(cb, st); break;
+    case 5: launch_ccf_batch_n<T, 5, STG>(cb, st); break;
+    default: launch_ccf_batch_n<T, 10, STG>(cb, st); break;
+  }
+}
+
+template <typename T>
+void launch_ccf_batch_t(const CcfBatch& cb, hipStream_t st) {
+  if (cb.shape.stg <= 256) launch_ccf_batch_s<T, 256>(cb, st);
+  else launch_ccf_batch_s<T, CCF_STG_MAX>(cb, st);
+}
+
+template <typename PT>
+hipError_t launch_fit_batch_pt(const CcfBatch& cb, hipStream_t st) {
+  const int npt = (cb.shape.nv + 63) / 64;
+#define FITB_CASE(N)                                                                                           \
+  case N:                                                                                                      \
+    hipLaunchKernelGGL((k_ccf_fit_batch<N, PT>), dim3((unsigned)cb.n_fit_blocks), dim3(CCF_FIN_THREADS), 0, st, \
+                       cb.sets, cb.fit_blk, cb.shape.nv, cb.shape.v0, cb.shape.dv);                            \
+    break;
+  switch (npt) {
+    FITB_CASE(1) FITB_CASE(2) FITB_CASE(3) FITB_CASE(4) FITB_CASE(5) FITB_CASE(6)
+    FITB_CASE(7) FITB_CASE(8) FITB_CASE(9) FITB_CASE(10) FITB_CASE(11) FITB_CASE(12)
+    default: return hipErrorInvalidValue;
+  }
+#undef FITB_CASE
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t ccf_batch_bytes(const CcfPlan* plans, const int64_t* n_spec, int n) {
+  size_t ccf_blocks = 0, fit_blocks = 0;
+  for (int i = 0; i < n; ++i) {
+    ccf_blocks += (size_t)ccf_line_blocks(plans[i].n_lines) * (size_t)((n_spec[i] + CCF_SB - 1) / CCF_SB);
+    fit_blocks += (size_t)n_spec[i];
+  }
+  return al256c(sizeof(CcfBatchSet) * n) + al256c(sizeof(int4) * ccf_blocks) + al256c(sizeof(int2) * fit_blocks);
+}
+
+hipError_t ccf_batch_upload(const CcfPlan* plans, const CcfBatchSet* sets, int n, void* d_buf, CcfBatch* cb) {
+  if (n < 1) return hipErrorInvalidValue;
+  std::vector<CcfBatchSet> hs(sets, sets + n);
+  std::vector<int4> cblk;
+  std::vector<int2> fblk;
+  for (int i = 0; i < n; ++i) {
+    if (!ccf_same_layout(plans[i], plans[0]) || sets[i].n_spec < 1 || sets[i].n_spec > (int64_t(1) << 24))
+      return hipErrorInvalidValue;
+    const CcfPlan& q = plans[i];
+    CcfBatchSet& h = hs[i];
+    h.P = (int)q.P;
+    h.nlb = ccf_line_blocks(q.n_lines);
+    h.tables = q.tables;
+    h.off_edges = q.off_edges;
+    h.off_batch = q.off_batch;
+    h.off_bfirst = q.off_bfirst;
+    const int nsb = (int)((h.n_spec + CCF_SB - 1) / CCF_SB);
+    for (int lb = 0; lb < h.nlb; ++lb)
+      for (int sb = 0; sb < nsb; ++sb) cblk.push_back(make_int4(i, lb, sb, 0));
+    for (int64_t sp = 0; sp < h.n_spec; ++sp) fblk.push_back(make_int2(i, (int)sp));
+  }
+  unsigned char* base = static_cast<unsigned char*>(d_buf);
+  cb->shape = plans[0];
+  cb->n_sets = n;
+  cb->n_ccf_blocks = (int)cblk.size();
+  cb->n_fit_blocks = (int)fblk.size();
+  cb->sets = reinterpret_cast<CcfBatchSet*>(base);
+  size_t used = al256c(sizeof(CcfBatchSet) * n);
+  cb->ccf_blk = reinterpret_cast<int4*>(base + used);
+  used += al256c(sizeof(int4) * cblk.size());
+  cb->fit_blk = reinterpret_cast<int2*>(base + used);
+  hipError_t e = hipMemcpy(cb->sets, hs.data(), sizeof(CcfBatchSet) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(cb->ccf_blk, cblk.data(), sizeof(int4) * cblk.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(cb->fit_blk, fblk.data(), sizeof(int2) * fblk.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+hipError_t ccf_batch_launch(const CcfBatch& cb, hipStream_t st) {
+  if (cb.n_ccf_blocks <= 0) return hipSuccess;
+  if (cb.shape.fp32) launch_ccf_batch_t<float>(cb, st);
+  else launch_ccf_batch_t<double>(cb, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return cb.shape.fp32 ? launch_fit_batch_pt<float>(cb, st) : launch_fit_batch_pt<double>(cb, st);
 }
 
 // ccf[i][v] = base[v] + sum_k coef[i][k] basis[k][v] (double, increasing k):

@@ -382,6 +382,33 @@ struct CcfPlan {
   int64_t P = 0;
 };
 CcfPlan ccf_plan(const soap_ctx* c, int n_lines, const void* tables);
+// One spectra set of a work-list CCF + fit launch (every set of one launch
+// shares the mask layout: velocities, pixels per hole, stage width, float
+// type).
+struct CcfBatchSet {
+  const void* flux;
+  void* part;        // [nlb][n_spec][n_v] partials
+  double* ccf;       // [n_spec][n_v]
+  soap_rv* rv;       // [n_spec], or NULL (sums only)
+  int64_t n_spec;
+  int P, nlb;
+  const unsigned char* tables;
+  size_t off_edges, off_batch, off_bfirst;
+};
+struct CcfBatch {
+  CcfPlan shape;               // a plan with the shared layout
+  int n_sets = 0, n_ccf_blocks = 0, n_fit_blocks = 0;
+  CcfBatchSet* sets = nullptr;  // device
+  int4* ccf_blk = nullptr;      // device (set, line block, spectrum block)
+  int2* fit_blk = nullptr;      // device (set, spectrum)
+};
+// same layout: the sets of one CcfBatch must agree on these
+bool ccf_same_layout(const CcfPlan& a, const CcfPlan& b);
+size_t ccf_batch_bytes(const CcfPlan* plans, const int64_t* n_spec, int n);
+// sets i of plans[i] (tables, lines) and the given buffers; d_buf of
+// ccf_batch_bytes bytes
+hipError_t ccf_batch_upload(const CcfPlan* plans, const CcfBatchSet* sets, int n, void* d_buf, CcfBatch* cb);
+hipError_t ccf_batch_launch(const CcfBatch& cb, hipStream_t st);
 soap_status ctx_set_mask(soap_ctx* c, const soap_mask* mask);
 hipError_t launch_ccf_p(const CcfPlan& q, hipStream_t st, const void* d_flux, int64_t n_spec, void* d_part);
 hipError_t launch_ccf_fit_p(const CcfPlan& q, hipStream_t st, const void* d_part, int64_t n_spec, double* d_ccf,
