@@ -357,7 +357,9 @@ soap_status soap_ccf_linear_rv(soap_ctx* ctx, const float* coef, int64_t n, int3
  * fallback); basis[k][n_v]
  * double; all on the context's mask grid (which must exist); outputs device
  * arrays (rv_out and err_kms may be NULL).  n 1 .. 1<<24, n_ens 2 .. 16.
- * Enqueues only.                                                             */
+ * Enqueues only, after growing a context workspace (16 n_v + 4 bytes per
+ * sample, waiting for the stream) when a call has more samples than any
+ * before.                                                                    */
 soap_status soap_surrogate_rv(soap_ctx* ctx, const float* coef, const float* members, int64_t n, int32_t n_ens,
                               int32_t k, const double* base, const int32_t* base_index, int32_t n_base,
                               const double* basis, double calib, double threshold_kms, soap_rv* rv_out,

@@ -937,40 +937,36 @@ constexpr int sg_rows_in_flight() {
   return NPT <= 3 ? 8 : (NPT <= 6 ? 4 : 2);
 }
 
-// Surrogate RVs and their gate, SS = sg_samples consecutive samples per wave
-// (64-thread blocks), each basis row loaded once for all of them:
-//   1. CCF of the ensemble-mean prediction by linearity, base (the sample's
-//      row base[base_idx[i]] when base_idx is given) + sum_k
-//      coef[i][k] basis[k] (double, increasing k: the same sums as
-//      k_ccf_linear), and its Gaussian fit (fit_wave);
-//   2. first-order RV change of each member: the fitted parameters move by
-//      dp = H^-1 J^T dy for a CCF change dy (H the Hessian of chi^2 / 2 at
-//      the fit, J the model Jacobian), so dRV = g . dy with
-//      g = J H^-1 e_mu, and dy_e = sum_k (y_e,k - coef_k) basis[k], i.e.
-//      dRV_e = sum_k h_k (y_e,k - coef_k) with h = basis g;
-//   3. err = calib x sample standard deviation of dRV_e over the members;
-//      fallback when err is not below thr or the fit did not converge.
-// Every sum of one sample has the order it would have alone.  EB bounds the
-// member count (registers for the members' RV changes).
-template <int NPT, int EB>
-__global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, double v0, double dv,
-                                              const float* __restrict__ coef, const float* __restrict__ members,
-                                              const double* __restrict__ base, const int* __restrict__ base_idx,
-                                              int n_base, const double* __restrict__ basis, double calib,
-                                              double thr, soap_rv* __restrict__ out,
-                                              double* __restrict__ rv_kms, double* __restrict__ err_kms,
-                                              int* __restrict__ fallback) {
+// Surrogate RVs and their gate in three launches (so that each keeps few
+// registers and many waves in flight):
+//   k_sg_lin: CCF of the ensemble-mean prediction by linearity, base (the
+//     sample's row base[base_idx[i]] when base_idx is given) + sum_k
+//     coef[i][k] basis[k] (double, increasing k: the same sums as
+//     k_ccf_linear), SS = sg_samples samples per wave sharing every basis
+//     row loaded;
+//   k_sg_fit: its Gaussian fit (fit_wave), one wave per sample, and the RV
+//     sensitivity g = J H^-1 e_mu at the fit: the fitted parameters move by
+//     dp = H^-1 J^T dy for a CCF change dy (H the Hessian of chi^2 / 2 at the
+//     fit, J the model Jacobian), so dRV = g . dy;
+//   k_sg_spread: each member's RV change dRV_e = sum_k h_k (y_e,k - coef_k)
+//     with h = basis g (dy_e = sum_k (y_e,k - coef_k) basis[k]), SS samples
+//     per wave; err = calib x the sample standard deviation of the dRV_e;
+//     fallback when err is not below thr or the fit did not converge.
+// Every sum of a sample keeps one fixed order.
+template <int NPT>
+__global__ void __launch_bounds__(64) k_sg_lin(int64_t n, int k, int n_v, const float* __restrict__ coef,
+                                               const double* __restrict__ base, const int* __restrict__ base_idx,
+                                               int n_base, const double* __restrict__ basis,
+                                               double* __restrict__ Y, int* __restrict__ flag) {
   constexpr int SS = sg_samples<NPT>();
   constexpr int JU = sg_rows_in_flight<NPT>();
   __shared__ double s_c[SS][64];
-  __shared__ double s_g[SS][NPT * 64];
   const int lane = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.x * SS;
-  // Loads are unconditional, with indices clamped into the rows (the lanes
-  // past the grid, and the samples past n, compute values that are never
-  // used): a load under a branch is waited for before the next one is
-  // issued.  A sample whose star row does not exist reads row 0 and is
-  // reported without a surrogate RV.
+  // Loads are unconditional, with indices clamped into the rows (lanes past
+  // the grid and samples past n compute values that are never stored): a
+  // load under a branch is waited for before the next one is issued.  A
+  // sample whose star row does not exist reads row 0 and is flagged.
   int64_t ii[SS];
   bool row_ok[SS];
   const double* bs[SS];
@@ -1013,45 +1009,90 @@ __global__ void __launch_bounds__(64) k_sg_rv(int64_t n, int k, int E, int n_v, 
         }
     }
   }
-  bool bad[SS];
 #pragma unroll
   for (int s = 0; s < SS; ++s) {
-    double p[4], S[20];
-    soap_rv res = fit_wave(y[s], n_v, v0, dv, p, S);
-    bad[s] = res.status != 0 || !row_ok[s];
-    if (lane == 0 && i0 + s < n) {  // the fit's record and RV now; the gate after the spreads
-      if (!row_ok[s]) {
-        res = soap_rv{};
-        res.status = 2;
-      }
-      if (out) out[i0 + s] = res;
-      rv_kms[i0 + s] = row_ok[s] ? res.rv_kms : 0.0;
-    }
-    // g = J H^-1 e_mu at the fit (full Hessian; J^T J where that is not
-    // positive definite); zero for a sample that has none
-    double z[4] = {0.0, 0.0, 0.0, 0.0};
-    if (!bad[s]) {
-      double Sz[20];
-#pragma unroll
-      for (int q = 0; q < 20; ++q) Sz[q] = S[q];
-      Sz[1] = 0.0;
-      Sz[2] = 0.0;
-      Sz[3] = -1.0;  // gf_solve solves A x = -S[1..4]
-      Sz[4] = 0.0;
-      if (!(gf_solve(Sz, true, 0.0, z) || gf_solve(Sz, false, 0.0, z))) bad[s] = true;
-    }
-    const double is = 1.0 / p[3];
-    const double is2 = is * is;
+    if (i0 + s >= n) break;
 #pragma unroll
     for (int t = 0; t < NPT; ++t) {
       const int v = lane + 64 * t;
-      if (v < n_v) {
-        const double d = v0 + dv * v - p[2];
-        const double zz = d * d * is2;
-        const double e = exp(-0.5 * zz);
-        const double ae = p[1] * e;
-        s_g[s][v] = bad[s] ? 0.0 : z[0] - e * z[1] - ae * d * is2 * z[2] - ae * zz * is * z[3];
-      }
+      if (v < n_v) Y[(i0 + s) * n_v + v] = y[s][t];
+    }
+    if (lane == 0) flag[i0 + s] = row_ok[s] ? 0 : 1;
+  }
+}
+
+// flag[i] on entry: 1 when the sample has no star row; on exit: 1 when it
+// has no surrogate RV (no row, or the fit or its sensitivity failed).
+template <int NPT>
+__global__ void __launch_bounds__(64) k_sg_fit(int64_t n, int n_v, double v0, double dv,
+                                               const double* __restrict__ Y, int* __restrict__ flag,
+                                               soap_rv* __restrict__ out, double* __restrict__ rv_kms,
+                                               double* __restrict__ G) {
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const bool row_ok = flag[i] == 0;
+  double y[NPT];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) y[t] = Y[i * n_v + min(lane + 64 * t, n_v - 1)];
+  double p[4], S[20];
+  soap_rv res = fit_wave(y, n_v, v0, dv, p, S);
+  bool bad = res.status != 0 || !row_ok;
+  double z[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!bad) {
+    // z = H^-1 e_mu (full Hessian; J^T J where that is not positive definite)
+    double Sz[20];
+#pragma unroll
+    for (int q = 0; q < 20; ++q) Sz[q] = S[q];
+    Sz[1] = 0.0;
+    Sz[2] = 0.0;
+    Sz[3] = -1.0;  // gf_solve solves A x = -S[1..4]
+    Sz[4] = 0.0;
+    if (!(gf_solve(Sz, true, 0.0, z) || gf_solve(Sz, false, 0.0, z))) bad = true;
+  }
+  const double is = 1.0 / p[3];
+  const double is2 = is * is;
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    const int v = lane + 64 * t;
+    if (v < n_v) {
+      const double d = v0 + dv * v - p[2];
+      const double zz = d * d * is2;
+      const double e = exp(-0.5 * zz);
+      const double ae = p[1] * e;
+      G[i * n_v + v] = bad ? 0.0 : z[0] - e * z[1] - ae * d * is2 * z[2] - ae * zz * is * z[3];
+    }
+  }
+  if (lane == 0) {
+    if (!row_ok) {
+      res = soap_rv{};
+      res.status = 2;
+    }
+    if (out) out[i] = res;
+    rv_kms[i] = row_ok ? res.rv_kms : 0.0;
+    flag[i] = bad ? 1 : 0;
+  }
+}
+
+template <int NPT, int EB>
+__global__ void __launch_bounds__(64) k_sg_spread(int64_t n, int k, int E, int n_v, const float* __restrict__ coef,
+                                                  const float* __restrict__ members,
+                                                  const double* __restrict__ basis, const double* __restrict__ G,
+                                                  const int* __restrict__ flag, double calib, double thr,
+                                                  double* __restrict__ err_kms, int* __restrict__ fallback) {
+  constexpr int SS = sg_samples<NPT>();
+  __shared__ double s_g[SS][NPT * 64];
+  const int lane = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * SS;
+  int64_t ii[SS];
+  bool bad[SS];
+#pragma unroll
+  for (int s = 0; s < SS; ++s) {
+    ii[s] = min(i0 + s, n - 1);
+    bad[s] = flag[ii[s]] != 0;
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+      const int v = lane + 64 * t;
+      if (v < n_v) s_g[s][v] = G[ii[s] * n_v + v];
     }
   }
   __syncthreads();
@@ -1131,21 +1172,23 @@ namespace {
 template <int NPT>
 void launch_sg_rv_n(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
                     const double* d_base, const int* d_base_idx, int n_base, const double* d_basis, double calib,
-                    double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err, int* d_fallback) {
-  const dim3 grid((unsigned)((n + sg_samples<NPT>() - 1) / sg_samples<NPT>())), block(64);
+                    double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err, int* d_fallback, double* Y,
+                    double* G, int* flag) {
+  const dim3 grid_s((unsigned)((n + sg_samples<NPT>() - 1) / sg_samples<NPT>())), block(64);
   const int nb = d_base_idx ? n_base : 1;
+  hipLaunchKernelGGL((k_sg_lin<NPT>), grid_s, block, 0, c->stream, n, k, c->mask_nv, d_coef, d_base, d_base_idx, nb,
+                     d_basis, Y, flag);
+  hipLaunchKernelGGL((k_sg_fit<NPT>), dim3((unsigned)n), block, 0, c->stream, n, c->mask_nv, c->mask_v0,
+                     c->mask_dv, Y, flag, d_rv, d_rv_kms, G);
   if (E <= 4)
-    hipLaunchKernelGGL((k_sg_rv<NPT, 4>), grid, block, 0, c->stream, n, k, E, c->mask_nv, c->mask_v0, c->mask_dv,
-                       d_coef, d_members, d_base, d_base_idx, nb, d_basis, calib, thr, d_rv, d_rv_kms, d_err,
-                       d_fallback);
+    hipLaunchKernelGGL((k_sg_spread<NPT, 4>), grid_s, block, 0, c->stream, n, k, E, c->mask_nv, d_coef, d_members,
+                       d_basis, G, flag, calib, thr, d_err, d_fallback);
   else if (E <= 8)
-    hipLaunchKernelGGL((k_sg_rv<NPT, 8>), grid, block, 0, c->stream, n, k, E, c->mask_nv, c->mask_v0, c->mask_dv,
-                       d_coef, d_members, d_base, d_base_idx, nb, d_basis, calib, thr, d_rv, d_rv_kms, d_err,
-                       d_fallback);
+    hipLaunchKernelGGL((k_sg_spread<NPT, 8>), grid_s, block, 0, c->stream, n, k, E, c->mask_nv, d_coef, d_members,
+                       d_basis, G, flag, calib, thr, d_err, d_fallback);
   else
-    hipLaunchKernelGGL((k_sg_rv<NPT, SG_MAX_ENS>), grid, block, 0, c->stream, n, k, E, c->mask_nv, c->mask_v0,
-                       c->mask_dv, d_coef, d_members, d_base, d_base_idx, nb, d_basis, calib, thr, d_rv, d_rv_kms,
-                       d_err, d_fallback);
+    hipLaunchKernelGGL((k_sg_spread<NPT, SG_MAX_ENS>), grid_s, block, 0, c->stream, n, k, E, c->mask_nv, d_coef,
+                       d_members, d_basis, G, flag, calib, thr, d_err, d_fallback);
 }
 
 }  // namespace
@@ -1153,13 +1196,16 @@ void launch_sg_rv_n(soap_ctx* c, const float* d_coef, const float* d_members, in
 hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
                         const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
                         double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
-                        int* d_fallback) {
+                        int* d_fallback, void* d_work) {
   if (E < 2 || E > SG_MAX_ENS) return hipErrorInvalidValue;
   const int npt = (c->mask_nv + 63) / 64;
+  double* Y = static_cast<double*>(d_work);
+  double* G = Y + (size_t)n * c->mask_nv;
+  int* flag = reinterpret_cast<int*>(G + (size_t)n * c->mask_nv);
 #define SG_CASE(N)                                                                                              \
   case N:                                                                                                       \
     launch_sg_rv_n<N>(c, d_coef, d_members, n, E, k, d_base, d_base_idx, n_base, d_basis, calib, thr, d_rv,     \
-                      d_rv_kms, d_err, d_fallback);                                                             \
+                      d_rv_kms, d_err, d_fallback, Y, G, flag);                                                 \
     break;
   switch (npt) {
     SG_CASE(1) SG_CASE(2) SG_CASE(3) SG_CASE(4) SG_CASE(5) SG_CASE(6)
@@ -1168,6 +1214,10 @@ hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members
   }
 #undef SG_CASE
   return hipGetLastError();
+}
+
+size_t sg_rv_work_bytes(const soap_ctx* c, int64_t n) {
+  return sizeof(double) * 2 * (size_t)n * c->mask_nv + sizeof(int) * (size_t)n;
 }
 
 hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, int k, const double* d_base,

@@ -153,7 +153,7 @@ void destroy_ctx(soap_ctx* c) {
   for (void* p : bufs)
     if (p) (void)soap::dev_free(p);
   soap::Workspace* ws[] = {&c->ws_flux, &c->ws_ccf, &c->ws_ccfout, &c->ws_rv, &c->ws_mask, &c->ws_specin,
-                           &c->ws_lsf};
+                           &c->ws_lsf, &c->ws_sg};
   for (auto* w : ws) free_ws(*w);
   for (auto& S : c->prep) {
     soap::Workspace* pw[] = {&S.par, &S.Kfx, &S.K, &S.mask64, &S.vg, &S.nvg};
@@ -1037,8 +1037,14 @@ SOAP_API soap_status soap_surrogate_rv(soap_ctx* c, const float* coef, const flo
     return SOAP_ERR_STATE;
   }
   ARG_CHECK(!base_index || n_base >= 1, "n_base must be >= 1 with base_index");
+  const size_t wb = soap::sg_rv_work_bytes(c, n);
+  if (c->ws_sg.bytes < wb) {
+    // the workspace is replaced only with the stream idle
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(grow(c->ws_sg, wb));
+  }
   HIP_TRY(soap::launch_sg_rv(c, coef, members, n, n_ens, k, base, base_index, n_base, basis, calib, threshold_kms,
-                             rv_out, rv_kms, err_kms, fallback));
+                             rv_out, rv_kms, err_kms, fallback, c->ws_sg.ptr));
   return SOAP_OK;
 }
 

@@ -214,6 +214,7 @@ struct soap_ctx {
   double lsf_resolution = 0.0;
   soap::LsfPlan lsf;
   soap::Workspace ws_lsf;  // synthesis output before the lowering
+  soap::Workspace ws_sg;   // surrogate RVs: mean-prediction CCFs, sensitivities, flags
   int last_phases = 0, last_effect = 0, last_vg_cap = 0, last_paired = 0, last_pc = 0;
 
   // cached mask
@@ -422,7 +423,9 @@ hipError_t launch_ccf_linear_fit(soap_ctx* c, const float* d_coef, int64_t n, in
 hipError_t launch_sg_rv(soap_ctx* c, const float* d_coef, const float* d_members, int64_t n, int E, int k,
                         const double* d_base, const int* d_base_idx, int n_base, const double* d_basis,
                         double calib, double thr, soap_rv* d_rv, double* d_rv_kms, double* d_err,
-                        int* d_fallback);
+                        int* d_fallback, void* d_work);
+// device workspace of launch_sg_rv for n samples
+size_t sg_rv_work_bytes(const soap_ctx* c, int64_t n);
 
 // resolution lowering: kernel weights of a resolving power on the grid
 // (false when the kernel would be wider than LSF_KMAX pixels each side), the
