@@ -347,15 +347,16 @@ def _surrogate_timing(S, np, torch, model, stars, mask, test, calib_alpha0=None)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / reps, out
 
-    t_plain, _ = timed(lambda: S.plain_rv(stars, test, mask, idx), 5)
-    t_kern, _ = timed(lambda: model.surrogate_rv(x, r, bufs), 5)
-    t_gated, (rv_s, fb, _) = timed(lambda: model.rv(test, idx, bufs), 5)
+    # 20 repetitions each: one repetition takes about a millisecond
+    t_plain, _ = timed(lambda: S.plain_rv(stars, test, mask, idx), 20)
+    t_kern, _ = timed(lambda: model.surrogate_rv(x, r, bufs), 20)
+    t_gated, (rv_s, fb, _) = timed(lambda: model.rv(test, idx, bufs), 20)
     e = np.abs(rv_s - rv_plain) * 1e5
     acc = ~fb
     alpha0 = None
     if calib_alpha0 is not None:
         # the same gate with the factor that let no held-out sample miss
-        t0g, (rv0, fb0, _) = timed(lambda: model.rv(test, idx, bufs, calib=calib_alpha0), 5)
+        t0g, (rv0, fb0, _) = timed(lambda: model.rv(test, idx, bufs, calib=calib_alpha0), 20)
         e0 = np.abs(rv0 - rv_plain) * 1e5
         a0 = ~fb0
         alpha0 = {"calib": calib_alpha0, "gated_rv_per_s": nt / t0g, "surrogate_x": t_plain / t0g,

@@ -926,8 +926,8 @@ __global__ void __launch_bounds__(256) k_ccf_linear(int64_t n, int k, int n_v, c
 
 constexpr int SG_MAX_ENS = 16;
 
-// samples per wave of k_sg_rv (they share every basis row it loads) and
-// basis rows in flight, by CCF points per lane
+// samples per wave of k_sg_lin and k_sg_spread (they share every basis row
+// loaded) and basis rows in flight, by CCF points per lane
 template <int NPT>
 constexpr int sg_samples() {
   return NPT <= 3 ? 4 : (NPT <= 6 ? 2 : 1);
