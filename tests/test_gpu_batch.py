@@ -113,24 +113,27 @@ def test_batch_ccf_and_fit_equal_single_calls():
     """The CCF + fit stage of a batch graph gives, on every replay, what
     soap_ccf_rv gives on the same spectra, bit for bit (section 4.1)."""
     stars = [W.make_tiny(21, n_grid=30, n_pix=2600, n_mu=4, precision=W.PREC_FP32, contrast_mode=W.CONTRAST_PLANCK),
-             W.make_tiny(21, n_grid=44, n_pix=2600, n_mu=4, precision=W.PREC_FP32)]
+             W.make_tiny(21, n_grid=44, n_pix=2600, n_mu=4, precision=W.PREC_FP32),
+             # FP64: a second CCF layout, so a second pair of work-list launches
+             W.make_tiny(21, n_grid=36, n_pix=2600, n_mu=4, precision=W.PREC_FP64)]
     mask = stars[0].mask
     ctxs = [L.soap_grid_init(s) for s in stars]
     L.soap_set_apply_shape(ctxs[1], 2, 0, 16)
     rng = np.random.default_rng(9)
     cfg_ctx, cfg_regs, cfg_ph, outs, ccfs, rvs = [], [], [], [], [], []
     for i in range(7):
-        k = i % 2
+        k = i % 3
         regs = [W.Region(W.SPOT, float(rng.uniform(-50, 50)), float(rng.uniform(0, 360)), float(rng.uniform(0.1, 0.3)),
                          0.6)]
         ph = np.sort(rng.uniform(0, 1, int(rng.integers(3, 30))))
         cfg_ctx.append(ctxs[k])
         cfg_regs.append(regs)
         cfg_ph.append(ph)
-        outs.append(torch.empty((len(ph), stars[k].n_pix), dtype=torch.float32, device="cuda"))
+        dt = torch.float32 if stars[k].precision == W.PREC_FP32 else torch.float64
+        outs.append(torch.empty((len(ph), stars[k].n_pix), dtype=dt, device="cuda"))
         ccfs.append(torch.full((len(ph), mask.n_v), -1.0, dtype=torch.float64, device="cuda") if i != 3 else None)
         rvs.append(torch.zeros(len(ph) * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda") if i != 5 else None)
-    _say("batch with CCF + fit: 7 configurations over 2 stars")
+    _say("batch with CCF + fit: 7 configurations over 3 stars, two precisions")
     b = L.soap_batch_create(cfg_ctx, cfg_regs, cfg_ph, W.EFFECT_TOT, outs, mask=mask, ccf_outs=ccfs, rv_outs=rvs)
     for rep in range(2):
         for o in outs:

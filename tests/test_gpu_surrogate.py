@@ -519,3 +519,42 @@ def test_device_features_match_host_features():
     L.soap_surrogate_features(torch.from_numpy(raw).cuda(), x)
     torch.cuda.synchronize()
     np.testing.assert_allclose(x.cpu().numpy(), want, rtol=0, atol=2e-6)
+
+
+def test_multi_star_synthesis_at_bench_scale_matches_oracle():
+    """The surrogate's data path at the benchmark's scale: stars of the full
+    300 x 300 grid on the 20000-pixel window, several spots each, synthesised
+    by one call over many contexts; sampled rows against the oracle within
+    the FP32 flux bar, and every row equal to the single-context call."""
+    from paper_2301_04259_amd import surrogate as S
+
+    smp = W.cfg5_multi_samples(6, n_per=4, seed=29, teff_subset=[5000.0, 6000.0])
+    stars = S.Stars()
+    spec = {}
+    for sid in np.unique(smp.star):
+        t, inc, vs = smp.star_params(sid)
+        if float(t) not in spec:
+            spec[float(t)] = W.cfg5_window_spectra(t)
+        stars.add(sid, L.soap_grid_init(W.cfg5_star(t, inc, vs, spec[float(t)])), t, inc, vs)
+    _say("bench-scale stars", len(stars.ids), "samples", smp.n)
+    F = torch.empty((smp.n, stars.ref.n_pix), dtype=torch.float32, device="cuda")
+    S.synthesize(stars, smp, F)
+    torch.cuda.synchronize()
+    got = F.cpu().numpy()
+    worst = 0.0
+    for i in range(0, smp.n, 5):
+        k = i // smp.n_per
+        t, inc, vs = smp.star_params(smp.star[k])
+        st = W.cfg5_star(t, inc, vs, spec[float(t)])
+        reg = [W.Region(W.SPOT, smp.lat_deg[k], smp.lon_deg[k], smp.radius[k], smp.contrast[k])]
+        f = OS_spec.integrated(st, smp.phases.reshape(-1)[i], OS_spec.TOT, regions=reg)
+        worst = max(worst, float(np.max(np.abs(got[i] - f) / np.abs(f))))
+        one = torch.empty((1, stars.ref.n_pix), dtype=torch.float32, device="cuda")
+        ctx = stars.ctxs[stars.row[int(smp.star[k])]]
+        L.soap_active_spectra(ctx, reg, [smp.phases.reshape(-1)[i]], W.EFFECT_TOT, one)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(one.cpu().numpy()[0], got[i])
+    _say(f"bench-scale multi-star rows vs oracle: worst relative error {worst:.2e}")
+    assert worst <= 1e-6
+    for c in stars.ctxs:
+        L.soap_destroy(c)
