@@ -219,3 +219,33 @@ def test_planck_ratio_limits_and_textbook_form():
     assert np.isclose(S.planck_ratio(np.array([1e9]), t1, t2)[0], t1 / t2, rtol=1e-4)
     # identity
     assert np.allclose(S.planck_ratio(lam, t2, t2), 1.0, rtol=1e-15)
+
+
+def test_bank_windows_show_a_ccf_dip_under_the_headline_mask():
+    """The batched workload's spectral banks (every T_eff) and the headline
+    star draw their lines from one master list, so the headline star's mask
+    marks lines of every bank: a window of each bank correlated with that
+    mask gives a Gaussian-like dip at zero velocity that the oracle's fit
+    recovers (section 4.1: CCF with a line mask, then a Gaussian fit)."""
+    from workloads.stars import _select_mask_lines
+
+    c30, u30, s30 = W.full_range_lines(30000)
+    mlam, _ = _select_mask_lines(c30, 0.05 + 0.85 * u30**2, s30, 4000)
+    dln = 1.0 / (3.0 * 115000.0)
+    n_pix, start = 12000, 60000
+    ln0 = np.log(3800.0) + start * dln
+    lam_lo, lam_hi = np.exp(ln0), np.exp(ln0 + dln * (n_pix - 1))
+    v = C.velocity_grid(-20.0, 0.25, 161)
+    for teff in W.BANK_TEFF:
+        scale = 5778.0 / teff
+        c, u, sg = W.full_range_lines(int(round(30000 * scale**3)))
+        sel = (c > lam_lo - 2.0) & (c < lam_hi + 2.0)
+        depth = np.minimum((0.05 + 0.85 * u[sel] ** 2) * scale**1.5, 0.95)
+        flux = _render(ln0, dln, n_pix, c[sel], depth, sg[sel], np.zeros(int(sel.sum())), 0.0)
+        m = (mlam > lam_lo + 1.0) & (mlam < lam_hi - 1.0)
+        assert m.sum() > 100
+        y = C.ccf(flux, ln0, dln, np.log(mlam[m]), np.ones(int(m.sum())), 0.41, v)
+        r = F.gauss_fit(v, y)
+        assert r["a"] > 0.15 * r["c0"], (teff, r)  # a real dip, not a noise floor
+        assert abs(r["rv_kms"]) < 0.2, (teff, r)  # blends of the window's other lines shift it a little
+        assert 1.0 < r["sigma"] < 4.0, (teff, r)

@@ -38,6 +38,7 @@ from .stars import (  # noqa: F401
     CFG5_INCL,
     CFG5_VSINI,
     make_bank,
+    full_range_lines,
     batch_configs,
     batch_star,
     bank_for,

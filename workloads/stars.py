@@ -264,11 +264,8 @@ def make_cfg2(seed: int = 2, precision: int = PREC_FP32, n_phases: int = 100) ->
     ln0 = np.log(3800.0)
     n_pix = int(np.floor(np.log(6900.0 / 3800.0) / dln)) + 1
     n_lines = 30000
-    centre = rng.uniform(3805.0, 6895.0, n_lines)
-    u = rng.uniform(0.0, 1.0, n_lines)
+    centre, u, sigma = _headline_lines(rng)
     depth = 0.05 + 0.85 * u * u
-    sig_v = rng.uniform(1.5, 3.0, n_lines)
-    sigma = centre * sig_v / C_KMS
     gamma = np.zeros(n_lines)
     deep = np.argsort(-depth)[: n_lines // 10]
     gamma[deep] = 0.1 * sigma[deep]
@@ -508,25 +505,53 @@ def cfg5_samples(n_spots: int, n_per: int = 8, seed: int = 5) -> SpotSamples:
     )
 
 
+def _headline_lines(rng):
+    """The headline star's 30000 lines (centre_A, u, sigma_A), the first
+    draws of its generator."""
+    centre = rng.uniform(3805.0, 6895.0, 30000)
+    u = rng.uniform(0.0, 1.0, 30000)
+    sigma = centre * rng.uniform(1.5, 3.0, 30000) / C_KMS
+    return centre, u, sigma
+
+
+def full_range_lines(n_lines: int, seed: int = 2, extra_seed: int = 3):
+    """Master line list of the full range (3800-6900 A): (centre_A, u,
+    sigma_A) of n_lines lines, depth (0.05 + 0.85 u^2) before any T_eff
+    scaling.  The first 30000 are the headline star's lines (make_cfg2 draws
+    them first from the same seed, in the same order), so its mask marks
+    lines of every star built on this list, as a real line mask marks the
+    same atomic lines in stars of any T_eff; further lines (denser lists of
+    cooler stars) come from a second stream."""
+    n0 = 30000
+    centre, u, sigma = _headline_lines(np.random.default_rng(seed))
+    if n_lines > n0:
+        r2 = np.random.default_rng([extra_seed, 77])
+        m = n_lines - n0
+        c2 = r2.uniform(3805.0, 6895.0, m)
+        centre = np.concatenate([centre, c2])
+        u = np.concatenate([u, r2.uniform(0.0, 1.0, m)])
+        sigma = np.concatenate([sigma, c2 * r2.uniform(1.5, 3.0, m) / C_KMS])
+    return centre[:n_lines], u[:n_lines], sigma[:n_lines]
+
+
 def make_bank(teff_k: float, seed: int = 3, n_mu: int = 20):
     """Full-range local spectra (3800-6900 A at R = 115000, 205800 px) of a
     star of effective temperature teff_k, for windows of the batched
-    workload: 30k (5778/T)^3 lines with depths scaled by (5778/T)^1.5 (capped
-    at 0.95), convective blueshift from the cubic in T_eff (clamped to its
-    4800-6300 K range), spot spectrum with 30% deeper lines and no blueshift,
-    facula spectrum = quiet lines without blueshift.  Returns (ln_lambda0,
-    dln_lambda, mu_bins, [quiet, spot, facula]) with float32 arrays
-    [n_mu][205800]."""
-    rng = np.random.default_rng([seed, int(round(teff_k))])
+    workload: the first 30k (5778/T)^3 lines of the master list
+    (full_range_lines: hotter stars keep a subset of the headline star's
+    lines, cooler ones add weaker-list lines), depths scaled by (5778/T)^1.5
+    (capped at 0.95), convective blueshift from the cubic in T_eff (clamped
+    to its 4800-6300 K range), spot spectrum with 30% deeper lines and no
+    blueshift, facula spectrum = quiet lines without blueshift.  Returns
+    (ln_lambda0, dln_lambda, mu_bins, [quiet, spot, facula]) with float32
+    arrays [n_mu][205800]."""
     dln = 1.0 / (3.0 * 115000.0)
     ln0 = np.log(3800.0)
     n_pix = int(np.floor(np.log(6900.0 / 3800.0) / dln)) + 1
     scale = 5778.0 / teff_k
     n_lines = int(round(30000 * scale**3))
-    centre = rng.uniform(3805.0, 6895.0, n_lines)
-    u = rng.uniform(0.0, 1.0, n_lines)
+    centre, u, sigma = full_range_lines(n_lines, extra_seed=seed)
     depth = np.minimum((0.05 + 0.85 * u * u) * scale**1.5, 0.95)
-    sigma = centre * rng.uniform(1.5, 3.0, n_lines) / C_KMS
     gamma = np.zeros(n_lines)
     deep = np.argsort(-depth)[: n_lines // 10]
     gamma[deep] = 0.1 * sigma[deep]
