@@ -112,24 +112,28 @@ __device__ __forceinline__ void ccf_block(int P, int64_t n_spec, const T* __rest
     for (int s = 0; s < SB; ++s) acc[a][s] = T(0);
   }
   T vals[R][SB];
+  // only the batch's read span (batches[bi].w <= STG pixels) is loaded and
+  // staged: no hole of the batch reads past it
   auto load = [&](int bi) {
     if (bi >= b1) return;
-    const int lo = batches[bi].x;
+    const int lo = batches[bi].x, span = batches[bi].w;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int m = min(max(lo + tid + r * CCF_THREADS, 0), P - 1);
+      if (tid + r * CCF_THREADS < span) {
+        const int m = min(max(lo + tid + r * CCF_THREADS, 0), P - 1);
 #pragma unroll
-      for (int s = 0; s < SB; ++s) vals[r][s] = F[(s0 + min(s, ns - 1)) * (int64_t)P + m];
+        for (int s = 0; s < SB; ++s) vals[r][s] = F[(s0 + min(s, ns - 1)) * (int64_t)P + m];
+      }
     }
   };
   auto put = [&](int bi) {
     if (bi >= b1) return;
-    const int lo = batches[bi].x;
+    const int lo = batches[bi].x, span = batches[bi].w;
     T(*sb)[SB] = st[(bi - b0) & 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = tid + r * CCF_THREADS;
-      if (r < R - 1 || i < STG) {
+      if (i < span) {
         const int m = lo + i;
         const bool ok = m >= 0 && m < P;
 #pragma unroll
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(CCF_THREADS) k_ccf_batch(const CcfBatchSet* __
 // Host tables of one mask (section 4.1's CCF with the holes of Eq. 6),
 // appended to blob with 16-byte-aligned sections: lines (u, w) double2[nl],
 // hole edges (a^-, a^+) double2[n_v], batches int4 {first staged pixel,
-// first line, end line, 0}, and per line block the index of its first batch
+// first line, end line, pixels read}, and per line block the index of its first batch
 // (int[n_lb + 1]).  Batches hold consecutive lines whose reads, from the
 // floor of the lowest hole edge to NPX pixels past the floor of the highest,
 // fit a span of STG pixels.
@@ -274,7 +278,7 @@ bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, 
     for (int l = l0 + 1; l < l1; ++l) {
       const int nlo = std::min(lo, span_lo(l)), nhi = std::max(hi, span_end(l));
       if (nhi - nlo > stg) {
-        bat.push_back(make_int4(lo, beg, l, 0));
+        bat.push_back(make_int4(lo, beg, l, hi - lo));
         lo = span_lo(l);
         hi = span_end(l);
         beg = l;
@@ -283,7 +287,7 @@ bool ccf_build_tables(soap_ctx* c, const double* lnl, const double* wl, int nl, 
         hi = nhi;
       }
     }
-    bat.push_back(make_int4(lo, beg, l1, 0));
+    bat.push_back(make_int4(lo, beg, l1, hi - lo));
   }
   bfirst[nlb] = (int)bat.size();
   auto al16 = [](size_t v) { return (v + 15) & ~size_t(15); };
