@@ -685,14 +685,68 @@ __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit(int n_lb, int64_t n
   fit_block<NPT, PT>(n_lb, n_spec, n_v, v0, dv, part, ccf, fit, out, blockIdx.x);
 }
 
-// Work-list form: blk[b] = (set, spectrum).
+// One wave per spectrum: the same sums in the same order as fit_block's
+// four waves (row lb goes to accumulator lb mod 4, rows ascending; the four
+// accumulators are then added in order), so the CCF and the fit repeat
+// fit_block's bit for bit; with every wave of a block fitting, four times as
+// many fits are in flight.
+template <int NPT, typename PT>
+__device__ __forceinline__ void fit_one_wave(int n_lb, int64_t n_spec, int n_v, double v0, double dv,
+                                             const PT* __restrict__ part, double* __restrict__ ccf, int fit,
+                                             soap_rv* __restrict__ out, int64_t s) {
+  const int lane = threadIdx.x & 63;
+  constexpr int NW = CCF_FIN_THREADS / 64;  // fit_block's interleave of line blocks
+  constexpr int RB = 2 * NW;                // rows in flight, a multiple of NW
+  double acc[NW][NPT];
+#pragma unroll
+  for (int w = 0; w < NW; ++w)
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) acc[w][t] = 0.0;
+  for (int lb0 = 0; lb0 < n_lb; lb0 += RB) {
+    // unconditional loads (indices clamped), out-of-range values zeroed after
+    PT raw[RB][NPT];
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+      const int lb = min(lb0 + u, n_lb - 1);
+      const PT* src = part + ((int64_t)lb * n_spec + s) * n_v;
+#pragma unroll
+      for (int t = 0; t < NPT; ++t) raw[u][t] = src[min(lane + 64 * t, n_v - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < RB; ++u)
+#pragma unroll
+      for (int t = 0; t < NPT; ++t) {
+        const int i = lane + 64 * t;
+        acc[u % NW][t] += (lb0 + u < n_lb && i < n_v) ? (double)raw[u][t] : 0.0;
+      }
+  }
+  double y[NPT];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    const int i = lane + 64 * t;
+    double a = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) a += acc[w][t];
+    y[t] = a;
+    if (i < n_v) ccf[s * n_v + i] = a;
+  }
+  if (!fit) return;
+  double p[4], S[20];
+  const soap_rv res = fit_wave(y, n_v, v0, dv, p, S);
+  if (lane == 0) out[s] = res;
+}
+
+// Work-list form, one wave per entry: blk[b] = (set, spectrum).
 template <int NPT, typename PT>
 __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit_batch(const CcfBatchSet* __restrict__ sets,
-                                                                   const int2* __restrict__ blk, int n_v, double v0,
-                                                                   double dv) {
-  const int2 t = blk[blockIdx.x];
+                                                                   const int2* __restrict__ blk, int n_blk, int n_v,
+                                                                   double v0, double dv) {
+  const int b = blockIdx.x * (CCF_FIN_THREADS / 64) + (threadIdx.x >> 6);
+  if (b >= n_blk) return;  // whole waves
+  const int2 t = blk[b];
   const CcfBatchSet c = sets[t.x];
-  fit_block<NPT, PT>(c.nlb, c.n_spec, n_v, v0, dv, static_cast<const PT*>(c.part), c.ccf, c.rv ? 1 : 0, c.rv, t.y);
+  fit_one_wave<NPT, PT>(c.nlb, c.n_spec, n_v, v0, dv, static_cast<const PT*>(c.part), c.ccf, c.rv ? 1 : 0, c.rv,
+                        t.y);
 }
 
 template <typename T, int A, int NPX, int STG>
@@ -835,10 +889,12 @@ void launch_ccf_batch_t(const CcfBatch& cb, hipStream_t st) {
 template <typename PT>
 hipError_t launch_fit_batch_pt(const CcfBatch& cb, hipStream_t st) {
   const int npt = (cb.shape.nv + 63) / 64;
+  constexpr int kWaves = CCF_FIN_THREADS / 64;  // one spectrum per wave
+  const unsigned grid = (unsigned)((cb.n_fit_blocks + kWaves - 1) / kWaves);
 #define FITB_CASE(N)                                                                                           \
   case N:                                                                                                      \
-    hipLaunchKernelGGL((k_ccf_fit_batch<N, PT>), dim3((unsigned)cb.n_fit_blocks), dim3(CCF_FIN_THREADS), 0, st, \
-                       cb.sets, cb.fit_blk, cb.shape.nv, cb.shape.v0, cb.shape.dv);                            \
+    hipLaunchKernelGGL((k_ccf_fit_batch<N, PT>), dim3(grid), dim3(CCF_FIN_THREADS), 0, st, cb.sets, cb.fit_blk, \
+                       cb.n_fit_blocks, cb.shape.nv, cb.shape.v0, cb.shape.dv);                                 \
     break;
   switch (npt) {
     FITB_CASE(1) FITB_CASE(2) FITB_CASE(3) FITB_CASE(4) FITB_CASE(5) FITB_CASE(6)
