@@ -313,6 +313,7 @@ namespace {
 
 constexpr double FWHM_PER_SIGMA = 2.3548200450309493;  // 2 sqrt(2 ln 2)
 constexpr int CCF_FIN_THREADS = 256;
+constexpr int64_t CCF_FIT_WAVES_FROM = 512;  // spectra per call above which one wave fits each
 
 // Sums of the fit at p, identical in every lane: S[0] = chi^2,
 // S[1..4] = g = J^T r, S[5..14] = J^T J (upper triangle, row by row),
@@ -736,6 +737,17 @@ __device__ __forceinline__ void fit_one_wave(int n_lb, int64_t n_spec, int n_v, 
   if (lane == 0) out[s] = res;
 }
 
+// One wave per spectrum over one spectra set (calls with many spectra).
+template <int NPT, typename PT>
+__global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit_waves(int n_lb, int64_t n_spec, int n_v, double v0,
+                                                                   double dv, const PT* __restrict__ part,
+                                                                   double* __restrict__ ccf, int fit,
+                                                                   soap_rv* __restrict__ out) {
+  const int64_t s = (int64_t)blockIdx.x * (CCF_FIN_THREADS / 64) + (threadIdx.x >> 6);
+  if (s >= n_spec) return;  // whole waves
+  fit_one_wave<NPT, PT>(n_lb, n_spec, n_v, v0, dv, part, ccf, fit, out, s);
+}
+
 // Work-list form, one wave per entry: blk[b] = (set, spectrum).
 template <int NPT, typename PT>
 __global__ void __launch_bounds__(CCF_FIN_THREADS) k_ccf_fit_batch(const CcfBatchSet* __restrict__ sets,
@@ -820,10 +832,21 @@ template <typename PT>
 static hipError_t launch_fit_npt(const CcfPlan& q, hipStream_t st, int nlb, int64_t n_spec, const PT* d_part,
                                  double* d_ccf, soap_rv* d_rv) {
   const int npt = (q.nv + 63) / 64;
-#define FIT_CASE(N)                                                                                         \
-  case N:                                                                                                   \
-    hipLaunchKernelGGL((k_ccf_fit<N, PT>), dim3((unsigned)n_spec), dim3(CCF_FIN_THREADS), 0, st, nlb, n_spec, \
-                       q.nv, q.v0, q.dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);                                \
+  // up to CCF_FIT_WAVES_FROM spectra a block of four waves per spectrum
+  // (partial sums spread over the block, every fit in flight at once);
+  // beyond, a wave per spectrum (four fits in flight per block); both give
+  // the same records bit for bit
+  constexpr int kWaves = CCF_FIN_THREADS / 64;
+  const bool waves = n_spec > CCF_FIT_WAVES_FROM;
+  const unsigned grid = waves ? (unsigned)((n_spec + kWaves - 1) / kWaves) : (unsigned)n_spec;
+#define FIT_CASE(N)                                                                                          \
+  case N:                                                                                                    \
+    if (waves)                                                                                               \
+      hipLaunchKernelGGL((k_ccf_fit_waves<N, PT>), dim3(grid), dim3(CCF_FIN_THREADS), 0, st, nlb, n_spec, q.nv, \
+                         q.v0, q.dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);                                     \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_ccf_fit<N, PT>), dim3(grid), dim3(CCF_FIN_THREADS), 0, st, nlb, n_spec, q.nv, q.v0, \
+                         q.dv, d_part, d_ccf, d_rv ? 1 : 0, d_rv);                                           \
     break;
   switch (npt) {
     FIT_CASE(1) FIT_CASE(2) FIT_CASE(3) FIT_CASE(4) FIT_CASE(5) FIT_CASE(6)

@@ -64,3 +64,33 @@ def test_ccf_shapes_match_oracle(seed, prec, hole_px, n_v, span_px, edge, shuffl
     # of the running (positive) sum, bounds the error by 2e-5 relative
     rel = np.max(np.abs(got - c_or) / np.abs(c_or))
     assert rel < (1e-9 if prec == W.PREC_FP64 else 2e-5), rel
+
+
+def test_fit_wave_per_spectrum_equals_block_per_spectrum():
+    """Calls of more than 512 spectra fit with one wave per spectrum, smaller
+    ones with a block of four waves per spectrum; both add the partial CCFs
+    in the same order, so the CCF and RV records are the same bit for bit."""
+    star = W.make_tiny(39, n_grid=8, n_pix=3000, n_mu=2, precision=W.PREC_FP32, n_phases=1)
+    print("[ccf-shapes] wave-per-spectrum fit vs block-per-spectrum fit, 700 spectra", flush=True)
+    ctx = L.soap_grid_init(star)
+    rng = np.random.default_rng(39)
+    base = np.asarray(star.spectra[0][0], dtype=np.float64)
+    flux_h = (base[None, :] * (1.0 + 1e-3 * rng.standard_normal((700, star.n_pix)))).astype(np.float32)
+    flux = torch.from_numpy(flux_h).cuda()
+    m = star.mask
+    out = []
+    for parts in ([700], [350, 350]):
+        ccf = torch.empty((700, m.n_v), dtype=torch.float64, device="cuda")
+        rv = torch.zeros(700 * L.RV_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        a = 0
+        for n in parts:
+            L.soap_ccf_rv(ctx, flux[a:a + n], m, ccf_out=ccf[a:a + n],
+                          rv_out=rv[a * L.RV_DTYPE.itemsize:(a + n) * L.RV_DTYPE.itemsize])
+            a += n
+        torch.cuda.synchronize()
+        out.append((ccf.cpu().numpy(), rv.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    rec = np.frombuffer(out[0][1].tobytes(), dtype=L.RV_DTYPE)
+    assert np.mean(rec["status"] == 0) > 0.9
+    L.soap_destroy(ctx)
