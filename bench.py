@@ -421,7 +421,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--surrogate-spots", type=int, default=50000,
                     help="training spots of the surrogate leg (8 phases each; 0 = skip the leg)")
-    ap.add_argument("--surrogate-epochs", type=int, default=100)
+    ap.add_argument("--surrogate-epochs", type=int, default=600,
+                    help="training epochs of the multi-star surrogate (the one-star leg trains half as many)")
     ap.add_argument("--surrogate-single-star", type=int, default=1,
                     help="also run the one-star surrogate comparison (0 = skip)")
     ap.add_argument("--surrogate-components", type=int, default=128, help="PCA components (multiple of 32)")

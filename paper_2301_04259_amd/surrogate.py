@@ -441,10 +441,11 @@ class SurrogateModel:
         return ((np.asarray(coef_host, np.float64) - b.mu) / b.sigma).astype(np.float32)
 
     # -- training -----------------------------------------------------------
-    def train(self, X, Y, epochs, batch=512, lr=2e-3, lr_final=1e-4, seed=0, log=None):
+    def train(self, X, Y, epochs, batch=512, lr=2e-3, lr_final=1e-4, seed=0, log=None, log_every=1):
         """Adam over shuffled batches (X [n][features], Y [n][k] normalised,
         host float32).  The learning rate decays geometrically from lr to
-        lr_final.  Returns the last batch's loss of every epoch."""
+        lr_final.  Returns the last batch's loss of every epoch; log (if
+        given) gets a line every log_every epochs."""
         torch = self.torch
         rng = np.random.default_rng(seed)
         n = (len(X) // batch) * batch
@@ -465,8 +466,8 @@ class SurrogateModel:
                 if want:
                     tot = l
             losses.append(tot)
-            if log:
-                log(f"epoch {ep} loss {tot:.4g}")
+            if log and ((ep + 1) % log_every == 0 or ep + 1 == epochs):
+                log(f"epoch {ep + 1} of {epochs}, loss {tot:.4g}")
         return losses
 
     # -- inference ----------------------------------------------------------
@@ -572,7 +573,7 @@ def build(stars, mask, train, heldout, n_components=64, hidden=256, n_ensemble=4
     X = model.inputs(train, np.arange(train.n))[0].cpu().numpy()
     Y = model.normalise(coef)
     t = time.perf_counter()
-    losses = model.train(X, Y, epochs, batch=batch, seed=seed)
+    losses = model.train(X, Y, epochs, batch=batch, seed=seed, log=log, log_every=max(1, epochs // 10))
     torch.cuda.synchronize()
     info["train_s"] = time.perf_counter() - t
     info["train_steps"] = epochs * (len(X) // batch)
